@@ -1,0 +1,328 @@
+"""Python view of the CPU oracle (test infrastructure only).
+
+The oracle is a plain C statement of the method (liboracle.so, built by
+oracle/build.sh).  Only the tests, the package's smoke check and the CPU
+baseline leg of the benchmark use it; the GPU library never does.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+ME, LHZ = 0, 1
+STREAM_INIT, STREAM_SQA, STREAM_PT, STREAM_SWAP, STREAM_TREE, STREAM_PT_INIT = 1, 2, 3, 4, 5, 6
+ALWAYS = 0xFFFFFFFF
+
+
+def build() -> None:
+    subprocess.run(["sh", os.path.join(_HERE, "build.sh")], check=True)
+
+
+class OEmb(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("N", C.c_int32), ("n_sites", C.c_int32),
+                ("n_terms", C.c_int32), ("fmax", C.c_int32), ("emax", C.c_int32),
+                ("h", C.POINTER(C.c_int32)), ("colour", C.POINTER(C.c_int32)),
+                ("w", C.POINTER(C.c_int32)), ("arity", C.POINTER(C.c_int32)),
+                ("tsite", C.POINTER(C.c_int32)), ("row", C.POINTER(C.c_int32)),
+                ("inc", C.POINTER(C.c_int32))]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        _lib = C.CDLL(_LIB_PATH)
+        L = _lib
+        L.oracle_sqa_word.restype = C.c_uint32
+        L.oracle_sqa_word.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32]
+        L.oracle_pt_word.restype = C.c_uint32
+        L.oracle_pt_word.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32]
+        L.oracle_threshold.restype = C.c_uint32
+        L.oracle_threshold.argtypes = [C.c_double]
+        L.oracle_embed.restype = C.c_int
+        L.oracle_local_field.restype = C.c_int32
+        L.oracle_energy.restype = C.c_int32
+        L.oracle_logical_energy.restype = C.c_int32
+        L.oracle_sqa_sweep_order.restype = C.c_int32
+        L.oracle_sqa_attempt_threshold.restype = C.c_uint32
+        L.oracle_ground_states.restype = C.c_int32
+        L.oracle_random_trees.restype = C.c_int
+        L.oracle_me_site.restype = C.c_int32
+        L.oracle_lhz_site.restype = C.c_int32
+    return _lib
+
+
+def _p(a, ct):
+    return a.ctypes.data_as(C.POINTER(ct))
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+# ---------------------------------------------------------------- Philox
+def philox4x32(ctr, key):
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().oracle_philox4x32(_p(c, C.c_uint32), _p(k, C.c_uint32), _p(out, C.c_uint32))
+    return out
+
+
+def philox4x64(ctr, key):
+    c = np.ascontiguousarray(ctr, dtype=np.uint64)
+    k = np.ascontiguousarray(key, dtype=np.uint64)
+    out = np.zeros(4, dtype=np.uint64)
+    lib().oracle_philox4x64(_p(c, C.c_uint64), _p(k, C.c_uint64), _p(out, C.c_uint64))
+    return out
+
+
+def sqa_word(seed, stream, replica, site, slice_, sweep) -> int:
+    return int(lib().oracle_sqa_word(seed, stream, replica, site, slice_, sweep))
+
+
+def pt_word(seed, stream, replica, site, sweep) -> int:
+    return int(lib().oracle_pt_word(seed, stream, replica, site, sweep))
+
+
+# ---------------------------------------------------------------- embeddings
+class Embedding:
+    """An embedded physical Hamiltonian built by the oracle."""
+
+    def __init__(self, kind: int, J, penalty: int, h=None):
+        J = _i32(J)
+        N = J.shape[0]
+        self.J = J
+        self.h_logical = None if h is None else _i32(h)
+        self._e = OEmb()
+        hp = _p(self.h_logical, C.c_int32) if h is not None else None
+        rc = lib().oracle_embed(kind, N, _p(J, C.c_int32), hp, penalty, C.byref(self._e))
+        if rc != 0:
+            raise ValueError("invalid embedding arguments")
+        e = self._e
+        n, t = e.n_sites, e.n_terms
+        self.kind, self.N, self.n_sites, self.n_terms = kind, N, n, t
+        self.fmax, self.emax = e.fmax, e.emax
+        self.h = np.ctypeslib.as_array(e.h, (n,)).copy()
+        self.colour = np.ctypeslib.as_array(e.colour, (n,)).copy()
+        self.w = np.ctypeslib.as_array(e.w, (max(t, 1),))[:t].copy()
+        self.arity = np.ctypeslib.as_array(e.arity, (max(t, 1),))[:t].copy()
+        self.tsite = np.ctypeslib.as_array(e.tsite, (max(t, 1) * 4,))[:4 * t].reshape(t, 4).copy()
+        self.row = np.ctypeslib.as_array(e.row, (n + 1,)).copy()
+        self.inc = np.ctypeslib.as_array(e.inc, (max(int(self.row[-1]), 1),))[:int(self.row[-1])].copy()
+
+    def __del__(self):
+        try:
+            lib().oracle_emb_free(C.byref(self._e))
+        except Exception:
+            pass
+
+    @property
+    def ptr(self):
+        return C.byref(self._e)
+
+    def local_field(self, s, k) -> int:
+        s = np.ascontiguousarray(s, dtype=np.int8)
+        return int(lib().oracle_local_field(self.ptr, _p(s, C.c_int8), k))
+
+    def energy(self, s) -> int:
+        s = np.ascontiguousarray(s, dtype=np.int8)
+        return int(lib().oracle_energy(self.ptr, _p(s, C.c_int8)))
+
+
+def me_site(N, i, r) -> int:
+    return int(lib().oracle_me_site(N, i, r))
+
+
+def lhz_site(N, i, j) -> int:
+    return int(lib().oracle_lhz_site(N, i, j))
+
+
+def logical_energy(J, sigma, h=None) -> int:
+    J = _i32(J)
+    s = np.ascontiguousarray(sigma, dtype=np.int8)
+    hp = _p(_i32(h), C.c_int32) if h is not None else None
+    return int(lib().oracle_logical_energy(J.shape[0], _p(J, C.c_int32), hp, _p(s, C.c_int8)))
+
+
+# ---------------------------------------------------------------- tables
+def threshold(x: float) -> int:
+    return int(lib().oracle_threshold(C.c_double(x)))
+
+
+def gamma_schedule(g0, g1, M):
+    out = np.zeros(M, dtype=np.float64)
+    lib().oracle_gamma_schedule(C.c_double(g0), C.c_double(g1), M, _p(out, C.c_double))
+    return out
+
+
+def sqa_table(beta, L, gamma, F, bscale=None):
+    gamma = np.ascontiguousarray(gamma, dtype=np.float64)
+    M = gamma.shape[0]
+    out = np.zeros((M, 2 * F + 1, 3), dtype=np.uint32)
+    bp = None
+    if bscale is not None:
+        bscale = np.ascontiguousarray(bscale, dtype=np.float64)
+        bp = _p(bscale, C.c_double)
+    lib().oracle_sqa_table(C.c_double(beta), L, M, _p(gamma, C.c_double), bp, F, _p(out, C.c_uint32))
+    return out
+
+
+def pt_ladder(beta_min, beta_max, R):
+    out = np.zeros(R, dtype=np.float64)
+    lib().oracle_pt_ladder(C.c_double(beta_min), C.c_double(beta_max), R, _p(out, C.c_double))
+    return out
+
+
+def pt_table(betas, F):
+    betas = np.ascontiguousarray(betas, dtype=np.float64)
+    out = np.zeros((betas.shape[0], 2 * F + 1), dtype=np.uint32)
+    lib().oracle_pt_table(_p(betas, C.c_double), betas.shape[0], F, _p(out, C.c_uint32))
+    return out
+
+
+def swap_table(betas, Dmax):
+    betas = np.ascontiguousarray(betas, dtype=np.float64)
+    R = betas.shape[0]
+    out = np.zeros((max(R - 1, 1), Dmax + 1), dtype=np.uint32)
+    lib().oracle_swap_table(_p(betas, C.c_double), R, Dmax, _p(out, C.c_uint32))
+    return out[:max(R - 1, 0)]
+
+
+# ---------------------------------------------------------------- SQA
+def sqa_init(emb: Embedding, L, R, seed):
+    out = np.zeros((R, L, emb.n_sites), dtype=np.int8)
+    lib().oracle_sqa_init(emb.ptr, L, R, C.c_uint64(seed), _p(out, C.c_int8))
+    return out
+
+
+def sqa_sweep_order(emb: Embedding, L):
+    n = emb.n_sites * L
+    k = np.zeros(n, dtype=np.int32)
+    t = np.zeros(n, dtype=np.int32)
+    cnt = lib().oracle_sqa_sweep_order(emb.ptr, L, _p(k, C.c_int32), _p(t, C.c_int32))
+    return k[:cnt], t[:cnt]
+
+
+def sqa_attempt_threshold(emb: Embedding, L, table, lat, k, tau, m) -> int:
+    table = np.ascontiguousarray(table, dtype=np.uint32)
+    F = (table.shape[1] - 1) // 2
+    lat = np.ascontiguousarray(lat, dtype=np.int8)
+    return int(lib().oracle_sqa_attempt_threshold(emb.ptr, L, _p(table, C.c_uint32), F,
+                                                  _p(lat, C.c_int8), k, tau, m))
+
+
+def sqa_run(emb: Embedding, L, spins, m0, m1, table, seed, nthreads=1):
+    """Runs sweeps m0..m1-1 in place on spins[R][L][n]."""
+    assert spins.dtype == np.int8 and spins.flags.c_contiguous
+    table = np.ascontiguousarray(table, dtype=np.uint32)
+    F = (table.shape[1] - 1) // 2
+    lib().oracle_sqa_run(emb.ptr, L, spins.shape[0], m0, m1, _p(table, C.c_uint32), F,
+                         C.c_uint64(seed), _p(spins, C.c_int8), nthreads)
+    return spins
+
+
+def sqa_energies(emb: Embedding, spins):
+    R, L, _ = spins.shape
+    E = np.zeros((R, L), dtype=np.int32)
+    s = np.ascontiguousarray(spins, dtype=np.int8)
+    lib().oracle_sqa_energies(emb.ptr, L, R, _p(s, C.c_int8), _p(E, C.c_int32))
+    return E
+
+
+def sqa_anneal(kind, J, penalty, beta, L, sweeps, replicas, gamma0, gamma1, seed,
+               h=None, gamma=None, bscale=None, nthreads=1, fmax=None):
+    """The whole single-instance SQA path: embed, tabulate, init, anneal, energies.
+    `fmax` widens the table's field range beyond the embedding's own (results do not
+    depend on it)."""
+    emb = Embedding(kind, J, penalty, h)
+    g = gamma_schedule(gamma0, gamma1, sweeps) if gamma is None else np.asarray(gamma, dtype=np.float64)
+    F = emb.fmax if fmax is None else fmax
+    table = sqa_table(beta, L, g, F, bscale)
+    spins = sqa_init(emb, L, replicas, seed)
+    sqa_run(emb, L, spins, 0, sweeps, table, seed, nthreads)
+    return emb, table, spins, sqa_energies(emb, spins)
+
+
+# ---------------------------------------------------------------- PT
+def pt_init(emb: Embedding, R, seed):
+    out = np.zeros((R, emb.n_sites), dtype=np.int8)
+    lib().oracle_pt_init(emb.ptr, R, C.c_uint64(seed), _p(out, C.c_int8))
+    return out
+
+
+def pt_run(emb: Embedding, betas, sweeps, sweeps_per_swap, seed):
+    betas = np.ascontiguousarray(betas, dtype=np.float64)
+    R = betas.shape[0]
+    F = emb.fmax
+    Dmax = 2 * emb.emax
+    mt = pt_table(betas, F)
+    st = swap_table(betas, Dmax)
+    st_c = np.ascontiguousarray(st if st.size else np.zeros((1, Dmax + 1), np.uint32))
+    spins = np.zeros((R, emb.n_sites), dtype=np.int8)
+    E = np.zeros(R, dtype=np.int32)
+    rep_at = np.zeros(R, dtype=np.int32)
+    acc = np.zeros(max(R - 1, 1), dtype=np.uint64)
+    lib().oracle_pt_run(emb.ptr, R, sweeps, sweeps_per_swap, _p(mt, C.c_uint32), F,
+                        _p(st_c, C.c_uint32), Dmax, C.c_uint64(seed), _p(spins, C.c_int8),
+                        _p(E, C.c_int32), _p(rep_at, C.c_int32), _p(acc, C.c_uint64))
+    return spins, E, rep_at, acc[:max(R - 1, 0)]
+
+
+# ---------------------------------------------------------------- decoders
+def me_majority(emb: Embedding, slice_):
+    s = np.ascontiguousarray(slice_, dtype=np.int8)
+    out = np.zeros(emb.N, dtype=np.int8)
+    lib().oracle_me_majority(emb.ptr, _p(s, C.c_int8), _p(out, C.c_int8))
+    return out
+
+
+def lhz_tree_decode(N, slice_, parents):
+    s = np.ascontiguousarray(slice_, dtype=np.int8)
+    par = _i32(parents).reshape(-1, N)
+    out = np.zeros(N, dtype=np.int8)
+    lib().oracle_lhz_tree_decode(N, _p(s, C.c_int8), _p(par, C.c_int32), par.shape[0], _p(out, C.c_int8))
+    return out
+
+
+def random_trees(seed, N, n_trees):
+    out = np.zeros((n_trees, N), dtype=np.int32)
+    rc = lib().oracle_random_trees(C.c_uint64(seed), N, n_trees, _p(out, C.c_int32))
+    if rc != 0:
+        raise ValueError("N must be >= 1")
+    return out
+
+
+def lhz_mwd(N, slice_):
+    s = np.ascontiguousarray(slice_, dtype=np.int8)
+    out = np.zeros(N, dtype=np.int8)
+    lib().oracle_lhz_mwd(N, _p(s, C.c_int8), _p(out, C.c_int8))
+    return out
+
+
+def ground_states(J, h=None, max_states=64):
+    J = _i32(J)
+    N = J.shape[0]
+    out = np.zeros((max_states, N), dtype=np.int8)
+    cnt = C.c_int32(0)
+    hp = _p(_i32(h), C.c_int32) if h is not None else None
+    E = lib().oracle_ground_states(N, _p(J, C.c_int32), hp, _p(out, C.c_int8), max_states, C.byref(cnt))
+    return int(E), out[:min(cnt.value, max_states)], cnt.value
+
+
+def chain_tree(N):
+    """Eq. (A1): parent(v) = v-1."""
+    return np.array([-1] + list(range(N - 1)), dtype=np.int32)
+
+
+def star_tree(N):
+    """Eq. (A2): parent(v) = 0."""
+    return np.array([-1] + [0] * (N - 1), dtype=np.int32)
