@@ -1,0 +1,279 @@
+/*
+ * sqa.h - C ABI of the MI355X (gfx950) simulated-quantum-annealing and
+ * parallel-tempering library for embedded all-to-all Ising problems.
+ *
+ * Method: T. Albash, W. Vinci, D. A. Lidar, "Simulated Quantum Annealing
+ * Comparison between All-to-All Connectivity Schemes", arXiv:1603.03755.
+ *   - logical problem: Eq. (1), Sec. II
+ *   - annealing Hamiltonian H(t) = A(t) H_X + B(t) H_P: Eq. (2), Sec. II
+ *   - minor embedding with ferromagnetic chains: Sec. II A
+ *   - LHZ parity embedding with 3- and 4-body constraints: Eq. (3), Sec. II B
+ *   - majority-vote decoding: Eq. (4) (ME, Sec. II D), Eq. (5) (LHZ, Sec. II E,
+ *     Appendix A, Eqs. (A1)-(A2))
+ *   - minimum-weight decoding: Sec. IV A, Eqs. (6)-(10)
+ *   - SQA and PT: Sec. III and Appendix B, Eqs. (B1)-(B2)
+ *
+ * Conventions shared by every call
+ *   - Spins are int8_t with values +1 / -1.
+ *   - J is int32_t n*n row-major; only the upper triangle (i < j) is read.
+ *     J_ij < 0 is ferromagnetic.  h is int32_t[n] or NULL (all zero).
+ *   - Penalties are signed Hamiltonian coefficients: the ME chain coupling
+ *     J_F and the LHZ constraint coefficient C multiply s s' (ME) or the
+ *     product of the constraint's spins (LHZ); the paper's penalty strength
+ *     lambda corresponds to C = -lambda, so -2 is a penalty of strength 2.
+ *   - Physical site numbering.  ME: chain i, slot r -> i*(n-1)+r; J_ij (i<j)
+ *     couples slot j-1 of chain i with slot i of chain j; h_i sits on slot 0.
+ *     LHZ: pair (i,j), i<j -> i*(2n-i-1)/2 + (j-i-1).
+ *   - SQA state layout in host and device memory: [replica][slice][site]
+ *     (slice-major), int8.  Energies: [replica][slice], int32.
+ *   - All device work is asynchronous on the HIP stream passed as `stream`
+ *     (a hipStream_t; NULL = the default stream).  Reading calls synchronise
+ *     with the handle's last stream themselves.
+ *   - Every call returns sqa_status; nothing throws across the ABI.  On
+ *     failure sqa_last_error() returns a thread-local message.
+ *   - The library deep-copies every input at create/submit time.  Caller
+ *     buffers passed to read calls must hold at least `len` elements; a
+ *     shorter `len` than required returns SQA_ERR_INVALID.
+ *   - Results depend only on (problem, embedding, schedule, seed): never on
+ *     batch composition, launch shape or how the sweeps are split into calls.
+ */
+#ifndef SQA_MI355X_H
+#define SQA_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define SQA_API __attribute__((visibility("default")))
+#else
+#define SQA_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SQA_OK = 0,
+  SQA_ERR_INVALID = -1,     /* bad argument, short buffer, wrong state */
+  SQA_ERR_OOM = -2,         /* device or host allocation failed */
+  SQA_ERR_DEVICE = -3,      /* a HIP call failed; the handle is poisoned */
+  SQA_ERR_UNSUPPORTED = -4, /* valid for the method, outside this library's limits */
+  SQA_ERR_BUSY = -5,        /* server: no slot / memory right now */
+  SQA_ERR_NOT_READY = -6    /* server: result not finished yet */
+} sqa_status;
+
+typedef enum { SQA_EMB_ME = 0, SQA_EMB_LHZ = 1 } sqa_emb_kind;
+
+/* Eq. (1): H_P = sum_i h_i s_i + sum_{i<j} J_ij s_i s_j. */
+typedef struct {
+  int32_t n;          /* logical spins; ME: 2..256, LHZ: 3..256 */
+  const int32_t *J;   /* n*n, row-major, i<j read */
+  const int32_t *h;   /* n or NULL; must be NULL/zero for LHZ (ancilla not supported) */
+} sqa_problem;
+
+typedef struct {
+  int32_t kind;       /* sqa_emb_kind */
+  int32_t penalty;    /* ME: J_F; LHZ: C (signed coefficient, e.g. -2) */
+} sqa_embedding;
+
+/* Annealing schedule (Eq. (2)): sweep m uses Gamma_m (transverse field A) and
+ * B_m.  Gamma_m = gamma_start (1 - t) + gamma_end t, t = m / (sweeps - 1),
+ * unless `gamma` supplies all `sweeps` values; B_m = 1 unless `bscale` does.
+ * Trotter slices L: 1 (classical) or even, at most 64. */
+typedef struct {
+  double beta;        /* inverse temperature, > 0 */
+  int32_t slices;     /* L */
+  int32_t sweeps;     /* M >= 1 */
+  int32_t replicas;   /* independent Markov chains, 1..65536 */
+  double gamma_start;
+  double gamma_end;
+  const double *gamma;   /* [sweeps] or NULL */
+  const double *bscale;  /* [sweeps] or NULL */
+  uint64_t seed;         /* Philox key */
+} sqa_schedule;
+
+typedef struct sqa_handle sqa_handle;
+typedef struct sqa_batch sqa_batch;
+typedef struct pt_handle pt_handle;
+typedef struct sqa_server sqa_server;
+
+/* Launch shape of the persistent sweep kernel.  Every field 0 = choose
+ * automatically (the autotuner's cached choice for this device and shape). */
+typedef struct {
+  int32_t waves_per_group;    /* replicas processed together by one workgroup: 1, 2, 4 or 8 */
+  int32_t groups_per_cu;      /* resident workgroups per compute unit targeted by the grid */
+} sqa_launch_config;
+
+/* ---------------------------------------------------------------- SQA */
+
+/* Builds the embedding (Sec. II A / II B), its four-colour update classes,
+ * the per-sweep acceptance-threshold table and the device buffers.  No
+ * device work is queued; the lattice is initialised by the first anneal.
+ * Errors: SQA_ERR_INVALID (null pointers, n out of range, slices odd > 1,
+ * sweeps < 1, replicas out of range, beta <= 0, negative Gamma, |field| sum
+ * per site > 127), SQA_ERR_UNSUPPORTED (LHZ with h != 0, slices > 64),
+ * SQA_ERR_OOM, SQA_ERR_DEVICE. */
+SQA_API sqa_status sqa_create(const sqa_problem *problem, const sqa_embedding *embedding,
+                      const sqa_schedule *schedule, sqa_handle **out);
+
+/* Runs sweeps 0..M-1 from the seeded initial state (Philox INIT stream) and
+ * computes per-slice energies.  Asynchronous on `stream`. */
+SQA_API sqa_status sqa_anneal(sqa_handle *h, void *stream);
+
+/* Runs sweeps m0..m1-1 (0 <= m0 < m1 <= M) on the current device state
+ * (initialising it first if no sweep has run), then recomputes energies.
+ * Splitting 0..M into ranges gives bit-identical results (checkpoint/resume). */
+SQA_API sqa_status sqa_anneal_range(sqa_handle *h, int32_t m0, int32_t m1, void *stream);
+
+/* Resets the device state to the seeded initial lattice. */
+SQA_API sqa_status sqa_reset(sqa_handle *h, void *stream);
+
+/* Waits for the handle's queued work.  SQA_ERR_DEVICE if it failed. */
+SQA_API sqa_status sqa_sync(sqa_handle *h);
+
+/* Copies the spins [replica][slice][site] (len >= replicas*slices*sites) or
+ * the energies [replica][slice] to host memory, after waiting for the handle. */
+SQA_API sqa_status sqa_read_spins(sqa_handle *h, int8_t *out, size_t len);
+SQA_API sqa_status sqa_read_energies(sqa_handle *h, int32_t *out, size_t len);
+
+/* Replaces the device state (checkpoint restore); values must be +1/-1. */
+SQA_API sqa_status sqa_write_spins(sqa_handle *h, const int8_t *in, size_t len);
+
+/* Device addresses of the spin and energy buffers (for zero-copy use from
+ * frameworks that wrap device pointers).  Owned by the handle. */
+SQA_API void *sqa_device_spins(sqa_handle *h);
+SQA_API void *sqa_device_energies(sqa_handle *h);
+
+/* Decoders, on slice `readout_slice` of every replica.
+ *   SQA_DEC_ME_MAJORITY  Eq. (4): qbar_i = sign(sum of chain i), tie -> +1.
+ *                        Runs on the device.
+ *   SQA_DEC_LHZ_TREES    Eq. (5): majority over n_trees spanning trees given
+ *                        as parent arrays tree_parents[n_trees][n] rooted at
+ *                        logical spin 0 (parent -1), qbar_0 = +1, tie -> +1.
+ *   SQA_DEC_LHZ_MWD      Sec. IV A: the constraint-satisfying state nearest in
+ *                        Hamming distance; exact search over 2^(n-1) logical
+ *                        states with qbar_0 = +1, ties -> the candidate whose
+ *                        bit pattern (bit b set <=> qbar_{b+1} = -1) is smallest.
+ * Outputs: logical_out[replica][n] (+1/-1) and logical_energy_out[replica]
+ * (Eq. (1) of the decoded state); either may be NULL.  Blocking.
+ * Errors: SQA_ERR_INVALID on a decoder/embedding mismatch or bad slice;
+ * SQA_ERR_UNSUPPORTED for MWD with n > 30. */
+typedef enum { SQA_DEC_ME_MAJORITY = 0, SQA_DEC_LHZ_TREES = 1, SQA_DEC_LHZ_MWD = 2 } sqa_decoder;
+SQA_API sqa_status sqa_decode(sqa_handle *h, int32_t decoder, int32_t readout_slice,
+                      const int32_t *tree_parents, int32_t n_trees,
+                      int8_t *logical_out, int32_t *logical_energy_out);
+
+/* Uniform random labelled spanning trees of K_n (Pruefer sequences drawn from
+ * the Philox TREE stream keyed by `seed`), as parent arrays rooted at 0:
+ * parents_out[n_trees][n]. */
+SQA_API sqa_status sqa_random_trees(uint64_t seed, int32_t n, int32_t n_trees, int32_t *parents_out);
+
+/* Exports the handle's acceptance-threshold table T[m][a+F][(b+2)/2]
+ * (uint32, M*(2F+1)*3 entries) and F, for parity checks. */
+SQA_API sqa_status sqa_export_table(sqa_handle *h, uint32_t *out, size_t len, int32_t *F_out);
+
+/* Shape queries. */
+SQA_API int64_t sqa_physical_sites(int32_t kind, int32_t n);
+SQA_API sqa_status sqa_handle_info(sqa_handle *h, int32_t *sites, int32_t *slices, int32_t *replicas,
+                           int32_t *sweeps, int32_t *fmax);
+
+SQA_API void sqa_destroy(sqa_handle *h);
+
+/* ------------------------------------------------------- batched SQA */
+
+/* A batch runs every handle's full anneal (init, sweeps 0..M-1, energies) in
+ * ONE persistent launch: work items (handle, group of replicas) are sorted
+ * by cost (longest first) and pulled from a device work counter.  The launch
+ * sequence is captured once in a HIP graph and replayed by sqa_batch_run.
+ * `config` NULL or zero fields = autotuned.  The handles must outlive the
+ * batch and must not be used concurrently with it. */
+SQA_API sqa_status sqa_batch_create(sqa_handle *const *handles, int32_t count,
+                            const sqa_launch_config *config, sqa_batch **out);
+SQA_API sqa_status sqa_batch_run(sqa_batch *b, void *stream);
+SQA_API sqa_status sqa_batch_config(sqa_batch *b, sqa_launch_config *out);
+SQA_API void sqa_batch_destroy(sqa_batch *b);
+
+/* One-shot convenience: create, run on `stream`, destroy (no graph reuse). */
+SQA_API sqa_status sqa_anneal_batch(sqa_handle *const *handles, int32_t count, void *stream);
+
+/* Autotuner: times candidate launch shapes on the given handles (short
+ * sweep ranges, device state restored afterwards) and stores the best per
+ * (device architecture, shape class) in the JSON cache at `cache_path`
+ * (NULL = $SQA_AUTOTUNE_CACHE or no file).  Returns the choice in *best. */
+SQA_API sqa_status sqa_autotune(sqa_handle *const *handles, int32_t count, const char *cache_path,
+                        sqa_launch_config *best);
+
+/* ------------------------------------------------------ parallel tempering */
+
+/* Appendix B: `temps` replicas of the classical embedded Hamiltonian at
+ * beta_r = beta_max (beta_min/beta_max)^(r/(temps-1)) (slot 0 coldest),
+ * single-spin Metropolis sweeps, and after every sweeps_per_swap sweeps one
+ * swap phase (even slot pairs, then odd pairs) with Eq. (B1)'s probability.
+ * temps: 1..64. */
+typedef struct {
+  double beta_min;
+  double beta_max;
+  int32_t temps;
+  int32_t sweeps;
+  int32_t sweeps_per_swap;
+  uint64_t seed;
+} pt_params;
+
+SQA_API sqa_status pt_create(const sqa_problem *problem, const sqa_embedding *embedding,
+                     const pt_params *params, pt_handle **out);
+/* Runs the whole PT schedule from the seeded initial state. */
+SQA_API sqa_status pt_run_handle(pt_handle *h, void *stream);
+/* All handles in one launch (one workgroup per ladder). */
+SQA_API sqa_status pt_run_batch(pt_handle *const *handles, int32_t count, void *stream);
+/* Results after a run, blocking.  spins_out[temp][site] and energies_out[temp]
+ * are ordered BY SLOT (temperature), slot_to_replica_out[temp] gives the
+ * replica in each slot, swap_accepts_out[temps-1] counts accepted swaps per
+ * slot pair.  Any output may be NULL. */
+SQA_API sqa_status pt_read(pt_handle *h, int8_t *spins_out, size_t spins_len, int32_t *energies_out,
+                   int32_t *slot_to_replica_out, uint64_t *swap_accepts_out);
+SQA_API void pt_destroy(pt_handle *h);
+
+/* One-shot: create, run, read, destroy. */
+SQA_API sqa_status pt_run(const sqa_problem *problem, const sqa_embedding *embedding,
+                  const pt_params *params, void *stream, int8_t *spins_out, size_t spins_len,
+                  int32_t *energies_out, int32_t *slot_to_replica_out,
+                  uint64_t *swap_accepts_out);
+
+/* ------------------------------------------------------------- serving */
+
+/* Continuous batching.  Jobs are admitted while their device bytes fit in
+ * `hbm_budget_bytes` and fewer than `max_slots` are resident; admitted jobs
+ * advance together, `chunk_sweeps` sweeps per persistent launch, and a job
+ * that finishes frees its slot and memory for the next waiting job at the
+ * following launch boundary.  Results are bit-identical to running the job
+ * alone.  A server thread owns the device work. */
+SQA_API sqa_status sqa_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t chunk_sweeps,
+                             sqa_server **out);
+/* Queues a job (inputs deep-copied).  SQA_ERR_INVALID for a bad job,
+ * SQA_ERR_BUSY if the job alone exceeds the budget. */
+SQA_API sqa_status sqa_server_submit(sqa_server *s, const sqa_problem *problem,
+                             const sqa_embedding *embedding, const sqa_schedule *schedule,
+                             uint64_t *ticket);
+/* *done = 1 once the result is on the host. */
+SQA_API sqa_status sqa_server_poll(sqa_server *s, uint64_t ticket, int32_t *done);
+/* Blocks until done (timeout_ms < 0: forever); SQA_ERR_NOT_READY on timeout. */
+SQA_API sqa_status sqa_server_wait(sqa_server *s, uint64_t ticket, int32_t timeout_ms);
+/* Copies a finished job's spins [replica][slice][site] and energies
+ * [replica][slice]; either may be NULL.  Latency in seconds from submit to
+ * result-on-host goes to *latency_s (may be NULL).  The ticket is released. */
+SQA_API sqa_status sqa_server_result(sqa_server *s, uint64_t ticket, int8_t *spins, size_t spins_len,
+                             int32_t *energies, size_t energies_len, double *latency_s);
+/* Counters: completed jobs, device launches, peak resident bytes. */
+SQA_API sqa_status sqa_server_stats(sqa_server *s, uint64_t *completed, uint64_t *launches,
+                            uint64_t *peak_bytes);
+SQA_API void sqa_server_destroy(sqa_server *s);
+
+/* ------------------------------------------------------------- misc */
+SQA_API const char *sqa_last_error(void);
+SQA_API const char *sqa_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SQA_MI355X_H */

@@ -198,9 +198,10 @@ def swap_table(betas, Dmax):
 
 
 # ---------------------------------------------------------------- SQA
-def sqa_init(emb: Embedding, L, R, seed):
+def sqa_init(emb: Embedding, L, R, seed, r0=0):
+    """Initial lattices of replicas r0..r0+R-1."""
     out = np.zeros((R, L, emb.n_sites), dtype=np.int8)
-    lib().oracle_sqa_init(emb.ptr, L, R, C.c_uint64(seed), _p(out, C.c_int8))
+    lib().oracle_sqa_init_from(emb.ptr, L, r0, R, C.c_uint64(seed), _p(out, C.c_int8))
     return out
 
 
@@ -220,13 +221,13 @@ def sqa_attempt_threshold(emb: Embedding, L, table, lat, k, tau, m) -> int:
                                                   _p(lat, C.c_int8), k, tau, m))
 
 
-def sqa_run(emb: Embedding, L, spins, m0, m1, table, seed, nthreads=1):
-    """Runs sweeps m0..m1-1 in place on spins[R][L][n]."""
+def sqa_run(emb: Embedding, L, spins, m0, m1, table, seed, nthreads=1, r0=0):
+    """Runs sweeps m0..m1-1 in place on spins[R][L][n] holding replicas r0..r0+R-1."""
     assert spins.dtype == np.int8 and spins.flags.c_contiguous
     table = np.ascontiguousarray(table, dtype=np.uint32)
     F = (table.shape[1] - 1) // 2
-    lib().oracle_sqa_run(emb.ptr, L, spins.shape[0], m0, m1, _p(table, C.c_uint32), F,
-                         C.c_uint64(seed), _p(spins, C.c_int8), nthreads)
+    lib().oracle_sqa_run_from(emb.ptr, L, r0, spins.shape[0], m0, m1, _p(table, C.c_uint32), F,
+                              C.c_uint64(seed), _p(spins, C.c_int8), nthreads)
     return spins
 
 
@@ -239,16 +240,16 @@ def sqa_energies(emb: Embedding, spins):
 
 
 def sqa_anneal(kind, J, penalty, beta, L, sweeps, replicas, gamma0, gamma1, seed,
-               h=None, gamma=None, bscale=None, nthreads=1, fmax=None):
-    """The whole single-instance SQA path: embed, tabulate, init, anneal, energies.
-    `fmax` widens the table's field range beyond the embedding's own (results do not
-    depend on it)."""
+               h=None, gamma=None, bscale=None, nthreads=1, fmax=None, r0=0):
+    """The whole single-instance SQA path: embed, tabulate, init, anneal, energies,
+    for replicas r0..r0+replicas-1.  `fmax` widens the table's field range beyond the
+    embedding's own (results do not depend on it)."""
     emb = Embedding(kind, J, penalty, h)
     g = gamma_schedule(gamma0, gamma1, sweeps) if gamma is None else np.asarray(gamma, dtype=np.float64)
     F = emb.fmax if fmax is None else fmax
     table = sqa_table(beta, L, g, F, bscale)
-    spins = sqa_init(emb, L, replicas, seed)
-    sqa_run(emb, L, spins, 0, sweeps, table, seed, nthreads)
+    spins = sqa_init(emb, L, replicas, seed, r0)
+    sqa_run(emb, L, spins, 0, sweeps, table, seed, nthreads, r0)
     return emb, table, spins, sqa_energies(emb, spins)
 
 

@@ -79,6 +79,7 @@ void oracle_swap_table(const double *betas, int32_t R, int32_t Dmax, uint32_t *o
 
 /* ---- SQA ----------------------------------------------------------------- */
 void oracle_sqa_init(const OEmb *e, int32_t L, int32_t R, uint64_t seed, int8_t *spins);
+void oracle_sqa_init_from(const OEmb *e, int32_t L, int32_t r0, int32_t R, uint64_t seed, int8_t *spins);
 int32_t oracle_sqa_sweep_order(const OEmb *e, int32_t L, int32_t *site_out, int32_t *slice_out);
 uint32_t oracle_sqa_attempt_threshold(const OEmb *e, int32_t L, const uint32_t *table,
                                       int32_t F, const int8_t *lat, int32_t k,
@@ -86,6 +87,9 @@ uint32_t oracle_sqa_attempt_threshold(const OEmb *e, int32_t L, const uint32_t *
 void oracle_sqa_run(const OEmb *e, int32_t L, int32_t R, int32_t m0, int32_t m1,
                     const uint32_t *table, int32_t F, uint64_t seed,
                     int8_t *spins, int32_t nthreads);
+void oracle_sqa_run_from(const OEmb *e, int32_t L, int32_t r0, int32_t R, int32_t m0, int32_t m1,
+                         const uint32_t *table, int32_t F, uint64_t seed,
+                         int8_t *spins, int32_t nthreads);
 void oracle_sqa_energies(const OEmb *e, int32_t L, int32_t R, const int8_t *spins,
                          int32_t *E);
 

@@ -22,15 +22,20 @@
 #include <stdlib.h>
 #include "oracle.h"
 
-void oracle_sqa_init(const OEmb *e, int32_t L, int32_t R, uint64_t seed, int8_t *spins) {
+/* Replicas r0 .. r0+R-1 into spins[R][L][n]. */
+void oracle_sqa_init_from(const OEmb *e, int32_t L, int32_t r0, int32_t R, uint64_t seed, int8_t *spins) {
   int n = e->n_sites;
   for (int r = 0; r < R; ++r)
     for (int tau = 0; tau < L; ++tau)
       for (int k = 0; k < n; ++k) {
-        uint32_t u = oracle_sqa_word(seed, OR_STREAM_INIT, (uint32_t)r, (uint32_t)k,
+        uint32_t u = oracle_sqa_word(seed, OR_STREAM_INIT, (uint32_t)(r0 + r), (uint32_t)k,
                                      (uint32_t)tau, 0u);
         spins[((size_t)r * L + tau) * n + k] = (u >> 31) ? (int8_t)-1 : (int8_t)1;
       }
+}
+
+void oracle_sqa_init(const OEmb *e, int32_t L, int32_t R, uint64_t seed, int8_t *spins) {
+  oracle_sqa_init_from(e, L, 0, R, seed, spins);
 }
 
 /* The attempt sequence of one sweep; returns its length n*L. */
@@ -83,7 +88,7 @@ static void run_replica(const OEmb *e, int32_t L, int32_t r, int32_t m0, int32_t
 
 typedef struct {
   const OEmb *e;
-  int32_t L, R, m0, m1, F, first, stride;
+  int32_t L, r0, R, m0, m1, F, first, stride;
   const uint32_t *table;
   uint64_t seed;
   int8_t *spins;
@@ -93,21 +98,22 @@ static void *worker(void *arg) {
   Job *j = (Job *)arg;
   size_t per = (size_t)j->L * j->e->n_sites;
   for (int r = j->first; r < j->R; r += j->stride)
-    run_replica(j->e, j->L, r, j->m0, j->m1, j->table, j->F, j->seed, j->spins + per * r);
+    run_replica(j->e, j->L, j->r0 + r, j->m0, j->m1, j->table, j->F, j->seed, j->spins + per * r);
   return NULL;
 }
 
-/* Sweeps m0 .. m1-1 on replicas 0 .. R-1 of spins[R][L][n].  Replicas are
- * independent lattices; nthreads > 1 spreads them over host threads. */
-void oracle_sqa_run(const OEmb *e, int32_t L, int32_t R, int32_t m0, int32_t m1,
-                    const uint32_t *table, int32_t F, uint64_t seed,
-                    int8_t *spins, int32_t nthreads) {
+/* Sweeps m0 .. m1-1 on replicas r0 .. r0+R-1 held in spins[R][L][n].
+ * Replicas are independent lattices; nthreads > 1 spreads them over host
+ * threads. */
+void oracle_sqa_run_from(const OEmb *e, int32_t L, int32_t r0, int32_t R, int32_t m0, int32_t m1,
+                         const uint32_t *table, int32_t F, uint64_t seed,
+                         int8_t *spins, int32_t nthreads) {
   if (nthreads < 1) nthreads = 1;
   if (nthreads > R) nthreads = R;
   Job *jobs = (Job *)malloc(sizeof(Job) * (size_t)(nthreads > 0 ? nthreads : 1));
   pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * (size_t)(nthreads > 0 ? nthreads : 1));
   for (int t = 0; t < nthreads; ++t) {
-    Job j = {e, L, R, m0, m1, F, t, nthreads, table, seed, spins};
+    Job j = {e, L, r0, R, m0, m1, F, t, nthreads, table, seed, spins};
     jobs[t] = j;
   }
   for (int t = 1; t < nthreads; ++t) pthread_create(&th[t], NULL, worker, &jobs[t]);
@@ -115,6 +121,12 @@ void oracle_sqa_run(const OEmb *e, int32_t L, int32_t R, int32_t m0, int32_t m1,
   for (int t = 1; t < nthreads; ++t) pthread_join(th[t], NULL);
   free(jobs);
   free(th);
+}
+
+void oracle_sqa_run(const OEmb *e, int32_t L, int32_t R, int32_t m0, int32_t m1,
+                    const uint32_t *table, int32_t F, uint64_t seed,
+                    int8_t *spins, int32_t nthreads) {
+  oracle_sqa_run_from(e, L, 0, R, m0, m1, table, F, seed, spins, nthreads);
 }
 
 /* E[r][tau] = energy of slice tau of replica r. */

@@ -1,0 +1,257 @@
+// C ABI: parallel tempering handles (Appendix B, Eqs. (B1)-(B2)).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "host_core.h"
+
+using namespace sqa;
+
+struct pt_handle {
+  Embedded emb;
+  DeviceLayout lay;
+  int32_t R = 0, F = 0, Dmax = 0, sweeps = 0, sps = 1;
+  uint64_t seed = 0;
+  std::vector<double> betas;
+  std::vector<uint32_t> mtab, stab;
+  Arena arena;
+  size_t off_rec = 0, off_devof = 0, off_hfield = 0, off_tw = 0, off_ts = 0, off_mtab = 0, off_stab = 0,
+         off_spins = 0, off_energy = 0, off_repat = 0, off_acc = 0, off_pd = 0;
+  bool ran = false;
+  bool poisoned = false;
+  hipEvent_t done = nullptr;
+
+  PTDev dev() const {
+    PTDev P{};
+    P.rec = arena.at<uint32_t>(off_rec);
+    P.hfield = arena.at<int32_t>(off_hfield);
+    P.term_w = arena.at<int32_t>(off_tw);
+    P.term_s = arena.at<uint32_t>(off_ts);
+    P.mtab = arena.at<uint32_t>(off_mtab);
+    P.stab = arena.at<uint32_t>(off_stab);
+    P.dev_of = arena.at<uint16_t>(off_devof);
+    P.spins = arena.at<int8_t>(off_spins);
+    P.energy = arena.at<int32_t>(off_energy);
+    P.rep_at = arena.at<int32_t>(off_repat);
+    P.swap_acc = arena.at<uint64_t>(off_acc);
+    P.kind = emb.kind;
+    P.n = emb.n;
+    P.n_terms = static_cast<int32_t>(emb.terms.size());
+    P.R = R;
+    P.F = F;
+    P.Dmax = Dmax;
+    P.sweeps = sweeps;
+    P.sweeps_per_swap = sps;
+    P.seed_lo = static_cast<uint32_t>(seed);
+    P.seed_hi = static_cast<uint32_t>(seed >> 32);
+    for (int c = 0; c < 5; ++c) P.cls[c] = lay.cls[c];
+    return P;
+  }
+};
+
+namespace {
+
+struct PTShape {
+  int waves = 4;
+  int rec_cap = 0, lat_cap = 0, mtab_cap = 0;
+  size_t lds() const { return (static_cast<size_t>(rec_cap) + 2ull * lat_cap + mtab_cap + 256) * 4; }
+};
+
+PTShape pt_shape(const std::vector<const pt_handle *> &hs) {
+  PTShape s;
+  int maxn = 0;
+  for (const pt_handle *h : hs) {
+    s.rec_cap = std::max(s.rec_cap, h->emb.n * h->lay.rec_words);
+    s.lat_cap = std::max(s.lat_cap, h->emb.n + 1);
+    s.mtab_cap = std::max(s.mtab_cap, h->R * (2 * h->F + 1));
+    maxn = std::max(maxn, h->emb.n);
+  }
+  s.rec_cap = (s.rec_cap + 3) & ~3;
+  s.lat_cap = (s.lat_cap + 1) & ~1;
+  s.mtab_cap = (s.mtab_cap + 3) & ~3;
+  // enough lanes for one item per lane on the largest colour class
+  s.waves = maxn > 300 ? 8 : 4;
+  return s;
+}
+
+sqa_status pt_launch(const std::vector<pt_handle *> &hs, hipStream_t stream) {
+  std::vector<const pt_handle *> ch(hs.begin(), hs.end());
+  PTShape s = pt_shape(ch);
+  if (s.lds() > kMaxLds) return fail(SQA_ERR_UNSUPPORTED, "PT ladder does not fit in LDS");
+  (void)set_pt_lds_limit(kMaxLds);
+  (void)hipGetLastError();
+  hipError_t e = hipSuccess;
+  std::vector<PTDev> pds;
+  for (pt_handle *h : hs) {
+    e = hipEventSynchronize(h->done);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    pds.push_back(h->dev());
+  }
+  void *dev = nullptr;
+  e = hipMalloc(&dev, sizeof(PTDev) * pds.size());
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc (PT descriptors)");
+  e = hipMemcpy(dev, pds.data(), sizeof(PTDev) * pds.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = launch_pt(static_cast<const PTDev *>(dev), static_cast<int>(pds.size()), s.waves, s.rec_cap, s.lat_cap,
+                  s.mtab_cap, stream);
+  if (e == hipSuccess)
+    for (pt_handle *h : hs) {
+      e = hipEventRecord(h->done, stream);
+      if (e != hipSuccess) break;
+    }
+  hipError_t e2 = hipStreamSynchronize(stream);
+  (void)hipFree(dev);
+  if (e == hipSuccess) e = e2;
+  if (e != hipSuccess) {
+    for (pt_handle *h : hs) h->poisoned = true;
+    return hip_fail(e, "PT launch");
+  }
+  for (pt_handle *h : hs) h->ran = true;
+  return SQA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sqa_status pt_create(const sqa_problem *problem, const sqa_embedding *embedding, const pt_params *params,
+                     pt_handle **out) {
+  if (!problem || !embedding || !params || !out || !problem->J) return fail(SQA_ERR_INVALID, "null argument");
+  *out = nullptr;
+  const pt_params &p = *params;
+  if (p.temps < 1 || p.temps > 64) return fail(SQA_ERR_INVALID, "temps must be in 1..64");
+  if (p.sweeps < 1 || p.sweeps_per_swap < 1) return fail(SQA_ERR_INVALID, "sweeps and sweeps_per_swap must be >= 1");
+  if (!(p.beta_min > 0) || !(p.beta_max >= p.beta_min) || !std::isfinite(p.beta_max))
+    return fail(SQA_ERR_INVALID, "need 0 < beta_min <= beta_max");
+  pt_handle *h = new (std::nothrow) pt_handle();
+  if (!h) return fail(SQA_ERR_OOM, "host allocation");
+  sqa_status st = build_embedding(*problem, *embedding, &h->emb);
+  if (st == SQA_OK) st = build_layout(h->emb, h->emb.fmax, &h->lay);
+  if (st != SQA_OK) {
+    delete h;
+    return st;
+  }
+  h->R = p.temps;
+  h->F = h->emb.fmax;
+  h->Dmax = 2 * h->emb.emax;
+  h->sweeps = p.sweeps;
+  h->sps = p.sweeps_per_swap;
+  h->seed = p.seed;
+  h->betas = pt_betas(p.beta_min, p.beta_max, p.temps);
+  h->mtab = pt_metropolis_table(h->betas, h->F);
+  h->stab = pt_swap_table(h->betas, h->Dmax);
+  const int n = h->emb.n;
+  const size_t nt = h->emb.terms.size();
+  Arena &A = h->arena;
+  h->off_rec = A.take(h->lay.rec.size() * 4);
+  h->off_devof = A.take(static_cast<size_t>(n) * 2);
+  h->off_hfield = A.take(static_cast<size_t>(n) * 4);
+  h->off_tw = A.take(std::max<size_t>(nt, 1) * 4);
+  h->off_ts = A.take(std::max<size_t>(nt, 1) * 8);
+  h->off_mtab = A.take(h->mtab.size() * 4);
+  h->off_stab = A.take(h->stab.size() * 4);
+  h->off_spins = A.take(static_cast<size_t>(h->R) * n);
+  h->off_energy = A.take(static_cast<size_t>(h->R) * 4);
+  h->off_repat = A.take(static_cast<size_t>(h->R) * 4);
+  h->off_acc = A.take(64 * 8);
+  A.size = A.used;
+  hipError_t e = hipMalloc(&A.base, A.size);
+  if (e != hipSuccess) {
+    delete h;
+    return hip_fail(e, "hipMalloc (PT handle)");
+  }
+  struct Up {
+    size_t off;
+    const void *ptr;
+    size_t bytes;
+  } ups[] = {{h->off_rec, h->lay.rec.data(), h->lay.rec.size() * 4},
+             {h->off_devof, h->lay.dev_of.data(), static_cast<size_t>(n) * 2},
+             {h->off_hfield, h->lay.hfield.data(), static_cast<size_t>(n) * 4},
+             {h->off_tw, h->lay.term_w.data(), nt * 4},
+             {h->off_ts, h->lay.term_s.data(), nt * 8},
+             {h->off_mtab, h->mtab.data(), h->mtab.size() * 4},
+             {h->off_stab, h->stab.data(), h->stab.size() * 4}};
+  for (const Up &u : ups) {
+    if (!u.bytes) continue;
+    e = hipMemcpy(A.at<char>(u.off), u.ptr, u.bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) break;
+  }
+  if (e == hipSuccess) e = hipMemset(A.at<char>(h->off_acc), 0, 64 * 8);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&h->done, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    (void)hipFree(A.base);
+    delete h;
+    return hip_fail(e, "PT handle setup");
+  }
+  *out = h;
+  return SQA_OK;
+}
+
+sqa_status pt_run_handle(pt_handle *h, void *stream) {
+  if (!h) return fail(SQA_ERR_INVALID, "null handle");
+  if (h->poisoned) return fail(SQA_ERR_DEVICE, "handle is poisoned");
+  return pt_launch({h}, static_cast<hipStream_t>(stream));
+}
+
+sqa_status pt_run_batch(pt_handle *const *handles, int32_t count, void *stream) {
+  if (!handles || count < 1) return fail(SQA_ERR_INVALID, "bad batch arguments");
+  std::vector<pt_handle *> hs(handles, handles + count);
+  for (pt_handle *h : hs) {
+    if (!h) return fail(SQA_ERR_INVALID, "null handle");
+    if (h->poisoned) return fail(SQA_ERR_DEVICE, "handle is poisoned");
+  }
+  return pt_launch(hs, static_cast<hipStream_t>(stream));
+}
+
+sqa_status pt_read(pt_handle *h, int8_t *spins_out, size_t spins_len, int32_t *energies_out,
+                   int32_t *slot_to_replica_out, uint64_t *swap_accepts_out) {
+  if (!h) return fail(SQA_ERR_INVALID, "null handle");
+  if (!h->ran) return fail(SQA_ERR_INVALID, "run the handle first");
+  hipError_t e = hipEventSynchronize(h->done);
+  if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+  const int R = h->R, n = h->emb.n;
+  std::vector<int8_t> sp(static_cast<size_t>(R) * n);
+  std::vector<int32_t> E(R), rep(R);
+  std::vector<uint64_t> acc(64);
+  e = hipMemcpy(sp.data(), h->arena.at<void>(h->off_spins), sp.size(), hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(E.data(), h->arena.at<void>(h->off_energy), R * 4, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(rep.data(), h->arena.at<void>(h->off_repat), R * 4, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(acc.data(), h->arena.at<void>(h->off_acc), 64 * 8, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy (PT results)");
+  if (spins_out) {
+    if (spins_len < sp.size()) return fail(SQA_ERR_INVALID, "spin buffer too short");
+    for (int slot = 0; slot < R; ++slot)
+      std::memcpy(spins_out + static_cast<size_t>(slot) * n, sp.data() + static_cast<size_t>(rep[slot]) * n, n);
+  }
+  if (energies_out)
+    for (int slot = 0; slot < R; ++slot) energies_out[slot] = E[rep[slot]];
+  if (slot_to_replica_out) std::memcpy(slot_to_replica_out, rep.data(), R * 4);
+  if (swap_accepts_out)
+    for (int r = 0; r + 1 < R; ++r) swap_accepts_out[r] = acc[r];
+  return SQA_OK;
+}
+
+void pt_destroy(pt_handle *h) {
+  if (!h) return;
+  if (h->done) {
+    (void)hipEventSynchronize(h->done);
+    (void)hipEventDestroy(h->done);
+  }
+  if (h->arena.base) (void)hipFree(h->arena.base);
+  delete h;
+}
+
+sqa_status pt_run(const sqa_problem *problem, const sqa_embedding *embedding, const pt_params *params, void *stream,
+                  int8_t *spins_out, size_t spins_len, int32_t *energies_out, int32_t *slot_to_replica_out,
+                  uint64_t *swap_accepts_out) {
+  pt_handle *h = nullptr;
+  sqa_status st = pt_create(problem, embedding, params, &h);
+  if (st != SQA_OK) return st;
+  st = pt_run_handle(h, stream);
+  if (st == SQA_OK) st = pt_read(h, spins_out, spins_len, energies_out, slot_to_replica_out, swap_accepts_out);
+  pt_destroy(h);
+  return st;
+}
+
+}  // extern "C"

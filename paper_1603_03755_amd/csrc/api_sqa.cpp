@@ -1,0 +1,938 @@
+// C ABI: SQA handles, batched persistent launches, decoders, autotuner.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "host_core.h"
+
+using namespace sqa;
+
+namespace sqa {
+const char *last_error_cstr();
+
+// Pinned staging of one single-handle launch descriptor.
+struct Staging {
+  HandleDev hd;
+  WorkItem items[1];
+};
+
+static std::once_flag g_lds_once;
+static hipError_t g_lds_status = hipSuccess;
+
+// Raises the kernels' dynamic-LDS limit where the runtime supports the
+// attribute; a refusal is not an error (launches above the default limit then
+// fail and are reported at launch).
+static hipError_t ensure_lds_limits() {
+  std::call_once(g_lds_once, [] {
+    (void)set_sqa_anneal_lds_limit(kMaxLds);
+    (void)set_pt_lds_limit(kMaxLds);
+    (void)hipGetLastError();
+  });
+  return g_lds_status;
+}
+
+// Work items (handle, replica group) for a set of handles, longest first.
+static std::vector<WorkItem> plan_items(const std::vector<const sqa_handle *> &hs, const std::vector<int> &m0,
+                                        const std::vector<int> &m1, int waves) {
+  std::vector<std::pair<double, WorkItem>> v;
+  for (size_t i = 0; i < hs.size(); ++i) {
+    const sqa_handle *h = hs[i];
+    const double cost = static_cast<double>(h->emb.n) * h->L * std::max(1, m1[i] - m0[i]);
+    for (int r = 0; r < h->R; r += waves) {
+      WorkItem w{static_cast<int32_t>(i), r, std::min(waves, h->R - r)};
+      v.push_back({cost * w.nrep / waves, w});
+    }
+  }
+  std::stable_sort(v.begin(), v.end(), [](const auto &a, const auto &b) { return a.first > b.first; });
+  std::vector<WorkItem> out;
+  out.reserve(v.size());
+  for (auto &p : v) out.push_back(p.second);
+  return out;
+}
+
+static LaunchShape shape_for(const std::vector<const sqa_handle *> &hs, int waves, int groups_per_cu,
+                             size_t n_items) {
+  LaunchShape s;
+  s.waves = waves;
+  for (const sqa_handle *h : hs) {
+    s.rec_cap = std::max(s.rec_cap, h->emb.n * h->lay.rec_words);
+    s.lat_cap = std::max(s.lat_cap, h->emb.n + 1);
+    s.tab_cap = std::max(s.tab_cap, h->tw);
+  }
+  s.rec_cap = (s.rec_cap + 3) & ~3;
+  s.lat_cap = (s.lat_cap + 1) & ~1;
+  s.tab_cap = (s.tab_cap + 3) & ~3;
+  int gpc = groups_per_cu > 0 ? groups_per_cu : occupancy_groups_per_cu(s);
+  long long grid = static_cast<long long>(device_cu_count()) * gpc;
+  s.grid = static_cast<int>(std::max<long long>(1, std::min<long long>(grid, static_cast<long long>(n_items))));
+  return s;
+}
+
+// ---------------------------------------------------------------- autotune cache
+struct TuneKey {
+  std::string arch;
+  std::string cls;
+};
+
+static std::string device_arch() {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+  std::string a = prop.gcnArchName;
+  size_t c = a.find(':');
+  return c == std::string::npos ? a : a.substr(0, c);
+}
+
+// Shape class: largest lattice (sites x slices) rounded up to a power of two,
+// replica count rounded up to a power of two, and whether both kinds are present.
+static std::string shape_class(const std::vector<const sqa_handle *> &hs) {
+  int maxcells = 1, maxrep = 1;
+  bool me = false, lhz = false;
+  for (const sqa_handle *h : hs) {
+    maxcells = std::max(maxcells, h->emb.n * h->L);
+    maxrep = std::max(maxrep, h->R);
+    (h->emb.kind == SQA_EMB_ME ? me : lhz) = true;
+  }
+  auto p2 = [](int v) {
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+  };
+  char buf[96];
+  std::snprintf(buf, sizeof(buf), "cells%d_rep%d_%s", p2(maxcells), p2(maxrep), me && lhz ? "mix" : (me ? "me" : "lhz"));
+  return buf;
+}
+
+static const char *cache_path_or_env(const char *p) {
+  if (p && *p) return p;
+  const char *e = std::getenv("SQA_AUTOTUNE_CACHE");
+  return (e && *e) ? e : nullptr;
+}
+
+// The cache is a flat JSON object {"<arch>/<class>": [waves, groups_per_cu], ...}.
+static std::map<std::string, std::pair<int, int>> read_cache(const char *path) {
+  std::map<std::string, std::pair<int, int>> m;
+  if (!path) return m;
+  std::ifstream f(path);
+  if (!f) return m;
+  std::stringstream ss;
+  ss << f.rdbuf();
+  const std::string s = ss.str();
+  size_t i = 0;
+  while ((i = s.find('"', i)) != std::string::npos) {
+    size_t j = s.find('"', i + 1);
+    if (j == std::string::npos) break;
+    std::string key = s.substr(i + 1, j - i - 1);
+    size_t lb = s.find('[', j), rb = s.find(']', j);
+    if (lb == std::string::npos || rb == std::string::npos) break;
+    int a = 0, b = 0;
+    if (std::sscanf(s.c_str() + lb + 1, "%d , %d", &a, &b) == 2) m[key] = {a, b};
+    i = rb + 1;
+  }
+  return m;
+}
+
+static void write_cache(const char *path, const std::map<std::string, std::pair<int, int>> &m) {
+  if (!path) return;
+  std::ofstream f(path);
+  f << "{\n";
+  size_t k = 0;
+  for (auto &kv : m) {
+    f << "  \"" << kv.first << "\": [" << kv.second.first << ", " << kv.second.second << "]"
+      << (++k < m.size() ? ",\n" : "\n");
+  }
+  f << "}\n";
+}
+
+static std::mutex g_cache_mu;
+
+static bool cached_config(const std::vector<const sqa_handle *> &hs, sqa_launch_config *out) {
+  const char *path = cache_path_or_env(nullptr);
+  if (!path) return false;
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  auto m = read_cache(path);
+  auto it = m.find(device_arch() + "/" + shape_class(hs));
+  if (it == m.end()) return false;
+  out->waves_per_group = it->second.first;
+  out->groups_per_cu = it->second.second;
+  return true;
+}
+
+static void resolve_config(const std::vector<const sqa_handle *> &hs, const sqa_launch_config *cfg, int *waves,
+                           int *gpc) {
+  sqa_launch_config c{0, 0};
+  if (cfg) c = *cfg;
+  if (c.waves_per_group == 0 || c.groups_per_cu == 0) {
+    sqa_launch_config cached{0, 0};
+    if (cached_config(hs, &cached)) {
+      if (c.waves_per_group == 0) c.waves_per_group = cached.waves_per_group;
+      if (c.groups_per_cu == 0) c.groups_per_cu = cached.groups_per_cu;
+    }
+  }
+  *waves = c.waves_per_group > 0 ? c.waves_per_group : 4;
+  *gpc = c.groups_per_cu;   // 0 = from occupancy
+}
+
+static bool valid_waves(int w) { return w == 1 || w == 2 || w == 4 || w == 8; }
+
+}  // namespace sqa
+
+// =================================================================== C ABI
+extern "C" {
+
+const char *sqa_last_error(void) { return sqa::last_error_cstr(); }
+const char *sqa_version(void) { return "sqa-mi355x 0.1 (gfx950)"; }
+
+int64_t sqa_physical_sites(int32_t kind, int32_t n) {
+  if (kind == SQA_EMB_ME) return n >= 2 ? static_cast<int64_t>(n) * (n - 1) : -1;
+  if (kind == SQA_EMB_LHZ) return n >= 3 ? static_cast<int64_t>(n) * (n - 1) / 2 : -1;
+  return -1;
+}
+
+sqa_status sqa_create(const sqa_problem *problem, const sqa_embedding *embedding, const sqa_schedule *schedule,
+                      sqa_handle **out) {
+  if (!problem || !embedding || !schedule || !out) return fail(SQA_ERR_INVALID, "null argument");
+  *out = nullptr;
+  if (!problem->J) return fail(SQA_ERR_INVALID, "J is null");
+  const sqa_schedule &s = *schedule;
+  if (!(s.beta > 0.0) || !std::isfinite(s.beta)) return fail(SQA_ERR_INVALID, "beta must be positive and finite");
+  if (s.slices < 1 || (s.slices > 1 && (s.slices & 1))) return fail(SQA_ERR_INVALID, "slices must be 1 or even");
+  if (s.slices > 64) return fail(SQA_ERR_UNSUPPORTED, "at most 64 Trotter slices");
+  if (s.sweeps < 1) return fail(SQA_ERR_INVALID, "sweeps must be >= 1");
+  if (s.replicas < 1 || s.replicas > 65536) return fail(SQA_ERR_INVALID, "replicas must be in 1..65536");
+  std::vector<double> gamma;
+  if (s.gamma) gamma.assign(s.gamma, s.gamma + s.sweeps);
+  else gamma = linear_gamma(s.gamma_start, s.gamma_end, s.sweeps);
+  for (double g : gamma)
+    if (!(g >= 0.0) || !std::isfinite(g)) return fail(SQA_ERR_INVALID, "Gamma must be finite and >= 0");
+  std::vector<double> bscale;
+  if (s.bscale) {
+    bscale.assign(s.bscale, s.bscale + s.sweeps);
+    for (double b : bscale)
+      if (!std::isfinite(b)) return fail(SQA_ERR_INVALID, "B must be finite");
+  }
+
+  sqa_handle *h = new (std::nothrow) sqa_handle();
+  if (!h) return fail(SQA_ERR_OOM, "host allocation");
+  sqa_status st = build_embedding(*problem, *embedding, &h->emb);
+  if (st != SQA_OK) {
+    delete h;
+    return st;
+  }
+  h->N = problem->n;
+  h->L = s.slices;
+  h->M = s.sweeps;
+  h->R = s.replicas;
+  h->beta = s.beta;
+  h->seed = s.seed;
+  h->F = h->emb.fmax;
+  h->tw = 3 * (2 * h->F + 1);
+  h->J.assign(problem->J, problem->J + static_cast<size_t>(h->N) * h->N);
+  h->h.assign(h->N, 0);
+  if (problem->h) {
+    h->has_h = true;
+    std::copy(problem->h, problem->h + h->N, h->h.begin());
+  }
+  st = build_layout(h->emb, h->F, &h->lay);
+  if (st != SQA_OK) {
+    delete h;
+    return st;
+  }
+  h->table = sqa_threshold_table(s.beta, s.slices, gamma, s.bscale ? &bscale : nullptr, h->F);
+
+  const int n = h->emb.n, R = h->R, L = h->L, N = h->N;
+  const size_t nt = h->emb.terms.size();
+  Arena &A = h->arena;
+  h->off_rec = A.take(h->lay.rec.size() * 4);
+  h->off_devof = A.take(static_cast<size_t>(n) * 2);
+  h->off_hfield = A.take(static_cast<size_t>(n) * 4);
+  h->off_tw = A.take(std::max<size_t>(nt, 1) * 4);
+  h->off_ts = A.take(std::max<size_t>(nt, 1) * 8);
+  h->off_table = A.take(h->table.size() * 4);
+  h->off_spins = A.take(static_cast<size_t>(R) * L * n);
+  h->off_energy = A.take(static_cast<size_t>(R) * L * 4);
+  h->off_J = A.take(static_cast<size_t>(N) * N * 4);
+  h->off_h = A.take(static_cast<size_t>(N) * 4);
+  h->off_logical = A.take(static_cast<size_t>(R) * N);
+  h->off_lenergy = A.take(static_cast<size_t>(R) * 4);
+  h->off_hd = A.take(sizeof(HandleDev));
+  h->off_items = A.take(sizeof(WorkItem) * static_cast<size_t>(R));
+  h->off_counter = A.take(256);
+  A.size = A.used;
+  hipError_t e = hipMalloc(&A.base, A.size);
+  if (e != hipSuccess) {
+    delete h;
+    return hip_fail(e, "hipMalloc (handle)");
+  }
+  h->device_bytes = A.size;
+  struct Up {
+    size_t off;
+    const void *p;
+    size_t bytes;
+  } ups[] = {
+      {h->off_rec, h->lay.rec.data(), h->lay.rec.size() * 4},
+      {h->off_devof, h->lay.dev_of.data(), static_cast<size_t>(n) * 2},
+      {h->off_hfield, h->lay.hfield.data(), static_cast<size_t>(n) * 4},
+      {h->off_tw, h->lay.term_w.data(), nt * 4},
+      {h->off_ts, h->lay.term_s.data(), nt * 8},
+      {h->off_table, h->table.data(), h->table.size() * 4},
+      {h->off_J, h->J.data(), static_cast<size_t>(N) * N * 4},
+      {h->off_h, h->h.data(), static_cast<size_t>(N) * 4},
+  };
+  for (const Up &u : ups) {
+    if (u.bytes == 0) continue;
+    e = hipMemcpy(A.at<char>(u.off), u.p, u.bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(A.base);
+      delete h;
+      return hip_fail(e, "hipMemcpy (handle setup)");
+    }
+  }
+  e = hipEventCreateWithFlags(&h->done, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    (void)hipFree(A.base);
+    delete h;
+    return hip_fail(e, "hipEventCreate");
+  }
+  *out = h;
+  return SQA_OK;
+}
+
+void sqa_destroy(sqa_handle *h) {
+  if (!h) return;
+  if (h->done) {
+    (void)hipEventSynchronize(h->done);
+    (void)hipEventDestroy(h->done);
+  }
+  if (h->arena.base) (void)hipFree(h->arena.base);
+  delete h;
+}
+
+static sqa_status check_handle(sqa_handle *h) {
+  if (!h) return fail(SQA_ERR_INVALID, "null handle");
+  if (h->poisoned) return fail(SQA_ERR_DEVICE, "handle is poisoned by an earlier device error");
+  return SQA_OK;
+}
+
+static sqa_status run_single(sqa_handle *h, int m0, int m1, int flags, hipStream_t stream) {
+  hipError_t e = ensure_lds_limits();
+  if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
+  std::vector<const sqa_handle *> hs{h};
+  int waves = 4, gpc = 0;
+  resolve_config(hs, nullptr, &waves, &gpc);
+  std::vector<WorkItem> items = plan_items(hs, {m0}, {m1}, waves);
+  LaunchShape shape = shape_for(hs, waves, gpc, items.size());
+  if (shape.lds_bytes() > kMaxLds) return fail(SQA_ERR_UNSUPPORTED, "lattice does not fit in LDS");
+  // previous work on this handle must have consumed the staging copy
+  e = hipEventSynchronize(h->done);
+  if (e != hipSuccess) {
+    h->poisoned = true;
+    return hip_fail(e, "hipEventSynchronize");
+  }
+  HandleDev hd = h->dev(m0, m1, flags);
+  e = hipMemcpyAsync(h->arena.at<void>(h->off_hd), &hd, sizeof(hd), hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h->arena.at<void>(h->off_items), items.data(), items.size() * sizeof(WorkItem),
+                       hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess)
+    e = launch_sqa_anneal(h->arena.at<HandleDev>(h->off_hd), h->arena.at<WorkItem>(h->off_items),
+                          static_cast<int>(items.size()), h->arena.at<int>(h->off_counter), shape.grid, shape.waves,
+                          shape.rec_cap, shape.lat_cap, shape.tab_cap, stream);
+  if (e == hipSuccess) e = hipEventRecord(h->done, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);  // host staging above is pageable
+  if (e != hipSuccess) {
+    h->poisoned = true;
+    return hip_fail(e, "anneal launch");
+  }
+  h->initialised = true;
+  return SQA_OK;
+}
+
+sqa_status sqa_anneal(sqa_handle *h, void *stream) {
+  sqa_status st = check_handle(h);
+  if (st != SQA_OK) return st;
+  return run_single(h, 0, h->M, kFlagInit | kFlagEnergy, static_cast<hipStream_t>(stream));
+}
+
+sqa_status sqa_anneal_range(sqa_handle *h, int32_t m0, int32_t m1, void *stream) {
+  sqa_status st = check_handle(h);
+  if (st != SQA_OK) return st;
+  if (m0 < 0 || m1 > h->M || m0 >= m1) return fail(SQA_ERR_INVALID, "need 0 <= m0 < m1 <= sweeps");
+  return run_single(h, m0, m1, (h->initialised ? 0 : kFlagInit) | kFlagEnergy, static_cast<hipStream_t>(stream));
+}
+
+sqa_status sqa_reset(sqa_handle *h, void *stream) {
+  sqa_status st = check_handle(h);
+  if (st != SQA_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = launch_sqa_init(h->dev(0, 0, 0), s);
+  if (e == hipSuccess) e = hipEventRecord(h->done, s);
+  if (e != hipSuccess) {
+    h->poisoned = true;
+    return hip_fail(e, "init launch");
+  }
+  h->initialised = true;
+  return SQA_OK;
+}
+
+sqa_status sqa_sync(sqa_handle *h) {
+  if (!h) return fail(SQA_ERR_INVALID, "null handle");
+  hipError_t e = hipEventSynchronize(h->done);
+  if (e != hipSuccess) {
+    h->poisoned = true;
+    return hip_fail(e, "hipEventSynchronize");
+  }
+  return h->poisoned ? fail(SQA_ERR_DEVICE, "handle is poisoned") : SQA_OK;
+}
+
+sqa_status sqa_read_spins(sqa_handle *h, int8_t *out, size_t len) {
+  sqa_status st = check_handle(h);
+  if (st != SQA_OK) return st;
+  const size_t need = static_cast<size_t>(h->R) * h->L * h->emb.n;
+  if (!out || len < need) return fail(SQA_ERR_INVALID, "spin buffer too short");
+  if (!h->initialised) return fail(SQA_ERR_INVALID, "no state yet: anneal or reset first");
+  if ((st = sqa_sync(h)) != SQA_OK) return st;
+  hipError_t e = hipMemcpy(out, h->arena.at<void>(h->off_spins), need, hipMemcpyDeviceToHost);
+  return e == hipSuccess ? SQA_OK : hip_fail(e, "hipMemcpy spins");
+}
+
+sqa_status sqa_read_energies(sqa_handle *h, int32_t *out, size_t len) {
+  sqa_status st = check_handle(h);
+  if (st != SQA_OK) return st;
+  const size_t need = static_cast<size_t>(h->R) * h->L;
+  if (!out || len < need) return fail(SQA_ERR_INVALID, "energy buffer too short");
+  if (!h->initialised) return fail(SQA_ERR_INVALID, "no state yet: anneal first");
+  if ((st = sqa_sync(h)) != SQA_OK) return st;
+  hipError_t e = hipMemcpy(out, h->arena.at<void>(h->off_energy), need * 4, hipMemcpyDeviceToHost);
+  return e == hipSuccess ? SQA_OK : hip_fail(e, "hipMemcpy energies");
+}
+
+sqa_status sqa_write_spins(sqa_handle *h, const int8_t *in, size_t len) {
+  sqa_status st = check_handle(h);
+  if (st != SQA_OK) return st;
+  const size_t need = static_cast<size_t>(h->R) * h->L * h->emb.n;
+  if (!in || len < need) return fail(SQA_ERR_INVALID, "spin buffer too short");
+  for (size_t i = 0; i < need; ++i)
+    if (in[i] != 1 && in[i] != -1) return fail(SQA_ERR_INVALID, "spins must be +1 or -1");
+  if ((st = sqa_sync(h)) != SQA_OK) return st;
+  hipError_t e = hipMemcpy(h->arena.at<void>(h->off_spins), in, need, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy spins");
+  h->initialised = true;
+  return SQA_OK;
+}
+
+void *sqa_device_spins(sqa_handle *h) { return h ? h->arena.at<void>(h->off_spins) : nullptr; }
+void *sqa_device_energies(sqa_handle *h) { return h ? h->arena.at<void>(h->off_energy) : nullptr; }
+
+sqa_status sqa_handle_info(sqa_handle *h, int32_t *sites, int32_t *slices, int32_t *replicas, int32_t *sweeps,
+                           int32_t *fmax) {
+  if (!h) return fail(SQA_ERR_INVALID, "null handle");
+  if (sites) *sites = h->emb.n;
+  if (slices) *slices = h->L;
+  if (replicas) *replicas = h->R;
+  if (sweeps) *sweeps = h->M;
+  if (fmax) *fmax = h->F;
+  return SQA_OK;
+}
+
+sqa_status sqa_export_table(sqa_handle *h, uint32_t *out, size_t len, int32_t *F_out) {
+  if (!h) return fail(SQA_ERR_INVALID, "null handle");
+  if (F_out) *F_out = h->F;
+  if (!out) return SQA_OK;
+  if (len < h->table.size()) return fail(SQA_ERR_INVALID, "table buffer too short");
+  std::memcpy(out, h->table.data(), h->table.size() * 4);
+  return SQA_OK;
+}
+
+// ------------------------------------------------------------------ decoders
+static int pair_index(int N, int a, int b) {
+  if (a > b) std::swap(a, b);
+  return a * (2 * N - a - 1) / 2 + (b - a - 1);
+}
+
+static int32_t logical_energy(const sqa_handle *h, const int8_t *q) {
+  int32_t E = 0;
+  const int N = h->N;
+  for (int i = 0; i < N; ++i) {
+    E += h->h[i] * q[i];
+    for (int j = i + 1; j < N; ++j) E += h->J[i * N + j] * q[i] * q[j];
+  }
+  return E;
+}
+
+sqa_status sqa_decode(sqa_handle *h, int32_t decoder, int32_t readout_slice, const int32_t *tree_parents,
+                      int32_t n_trees, int8_t *logical_out, int32_t *logical_energy_out) {
+  sqa_status st = check_handle(h);
+  if (st != SQA_OK) return st;
+  if (readout_slice < 0 || readout_slice >= h->L) return fail(SQA_ERR_INVALID, "readout slice out of range");
+  if (!h->initialised) return fail(SQA_ERR_INVALID, "no state yet: anneal first");
+  const int N = h->N, R = h->R, n = h->emb.n, L = h->L;
+  if (decoder == SQA_DEC_ME_MAJORITY) {
+    if (h->emb.kind != SQA_EMB_ME) return fail(SQA_ERR_INVALID, "majority decoding of chains needs an ME handle");
+    if ((st = sqa_sync(h)) != SQA_OK) return st;
+    hipError_t e = launch_me_majority(h->arena.at<int8_t>(h->off_spins), R, N, n, L, readout_slice,
+                                      h->arena.at<int32_t>(h->off_J), h->has_h ? h->arena.at<int32_t>(h->off_h) : nullptr,
+                                      h->arena.at<int8_t>(h->off_logical), h->arena.at<int32_t>(h->off_lenergy), nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e == hipSuccess && logical_out)
+      e = hipMemcpy(logical_out, h->arena.at<void>(h->off_logical), static_cast<size_t>(R) * N, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && logical_energy_out)
+      e = hipMemcpy(logical_energy_out, h->arena.at<void>(h->off_lenergy), static_cast<size_t>(R) * 4,
+                    hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+      h->poisoned = true;
+      return hip_fail(e, "majority decode");
+    }
+    return SQA_OK;
+  }
+  if (decoder != SQA_DEC_LHZ_TREES && decoder != SQA_DEC_LHZ_MWD) return fail(SQA_ERR_INVALID, "unknown decoder");
+  if (h->emb.kind != SQA_EMB_LHZ) return fail(SQA_ERR_INVALID, "tree and minimum-weight decoding need an LHZ handle");
+  if (decoder == SQA_DEC_LHZ_TREES) {
+    if (!tree_parents || n_trees < 1) return fail(SQA_ERR_INVALID, "tree decoding needs at least one tree");
+    for (int t = 0; t < n_trees; ++t) {
+      const int32_t *par = tree_parents + static_cast<size_t>(t) * N;
+      if (par[0] != -1) return fail(SQA_ERR_INVALID, "tree must be rooted at logical spin 0");
+      for (int v = 1; v < N; ++v)
+        if (par[v] < 0 || par[v] >= N || par[v] == v) return fail(SQA_ERR_INVALID, "bad parent array");
+      // every vertex must reach the root within N steps
+      for (int v = 1; v < N; ++v) {
+        int x = v, steps = 0;
+        while (x != 0 && steps <= N) { x = par[x]; ++steps; }
+        if (x != 0) return fail(SQA_ERR_INVALID, "parent array is not a tree rooted at 0");
+      }
+    }
+  } else if (N > 30) {
+    return fail(SQA_ERR_UNSUPPORTED, "exact minimum-weight decoding limited to n <= 30");
+  }
+  if ((st = sqa_sync(h)) != SQA_OK) return st;
+  std::vector<int8_t> slice(static_cast<size_t>(R) * n);
+  for (int r = 0; r < R; ++r) {
+    hipError_t e = hipMemcpy(slice.data() + static_cast<size_t>(r) * n,
+                             h->arena.at<int8_t>(h->off_spins) + (static_cast<size_t>(r) * L + readout_slice) * n, n,
+                             hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy readout slice");
+  }
+  std::vector<int8_t> q(N);
+  std::vector<int8_t> val(N);
+  std::vector<int> votes(N);
+  std::vector<int8_t> sig(N);
+  for (int r = 0; r < R; ++r) {
+    const int8_t *s = slice.data() + static_cast<size_t>(r) * n;
+    if (decoder == SQA_DEC_LHZ_TREES) {
+      // Eq. (5) / Appendix A: qbar_0 = +1, qbar_v = qbar_parent(v) * q_{v,parent(v)}; majority, tie -> +1
+      std::fill(votes.begin(), votes.end(), 0);
+      for (int t = 0; t < n_trees; ++t) {
+        const int32_t *par = tree_parents + static_cast<size_t>(t) * N;
+        std::fill(val.begin(), val.end(), 0);
+        val[0] = 1;
+        for (int v = 1; v < N; ++v) {
+          // resolve the path to the first vertex with a known value
+          int x = v;
+          int path[256];
+          int len = 0;
+          while (val[x] == 0) { path[len++] = x; x = par[x]; }
+          for (int k = len - 1; k >= 0; --k) {
+            const int y = path[k];
+            val[y] = static_cast<int8_t>(val[par[y]] * s[pair_index(N, y, par[y])]);
+          }
+        }
+        for (int v = 0; v < N; ++v) votes[v] += val[v];
+      }
+      for (int v = 0; v < N; ++v) q[v] = votes[v] >= 0 ? 1 : -1;
+    } else {
+      // Sec. IV A: maximise sum_{i<j} s_ij sig_i sig_j over sig_0 = +1 (nearest
+      // constraint-satisfying state), visiting candidates in Gray-code order;
+      // ties -> smallest candidate index (bit b set <=> sig_{b+1} = -1).
+      std::vector<int32_t> field(N, 0);   // field[i] = sum_{j != i} s_ij sig_j
+      std::fill(sig.begin(), sig.end(), 1);
+      long long score = 0;
+      for (int i = 0; i < N; ++i)
+        for (int j = i + 1; j < N; ++j) score += s[pair_index(N, i, j)];
+      for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j)
+          if (j != i) field[i] += s[pair_index(N, i, j)];
+      long long best = score;
+      uint64_t best_m = 0, m = 0;
+      const uint64_t total = 1ull << (N - 1);
+      for (uint64_t g = 1; g < total; ++g) {
+        const int b = __builtin_ctzll(g);
+        const int i = b + 1;
+        score -= 2LL * sig[i] * field[i];
+        sig[i] = static_cast<int8_t>(-sig[i]);
+        for (int j = 0; j < N; ++j)
+          if (j != i) field[j] += 2 * s[pair_index(N, i, j)] * sig[i];
+        m ^= 1ull << b;
+        if (score > best || (score == best && m < best_m)) {
+          best = score;
+          best_m = m;
+        }
+      }
+      q[0] = 1;
+      for (int b = 0; b + 1 < N; ++b) q[b + 1] = ((best_m >> b) & 1u) ? -1 : 1;
+    }
+    if (logical_out) std::memcpy(logical_out + static_cast<size_t>(r) * N, q.data(), N);
+    if (logical_energy_out) logical_energy_out[r] = logical_energy(h, q.data());
+  }
+  return SQA_OK;
+}
+
+// Uniform labelled spanning trees from Pruefer sequences, entry i of tree t =
+// floor(u N / 2^32) with u = word 0 of Philox(i, t, 0, TREE<<24); the
+// smallest-leaf rule turns the sequence into edges, rooted at 0 by BFS.
+sqa_status sqa_random_trees(uint64_t seed, int32_t n, int32_t n_trees, int32_t *parents_out) {
+  if (n < 1 || n_trees < 0 || (!parents_out && n_trees > 0)) return fail(SQA_ERR_INVALID, "bad tree arguments");
+  std::vector<int> seq(n > 2 ? n - 2 : 0), deg(n);
+  std::vector<std::vector<int>> adj(n);
+  for (int t = 0; t < n_trees; ++t) {
+    for (int i = 0; i + 2 < n; ++i) {
+      const uint32_t ctr[4] = {static_cast<uint32_t>(i), static_cast<uint32_t>(t), 0u, kStreamTree << 24};
+      uint32_t o[4];
+      host_philox4x32(ctr, static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32), o);
+      seq[i] = static_cast<int>((static_cast<uint64_t>(o[0]) * static_cast<uint64_t>(n)) >> 32);
+    }
+    for (auto &a : adj) a.clear();
+    std::fill(deg.begin(), deg.end(), 1);
+    for (int x : seq) deg[x]++;
+    for (int x : seq) {
+      int leaf = 0;
+      while (deg[leaf] != 1) ++leaf;
+      adj[leaf].push_back(x);
+      adj[x].push_back(leaf);
+      deg[leaf]--;
+      deg[x]--;
+    }
+    if (n >= 2) {
+      int a = -1, b = -1;
+      for (int v = 0; v < n; ++v)
+        if (deg[v] == 1) (a < 0 ? a : b) = v;
+      adj[a].push_back(b);
+      adj[b].push_back(a);
+    }
+    int32_t *par = parents_out + static_cast<size_t>(t) * n;
+    for (int v = 0; v < n; ++v) par[v] = -2;
+    par[0] = -1;
+    std::vector<int> queue{0};
+    for (size_t qi = 0; qi < queue.size(); ++qi) {
+      const int x = queue[qi];
+      std::vector<int> nb = adj[x];
+      std::sort(nb.begin(), nb.end());
+      for (int y : nb)
+        if (par[y] == -2) {
+          par[y] = x;
+          queue.push_back(y);
+        }
+    }
+  }
+  return SQA_OK;
+}
+
+// -------------------------------------------------------------- batches
+}  // extern "C"
+
+namespace sqa {
+
+size_t handle_device_bytes(const sqa_handle *h) { return h->device_bytes; }
+
+sqa_status run_handles(const std::vector<sqa_handle *> &hs, const std::vector<int> &m0, const std::vector<int> &m1,
+                       const std::vector<int> &flags, hipStream_t stream, void **scratch, size_t *scratch_bytes) {
+  hipError_t e = ensure_lds_limits();
+  if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
+  std::vector<const sqa_handle *> ch(hs.begin(), hs.end());
+  int waves = 4, gpc = 0;
+  resolve_config(ch, nullptr, &waves, &gpc);
+  std::vector<WorkItem> items = plan_items(ch, m0, m1, waves);
+  LaunchShape shape = shape_for(ch, waves, gpc, items.size());
+  if (shape.lds_bytes() > kMaxLds) return fail(SQA_ERR_UNSUPPORTED, "lattices do not fit in LDS");
+  std::vector<HandleDev> hds(hs.size());
+  for (size_t i = 0; i < hs.size(); ++i) hds[i] = hs[i]->dev(m0[i], m1[i], flags[i]);
+  const size_t bh = sizeof(HandleDev) * hds.size();
+  const size_t oi = (bh + 255) & ~size_t(255);
+  const size_t oc = (oi + sizeof(WorkItem) * items.size() + 255) & ~size_t(255);
+  const size_t need = oc + 256;
+  if (*scratch_bytes < need) {
+    if (*scratch) (void)hipFree(*scratch);
+    *scratch = nullptr;
+    *scratch_bytes = 0;
+    e = hipMalloc(scratch, need);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc (launch scratch)");
+    *scratch_bytes = need;
+  }
+  char *base = static_cast<char *>(*scratch);
+  e = hipMemcpyAsync(base, hds.data(), bh, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(base + oi, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess)
+    e = launch_sqa_anneal(reinterpret_cast<HandleDev *>(base), reinterpret_cast<WorkItem *>(base + oi),
+                          static_cast<int>(items.size()), reinterpret_cast<int *>(base + oc), shape.grid, shape.waves,
+                          shape.rec_cap, shape.lat_cap, shape.tab_cap, stream);
+  if (e == hipSuccess)
+    for (sqa_handle *h : hs) {
+      e = hipEventRecord(h->done, stream);
+      if (e != hipSuccess) break;
+    }
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) {
+    for (sqa_handle *h : hs) h->poisoned = true;
+    return hip_fail(e, "multi-handle launch");
+  }
+  for (sqa_handle *h : hs) h->initialised = true;
+  return SQA_OK;
+}
+
+}  // namespace sqa
+
+struct sqa_batch {
+  std::vector<sqa_handle *> handles;
+  sqa_launch_config config{0, 0};
+  LaunchShape shape;
+  int n_items = 0;
+  void *dev = nullptr;
+  HandleDev *d_hds = nullptr;
+  WorkItem *d_items = nullptr;
+  int *d_counter = nullptr;
+  hipStream_t capture_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+static sqa_status batch_build(sqa_handle *const *handles, int32_t count, int waves, int gpc, sqa_batch **out) {
+  std::vector<const sqa_handle *> hs(handles, handles + count);
+  std::vector<int> m0(count, 0), m1(count);
+  for (int i = 0; i < count; ++i) m1[i] = handles[i]->M;
+  std::vector<WorkItem> items = plan_items(hs, m0, m1, waves);
+  LaunchShape shape = shape_for(hs, waves, gpc, items.size());
+  if (shape.lds_bytes() > kMaxLds) return fail(SQA_ERR_UNSUPPORTED, "batch lattices do not fit in LDS");
+  std::vector<HandleDev> hds(count);
+  for (int i = 0; i < count; ++i) hds[i] = handles[i]->dev(0, handles[i]->M, kFlagInit | kFlagEnergy);
+  sqa_batch *b = new (std::nothrow) sqa_batch();
+  if (!b) return fail(SQA_ERR_OOM, "host allocation");
+  b->handles.assign(handles, handles + count);
+  b->config.waves_per_group = waves;
+  b->config.groups_per_cu = gpc > 0 ? gpc : occupancy_groups_per_cu(shape);
+  b->shape = shape;
+  b->n_items = static_cast<int>(items.size());
+  const size_t bh = sizeof(HandleDev) * hds.size();
+  const size_t bi = sizeof(WorkItem) * items.size();
+  const size_t oi = (bh + 255) & ~size_t(255);
+  const size_t oc = (oi + bi + 255) & ~size_t(255);
+  hipError_t e = hipMalloc(&b->dev, oc + 256);
+  if (e != hipSuccess) {
+    delete b;
+    return hip_fail(e, "hipMalloc (batch)");
+  }
+  b->d_hds = reinterpret_cast<HandleDev *>(b->dev);
+  b->d_items = reinterpret_cast<WorkItem *>(static_cast<char *>(b->dev) + oi);
+  b->d_counter = reinterpret_cast<int *>(static_cast<char *>(b->dev) + oc);
+  e = hipMemcpy(b->d_hds, hds.data(), bh, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(b->d_items, items.data(), bi, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(b->dev);
+    delete b;
+    return hip_fail(e, "hipMemcpy (batch)");
+  }
+  *out = b;
+  return SQA_OK;
+}
+
+static sqa_status batch_capture(sqa_batch *b) {
+  hipError_t e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+  e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+  hipError_t le = launch_sqa_anneal(b->d_hds, b->d_items, b->n_items, b->d_counter, b->shape.grid, b->shape.waves,
+                                    b->shape.rec_cap, b->shape.lat_cap, b->shape.tab_cap, b->capture_stream);
+  e = hipStreamEndCapture(b->capture_stream, &b->graph);
+  if (le != hipSuccess) return hip_fail(le, "capture anneal launch");
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+  return SQA_OK;
+}
+
+static void batch_free(sqa_batch *b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+  if (b->dev) (void)hipFree(b->dev);
+  delete b;
+}
+
+extern "C" {
+
+sqa_status sqa_batch_create(sqa_handle *const *handles, int32_t count, const sqa_launch_config *config,
+                            sqa_batch **out) {
+  if (!handles || count < 1 || !out) return fail(SQA_ERR_INVALID, "bad batch arguments");
+  *out = nullptr;
+  for (int i = 0; i < count; ++i) {
+    sqa_status st = check_handle(handles[i]);
+    if (st != SQA_OK) return st;
+  }
+  if (config && ((config->waves_per_group != 0 && !valid_waves(config->waves_per_group)) || config->groups_per_cu < 0))
+    return fail(SQA_ERR_INVALID, "waves_per_group must be 1, 2, 4 or 8");
+  hipError_t e = ensure_lds_limits();
+  if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
+  std::vector<const sqa_handle *> hs(handles, handles + count);
+  int waves = 4, gpc = 0;
+  resolve_config(hs, config, &waves, &gpc);
+  sqa_batch *b = nullptr;
+  sqa_status st = batch_build(handles, count, waves, gpc, &b);
+  if (st != SQA_OK) return st;
+  st = batch_capture(b);
+  if (st != SQA_OK) {
+    batch_free(b);
+    return st;
+  }
+  *out = b;
+  return SQA_OK;
+}
+
+sqa_status sqa_batch_run(sqa_batch *b, void *stream) {
+  if (!b) return fail(SQA_ERR_INVALID, "null batch");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  for (sqa_handle *h : b->handles) {
+    if (h->poisoned) return fail(SQA_ERR_DEVICE, "a handle of the batch is poisoned");
+    hipError_t e = hipStreamWaitEvent(s, h->done, 0);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
+  }
+  hipError_t e = hipGraphLaunch(b->exec, s);
+  if (e != hipSuccess) {
+    for (sqa_handle *h : b->handles) h->poisoned = true;
+    return hip_fail(e, "hipGraphLaunch");
+  }
+  for (sqa_handle *h : b->handles) {
+    e = hipEventRecord(h->done, s);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    h->initialised = true;
+  }
+  return SQA_OK;
+}
+
+sqa_status sqa_batch_config(sqa_batch *b, sqa_launch_config *out) {
+  if (!b || !out) return fail(SQA_ERR_INVALID, "null argument");
+  *out = b->config;
+  return SQA_OK;
+}
+
+void sqa_batch_destroy(sqa_batch *b) {
+  if (!b) return;
+  (void)hipDeviceSynchronize();
+  batch_free(b);
+}
+
+sqa_status sqa_anneal_batch(sqa_handle *const *handles, int32_t count, void *stream) {
+  sqa_batch *b = nullptr;
+  sqa_status st = sqa_batch_create(handles, count, nullptr, &b);
+  if (st != SQA_OK) return st;
+  st = sqa_batch_run(b, stream);
+  (void)hipStreamSynchronize(static_cast<hipStream_t>(stream));
+  sqa_batch_destroy(b);
+  return st;
+}
+
+// Times each candidate shape on a short sweep range of the handles' full
+// batch (state saved and restored), keeps the fastest.
+sqa_status sqa_autotune(sqa_handle *const *handles, int32_t count, const char *cache_path, sqa_launch_config *best) {
+  if (!handles || count < 1) return fail(SQA_ERR_INVALID, "bad autotune arguments");
+  for (int i = 0; i < count; ++i) {
+    sqa_status st = check_handle(handles[i]);
+    if (st != SQA_OK) return st;
+  }
+  hipError_t e = ensure_lds_limits();
+  if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
+  std::vector<const sqa_handle *> hs(handles, handles + count);
+  // save device state
+  std::vector<void *> saved(count, nullptr);
+  for (int i = 0; i < count; ++i) {
+    sqa_handle *h = handles[i];
+    const size_t bytes = static_cast<size_t>(h->R) * h->L * h->emb.n + static_cast<size_t>(h->R) * h->L * 4;
+    e = hipMalloc(&saved[i], bytes);
+    if (e != hipSuccess) break;
+    e = hipMemcpy(saved[i], h->arena.at<void>(h->off_spins), static_cast<size_t>(h->R) * h->L * h->emb.n,
+                  hipMemcpyDeviceToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(static_cast<char *>(saved[i]) + static_cast<size_t>(h->R) * h->L * h->emb.n,
+                    h->arena.at<void>(h->off_energy), static_cast<size_t>(h->R) * h->L * 4, hipMemcpyDeviceToDevice);
+    if (e != hipSuccess) break;
+  }
+  double best_t = 1e300;
+  int best_w = 4, best_g = 0;
+  if (e == hipSuccess) {
+    hipEvent_t a, z;
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&z);
+    const int trial_sweeps = 20;
+    for (int w : {1, 2, 4, 8}) {
+      std::vector<int> m0(count, 0), m1(count);
+      for (int i = 0; i < count; ++i) m1[i] = std::min(handles[i]->M, trial_sweeps);
+      std::vector<WorkItem> items = plan_items(hs, m0, m1, w);
+      LaunchShape base = shape_for(hs, w, 0, items.size());
+      if (base.lds_bytes() > kMaxLds) continue;
+      const int occ = occupancy_groups_per_cu(base);
+      std::vector<int> gpcs{occ};
+      if (occ >= 2) gpcs.push_back(occ / 2);
+      for (int g : gpcs) {
+        LaunchShape s = shape_for(hs, w, g, items.size());
+        std::vector<HandleDev> hds(count);
+        for (int i = 0; i < count; ++i) hds[i] = handles[i]->dev(0, m1[i], kFlagInit);
+        void *dev = nullptr;
+        const size_t bh = sizeof(HandleDev) * count, oi = (bh + 255) & ~size_t(255);
+        const size_t oc = (oi + sizeof(WorkItem) * items.size() + 255) & ~size_t(255);
+        if (hipMalloc(&dev, oc + 256) != hipSuccess) continue;
+        (void)hipMemcpy(dev, hds.data(), bh, hipMemcpyHostToDevice);
+        (void)hipMemcpy(static_cast<char *>(dev) + oi, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice);
+        float ms = 0;
+        (void)hipEventRecord(a, nullptr);
+        hipError_t le = launch_sqa_anneal(reinterpret_cast<HandleDev *>(dev),
+                                          reinterpret_cast<WorkItem *>(static_cast<char *>(dev) + oi),
+                                          static_cast<int>(items.size()), reinterpret_cast<int *>(static_cast<char *>(dev) + oc),
+                                          s.grid, s.waves, s.rec_cap, s.lat_cap, s.tab_cap, nullptr);
+        (void)hipEventRecord(z, nullptr);
+        (void)hipEventSynchronize(z);
+        (void)hipEventElapsedTime(&ms, a, z);
+        (void)hipFree(dev);
+        if (le == hipSuccess && ms < best_t) {
+          best_t = ms;
+          best_w = w;
+          best_g = g;
+        }
+      }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(z);
+  }
+  // restore device state
+  for (int i = 0; i < count; ++i) {
+    sqa_handle *h = handles[i];
+    if (!saved[i]) continue;
+    (void)hipMemcpy(h->arena.at<void>(h->off_spins), saved[i], static_cast<size_t>(h->R) * h->L * h->emb.n,
+              hipMemcpyDeviceToDevice);
+    (void)hipMemcpy(h->arena.at<void>(h->off_energy), static_cast<char *>(saved[i]) + static_cast<size_t>(h->R) * h->L * h->emb.n,
+              static_cast<size_t>(h->R) * h->L * 4, hipMemcpyDeviceToDevice);
+    (void)hipFree(saved[i]);
+  }
+  if (e != hipSuccess) return hip_fail(e, "autotune state save");
+  if (best_t >= 1e300) return fail(SQA_ERR_UNSUPPORTED, "no launch shape fits");
+  if (best) {
+    best->waves_per_group = best_w;
+    best->groups_per_cu = best_g;
+  }
+  const char *path = cache_path_or_env(cache_path);
+  if (path) {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto m = read_cache(path);
+    m[device_arch() + "/" + shape_class(hs)] = {best_w, best_g};
+    write_cache(path, m);
+  }
+  return SQA_OK;
+}
+
+}  // extern "C"

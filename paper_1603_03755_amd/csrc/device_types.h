@@ -1,0 +1,88 @@
+// Structures passed from the host library to the gfx950 kernels.
+//
+// Device site order: sites are renumbered so that each of the four colour
+// classes is contiguous (class c occupies [cls[c], cls[c+1])) and increasing
+// by physical site id inside a class.  The lattice of one replica lives in
+// LDS as one 64-bit word per site (bit tau = 1 <=> spin -1 on slice tau),
+// followed by one all-zero word (index n) that unused partner slots point to.
+#pragma once
+#include <cstdint>
+
+namespace sqa {
+
+constexpr int kKindME = 0;
+constexpr int kKindLHZ = 1;
+
+// Per-site records, kind-specific layouts (32-bit words):
+//  ME  (4 words, 16 B): terms T=3, one partner each
+//    w0 = site | base << 16
+//    w1 = |w0| | |w1| << 8 | |w2| << 16 | |h| << 24
+//    w2 = negmask | part0 << 16
+//    w3 = part1 | part2 << 16
+//  LHZ (12 words, 48 B): terms T=4, three partners each (a 3-body term's
+//  third partner is the zero word)
+//    w0 = site | base << 16
+//    w1 = |w0..w3| bytes
+//    w2 = |h| | negmask << 8
+//    w3 = 0
+//    w4..w9 = part[0..11] as u16 pairs (term t partner q at index 3t+q)
+//    w10, w11 = 0
+// negmask bit t (t < 4): weight of term t is negative; bit 4: h < 0.
+// base = 3 * (F_site + F) + 2, F_site = |h| + sum |w_t|.
+constexpr int kRecWordsME = 4;
+constexpr int kRecWordsLHZ = 12;
+
+constexpr uint32_t kStreamInit = 1;
+constexpr uint32_t kStreamSQA = 2;
+constexpr uint32_t kStreamPT = 3;
+constexpr uint32_t kStreamSwap = 4;
+constexpr uint32_t kStreamTree = 5;
+constexpr uint32_t kStreamPTInit = 6;
+
+constexpr uint32_t kAlways = 0xFFFFFFFFu;
+
+// Flags of one anneal launch for one handle.
+constexpr int kFlagInit = 1;        // build the lattice from the INIT stream instead of loading it
+constexpr int kFlagEnergy = 2;      // compute per-slice energies after the last sweep
+
+struct HandleDev {
+  const uint32_t *rec;      // [n][rec_words], device order
+  const uint16_t *dev_of;   // [n] physical site -> device index
+  const int32_t *hfield;    // [n] field of each device-order site
+  const int32_t *term_w;    // [n_terms]
+  const uint32_t *term_s;   // [n_terms][2]: four u16 device indices (zero word = n)
+  const uint32_t *table;    // [M][tw]
+  int8_t *spins;            // [R][L][n] physical order, +1/-1
+  int32_t *energy;          // [R][L]
+  int32_t kind, n, n_terms, L, M, R, F, tw;
+  int32_t m0, m1, flags;
+  uint32_t seed_lo, seed_hi;
+  int32_t cls[5];
+};
+
+// One unit of persistent-kernel work: handle index, first replica, count.
+struct WorkItem {
+  int32_t handle;
+  int32_t rep0;
+  int32_t nrep;
+};
+
+// PT ladder state for one handle.
+struct PTDev {
+  const uint32_t *rec;      // same record layouts as SQA
+  const int32_t *hfield;
+  const int32_t *term_w;
+  const uint32_t *term_s;
+  const uint32_t *mtab;     // [R][2F+1]  Metropolis thresholds by slot
+  const uint32_t *stab;     // [R-1][Dmax+1] swap thresholds
+  const uint16_t *dev_of;
+  int8_t *spins;            // [R][n] by replica, physical order
+  int32_t *energy;          // [R] by replica
+  int32_t *rep_at;          // [R] slot -> replica
+  uint64_t *swap_acc;       // [R-1]
+  int32_t kind, n, n_terms, R, F, Dmax, sweeps, sweeps_per_swap;
+  uint32_t seed_lo, seed_hi;
+  int32_t cls[5];
+};
+
+}  // namespace sqa

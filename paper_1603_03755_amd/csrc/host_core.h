@@ -1,0 +1,143 @@
+// Host-side pieces of the library shared between its translation units:
+// embedding construction, device-order site records, acceptance tables,
+// error reporting and the handle structures.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/sqa.h"
+#include "device_types.h"
+
+namespace sqa {
+
+// ------------------------------------------------------------- errors
+void set_error(const std::string &msg);
+sqa_status fail(sqa_status st, const std::string &msg);
+sqa_status hip_fail(hipError_t e, const char *what);
+
+// -------------------------------------------------------- embeddings
+// One k-body term (k = 2..4) of the physical Hamiltonian.
+struct Term {
+  int32_t w;
+  int32_t arity;
+  int32_t s[4];
+};
+
+// Physical Hamiltonian of an embedded problem (Sec. II A / II B).
+struct Embedded {
+  int32_t kind = 0, N = 0, n = 0;
+  std::vector<int32_t> h;        // [n] fields
+  std::vector<int32_t> colour;   // [n] 0..3
+  std::vector<Term> terms;
+  int32_t fmax = 0;              // max_k |h_k| + sum_{t ni k} |w_t|
+  int32_t emax = 0;              // sum |h| + sum |w|
+};
+
+sqa_status build_embedding(const sqa_problem &p, const sqa_embedding &e, Embedded *out);
+
+// Device-ready form: colour-sorted order, packed records, terms in device indices.
+struct DeviceLayout {
+  int32_t rec_words = 0;                 // per site
+  std::vector<uint32_t> rec;             // [n][rec_words]
+  std::vector<uint16_t> dev_of;          // [n] physical -> device
+  std::vector<int32_t> phys_of;          // [n] device -> physical
+  std::vector<int32_t> hfield;           // [n] device order
+  std::vector<int32_t> term_w;           // [n_terms]
+  std::vector<uint32_t> term_s;          // [n_terms][2]
+  int32_t cls[5] = {0, 0, 0, 0, 0};
+};
+
+sqa_status build_layout(const Embedded &emb, int32_t F, DeviceLayout *out);
+
+// ---------------------------------------------------------- tables
+uint32_t threshold_from_log(double x);
+std::vector<double> linear_gamma(double g0, double g1, int32_t M);
+// T[m][a+F][(b+2)/2]
+std::vector<uint32_t> sqa_threshold_table(double beta, int32_t L, const std::vector<double> &gamma,
+                                          const std::vector<double> *bscale, int32_t F);
+std::vector<double> pt_betas(double beta_min, double beta_max, int32_t R);
+std::vector<uint32_t> pt_metropolis_table(const std::vector<double> &betas, int32_t F);
+std::vector<uint32_t> pt_swap_table(const std::vector<double> &betas, int32_t Dmax);
+
+// ---------------------------------------------------------- host Philox
+void host_philox4x32(const uint32_t ctr[4], uint32_t k0, uint32_t k1, uint32_t out[4]);
+
+// --------------------------------------------------------- device arena
+// One device allocation carved into aligned sub-buffers.
+struct Arena {
+  void *base = nullptr;
+  size_t size = 0;
+  size_t used = 0;
+  size_t take(size_t bytes) {
+    size_t off = (used + 255) & ~size_t(255);
+    used = off + bytes;
+    return off;
+  }
+  template <class T>
+  T *at(size_t off) const { return reinterpret_cast<T *>(static_cast<char *>(base) + off); }
+};
+
+// Kernel launchers (kernels.hip).
+hipError_t launch_sqa_anneal(const HandleDev *hds, const WorkItem *items, int n_items, int *counter, int grid,
+                             int waves, int rec_cap, int lat_cap, int tab_cap, hipStream_t stream);
+hipError_t set_sqa_anneal_lds_limit(size_t bytes);
+hipError_t launch_sqa_init(const HandleDev &H, hipStream_t stream);
+hipError_t launch_me_majority(const int8_t *spins, int R, int N, int n_sites, int L, int slice, const int32_t *J,
+                              const int32_t *h, int8_t *logical, int32_t *energy, hipStream_t stream);
+hipError_t launch_pt(const PTDev *pts, int count, int waves, int rec_cap, int lat_cap, int mtab_cap,
+                     hipStream_t stream);
+hipError_t set_pt_lds_limit(size_t bytes);
+
+// LDS budget of one workgroup on gfx950 (160 KiB, less room for the kernels'
+// static LDS variables).
+constexpr size_t kMaxLds = 160 * 1024 - 512;
+
+// Launch geometry for a set of handles.
+struct LaunchShape {
+  int waves = 4;
+  int grid = 0;
+  int rec_cap = 0, lat_cap = 0, tab_cap = 0;
+  size_t lds_bytes() const {
+    return (static_cast<size_t>(rec_cap) + 2ull * waves * lat_cap + static_cast<size_t>(waves) * tab_cap) * 4;
+  }
+};
+
+int device_cu_count();
+int occupancy_groups_per_cu(const LaunchShape &s);
+
+}  // namespace sqa
+
+struct sqa_handle;
+
+namespace sqa {
+// One persistent launch over several handles, each advancing sweeps
+// [m0[i], m1[i]) with its own flags.  `scratch` is a device buffer grown on
+// demand and owned by the caller.  Blocks until the launch has finished.
+sqa_status run_handles(const std::vector<sqa_handle *> &hs, const std::vector<int> &m0, const std::vector<int> &m1,
+                       const std::vector<int> &flags, hipStream_t stream, void **scratch, size_t *scratch_bytes);
+size_t handle_device_bytes(const sqa_handle *h);
+}  // namespace sqa
+
+// Handle: one problem x embedding x schedule, its device buffers and state.
+struct sqa_handle {
+  sqa::Embedded emb;
+  sqa::DeviceLayout lay;
+  int32_t N = 0, L = 0, M = 0, R = 0, F = 0, tw = 0;
+  double beta = 0;
+  uint64_t seed = 0;
+  std::vector<int32_t> J, h;         // logical problem (n*n, n)
+  bool has_h = false;
+  std::vector<uint32_t> table;       // host copy, exported for parity checks
+  sqa::Arena arena;
+  size_t off_rec = 0, off_devof = 0, off_hfield = 0, off_tw = 0, off_ts = 0, off_table = 0, off_spins = 0,
+         off_energy = 0, off_J = 0, off_h = 0, off_logical = 0, off_lenergy = 0, off_hd = 0, off_items = 0,
+         off_counter = 0;
+  bool initialised = false;          // device lattice holds a state
+  bool poisoned = false;
+  hipEvent_t done = nullptr;
+  size_t device_bytes = 0;
+  sqa::HandleDev dev(int m0, int m1, int flags) const;
+};

@@ -1,0 +1,370 @@
+"""ctypes binding of libsqa.so (C ABI in include/sqa.h).
+
+Every function here only marshals arguments: device work, tables and
+decoding all happen in the library.  Import fails loudly if the library has
+not been built (python -m paper_1603_03755_amd.build); there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsqa.so")
+
+SQA_OK, SQA_ERR_INVALID, SQA_ERR_OOM, SQA_ERR_DEVICE, SQA_ERR_UNSUPPORTED, SQA_ERR_BUSY, SQA_ERR_NOT_READY = \
+    0, -1, -2, -3, -4, -5, -6
+SQA_EMB_ME, SQA_EMB_LHZ = 0, 1
+SQA_DEC_ME_MAJORITY, SQA_DEC_LHZ_TREES, SQA_DEC_LHZ_MWD = 0, 1, 2
+
+
+class SqaError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"sqa status {status}: {msg}")
+        self.status = status
+
+
+class sqa_problem(C.Structure):
+    _fields_ = [("n", C.c_int32), ("J", C.POINTER(C.c_int32)), ("h", C.POINTER(C.c_int32))]
+
+
+class sqa_embedding(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("penalty", C.c_int32)]
+
+
+class sqa_schedule(C.Structure):
+    _fields_ = [("beta", C.c_double), ("slices", C.c_int32), ("sweeps", C.c_int32), ("replicas", C.c_int32),
+                ("gamma_start", C.c_double), ("gamma_end", C.c_double),
+                ("gamma", C.POINTER(C.c_double)), ("bscale", C.POINTER(C.c_double)), ("seed", C.c_uint64)]
+
+
+class sqa_launch_config(C.Structure):
+    _fields_ = [("waves_per_group", C.c_int32), ("groups_per_cu", C.c_int32)]
+
+
+class pt_params(C.Structure):
+    _fields_ = [("beta_min", C.c_double), ("beta_max", C.c_double), ("temps", C.c_int32), ("sweeps", C.c_int32),
+                ("sweeps_per_swap", C.c_int32), ("seed", C.c_uint64)]
+
+
+_lib = None
+_VP = C.c_void_p
+_PVP = C.POINTER(C.c_void_p)
+_SIGS = {
+    "sqa_create": (C.c_int, [C.POINTER(sqa_problem), C.POINTER(sqa_embedding), C.POINTER(sqa_schedule), _PVP]),
+    "sqa_anneal": (C.c_int, [_VP, _VP]),
+    "sqa_anneal_range": (C.c_int, [_VP, C.c_int32, C.c_int32, _VP]),
+    "sqa_reset": (C.c_int, [_VP, _VP]),
+    "sqa_sync": (C.c_int, [_VP]),
+    "sqa_read_spins": (C.c_int, [_VP, _VP, C.c_size_t]),
+    "sqa_read_energies": (C.c_int, [_VP, _VP, C.c_size_t]),
+    "sqa_write_spins": (C.c_int, [_VP, _VP, C.c_size_t]),
+    "sqa_device_spins": (_VP, [_VP]),
+    "sqa_device_energies": (_VP, [_VP]),
+    "sqa_decode": (C.c_int, [_VP, C.c_int32, C.c_int32, _VP, C.c_int32, _VP, _VP]),
+    "sqa_random_trees": (C.c_int, [C.c_uint64, C.c_int32, C.c_int32, _VP]),
+    "sqa_export_table": (C.c_int, [_VP, _VP, C.c_size_t, C.POINTER(C.c_int32)]),
+    "sqa_physical_sites": (C.c_int64, [C.c_int32, C.c_int32]),
+    "sqa_handle_info": (C.c_int, [_VP] + [C.POINTER(C.c_int32)] * 5),
+    "sqa_destroy": (None, [_VP]),
+    "sqa_batch_create": (C.c_int, [_PVP, C.c_int32, C.POINTER(sqa_launch_config), _PVP]),
+    "sqa_batch_run": (C.c_int, [_VP, _VP]),
+    "sqa_batch_config": (C.c_int, [_VP, C.POINTER(sqa_launch_config)]),
+    "sqa_batch_destroy": (None, [_VP]),
+    "sqa_anneal_batch": (C.c_int, [_PVP, C.c_int32, _VP]),
+    "sqa_autotune": (C.c_int, [_PVP, C.c_int32, C.c_char_p, C.POINTER(sqa_launch_config)]),
+    "pt_create": (C.c_int, [C.POINTER(sqa_problem), C.POINTER(sqa_embedding), C.POINTER(pt_params), _PVP]),
+    "pt_run_handle": (C.c_int, [_VP, _VP]),
+    "pt_run_batch": (C.c_int, [_PVP, C.c_int32, _VP]),
+    "pt_read": (C.c_int, [_VP, _VP, C.c_size_t, _VP, _VP, _VP]),
+    "pt_destroy": (None, [_VP]),
+    "pt_run": (C.c_int, [C.POINTER(sqa_problem), C.POINTER(sqa_embedding), C.POINTER(pt_params), _VP, _VP,
+                         C.c_size_t, _VP, _VP, _VP]),
+    "sqa_server_create": (C.c_int, [C.c_size_t, C.c_int32, C.c_int32, _PVP]),
+    "sqa_server_submit": (C.c_int, [_VP, C.POINTER(sqa_problem), C.POINTER(sqa_embedding), C.POINTER(sqa_schedule),
+                                    C.POINTER(C.c_uint64)]),
+    "sqa_server_poll": (C.c_int, [_VP, C.c_uint64, C.POINTER(C.c_int32)]),
+    "sqa_server_wait": (C.c_int, [_VP, C.c_uint64, C.c_int32]),
+    "sqa_server_result": (C.c_int, [_VP, C.c_uint64, _VP, C.c_size_t, _VP, C.c_size_t, C.POINTER(C.c_double)]),
+    "sqa_server_stats": (C.c_int, [_VP] + [C.POINTER(C.c_uint64)] * 3),
+    "sqa_server_destroy": (None, [_VP]),
+    "sqa_last_error": (C.c_char_p, []),
+    "sqa_version": (C.c_char_p, []),
+}
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1603_03755_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(st: int):
+    if st != SQA_OK:
+        msg = lib().sqa_last_error()
+        raise SqaError(st, msg.decode() if msg else "")
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else C.c_void_p(a.ctypes.data)
+
+
+def _stream(stream) -> Optional[int]:
+    """Accepts None, an int hipStream_t, or a torch.cuda.Stream."""
+    if stream is None:
+        return None
+    if hasattr(stream, "cuda_stream"):
+        return C.c_void_p(stream.cuda_stream)
+    return C.c_void_p(int(stream))
+
+
+def make_problem(J, h=None):
+    J = np.ascontiguousarray(J, dtype=np.int32)
+    hh = None if h is None else np.ascontiguousarray(h, dtype=np.int32)
+    p = sqa_problem(J.shape[0], J.ctypes.data_as(C.POINTER(C.c_int32)),
+                    hh.ctypes.data_as(C.POINTER(C.c_int32)) if hh is not None else None)
+    return p, (J, hh)
+
+
+# ---------------------------------------------------------------- SQA handle
+class SQA:
+    """One problem x embedding x schedule on the GPU (sqa_create / sqa_destroy)."""
+
+    def __init__(self, kind: int, J, penalty: int, beta: float, slices: int, sweeps: int, replicas: int,
+                 gamma_start: float, gamma_end: float, seed: int, h=None, gamma=None, bscale=None):
+        prob, self._keep = make_problem(J, h)
+        g = None if gamma is None else np.ascontiguousarray(gamma, dtype=np.float64)
+        b = None if bscale is None else np.ascontiguousarray(bscale, dtype=np.float64)
+        sched = sqa_schedule(beta, slices, sweeps, replicas, gamma_start, gamma_end,
+                             g.ctypes.data_as(C.POINTER(C.c_double)) if g is not None else None,
+                             b.ctypes.data_as(C.POINTER(C.c_double)) if b is not None else None, seed)
+        emb = sqa_embedding(kind, penalty)
+        out = C.c_void_p()
+        _check(lib().sqa_create(C.byref(prob), C.byref(emb), C.byref(sched), C.byref(out)))
+        self.h = out
+        self.kind, self.N = kind, int(np.asarray(J).shape[0])
+        vals = [C.c_int32() for _ in range(5)]
+        _check(lib().sqa_handle_info(self.h, *[C.byref(v) for v in vals]))
+        self.sites, self.slices, self.replicas, self.sweeps, self.fmax = [v.value for v in vals]
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().sqa_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def anneal(self, stream=None):
+        _check(lib().sqa_anneal(self.h, _stream(stream)))
+        return self
+
+    def anneal_range(self, m0: int, m1: int, stream=None):
+        _check(lib().sqa_anneal_range(self.h, m0, m1, _stream(stream)))
+        return self
+
+    def reset(self, stream=None):
+        _check(lib().sqa_reset(self.h, _stream(stream)))
+
+    def sync(self):
+        _check(lib().sqa_sync(self.h))
+
+    def spins(self) -> np.ndarray:
+        out = np.empty((self.replicas, self.slices, self.sites), dtype=np.int8)
+        _check(lib().sqa_read_spins(self.h, _ptr(out), out.size))
+        return out
+
+    def energies(self) -> np.ndarray:
+        out = np.empty((self.replicas, self.slices), dtype=np.int32)
+        _check(lib().sqa_read_energies(self.h, _ptr(out), out.size))
+        return out
+
+    def write_spins(self, s):
+        s = np.ascontiguousarray(s, dtype=np.int8)
+        _check(lib().sqa_write_spins(self.h, _ptr(s), s.size))
+
+    def table(self):
+        F = C.c_int32()
+        _check(lib().sqa_export_table(self.h, None, 0, C.byref(F)))
+        out = np.empty((self.sweeps, 2 * F.value + 1, 3), dtype=np.uint32)
+        _check(lib().sqa_export_table(self.h, _ptr(out), out.size, C.byref(F)))
+        return out
+
+    def decode(self, decoder: int, readout_slice: int = 0, trees=None):
+        logical = np.empty((self.replicas, self.N), dtype=np.int8)
+        energy = np.empty(self.replicas, dtype=np.int32)
+        t = None if trees is None else np.ascontiguousarray(trees, dtype=np.int32).reshape(-1, self.N)
+        _check(lib().sqa_decode(self.h, decoder, readout_slice, _ptr(t), 0 if t is None else t.shape[0],
+                                _ptr(logical), _ptr(energy)))
+        return logical, energy
+
+    def device_spins(self) -> int:
+        return lib().sqa_device_spins(self.h)
+
+
+def sqa_random_trees(seed: int, n: int, n_trees: int) -> np.ndarray:
+    out = np.empty((n_trees, n), dtype=np.int32)
+    _check(lib().sqa_random_trees(seed, n, n_trees, _ptr(out)))
+    return out
+
+
+def sqa_physical_sites(kind: int, n: int) -> int:
+    return int(lib().sqa_physical_sites(kind, n))
+
+
+def _handle_array(handles: Sequence[SQA]):
+    arr = (C.c_void_p * len(handles))(*[h.h.value for h in handles])
+    return arr
+
+
+class Batch:
+    """All handles' full anneals in one persistent launch, replayed from a HIP graph."""
+
+    def __init__(self, handles: Sequence[SQA], waves_per_group: int = 0, groups_per_cu: int = 0):
+        self.handles = list(handles)
+        self._arr = _handle_array(self.handles)
+        cfg = sqa_launch_config(waves_per_group, groups_per_cu)
+        out = C.c_void_p()
+        _check(lib().sqa_batch_create(C.cast(self._arr, _PVP), len(self.handles), C.byref(cfg), C.byref(out)))
+        self.b = out
+
+    def run(self, stream=None):
+        _check(lib().sqa_batch_run(self.b, _stream(stream)))
+
+    def config(self):
+        c = sqa_launch_config()
+        _check(lib().sqa_batch_config(self.b, C.byref(c)))
+        return c.waves_per_group, c.groups_per_cu
+
+    def close(self):
+        if getattr(self, "b", None):
+            lib().sqa_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sqa_anneal_batch(handles: Sequence[SQA], stream=None):
+    arr = _handle_array(handles)
+    _check(lib().sqa_anneal_batch(C.cast(arr, _PVP), len(handles), _stream(stream)))
+
+
+def sqa_autotune(handles: Sequence[SQA], cache_path: Optional[str] = None):
+    arr = _handle_array(handles)
+    best = sqa_launch_config()
+    _check(lib().sqa_autotune(C.cast(arr, _PVP), len(handles), cache_path.encode() if cache_path else None,
+                              C.byref(best)))
+    return best.waves_per_group, best.groups_per_cu
+
+
+# ---------------------------------------------------------------- PT
+class PT:
+    def __init__(self, kind: int, J, penalty: int, beta_min: float, beta_max: float, temps: int, sweeps: int,
+                 sweeps_per_swap: int, seed: int, h=None):
+        prob, self._keep = make_problem(J, h)
+        emb = sqa_embedding(kind, penalty)
+        p = pt_params(beta_min, beta_max, temps, sweeps, sweeps_per_swap, seed)
+        out = C.c_void_p()
+        _check(lib().pt_create(C.byref(prob), C.byref(emb), C.byref(p), C.byref(out)))
+        self.h = out
+        self.temps = temps
+        self.sites = sqa_physical_sites(kind, int(np.asarray(J).shape[0]))
+
+    def run(self, stream=None):
+        _check(lib().pt_run_handle(self.h, _stream(stream)))
+        return self
+
+    def read(self):
+        spins = np.empty((self.temps, self.sites), dtype=np.int8)
+        E = np.empty(self.temps, dtype=np.int32)
+        rep = np.empty(self.temps, dtype=np.int32)
+        acc = np.zeros(max(self.temps - 1, 1), dtype=np.uint64)
+        _check(lib().pt_read(self.h, _ptr(spins), spins.size, _ptr(E), _ptr(rep), _ptr(acc)))
+        return spins, E, rep, acc[:max(self.temps - 1, 0)]
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().pt_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pt_run_batch(handles: Sequence[PT], stream=None):
+    arr = (C.c_void_p * len(handles))(*[h.h.value for h in handles])
+    _check(lib().pt_run_batch(C.cast(arr, _PVP), len(handles), _stream(stream)))
+
+
+# ---------------------------------------------------------------- server
+class Server:
+    def __init__(self, hbm_budget_bytes: int, max_slots: int, chunk_sweeps: int):
+        out = C.c_void_p()
+        _check(lib().sqa_server_create(hbm_budget_bytes, max_slots, chunk_sweeps, C.byref(out)))
+        self.s = out
+        self._keep = {}
+
+    def submit(self, kind, J, penalty, beta, slices, sweeps, replicas, gamma_start, gamma_end, seed, h=None) -> int:
+        prob, keep = make_problem(J, h)
+        emb = sqa_embedding(kind, penalty)
+        sched = sqa_schedule(beta, slices, sweeps, replicas, gamma_start, gamma_end, None, None, seed)
+        t = C.c_uint64()
+        _check(lib().sqa_server_submit(self.s, C.byref(prob), C.byref(emb), C.byref(sched), C.byref(t)))
+        n = sqa_physical_sites(kind, int(np.asarray(J).shape[0]))
+        self._keep[t.value] = (replicas, slices, n)
+        return t.value
+
+    def poll(self, ticket: int) -> bool:
+        d = C.c_int32()
+        _check(lib().sqa_server_poll(self.s, ticket, C.byref(d)))
+        return bool(d.value)
+
+    def wait(self, ticket: int, timeout_ms: int = -1):
+        _check(lib().sqa_server_wait(self.s, ticket, timeout_ms))
+
+    def result(self, ticket: int):
+        R, L, n = self._keep.pop(ticket)
+        spins = np.empty((R, L, n), dtype=np.int8)
+        E = np.empty((R, L), dtype=np.int32)
+        lat = C.c_double()
+        _check(lib().sqa_server_result(self.s, ticket, _ptr(spins), spins.size, _ptr(E), E.size, C.byref(lat)))
+        return spins, E, lat.value
+
+    def stats(self):
+        v = [C.c_uint64() for _ in range(3)]
+        _check(lib().sqa_server_stats(self.s, *[C.byref(x) for x in v]))
+        return tuple(x.value for x in v)
+
+    def close(self):
+        if getattr(self, "s", None):
+            lib().sqa_server_destroy(self.s)
+            self.s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,150 @@
+"""GPU parity of the SQA path against the CPU oracle, element by element,
+bit-exact (integer spins, integer energies, integer decoded states)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1603_03755_amd.workloads import LHZ, ME, single_job, sk_instance
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sqa():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1603_03755_amd import sqa as s
+    s.lib()
+    return s
+
+
+def _run_both(sqa, kind, J, pen, beta, L, M, R, g0, g1, seed, h=None, gamma=None, bscale=None):
+    print(f"case kind={kind} N={J.shape[0]} L={L} M={M} R={R} seed={seed}", flush=True)
+    dev = sqa.SQA(kind, J, pen, beta, L, M, R, g0, g1, seed, h=h, gamma=gamma, bscale=bscale)
+    emb, table, ospins, oE = O.sqa_anneal(kind, J, pen, beta, L, M, R, g0, g1, seed, h=h, gamma=gamma,
+                                          bscale=bscale, nthreads=8)
+    assert (dev.table() == table).all(), "threshold tables differ"
+    dev.anneal()
+    return dev, emb, ospins, oE
+
+
+@pytest.mark.parametrize("kind", [ME, LHZ])
+def test_single_instance_workload_bit_exact(sqa, kind):
+    """N = 8, L = 32, 16 replicas, 1000 sweeps, beta = 10, Gamma 3 -> 0.01."""
+    j = single_job(kind)
+    dev, emb, ospins, oE = _run_both(sqa, kind, j.J, j.penalty, j.beta, j.slices, j.sweeps, j.replicas,
+                                     j.gamma0, j.gamma1, j.seed)
+    s = dev.spins()
+    assert (s == ospins).all()
+    assert (dev.energies() == oE).all()
+
+
+CASES = [
+    # kind, N, L, M, R, note
+    (ME, 2, 4, 30, 3, "two chains of one spin, empty colour classes"),
+    (ME, 3, 2, 40, 5, "L=2: both neighbours are the same slice"),
+    (LHZ, 3, 1, 50, 4, "L=1: classical Metropolis"),
+    (LHZ, 4, 6, 40, 2, "L not a multiple of 8"),
+    (ME, 5, 10, 25, 7, "ragged slice group, odd replica count"),
+    (LHZ, 7, 64, 20, 6, "L=64, full words"),
+    (ME, 9, 16, 20, 9, "odd N: even chains"),
+    (LHZ, 12, 62, 10, 3, "L=62"),
+    (ME, 24, 64, 3, 2, "largest batched ME lattice"),
+    (LHZ, 32, 64, 3, 2, "N=32 LHZ"),
+]
+
+
+@pytest.mark.parametrize("kind,N,L,M,R,note", CASES)
+def test_edge_shapes_bit_exact(sqa, kind, N, L, M, R, note):
+    J = sk_instance(N, 300 + N)
+    dev, emb, ospins, oE = _run_both(sqa, kind, J, -2, 6.0, L, M, R, 2.5, 0.05, 0xC0FFEE + N)
+    assert (dev.spins() == ospins).all(), note
+    assert (dev.energies() == oE).all(), note
+
+
+def test_fields_weights_and_bscale(sqa):
+    """ME with logical fields h, a strong penalty, mixed-sign J, explicit Gamma and B arrays."""
+    rng = np.random.default_rng(5)
+    N, L, M, R = 6, 8, 30, 4
+    J = sk_instance(N, 77, values=(-3, -1, 1, 2))
+    h = rng.integers(-3, 4, N).astype(np.int32)
+    gamma = np.linspace(2.0, 0.0, M)          # ends exactly at Gamma = 0
+    bscale = np.linspace(0.2, 1.5, M)
+    dev, emb, ospins, oE = _run_both(sqa, ME, J, -5, 3.0, L, M, R, 0, 0, 99, h=h, gamma=gamma, bscale=bscale)
+    assert (dev.spins() == ospins).all()
+    assert (dev.energies() == oE).all()
+
+
+def test_resume_is_bit_identical(sqa):
+    J = sk_instance(8, 4)
+    full = sqa.SQA(LHZ, J, -2, 10.0, 32, 60, 8, 3.0, 0.01, 5).anneal()
+    part = sqa.SQA(LHZ, J, -2, 10.0, 32, 60, 8, 3.0, 0.01, 5)
+    part.anneal_range(0, 17)
+    mid = part.spins()
+    part.anneal_range(17, 41)
+    part.write_spins(part.spins())              # checkpoint round trip through the host
+    part.anneal_range(41, 60)
+    assert (part.spins() == full.spins()).all()
+    emb = O.Embedding(LHZ, J, -2)
+    table = O.sqa_table(10.0, 32, O.gamma_schedule(3.0, 0.01, 60), emb.fmax)
+    ref = O.sqa_init(emb, 32, 8, 5)
+    O.sqa_run(emb, 32, ref, 0, 17, table, 5)
+    assert (mid == ref).all()
+
+
+def test_reset_gives_oracle_initial_state(sqa):
+    J = sk_instance(7, 8)
+    for kind in (ME, LHZ):
+        dev = sqa.SQA(kind, J, -2, 5.0, 24, 10, 5, 3.0, 0.01, 123)
+        dev.reset()
+        emb = O.Embedding(kind, J, -2)
+        assert (dev.spins() == O.sqa_init(emb, 24, 5, 123)).all()
+
+
+def test_me_majority_decode_matches_oracle(sqa):
+    j = single_job(ME, sweeps=200)
+    dev, emb, ospins, oE = _run_both(sqa, ME, j.J, -2, j.beta, j.slices, j.sweeps, j.replicas, j.gamma0, j.gamma1,
+                                     j.seed)
+    for slice_ in (0, 13, 31):
+        logical, E = dev.decode(sqa.SQA_DEC_ME_MAJORITY, slice_)
+        for r in range(j.replicas):
+            q = O.me_majority(emb, ospins[r, slice_])
+            assert (logical[r] == q).all()
+            assert E[r] == O.logical_energy(j.J, q)
+
+
+def test_lhz_tree_and_mwd_decode_match_oracle(sqa):
+    j = single_job(LHZ, sweeps=200)
+    dev, emb, ospins, oE = _run_both(sqa, LHZ, j.J, -2, j.beta, j.slices, j.sweeps, j.replicas, j.gamma0,
+                                     j.gamma1, j.seed)
+    trees = np.vstack([O.chain_tree(8), O.star_tree(8), O.random_trees(11, 8, 5)])
+    logical, E = dev.decode(sqa.SQA_DEC_LHZ_TREES, 3, trees)
+    for r in range(j.replicas):
+        q = O.lhz_tree_decode(8, ospins[r, 3], trees)
+        assert (logical[r] == q).all() and E[r] == O.logical_energy(j.J, q)
+    logical, E = dev.decode(sqa.SQA_DEC_LHZ_MWD, 0)
+    for r in range(j.replicas):
+        q = O.lhz_mwd(8, ospins[r, 0])
+        assert (logical[r] == q).all() and E[r] == O.logical_energy(j.J, q)
+
+
+def test_invalid_arguments_are_rejected(sqa):
+    J = sk_instance(5, 1)
+    with pytest.raises(sqa.SqaError) as e:
+        sqa.SQA(LHZ, J, -2, 1.0, 3, 10, 2, 1.0, 0.1, 1)          # odd L > 1
+    assert e.value.status == sqa.SQA_ERR_INVALID
+    with pytest.raises(sqa.SqaError) as e:
+        sqa.SQA(LHZ, J, -2, 1.0, 128, 10, 2, 1.0, 0.1, 1)        # more than 64 slices
+    assert e.value.status == sqa.SQA_ERR_UNSUPPORTED
+    with pytest.raises(sqa.SqaError) as e:
+        sqa.SQA(LHZ, J, -2, 1.0, 8, 10, 2, 1.0, 0.1, 1, h=np.ones(5, np.int32))
+    assert e.value.status == sqa.SQA_ERR_UNSUPPORTED
+    with pytest.raises(sqa.SqaError):
+        sqa.SQA(ME, J, -200, 1.0, 8, 10, 2, 1.0, 0.1, 1)         # field range above the table limit
+    dev = sqa.SQA(ME, J, -2, 1.0, 8, 10, 2, 1.0, 0.1, 1)
+    with pytest.raises(sqa.SqaError):
+        dev.spins()                                               # nothing run yet
+    with pytest.raises(sqa.SqaError):
+        dev.anneal_range(5, 3)
+    with pytest.raises(sqa.SqaError):
+        dev.decode(sqa.SQA_DEC_LHZ_MWD)
