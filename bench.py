@@ -27,9 +27,13 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_INT32_OPS = 256 * 64 * 2.4e9      # VALU lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz
-PHILOX_OPS_PER_WORD = 25.0             # 10 rounds x (4 multiply halves + 4 xor + 2 key adds) / 4 words
-DECISION_OPS = 6.0                     # time-neighbour sum (2), table index (2), compare (1), flip (1)
+# VALU peak in 32-bit lane-op slots: the fp32 vector rate (157.3 TFLOP/s = 2 flops
+# per FMA) is 78.6e12 full-rate lane-ops/s = 256 CUs x 128 lane-ops/clock x 2.4 GHz.
+PEAK_LANE_OPS = 157.3e12 / 2
+# Philox4x32-10 per 32-bit word: 10 rounds x (2 widening 32x32 multiplies, each
+# 4 full-rate slots at quarter rate, + 2 three-input XORs) / 4 words.
+PHILOX_OPS_PER_WORD = 10 * (2 * 4 + 2) / 4
+DECISION_OPS = 4.0   # compare + select of the Metropolis test, time-neighbour term, table index
 
 
 def parse():
@@ -40,68 +44,55 @@ def parse():
     ap.add_argument("--instances", type=int, default=512)
     ap.add_argument("--sweeps", type=int, default=10_000)
     ap.add_argument("--no-extras", action="store_true", help="only the timed batched steps")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-replicas", type=int, default=2, help="oracle lattices per stratum for cpu_baseline")
     return ap.parse_args()
 
 
 def algorithmic_ops_per_attempt(jobs, O) -> float:
-    """Method arithmetic per attempt averaged over the workload's sites: the
-    Philox share, one product and one accumulate per partner spin of each
-    incident term (plus the site field), and the Metropolis decision."""
+    """Method arithmetic per attempt (full-rate lane-op slots), averaged over the
+    workload's sites: the Philox share of the random word, one multiply-add per
+    incident term and per nonzero field in the local field, and the decision."""
     tot_ops, tot_w = 0.0, 0.0
     seen = {}
     for j in jobs:
         key = (j.kind, j.n)
         if key not in seen:
             emb = O.Embedding(j.kind, j.J, j.penalty)
-            partners = np.zeros(emb.n_sites)
-            for t in range(emb.n_terms):
-                for k in emb.tsite[t][:emb.arity[t]]:
-                    partners[k] += emb.arity[t] - 1
+            terms = np.diff(emb.row).astype(float)
             fields = (emb.h != 0).astype(float)
-            seen[key] = float(np.mean(PHILOX_OPS_PER_WORD + 2 * partners + 2 * fields + DECISION_OPS))
+            seen[key] = float(np.mean(PHILOX_OPS_PER_WORD + terms + fields + DECISION_OPS))
         w = j.sites * j.slices * j.replicas * j.sweeps
         tot_ops += seen[key] * w
         tot_w += w
     return tot_ops / tot_w
 
 
-def cpu_baseline(jobs, seconds: float):
-    """The oracle on a stratified sample: for every (embedding, N) stratum one
-    instance, 2 replicas, a sweep count sized to about `seconds` of total CPU work."""
+def cpu_baseline(jobs, replicas_per_stratum: int = 2):
+    """The oracle, as it stands, on a bounded sample of the same workload: for
+    every (embedding, N) stratum its first instance, `replicas_per_stratum`
+    replica lattices, the full sweep schedule; one host thread per lattice."""
     import oracle as O
-    cores = min(os.cpu_count() or 1, 16)
+    from concurrent.futures import ThreadPoolExecutor
     strata = {}
     for j in jobs:
         strata.setdefault((j.kind, j.n), j)
     sample = list(strata.values())
-    # calibrate on the smallest stratum
-    probe = min(sample, key=lambda j: j.sites)
-    t0 = time.perf_counter()
-    O.sqa_anneal(probe.kind, probe.J, probe.penalty, probe.beta, probe.slices, 20, 2, probe.gamma0,
-                 probe.gamma1, probe.seed, nthreads=2)
-    rate1 = probe.sites * probe.slices * 2 * 20 / max(time.perf_counter() - t0, 1e-6)
-    per_sweep = sum(j.sites * j.slices * 2 for j in sample)
-    sweeps = int(max(5, min(2000, seconds * rate1 * min(cores, 2 * len(sample)) / 2 / per_sweep)))
-    t0 = time.perf_counter()
-    attempts = 0
-    # replicas of all strata spread over the cores: run strata concurrently via threads in C
-    from concurrent.futures import ThreadPoolExecutor
+    lattices = [(j, r) for j in sample for r in range(replicas_per_stratum)]
+    threads = min(len(lattices), os.cpu_count() or 1)
 
-    def run(j):
-        O.sqa_anneal(j.kind, j.J, j.penalty, j.beta, j.slices, sweeps, 2, j.gamma0, j.gamma1, j.seed,
-                     nthreads=2)
-        return j.sites * j.slices * 2 * sweeps
+    def run(jr):
+        j, r = jr
+        O.sqa_anneal(j.kind, j.J, j.penalty, j.beta, j.slices, j.sweeps, 1, j.gamma0, j.gamma1, j.seed,
+                     nthreads=1, r0=r)
+        return j.sites * j.slices * j.sweeps
 
-    with ThreadPoolExecutor(max_workers=max(1, cores // 2)) as ex:
-        for a in ex.map(run, sample):
-            attempts += a
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        attempts = sum(ex.map(run, lattices))
     dt = time.perf_counter() - t0
-    return {"value": attempts / dt, "unit": "spin-flip attempts/s", "cores": min(cores, 2 * len(sample)),
-            "kind": "oracle",
-            "sample": f"{len(sample)} instances (one per embedding x N stratum), 2 replicas each, L=64, "
-                      f"{sweeps} sweeps of the 10^4-sweep schedule's table prefix; {attempts:.3e} attempts in "
-                      f"{dt:.1f} s"}
+    return {"value": attempts / dt, "unit": "spin-flip attempts/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(lattices)} of the workload's replica lattices ({replicas_per_stratum} per embedding x N "
+                      f"stratum), full {sample[0].sweeps}-sweep schedule: {attempts:.3e} attempts in {dt:.1f} s"}
 
 
 def main():
@@ -168,15 +159,17 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int8 spins / int32 energies / uint32 Philox thresholds",
+        "dtype": "int32",
+        "dtype_note": "integer path: +-1 spins (int8 in HBM, bits in LDS), int32 fields and energies, "
+                      "uint32 Philox words compared with uint32 thresholds",
         "data": "synthetic: seeded SK instances J=+-1 standing in for the paper's K8/K16 sets",
         "config": {"workload": f"batched SQA, {args.instances} instances N in {{12,16,20,24}}, half ME half LHZ, "
                                f"64 replicas, L=64, {args.sweeps} sweeps, beta=10, Gamma 3->0.01, penalty -2",
                    "attempts_per_step": attempts_per_step, "launch": {"waves_per_group": waves,
                                                                       "groups_per_cu": gpc},
                    "parallelism": "single GPU, one persistent launch"},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT32_OPS / 1e12,
-                     "unit": "TOP/s (int32 VALU lane-ops)", "frac": achieved / PEAK_INT32_OPS,
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+                     "unit": "TOP/s (32-bit VALU lane-op slots)", "frac": achieved / PEAK_LANE_OPS,
                      "traffic": None, "kernel": "sqa_anneal_kernel", "kernel_ms": kernel_s * 1e3,
                      "ops_per_attempt": ops},
         "kernel_attempts_per_s": attempts_per_step / kernel_s,
@@ -230,7 +223,7 @@ def main():
                           "p99_latency_s": float(np.percentile(lats, 99)), "jobs_per_s": len(tickets) / span,
                           "attempts_per_s": att3 / span, "launches": launches, "peak_resident_bytes": peak,
                           "budget_bytes": 64 << 20, "arrival_rate_per_s": 12.0}
-        out["cpu_baseline"] = cpu_baseline(jobs, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(jobs, args.cpu_replicas)
     print(json.dumps(out), flush=True)
 
 

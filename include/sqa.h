@@ -111,8 +111,9 @@ typedef struct {
  * the per-sweep acceptance-threshold table and the device buffers.  No
  * device work is queued; the lattice is initialised by the first anneal.
  * Errors: SQA_ERR_INVALID (null pointers, n out of range, slices odd > 1,
- * sweeps < 1, replicas out of range, beta <= 0, negative Gamma, |field| sum
- * per site > 127), SQA_ERR_UNSUPPORTED (LHZ with h != 0, slices > 64),
+ * sweeps < 1, replicas out of range, beta <= 0, negative Gamma),
+ * SQA_ERR_UNSUPPORTED (LHZ with h != 0, slices > 64, a site whose
+ * |h| + sum of |incident coefficients| exceeds 63),
  * SQA_ERR_OOM, SQA_ERR_DEVICE. */
 SQA_API sqa_status sqa_create(const sqa_problem *problem, const sqa_embedding *embedding,
                       const sqa_schedule *schedule, sqa_handle **out);

@@ -19,6 +19,7 @@ constexpr int kKindLHZ = 1;
 //    w1 = |w0| | |w1| << 8 | |w2| << 16 | |h| << 24
 //    w2 = negmask | part0 << 16
 //    w3 = part1 | part2 << 16
+//  (part = byte offset 8*d of the partner's lattice word)
 //  LHZ (12 words, 48 B): terms T=4, three partners each (a 3-body term's
 //  third partner is the zero word)
 //    w0 = site | base << 16

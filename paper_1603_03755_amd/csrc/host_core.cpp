@@ -103,7 +103,7 @@ sqa_status build_embedding(const sqa_problem &p, const sqa_embedding &em, Embedd
   }
   e.fmax = 0;
   for (int32_t f : fsite) e.fmax = std::max(e.fmax, f);
-  if (e.fmax > 127) return fail(SQA_ERR_INVALID, "sum of |coefficients| at one site exceeds 127");
+  if (e.fmax > 63) return fail(SQA_ERR_UNSUPPORTED, "sum of |coefficients| at one site exceeds 63");
   if (emax > (1ll << 30)) return fail(SQA_ERR_INVALID, "energy range too large");
   e.emax = static_cast<int32_t>(emax);
   *out = std::move(e);
@@ -131,6 +131,7 @@ sqa_status build_layout(const Embedded &emb, int32_t F, DeviceLayout *out) {
   for (size_t t = 0; t < emb.terms.size(); ++t)
     for (int q = 0; q < emb.terms[t].arity; ++q) inc[emb.terms[t].s[q]].push_back(static_cast<int32_t>(t));
   const uint32_t zero = static_cast<uint32_t>(n);  // index of the all-zero lattice word
+  if (8u * zero + 7u > 0xFFFFu) return fail(SQA_ERR_UNSUPPORTED, "lattice byte offsets exceed 16 bits");
   L.rec.assign(static_cast<size_t>(n) * L.rec_words, 0u);
   L.hfield.assign(n, 0);
   for (int32_t d = 0; d < n; ++d) {
@@ -138,8 +139,8 @@ sqa_status build_layout(const Embedded &emb, int32_t F, DeviceLayout *out) {
     if (static_cast<int>(inc[k].size()) > T) return fail(SQA_ERR_UNSUPPORTED, "site with too many terms");
     uint32_t aw[4] = {0, 0, 0, 0};
     uint32_t neg = 0;
-    uint32_t part[12];
-    for (int q = 0; q < 12; ++q) part[q] = zero;
+    uint32_t part[12];   // byte offsets of the partners' lattice words
+    for (int q = 0; q < 12; ++q) part[q] = 8u * zero;
     int32_t fs = std::abs(emb.h[k]);
     for (size_t a = 0; a < inc[k].size(); ++a) {
       const Term &t = emb.terms[inc[k][a]];
@@ -148,7 +149,7 @@ sqa_status build_layout(const Embedded &emb, int32_t F, DeviceLayout *out) {
       if (t.w < 0) neg |= 1u << a;
       int q = 0;
       for (int z = 0; z < t.arity; ++z)
-        if (t.s[z] != k) part[P * a + (q++)] = L.dev_of[t.s[z]];
+        if (t.s[z] != k) part[P * a + (q++)] = 8u * L.dev_of[t.s[z]];
       if (q > P) return fail(SQA_ERR_UNSUPPORTED, "term arity above the kernel limit");
     }
     if (emb.h[k] < 0) neg |= 1u << 4;

@@ -8,11 +8,12 @@
 // chains (Eq. (4)).
 //
 // Data layout on the device.  Each replica's space-time lattice is held in
-// LDS for the whole anneal, one 64-bit word per site with bit tau = 1 for a
-// -1 spin on slice tau.  A lane processes one "item": one site, one slice
-// parity p and one group g of eight slices, i.e. the four same-parity slices
-// 8g+p, 8g+p+2, 8g+p+4, 8g+p+6, which share one Philox4x32-10 call (counter
-// (site, 2g+p, sweep, SQA<<24 | replica), one 32-bit word per slice).  All
+// LDS for the whole anneal, one 64-bit word per site: even slices in the low
+// half (bit j = slice 2j), odd slices in the high half, a set bit = spin -1.
+// A lane processes one "item": one site, one slice parity p and one group g,
+// i.e. the four same-parity slices 8g+p, 8g+p+2, 8g+p+4, 8g+p+6 (a nibble of
+// the parity-p half), which share one Philox4x32-10 call (counter (site,
+// 2g+p, sweep, SQA<<24 | replica), one 32-bit word per slice).  All
 // arithmetic is integer; acceptance compares the word with a threshold read
 // from a per-sweep table indexed by (s*f, s*(time-neighbour sum)).
 #include <hip/hip_runtime.h>
@@ -37,8 +38,9 @@ __device__ __forceinline__ Words4 philox4x32_10(uint32_t x0, uint32_t x1, uint32
   for (int round = 0; round < 10; ++round) {
     const uint64_t pa = static_cast<uint64_t>(kMulA) * x0;
     const uint64_t pb = static_cast<uint64_t>(kMulB) * x2;
-    const uint32_t y0 = static_cast<uint32_t>(pb >> 32) ^ x1 ^ key0;
-    const uint32_t y2 = static_cast<uint32_t>(pa >> 32) ^ x3 ^ key1;
+    // three-input XORs (truth table 0x96)
+    const uint32_t y0 = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(pb >> 32), x1, key0, 0x96);
+    const uint32_t y2 = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(pa >> 32), x3, key1, 0x96);
     x1 = static_cast<uint32_t>(pb);
     x3 = static_cast<uint32_t>(pa);
     x0 = y0;
@@ -62,25 +64,32 @@ __device__ __forceinline__ void wave_sync() {
 __device__ __forceinline__ uint32_t bit_at(uint32_t v, int q) { return (v >> q) & 1u; }
 
 // ------------------------------------------------------------ lattice I/O
+// LDS word of a site: bits 0..31 hold the even slices (bit j = slice 2j),
+// bits 32..63 the odd slices (bit 32+j = slice 2j+1); a set bit is spin -1.
+// With L = 1 only bit 0 is used.
+__device__ __forceinline__ int slice_bit(int tau) { return (tau >> 1) + ((tau & 1) << 5); }
+
 // Builds the initial lattice in LDS: s = -1 iff bit 31 of the INIT-stream word
 // of (replica, slice, site, sweep 0).
 __device__ void init_lattice(const HandleDev &H, uint64_t *lat, int rep, int lane) {
   const int L = H.L, n = H.n;
   const int G = (L + 7) >> 3;
   const uint32_t c3 = (kStreamInit << 24) | static_cast<uint32_t>(rep);
-  const uint64_t valid = (L == 64) ? ~0ull : ((1ull << L) - 1ull);
+  const int rw = (H.kind == kKindME) ? kRecWordsME : kRecWordsLHZ;
   for (int d = lane; d < n; d += 64) {
-    const uint32_t site = H.rec[d * ((H.kind == kKindME) ? kRecWordsME : kRecWordsLHZ)] & 0xFFFFu;
+    const uint32_t site = H.rec[d * rw] & 0xFFFFu;
     uint64_t w = 0;
     for (int g = 0; g < G; ++g) {
       for (int p = 0; p < 2; ++p) {
         const Words4 u = philox4x32_10(site, static_cast<uint32_t>((g << 1) | p), 0u, c3, H.seed_lo, H.seed_hi);
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
-          w |= static_cast<uint64_t>(u.v[k] >> 31) << (8 * g + p + 2 * k);
+        for (int k = 0; k < 4; ++k) {
+          const int tau = 8 * g + p + 2 * k;
+          if (tau < L) w |= static_cast<uint64_t>(u.v[k] >> 31) << slice_bit(tau);
+        }
       }
     }
-    lat[d] = w & valid;
+    lat[d] = w;
   }
   if (lane == 0) lat[n] = 0;
 }
@@ -92,7 +101,7 @@ __device__ void load_lattice(const HandleDev &H, uint64_t *lat, int rep, int lan
   for (int k = lane; k < n; k += 64) {
     uint64_t w = 0;
     for (int tau = 0; tau < L; ++tau)
-      w |= static_cast<uint64_t>(src[static_cast<size_t>(tau) * n + k] < 0) << tau;
+      w |= static_cast<uint64_t>(src[static_cast<size_t>(tau) * n + k] < 0) << slice_bit(tau);
     lat[H.dev_of[k]] = w;
   }
   if (lane == 0) lat[n] = 0;
@@ -104,7 +113,7 @@ __device__ void store_lattice(const HandleDev &H, const uint64_t *lat, int rep, 
   for (int k = lane; k < n; k += 64) {
     const uint64_t w = lat[H.dev_of[k]];
     for (int tau = 0; tau < L; ++tau)
-      dst[static_cast<size_t>(tau) * n + k] = ((w >> tau) & 1ull) ? int8_t(-1) : int8_t(1);
+      dst[static_cast<size_t>(tau) * n + k] = ((w >> slice_bit(tau)) & 1ull) ? int8_t(-1) : int8_t(1);
   }
 }
 
@@ -112,22 +121,18 @@ __device__ void store_lattice(const HandleDev &H, const uint64_t *lat, int rep, 
 __device__ void slice_energies(const HandleDev &H, const uint64_t *lat, int rep, int lane) {
   const int tau = lane;
   if (tau >= H.L) return;
+  const int b = slice_bit(tau);
   int32_t E = 0;
-  for (int d = 0; d < H.n; ++d) {
-    const int32_t h = H.hfield[d];
-    const int32_t b = static_cast<int32_t>((lat[d] >> tau) & 1ull);
-    E += h * (1 - 2 * b);
-  }
+  for (int d = 0; d < H.n; ++d) E += H.hfield[d] * (1 - 2 * static_cast<int32_t>((lat[d] >> b) & 1ull));
   for (int t = 0; t < H.n_terms; ++t) {
     const uint32_t s01 = H.term_s[2 * t], s23 = H.term_s[2 * t + 1];
     const uint64_t x = lat[s01 & 0xFFFFu] ^ lat[s01 >> 16] ^ lat[s23 & 0xFFFFu] ^ lat[s23 >> 16];
-    E += H.term_w[t] * (1 - 2 * static_cast<int32_t>((x >> tau) & 1ull));
+    E += H.term_w[t] * (1 - 2 * static_cast<int32_t>((x >> b) & 1ull));
   }
   H.energy[static_cast<size_t>(rep) * H.L + tau] = E;
 }
 
 // ------------------------------------------------------------ SQA sweep
-// Site record fields decoded for one item.
 template <int KIND>
 struct Site;
 
@@ -140,37 +145,51 @@ struct Site<kKindLHZ> {
   static constexpr int T = 4, P = 3, RW = kRecWordsLHZ;
 };
 
-// Attempts on every (site of colour c) x (slice of parity p) of one replica.
-template <int KIND>
-__device__ __forceinline__ void sweep_class(const HandleDev &H, const uint32_t *__restrict__ rec,
-                                            uint64_t *lat, const uint32_t *tab, int c, int p,
-                                            uint32_t m, uint32_t c3, int lane) {
+// Four bits of a nibble moved to bit 0 of four 6-bit fields (bits 0, 6, 12,
+// 18): every partial product of the 24-bit multiply lands on a distinct bit.
+__device__ __forceinline__ uint32_t spread6(uint32_t nib) { return __umul24(nib, 0x8421u) & 0x41041u; }
+
+// 64-lane item loop over one (slice parity p, colour c) class of one replica.
+// Item = (site of colour c, group g of four parity-p slices), slices
+// tau = 8g + p + 2w (w = 0..3) = bits 4g+w of the parity-p half word.
+// For each slice the acceptance index is base - (6 S + e), with
+//   S = sum_t |w_t| X_t + |h| O   (X_t = 1 iff term t's product with the own
+//       spin disagrees with the sign of w_t; O likewise for the field),
+//   e = number of time neighbours whose spin differs from the own spin;
+// S and e of the four slices are accumulated side by side in 6-bit fields.
+// SMALLF: 6 S + e < 64 fits one field (F <= 10).
+template <int KIND, bool SMALLF>
+__device__ __forceinline__ void sweep_class(const HandleDev &H, const uint32_t *__restrict__ rec, uint32_t *lat32,
+                                            const uint32_t *tab, int c, int p, uint32_t m, uint32_t c3, int lane) {
   using S = Site<KIND>;
   const int L = H.L;
-  const int G = (L + 7) >> 3;
+  const int Hp = (L == 1) ? 1 : (L >> 1);       // slices of one parity
+  const int G = (Hp + 3) >> 2;
   const int lo = H.cls[c];
   const int nc = H.cls[c + 1] - lo;
   if (nc <= 0) return;
   const int cnt = nc * G;
-  const float inv = 1.0f / static_cast<float>(nc);
-  uint8_t *latb = reinterpret_cast<uint8_t *>(lat);
-  for (int it = lane; it < cnt; it += 64) {
-    int g = static_cast<int>(static_cast<float>(it) * inv);
-    int j = it - g * nc;
-    if (j < 0) { g -= 1; j += nc; }
-    else if (j >= nc) { g += 1; j -= nc; }
+  const uint8_t *latb = reinterpret_cast<const uint8_t *>(lat32);
+  const bool ring32 = (Hp & (Hp - 1)) == 0;     // Hp divides 32: rotate a replicated word
+  const bool ragged = (Hp & 3) != 0;            // last group has fewer than four slices
+  // item it = g * nc + j; lanes advance by 64 items: (j, g) += (64 % nc, 64 / nc)
+  const int dq = 64 / nc, dr = 64 - dq * nc;
+  int g = lane / nc;
+  int j = lane - g * nc;
+  for (int it = lane; it < cnt; it += 64, j += dr, g += dq) {
+    if (j >= nc) { j -= nc; g += 1; }
     const int d = lo + j;
     const uint32_t *r = rec + d * S::RW;
 
     uint32_t site, base, aw[4], ah, neg;
-    uint32_t part[S::T * S::P];
+    uint32_t poff[S::T * S::P];
     if constexpr (KIND == kKindME) {
       const uint4 r0 = *reinterpret_cast<const uint4 *>(r);
       site = r0.x & 0xFFFFu; base = r0.x >> 16;
       aw[0] = r0.y & 0xFFu; aw[1] = (r0.y >> 8) & 0xFFu; aw[2] = (r0.y >> 16) & 0xFFu; aw[3] = 0;
       ah = r0.y >> 24;
       neg = r0.z & 0xFFu;
-      part[0] = r0.z >> 16; part[1] = r0.w & 0xFFFFu; part[2] = r0.w >> 16;
+      poff[0] = r0.z >> 16; poff[1] = r0.w & 0xFFFFu; poff[2] = r0.w >> 16;
     } else {
       const uint4 r0 = *reinterpret_cast<const uint4 *>(r);
       const uint4 r1 = *reinterpret_cast<const uint4 *>(r + 4);
@@ -182,54 +201,77 @@ __device__ __forceinline__ void sweep_class(const HandleDev &H, const uint32_t *
       const uint32_t pw[6] = {r1.x, r1.y, r1.z, r1.w, r2.x, r2.y};
 #pragma unroll
       for (int q = 0; q < 6; ++q) {
-        part[2 * q] = pw[q] & 0xFFFFu;
-        part[2 * q + 1] = pw[q] >> 16;
+        poff[2 * q] = pw[q] & 0xFFFFu;
+        poff[2 * q + 1] = pw[q] >> 16;
       }
     }
 
-    // own spins of the eight slices 8g..8g+7 and their time neighbours
-    const uint64_t x = lat[d];
-    const int g8 = 8 * g;
-    const uint32_t own = static_cast<uint32_t>(x >> g8) & 0xFFu;
+    const uint2 word = *reinterpret_cast<const uint2 *>(lat32 + 2 * d);
+    const uint32_t own_half = p ? word.y : word.x;
+    const uint32_t oth_half = p ? word.x : word.y;
+    const int sh = 4 * g;
+    const uint32_t own = (own_half >> sh) & 0xFu;
+
+    // time neighbours: other-parity bits j (n0) and j-1 (p = 0) or j+1 (p = 1), ring of Hp
     uint32_t dn, up;
     if (L == 1) {
-      dn = own;            // no time coupling: b = 0 exactly
-      up = ~own;
+      dn = own;               // no time coupling: exactly one "differing neighbour", b = 0
+      up = own ^ 0xFu;
     } else {
-      const int sp = (g > 0) ? (g8 - 1) : (L - 1);
-      const int pos = min(7, L - 1 - g8);
-      const int sn = (g8 + pos + 1 == L) ? 0 : (g8 + pos + 1);
-      dn = ((own << 1) | static_cast<uint32_t>((x >> sp) & 1ull)) & 0xFFu;
-      up = (own >> 1) | (static_cast<uint32_t>((x >> sn) & 1ull) << pos);
+      const uint32_t n0 = (oth_half >> sh) & 0xFu;
+      const int s1 = p ? ((sh + 1 == Hp) ? 0 : sh + 1) : ((g == 0) ? Hp - 1 : sh - 1);
+      uint32_t n1;
+      if (ring32) {
+        uint32_t y = oth_half;
+        for (int k = Hp; k < 32; k <<= 1) y |= y << k;
+        n1 = __builtin_amdgcn_alignbit(y, y, static_cast<uint32_t>(s1)) & 0xFu;
+      } else {
+        const uint64_t yy = static_cast<uint64_t>(oth_half) | (static_cast<uint64_t>(oth_half) << Hp);
+        n1 = static_cast<uint32_t>(yy >> s1) & 0xFu;
+      }
+      dn = p ? n0 : n1;
+      up = p ? n1 : n0;
     }
-    const uint32_t e1 = own ^ dn, e2 = own ^ up;
+    const uint32_t ev = spread6(own ^ dn) + spread6(own ^ up);
 
-    // per-term "product differs from own spin" bits, sign-folded so that
-    // a = s*f = F_site - 2 * (sum_t |w_t| X_t + |h| O)
-    uint32_t X[S::T];
+    // weighted disagreement counts of the four slices, side by side
+    const uint8_t *lb = latb + (4 * p + (g >> 1));   // byte of the item's nibble in any site word
+    const uint32_t nsh = static_cast<uint32_t>(g & 1) * 4u;
+    const uint32_t own_byte = own << nsh;
+    uint32_t acc = __umul24(spread6(own ^ (0u - ((neg >> 4) & 1u) & 0xFu)), ah);
 #pragma unroll
     for (int t = 0; t < S::T; ++t) {
-      uint32_t prod = 0;
+      uint32_t prod = own_byte;
 #pragma unroll
-      for (int q = 0; q < S::P; ++q) prod ^= latb[part[S::P * t + q] * 8 + g];
-      X[t] = own ^ prod ^ (0u - ((neg >> t) & 1u));
+      for (int q = 0; q < S::P; ++q) prod ^= lb[poff[S::P * t + q]];
+      const uint32_t x = ((prod >> nsh) ^ (0u - ((neg >> t) & 1u))) & 0xFu;
+      acc += __umul24(spread6(x), aw[t]);
     }
-    const uint32_t O = own ^ (0u - ((neg >> 4) & 1u));
 
     const Words4 u = philox4x32_10(site, static_cast<uint32_t>((g << 1) | p), m, c3, H.seed_lo, H.seed_hi);
+    const uint32_t *tb = tab + base;                  // thresholds are read at tb[-(6 S + e)]
     uint32_t flip = 0;
+    if constexpr (SMALLF) {
+      const uint32_t f6 = (acc << 2) + (acc << 1) + ev;
 #pragma unroll
-    for (int w = 0; w < 4; ++w) {
-      const int q = p + 2 * w;
-      uint32_t s = ah * bit_at(O, q);
+      for (int w = 0; w < 4; ++w) {
+        const uint32_t R = *(tb - ((f6 >> (6 * w)) & 63u));
+        if (min(u.v[w], 0xFFFFFFFEu) < R) flip |= 1u << w;
+      }
+    } else {
 #pragma unroll
-      for (int t = 0; t < S::T; ++t) s += aw[t] * bit_at(X[t], q);
-      const uint32_t idx = base - 6u * s - bit_at(e1, q) - bit_at(e2, q);
-      const uint32_t R = tab[idx];
-      const bool acc = (min(u.v[w], 0xFFFFFFFEu) < R) && (g8 + q < L);
-      flip |= static_cast<uint32_t>(acc) << q;
+      for (int w = 0; w < 4; ++w) {
+        const uint32_t sv = (acc >> (6 * w)) & 63u;
+        const uint32_t e = (ev >> (6 * w)) & 3u;
+        const uint32_t R = *(tb - (6u * sv + e));
+        if (min(u.v[w], 0xFFFFFFFEu) < R) flip |= 1u << w;
+      }
     }
-    latb[d * 8 + g] = static_cast<uint8_t>(own ^ flip);
+    if (ragged) {            // slices beyond the parity's last one stay put
+      const int valid = Hp - sh;
+      if (valid < 4) flip &= (1u << valid) - 1u;
+    }
+    if (flip) atomicXor(lat32 + 2 * d + p, flip << sh);
   }
 }
 
@@ -245,9 +287,11 @@ __device__ void anneal_replica(const HandleDev &H, const uint32_t *rec, uint64_t
     const uint32_t *row = H.table + static_cast<size_t>(m) * H.tw;
     for (int i = lane; i < H.tw; i += 64) tab[i] = row[i];
     wave_sync();
+    uint32_t *lat32 = reinterpret_cast<uint32_t *>(lat);
     for (int p = 0; p < parities; ++p)
       for (int c = 0; c < 4; ++c) {
-        sweep_class<KIND>(H, rec, lat, tab, c, p, static_cast<uint32_t>(m), c3, lane);
+        if (H.F <= 10) sweep_class<KIND, true>(H, rec, lat32, tab, c, p, static_cast<uint32_t>(m), c3, lane);
+        else sweep_class<KIND, false>(H, rec, lat32, tab, c, p, static_cast<uint32_t>(m), c3, lane);
         wave_sync();
       }
   }
@@ -415,7 +459,7 @@ __device__ void pt_ladder(const PTDev &P, const uint32_t *rec, uint64_t *lat, co
         for (int t = 0; t < S::T; ++t) {
           uint32_t prod = 0;
 #pragma unroll
-          for (int q = 0; q < S::P; ++q) prod ^= latb[part[S::P * t + q] * 8 + byte];
+          for (int q = 0; q < S::P; ++q) prod ^= latb[part[S::P * t + q] + byte];
           X[t] = own ^ (prod >> nsh) ^ (0u - ((neg >> t) & 1u));
         }
         const uint32_t O = own ^ (0u - ((neg >> 4) & 1u));
