@@ -241,7 +241,7 @@ sqa_status sqa_create(const sqa_problem *problem, const sqa_embedding *embedding
     h->has_h = true;
     std::copy(problem->h, problem->h + h->N, h->h.begin());
   }
-  st = build_layout(h->emb, h->F, &h->lay);
+  st = build_layout(h->emb, h->F, true, &h->lay);
   if (st != SQA_OK) {
     delete h;
     return st;

@@ -30,6 +30,9 @@ constexpr int kKindLHZ = 1;
 //    w10, w11 = 0
 // negmask bit t (t < 4): weight of term t is negative; bit 4: h < 0.
 // base = 3 * (F_site + F) + 2, F_site = |h| + sum |w_t|.
+// Weights |w|, |h| in the records are stored multiplied by 6 when F <= kSmallF
+// (the sweep kernel then indexes the table with the field sums directly).
+constexpr int kSmallF = 10;
 constexpr int kRecWordsME = 4;
 constexpr int kRecWordsLHZ = 12;
 

@@ -110,7 +110,7 @@ sqa_status build_embedding(const sqa_problem &p, const sqa_embedding &em, Embedd
   return SQA_OK;
 }
 
-sqa_status build_layout(const Embedded &emb, int32_t F, DeviceLayout *out) {
+sqa_status build_layout(const Embedded &emb, int32_t F, bool scale6, DeviceLayout *out) {
   DeviceLayout L;
   const int32_t n = emb.n;
   const bool me = emb.kind == SQA_EMB_ME;
@@ -153,7 +153,11 @@ sqa_status build_layout(const Embedded &emb, int32_t F, DeviceLayout *out) {
       if (q > P) return fail(SQA_ERR_UNSUPPORTED, "term arity above the kernel limit");
     }
     if (emb.h[k] < 0) neg |= 1u << 4;
-    const uint32_t ah = static_cast<uint32_t>(std::abs(emb.h[k]));
+    uint32_t ah = static_cast<uint32_t>(std::abs(emb.h[k]));
+    if (scale6 && F <= kSmallF) {        // the SQA kernel sums 6|w| directly
+      for (int a = 0; a < 4; ++a) aw[a] *= 6u;
+      ah *= 6u;
+    }
     const uint32_t base = static_cast<uint32_t>(3 * (fs + F) + 2);
     uint32_t *r = &L.rec[static_cast<size_t>(d) * L.rec_words];
     r[0] = static_cast<uint32_t>(k) | (base << 16);

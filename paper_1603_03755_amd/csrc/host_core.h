@@ -50,7 +50,8 @@ struct DeviceLayout {
   int32_t cls[5] = {0, 0, 0, 0, 0};
 };
 
-sqa_status build_layout(const Embedded &emb, int32_t F, DeviceLayout *out);
+// scale6: store 6|w| and 6|h| when F <= kSmallF (SQA records; PT uses plain weights).
+sqa_status build_layout(const Embedded &emb, int32_t F, bool scale6, DeviceLayout *out);
 
 // ---------------------------------------------------------- tables
 uint32_t threshold_from_log(double x);

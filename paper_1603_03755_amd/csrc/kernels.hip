@@ -10,10 +10,11 @@
 // Data layout on the device.  Each replica's space-time lattice is held in
 // LDS for the whole anneal, one 64-bit word per site: even slices in the low
 // half (bit j = slice 2j), odd slices in the high half, a set bit = spin -1.
-// A lane processes one "item": one site, one slice parity p and one group g,
-// i.e. the four same-parity slices 8g+p, 8g+p+2, 8g+p+4, 8g+p+6 (a nibble of
-// the parity-p half), which share one Philox4x32-10 call (counter (site,
-// 2g+p, sweep, SQA<<24 | replica), one 32-bit word per slice).  All
+// A lane processes one "item": one site, one slice parity p and one byte b of
+// the parity-p half, i.e. the eight same-parity slices 16b+p+2k (k = 0..7).
+// Four same-parity slices 8g+p+2w (w = 0..3) share one Philox4x32-10 call
+// (counter (site, 2g+p, sweep, SQA<<24 | replica), one 32-bit word per
+// slice), so an item uses the calls of groups g = 2b and 2b+1.  All
 // arithmetic is integer; acceptance compares the word with a threshold read
 // from a per-sweep table indexed by (s*f, s*(time-neighbour sum)).
 #include <hip/hip_runtime.h>
@@ -147,47 +148,54 @@ struct Site<kKindLHZ> {
 
 // Four bits of a nibble moved to bit 0 of four 6-bit fields (bits 0, 6, 12,
 // 18): every partial product of the 24-bit multiply lands on a distinct bit.
-__device__ __forceinline__ uint32_t spread6(uint32_t nib) { return __umul24(nib, 0x8421u) & 0x41041u; }
+__device__ __forceinline__ uint32_t spread6(uint32_t nib) { return __umul24(nib & 0xFu, 0x8421u) & 0x41041u; }
+// The same for bits 4..7 of a byte.
+__device__ __forceinline__ uint32_t spread6_hi(uint32_t byte) {
+  return (__umul24(byte & 0xF0u, 0x8421u) >> 4) & 0x41041u;
+}
 
 // 64-lane item loop over one (slice parity p, colour c) class of one replica.
-// Item = (site of colour c, group g of four parity-p slices), slices
-// tau = 8g + p + 2w (w = 0..3) = bits 4g+w of the parity-p half word.
-// For each slice the acceptance index is base - (6 S + e), with
+// Item = (site of colour c, byte b of its parity-p half word): the eight slices
+// tau = 16b + 2k + p (k = 0..7), served by the two Philox calls of slice groups
+// 2b and 2b+1 (four words each).  For each slice the acceptance index is
+// base - (6 S + e), with
 //   S = sum_t |w_t| X_t + |h| O   (X_t = 1 iff term t's product with the own
 //       spin disagrees with the sign of w_t; O likewise for the field),
 //   e = number of time neighbours whose spin differs from the own spin;
-// S and e of the four slices are accumulated side by side in 6-bit fields.
-// SMALLF: 6 S + e < 64 fits one field (F <= 10).
-template <int KIND, bool SMALLF>
+// S and e are accumulated four slices at a time in 6-bit fields.
+// SMALLF (F <= 10): the records carry 6|w| and 6|h|, so the fields hold 6 S
+//   directly and 6 S + e < 64 stays inside a field.
+// FASTL: L in {16, 32, 64} (whole bytes, replicated-word rotation, L > 1).
+template <int KIND, bool SMALLF, bool FASTL>
 __device__ __forceinline__ void sweep_class(const HandleDev &H, const uint32_t *__restrict__ rec, uint32_t *lat32,
                                             const uint32_t *tab, int c, int p, uint32_t m, uint32_t c3, int lane) {
   using S = Site<KIND>;
   const int L = H.L;
   const int Hp = (L == 1) ? 1 : (L >> 1);       // slices of one parity
-  const int G = (Hp + 3) >> 2;
+  const int B = (Hp + 7) >> 3;                  // bytes per parity half
   const int lo = H.cls[c];
   const int nc = H.cls[c + 1] - lo;
   if (nc <= 0) return;
-  const int cnt = nc * G;
-  const uint8_t *latb = reinterpret_cast<const uint8_t *>(lat32);
-  const bool ring32 = (Hp & (Hp - 1)) == 0;     // Hp divides 32: rotate a replicated word
-  const bool ragged = (Hp & 3) != 0;            // last group has fewer than four slices
-  // item it = g * nc + j; lanes advance by 64 items: (j, g) += (64 % nc, 64 / nc)
+  const int cnt = nc * B;
+  uint8_t *latb = reinterpret_cast<uint8_t *>(lat32);
+  const bool ring32 = FASTL || (Hp & (Hp - 1)) == 0;   // Hp divides 32: rotate a replicated word
+  const bool ragged = !FASTL && (Hp & 7) != 0;          // last byte has fewer than eight slices
+  // item it = b * nc + j; lanes advance by 64 items: (j, b) += (64 % nc, 64 / nc)
   const int dq = 64 / nc, dr = 64 - dq * nc;
-  int g = lane / nc;
-  int j = lane - g * nc;
-  for (int it = lane; it < cnt; it += 64, j += dr, g += dq) {
-    if (j >= nc) { j -= nc; g += 1; }
+  int b = lane / nc;
+  int j = lane - b * nc;
+  for (int it = lane; it < cnt; it += 64, j += dr, b += dq) {
+    if (j >= nc) { j -= nc; b += 1; }
     const int d = lo + j;
     const uint32_t *r = rec + d * S::RW;
 
-    uint32_t site, base, aw[4], ah, neg;
+    uint32_t site, base, wts, hw, neg;
     uint32_t poff[S::T * S::P];
     if constexpr (KIND == kKindME) {
       const uint4 r0 = *reinterpret_cast<const uint4 *>(r);
       site = r0.x & 0xFFFFu; base = r0.x >> 16;
-      aw[0] = r0.y & 0xFFu; aw[1] = (r0.y >> 8) & 0xFFu; aw[2] = (r0.y >> 16) & 0xFFu; aw[3] = 0;
-      ah = r0.y >> 24;
+      wts = r0.y & 0xFFFFFFu;
+      hw = r0.y >> 24;
       neg = r0.z & 0xFFu;
       poff[0] = r0.z >> 16; poff[1] = r0.w & 0xFFFFu; poff[2] = r0.w >> 16;
     } else {
@@ -195,8 +203,8 @@ __device__ __forceinline__ void sweep_class(const HandleDev &H, const uint32_t *
       const uint4 r1 = *reinterpret_cast<const uint4 *>(r + 4);
       const uint2 r2 = *reinterpret_cast<const uint2 *>(r + 8);
       site = r0.x & 0xFFFFu; base = r0.x >> 16;
-      aw[0] = r0.y & 0xFFu; aw[1] = (r0.y >> 8) & 0xFFu; aw[2] = (r0.y >> 16) & 0xFFu; aw[3] = r0.y >> 24;
-      ah = r0.z & 0xFFu;
+      wts = r0.y;
+      hw = r0.z & 0xFFu;
       neg = (r0.z >> 8) & 0xFFu;
       const uint32_t pw[6] = {r1.x, r1.y, r1.z, r1.w, r2.x, r2.y};
 #pragma unroll
@@ -205,73 +213,82 @@ __device__ __forceinline__ void sweep_class(const HandleDev &H, const uint32_t *
         poff[2 * q + 1] = pw[q] >> 16;
       }
     }
+    const uint32_t negh = 0u - ((neg >> 4) & 1u);   // 0 or all ones: field sign
 
     const uint2 word = *reinterpret_cast<const uint2 *>(lat32 + 2 * d);
     const uint32_t own_half = p ? word.y : word.x;
     const uint32_t oth_half = p ? word.x : word.y;
-    const int sh = 4 * g;
-    const uint32_t own = (own_half >> sh) & 0xFu;
+    const int sh = 8 * b;
+    const uint32_t own = (own_half >> sh) & 0xFFu;
 
     // time neighbours: other-parity bits j (n0) and j-1 (p = 0) or j+1 (p = 1), ring of Hp
     uint32_t dn, up;
-    if (L == 1) {
+    if (!FASTL && L == 1) {
       dn = own;               // no time coupling: exactly one "differing neighbour", b = 0
-      up = own ^ 0xFu;
+      up = own ^ 0xFFu;
     } else {
-      const uint32_t n0 = (oth_half >> sh) & 0xFu;
-      const int s1 = p ? ((sh + 1 == Hp) ? 0 : sh + 1) : ((g == 0) ? Hp - 1 : sh - 1);
+      const uint32_t n0 = (oth_half >> sh) & 0xFFu;
+      const int s1 = p ? ((!FASTL && sh + 1 == Hp) ? 0 : sh + 1) : ((b == 0) ? Hp - 1 : sh - 1);
       uint32_t n1;
       if (ring32) {
         uint32_t y = oth_half;
         for (int k = Hp; k < 32; k <<= 1) y |= y << k;
-        n1 = __builtin_amdgcn_alignbit(y, y, static_cast<uint32_t>(s1)) & 0xFu;
+        n1 = __builtin_amdgcn_alignbit(y, y, static_cast<uint32_t>(s1)) & 0xFFu;
       } else {
         const uint64_t yy = static_cast<uint64_t>(oth_half) | (static_cast<uint64_t>(oth_half) << Hp);
-        n1 = static_cast<uint32_t>(yy >> s1) & 0xFu;
+        n1 = static_cast<uint32_t>(yy >> s1) & 0xFFu;
       }
       dn = p ? n0 : n1;
       up = p ? n1 : n0;
     }
-    const uint32_t ev = spread6(own ^ dn) + spread6(own ^ up);
+    const uint32_t e1 = own ^ dn, e2 = own ^ up;
+    const uint32_t ev_lo = spread6(__builtin_amdgcn_ubfe(e1, 0, 4)) + spread6(__builtin_amdgcn_ubfe(e2, 0, 4));
+    const uint32_t ev_hi = spread6_hi(e1) + spread6_hi(e2);
 
-    // weighted disagreement counts of the four slices, side by side
-    const uint8_t *lb = latb + (4 * p + (g >> 1));   // byte of the item's nibble in any site word
-    const uint32_t nsh = static_cast<uint32_t>(g & 1) * 4u;
-    const uint32_t own_byte = own << nsh;
-    uint32_t acc = __umul24(spread6(own ^ (0u - ((neg >> 4) & 1u) & 0xFu)), ah);
+    // weighted disagreement counts, slices k = 0..3 in acc_lo and 4..7 in acc_hi
+    const uint8_t *lb = latb + (4 * p + b);        // the item's byte in any site word
+    const uint32_t ox = (own ^ negh) & 0xFFu;
+    uint32_t acc_lo = __umul24(spread6(__builtin_amdgcn_ubfe(ox, 0, 4)), hw);
+    uint32_t acc_hi = __umul24(spread6(__builtin_amdgcn_ubfe(ox, 4, 4)), hw);
 #pragma unroll
     for (int t = 0; t < S::T; ++t) {
-      uint32_t prod = own_byte;
+      uint32_t prod = own;
 #pragma unroll
       for (int q = 0; q < S::P; ++q) prod ^= lb[poff[S::P * t + q]];
-      const uint32_t x = ((prod >> nsh) ^ (0u - ((neg >> t) & 1u))) & 0xFu;
-      acc += __umul24(spread6(x), aw[t]);
+      const uint32_t x = prod ^ (0u - ((neg >> t) & 1u));
+      const uint32_t wt = (wts >> (8 * t)) & 0xFFu;
+      acc_lo += __umul24(spread6(__builtin_amdgcn_ubfe(x, 0, 4)), wt);
+      acc_hi += __umul24(spread6(__builtin_amdgcn_ubfe(x, 4, 4)), wt);
     }
 
-    const Words4 u = philox4x32_10(site, static_cast<uint32_t>((g << 1) | p), m, c3, H.seed_lo, H.seed_hi);
+    const Words4 u0 = philox4x32_10(site, static_cast<uint32_t>((b << 2) | p), m, c3, H.seed_lo, H.seed_hi);
+    const Words4 u1 = philox4x32_10(site, static_cast<uint32_t>((b << 2) | 2 | p), m, c3, H.seed_lo, H.seed_hi);
     const uint32_t *tb = tab + base;                  // thresholds are read at tb[-(6 S + e)]
     uint32_t flip = 0;
     if constexpr (SMALLF) {
-      const uint32_t f6 = (acc << 2) + (acc << 1) + ev;
+      const uint32_t f_lo = acc_lo + ev_lo;
+      const uint32_t f_hi = acc_hi + ev_hi;
 #pragma unroll
       for (int w = 0; w < 4; ++w) {
-        const uint32_t R = *(tb - ((f6 >> (6 * w)) & 63u));
-        if (min(u.v[w], 0xFFFFFFFEu) < R) flip |= 1u << w;
+        const uint32_t R0 = *(tb - __builtin_amdgcn_ubfe(f_lo, 6 * w, 6));
+        const uint32_t R1 = *(tb - __builtin_amdgcn_ubfe(f_hi, 6 * w, 6));
+        if (min(u0.v[w], 0xFFFFFFFEu) < R0) flip |= 1u << w;
+        if (min(u1.v[w], 0xFFFFFFFEu) < R1) flip |= 16u << w;
       }
     } else {
 #pragma unroll
       for (int w = 0; w < 4; ++w) {
-        const uint32_t sv = (acc >> (6 * w)) & 63u;
-        const uint32_t e = (ev >> (6 * w)) & 3u;
-        const uint32_t R = *(tb - (6u * sv + e));
-        if (min(u.v[w], 0xFFFFFFFEu) < R) flip |= 1u << w;
+        const uint32_t i0 = 6u * __builtin_amdgcn_ubfe(acc_lo, 6 * w, 6) + __builtin_amdgcn_ubfe(ev_lo, 6 * w, 2);
+        const uint32_t i1 = 6u * __builtin_amdgcn_ubfe(acc_hi, 6 * w, 6) + __builtin_amdgcn_ubfe(ev_hi, 6 * w, 2);
+        if (min(u0.v[w], 0xFFFFFFFEu) < *(tb - i0)) flip |= 1u << w;
+        if (min(u1.v[w], 0xFFFFFFFEu) < *(tb - i1)) flip |= 16u << w;
       }
     }
     if (ragged) {            // slices beyond the parity's last one stay put
       const int valid = Hp - sh;
-      if (valid < 4) flip &= (1u << valid) - 1u;
+      if (valid < 8) flip &= (1u << valid) - 1u;
     }
-    if (flip) atomicXor(lat32 + 2 * d + p, flip << sh);
+    latb[8 * d + 4 * p + b] = static_cast<uint8_t>(own ^ flip);
   }
 }
 
@@ -283,6 +300,8 @@ __device__ void anneal_replica(const HandleDev &H, const uint32_t *rec, uint64_t
   wave_sync();
   const uint32_t c3 = (kStreamSQA << 24) | static_cast<uint32_t>(rep);
   const int parities = (H.L == 1) ? 1 : 2;
+  const bool smallf = H.F <= kSmallF;
+  const bool fast = smallf && (H.L == 16 || H.L == 32 || H.L == 64);
   for (int m = H.m0; m < H.m1; ++m) {
     const uint32_t *row = H.table + static_cast<size_t>(m) * H.tw;
     for (int i = lane; i < H.tw; i += 64) tab[i] = row[i];
@@ -290,8 +309,9 @@ __device__ void anneal_replica(const HandleDev &H, const uint32_t *rec, uint64_t
     uint32_t *lat32 = reinterpret_cast<uint32_t *>(lat);
     for (int p = 0; p < parities; ++p)
       for (int c = 0; c < 4; ++c) {
-        if (H.F <= 10) sweep_class<KIND, true>(H, rec, lat32, tab, c, p, static_cast<uint32_t>(m), c3, lane);
-        else sweep_class<KIND, false>(H, rec, lat32, tab, c, p, static_cast<uint32_t>(m), c3, lane);
+        if (fast) sweep_class<KIND, true, true>(H, rec, lat32, tab, c, p, static_cast<uint32_t>(m), c3, lane);
+        else if (smallf) sweep_class<KIND, true, false>(H, rec, lat32, tab, c, p, static_cast<uint32_t>(m), c3, lane);
+        else sweep_class<KIND, false, false>(H, rec, lat32, tab, c, p, static_cast<uint32_t>(m), c3, lane);
         wave_sync();
       }
   }
