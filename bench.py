@@ -35,6 +35,22 @@ PEAK_LANE_OPS = 157.3e12 / 2
 PHILOX_OPS_PER_WORD = 10 * (2 * 4 + 2) / 4
 DECISION_OPS = 4.0   # compare + select of the Metropolis test, time-neighbour term, table index
 
+# HBM bytes of one launch of the sweep kernel on this workload, from rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE passes (KiB per dispatch) scaled by the same counters on a cold 2 GiB copy
+# (profiles/sqa_anneal_kernel_batched512_L64.md).  Valid only for the kernel source it was taken on.
+TRAFFIC_PROFILE = {"kernel_sha256_prefix": "f9c1e5834a3d0d9e", "instances": 512, "sweeps": 10_000,
+                   "fetch_kib": 2215810.125, "write_kib": 775656.8125, "fetch_scale": 2.0, "write_scale": 1.0}
+
+
+def measured_traffic(args):
+    import hashlib
+    src = os.path.join(ROOT, "paper_1603_03755_amd", "csrc", "kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    t = TRAFFIC_PROFILE
+    if not sha.startswith(t["kernel_sha256_prefix"]) or args.instances != t["instances"] or args.sweeps != t["sweeps"]:
+        return None
+    return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -170,7 +186,8 @@ def main():
                    "parallelism": "single GPU, one persistent launch"},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
                      "unit": "TOP/s (32-bit VALU lane-op slots)", "frac": achieved / PEAK_LANE_OPS,
-                     "traffic": None, "kernel": "sqa_anneal_kernel", "kernel_ms": kernel_s * 1e3,
+                     "traffic": measured_traffic(args), "kernel": "sqa_anneal_kernel",
+                     "kernel_ms": kernel_s * 1e3,
                      "ops_per_attempt": ops},
         "kernel_attempts_per_s": attempts_per_step / kernel_s,
         "setup_s": setup_s,

@@ -869,7 +869,7 @@ sqa_status sqa_autotune(sqa_handle *const *handles, int32_t count, const char *c
     hipEvent_t a, z;
     (void)hipEventCreate(&a);
     (void)hipEventCreate(&z);
-    const int trial_sweeps = 20;
+    const int trial_sweeps = 100;
     for (int w : {1, 2, 4, 8}) {
       std::vector<int> m0(count, 0), m1(count);
       for (int i = 0; i < count; ++i) m1[i] = std::min(handles[i]->M, trial_sweeps);

@@ -302,9 +302,18 @@ __device__ void anneal_replica(const HandleDev &H, const uint32_t *rec, uint64_t
   const int parities = (H.L == 1) ? 1 : 2;
   const bool smallf = H.F <= kSmallF;
   const bool fast = smallf && (H.L == 16 || H.L == 32 || H.L == 64);
+  // the next sweep's table row is fetched into a register during the current sweep
+  const bool row_in_reg = H.tw <= 64;
+  uint32_t next_row = 0;
+  if (row_in_reg && lane < H.tw) next_row = H.table[static_cast<size_t>(H.m0) * H.tw + lane];
   for (int m = H.m0; m < H.m1; ++m) {
-    const uint32_t *row = H.table + static_cast<size_t>(m) * H.tw;
-    for (int i = lane; i < H.tw; i += 64) tab[i] = row[i];
+    if (row_in_reg) {
+      if (lane < H.tw) tab[lane] = next_row;
+      if (m + 1 < H.m1 && lane < H.tw) next_row = H.table[static_cast<size_t>(m + 1) * H.tw + lane];
+    } else {
+      const uint32_t *row = H.table + static_cast<size_t>(m) * H.tw;
+      for (int i = lane; i < H.tw; i += 64) tab[i] = row[i];
+    }
     wave_sync();
     uint32_t *lat32 = reinterpret_cast<uint32_t *>(lat);
     for (int p = 0; p < parities; ++p)
@@ -324,7 +333,10 @@ __device__ void anneal_replica(const HandleDev &H, const uint32_t *rec, uint64_t
 // (handle, replica group) from `counter`, stages the handle's site records in
 // LDS, and runs one replica per wavefront through sweeps m0..m1-1.
 // Dynamic LDS: [rec_cap words][waves x lat_cap u64][waves x tab_cap words].
-__global__ __launch_bounds__(512) void sqa_anneal_kernel(const HandleDev *__restrict__ hds,
+#ifndef SQA_WAVES_PER_EU
+#define SQA_WAVES_PER_EU 1
+#endif
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(SQA_WAVES_PER_EU, 8))) void sqa_anneal_kernel(const HandleDev *__restrict__ hds,
                                                          const WorkItem *__restrict__ items, int n_items,
                                                          int *__restrict__ counter, int rec_cap,
                                                          int lat_cap, int tab_cap) {
