@@ -889,15 +889,20 @@ sqa_status sqa_autotune(sqa_handle *const *handles, int32_t count, const char *c
         if (hipMalloc(&dev, oc + 256) != hipSuccess) continue;
         (void)hipMemcpy(dev, hds.data(), bh, hipMemcpyHostToDevice);
         (void)hipMemcpy(static_cast<char *>(dev) + oi, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice);
+        // the second of two identical launches is timed (the first warms caches and code)
         float ms = 0;
-        (void)hipEventRecord(a, nullptr);
-        hipError_t le = launch_sqa_anneal(reinterpret_cast<HandleDev *>(dev),
-                                          reinterpret_cast<WorkItem *>(static_cast<char *>(dev) + oi),
-                                          static_cast<int>(items.size()), reinterpret_cast<int *>(static_cast<char *>(dev) + oc),
-                                          s.grid, s.waves, s.rec_cap, s.lat_cap, s.tab_cap, nullptr);
-        (void)hipEventRecord(z, nullptr);
-        (void)hipEventSynchronize(z);
-        (void)hipEventElapsedTime(&ms, a, z);
+        hipError_t le = hipSuccess;
+        for (int rep = 0; rep < 2 && le == hipSuccess; ++rep) {
+          (void)hipEventRecord(a, nullptr);
+          le = launch_sqa_anneal(reinterpret_cast<HandleDev *>(dev),
+                                 reinterpret_cast<WorkItem *>(static_cast<char *>(dev) + oi),
+                                 static_cast<int>(items.size()),
+                                 reinterpret_cast<int *>(static_cast<char *>(dev) + oc), s.grid, s.waves, s.rec_cap,
+                                 s.lat_cap, s.tab_cap, nullptr);
+          (void)hipEventRecord(z, nullptr);
+          (void)hipEventSynchronize(z);
+          (void)hipEventElapsedTime(&ms, a, z);
+        }
         (void)hipFree(dev);
         if (le == hipSuccess && ms < best_t) {
           best_t = ms;
