@@ -61,6 +61,7 @@ def parse():
     ap.add_argument("--sweeps", type=int, default=10_000)
     ap.add_argument("--no-extras", action="store_true", help="only the timed batched steps")
     ap.add_argument("--cpu-replicas", type=int, default=2, help="oracle lattices per stratum for cpu_baseline")
+    ap.add_argument("--pt-sweeps", type=int, default=10_000, help="sweeps of the parallel-tempering leg")
     return ap.parse_args()
 
 
@@ -109,6 +110,24 @@ def cpu_baseline(jobs, replicas_per_stratum: int = 2):
     return {"value": attempts / dt, "unit": "spin-flip attempts/s", "cores": threads, "kind": "oracle",
             "sample": f"{len(lattices)} of the workload's replica lattices ({replicas_per_stratum} per embedding x N "
                       f"stratum), full {sample[0].sweeps}-sweep schedule: {attempts:.3e} attempts in {dt:.1f} s"}
+
+
+def pt_leg(sqa, sweeps: int):
+    """Parallel tempering over 128 N = 24 instances embedded both ways (256 ladders of 32
+    temperatures, beta geometric in [0.1, 5], a swap phase after every sweep), one launch."""
+    from paper_1603_03755_amd.workloads import pt_jobs
+    jobs = pt_jobs(sweeps=sweeps)
+    hs = [sqa.PT(j.kind, j.J, j.penalty, j.beta_min, j.beta_max, j.temps, j.sweeps, j.sweeps_per_swap, j.seed)
+          for j in jobs]
+    t0 = time.perf_counter()
+    sqa.pt_run_batch(hs)
+    dt = time.perf_counter() - t0
+    attempts = sum(j.sites * j.temps * j.sweeps for j in jobs)
+    swaps = sum((j.temps - 1) * (j.sweeps // j.sweeps_per_swap) for j in jobs)
+    for h in hs:
+        h.close()
+    return {"ladders": len(jobs), "temps": 32, "sweeps": sweeps, "attempts": attempts,
+            "attempts_per_s": attempts / dt, "swap_attempts_per_s": swaps / dt, "seconds": dt}
 
 
 def main():
@@ -240,6 +259,7 @@ def main():
                           "p99_latency_s": float(np.percentile(lats, 99)), "jobs_per_s": len(tickets) / span,
                           "attempts_per_s": att3 / span, "launches": launches, "peak_resident_bytes": peak,
                           "budget_bytes": 64 << 20, "arrival_rate_per_s": 12.0}
+        out["parallel_tempering"] = pt_leg(sqa, args.pt_sweeps)
         out["cpu_baseline"] = cpu_baseline(jobs, args.cpu_replicas)
     print(json.dumps(out), flush=True)
 

@@ -223,9 +223,10 @@ typedef struct {
 
 SQA_API sqa_status pt_create(const sqa_problem *problem, const sqa_embedding *embedding,
                      const pt_params *params, pt_handle **out);
-/* Runs the whole PT schedule from the seeded initial state. */
+/* Runs the whole PT schedule from the seeded initial state on `stream` and
+ * waits for it (blocking). */
 SQA_API sqa_status pt_run_handle(pt_handle *h, void *stream);
-/* All handles in one launch (one workgroup per ladder). */
+/* All handles in one launch (one workgroup per ladder); blocking. */
 SQA_API sqa_status pt_run_batch(pt_handle *const *handles, int32_t count, void *stream);
 /* Results after a run, blocking.  spins_out[temp][site] and energies_out[temp]
  * are ordered BY SLOT (temperature), slot_to_replica_out[temp] gives the

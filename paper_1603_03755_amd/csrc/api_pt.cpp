@@ -1,6 +1,7 @@
 // C ABI: parallel tempering handles (Appendix B, Eqs. (B1)-(B2)).
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -70,8 +71,9 @@ PTShape pt_shape(const std::vector<const pt_handle *> &hs) {
   s.rec_cap = (s.rec_cap + 3) & ~3;
   s.lat_cap = (s.lat_cap + 1) & ~1;
   s.mtab_cap = (s.mtab_cap + 3) & ~3;
-  // enough lanes for one item per lane on the largest colour class
-  s.waves = maxn > 300 ? 8 : 4;
+  // one workgroup owns a ladder: use many waves so that LDS and Philox latency is hidden
+  const char *env = std::getenv("SQA_PT_WAVES");
+  s.waves = env ? std::max(1, std::min(16, std::atoi(env))) : (maxn > 300 ? 12 : 8);
   return s;
 }
 

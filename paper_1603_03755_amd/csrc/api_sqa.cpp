@@ -18,12 +18,6 @@ using namespace sqa;
 namespace sqa {
 const char *last_error_cstr();
 
-// Pinned staging of one single-handle launch descriptor.
-struct Staging {
-  HandleDev hd;
-  WorkItem items[1];
-};
-
 static std::once_flag g_lds_once;
 static hipError_t g_lds_status = hipSuccess;
 
@@ -77,11 +71,6 @@ static LaunchShape shape_for(const std::vector<const sqa_handle *> &hs, int wave
 }
 
 // ---------------------------------------------------------------- autotune cache
-struct TuneKey {
-  std::string arch;
-  std::string cls;
-};
-
 static std::string device_arch() {
   int dev = 0;
   hipDeviceProp_t prop;
@@ -297,10 +286,12 @@ sqa_status sqa_create(const sqa_problem *problem, const sqa_embedding *embedding
     }
   }
   e = hipEventCreateWithFlags(&h->done, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipHostMalloc(&h->staging, sizeof(HandleDev) + sizeof(WorkItem) * static_cast<size_t>(R), 0);
   if (e != hipSuccess) {
+    if (h->done) (void)hipEventDestroy(h->done);
     (void)hipFree(A.base);
     delete h;
-    return hip_fail(e, "hipEventCreate");
+    return hip_fail(e, "handle setup (event / pinned staging)");
   }
   *out = h;
   return SQA_OK;
@@ -313,6 +304,7 @@ void sqa_destroy(sqa_handle *h) {
     (void)hipEventDestroy(h->done);
   }
   if (h->arena.base) (void)hipFree(h->arena.base);
+  if (h->staging) (void)hipHostFree(h->staging);
   delete h;
 }
 
@@ -331,23 +323,25 @@ static sqa_status run_single(sqa_handle *h, int m0, int m1, int flags, hipStream
   std::vector<WorkItem> items = plan_items(hs, {m0}, {m1}, waves);
   LaunchShape shape = shape_for(hs, waves, gpc, items.size());
   if (shape.lds_bytes() > kMaxLds) return fail(SQA_ERR_UNSUPPORTED, "lattice does not fit in LDS");
-  // previous work on this handle must have consumed the staging copy
+  // previous work on this handle must have consumed the pinned staging copy
   e = hipEventSynchronize(h->done);
   if (e != hipSuccess) {
     h->poisoned = true;
     return hip_fail(e, "hipEventSynchronize");
   }
-  HandleDev hd = h->dev(m0, m1, flags);
-  e = hipMemcpyAsync(h->arena.at<void>(h->off_hd), &hd, sizeof(hd), hipMemcpyHostToDevice, stream);
+  HandleDev *hd = static_cast<HandleDev *>(h->staging);
+  WorkItem *st_items = reinterpret_cast<WorkItem *>(hd + 1);
+  *hd = h->dev(m0, m1, flags);
+  std::copy(items.begin(), items.end(), st_items);
+  e = hipMemcpyAsync(h->arena.at<void>(h->off_hd), hd, sizeof(HandleDev), hipMemcpyHostToDevice, stream);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(h->arena.at<void>(h->off_items), items.data(), items.size() * sizeof(WorkItem),
+    e = hipMemcpyAsync(h->arena.at<void>(h->off_items), st_items, items.size() * sizeof(WorkItem),
                        hipMemcpyHostToDevice, stream);
   if (e == hipSuccess)
     e = launch_sqa_anneal(h->arena.at<HandleDev>(h->off_hd), h->arena.at<WorkItem>(h->off_items),
                           static_cast<int>(items.size()), h->arena.at<int>(h->off_counter), shape.grid, shape.waves,
                           shape.rec_cap, shape.lat_cap, shape.tab_cap, stream);
   if (e == hipSuccess) e = hipEventRecord(h->done, stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(stream);  // host staging above is pageable
   if (e != hipSuccess) {
     h->poisoned = true;
     return hip_fail(e, "anneal launch");

@@ -140,5 +140,7 @@ struct sqa_handle {
   bool poisoned = false;
   hipEvent_t done = nullptr;
   size_t device_bytes = 0;
+  // pinned staging of the single-handle launch descriptor: HandleDev then R work items
+  void *staging = nullptr;
   sqa::HandleDev dev(int m0, int m1, int flags) const;
 };

@@ -556,7 +556,7 @@ __device__ void pt_ladder(const PTDev &P, const uint32_t *rec, uint64_t *lat, co
 }
 
 // Dynamic LDS: [rec_cap words][lat_cap u64][mtab_cap words][E, rep_at, slot_of, acc: 64 each].
-__global__ __launch_bounds__(512) void pt_kernel(const PTDev *__restrict__ pts, int rec_cap, int lat_cap,
+__global__ __launch_bounds__(1024) void pt_kernel(const PTDev *__restrict__ pts, int rec_cap, int lat_cap,
                                                  int mtab_cap) {
   extern __shared__ __align__(16) uint32_t smem[];
   const PTDev P = pts[blockIdx.x];

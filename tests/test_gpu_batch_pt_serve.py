@@ -1,0 +1,245 @@
+"""GPU parity of the batched persistent launch, parallel tempering and the
+continuous-batching server against the CPU oracle (bit-exact), plus the
+full-size batched workload checked on sampled replicas."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1603_03755_amd.workloads import LHZ, ME, batch_jobs, pt_jobs, sk_instance
+
+pytestmark = pytest.mark.gpu
+NTH = min(os.cpu_count() or 1, 16)
+
+
+@pytest.fixture(scope="module")
+def sqa():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1603_03755_amd import sqa as s
+    s.lib()
+    return s
+
+
+def _mixed_jobs():
+    """Uneven handles: both embeddings, several N, L and replica counts."""
+    spec = [(ME, 5, 32, 7), (LHZ, 8, 64, 16), (ME, 12, 16, 3), (LHZ, 6, 8, 9), (ME, 8, 64, 4),
+            (LHZ, 12, 32, 5), (ME, 3, 2, 2), (LHZ, 4, 1, 6)]
+    out = []
+    for q, (kind, N, L, R) in enumerate(spec):
+        out.append(dict(kind=kind, J=sk_instance(N, 900 + q), pen=-2, beta=8.0, L=L, M=40 + 7 * q, R=R,
+                        g0=3.0, g1=0.02, seed=0xBA7C0000 + q))
+    return out
+
+
+@pytest.mark.parametrize("waves", [1, 2, 4, 8])
+def test_batch_equals_oracle_for_every_handle(sqa, waves):
+    specs = _mixed_jobs()
+    print(f"batch of {len(specs)} uneven handles, waves_per_group={waves}", flush=True)
+    hs = [sqa.SQA(s["kind"], s["J"], s["pen"], s["beta"], s["L"], s["M"], s["R"], s["g0"], s["g1"], s["seed"])
+          for s in specs]
+    b = sqa.Batch(hs, waves_per_group=waves)
+    b.run()
+    for s, h in zip(specs, hs):
+        emb, table, ospins, oE = O.sqa_anneal(s["kind"], s["J"], s["pen"], s["beta"], s["L"], s["M"], s["R"],
+                                              s["g0"], s["g1"], s["seed"], nthreads=NTH)
+        assert (h.spins() == ospins).all()
+        assert (h.energies() == oE).all()
+    # graph replay gives the same result again (state re-initialised from the seed)
+    first = [h.spins() for h in hs]
+    b.run()
+    for f, h in zip(first, hs):
+        assert (h.spins() == f).all()
+    b.close()
+
+
+def test_batch_graph_replays_with_eager_work_between(sqa):
+    specs = _mixed_jobs()[:4]
+    hs = [sqa.SQA(s["kind"], s["J"], s["pen"], s["beta"], s["L"], s["M"], s["R"], s["g0"], s["g1"], s["seed"])
+          for s in specs]
+    ref = []
+    for h in hs:
+        h.anneal()
+        ref.append((h.spins(), h.energies()))
+    b = sqa.Batch(hs)
+    for rep in range(3):
+        b.run()
+        for (s0, e0), h in zip(ref, hs):
+            assert (h.spins() == s0).all() and (h.energies() == e0).all()
+        hs[rep].anneal_range(0, 5)          # eager work on a handle between replays
+    b.close()
+
+
+def test_anneal_batch_one_shot(sqa):
+    specs = _mixed_jobs()[2:6]
+    hs = [sqa.SQA(s["kind"], s["J"], s["pen"], s["beta"], s["L"], s["M"], s["R"], s["g0"], s["g1"], s["seed"])
+          for s in specs]
+    sqa.sqa_anneal_batch(hs)
+    for s, h in zip(specs, hs):
+        _, _, ospins, _ = O.sqa_anneal(s["kind"], s["J"], s["pen"], s["beta"], s["L"], s["M"], s["R"], s["g0"],
+                                       s["g1"], s["seed"], nthreads=NTH)
+        assert (h.spins() == ospins).all()
+
+
+def test_full_size_batched_workload_sampled(sqa):
+    """The benchmark's workload at full size (512 instances, 64 replicas, L = 64,
+    10^4 sweeps, one persistent launch): sampled replicas of every (embedding, N)
+    stratum equal the oracle's; every replica's energies equal its spins' energies."""
+    jobs = batch_jobs()
+    hs = [sqa.SQA(j.kind, j.J, j.penalty, j.beta, j.slices, j.sweeps, j.replicas, j.gamma0, j.gamma1, j.seed)
+          for j in jobs]
+    print("full-size batch: 512 handles, running", flush=True)
+    b = sqa.Batch(hs)
+    b.run()
+    hs[0].sync()
+    print("full-size batch done, checking samples", flush=True)
+    seen = {}
+    rng = np.random.default_rng(0)
+    for i, j in enumerate(jobs):
+        if (j.kind, j.n) not in seen:
+            seen[(j.kind, j.n)] = (i, int(rng.integers(0, j.replicas)))
+    from concurrent.futures import ThreadPoolExecutor
+
+    def oracle_replica(ir):
+        i, r = ir
+        j = jobs[i]
+        return O.sqa_anneal(j.kind, j.J, j.penalty, j.beta, j.slices, j.sweeps, 1, j.gamma0, j.gamma1, j.seed,
+                            nthreads=1, r0=r)
+
+    with ThreadPoolExecutor(max_workers=8) as ex:
+        refs = list(ex.map(oracle_replica, seen.values()))
+    for (i, r), (emb, _, ospins, oE) in zip(seen.values(), refs):
+        spins, E = hs[i].spins(), hs[i].energies()
+        assert (spins[r] == ospins[0]).all(), (i, r)
+        assert (E[r] == oE[0]).all(), (i, r)
+        assert (O.sqa_energies(emb, spins) == E).all()
+    b.close()
+
+
+# ------------------------------------------------------------------ PT
+PT_CASES = [(LHZ, 5, 8, 300, 1), (ME, 4, 5, 200, 2), (LHZ, 3, 1, 50, 1), (ME, 6, 64, 40, 3), (LHZ, 8, 32, 500, 1),
+            (ME, 2, 3, 30, 1)]
+
+
+@pytest.mark.parametrize("kind,N,R,sweeps,sps", PT_CASES)
+def test_pt_bit_exact(sqa, kind, N, R, sweeps, sps):
+    J = sk_instance(N, 700 + N)
+    seed = 0x9700 + N
+    print(f"PT kind={kind} N={N} R={R} sweeps={sweeps}", flush=True)
+    dev = sqa.PT(kind, J, -2, 0.1, 5.0, R, sweeps, sps, seed).run()
+    spins, E, rep, acc = dev.read()
+    emb = O.Embedding(kind, J, -2)
+    betas = O.pt_ladder(0.1, 5.0, R)
+    ospins, oE, orep, oacc = O.pt_run(emb, betas, sweeps, sps, seed)
+    assert (rep == orep).all()
+    assert (spins == ospins[orep]).all()       # device returns spins by slot
+    assert (E == oE[orep]).all()
+    assert (acc == oacc).all()
+
+
+def test_pt_workload_shape_sampled(sqa):
+    """PT workload shape (N = 24, 32 temperatures, both embeddings) in one batched
+    launch, at a reduced sweep count the oracle can finish: two instances exact."""
+    jobs = pt_jobs(instances=2, sweeps=2000)
+    hs = [sqa.PT(j.kind, j.J, j.penalty, j.beta_min, j.beta_max, j.temps, j.sweeps, j.sweeps_per_swap, j.seed)
+          for j in jobs]
+    sqa.pt_run_batch(hs)
+    for j, h in zip(jobs, hs):
+        spins, E, rep, acc = h.read()
+        emb = O.Embedding(j.kind, j.J, j.penalty)
+        ospins, oE, orep, oacc = O.pt_run(emb, O.pt_ladder(j.beta_min, j.beta_max, j.temps), j.sweeps,
+                                          j.sweeps_per_swap, j.seed)
+        assert (rep == orep).all() and (spins == ospins[orep]).all() and (E == oE[orep]).all()
+        assert (acc == oacc).all()
+
+
+# ------------------------------------------------------------------ serving
+def test_server_results_equal_alone_runs(sqa):
+    """Jobs of mixed size run together through the server equal the same jobs run
+    alone (and the oracle), whatever else shares their launches."""
+    specs = _mixed_jobs()
+    srv = sqa.Server(hbm_budget_bytes=3 << 20, max_slots=3, chunk_sweeps=13)
+    tickets = [srv.submit(s["kind"], s["J"], s["pen"], s["beta"], s["L"], s["M"], s["R"], s["g0"], s["g1"],
+                          s["seed"]) for s in specs]
+    for t, s in zip(tickets, specs):
+        srv.wait(t, 120_000)
+        spins, E, lat = srv.result(t)
+        assert lat > 0
+        alone = sqa.SQA(s["kind"], s["J"], s["pen"], s["beta"], s["L"], s["M"], s["R"], s["g0"], s["g1"],
+                        s["seed"]).anneal()
+        assert (spins == alone.spins()).all() and (E == alone.energies()).all()
+        _, _, ospins, oE = O.sqa_anneal(s["kind"], s["J"], s["pen"], s["beta"], s["L"], s["M"], s["R"], s["g0"],
+                                        s["g1"], s["seed"], nthreads=NTH)
+        assert (spins == ospins).all() and (E == oE).all()
+    completed, launches, peak = srv.stats()
+    assert completed == len(specs)
+    assert peak <= 3 << 20
+    srv.close()
+
+
+def test_server_rejects_job_over_budget(sqa):
+    srv = sqa.Server(hbm_budget_bytes=1 << 16, max_slots=2, chunk_sweeps=10)
+    with pytest.raises(sqa.SqaError) as e:
+        srv.submit(ME, sk_instance(24, 1), -2, 10.0, 64, 100, 64, 3.0, 0.01, 1)
+    assert e.value.status == sqa.SQA_ERR_BUSY
+    srv.close()
+
+
+def test_batch_mixed_field_ranges_and_slices(sqa):
+    """One launch mixing handles on the fast path (L in {16, 32, 64}, F <= 10), the
+    general small-F path (other L) and the wide-field path (F > 10)."""
+    specs = [dict(kind=ME, J=sk_instance(6, 11), pen=-2, L=32, R=5),            # fast, F = 5
+             dict(kind=LHZ, J=sk_instance(7, 12), pen=-2, L=16, R=3),           # fast, F = 9
+             dict(kind=ME, J=sk_instance(5, 13), pen=-6, L=64, R=4),            # F = 13: wide path
+             dict(kind=LHZ, J=sk_instance(6, 14), pen=-3, L=10, R=6),           # F = 13, ragged L
+             dict(kind=ME, J=sk_instance(4, 15), pen=-2, L=6, R=2),             # small F, ragged L
+             dict(kind=LHZ, J=sk_instance(5, 16), pen=-2, L=1, R=7)]            # classical
+    hs = []
+    for q, s in enumerate(specs):
+        s.update(beta=7.0, M=30 + 5 * q, g0=2.0, g1=0.05, seed=0xF1E1D + q)
+        hs.append(sqa.SQA(s["kind"], s["J"], s["pen"], s["beta"], s["L"], s["M"], s["R"], s["g0"], s["g1"],
+                          s["seed"]))
+    sqa.sqa_anneal_batch(hs)
+    for s, h in zip(specs, hs):
+        _, _, ospins, oE = O.sqa_anneal(s["kind"], s["J"], s["pen"], s["beta"], s["L"], s["M"], s["R"], s["g0"],
+                                        s["g1"], s["seed"], nthreads=NTH)
+        assert (h.spins() == ospins).all() and (h.energies() == oE).all()
+
+
+def test_autotune_writes_cache_and_batch_uses_it(sqa, tmp_path, monkeypatch):
+    specs = _mixed_jobs()[:4]
+    hs = [sqa.SQA(s["kind"], s["J"], s["pen"], s["beta"], s["L"], s["M"], s["R"], s["g0"], s["g1"], s["seed"])
+          for s in specs]
+    hs[0].anneal()
+    before = hs[0].spins()
+    cache = tmp_path / "tune.json"
+    best = sqa.sqa_autotune(hs, str(cache))
+    assert best[0] in (1, 2, 4, 8) and best[1] >= 1
+    assert (hs[0].spins() == before).all()          # tuning restores the device state
+    text = cache.read_text()
+    assert "gfx950" in text
+    monkeypatch.setenv("SQA_AUTOTUNE_CACHE", str(cache))
+    b = sqa.Batch(hs)
+    assert b.config() == best
+    b.run()
+    for s, h in zip(specs, hs):
+        _, _, ospins, _ = O.sqa_anneal(s["kind"], s["J"], s["pen"], s["beta"], s["L"], s["M"], s["R"], s["g0"],
+                                       s["g1"], s["seed"], nthreads=NTH)
+        assert (h.spins() == ospins).all()
+    b.close()
+
+
+def test_async_anneals_on_torch_streams(sqa):
+    """sqa_anneal is asynchronous on the given stream; two handles on two streams."""
+    import torch
+    specs = _mixed_jobs()[:2]
+    hs = [sqa.SQA(s["kind"], s["J"], s["pen"], s["beta"], s["L"], s["M"], s["R"], s["g0"], s["g1"], s["seed"])
+          for s in specs]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    for h, st in zip(hs, streams):
+        h.anneal(st)
+    for s, h in zip(specs, hs):
+        _, _, ospins, _ = O.sqa_anneal(s["kind"], s["J"], s["pen"], s["beta"], s["L"], s["M"], s["R"], s["g0"],
+                                       s["g1"], s["seed"], nthreads=NTH)
+        assert (h.spins() == ospins).all()
