@@ -101,7 +101,7 @@ typedef struct sqa_server sqa_server;
 /* Launch shape of the persistent sweep kernel.  Every field 0 = choose
  * automatically (the autotuner's cached choice for this device and shape). */
 typedef struct {
-  int32_t waves_per_group;    /* replicas processed together by one workgroup: 1, 2, 4 or 8 */
+  int32_t waves_per_group;    /* replicas processed together by one workgroup: 1..8 */
   int32_t groups_per_cu;      /* resident workgroups per compute unit targeted by the grid */
 } sqa_launch_config;
 

@@ -170,7 +170,7 @@ static void resolve_config(const std::vector<const sqa_handle *> &hs, const sqa_
   *gpc = c.groups_per_cu;   // 0 = from occupancy
 }
 
-static bool valid_waves(int w) { return w == 1 || w == 2 || w == 4 || w == 8; }
+static bool valid_waves(int w) { return w >= 1 && w <= 8; }
 
 }  // namespace sqa
 
@@ -771,7 +771,7 @@ sqa_status sqa_batch_create(sqa_handle *const *handles, int32_t count, const sqa
     if (st != SQA_OK) return st;
   }
   if (config && ((config->waves_per_group != 0 && !valid_waves(config->waves_per_group)) || config->groups_per_cu < 0))
-    return fail(SQA_ERR_INVALID, "waves_per_group must be 1, 2, 4 or 8");
+    return fail(SQA_ERR_INVALID, "waves_per_group must be in 1..8");
   hipError_t e = ensure_lds_limits();
   if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
   std::vector<const sqa_handle *> hs(handles, handles + count);
@@ -864,7 +864,7 @@ sqa_status sqa_autotune(sqa_handle *const *handles, int32_t count, const char *c
     (void)hipEventCreate(&a);
     (void)hipEventCreate(&z);
     const int trial_sweeps = 100;
-    for (int w : {1, 2, 4, 8}) {
+    for (int w : {2, 4, 8}) {   // multiples of the 4 SIMDs of a CU keep waves balanced
       std::vector<int> m0(count, 0), m1(count);
       for (int i = 0; i < count; ++i) m1[i] = std::min(handles[i]->M, trial_sweeps);
       std::vector<WorkItem> items = plan_items(hs, m0, m1, w);

@@ -294,7 +294,11 @@ int device_cu_count() {
   return cus;
 }
 
+// Resident groups per CU: the runtime's occupancy calculation for the sweep
+// kernel (registers, LDS, wave slots), else an LDS / wave-slot estimate.
 int occupancy_groups_per_cu(const LaunchShape &s) {
+  const int rt = sqa_anneal_occupancy(s.waves, s.lds_bytes());
+  if (rt > 0) return rt;
   const size_t lds = s.lds_bytes() + 64;
   int by_lds = static_cast<int>(kMaxLds / std::max<size_t>(lds, 1));
   int by_waves = 32 / s.waves;  // 8 waves per SIMD x 4 SIMDs

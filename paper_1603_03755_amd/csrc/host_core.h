@@ -85,6 +85,7 @@ struct Arena {
 hipError_t launch_sqa_anneal(const HandleDev *hds, const WorkItem *items, int n_items, int *counter, int grid,
                              int waves, int rec_cap, int lat_cap, int tab_cap, hipStream_t stream);
 hipError_t set_sqa_anneal_lds_limit(size_t bytes);
+int sqa_anneal_occupancy(int waves, size_t lds_bytes);
 hipError_t launch_sqa_init(const HandleDev &H, hipStream_t stream);
 hipError_t launch_me_majority(const int8_t *spins, int R, int N, int n_sites, int L, int slice, const int32_t *J,
                               const int32_t *h, int8_t *logical, int32_t *energy, hipStream_t stream);

@@ -72,7 +72,7 @@ __device__ __forceinline__ int slice_bit(int tau) { return (tau >> 1) + ((tau & 
 
 // Builds the initial lattice in LDS: s = -1 iff bit 31 of the INIT-stream word
 // of (replica, slice, site, sweep 0).
-__device__ void init_lattice(const HandleDev &H, uint64_t *lat, int rep, int lane) {
+__device__ __forceinline__ void init_lattice(const HandleDev &H, uint64_t *lat, int rep, int lane) {
   const int L = H.L, n = H.n;
   const int G = (L + 7) >> 3;
   const uint32_t c3 = (kStreamInit << 24) | static_cast<uint32_t>(rep);
@@ -96,7 +96,7 @@ __device__ void init_lattice(const HandleDev &H, uint64_t *lat, int rep, int lan
 }
 
 // Loads [L][n] int8 spins of one replica (physical order) into LDS words.
-__device__ void load_lattice(const HandleDev &H, uint64_t *lat, int rep, int lane) {
+__device__ __forceinline__ void load_lattice(const HandleDev &H, uint64_t *lat, int rep, int lane) {
   const int L = H.L, n = H.n;
   const int8_t *src = H.spins + static_cast<size_t>(rep) * L * n;
   for (int k = lane; k < n; k += 64) {
@@ -108,7 +108,7 @@ __device__ void load_lattice(const HandleDev &H, uint64_t *lat, int rep, int lan
   if (lane == 0) lat[n] = 0;
 }
 
-__device__ void store_lattice(const HandleDev &H, const uint64_t *lat, int rep, int lane) {
+__device__ __forceinline__ void store_lattice(const HandleDev &H, const uint64_t *lat, int rep, int lane) {
   const int L = H.L, n = H.n;
   int8_t *dst = H.spins + static_cast<size_t>(rep) * L * n;
   for (int k = lane; k < n; k += 64) {
@@ -119,7 +119,7 @@ __device__ void store_lattice(const HandleDev &H, const uint64_t *lat, int rep, 
 }
 
 // E^tau = sum_k h_k s_k + sum_t w_t prod s, one lane per slice.
-__device__ void slice_energies(const HandleDev &H, const uint64_t *lat, int rep, int lane) {
+__device__ __forceinline__ void slice_energies(const HandleDev &H, const uint64_t *lat, int rep, int lane) {
   const int tau = lane;
   if (tau >= H.L) return;
   const int b = slice_bit(tau);
@@ -293,7 +293,7 @@ __device__ __forceinline__ void sweep_class(const HandleDev &H, const uint32_t *
 }
 
 template <int KIND>
-__device__ void anneal_replica(const HandleDev &H, const uint32_t *rec, uint64_t *lat, uint32_t *tab,
+__device__ __forceinline__ void anneal_replica(const HandleDev &H, const uint32_t *rec, uint64_t *lat, uint32_t *tab,
                                int rep, int lane) {
   if (H.flags & kFlagInit) init_lattice(H, lat, rep, lane);
   else load_lattice(H, lat, rep, lane);
@@ -351,10 +351,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(SQA_WAVES_P
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
     __syncthreads();
-    const int it = s_item;
+    const int it = __builtin_amdgcn_readfirstlane(s_item);   // uniform: handle fields go to SGPRs
     if (it >= n_items) break;
     const WorkItem wi = items[it];
-    const HandleDev H = hds[wi.handle];
+    const HandleDev &H = hds[wi.handle];      // read in place: uniform fields become scalar loads
     const int rw = (H.kind == kKindME) ? kRecWordsME : kRecWordsLHZ;
     const int nwords = H.n * rw;
     for (int i = threadIdx.x; i < nwords; i += blockDim.x) rec[i] = H.rec[i];
@@ -630,6 +630,16 @@ hipError_t launch_sqa_anneal(const HandleDev *hds, const WorkItem *items, int n_
   hipLaunchKernelGGL(sqa_anneal_kernel, dim3(grid), dim3(64 * waves), lds, stream, hds, items, n_items, counter,
                      rec_cap, lat_cap, tab_cap);
   return hipGetLastError();
+}
+
+// Resident workgroups of `waves` waves per compute unit for the given dynamic LDS.
+int sqa_anneal_occupancy(int waves, size_t lds_bytes) {
+  int blocks = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, sqa_anneal_kernel, 64 * waves, lds_bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return blocks;
 }
 
 hipError_t set_sqa_anneal_lds_limit(size_t bytes) {
