@@ -44,7 +44,7 @@ TRAFFIC_PROFILE = {"kernel_sha256_prefix": "f9c1e5834a3d0d9e", "instances": 512,
 
 def measured_traffic(args):
     import hashlib
-    src = os.path.join(ROOT, "paper_1603_03755_amd", "csrc", "kernels.hip")
+    src = os.path.join(ROOT, "paper_1603_03755_amd", "csrc", "sqa_kernels.hip")
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     t = TRAFFIC_PROFILE
     if not sha.startswith(t["kernel_sha256_prefix"]) or args.instances != t["instances"] or args.sweeps != t["sweeps"]:

@@ -1,0 +1,72 @@
+// Device helpers shared by the SQA and PT kernels: Philox4x32-10, LDS
+// ordering inside a wavefront, the per-kind site-record shapes and the
+// carry-free bit spreading used to sum four slices side by side.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "device_types.h"
+
+namespace sqa {
+
+// ---------------------------------------------------------------- Philox
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds, each multiplying counter
+// words 0 and 2 by fixed odd constants, swapping the high halves with the key
+// mixed in; the key advances by a Weyl increment between rounds.
+struct Words4 {
+  uint32_t v[4];
+};
+
+__device__ __forceinline__ Words4 philox4x32_10(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
+                                               uint32_t key0, uint32_t key1) {
+  constexpr uint32_t kMulA = 0xD2511F53u, kMulB = 0xCD9E8D57u;
+  constexpr uint32_t kWeylA = 0x9E3779B9u, kWeylB = 0xBB67AE85u;
+#pragma unroll
+  for (int round = 0; round < 10; ++round) {
+    const uint64_t pa = static_cast<uint64_t>(kMulA) * x0;
+    const uint64_t pb = static_cast<uint64_t>(kMulB) * x2;
+    // three-input XORs (truth table 0x96)
+    const uint32_t y0 = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(pb >> 32), x1, key0, 0x96);
+    const uint32_t y2 = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(pa >> 32), x3, key1, 0x96);
+    x1 = static_cast<uint32_t>(pb);
+    x3 = static_cast<uint32_t>(pa);
+    x0 = y0;
+    x2 = y2;
+    key0 += kWeylA;
+    key1 += kWeylB;
+  }
+  Words4 r;
+  r.v[0] = x0; r.v[1] = x1; r.v[2] = x2; r.v[3] = x3;
+  return r;
+}
+
+// Orders LDS accesses of one wavefront around a phase boundary.  A wave's LDS
+// operations are executed in program order, so only the compiler needs fencing.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint32_t bit_at(uint32_t v, int q) { return (v >> q) & 1u; }
+
+template <int KIND>
+struct Site;
+
+template <>
+struct Site<kKindME> {
+  static constexpr int T = 3, P = 1, RW = kRecWordsME;
+};
+template <>
+struct Site<kKindLHZ> {
+  static constexpr int T = 4, P = 3, RW = kRecWordsLHZ;
+};
+
+// Four bits of a nibble moved to bit 0 of four 6-bit fields (bits 0, 6, 12,
+// 18): every partial product of the 24-bit multiply lands on a distinct bit.
+__device__ __forceinline__ uint32_t spread6(uint32_t nib) { return __umul24(nib & 0xFu, 0x8421u) & 0x41041u; }
+// The same for bits 4..7 of a byte.
+__device__ __forceinline__ uint32_t spread6_hi(uint32_t byte) {
+  return (__umul24(byte & 0xF0u, 0x8421u) >> 4) & 0x41041u;
+}
+
+}  // namespace sqa

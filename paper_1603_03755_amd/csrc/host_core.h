@@ -81,7 +81,7 @@ struct Arena {
   T *at(size_t off) const { return reinterpret_cast<T *>(static_cast<char *>(base) + off); }
 };
 
-// Kernel launchers (kernels.hip).
+// Kernel launchers (sqa_kernels.hip, pt_kernels.hip).
 hipError_t launch_sqa_anneal(const HandleDev *hds, const WorkItem *items, int n_items, int *counter, int grid,
                              int waves, int rec_cap, int lat_cap, int tab_cap, hipStream_t stream);
 hipError_t set_sqa_anneal_lds_limit(size_t bytes);
