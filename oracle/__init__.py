@@ -17,7 +17,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 ME, LHZ = 0, 1
-STREAM_INIT, STREAM_SQA, STREAM_PT, STREAM_SWAP, STREAM_TREE, STREAM_PT_INIT = 1, 2, 3, 4, 5, 6
+STREAM_INIT, STREAM_SQA, STREAM_PT, STREAM_SWAP, STREAM_TREE, STREAM_PT_INIT, STREAM_WOLFF = 1, 2, 3, 4, 5, 6, 7
 ALWAYS = 0xFFFFFFFF
 
 
@@ -56,6 +56,9 @@ def lib():
         L.oracle_ground_states.restype = C.c_int32
         L.oracle_random_trees.restype = C.c_int
         L.oracle_me_site.restype = C.c_int32
+        L.oracle_wolff_bond_word.restype = C.c_uint32
+        L.oracle_wolff_bond_word.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32]
+        L.oracle_wolff_site_order.restype = C.c_int32
         L.oracle_lhz_site.restype = C.c_int32
     return _lib
 
@@ -251,6 +254,78 @@ def sqa_anneal(kind, J, penalty, beta, L, sweeps, replicas, gamma0, gamma1, seed
     spins = sqa_init(emb, L, replicas, seed, r0)
     sqa_run(emb, L, spins, 0, sweeps, table, seed, nthreads, r0)
     return emb, table, spins, sqa_energies(emb, spins)
+
+
+# ---------------------------------------------------------------- SQA, Wolff moves
+def wolff_bond_word(seed, replica, site, bond, sweep) -> int:
+    return int(lib().oracle_wolff_bond_word(seed, replica, site, bond, sweep))
+
+
+def wolff_site_words(seed, replica, site, sweep):
+    """(seed-slice word, acceptance word) of one site move."""
+    us, ua = C.c_uint32(), C.c_uint32()
+    lib().oracle_wolff_site_words(C.c_uint64(seed), replica, site, sweep, C.byref(us), C.byref(ua))
+    return int(us.value), int(ua.value)
+
+
+def wolff_tables(beta, L, gamma, F, bscale=None):
+    """(join thresholds padd[M], acceptance thresholds acc[rows][2 L F + 1])."""
+    gamma = np.ascontiguousarray(gamma, dtype=np.float64)
+    M = gamma.shape[0]
+    rows = M if bscale is not None else 1
+    padd = np.zeros(M, dtype=np.uint32)
+    acc = np.zeros((rows, 2 * L * F + 1), dtype=np.uint32)
+    bp = None
+    if bscale is not None:
+        bscale = np.ascontiguousarray(bscale, dtype=np.float64)
+        bp = _p(bscale, C.c_double)
+    lib().oracle_wolff_tables(C.c_double(beta), L, M, _p(gamma, C.c_double), bp, F, _p(padd, C.c_uint32),
+                              _p(acc, C.c_uint32))
+    return padd, acc
+
+
+def wolff_move(emb: Embedding, L, lats, k, tau0, bond_u, u_acc, padd, acc_row):
+    """Applies one cluster move of site k with the given words to every lattice of
+    lats[count][L][n] in place; returns (thresholds[count], cluster bit masks[count])."""
+    assert lats.dtype == np.int8 and lats.flags.c_contiguous and lats.ndim == 3
+    bond_u = np.ascontiguousarray(bond_u, dtype=np.uint32)
+    acc_row = np.ascontiguousarray(acc_row, dtype=np.uint32)
+    F = (acc_row.shape[0] - 1) // (2 * L)
+    count = lats.shape[0]
+    thr = np.zeros(count, dtype=np.uint32)
+    cl = np.zeros(count, dtype=np.uint64)
+    lib().oracle_wolff_move(emb.ptr, L, count, _p(lats, C.c_int8), k, tau0, _p(bond_u, C.c_uint32),
+                            C.c_uint32(u_acc), C.c_uint32(int(padd)), _p(acc_row, C.c_uint32), F,
+                            _p(thr, C.c_uint32), _p(cl, C.c_uint64))
+    return thr, cl
+
+
+def wolff_site_order(emb: Embedding):
+    out = np.zeros(emb.n_sites, dtype=np.int32)
+    cnt = lib().oracle_wolff_site_order(emb.ptr, _p(out, C.c_int32))
+    return out[:cnt]
+
+
+def wolff_run(emb: Embedding, L, spins, m0, m1, padd, acc, seed, nthreads=1, r0=0):
+    """Runs Wolff sweeps m0..m1-1 in place on spins[R][L][n] (replicas r0..r0+R-1)."""
+    assert spins.dtype == np.int8 and spins.flags.c_contiguous
+    padd = np.ascontiguousarray(padd, dtype=np.uint32)
+    acc = np.ascontiguousarray(acc, dtype=np.uint32)
+    F = (acc.shape[1] - 1) // (2 * L)
+    lib().oracle_wolff_run(emb.ptr, L, r0, spins.shape[0], m0, m1, _p(padd, C.c_uint32), _p(acc, C.c_uint32),
+                           acc.shape[0], F, C.c_uint64(seed), _p(spins, C.c_int8), nthreads)
+    return spins
+
+
+def sqa_anneal_wolff(kind, J, penalty, beta, L, sweeps, replicas, gamma0, gamma1, seed, h=None, gamma=None,
+                     bscale=None, nthreads=1, r0=0):
+    """SQA with time-like Wolff moves: embed, tabulate, init (INIT stream), anneal, energies."""
+    emb = Embedding(kind, J, penalty, h)
+    g = gamma_schedule(gamma0, gamma1, sweeps) if gamma is None else np.asarray(gamma, dtype=np.float64)
+    padd, acc = wolff_tables(beta, L, g, emb.fmax, bscale)
+    spins = sqa_init(emb, L, replicas, seed, r0)
+    wolff_run(emb, L, spins, 0, sweeps, padd, acc, seed, nthreads, r0)
+    return emb, (padd, acc), spins, sqa_energies(emb, spins)
 
 
 # ---------------------------------------------------------------- PT

@@ -4,4 +4,4 @@
 set -e
 cd "$(dirname "$0")"
 gcc -std=gnu99 -O2 -fno-fast-math -ffp-contract=off -fPIC -shared -Wall -Wextra \
-    -o liboracle.so philox.c embed.c tables.c sqa.c pt.c decode.c -lm -lpthread
+    -o liboracle.so philox.c embed.c tables.c sqa.c wolff.c pt.c decode.c -lm -lpthread

@@ -29,7 +29,7 @@ extern "C" {
 
 /* RNG streams of the counter layout. */
 enum { OR_STREAM_INIT = 1, OR_STREAM_SQA = 2, OR_STREAM_PT = 3,
-       OR_STREAM_SWAP = 4, OR_STREAM_TREE = 5, OR_STREAM_PT_INIT = 6 };
+       OR_STREAM_SWAP = 4, OR_STREAM_TREE = 5, OR_STREAM_PT_INIT = 6, OR_STREAM_WOLFF = 7 };
 
 enum { OR_ME = 0, OR_LHZ = 1 };
 
@@ -92,6 +92,20 @@ void oracle_sqa_run_from(const OEmb *e, int32_t L, int32_t r0, int32_t R, int32_
                          int8_t *spins, int32_t nthreads);
 void oracle_sqa_energies(const OEmb *e, int32_t L, int32_t R, const int8_t *spins,
                          int32_t *E);
+
+/* ---- SQA with time-like Wolff cluster updates (Sec. III) ------------------ */
+uint32_t oracle_wolff_bond_word(uint64_t seed, uint32_t r, uint32_t k, uint32_t b, uint32_t m);
+void oracle_wolff_site_words(uint64_t seed, uint32_t r, uint32_t k, uint32_t m, uint32_t *u_seed,
+                             uint32_t *u_acc);
+void oracle_wolff_tables(double beta, int32_t L, int32_t M, const double *gamma,
+                         const double *bscale, int32_t F, uint32_t *padd, uint32_t *acc);
+void oracle_wolff_move(const OEmb *e, int32_t L, int32_t count, int8_t *lats, int32_t k, int32_t tau0,
+                       const uint32_t *bond_u, uint32_t u_acc, uint32_t padd, const uint32_t *acc_row,
+                       int32_t F, uint32_t *thr_out, uint64_t *cl_out);
+int32_t oracle_wolff_site_order(const OEmb *e, int32_t *site_out);
+void oracle_wolff_run(const OEmb *e, int32_t L, int32_t r0, int32_t R, int32_t m0, int32_t m1,
+                      const uint32_t *padd, const uint32_t *acc, int32_t rows, int32_t F,
+                      uint64_t seed, int8_t *spins, int32_t nthreads);
 
 /* ---- PT ------------------------------------------------------------------ */
 void oracle_pt_init(const OEmb *e, int32_t R, uint64_t seed, int8_t *spins);
