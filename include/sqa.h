@@ -77,6 +77,21 @@ typedef struct {
   int32_t penalty;    /* ME: J_F; LHZ: C (signed coefficient, e.g. -2) */
 } sqa_embedding;
 
+/* SQA update move (Sec. III).
+ *   SQA_MOVE_METROPOLIS  single-site Metropolis on the space-time lattice; a
+ *                        sweep visits every (site, slice) once, by slice
+ *                        parity, colour class, slice, site.
+ *   SQA_MOVE_WOLFF       the paper's move: for every site, one Wolff cluster
+ *                        along imaginary time.  Aligned ring bonds join with
+ *                        probability 1 - tanh(beta Gamma / L), the cluster is
+ *                        the run of joined bonds through a uniform seed slice,
+ *                        and it flips with min(1, exp(2 beta B / L sum s f)).
+ *                        A sweep visits the sites by colour class, then index.
+ * Random words: Philox4x32-10 keyed by the seed, stream SQA (2) for
+ * Metropolis and WOLFF (7) for Wolff moves; both moves start from the same
+ * INIT-stream lattice. */
+typedef enum { SQA_MOVE_METROPOLIS = 0, SQA_MOVE_WOLFF = 1 } sqa_move;
+
 /* Annealing schedule (Eq. (2)): sweep m uses Gamma_m (transverse field A) and
  * B_m.  Gamma_m = gamma_start (1 - t) + gamma_end t, t = m / (sweeps - 1),
  * unless `gamma` supplies all `sweeps` values; B_m = 1 unless `bscale` does.
@@ -91,6 +106,7 @@ typedef struct {
   const double *gamma;   /* [sweeps] or NULL */
   const double *bscale;  /* [sweeps] or NULL */
   uint64_t seed;         /* Philox key */
+  int32_t move;          /* sqa_move; 0 = SQA_MOVE_METROPOLIS */
 } sqa_schedule;
 
 typedef struct sqa_handle sqa_handle;
@@ -171,8 +187,17 @@ SQA_API sqa_status sqa_decode(sqa_handle *h, int32_t decoder, int32_t readout_sl
 SQA_API sqa_status sqa_random_trees(uint64_t seed, int32_t n, int32_t n_trees, int32_t *parents_out);
 
 /* Exports the handle's acceptance-threshold table T[m][a+F][(b+2)/2]
- * (uint32, M*(2F+1)*3 entries) and F, for parity checks. */
+ * (uint32, M*(2F+1)*3 entries) and F, for parity checks.  Metropolis
+ * handles only (SQA_ERR_INVALID for a Wolff handle). */
 SQA_API sqa_status sqa_export_table(sqa_handle *h, uint32_t *out, size_t len, int32_t *F_out);
+
+/* Exports a Wolff handle's tables: join thresholds padd[M] (accept a bond iff
+ * word < threshold, or always for 0xFFFFFFFF) and acceptance thresholds
+ * acc[rows][2 L F + 1] indexed by A + L F (rows = M when the schedule has
+ * bscale, else 1).  Either output may be NULL; rows_out / width_out report the
+ * shape.  SQA_ERR_INVALID for a Metropolis handle or a short buffer. */
+SQA_API sqa_status sqa_export_wolff_tables(sqa_handle *h, uint32_t *padd_out, size_t padd_len, uint32_t *acc_out,
+                                   size_t acc_len, int32_t *rows_out, int32_t *width_out);
 
 /* Shape queries. */
 SQA_API int64_t sqa_physical_sites(int32_t kind, int32_t n);

@@ -46,7 +46,11 @@ size_t estimate_bytes(const Embedded &e, const sqa_schedule &s) {
   const size_t n = e.n, R = s.replicas, L = s.slices, M = s.sweeps;
   const size_t F = e.fmax;
   const size_t rw = e.kind == SQA_EMB_ME ? kRecWordsME : kRecWordsLHZ;
-  size_t b = R * L * n + R * L * 4 + M * 3 * (2 * F + 1) * 4 + n * (rw * 4 + 6) + e.terms.size() * 12;
+  size_t b = R * L * n + R * L * 4 + n * (rw * 4 + 6) + e.terms.size() * 12;
+  if (s.move == SQA_MOVE_WOLFF)
+    b += M * 4 + (s.bscale ? M : 1) * (2 * L * F + 1) * 4;   // join thresholds, acceptance rows
+  else
+    b += M * 3 * (2 * F + 1) * 4;
   b += static_cast<size_t>(e.N) * e.N * 4 + R * (e.N + 4) + 4096;
   return b;
 }
@@ -181,7 +185,7 @@ sqa_status sqa_server_submit(sqa_server *s, const sqa_problem *problem, const sq
   if (!s || !problem || !embedding || !schedule || !ticket || !problem->J) return fail(SQA_ERR_INVALID, "null argument");
   const sqa_schedule &sc = *schedule;
   if (sc.slices < 1 || (sc.slices > 1 && (sc.slices & 1)) || sc.slices > 64 || sc.sweeps < 1 || sc.replicas < 1 ||
-      sc.replicas > 65536 || !(sc.beta > 0))
+      sc.replicas > 65536 || !(sc.beta > 0) || (sc.move != SQA_MOVE_METROPOLIS && sc.move != SQA_MOVE_WOLFF))
     return fail(SQA_ERR_INVALID, "bad schedule");
   Embedded e;
   sqa_status st = build_embedding(*problem, *embedding, &e);

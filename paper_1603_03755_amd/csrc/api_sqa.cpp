@@ -33,12 +33,14 @@ static hipError_t ensure_lds_limits() {
   return g_lds_status;
 }
 
-// Work items (handle, replica group) for a set of handles, longest first.
+// Work items (handle, replica group) of the handles with update move `move`,
+// longest first.
 static std::vector<WorkItem> plan_items(const std::vector<const sqa_handle *> &hs, const std::vector<int> &m0,
-                                        const std::vector<int> &m1, int waves) {
+                                        const std::vector<int> &m1, int waves, int move) {
   std::vector<std::pair<double, WorkItem>> v;
   for (size_t i = 0; i < hs.size(); ++i) {
     const sqa_handle *h = hs[i];
+    if (h->move != move) continue;
     const double cost = static_cast<double>(h->emb.n) * h->L * std::max(1, m1[i] - m0[i]);
     for (int r = 0; r < h->R; r += waves) {
       WorkItem w{static_cast<int32_t>(i), r, std::min(waves, h->R - r)};
@@ -53,13 +55,21 @@ static std::vector<WorkItem> plan_items(const std::vector<const sqa_handle *> &h
 }
 
 static LaunchShape shape_for(const std::vector<const sqa_handle *> &hs, int waves, int groups_per_cu,
-                             size_t n_items) {
+                             size_t n_items, int move) {
   LaunchShape s;
+  s.move = move;
   s.waves = waves;
   for (const sqa_handle *h : hs) {
+    if (h->move != move) continue;
     s.rec_cap = std::max(s.rec_cap, h->emb.n * h->lay.rec_words);
     s.lat_cap = std::max(s.lat_cap, h->emb.n + 1);
-    s.tab_cap = std::max(s.tab_cap, h->tw);
+    if (move == kMoveWolff) {
+      int maxclass = 0;
+      for (int c = 0; c < 4; ++c) maxclass = std::max(maxclass, h->lay.cls[c + 1] - h->lay.cls[c]);
+      s.tab_cap = std::max(s.tab_cap, kWolffScratchWords * maxclass);
+    } else {
+      s.tab_cap = std::max(s.tab_cap, h->tw);
+    }
   }
   s.rec_cap = (s.rec_cap + 3) & ~3;
   s.lat_cap = (s.lat_cap + 1) & ~1;
@@ -68,6 +78,61 @@ static LaunchShape shape_for(const std::vector<const sqa_handle *> &hs, int wave
   long long grid = static_cast<long long>(device_cu_count()) * gpc;
   s.grid = static_cast<int>(std::max<long long>(1, std::min<long long>(grid, static_cast<long long>(n_items))));
   return s;
+}
+
+// One persistent launch per update move present in a handle set.  Device
+// buffer of a set: [HandleDev x handles][items of each group][a counter per group].
+struct MoveGroup {
+  int move = kMoveMetropolis;
+  std::vector<WorkItem> items;
+  LaunchShape shape;
+  size_t items_off = 0, counter_off = 0;
+};
+
+static sqa_status plan_groups(const std::vector<const sqa_handle *> &hs, const std::vector<int> &m0,
+                              const std::vector<int> &m1, int waves, int gpc, std::vector<MoveGroup> *out,
+                              size_t *bytes) {
+  out->clear();
+  size_t off = (sizeof(HandleDev) * hs.size() + 255) & ~size_t(255);
+  for (int move : {kMoveMetropolis, kMoveWolff}) {
+    MoveGroup g;
+    g.move = move;
+    g.items = plan_items(hs, m0, m1, waves, move);
+    if (g.items.empty()) continue;
+    g.shape = shape_for(hs, waves, gpc, g.items.size(), move);
+    if (g.shape.lds_bytes() > kMaxLds) return fail(SQA_ERR_UNSUPPORTED, "lattices do not fit in LDS");
+    g.items_off = off;
+    off = (off + sizeof(WorkItem) * g.items.size() + 255) & ~size_t(255);
+    out->push_back(std::move(g));
+  }
+  for (MoveGroup &g : *out) {
+    g.counter_off = off;
+    off += 256;
+  }
+  *bytes = off;
+  return SQA_OK;
+}
+
+static hipError_t upload_groups(char *base, const std::vector<HandleDev> &hds, const std::vector<MoveGroup> &gs,
+                                hipStream_t stream) {
+  hipError_t e = hipMemcpyAsync(base, hds.data(), sizeof(HandleDev) * hds.size(), hipMemcpyHostToDevice, stream);
+  for (const MoveGroup &g : gs) {
+    if (e != hipSuccess) break;
+    e = hipMemcpyAsync(base + g.items_off, g.items.data(), sizeof(WorkItem) * g.items.size(), hipMemcpyHostToDevice,
+                       stream);
+  }
+  return e;
+}
+
+static hipError_t launch_groups(char *base, const std::vector<MoveGroup> &gs, hipStream_t stream) {
+  hipError_t e = hipSuccess;
+  for (const MoveGroup &g : gs) {
+    e = launch_sqa_anneal(g.move, reinterpret_cast<HandleDev *>(base), reinterpret_cast<WorkItem *>(base + g.items_off),
+                          static_cast<int>(g.items.size()), reinterpret_cast<int *>(base + g.counter_off), g.shape.grid,
+                          g.shape.waves, g.shape.rec_cap, g.shape.lat_cap, g.shape.tab_cap, stream);
+    if (e != hipSuccess) break;
+  }
+  return e;
 }
 
 // ---------------------------------------------------------------- autotune cache
@@ -84,11 +149,12 @@ static std::string device_arch() {
 // replica count rounded up to a power of two, and whether both kinds are present.
 static std::string shape_class(const std::vector<const sqa_handle *> &hs) {
   int maxcells = 1, maxrep = 1;
-  bool me = false, lhz = false;
+  bool me = false, lhz = false, wolff = false;
   for (const sqa_handle *h : hs) {
     maxcells = std::max(maxcells, h->emb.n * h->L);
     maxrep = std::max(maxrep, h->R);
     (h->emb.kind == SQA_EMB_ME ? me : lhz) = true;
+    wolff = wolff || h->move == kMoveWolff;
   }
   auto p2 = [](int v) {
     int p = 1;
@@ -96,7 +162,8 @@ static std::string shape_class(const std::vector<const sqa_handle *> &hs) {
     return p;
   };
   char buf[96];
-  std::snprintf(buf, sizeof(buf), "cells%d_rep%d_%s", p2(maxcells), p2(maxrep), me && lhz ? "mix" : (me ? "me" : "lhz"));
+  std::snprintf(buf, sizeof(buf), "cells%d_rep%d_%s%s", p2(maxcells), p2(maxrep), me && lhz ? "mix" : (me ? "me" : "lhz"),
+                wolff ? "_wolff" : "");
   return buf;
 }
 
@@ -197,6 +264,7 @@ sqa_status sqa_create(const sqa_problem *problem, const sqa_embedding *embedding
   if (s.slices > 64) return fail(SQA_ERR_UNSUPPORTED, "at most 64 Trotter slices");
   if (s.sweeps < 1) return fail(SQA_ERR_INVALID, "sweeps must be >= 1");
   if (s.replicas < 1 || s.replicas > 65536) return fail(SQA_ERR_INVALID, "replicas must be in 1..65536");
+  if (s.move != SQA_MOVE_METROPOLIS && s.move != SQA_MOVE_WOLFF) return fail(SQA_ERR_INVALID, "unknown update move");
   std::vector<double> gamma;
   if (s.gamma) gamma.assign(s.gamma, s.gamma + s.sweeps);
   else gamma = linear_gamma(s.gamma_start, s.gamma_end, s.sweeps);
@@ -223,19 +291,27 @@ sqa_status sqa_create(const sqa_problem *problem, const sqa_embedding *embedding
   h->beta = s.beta;
   h->seed = s.seed;
   h->F = h->emb.fmax;
-  h->tw = 3 * (2 * h->F + 1);
+  h->move = s.move;
+  h->tw = (h->move == kMoveWolff) ? 1 : 3 * (2 * h->F + 1);
   h->J.assign(problem->J, problem->J + static_cast<size_t>(h->N) * h->N);
   h->h.assign(h->N, 0);
   if (problem->h) {
     h->has_h = true;
     std::copy(problem->h, problem->h + h->N, h->h.begin());
   }
-  st = build_layout(h->emb, h->F, true, &h->lay);
+  // Wolff moves sum plain weights per slice; Metropolis records carry 6|w| when F is small
+  st = build_layout(h->emb, h->F, h->move != kMoveWolff, &h->lay);
   if (st != SQA_OK) {
     delete h;
     return st;
   }
-  h->table = sqa_threshold_table(s.beta, s.slices, gamma, s.bscale ? &bscale : nullptr, h->F);
+  if (h->move == kMoveWolff) {
+    h->table = wolff_join_table(s.beta, s.slices, gamma);
+    h->wacc = wolff_accept_table(s.beta, s.slices, s.bscale ? &bscale : nullptr, h->F, &h->wrows);
+    h->wwidth = 2 * s.slices * h->F + 1;
+  } else {
+    h->table = sqa_threshold_table(s.beta, s.slices, gamma, s.bscale ? &bscale : nullptr, h->F);
+  }
 
   const int n = h->emb.n, R = h->R, L = h->L, N = h->N;
   const size_t nt = h->emb.terms.size();
@@ -246,6 +322,7 @@ sqa_status sqa_create(const sqa_problem *problem, const sqa_embedding *embedding
   h->off_tw = A.take(std::max<size_t>(nt, 1) * 4);
   h->off_ts = A.take(std::max<size_t>(nt, 1) * 8);
   h->off_table = A.take(h->table.size() * 4);
+  h->off_wacc = A.take(std::max<size_t>(h->wacc.size(), 1) * 4);
   h->off_spins = A.take(static_cast<size_t>(R) * L * n);
   h->off_energy = A.take(static_cast<size_t>(R) * L * 4);
   h->off_J = A.take(static_cast<size_t>(N) * N * 4);
@@ -273,6 +350,7 @@ sqa_status sqa_create(const sqa_problem *problem, const sqa_embedding *embedding
       {h->off_tw, h->lay.term_w.data(), nt * 4},
       {h->off_ts, h->lay.term_s.data(), nt * 8},
       {h->off_table, h->table.data(), h->table.size() * 4},
+      {h->off_wacc, h->wacc.data(), h->wacc.size() * 4},
       {h->off_J, h->J.data(), static_cast<size_t>(N) * N * 4},
       {h->off_h, h->h.data(), static_cast<size_t>(N) * 4},
   };
@@ -320,8 +398,8 @@ static sqa_status run_single(sqa_handle *h, int m0, int m1, int flags, hipStream
   std::vector<const sqa_handle *> hs{h};
   int waves = 4, gpc = 0;
   resolve_config(hs, nullptr, &waves, &gpc);
-  std::vector<WorkItem> items = plan_items(hs, {m0}, {m1}, waves);
-  LaunchShape shape = shape_for(hs, waves, gpc, items.size());
+  std::vector<WorkItem> items = plan_items(hs, {m0}, {m1}, waves, h->move);
+  LaunchShape shape = shape_for(hs, waves, gpc, items.size(), h->move);
   if (shape.lds_bytes() > kMaxLds) return fail(SQA_ERR_UNSUPPORTED, "lattice does not fit in LDS");
   // previous work on this handle must have consumed the pinned staging copy
   e = hipEventSynchronize(h->done);
@@ -338,7 +416,7 @@ static sqa_status run_single(sqa_handle *h, int m0, int m1, int flags, hipStream
     e = hipMemcpyAsync(h->arena.at<void>(h->off_items), st_items, items.size() * sizeof(WorkItem),
                        hipMemcpyHostToDevice, stream);
   if (e == hipSuccess)
-    e = launch_sqa_anneal(h->arena.at<HandleDev>(h->off_hd), h->arena.at<WorkItem>(h->off_items),
+    e = launch_sqa_anneal(h->move, h->arena.at<HandleDev>(h->off_hd), h->arena.at<WorkItem>(h->off_items),
                           static_cast<int>(items.size()), h->arena.at<int>(h->off_counter), shape.grid, shape.waves,
                           shape.rec_cap, shape.lat_cap, shape.tab_cap, stream);
   if (e == hipSuccess) e = hipEventRecord(h->done, stream);
@@ -439,10 +517,28 @@ sqa_status sqa_handle_info(sqa_handle *h, int32_t *sites, int32_t *slices, int32
 
 sqa_status sqa_export_table(sqa_handle *h, uint32_t *out, size_t len, int32_t *F_out) {
   if (!h) return fail(SQA_ERR_INVALID, "null handle");
+  if (h->move != kMoveMetropolis) return fail(SQA_ERR_INVALID, "Wolff handle: use sqa_export_wolff_tables");
   if (F_out) *F_out = h->F;
   if (!out) return SQA_OK;
   if (len < h->table.size()) return fail(SQA_ERR_INVALID, "table buffer too short");
   std::memcpy(out, h->table.data(), h->table.size() * 4);
+  return SQA_OK;
+}
+
+sqa_status sqa_export_wolff_tables(sqa_handle *h, uint32_t *padd_out, size_t padd_len, uint32_t *acc_out,
+                                   size_t acc_len, int32_t *rows_out, int32_t *width_out) {
+  if (!h) return fail(SQA_ERR_INVALID, "null handle");
+  if (h->move != kMoveWolff) return fail(SQA_ERR_INVALID, "not a Wolff handle");
+  if (rows_out) *rows_out = h->wrows;
+  if (width_out) *width_out = h->wwidth;
+  if (padd_out) {
+    if (padd_len < h->table.size()) return fail(SQA_ERR_INVALID, "join-threshold buffer too short");
+    std::memcpy(padd_out, h->table.data(), h->table.size() * 4);
+  }
+  if (acc_out) {
+    if (acc_len < h->wacc.size()) return fail(SQA_ERR_INVALID, "acceptance buffer too short");
+    std::memcpy(acc_out, h->wacc.data(), h->wacc.size() * 4);
+  }
   return SQA_OK;
 }
 
@@ -642,15 +738,12 @@ sqa_status run_handles(const std::vector<sqa_handle *> &hs, const std::vector<in
   std::vector<const sqa_handle *> ch(hs.begin(), hs.end());
   int waves = 4, gpc = 0;
   resolve_config(ch, nullptr, &waves, &gpc);
-  std::vector<WorkItem> items = plan_items(ch, m0, m1, waves);
-  LaunchShape shape = shape_for(ch, waves, gpc, items.size());
-  if (shape.lds_bytes() > kMaxLds) return fail(SQA_ERR_UNSUPPORTED, "lattices do not fit in LDS");
+  std::vector<MoveGroup> groups;
+  size_t need = 0;
+  sqa_status st = plan_groups(ch, m0, m1, waves, gpc, &groups, &need);
+  if (st != SQA_OK) return st;
   std::vector<HandleDev> hds(hs.size());
   for (size_t i = 0; i < hs.size(); ++i) hds[i] = hs[i]->dev(m0[i], m1[i], flags[i]);
-  const size_t bh = sizeof(HandleDev) * hds.size();
-  const size_t oi = (bh + 255) & ~size_t(255);
-  const size_t oc = (oi + sizeof(WorkItem) * items.size() + 255) & ~size_t(255);
-  const size_t need = oc + 256;
   if (*scratch_bytes < need) {
     if (*scratch) (void)hipFree(*scratch);
     *scratch = nullptr;
@@ -660,13 +753,8 @@ sqa_status run_handles(const std::vector<sqa_handle *> &hs, const std::vector<in
     *scratch_bytes = need;
   }
   char *base = static_cast<char *>(*scratch);
-  e = hipMemcpyAsync(base, hds.data(), bh, hipMemcpyHostToDevice, stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(base + oi, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice, stream);
-  if (e == hipSuccess)
-    e = launch_sqa_anneal(reinterpret_cast<HandleDev *>(base), reinterpret_cast<WorkItem *>(base + oi),
-                          static_cast<int>(items.size()), reinterpret_cast<int *>(base + oc), shape.grid, shape.waves,
-                          shape.rec_cap, shape.lat_cap, shape.tab_cap, stream);
+  e = upload_groups(base, hds, groups, stream);
+  if (e == hipSuccess) e = launch_groups(base, groups, stream);
   if (e == hipSuccess)
     for (sqa_handle *h : hs) {
       e = hipEventRecord(h->done, stream);
@@ -686,12 +774,8 @@ sqa_status run_handles(const std::vector<sqa_handle *> &hs, const std::vector<in
 struct sqa_batch {
   std::vector<sqa_handle *> handles;
   sqa_launch_config config{0, 0};
-  LaunchShape shape;
-  int n_items = 0;
+  std::vector<sqa::MoveGroup> groups;
   void *dev = nullptr;
-  HandleDev *d_hds = nullptr;
-  WorkItem *d_items = nullptr;
-  int *d_counter = nullptr;
   hipStream_t capture_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -701,32 +785,25 @@ static sqa_status batch_build(sqa_handle *const *handles, int32_t count, int wav
   std::vector<const sqa_handle *> hs(handles, handles + count);
   std::vector<int> m0(count, 0), m1(count);
   for (int i = 0; i < count; ++i) m1[i] = handles[i]->M;
-  std::vector<WorkItem> items = plan_items(hs, m0, m1, waves);
-  LaunchShape shape = shape_for(hs, waves, gpc, items.size());
-  if (shape.lds_bytes() > kMaxLds) return fail(SQA_ERR_UNSUPPORTED, "batch lattices do not fit in LDS");
+  std::vector<MoveGroup> groups;
+  size_t bytes = 0;
+  sqa_status st = plan_groups(hs, m0, m1, waves, gpc, &groups, &bytes);
+  if (st != SQA_OK) return st;
   std::vector<HandleDev> hds(count);
   for (int i = 0; i < count; ++i) hds[i] = handles[i]->dev(0, handles[i]->M, kFlagInit | kFlagEnergy);
   sqa_batch *b = new (std::nothrow) sqa_batch();
   if (!b) return fail(SQA_ERR_OOM, "host allocation");
   b->handles.assign(handles, handles + count);
   b->config.waves_per_group = waves;
-  b->config.groups_per_cu = gpc > 0 ? gpc : occupancy_groups_per_cu(shape);
-  b->shape = shape;
-  b->n_items = static_cast<int>(items.size());
-  const size_t bh = sizeof(HandleDev) * hds.size();
-  const size_t bi = sizeof(WorkItem) * items.size();
-  const size_t oi = (bh + 255) & ~size_t(255);
-  const size_t oc = (oi + bi + 255) & ~size_t(255);
-  hipError_t e = hipMalloc(&b->dev, oc + 256);
+  b->config.groups_per_cu = gpc > 0 ? gpc : occupancy_groups_per_cu(groups.front().shape);
+  b->groups = std::move(groups);
+  hipError_t e = hipMalloc(&b->dev, bytes);
   if (e != hipSuccess) {
     delete b;
     return hip_fail(e, "hipMalloc (batch)");
   }
-  b->d_hds = reinterpret_cast<HandleDev *>(b->dev);
-  b->d_items = reinterpret_cast<WorkItem *>(static_cast<char *>(b->dev) + oi);
-  b->d_counter = reinterpret_cast<int *>(static_cast<char *>(b->dev) + oc);
-  e = hipMemcpy(b->d_hds, hds.data(), bh, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(b->d_items, items.data(), bi, hipMemcpyHostToDevice);
+  e = upload_groups(static_cast<char *>(b->dev), hds, b->groups, nullptr);
+  if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
   if (e != hipSuccess) {
     (void)hipFree(b->dev);
     delete b;
@@ -741,8 +818,7 @@ static sqa_status batch_capture(sqa_batch *b) {
   if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
   e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-  hipError_t le = launch_sqa_anneal(b->d_hds, b->d_items, b->n_items, b->d_counter, b->shape.grid, b->shape.waves,
-                                    b->shape.rec_cap, b->shape.lat_cap, b->shape.tab_cap, b->capture_stream);
+  hipError_t le = launch_groups(static_cast<char *>(b->dev), b->groups, b->capture_stream);
   e = hipStreamEndCapture(b->capture_stream, &b->graph);
   if (le != hipSuccess) return hip_fail(le, "capture anneal launch");
   if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
@@ -867,32 +943,26 @@ sqa_status sqa_autotune(sqa_handle *const *handles, int32_t count, const char *c
     for (int w : {2, 4, 8}) {   // multiples of the 4 SIMDs of a CU keep waves balanced
       std::vector<int> m0(count, 0), m1(count);
       for (int i = 0; i < count; ++i) m1[i] = std::min(handles[i]->M, trial_sweeps);
-      std::vector<WorkItem> items = plan_items(hs, m0, m1, w);
-      LaunchShape base = shape_for(hs, w, 0, items.size());
-      if (base.lds_bytes() > kMaxLds) continue;
-      const int occ = occupancy_groups_per_cu(base);
+      std::vector<MoveGroup> base;
+      size_t bytes = 0;
+      if (plan_groups(hs, m0, m1, w, 0, &base, &bytes) != SQA_OK) continue;
+      // groups-per-CU candidates from the occupancy of the first group's kernel
+      const int occ = occupancy_groups_per_cu(base.front().shape);
       std::vector<int> gpcs{occ};
       if (occ >= 2) gpcs.push_back(occ / 2);
       for (int g : gpcs) {
-        LaunchShape s = shape_for(hs, w, g, items.size());
+        std::vector<MoveGroup> groups;
+        if (plan_groups(hs, m0, m1, w, g, &groups, &bytes) != SQA_OK) continue;
         std::vector<HandleDev> hds(count);
         for (int i = 0; i < count; ++i) hds[i] = handles[i]->dev(0, m1[i], kFlagInit);
         void *dev = nullptr;
-        const size_t bh = sizeof(HandleDev) * count, oi = (bh + 255) & ~size_t(255);
-        const size_t oc = (oi + sizeof(WorkItem) * items.size() + 255) & ~size_t(255);
-        if (hipMalloc(&dev, oc + 256) != hipSuccess) continue;
-        (void)hipMemcpy(dev, hds.data(), bh, hipMemcpyHostToDevice);
-        (void)hipMemcpy(static_cast<char *>(dev) + oi, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice);
+        if (hipMalloc(&dev, bytes) != hipSuccess) continue;
+        hipError_t le = upload_groups(static_cast<char *>(dev), hds, groups, nullptr);
         // the second of two identical launches is timed (the first warms caches and code)
         float ms = 0;
-        hipError_t le = hipSuccess;
         for (int rep = 0; rep < 2 && le == hipSuccess; ++rep) {
           (void)hipEventRecord(a, nullptr);
-          le = launch_sqa_anneal(reinterpret_cast<HandleDev *>(dev),
-                                 reinterpret_cast<WorkItem *>(static_cast<char *>(dev) + oi),
-                                 static_cast<int>(items.size()),
-                                 reinterpret_cast<int *>(static_cast<char *>(dev) + oc), s.grid, s.waves, s.rec_cap,
-                                 s.lat_cap, s.tab_cap, nullptr);
+          le = launch_groups(static_cast<char *>(dev), groups, nullptr);
           (void)hipEventRecord(z, nullptr);
           (void)hipEventSynchronize(z);
           (void)hipEventElapsedTime(&ms, a, z);

@@ -69,4 +69,9 @@ __device__ __forceinline__ uint32_t spread6_hi(uint32_t byte) {
   return (__umul24(byte & 0xF0u, 0x8421u) >> 4) & 0x41041u;
 }
 
+// Four bits of a nibble moved to bit 0 of the four bytes of a word (partial
+// products at bits j + 7i, all distinct: no carries).  The result has bit 24
+// set for nibble bit 3, so it must not be an operand of a 24-bit multiply.
+__device__ __forceinline__ uint32_t spread8(uint32_t nib) { return __umul24(nib & 0xFu, 0x204081u) & 0x01010101u; }
+
 }  // namespace sqa

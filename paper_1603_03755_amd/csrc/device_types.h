@@ -3,8 +3,10 @@
 // Device site order: sites are renumbered so that each of the four colour
 // classes is contiguous (class c occupies [cls[c], cls[c+1])) and increasing
 // by physical site id inside a class.  The lattice of one replica lives in
-// LDS as one 64-bit word per site (bit tau = 1 <=> spin -1 on slice tau),
-// followed by one all-zero word (index n) that unused partner slots point to.
+// LDS as one 64-bit word per site (a set bit = spin -1; the Metropolis kernel
+// keeps even slices in the low half and odd slices in the high half, the
+// Wolff kernel keeps slice tau at bit tau), followed by one all-zero word
+// (index n) that unused partner slots point to.
 #pragma once
 #include <cstdint>
 
@@ -42,6 +44,16 @@ constexpr uint32_t kStreamPT = 3;
 constexpr uint32_t kStreamSwap = 4;
 constexpr uint32_t kStreamTree = 5;
 constexpr uint32_t kStreamPTInit = 6;
+constexpr uint32_t kStreamWolff = 7;
+
+// SQA update move of a handle.
+constexpr int kMoveMetropolis = 0;   // single-site Metropolis on the space-time lattice
+constexpr int kMoveWolff = 1;        // time-like Wolff cluster per site (records with plain weights)
+// Counter word 1 of the Philox call that draws a Wolff move's seed slice and acceptance word.
+constexpr uint32_t kWolffSiteCtr = 64;
+// LDS scratch of one wave for Wolff moves, per site of the largest colour class (32-bit words):
+// the 64-bit join mask and the 64 per-slice disagreement sums as bytes.
+constexpr int kWolffScratchWords = 18;
 
 constexpr uint32_t kAlways = 0xFFFFFFFFu;
 
@@ -55,13 +67,15 @@ struct HandleDev {
   const int32_t *hfield;    // [n] field of each device-order site
   const int32_t *term_w;    // [n_terms]
   const uint32_t *term_s;   // [n_terms][2]: four u16 device indices (zero word = n)
-  const uint32_t *table;    // [M][tw]
+  const uint32_t *table;    // Metropolis: [M][tw]; Wolff: join thresholds [M] (tw = 1)
+  const uint32_t *wacc;     // Wolff: acceptance thresholds [wrows][wwidth], index A + L F
   int8_t *spins;            // [R][L][n] physical order, +1/-1
   int32_t *energy;          // [R][L]
   int32_t kind, n, n_terms, L, M, R, F, tw;
   int32_t m0, m1, flags;
   uint32_t seed_lo, seed_hi;
   int32_t cls[5];
+  int32_t move, wrows, wwidth;
 };
 
 // One unit of persistent-kernel work: handle index, first replica, count.

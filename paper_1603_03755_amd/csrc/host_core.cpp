@@ -233,6 +233,32 @@ std::vector<uint32_t> sqa_threshold_table(double beta, int32_t L, const std::vec
   return T;
 }
 
+// Sec. III, time-like Wolff moves on the same Trotter action: an aligned ring
+// bond joins the cluster with probability 1 - exp(-2 J_perp) = 1 - tanh(beta
+// Gamma / L) (no bonds with L = 1); a cluster whose spins carry sum s f = A
+// flips with min(1, exp(2 beta B / L * A)).
+std::vector<uint32_t> wolff_join_table(double beta, int32_t L, const std::vector<double> &gamma) {
+  std::vector<uint32_t> T(gamma.size(), 0u);
+  if (L > 1)
+    for (size_t m = 0; m < gamma.size(); ++m)
+      T[m] = threshold_from_log(std::log(1.0 - std::tanh(beta * gamma[m] / static_cast<double>(L))));
+  return T;
+}
+
+std::vector<uint32_t> wolff_accept_table(double beta, int32_t L, const std::vector<double> *bscale, int32_t F,
+                                         int32_t *rows) {
+  const int32_t nrows = bscale ? static_cast<int32_t>(bscale->size()) : 1;
+  const int32_t width = 2 * L * F + 1;
+  std::vector<uint32_t> T(static_cast<size_t>(nrows) * width);
+  for (int32_t r = 0; r < nrows; ++r) {
+    const double bl = beta * (bscale ? (*bscale)[r] : 1.0) / static_cast<double>(L);
+    for (int32_t a = -L * F; a <= L * F; ++a)
+      T[static_cast<size_t>(r) * width + (a + L * F)] = threshold_from_log(2.0 * (bl * static_cast<double>(a)));
+  }
+  *rows = nrows;
+  return T;
+}
+
 // Appendix B, Eq. (B2): geometric ladder, slot 0 coldest.
 std::vector<double> pt_betas(double beta_min, double beta_max, int32_t R) {
   std::vector<double> b(R);
@@ -297,7 +323,7 @@ int device_cu_count() {
 // Resident groups per CU: the runtime's occupancy calculation for the sweep
 // kernel (registers, LDS, wave slots), else an LDS / wave-slot estimate.
 int occupancy_groups_per_cu(const LaunchShape &s) {
-  const int rt = sqa_anneal_occupancy(s.waves, s.lds_bytes());
+  const int rt = sqa_anneal_occupancy(s.move, s.waves, s.lds_bytes());
   if (rt > 0) return rt;
   const size_t lds = s.lds_bytes() + 64;
   int by_lds = static_cast<int>(kMaxLds / std::max<size_t>(lds, 1));
@@ -316,6 +342,10 @@ sqa::HandleDev sqa_handle::dev(int m0, int m1, int flags) const {
   H.term_w = arena.at<int32_t>(off_tw);
   H.term_s = arena.at<uint32_t>(off_ts);
   H.table = arena.at<uint32_t>(off_table);
+  H.wacc = (move == sqa::kMoveWolff) ? arena.at<uint32_t>(off_wacc) : nullptr;
+  H.move = move;
+  H.wrows = wrows;
+  H.wwidth = wwidth;
   H.spins = arena.at<int8_t>(off_spins);
   H.energy = arena.at<int32_t>(off_energy);
   H.kind = emb.kind;

@@ -59,6 +59,12 @@ std::vector<double> linear_gamma(double g0, double g1, int32_t M);
 // T[m][a+F][(b+2)/2]
 std::vector<uint32_t> sqa_threshold_table(double beta, int32_t L, const std::vector<double> &gamma,
                                           const std::vector<double> *bscale, int32_t F);
+// Wolff moves (Sec. III): join thresholds of aligned ring bonds, p = 1 - tanh(beta Gamma_m / L),
+// per sweep; acceptance thresholds of a cluster with sum s f = A, exp(2 beta B / L A), indexed
+// [row][A + L F] with one row per sweep when B varies, else one row.
+std::vector<uint32_t> wolff_join_table(double beta, int32_t L, const std::vector<double> &gamma);
+std::vector<uint32_t> wolff_accept_table(double beta, int32_t L, const std::vector<double> *bscale, int32_t F,
+                                         int32_t *rows);
 std::vector<double> pt_betas(double beta_min, double beta_max, int32_t R);
 std::vector<uint32_t> pt_metropolis_table(const std::vector<double> &betas, int32_t F);
 std::vector<uint32_t> pt_swap_table(const std::vector<double> &betas, int32_t Dmax);
@@ -82,10 +88,10 @@ struct Arena {
 };
 
 // Kernel launchers (sqa_kernels.hip, pt_kernels.hip).
-hipError_t launch_sqa_anneal(const HandleDev *hds, const WorkItem *items, int n_items, int *counter, int grid,
+hipError_t launch_sqa_anneal(int move, const HandleDev *hds, const WorkItem *items, int n_items, int *counter, int grid,
                              int waves, int rec_cap, int lat_cap, int tab_cap, hipStream_t stream);
 hipError_t set_sqa_anneal_lds_limit(size_t bytes);
-int sqa_anneal_occupancy(int waves, size_t lds_bytes);
+int sqa_anneal_occupancy(int move, int waves, size_t lds_bytes);
 hipError_t launch_sqa_init(const HandleDev &H, hipStream_t stream);
 hipError_t launch_me_majority(const int8_t *spins, int R, int N, int n_sites, int L, int slice, const int32_t *J,
                               const int32_t *h, int8_t *logical, int32_t *energy, hipStream_t stream);
@@ -99,6 +105,7 @@ constexpr size_t kMaxLds = 160 * 1024 - 512;
 
 // Launch geometry for a set of handles.
 struct LaunchShape {
+  int move = kMoveMetropolis;
   int waves = 4;
   int grid = 0;
   int rec_cap = 0, lat_cap = 0, tab_cap = 0;
@@ -128,14 +135,17 @@ struct sqa_handle {
   sqa::Embedded emb;
   sqa::DeviceLayout lay;
   int32_t N = 0, L = 0, M = 0, R = 0, F = 0, tw = 0;
+  int32_t move = 0;                  // kMoveMetropolis or kMoveWolff
+  int32_t wrows = 0, wwidth = 0;     // Wolff acceptance table shape
+  std::vector<uint32_t> wacc;        // Wolff acceptance table, host copy
   double beta = 0;
   uint64_t seed = 0;
   std::vector<int32_t> J, h;         // logical problem (n*n, n)
   bool has_h = false;
-  std::vector<uint32_t> table;       // host copy, exported for parity checks
+  std::vector<uint32_t> table;       // per-sweep table, host copy (Metropolis T[m][a][b]; Wolff join thresholds)
   sqa::Arena arena;
   size_t off_rec = 0, off_devof = 0, off_hfield = 0, off_tw = 0, off_ts = 0, off_table = 0, off_spins = 0,
-         off_energy = 0, off_J = 0, off_h = 0, off_logical = 0, off_lenergy = 0, off_hd = 0, off_items = 0,
+         off_energy = 0, off_wacc = 0, off_J = 0, off_h = 0, off_logical = 0, off_lenergy = 0, off_hd = 0, off_items = 0,
          off_counter = 0;
   bool initialised = false;          // device lattice holds a state
   bool poisoned = false;

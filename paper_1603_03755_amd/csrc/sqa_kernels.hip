@@ -1,11 +1,10 @@
-// gfx950 SQA kernels: lattice initialisation, the persistent sweep kernel,
-// per-slice energies and ME majority-vote decoding.
+// gfx950 SQA kernels: lattice initialisation, the persistent sweep kernels
+// (single-site Metropolis moves, and the time-like Wolff cluster moves of
+// Sec. III), per-slice energies and ME majority-vote decoding.
 //
 // Method (arXiv:1603.03755): discrete-time path-integral Monte Carlo on L
-// Trotter slices of an embedded Ising Hamiltonian (Sec. III, Appendix B) with
-// single-site Metropolis moves; parallel tempering of the classical embedded
-// Hamiltonian (Appendix B, Eqs. (B1)-(B2)); majority-vote decoding of ME
-// chains (Eq. (4)).
+// Trotter slices of an embedded Ising Hamiltonian (Sec. III, Appendix B);
+// majority-vote decoding of ME chains (Eq. (4)).
 //
 // Data layout on the device.  Each replica's space-time lattice is held in
 // LDS for the whole anneal, one 64-bit word per site: even slices in the low
@@ -24,13 +23,16 @@
 namespace sqa {
 
 // ------------------------------------------------------------ lattice I/O
-// LDS word of a site: bits 0..31 hold the even slices (bit j = slice 2j),
-// bits 32..63 the odd slices (bit 32+j = slice 2j+1); a set bit is spin -1.
-// With L = 1 only bit 0 is used.
-__device__ __forceinline__ int slice_bit(int tau) { return (tau >> 1) + ((tau & 1) << 5); }
+// LDS word of a site, a set bit is spin -1.  Parity-split layout (Metropolis
+// kernel): bits 0..31 hold the even slices (bit j = slice 2j), bits 32..63 the
+// odd slices (bit 32+j = slice 2j+1).  Natural layout (NAT, Wolff kernel):
+// bit tau = slice tau.  With L = 1 only bit 0 is used.
+template <bool NAT>
+__device__ __forceinline__ int slice_bit(int tau) { return NAT ? tau : (tau >> 1) + ((tau & 1) << 5); }
 
 // Builds the initial lattice in LDS: s = -1 iff bit 31 of the INIT-stream word
 // of (replica, slice, site, sweep 0).
+template <bool NAT>
 __device__ __forceinline__ void init_lattice(const HandleDev &H, uint64_t *lat, int rep, int lane) {
   const int L = H.L, n = H.n;
   const int G = (L + 7) >> 3;
@@ -45,7 +47,7 @@ __device__ __forceinline__ void init_lattice(const HandleDev &H, uint64_t *lat, 
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
           const int tau = 8 * g + p + 2 * k;
-          if (tau < L) w |= static_cast<uint64_t>(u.v[k] >> 31) << slice_bit(tau);
+          if (tau < L) w |= static_cast<uint64_t>(u.v[k] >> 31) << slice_bit<NAT>(tau);
         }
       }
     }
@@ -55,33 +57,36 @@ __device__ __forceinline__ void init_lattice(const HandleDev &H, uint64_t *lat, 
 }
 
 // Loads [L][n] int8 spins of one replica (physical order) into LDS words.
+template <bool NAT>
 __device__ __forceinline__ void load_lattice(const HandleDev &H, uint64_t *lat, int rep, int lane) {
   const int L = H.L, n = H.n;
   const int8_t *src = H.spins + static_cast<size_t>(rep) * L * n;
   for (int k = lane; k < n; k += 64) {
     uint64_t w = 0;
     for (int tau = 0; tau < L; ++tau)
-      w |= static_cast<uint64_t>(src[static_cast<size_t>(tau) * n + k] < 0) << slice_bit(tau);
+      w |= static_cast<uint64_t>(src[static_cast<size_t>(tau) * n + k] < 0) << slice_bit<NAT>(tau);
     lat[H.dev_of[k]] = w;
   }
   if (lane == 0) lat[n] = 0;
 }
 
+template <bool NAT>
 __device__ __forceinline__ void store_lattice(const HandleDev &H, const uint64_t *lat, int rep, int lane) {
   const int L = H.L, n = H.n;
   int8_t *dst = H.spins + static_cast<size_t>(rep) * L * n;
   for (int k = lane; k < n; k += 64) {
     const uint64_t w = lat[H.dev_of[k]];
     for (int tau = 0; tau < L; ++tau)
-      dst[static_cast<size_t>(tau) * n + k] = ((w >> slice_bit(tau)) & 1ull) ? int8_t(-1) : int8_t(1);
+      dst[static_cast<size_t>(tau) * n + k] = ((w >> slice_bit<NAT>(tau)) & 1ull) ? int8_t(-1) : int8_t(1);
   }
 }
 
 // E^tau = sum_k h_k s_k + sum_t w_t prod s, one lane per slice.
+template <bool NAT>
 __device__ __forceinline__ void slice_energies(const HandleDev &H, const uint64_t *lat, int rep, int lane) {
   const int tau = lane;
   if (tau >= H.L) return;
-  const int b = slice_bit(tau);
+  const int b = slice_bit<NAT>(tau);
   int32_t E = 0;
   for (int d = 0; d < H.n; ++d) E += H.hfield[d] * (1 - 2 * static_cast<int32_t>((lat[d] >> b) & 1ull));
   for (int t = 0; t < H.n_terms; ++t) {
@@ -234,8 +239,8 @@ __device__ __forceinline__ void sweep_class(const HandleDev &H, const uint32_t *
 template <int KIND>
 __device__ __forceinline__ void anneal_replica(const HandleDev &H, const uint32_t *rec, uint64_t *lat, uint32_t *tab,
                                int rep, int lane) {
-  if (H.flags & kFlagInit) init_lattice(H, lat, rep, lane);
-  else load_lattice(H, lat, rep, lane);
+  if (H.flags & kFlagInit) init_lattice<false>(H, lat, rep, lane);
+  else load_lattice<false>(H, lat, rep, lane);
   wave_sync();
   const uint32_t c3 = (kStreamSQA << 24) | static_cast<uint32_t>(rep);
   const int parities = (H.L == 1) ? 1 : 2;
@@ -263,18 +268,198 @@ __device__ __forceinline__ void anneal_replica(const HandleDev &H, const uint32_
         wave_sync();
       }
   }
-  store_lattice(H, lat, rep, lane);
-  if (H.flags & kFlagEnergy) slice_energies(H, lat, rep, lane);
+  store_lattice<false>(H, lat, rep, lane);
+  if (H.flags & kFlagEnergy) slice_energies<false>(H, lat, rep, lane);
   wave_sync();
 }
 
-// Persistent kernel: each workgroup repeatedly takes the next work item
-// (handle, replica group) from `counter`, stages the handle's site records in
-// LDS, and runs one replica per wavefront through sweeps m0..m1-1.
-// Dynamic LDS: [rec_cap words][waves x lat_cap u64][waves x tab_cap words].
+// ------------------------------------------------------ SQA, Wolff moves
+// Time-like Wolff cluster moves (Sec. III), lattice in natural layout.  For
+// each colour class, two phases separated by a wave-level barrier:
+//  1. item = (site of the class, byte q of its word): the eight slices
+//     8q..8q+7 and the ring bonds that start at them.  Bond b = 8q+k joins
+//     when its two spins are equal and its word (word b & 3 of the WOLFF call
+//     with counter word 1 = b >> 2, so calls 2q and 2q+1) passes the sweep's
+//     join threshold.  The item also forms, per slice, the weighted
+//     disagreement sum S = sum_t |w_t| X_t + |h| O (as in the Metropolis
+//     kernel; s f = F_site - 2 S) as one byte per slice.  Join bits and S bytes
+//     go to the wave's LDS scratch.
+//  2. one lane per site: the seed slice tau0 = floor(u L / 2^32) and the
+//     acceptance word (counter word 1 = 64); the cluster is the run of joined
+//     bonds through tau0 (ring rotation, trailing and leading ones); with
+//     A = |C| F_site - 2 sum_{tau in C} S_tau the move is accepted when the
+//     acceptance word passes the threshold at A + L F, and the cluster's bits
+//     are flipped.
+// Sites of one class share no term, so their moves commute and every read in
+// phase 1 sees the state left by the previous class.
+
+// Four 6-bit fields (bits 0, 6, 12, 18) moved to the four bytes of a word.
+__device__ __forceinline__ uint32_t fields6_to_bytes(uint32_t a) {
+  return __builtin_amdgcn_ubfe(a, 0, 6) | (__builtin_amdgcn_ubfe(a, 6, 6) << 8) |
+         (__builtin_amdgcn_ubfe(a, 12, 6) << 16) | (__builtin_amdgcn_ubfe(a, 18, 6) << 24);
+}
+
+// Cluster through slice t0 of a ring of L slices whose joined bonds are the
+// bits of jn (bit b: slices b and b+1 mod L; bits L..63 are ignored).
+__device__ __forceinline__ uint64_t ring_cluster(uint64_t jn, int t0, int L) {
+  const uint64_t full = (L == 64) ? ~0ull : ((1ull << L) - 1ull);
+  jn &= full;
+  const uint64_t r = t0 ? (((jn >> t0) | (jn << (L - t0))) & full) : jn;   // bond t0 at bit 0
+  if (r == full) return full;
+  const int f = __builtin_ctzll(~r);                     // joined bonds forward of t0
+  const int g = __builtin_clzll(~(r << (64 - L)));       // joined bonds backward of t0
+  uint64_t cr = (2ull << f) - 1ull;                      // slices t0 .. t0+f
+  if (g) cr |= full ^ (full >> g);                       // slices t0-g .. t0-1
+  return t0 ? (((cr << t0) | (cr >> (L - t0))) & full) : cr;
+}
+
+template <int KIND>
+__device__ __forceinline__ void wolff_bonds(const HandleDev &H, const uint32_t *__restrict__ rec, const uint64_t *lat,
+                                            uint32_t *scr, int c, uint32_t m, uint32_t c3, uint32_t padd, int lane) {
+  using S = Site<KIND>;
+  const int L = H.L;
+  const int Q = (L + 7) >> 3;
+  const int lo = H.cls[c];
+  const int nc = H.cls[c + 1] - lo;
+  if (nc <= 0) return;
+  const int cnt = nc * Q;
+  const uint8_t *latb = reinterpret_cast<const uint8_t *>(lat);
+  uint8_t *jb = reinterpret_cast<uint8_t *>(scr);        // [nc] 64-bit join masks
+  uint32_t *sb = scr + 2 * nc;                            // [16][nc] S bytes of slices 4i..4i+3
+  const int dq = 64 / nc, dr = 64 - dq * nc;
+  int q = lane / nc;
+  int j = lane - q * nc;
+  for (int it = lane; it < cnt; it += 64, j += dr, q += dq) {
+    if (j >= nc) { j -= nc; q += 1; }
+    const int d = lo + j;
+    const uint32_t *r = rec + d * S::RW;
+    uint32_t site, wts, hw, neg;
+    uint32_t poff[S::T * S::P];
+    if constexpr (KIND == kKindME) {
+      const uint4 r0 = *reinterpret_cast<const uint4 *>(r);
+      site = r0.x & 0xFFFFu;
+      wts = r0.y & 0xFFFFFFu;
+      hw = r0.y >> 24;
+      neg = r0.z & 0xFFu;
+      poff[0] = r0.z >> 16; poff[1] = r0.w & 0xFFFFu; poff[2] = r0.w >> 16;
+    } else {
+      const uint4 r0 = *reinterpret_cast<const uint4 *>(r);
+      const uint4 r1 = *reinterpret_cast<const uint4 *>(r + 4);
+      const uint2 r2 = *reinterpret_cast<const uint2 *>(r + 8);
+      site = r0.x & 0xFFFFu;
+      wts = r0.y;
+      hw = r0.z & 0xFFu;
+      neg = (r0.z >> 8) & 0xFFu;
+      const uint32_t pw[6] = {r1.x, r1.y, r1.z, r1.w, r2.x, r2.y};
+#pragma unroll
+      for (int x = 0; x < 6; ++x) {
+        poff[2 * x] = pw[x] & 0xFFFFu;
+        poff[2 * x + 1] = pw[x] >> 16;
+      }
+    }
+    const uint64_t w = lat[d];
+    const int sh = 8 * q;
+    const uint32_t own = static_cast<uint32_t>(w >> sh) & 0xFFu;
+    // bit tau of nx: the spin of slice tau + 1 (mod L)
+    const uint64_t nx = (w >> 1) | ((w & 1ull) << (L - 1));
+    const uint32_t nb = static_cast<uint32_t>(nx >> sh) & 0xFFu;
+    const uint32_t valid = (L - sh >= 8) ? 0xFFu : ((1u << (L - sh)) - 1u);
+    const uint32_t eq = ~(own ^ nb) & valid;
+
+    const Words4 u0 = philox4x32_10(site, static_cast<uint32_t>(2 * q), m, c3, H.seed_lo, H.seed_hi);
+    const Words4 u1 = philox4x32_10(site, static_cast<uint32_t>(2 * q + 1), m, c3, H.seed_lo, H.seed_hi);
+    uint32_t join = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (min(u0.v[k], 0xFFFFFFFEu) < padd) join |= 1u << k;
+      if (min(u1.v[k], 0xFFFFFFFEu) < padd) join |= 16u << k;
+    }
+    jb[8 * j + q] = static_cast<uint8_t>(join & eq);
+
+    // S of slices 8q..8q+3 (acc_lo) and 8q+4..8q+7 (acc_hi) in 6-bit fields; the
+    // 24-bit multiplies need both operands below 2^24, which fields at bits
+    // 0/6/12/18 keep (S <= 63 fits a field).  Repacked to bytes for the store.
+    const uint32_t negh = 0u - ((neg >> 4) & 1u);
+    const uint8_t *lb = latb + q;
+    const uint32_t ox = (own ^ negh) & 0xFFu;
+    uint32_t acc_lo = __umul24(spread6(__builtin_amdgcn_ubfe(ox, 0, 4)), hw);
+    uint32_t acc_hi = __umul24(spread6(__builtin_amdgcn_ubfe(ox, 4, 4)), hw);
+#pragma unroll
+    for (int t = 0; t < S::T; ++t) {
+      uint32_t prod = own;
+#pragma unroll
+      for (int x = 0; x < S::P; ++x) prod ^= lb[poff[S::P * t + x]];
+      const uint32_t xt = prod ^ (0u - ((neg >> t) & 1u));
+      const uint32_t wt = (wts >> (8 * t)) & 0xFFu;
+      acc_lo += __umul24(spread6(__builtin_amdgcn_ubfe(xt, 0, 4)), wt);
+      acc_hi += __umul24(spread6(__builtin_amdgcn_ubfe(xt, 4, 4)), wt);
+    }
+    sb[(2 * q) * nc + j] = fields6_to_bytes(acc_lo);
+    sb[(2 * q + 1) * nc + j] = fields6_to_bytes(acc_hi);
+  }
+}
+
+template <int KIND>
+__device__ __forceinline__ void wolff_flips(const HandleDev &H, const uint32_t *__restrict__ rec, uint64_t *lat,
+                                            const uint32_t *scr, int c, uint32_t m, uint32_t c3,
+                                            const uint32_t *arow, int lane) {
+  using S = Site<KIND>;
+  const int L = H.L;
+  const int lo = H.cls[c];
+  const int nc = H.cls[c + 1] - lo;
+  const int words = (L + 3) >> 2;
+  const uint64_t *jw = reinterpret_cast<const uint64_t *>(scr);
+  const uint32_t *sb = scr + 2 * nc;
+  for (int j = lane; j < nc; j += 64) {
+    const int d = lo + j;
+    const uint4 r0 = *reinterpret_cast<const uint4 *>(rec + d * S::RW);
+    const uint32_t site = r0.x & 0xFFFFu;
+    // F_site = |h| + sum |w_t|: the bytes of record word 1 (and, for LHZ, |h|)
+    const uint32_t fs = (KIND == kKindME) ? __builtin_amdgcn_sad_u8(r0.y, 0u, 0u)
+                                          : __builtin_amdgcn_sad_u8(r0.y, 0u, r0.z & 0xFFu);
+    const Words4 u = philox4x32_10(site, kWolffSiteCtr, m, c3, H.seed_lo, H.seed_hi);
+    const int t0 = static_cast<int>(__umulhi(u.v[0], static_cast<uint32_t>(L)));
+    const uint64_t cl = ring_cluster(jw[j], t0, L);
+    uint32_t ssum = 0;
+    for (int i = 0; i < words; ++i)
+      ssum = __builtin_amdgcn_udot4(sb[i * nc + j], spread8(static_cast<uint32_t>(cl >> (4 * i))), ssum, false);
+    const int a = __popcll(cl) * static_cast<int>(fs) - 2 * static_cast<int>(ssum);
+    if (min(u.v[1], 0xFFFFFFFEu) < arow[a]) lat[d] ^= cl;
+  }
+}
+
+template <int KIND>
+__device__ __forceinline__ void wolff_replica(const HandleDev &H, const uint32_t *rec, uint64_t *lat, uint32_t *scr,
+                                              int rep, int lane) {
+  if (H.flags & kFlagInit) init_lattice<true>(H, lat, rep, lane);
+  else load_lattice<true>(H, lat, rep, lane);
+  wave_sync();
+  const uint32_t c3 = (kStreamWolff << 24) | static_cast<uint32_t>(rep);
+  for (int m = H.m0; m < H.m1; ++m) {
+    const uint32_t padd = H.table[m];
+    const uint32_t *arow = H.wacc + static_cast<size_t>(H.wrows > 1 ? m : 0) * H.wwidth + H.L * H.F;
+    for (int c = 0; c < 4; ++c) {
+      wolff_bonds<KIND>(H, rec, lat, scr, c, static_cast<uint32_t>(m), c3, padd, lane);
+      wave_sync();
+      wolff_flips<KIND>(H, rec, lat, scr, c, static_cast<uint32_t>(m), c3, arow, lane);
+      wave_sync();
+    }
+  }
+  store_lattice<true>(H, lat, rep, lane);
+  if (H.flags & kFlagEnergy) slice_energies<true>(H, lat, rep, lane);
+  wave_sync();
+}
+
+// Persistent kernels, one per move type (each keeps its own register budget):
+// each workgroup repeatedly takes the next work item (handle, replica group)
+// from `counter`, stages the handle's site records in LDS, and runs one
+// replica per wavefront through sweeps m0..m1-1.
+// Dynamic LDS: [rec_cap words][waves x lat_cap u64][waves x tab_cap words]
+// (tab: the Metropolis table row, or the Wolff phase scratch).
 #ifndef SQA_WAVES_PER_EU
 #define SQA_WAVES_PER_EU 1
 #endif
+template <int MOVE>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(SQA_WAVES_PER_EU, 8))) void sqa_anneal_kernel(const HandleDev *__restrict__ hds,
                                                          const WorkItem *__restrict__ items, int n_items,
                                                          int *__restrict__ counter, int rec_cap,
@@ -299,8 +484,13 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(SQA_WAVES_P
     for (int i = threadIdx.x; i < nwords; i += blockDim.x) rec[i] = H.rec[i];
     __syncthreads();
     if (wave < wi.nrep) {
-      if (H.kind == kKindME) anneal_replica<kKindME>(H, rec, lat, tab, wi.rep0 + wave, lane);
-      else anneal_replica<kKindLHZ>(H, rec, lat, tab, wi.rep0 + wave, lane);
+      if constexpr (MOVE == kMoveWolff) {
+        if (H.kind == kKindME) wolff_replica<kKindME>(H, rec, lat, tab, wi.rep0 + wave, lane);
+        else wolff_replica<kKindLHZ>(H, rec, lat, tab, wi.rep0 + wave, lane);
+      } else {
+        if (H.kind == kKindME) anneal_replica<kKindME>(H, rec, lat, tab, wi.rep0 + wave, lane);
+        else anneal_replica<kKindLHZ>(H, rec, lat, tab, wi.rep0 + wave, lane);
+      }
     }
     __syncthreads();
   }
@@ -366,7 +556,7 @@ __global__ void me_majority_kernel(const int8_t *__restrict__ spins, int N, int 
 }
 
 // ----------------------------------------------------------- host launchers
-hipError_t launch_sqa_anneal(const HandleDev *hds, const WorkItem *items, int n_items, int *counter,
+hipError_t launch_sqa_anneal(int move, const HandleDev *hds, const WorkItem *items, int n_items, int *counter,
                              int grid, int waves, int rec_cap, int lat_cap, int tab_cap,
                              hipStream_t stream) {
   const size_t lds = (static_cast<size_t>(rec_cap) + 2ull * waves * lat_cap + static_cast<size_t>(waves) * tab_cap) * 4;
@@ -374,15 +564,24 @@ hipError_t launch_sqa_anneal(const HandleDev *hds, const WorkItem *items, int n_
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, stream, counter);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(sqa_anneal_kernel, dim3(grid), dim3(64 * waves), lds, stream, hds, items, n_items, counter,
-                     rec_cap, lat_cap, tab_cap);
+  if (move == kMoveWolff)
+    hipLaunchKernelGGL(sqa_anneal_kernel<kMoveWolff>, dim3(grid), dim3(64 * waves), lds, stream, hds, items, n_items,
+                       counter, rec_cap, lat_cap, tab_cap);
+  else
+    hipLaunchKernelGGL(sqa_anneal_kernel<kMoveMetropolis>, dim3(grid), dim3(64 * waves), lds, stream, hds, items,
+                       n_items, counter, rec_cap, lat_cap, tab_cap);
   return hipGetLastError();
 }
 
 // Resident workgroups of `waves` waves per compute unit for the given dynamic LDS.
-int sqa_anneal_occupancy(int waves, size_t lds_bytes) {
+int sqa_anneal_occupancy(int move, int waves, size_t lds_bytes) {
   int blocks = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, sqa_anneal_kernel, 64 * waves, lds_bytes) != hipSuccess) {
+  hipError_t e = (move == kMoveWolff)
+                     ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, sqa_anneal_kernel<kMoveWolff>, 64 * waves,
+                                                                    lds_bytes)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, sqa_anneal_kernel<kMoveMetropolis>,
+                                                                    64 * waves, lds_bytes);
+  if (e != hipSuccess) {
     (void)hipGetLastError();
     return 0;
   }
@@ -390,8 +589,11 @@ int sqa_anneal_occupancy(int waves, size_t lds_bytes) {
 }
 
 hipError_t set_sqa_anneal_lds_limit(size_t bytes) {
-  return hipFuncSetAttribute(reinterpret_cast<const void *>(sqa_anneal_kernel),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(sqa_anneal_kernel<kMoveMetropolis>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
+  hipError_t e2 = hipFuncSetAttribute(reinterpret_cast<const void *>(sqa_anneal_kernel<kMoveWolff>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
+  return e != hipSuccess ? e : e2;
 }
 
 hipError_t launch_sqa_init(const HandleDev &H, hipStream_t stream) {

@@ -20,6 +20,7 @@ SQA_OK, SQA_ERR_INVALID, SQA_ERR_OOM, SQA_ERR_DEVICE, SQA_ERR_UNSUPPORTED, SQA_E
     0, -1, -2, -3, -4, -5, -6
 SQA_EMB_ME, SQA_EMB_LHZ = 0, 1
 SQA_DEC_ME_MAJORITY, SQA_DEC_LHZ_TREES, SQA_DEC_LHZ_MWD = 0, 1, 2
+SQA_MOVE_METROPOLIS, SQA_MOVE_WOLFF = 0, 1
 
 
 class SqaError(RuntimeError):
@@ -39,7 +40,8 @@ class sqa_embedding(C.Structure):
 class sqa_schedule(C.Structure):
     _fields_ = [("beta", C.c_double), ("slices", C.c_int32), ("sweeps", C.c_int32), ("replicas", C.c_int32),
                 ("gamma_start", C.c_double), ("gamma_end", C.c_double),
-                ("gamma", C.POINTER(C.c_double)), ("bscale", C.POINTER(C.c_double)), ("seed", C.c_uint64)]
+                ("gamma", C.POINTER(C.c_double)), ("bscale", C.POINTER(C.c_double)), ("seed", C.c_uint64),
+                ("move", C.c_int32)]
 
 
 class sqa_launch_config(C.Structure):
@@ -68,6 +70,8 @@ _SIGS = {
     "sqa_decode": (C.c_int, [_VP, C.c_int32, C.c_int32, _VP, C.c_int32, _VP, _VP]),
     "sqa_random_trees": (C.c_int, [C.c_uint64, C.c_int32, C.c_int32, _VP]),
     "sqa_export_table": (C.c_int, [_VP, _VP, C.c_size_t, C.POINTER(C.c_int32)]),
+    "sqa_export_wolff_tables": (C.c_int, [_VP, _VP, C.c_size_t, _VP, C.c_size_t, C.POINTER(C.c_int32),
+                                          C.POINTER(C.c_int32)]),
     "sqa_physical_sites": (C.c_int64, [C.c_int32, C.c_int32]),
     "sqa_handle_info": (C.c_int, [_VP] + [C.POINTER(C.c_int32)] * 5),
     "sqa_destroy": (None, [_VP]),
@@ -144,18 +148,19 @@ class SQA:
     """One problem x embedding x schedule on the GPU (sqa_create / sqa_destroy)."""
 
     def __init__(self, kind: int, J, penalty: int, beta: float, slices: int, sweeps: int, replicas: int,
-                 gamma_start: float, gamma_end: float, seed: int, h=None, gamma=None, bscale=None):
+                 gamma_start: float, gamma_end: float, seed: int, h=None, gamma=None, bscale=None,
+                 move: int = SQA_MOVE_METROPOLIS):
         prob, self._keep = make_problem(J, h)
         g = None if gamma is None else np.ascontiguousarray(gamma, dtype=np.float64)
         b = None if bscale is None else np.ascontiguousarray(bscale, dtype=np.float64)
         sched = sqa_schedule(beta, slices, sweeps, replicas, gamma_start, gamma_end,
                              g.ctypes.data_as(C.POINTER(C.c_double)) if g is not None else None,
-                             b.ctypes.data_as(C.POINTER(C.c_double)) if b is not None else None, seed)
+                             b.ctypes.data_as(C.POINTER(C.c_double)) if b is not None else None, seed, move)
         emb = sqa_embedding(kind, penalty)
         out = C.c_void_p()
         _check(lib().sqa_create(C.byref(prob), C.byref(emb), C.byref(sched), C.byref(out)))
         self.h = out
-        self.kind, self.N = kind, int(np.asarray(J).shape[0])
+        self.kind, self.N, self.move = kind, int(np.asarray(J).shape[0]), move
         vals = [C.c_int32() for _ in range(5)]
         _check(lib().sqa_handle_info(self.h, *[C.byref(v) for v in vals]))
         self.sites, self.slices, self.replicas, self.sweeps, self.fmax = [v.value for v in vals]
@@ -205,6 +210,16 @@ class SQA:
         out = np.empty((self.sweeps, 2 * F.value + 1, 3), dtype=np.uint32)
         _check(lib().sqa_export_table(self.h, _ptr(out), out.size, C.byref(F)))
         return out
+
+    def wolff_tables(self):
+        """(join thresholds [sweeps], acceptance thresholds [rows][2 L F + 1]) of a Wolff handle."""
+        rows, width = C.c_int32(), C.c_int32()
+        _check(lib().sqa_export_wolff_tables(self.h, None, 0, None, 0, C.byref(rows), C.byref(width)))
+        padd = np.empty(self.sweeps, dtype=np.uint32)
+        acc = np.empty((rows.value, width.value), dtype=np.uint32)
+        _check(lib().sqa_export_wolff_tables(self.h, _ptr(padd), padd.size, _ptr(acc), acc.size, C.byref(rows),
+                                             C.byref(width)))
+        return padd, acc
 
     def decode(self, decoder: int, readout_slice: int = 0, trees=None):
         logical = np.empty((self.replicas, self.N), dtype=np.int8)
@@ -327,10 +342,11 @@ class Server:
         self.s = out
         self._keep = {}
 
-    def submit(self, kind, J, penalty, beta, slices, sweeps, replicas, gamma_start, gamma_end, seed, h=None) -> int:
+    def submit(self, kind, J, penalty, beta, slices, sweeps, replicas, gamma_start, gamma_end, seed, h=None,
+               move: int = SQA_MOVE_METROPOLIS) -> int:
         prob, keep = make_problem(J, h)
         emb = sqa_embedding(kind, penalty)
-        sched = sqa_schedule(beta, slices, sweeps, replicas, gamma_start, gamma_end, None, None, seed)
+        sched = sqa_schedule(beta, slices, sweeps, replicas, gamma_start, gamma_end, None, None, seed, move)
         t = C.c_uint64()
         _check(lib().sqa_server_submit(self.s, C.byref(prob), C.byref(emb), C.byref(sched), C.byref(t)))
         n = sqa_physical_sites(kind, int(np.asarray(J).shape[0]))

@@ -1,0 +1,204 @@
+"""GPU parity of SQA with time-like Wolff cluster moves (Sec. III) against the
+CPU oracle: bit-exact spins and energies, tables equal entry by entry."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1603_03755_amd.workloads import LHZ, ME, batch_jobs, single_job, sk_instance
+
+pytestmark = pytest.mark.gpu
+NTH = 8
+
+
+@pytest.fixture(scope="module")
+def sqa():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1603_03755_amd import sqa as s
+    s.lib()
+    return s
+
+
+def _run_both(sqa, kind, J, pen, beta, L, M, R, g0, g1, seed, h=None, gamma=None, bscale=None):
+    print(f"wolff case kind={kind} N={J.shape[0]} L={L} M={M} R={R} seed={seed}", flush=True)
+    dev = sqa.SQA(kind, J, pen, beta, L, M, R, g0, g1, seed, h=h, gamma=gamma, bscale=bscale,
+                  move=sqa.SQA_MOVE_WOLFF)
+    emb, (padd, acc), ospins, oE = O.sqa_anneal_wolff(kind, J, pen, beta, L, M, R, g0, g1, seed, h=h, gamma=gamma,
+                                                      bscale=bscale, nthreads=NTH)
+    dpadd, dacc = dev.wolff_tables()
+    assert (dpadd == padd).all(), "join thresholds differ"
+    assert dacc.shape == acc.shape and (dacc == acc).all(), "acceptance thresholds differ"
+    dev.anneal()
+    return dev, emb, ospins, oE
+
+
+@pytest.mark.parametrize("kind", [ME, LHZ])
+def test_single_instance_workload_bit_exact(sqa, kind):
+    """N = 8, L = 32, 16 replicas, 1000 sweeps, beta = 10, Gamma 3 -> 0.01, Wolff moves."""
+    j = single_job(kind)
+    dev, emb, ospins, oE = _run_both(sqa, kind, j.J, j.penalty, j.beta, j.slices, j.sweeps, j.replicas,
+                                     j.gamma0, j.gamma1, j.seed)
+    assert (dev.spins() == ospins).all()
+    assert (dev.energies() == oE).all()
+
+
+CASES = [
+    # kind, N, L, M, R, note
+    (ME, 2, 4, 30, 3, "two chains of one spin, empty colour classes"),
+    (ME, 3, 2, 40, 5, "L=2: two bonds between the same two slices"),
+    (LHZ, 3, 1, 50, 4, "L=1: no bonds, classical Metropolis"),
+    (LHZ, 4, 6, 40, 2, "L not a multiple of 8"),
+    (ME, 5, 10, 25, 7, "ragged last byte, odd replica count"),
+    (LHZ, 7, 64, 20, 6, "L=64, full words"),
+    (ME, 9, 16, 20, 9, "odd N"),
+    (LHZ, 12, 62, 10, 3, "L=62"),
+    (ME, 24, 64, 3, 2, "largest batched ME lattice, 144-site colour classes"),
+    (LHZ, 32, 64, 3, 2, "N=32 LHZ"),
+]
+
+
+@pytest.mark.parametrize("kind,N,L,M,R,note", CASES)
+def test_edge_shapes_bit_exact(sqa, kind, N, L, M, R, note):
+    J = sk_instance(N, 300 + N)
+    dev, emb, ospins, oE = _run_both(sqa, kind, J, -2, 6.0, L, M, R, 2.5, 0.05, 0xC0FFEE + N)
+    assert (dev.spins() == ospins).all(), note
+    assert (dev.energies() == oE).all(), note
+
+
+@pytest.mark.parametrize("g_last", [0.0, 50.0])
+def test_fields_weights_bscale_and_extreme_gamma(sqa, g_last):
+    """ME with logical fields, a strong penalty, mixed-sign J, per-sweep B rows, and a
+    Gamma schedule ending at 0 (every aligned bond joins: whole-ring clusters) or at
+    a large value (no bond joins: single-slice clusters)."""
+    rng = np.random.default_rng(5)
+    N, L, M, R = 6, 8, 30, 4
+    J = sk_instance(N, 77, values=(-3, -1, 1, 2))
+    h = rng.integers(-3, 4, N).astype(np.int32)
+    gamma = np.linspace(2.0, g_last, M)
+    bscale = np.linspace(0.2, 1.5, M)
+    dev, emb, ospins, oE = _run_both(sqa, ME, J, -5, 3.0, L, M, R, 0, 0, 99, h=h, gamma=gamma, bscale=bscale)
+    assert (dev.spins() == ospins).all()
+    assert (dev.energies() == oE).all()
+
+
+def test_large_field_sums(sqa):
+    """Weights up to 9 and penalty 9: per-site field sums near the 63 limit, so the
+    per-slice byte sums and the cluster sum reach their largest values."""
+    J = sk_instance(8, 12, values=(-9, -5, 5, 9))
+    dev, emb, ospins, oE = _run_both(sqa, LHZ, J, -9, 0.3, 16, 40, 4, 3.0, 0.01, 7)
+    assert emb.fmax > 30
+    assert (dev.spins() == ospins).all()
+    assert (dev.energies() == oE).all()
+
+
+def test_resume_and_checkpoint_are_bit_identical(sqa):
+    J = sk_instance(8, 4)
+    args = (LHZ, J, -2, 10.0, 32, 60, 8, 3.0, 0.01, 5)
+    full = sqa.SQA(*args, move=sqa.SQA_MOVE_WOLFF).anneal()
+    part = sqa.SQA(*args, move=sqa.SQA_MOVE_WOLFF)
+    part.anneal_range(0, 17)
+    mid = part.spins()
+    part.anneal_range(17, 41)
+    part.write_spins(part.spins())
+    part.anneal_range(41, 60)
+    assert (part.spins() == full.spins()).all()
+    assert (part.energies() == full.energies()).all()
+    emb = O.Embedding(LHZ, J, -2)
+    padd, acc = O.wolff_tables(10.0, 32, O.gamma_schedule(3.0, 0.01, 60), emb.fmax)
+    ref = O.sqa_init(emb, 32, 8, 5)
+    O.wolff_run(emb, 32, ref, 0, 17, padd, acc, 5)
+    assert (mid == ref).all()
+
+
+def test_moves_differ_and_metropolis_table_export_rejected(sqa):
+    J = sk_instance(6, 2)
+    met = sqa.SQA(ME, J, -2, 5.0, 8, 20, 4, 3.0, 0.01, 9).anneal()
+    wol = sqa.SQA(ME, J, -2, 5.0, 8, 20, 4, 3.0, 0.01, 9, move=sqa.SQA_MOVE_WOLFF).anneal()
+    assert (met.spins() != wol.spins()).any()
+    with pytest.raises(sqa.SqaError):
+        wol.table()
+    with pytest.raises(sqa.SqaError):
+        met.wolff_tables()
+    with pytest.raises(sqa.SqaError) as e:
+        sqa.SQA(ME, J, -2, 5.0, 8, 20, 4, 3.0, 0.01, 9, move=7)
+    assert e.value.status == sqa.SQA_ERR_INVALID
+
+
+def _mixed_specs():
+    out = []
+    for i, (kind, N, L, M, R) in enumerate([(ME, 6, 16, 40, 5), (LHZ, 7, 64, 30, 9), (ME, 4, 2, 50, 3),
+                                            (LHZ, 5, 10, 35, 12), (ME, 8, 64, 20, 17), (LHZ, 3, 1, 60, 2)]):
+        out.append(dict(kind=kind, J=sk_instance(N, 500 + i), L=L, M=M, R=R, seed=900 + i, wolff=(i % 2 == 0)))
+    return out
+
+
+@pytest.mark.parametrize("waves", [1, 4, 8])
+def test_batch_mixing_moves_equals_oracle(sqa, waves):
+    """One batch holding Metropolis and Wolff handles (one persistent launch per move,
+    both captured in one graph, replayed twice): every handle equals its oracle."""
+    specs = _mixed_specs()
+    hs = [sqa.SQA(s["kind"], s["J"], -2, 6.0, s["L"], s["M"], s["R"], 2.0, 0.05, s["seed"],
+                  move=sqa.SQA_MOVE_WOLFF if s["wolff"] else sqa.SQA_MOVE_METROPOLIS) for s in specs]
+    b = sqa.Batch(hs, waves_per_group=waves)
+    for replay in range(2):
+        b.run()
+        hs[0].sync()
+        for h, s in zip(hs, specs):
+            if s["wolff"]:
+                _, _, ospins, oE = O.sqa_anneal_wolff(s["kind"], s["J"], -2, 6.0, s["L"], s["M"], s["R"], 2.0, 0.05,
+                                                      s["seed"], nthreads=NTH)
+            else:
+                _, _, ospins, oE = O.sqa_anneal(s["kind"], s["J"], -2, 6.0, s["L"], s["M"], s["R"], 2.0, 0.05,
+                                                s["seed"], nthreads=NTH)
+            assert (h.spins() == ospins).all(), (replay, s["kind"], s["L"], s["wolff"])
+            assert (h.energies() == oE).all()
+    b.close()
+
+
+def test_server_runs_wolff_jobs(sqa):
+    specs = _mixed_specs()
+    srv = sqa.Server(hbm_budget_bytes=4 << 20, max_slots=3, chunk_sweeps=11)
+    tickets = [srv.submit(s["kind"], s["J"], -2, 6.0, s["L"], s["M"], s["R"], 2.0, 0.05, s["seed"],
+                          move=sqa.SQA_MOVE_WOLFF if s["wolff"] else sqa.SQA_MOVE_METROPOLIS) for s in specs]
+    for t, s in zip(tickets, specs):
+        srv.wait(t, 120_000)
+        spins, E, _ = srv.result(t)
+        run = O.sqa_anneal_wolff if s["wolff"] else O.sqa_anneal
+        _, _, ospins, oE = run(s["kind"], s["J"], -2, 6.0, s["L"], s["M"], s["R"], 2.0, 0.05, s["seed"], nthreads=NTH)
+        assert (spins == ospins).all() and (E == oE).all()
+    srv.close()
+
+
+def test_full_size_batched_workload_sampled(sqa):
+    """The 512-instance batch (64 replicas, L = 64, 10^4 sweeps, N in 12..24) with Wolff
+    moves in one persistent launch: one sampled replica of every (embedding, N)
+    stratum equals the oracle; every replica's energies equal its spins' energies."""
+    jobs = batch_jobs()
+    hs = [sqa.SQA(j.kind, j.J, j.penalty, j.beta, j.slices, j.sweeps, j.replicas, j.gamma0, j.gamma1, j.seed,
+                  move=sqa.SQA_MOVE_WOLFF) for j in jobs]
+    print("full-size Wolff batch: 512 handles, running", flush=True)
+    b = sqa.Batch(hs)
+    b.run()
+    hs[0].sync()
+    print("full-size Wolff batch done, checking samples", flush=True)
+    seen = {}
+    rng = np.random.default_rng(1)
+    for i, j in enumerate(jobs):
+        if (j.kind, j.n) not in seen:
+            seen[(j.kind, j.n)] = (i, int(rng.integers(0, j.replicas)))
+    from concurrent.futures import ThreadPoolExecutor
+
+    def oracle_replica(ir):
+        i, r = ir
+        j = jobs[i]
+        return O.sqa_anneal_wolff(j.kind, j.J, j.penalty, j.beta, j.slices, j.sweeps, 1, j.gamma0, j.gamma1, j.seed,
+                                  nthreads=1, r0=r)
+
+    with ThreadPoolExecutor(max_workers=8) as ex:
+        refs = list(ex.map(oracle_replica, seen.values()))
+    for (i, r), (emb, _, ospins, oE) in zip(seen.values(), refs):
+        spins, E = hs[i].spins(), hs[i].energies()
+        assert (spins[r] == ospins[0]).all(), (i, r)
+        assert (E[r] == oE[0]).all(), (i, r)
+        assert (O.sqa_energies(emb, spins) == E).all()
+    b.close()
