@@ -11,8 +11,12 @@ from a HIP graph) and majority-vote decoding of the ME replicas.  Inputs
 
 Prints one JSON line.  Also reports the same instances launched one per
 instance (at a reduced sweep count, both ways), serving latency percentiles on
-a short Poisson job stream, the roofline of the sweep kernel and the CPU
-oracle on a bounded sample of the workload.
+a short Poisson job stream, parallel tempering, the same batch with the
+paper's time-like Wolff cluster moves, the roofline of the sweep kernels and
+the CPU oracle on a bounded sample of the workload.
+
+`--copy-calibration` instead runs only a cold 2 GiB device-to-device copy, the
+reference for scaling the FETCH_SIZE / WRITE_SIZE counters to bytes.
 """
 from __future__ import annotations
 
@@ -34,22 +38,29 @@ PEAK_LANE_OPS = 157.3e12 / 2
 # 4 full-rate slots at quarter rate, + 2 three-input XORs) / 4 words.
 PHILOX_OPS_PER_WORD = 10 * (2 * 4 + 2) / 4
 DECISION_OPS = 4.0   # compare + select of the Metropolis test, time-neighbour term, table index
+# Wolff moves, per site-slice: bond test (equality, compare, select) and the masked cluster sum;
+# per site and sweep, amortised over the L slices: one Philox call (seed slice and acceptance
+# words), the run search on the ring and the acceptance decision.
+WOLFF_BOND_OPS = 4.0
+WOLFF_SITE_OPS = 4 * PHILOX_OPS_PER_WORD + 24.0
 
 # HBM bytes of one launch of the sweep kernel on this workload, from rocprofv3 --pmc FETCH_SIZE and
 # WRITE_SIZE passes (KiB per dispatch) scaled by the same counters on a cold 2 GiB copy
 # (profiles/sqa_anneal_kernel_batched512_L64.md).  Valid only for the kernel source it was taken on.
-TRAFFIC_PROFILE = {"kernel_sha256_prefix": "f9c1e5834a3d0d9e", "instances": 512, "sweeps": 10_000,
-                   "fetch_kib": 2215810.125, "write_kib": 775656.8125, "fetch_scale": 2.0, "write_scale": 1.0}
+TRAFFIC_PROFILE = {"kernel_sha256_prefix": "fb423641500161f0", "instances": 512, "sweeps": 10_000,
+                   "fetch_kib": 1422210.0, "write_kib": 509296.0, "fetch_scale": 2.0, "write_scale": 1.0,
+                   "wolff_fetch_kib": 24338.6, "wolff_write_kib": 509200.0}
 
 
-def measured_traffic(args):
+def measured_traffic(args, wolff=False):
     import hashlib
     src = os.path.join(ROOT, "paper_1603_03755_amd", "csrc", "sqa_kernels.hip")
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     t = TRAFFIC_PROFILE
     if not sha.startswith(t["kernel_sha256_prefix"]) or args.instances != t["instances"] or args.sweeps != t["sweeps"]:
         return None
-    return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024
+    f, w = (t["wolff_fetch_kib"], t["wolff_write_kib"]) if wolff else (t["fetch_kib"], t["write_kib"])
+    return (f * t["fetch_scale"] + w * t["write_scale"]) * 1024
 
 
 def parse():
@@ -60,6 +71,10 @@ def parse():
     ap.add_argument("--instances", type=int, default=512)
     ap.add_argument("--sweeps", type=int, default=10_000)
     ap.add_argument("--no-extras", action="store_true", help="only the timed batched steps")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 2 GiB device to device, source evicted from the last-level cache first")
+    ap.add_argument("--legs", default="per_instance,serving,pt,wolff,cpu",
+                    help="comma list of the extra legs to run after the timed steps")
     ap.add_argument("--cpu-replicas", type=int, default=2, help="oracle lattices per stratum for cpu_baseline")
     ap.add_argument("--pt-sweeps", type=int, default=10_000, help="sweeps of the parallel-tempering leg")
     return ap.parse_args()
@@ -82,6 +97,76 @@ def algorithmic_ops_per_attempt(jobs, O) -> float:
         tot_ops += seen[key] * w
         tot_w += w
     return tot_ops / tot_w
+
+
+def wolff_ops_per_site_slice(jobs, O) -> float:
+    """Method arithmetic of a Wolff sweep per site-slice (full-rate lane-op slots): the
+    Philox share of the bond word, the local-field terms, the bond test and cluster sum,
+    and the per-site work spread over the ring."""
+    tot_ops, tot_w = 0.0, 0.0
+    seen = {}
+    for j in jobs:
+        key = (j.kind, j.n)
+        if key not in seen:
+            emb = O.Embedding(j.kind, j.J, j.penalty)
+            terms = np.diff(emb.row).astype(float)
+            fields = (emb.h != 0).astype(float)
+            seen[key] = float(np.mean(PHILOX_OPS_PER_WORD + terms + fields + WOLFF_BOND_OPS
+                                      + WOLFF_SITE_OPS / j.slices))
+        w = j.sites * j.slices * j.replicas * j.sweeps
+        tot_ops += seen[key] * w
+        tot_w += w
+    return tot_ops / tot_w
+
+
+def wolff_leg(sqa, O, jobs, stream, metropolis_kernel_s, traffic):
+    """The same batch with the paper's move (one time-like Wolff cluster per site and
+    sweep) in one persistent launch replayed from its graph; kernel time from events on
+    the launch stream; the oracle on one replica lattice per stratum beside it."""
+    import torch
+    from concurrent.futures import ThreadPoolExecutor
+    hs = [sqa.SQA(j.kind, j.J, j.penalty, j.beta, j.slices, j.sweeps, j.replicas, j.gamma0, j.gamma1, j.seed,
+                  move=sqa.SQA_MOVE_WOLFF) for j in jobs]
+    b = sqa.Batch(hs)
+    waves, gpc = b.config()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    b.run(stream)
+    stream.synchronize()
+    with torch.cuda.stream(stream):
+        e0.record(stream)
+        b.run(stream)
+        e1.record(stream)
+    stream.synchronize()
+    kernel_s = e0.elapsed_time(e1) / 1e3
+    moves = sum(j.sites * j.replicas * j.sweeps for j in jobs)
+    cells = sum(j.sites * j.slices * j.replicas * j.sweeps for j in jobs)
+    ops = wolff_ops_per_site_slice(jobs, O)
+    b.close()
+    for h in hs:
+        h.close()
+    strata = {}
+    for j in jobs:
+        strata.setdefault((j.kind, j.n), j)
+    sample = list(strata.values())
+
+    def run(j):
+        O.sqa_anneal_wolff(j.kind, j.J, j.penalty, j.beta, j.slices, j.sweeps, 1, j.gamma0, j.gamma1, j.seed,
+                           nthreads=1)
+        return j.sites * j.slices * j.sweeps
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=min(len(sample), os.cpu_count() or 1)) as ex:
+        ocells = sum(ex.map(run, sample))
+    odt = time.perf_counter() - t0
+    return {"kernel": "sqa_anneal_kernel<Wolff>", "kernel_ms": kernel_s * 1e3,
+            "cluster_moves_per_s": moves / kernel_s, "site_slices_per_s": cells / kernel_s,
+            "launch": {"waves_per_group": waves, "groups_per_cu": gpc},
+            "vs_metropolis_sweep_time": metropolis_kernel_s / kernel_s,
+            "roofline": {"bound": "alu", "achieved": ops * cells / kernel_s / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+                         "unit": "TOP/s (32-bit VALU lane-op slots)", "frac": ops * cells / kernel_s / PEAK_LANE_OPS,
+                         "traffic": traffic, "ops_per_site_slice": ops},
+            "oracle": {"site_slices_per_s": ocells / odt, "cores": len(sample),
+                       "sample": f"one replica lattice per embedding x N stratum ({len(sample)}), full schedule"}}
 
 
 def cpu_baseline(jobs, replicas_per_stratum: int = 2):
@@ -130,8 +215,26 @@ def pt_leg(sqa, sweeps: int):
             "attempts_per_s": attempts / dt, "swap_attempts_per_s": swaps / dt, "seconds": dt}
 
 
+def copy_calibration():
+    import torch
+    torch.cuda.set_device(0)
+    n = 2 << 30
+    a = torch.empty(n, dtype=torch.uint8, device="cuda")
+    a.fill_(1)
+    junk = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    junk.fill_(2)            # 1 GiB written after the source: evicts it from the 256 MB last-level cache
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": n}), flush=True)
+
+
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (instances and replicas are "
               f"independent, see DESIGN.md for how the batch would shard).", file=sys.stderr)
@@ -211,7 +314,8 @@ def main():
         "kernel_attempts_per_s": attempts_per_step / kernel_s,
         "setup_s": setup_s,
     }
-    if not args.no_extras:
+    legs = set() if args.no_extras else {x.strip() for x in args.legs.split(",") if x.strip()}
+    if "per_instance" in legs:
         # one launch per instance vs one batched launch, same instances, reduced sweeps
         short = 200
         hs2 = [sqa.SQA(j.kind, j.J, j.penalty, j.beta, j.slices, short, j.replicas, j.gamma0, j.gamma1, j.seed)
@@ -235,6 +339,7 @@ def main():
         b2.close()
         for h in hs2:
             h.close()
+    if "serving" in legs:
         # serving: a Poisson stream of mixed jobs through the continuous-batching server
         stream_jobs = serving_stream(count=48, rate_per_s=12.0)
         srv = sqa.Server(hbm_budget_bytes=64 << 20, max_slots=32, chunk_sweeps=500)
@@ -259,7 +364,11 @@ def main():
                           "p99_latency_s": float(np.percentile(lats, 99)), "jobs_per_s": len(tickets) / span,
                           "attempts_per_s": att3 / span, "launches": launches, "peak_resident_bytes": peak,
                           "budget_bytes": 64 << 20, "arrival_rate_per_s": 12.0}
+    if "pt" in legs:
         out["parallel_tempering"] = pt_leg(sqa, args.pt_sweeps)
+    if "wolff" in legs:
+        out["wolff"] = wolff_leg(sqa, O, jobs, stream, kernel_s, measured_traffic(args, wolff=True))
+    if "cpu" in legs:
         out["cpu_baseline"] = cpu_baseline(jobs, args.cpu_replicas)
     print(json.dumps(out), flush=True)
 
