@@ -384,6 +384,28 @@ def lhz_mwd(N, slice_):
     return out
 
 
+def lhz_bp(N, slice_, parents, error_rate=0.2, iterations=10):
+    """Weight-3 parity-check decoding; returns (logical[N], final pair values[K])."""
+    s = np.ascontiguousarray(slice_, dtype=np.int8)
+    par = _i32(parents).reshape(-1, N)
+    out = np.zeros(N, dtype=np.int8)
+    pairs = np.zeros(N * (N - 1) // 2, dtype=np.int8)
+    lib().oracle_lhz_bp(N, _p(s, C.c_int8), C.c_double(error_rate), iterations, _p(par, C.c_int32), par.shape[0],
+                        _p(out, C.c_int8), _p(pairs, C.c_int8))
+    return out, pairs
+
+
+def lhz_mld(N, slice_, error_rate):
+    """Maximum-likelihood decoding at the Nishimori temperature; returns (logical[N],
+    integer numerators of <sigma_0 sigma_i>)."""
+    assert 3 <= N <= 24
+    s = np.ascontiguousarray(slice_, dtype=np.int8)
+    out = np.zeros(N, dtype=np.int8)
+    corr = np.zeros(N, dtype=np.int64)
+    lib().oracle_lhz_mld(N, _p(s, C.c_int8), C.c_double(error_rate), _p(out, C.c_int8), _p(corr, C.c_int64))
+    return out, corr
+
+
 def ground_states(J, h=None, max_states=64):
     J = _i32(J)
     N = J.shape[0]

@@ -1,6 +1,7 @@
 /*
  * Decoders and exact ground states for the oracle (test infrastructure only).
  */
+#include <math.h>
 #include <stdlib.h>
 #include <string.h>
 #include "oracle.h"
@@ -162,4 +163,92 @@ int32_t oracle_ground_states(int32_t N, const int32_t *J, const int32_t *h,
   *n_found = found;
   free(sig);
   return best;
+}
+
+/* Weight-3 parity-check decoding (Sec. IV D; its settings in Sec. IV E and
+ * Appendix C).  The paper follows an implementation it cites and describes it
+ * only in words: the alignment of each pair (i, j) is updated iteratively by a
+ * majority vote over the N-2 weight-3 checks q_il q_lj (l != i, j), given an
+ * error rate, and one spanning tree then reads the logical state.  Reading:
+ * the vote weighs the pair's own readout s_ij by its log-likelihood ratio
+ * w0 = ln((1-p)/p) and each check by the ratio of a product of two bits,
+ * w1 = ln((1-p2)/p2) with p2 = 2p(1-p); all pairs are updated together from
+ * the previous iteration's values,
+ *   x_ij <- sign(w0 s_ij + w1 sum_l x_il x_lj),  an exact tie keeps s_ij,
+ * starting from x = s; after `iterations` rounds the trees decode x as in
+ * Eq. (5).  0 < p < 1/2.  pairs_out (K entries, LHZ site order) may be NULL. */
+void oracle_lhz_bp(int32_t N, const int8_t *slice, double error_rate, int32_t iterations,
+                   const int32_t *parents, int32_t n_trees, int8_t *logical, int8_t *pairs_out) {
+  int K = N * (N - 1) / 2;
+  double p = error_rate, p2 = 2.0 * p * (1.0 - p);
+  double w0 = log((1.0 - p) / p), w1 = log((1.0 - p2) / p2);
+  int8_t *x = (int8_t *)malloc((size_t)K), *xn = (int8_t *)malloc((size_t)K);
+  memcpy(x, slice, (size_t)K);
+  for (int it = 0; it < iterations; ++it) {
+    for (int i = 0; i < N; ++i)
+      for (int j = i + 1; j < N; ++j) {
+        int c = 0;
+        for (int l = 0; l < N; ++l)
+          if (l != i && l != j) c += x[pair_site(N, i, l)] * x[pair_site(N, l, j)];
+        int k = oracle_lhz_site(N, i, j);
+        double v = w0 * (double)slice[k] + w1 * (double)c;
+        xn[k] = v > 0.0 ? (int8_t)1 : (v < 0.0 ? (int8_t)-1 : slice[k]);
+      }
+    memcpy(x, xn, (size_t)K);
+  }
+  oracle_lhz_tree_decode(N, x, parents, n_trees, logical);
+  if (pairs_out) memcpy(pairs_out, x, (size_t)K);
+  free(x);
+  free(xn);
+}
+
+/* Maximum-likelihood decoding, Sec. IV B, Eq. (11): the thermal average at the
+ * Nishimori inverse temperature beta_N = (1/2) ln((1-p)/p) of the decoding
+ * problem of Eq. (9) in the gauge g = s, P(sigma) ~ exp(beta_N sum_{i<j}
+ * s_ij sigma_i sigma_j).  That law is symmetric under sigma -> -sigma, so the
+ * gauge is fixed by sigma_0 = +1 and qbar_i = sign <sigma_0 sigma_i> (tie ->
+ * +1).  With O = sum s_ij sigma_i sigma_j and O_max its maximum over the states
+ * (the MWD score), every state's weight exp(-beta_N (O_max - O)) is quantised
+ * to round(2^36 exp(-beta_N (O_max - O))) and the averages are summed in 64-bit
+ * integers (exact, independent of summation order); N <= 24 keeps the sums
+ * below 2^63.  corr_out[i] (may be NULL) receives the integer numerator of
+ * <sigma_0 sigma_i>. */
+static int pair_score(int32_t N, const int8_t *slice, const int8_t *sig) {
+  int o = 0;
+  for (int i = 0; i < N; ++i)
+    for (int j = i + 1; j < N; ++j) o += slice[oracle_lhz_site(N, i, j)] * sig[i] * sig[j];
+  return o;
+}
+
+static void candidate(int32_t N, uint64_t m, int8_t *sig) {
+  sig[0] = 1;
+  for (int b = 0; b + 1 < N; ++b) sig[b + 1] = ((m >> b) & 1u) ? (int8_t)-1 : (int8_t)1;
+}
+
+void oracle_lhz_mld(int32_t N, const int8_t *slice, double error_rate, int8_t *logical, int64_t *corr_out) {
+  int K = N * (N - 1) / 2;
+  double beta = 0.5 * log((1.0 - error_rate) / error_rate);
+  int8_t *sig = (int8_t *)malloc((size_t)N);
+  uint64_t count = 1ull << (N - 1);
+  int omax = -K;
+  for (uint64_t m = 0; m < count; ++m) {
+    candidate(N, m, sig);
+    int o = pair_score(N, slice, sig);
+    if (o > omax) omax = o;
+  }
+  uint64_t *w = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(2 * K + 1));
+  for (int d = 0; d <= 2 * K; ++d) w[d] = (uint64_t)llround(ldexp(exp(-beta * (double)d), 36));
+  int64_t *acc = (int64_t *)calloc((size_t)N, sizeof(int64_t));
+  for (uint64_t m = 0; m < count; ++m) {
+    candidate(N, m, sig);
+    int64_t wt = (int64_t)w[omax - pair_score(N, slice, sig)];
+    for (int i = 0; i < N; ++i) acc[i] += sig[i] > 0 ? wt : -wt;
+  }
+  for (int i = 0; i < N; ++i) {
+    logical[i] = acc[i] >= 0 ? (int8_t)1 : (int8_t)-1;
+    if (corr_out) corr_out[i] = acc[i];
+  }
+  free(w);
+  free(acc);
+  free(sig);
 }

@@ -120,6 +120,9 @@ void oracle_lhz_tree_decode(int32_t N, const int8_t *slice, const int32_t *paren
                             int32_t n_trees, int8_t *logical);
 int  oracle_random_trees(uint64_t seed, int32_t N, int32_t n_trees, int32_t *parents);
 void oracle_lhz_mwd(int32_t N, const int8_t *slice, int8_t *logical);
+void oracle_lhz_bp(int32_t N, const int8_t *slice, double error_rate, int32_t iterations,
+                   const int32_t *parents, int32_t n_trees, int8_t *logical, int8_t *pairs_out);
+void oracle_lhz_mld(int32_t N, const int8_t *slice, double error_rate, int8_t *logical, int64_t *corr_out);
 int32_t oracle_ground_states(int32_t N, const int32_t *J, const int32_t *h,
                              int8_t *states, int32_t max_states, int32_t *n_found);
 
