@@ -6,8 +6,10 @@ i embedded as ME (even i) or LHZ (odd i) with N = 12, 16, 20, 24 in turn, 64
 replicas each, L = 64 Trotter slices, 10^4 sweeps, beta = 10, Gamma linear
 3 -> 0.01, penalty -2.  A step is the whole hot path on the device: lattice
 initialisation, all sweeps, per-slice energies (one persistent launch replayed
-from a HIP graph) and majority-vote decoding of the ME replicas.  Inputs
-(tables, site records) are resident in HBM before timing starts.
+from a HIP graph), then decoding of every replica's slice 0 on the device:
+majority vote of the ME chains and exhaustive minimum-weight decoding of the
+LHZ states.  Inputs (tables, site records) are resident in HBM before timing
+starts.
 
 Prints one JSON line.  Also reports the same instances launched one per
 instance (at a reduced sweep count, both ways), serving latency percentiles on
@@ -255,7 +257,7 @@ def main():
     waves, gpc = batch.config()
     setup_s = time.perf_counter() - t_setup
     attempts_per_step = sum(j.attempts for j in jobs)
-    me_handles = [h for h, j in zip(handles, jobs) if j.kind == ME]
+    decoders = [(h, sqa.SQA_DEC_ME_MAJORITY if j.kind == ME else sqa.SQA_DEC_LHZ_MWD) for h, j in zip(handles, jobs)]
 
     stream = torch.cuda.Stream()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
@@ -267,9 +269,9 @@ def main():
             batch.run(stream)
             if timed_kernel:
                 ev[1].record(stream)
+            for h, dec in decoders:
+                h.decode(dec, 0, stream=stream, host=False)
         stream.synchronize()
-        for h in me_handles:
-            h.decode(sqa.SQA_DEC_ME_MAJORITY, 0)
 
     for _ in range(args.warmup):
         step(False)

@@ -162,24 +162,77 @@ SQA_API sqa_status sqa_write_spins(sqa_handle *h, const int8_t *in, size_t len);
 SQA_API void *sqa_device_spins(sqa_handle *h);
 SQA_API void *sqa_device_energies(sqa_handle *h);
 
-/* Decoders, on slice `readout_slice` of every replica.
+/* Decoders, on slice `readout_slice` of every replica; all run on the device.
  *   SQA_DEC_ME_MAJORITY  Eq. (4): qbar_i = sign(sum of chain i), tie -> +1.
- *                        Runs on the device.
  *   SQA_DEC_LHZ_TREES    Eq. (5): majority over n_trees spanning trees given
  *                        as parent arrays tree_parents[n_trees][n] rooted at
  *                        logical spin 0 (parent -1), qbar_0 = +1, tie -> +1.
+ *                        n <= 256.
  *   SQA_DEC_LHZ_MWD      Sec. IV A: the constraint-satisfying state nearest in
- *                        Hamming distance; exact search over 2^(n-1) logical
- *                        states with qbar_0 = +1, ties -> the candidate whose
- *                        bit pattern (bit b set <=> qbar_{b+1} = -1) is smallest.
- * Outputs: logical_out[replica][n] (+1/-1) and logical_energy_out[replica]
- * (Eq. (1) of the decoded state); either may be NULL.  Blocking.
- * Errors: SQA_ERR_INVALID on a decoder/embedding mismatch or bad slice;
- * SQA_ERR_UNSUPPORTED for MWD with n > 30. */
-typedef enum { SQA_DEC_ME_MAJORITY = 0, SQA_DEC_LHZ_TREES = 1, SQA_DEC_LHZ_MWD = 2 } sqa_decoder;
+ *                        Hamming distance; exhaustive search over the 2^(n-1)
+ *                        logical states with qbar_0 = +1, ties -> the candidate
+ *                        whose bit pattern (bit b set <=> qbar_{b+1} = -1) is
+ *                        smallest.  n <= 32.
+ *   SQA_DEC_LHZ_MLD      Sec. IV B, Eq. (11): qbar_i = sign <qbar_0 qbar_i> of the
+ *                        thermal average at the Nishimori inverse temperature
+ *                        beta_N = ln((1-p)/p)/2 of P(sigma) ~ exp(beta_N sum
+ *                        s_ij sigma_i sigma_j), exact over the 2^(n-1) states;
+ *                        Boltzmann weights relative to the best state are
+ *                        quantised to 2^-36 and summed in 64-bit integers.
+ *                        tie -> +1.  n <= 24.  p = error_rate.
+ *   SQA_DEC_LHZ_BP       Sec. IV D: pair values x = s updated `iterations`
+ *                        times, all pairs together, by the weighted vote
+ *                        x_ij <- sign(w0 s_ij + w1 sum_{l != i,j} x_il x_lj),
+ *                        w0 = ln((1-p)/p), w1 = ln((1-p2)/p2), p2 = 2p(1-p),
+ *                        a tie keeps s_ij; then the trees decode x as for
+ *                        SQA_DEC_LHZ_TREES (the paper reads out with one random
+ *                        tree).  n <= 32.
+ * Outputs: logical[replica][n] (+1/-1) and logical energy[replica] (Eq. (1) of
+ * the decoded state).
+ * Errors: SQA_ERR_INVALID on a decoder/embedding mismatch, bad slice, bad
+ * trees, error rate outside (0, 1/2) or negative iterations;
+ * SQA_ERR_UNSUPPORTED above the size limits. */
+typedef enum {
+  SQA_DEC_ME_MAJORITY = 0,
+  SQA_DEC_LHZ_TREES = 1,
+  SQA_DEC_LHZ_MWD = 2,
+  SQA_DEC_LHZ_MLD = 3,
+  SQA_DEC_LHZ_BP = 4
+} sqa_decoder;
+
+typedef struct {
+  int32_t decoder;               /* sqa_decoder */
+  int32_t readout_slice;         /* 0..slices-1 */
+  const int32_t *tree_parents;   /* [n_trees][n], for SQA_DEC_LHZ_TREES and SQA_DEC_LHZ_BP */
+  int32_t n_trees;
+  double error_rate;             /* p of SQA_DEC_LHZ_MLD and SQA_DEC_LHZ_BP */
+  int32_t iterations;            /* rounds of SQA_DEC_LHZ_BP (0 = trees on the raw readout) */
+} sqa_decode_params;
+
+/* Queues the decoder on `stream` after the handle's previous work.  With both
+ * outputs NULL the call returns at once and the results stay in device memory
+ * (sqa_device_logical / sqa_device_logical_energies); otherwise it waits and
+ * copies them to logical_out (len replicas*n) and logical_energy_out (len
+ * replicas).  Decoders that take host tables (trees, MLD, BP) first wait for
+ * the handle's earlier work. */
+SQA_API sqa_status sqa_decode_ex(sqa_handle *h, const sqa_decode_params *params, int8_t *logical_out,
+                         int32_t *logical_energy_out, void *stream);
+
+/* Blocking form on the default stream, with error_rate = 0.2 and 10 iterations
+ * (the paper's BP settings, Sec. IV E). */
 SQA_API sqa_status sqa_decode(sqa_handle *h, int32_t decoder, int32_t readout_slice,
                       const int32_t *tree_parents, int32_t n_trees,
                       int8_t *logical_out, int32_t *logical_energy_out);
+
+/* Device buffers holding the last decode's logical states [replica][n] (int8)
+ * and logical energies [replica] (int32).  Owned by the handle. */
+SQA_API void *sqa_device_logical(sqa_handle *h);
+SQA_API void *sqa_device_logical_energies(sqa_handle *h);
+
+/* Waits for the handle and copies the last decode's logical states (len >=
+ * replicas*n) and logical energies (elen >= replicas); either may be NULL. */
+SQA_API sqa_status sqa_read_logical(sqa_handle *h, int8_t *logical_out, size_t len, int32_t *energy_out,
+                            size_t elen);
 
 /* Uniform random labelled spanning trees of K_n (Pruefer sequences drawn from
  * the Philox TREE stream keyed by `seed`), as parent arrays rooted at 0:

@@ -382,6 +382,7 @@ void sqa_destroy(sqa_handle *h) {
     (void)hipEventDestroy(h->done);
   }
   if (h->arena.base) (void)hipFree(h->arena.base);
+  if (h->dec_buf) (void)hipFree(h->dec_buf);
   if (h->staging) (void)hipHostFree(h->staging);
   delete h;
 }
@@ -543,135 +544,225 @@ sqa_status sqa_export_wolff_tables(sqa_handle *h, uint32_t *padd_out, size_t pad
 }
 
 // ------------------------------------------------------------------ decoders
-static int pair_index(int N, int a, int b) {
-  if (a > b) std::swap(a, b);
-  return a * (2 * N - a - 1) / 2 + (b - a - 1);
+void *sqa_device_logical(sqa_handle *h) { return h ? h->arena.at<void>(h->off_logical) : nullptr; }
+void *sqa_device_logical_energies(sqa_handle *h) { return h ? h->arena.at<void>(h->off_lenergy) : nullptr; }
+
+}  // extern "C"
+
+namespace {
+
+// Device scratch of the LHZ decoders, grown on demand (after the handle's queued
+// work, which may still read the old buffer, has finished).
+sqa_status decode_scratch(sqa_handle *h, size_t bytes) {
+  if (h->dec_bytes >= bytes) return SQA_OK;
+  hipError_t e = hipEventSynchronize(h->done);
+  if (e != hipSuccess) {
+    h->poisoned = true;
+    return hip_fail(e, "hipEventSynchronize");
+  }
+  if (h->dec_buf) (void)hipFree(h->dec_buf);
+  h->dec_buf = nullptr;
+  h->dec_bytes = 0;
+  e = hipMalloc(&h->dec_buf, bytes);
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc (decode scratch)");
+  h->dec_bytes = bytes;
+  return SQA_OK;
 }
 
-static int32_t logical_energy(const sqa_handle *h, const int8_t *q) {
-  int32_t E = 0;
-  const int N = h->N;
-  for (int i = 0; i < N; ++i) {
-    E += h->h[i] * q[i];
-    for (int j = i + 1; j < N; ++j) E += h->J[i * N + j] * q[i] * q[j];
+// Checks parent arrays (trees of K_N rooted at 0) and lists each tree's
+// vertices parents-first (breadth-first from 0).
+sqa_status tree_orders(int N, const int32_t *tree_parents, int n_trees, std::vector<int32_t> *order) {
+  if (!tree_parents || n_trees < 1) return fail(SQA_ERR_INVALID, "tree decoding needs at least one tree");
+  order->assign(static_cast<size_t>(n_trees) * N, 0);
+  std::vector<std::vector<int>> kids(N);
+  for (int t = 0; t < n_trees; ++t) {
+    const int32_t *par = tree_parents + static_cast<size_t>(t) * N;
+    if (par[0] != -1) return fail(SQA_ERR_INVALID, "tree must be rooted at logical spin 0");
+    for (auto &k : kids) k.clear();
+    for (int v = 1; v < N; ++v) {
+      if (par[v] < 0 || par[v] >= N || par[v] == v) return fail(SQA_ERR_INVALID, "bad parent array");
+      kids[par[v]].push_back(v);
+    }
+    int32_t *ord = order->data() + static_cast<size_t>(t) * N;
+    int head = 0, tail = 0;
+    ord[tail++] = 0;
+    while (head < tail) {
+      const int x = ord[head++];
+      for (int y : kids[x])
+        if (tail < N) ord[tail++] = y;
+    }
+    if (tail != N) return fail(SQA_ERR_INVALID, "parent array is not a tree rooted at 0");
   }
-  return E;
+  return SQA_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+extern "C" {
+
+sqa_status sqa_decode_ex(sqa_handle *h, const sqa_decode_params *prm, int8_t *logical_out,
+                         int32_t *logical_energy_out, void *stream) {
+  sqa_status st = check_handle(h);
+  if (st != SQA_OK) return st;
+  if (!prm) return fail(SQA_ERR_INVALID, "null decode parameters");
+  const sqa_decode_params p = *prm;
+  if (p.readout_slice < 0 || p.readout_slice >= h->L) return fail(SQA_ERR_INVALID, "readout slice out of range");
+  if (!h->initialised) return fail(SQA_ERR_INVALID, "no state yet: anneal first");
+  const int N = h->N, R = h->R, n = h->emb.n, L = h->L;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int8_t *spins = h->arena.at<int8_t>(h->off_spins);
+  int8_t *logical = h->arena.at<int8_t>(h->off_logical);
+  int32_t *lenergy = h->arena.at<int32_t>(h->off_lenergy);
+  const int32_t *dJ = h->arena.at<int32_t>(h->off_J);
+  const int32_t *dh = h->has_h ? h->arena.at<int32_t>(h->off_h) : nullptr;
+  hipError_t e = hipSuccess;
+  if (p.decoder == SQA_DEC_ME_MAJORITY) {
+    if (h->emb.kind != SQA_EMB_ME) return fail(SQA_ERR_INVALID, "majority decoding of chains needs an ME handle");
+    e = hipStreamWaitEvent(s, h->done, 0);
+    if (e == hipSuccess)
+      e = launch_me_majority(spins, R, N, n, L, p.readout_slice, dJ, dh, logical, lenergy, s);
+  } else {
+    if (p.decoder != SQA_DEC_LHZ_TREES && p.decoder != SQA_DEC_LHZ_MWD && p.decoder != SQA_DEC_LHZ_MLD &&
+        p.decoder != SQA_DEC_LHZ_BP)
+      return fail(SQA_ERR_INVALID, "unknown decoder");
+    if (h->emb.kind != SQA_EMB_LHZ) return fail(SQA_ERR_INVALID, "LHZ decoders need an LHZ handle");
+    const int K = n;
+    const bool trees = p.decoder == SQA_DEC_LHZ_TREES || p.decoder == SQA_DEC_LHZ_BP;
+    if (p.decoder == SQA_DEC_LHZ_MWD && N > 32)
+      return fail(SQA_ERR_UNSUPPORTED, "exhaustive minimum-weight decoding limited to n <= 32");
+    if (p.decoder == SQA_DEC_LHZ_MLD && N > 24)
+      return fail(SQA_ERR_UNSUPPORTED, "exhaustive maximum-likelihood decoding limited to n <= 24");
+    if (p.decoder == SQA_DEC_LHZ_BP && N > 32)
+      return fail(SQA_ERR_UNSUPPORTED, "parity-check decoding limited to n <= 32");
+    if ((p.decoder == SQA_DEC_LHZ_MLD || p.decoder == SQA_DEC_LHZ_BP) && !(p.error_rate > 0.0 && p.error_rate < 0.5))
+      return fail(SQA_ERR_INVALID, "error rate must be in (0, 1/2)");
+    if (p.decoder == SQA_DEC_LHZ_BP && p.iterations < 0) return fail(SQA_ERR_INVALID, "negative iteration count");
+    std::vector<int32_t> order;
+    if (trees) {
+      st = tree_orders(N, p.tree_parents, p.n_trees, &order);
+      if (st != SQA_OK) return st;
+    }
+    // scratch: rows, best keys, sums, BP pair values, weight table, vote table, trees
+    const size_t o_rows = 0;
+    const size_t o_best = align256(o_rows + static_cast<size_t>(R) * N * 4);
+    const size_t o_acc = align256(o_best + static_cast<size_t>(R) * 8);
+    const size_t o_pairs = align256(o_acc + static_cast<size_t>(R) * N * 8);
+    const size_t o_wtab = align256(o_pairs + static_cast<size_t>(R) * K);
+    const size_t o_dec = align256(o_wtab + static_cast<size_t>(2 * K + 1) * 8);
+    const size_t o_par = align256(o_dec + static_cast<size_t>(2 * (2 * N - 3) + 1));
+    const size_t o_ord = align256(o_par + order.size() * 4);
+    const size_t need = align256(o_ord + order.size() * 4);
+    st = decode_scratch(h, need);
+    if (st != SQA_OK) return st;
+    char *base = static_cast<char *>(h->dec_buf);
+    auto *rows = reinterpret_cast<uint32_t *>(base + o_rows);
+    auto *best = reinterpret_cast<unsigned long long *>(base + o_best);
+    auto *acc = reinterpret_cast<unsigned long long *>(base + o_acc);
+    auto *pairs = reinterpret_cast<int8_t *>(base + o_pairs);
+    auto *wtab = reinterpret_cast<uint64_t *>(base + o_wtab);
+    auto *dec = reinterpret_cast<int8_t *>(base + o_dec);
+    auto *par = reinterpret_cast<int32_t *>(base + o_par);
+    auto *ord = reinterpret_cast<int32_t *>(base + o_ord);
+    // host tables (the earlier decodes that read this scratch have finished first)
+    if (trees || p.decoder == SQA_DEC_LHZ_MLD) {
+      e = hipEventSynchronize(h->done);
+      if (e != hipSuccess) {
+        h->poisoned = true;
+        return hip_fail(e, "hipEventSynchronize");
+      }
+    }
+    if (trees) {
+      e = hipMemcpy(par, p.tree_parents, order.size() * 4, hipMemcpyHostToDevice);
+      if (e == hipSuccess) e = hipMemcpy(ord, order.data(), order.size() * 4, hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess && p.decoder == SQA_DEC_LHZ_MLD) {
+      // Sec. IV B: weights round(2^36 exp(-beta_N d)), d = O_max - O, beta_N = ln((1-p)/p) / 2
+      const double beta = 0.5 * std::log((1.0 - p.error_rate) / p.error_rate);
+      std::vector<uint64_t> w(2 * K + 1);
+      for (int d = 0; d <= 2 * K; ++d)
+        w[d] = static_cast<uint64_t>(std::llround(std::ldexp(std::exp(-beta * static_cast<double>(d)), 36)));
+      e = hipMemcpy(wtab, w.data(), w.size() * 8, hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess && p.decoder == SQA_DEC_LHZ_BP) {
+      // Sec. IV D: x_ij <- sign(w0 s_ij + w1 c), tie keeps s_ij; w0 = ln((1-p)/p), w1 = ln((1-p2)/p2), p2 = 2p(1-p)
+      const double q = p.error_rate, q2 = 2.0 * q * (1.0 - q);
+      const double w0 = std::log((1.0 - q) / q), w1 = std::log((1.0 - q2) / q2);
+      std::vector<int8_t> d(2 * (2 * N - 3) + 1, 1);
+      for (int neg = 0; neg < 2; ++neg)
+        for (int c = -(N - 2); c <= N - 2; ++c) {
+          const int sv = neg ? -1 : 1;
+          const double v = w0 * static_cast<double>(sv) + w1 * static_cast<double>(c);
+          d[neg * (2 * N - 3) + c + N - 2] = static_cast<int8_t>(v > 0.0 ? 1 : (v < 0.0 ? -1 : sv));
+        }
+      e = hipMemcpy(dec, d.data(), d.size(), hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, h->done, 0);
+    if (e == hipSuccess && p.decoder != SQA_DEC_LHZ_TREES)
+      e = launch_lhz_rows(spins, R, L, K, N, p.readout_slice, rows, s);
+    if (e == hipSuccess) {
+      switch (p.decoder) {
+        case SQA_DEC_LHZ_TREES:
+          e = launch_lhz_trees(spins + static_cast<size_t>(p.readout_slice) * K, static_cast<size_t>(L) * K, R, N,
+                               par, ord, p.n_trees, logical, s);
+          break;
+        case SQA_DEC_LHZ_MWD:
+          e = launch_lhz_mwd(rows, R, N, best, logical, s);
+          break;
+        case SQA_DEC_LHZ_MLD:
+          e = launch_lhz_mld(rows, R, N, best, wtab, 2 * K + 1, acc, logical, s);
+          break;
+        default:
+          e = launch_lhz_bp(rows, R, N, p.iterations, dec, pairs, s);
+          if (e == hipSuccess)
+            e = launch_lhz_trees(pairs, static_cast<size_t>(K), R, N, par, ord, p.n_trees, logical, s);
+          break;
+      }
+    }
+    if (e == hipSuccess) e = launch_logical_energy(logical, R, N, dJ, dh, lenergy, s);
+  }
+  if (e == hipSuccess) e = hipEventRecord(h->done, s);
+  if (e != hipSuccess) {
+    h->poisoned = true;
+    return hip_fail(e, "decode launch");
+  }
+  if (!logical_out && !logical_energy_out) return SQA_OK;    // results stay on the device
+  e = hipEventSynchronize(h->done);
+  if (e == hipSuccess && logical_out) e = hipMemcpy(logical_out, logical, static_cast<size_t>(R) * N, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && logical_energy_out)
+    e = hipMemcpy(logical_energy_out, lenergy, static_cast<size_t>(R) * 4, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) {
+    h->poisoned = true;
+    return hip_fail(e, "decode read-back");
+  }
+  return SQA_OK;
+}
+
+sqa_status sqa_read_logical(sqa_handle *h, int8_t *logical_out, size_t len, int32_t *energy_out, size_t elen) {
+  sqa_status st = check_handle(h);
+  if (st != SQA_OK) return st;
+  const size_t nq = static_cast<size_t>(h->R) * h->N, ne = static_cast<size_t>(h->R);
+  if ((logical_out && len < nq) || (energy_out && elen < ne)) return fail(SQA_ERR_INVALID, "buffer too short");
+  if ((st = sqa_sync(h)) != SQA_OK) return st;
+  hipError_t e = hipSuccess;
+  if (logical_out) e = hipMemcpy(logical_out, h->arena.at<void>(h->off_logical), nq, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && energy_out) e = hipMemcpy(energy_out, h->arena.at<void>(h->off_lenergy), ne * 4, hipMemcpyDeviceToHost);
+  return e == hipSuccess ? SQA_OK : hip_fail(e, "hipMemcpy logical");
 }
 
 sqa_status sqa_decode(sqa_handle *h, int32_t decoder, int32_t readout_slice, const int32_t *tree_parents,
                       int32_t n_trees, int8_t *logical_out, int32_t *logical_energy_out) {
-  sqa_status st = check_handle(h);
-  if (st != SQA_OK) return st;
-  if (readout_slice < 0 || readout_slice >= h->L) return fail(SQA_ERR_INVALID, "readout slice out of range");
-  if (!h->initialised) return fail(SQA_ERR_INVALID, "no state yet: anneal first");
-  const int N = h->N, R = h->R, n = h->emb.n, L = h->L;
-  if (decoder == SQA_DEC_ME_MAJORITY) {
-    if (h->emb.kind != SQA_EMB_ME) return fail(SQA_ERR_INVALID, "majority decoding of chains needs an ME handle");
-    if ((st = sqa_sync(h)) != SQA_OK) return st;
-    hipError_t e = launch_me_majority(h->arena.at<int8_t>(h->off_spins), R, N, n, L, readout_slice,
-                                      h->arena.at<int32_t>(h->off_J), h->has_h ? h->arena.at<int32_t>(h->off_h) : nullptr,
-                                      h->arena.at<int8_t>(h->off_logical), h->arena.at<int32_t>(h->off_lenergy), nullptr);
-    if (e == hipSuccess) e = hipDeviceSynchronize();
-    if (e == hipSuccess && logical_out)
-      e = hipMemcpy(logical_out, h->arena.at<void>(h->off_logical), static_cast<size_t>(R) * N, hipMemcpyDeviceToHost);
-    if (e == hipSuccess && logical_energy_out)
-      e = hipMemcpy(logical_energy_out, h->arena.at<void>(h->off_lenergy), static_cast<size_t>(R) * 4,
-                    hipMemcpyDeviceToHost);
-    if (e != hipSuccess) {
-      h->poisoned = true;
-      return hip_fail(e, "majority decode");
-    }
-    return SQA_OK;
-  }
-  if (decoder != SQA_DEC_LHZ_TREES && decoder != SQA_DEC_LHZ_MWD) return fail(SQA_ERR_INVALID, "unknown decoder");
-  if (h->emb.kind != SQA_EMB_LHZ) return fail(SQA_ERR_INVALID, "tree and minimum-weight decoding need an LHZ handle");
-  if (decoder == SQA_DEC_LHZ_TREES) {
-    if (!tree_parents || n_trees < 1) return fail(SQA_ERR_INVALID, "tree decoding needs at least one tree");
-    for (int t = 0; t < n_trees; ++t) {
-      const int32_t *par = tree_parents + static_cast<size_t>(t) * N;
-      if (par[0] != -1) return fail(SQA_ERR_INVALID, "tree must be rooted at logical spin 0");
-      for (int v = 1; v < N; ++v)
-        if (par[v] < 0 || par[v] >= N || par[v] == v) return fail(SQA_ERR_INVALID, "bad parent array");
-      // every vertex must reach the root within N steps
-      for (int v = 1; v < N; ++v) {
-        int x = v, steps = 0;
-        while (x != 0 && steps <= N) { x = par[x]; ++steps; }
-        if (x != 0) return fail(SQA_ERR_INVALID, "parent array is not a tree rooted at 0");
-      }
-    }
-  } else if (N > 30) {
-    return fail(SQA_ERR_UNSUPPORTED, "exact minimum-weight decoding limited to n <= 30");
-  }
-  if ((st = sqa_sync(h)) != SQA_OK) return st;
-  std::vector<int8_t> slice(static_cast<size_t>(R) * n);
-  for (int r = 0; r < R; ++r) {
-    hipError_t e = hipMemcpy(slice.data() + static_cast<size_t>(r) * n,
-                             h->arena.at<int8_t>(h->off_spins) + (static_cast<size_t>(r) * L + readout_slice) * n, n,
-                             hipMemcpyDeviceToHost);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpy readout slice");
-  }
-  std::vector<int8_t> q(N);
-  std::vector<int8_t> val(N);
-  std::vector<int> votes(N);
-  std::vector<int8_t> sig(N);
-  for (int r = 0; r < R; ++r) {
-    const int8_t *s = slice.data() + static_cast<size_t>(r) * n;
-    if (decoder == SQA_DEC_LHZ_TREES) {
-      // Eq. (5) / Appendix A: qbar_0 = +1, qbar_v = qbar_parent(v) * q_{v,parent(v)}; majority, tie -> +1
-      std::fill(votes.begin(), votes.end(), 0);
-      for (int t = 0; t < n_trees; ++t) {
-        const int32_t *par = tree_parents + static_cast<size_t>(t) * N;
-        std::fill(val.begin(), val.end(), 0);
-        val[0] = 1;
-        for (int v = 1; v < N; ++v) {
-          // resolve the path to the first vertex with a known value
-          int x = v;
-          int path[256];
-          int len = 0;
-          while (val[x] == 0) { path[len++] = x; x = par[x]; }
-          for (int k = len - 1; k >= 0; --k) {
-            const int y = path[k];
-            val[y] = static_cast<int8_t>(val[par[y]] * s[pair_index(N, y, par[y])]);
-          }
-        }
-        for (int v = 0; v < N; ++v) votes[v] += val[v];
-      }
-      for (int v = 0; v < N; ++v) q[v] = votes[v] >= 0 ? 1 : -1;
-    } else {
-      // Sec. IV A: maximise sum_{i<j} s_ij sig_i sig_j over sig_0 = +1 (nearest
-      // constraint-satisfying state), visiting candidates in Gray-code order;
-      // ties -> smallest candidate index (bit b set <=> sig_{b+1} = -1).
-      std::vector<int32_t> field(N, 0);   // field[i] = sum_{j != i} s_ij sig_j
-      std::fill(sig.begin(), sig.end(), 1);
-      long long score = 0;
-      for (int i = 0; i < N; ++i)
-        for (int j = i + 1; j < N; ++j) score += s[pair_index(N, i, j)];
-      for (int i = 0; i < N; ++i)
-        for (int j = 0; j < N; ++j)
-          if (j != i) field[i] += s[pair_index(N, i, j)];
-      long long best = score;
-      uint64_t best_m = 0, m = 0;
-      const uint64_t total = 1ull << (N - 1);
-      for (uint64_t g = 1; g < total; ++g) {
-        const int b = __builtin_ctzll(g);
-        const int i = b + 1;
-        score -= 2LL * sig[i] * field[i];
-        sig[i] = static_cast<int8_t>(-sig[i]);
-        for (int j = 0; j < N; ++j)
-          if (j != i) field[j] += 2 * s[pair_index(N, i, j)] * sig[i];
-        m ^= 1ull << b;
-        if (score > best || (score == best && m < best_m)) {
-          best = score;
-          best_m = m;
-        }
-      }
-      q[0] = 1;
-      for (int b = 0; b + 1 < N; ++b) q[b + 1] = ((best_m >> b) & 1u) ? -1 : 1;
-    }
-    if (logical_out) std::memcpy(logical_out + static_cast<size_t>(r) * N, q.data(), N);
-    if (logical_energy_out) logical_energy_out[r] = logical_energy(h, q.data());
-  }
-  return SQA_OK;
+  sqa_decode_params p{};
+  p.decoder = decoder;
+  p.readout_slice = readout_slice;
+  p.tree_parents = tree_parents;
+  p.n_trees = n_trees;
+  p.error_rate = 0.2;
+  p.iterations = 10;
+  sqa_status st = sqa_decode_ex(h, &p, logical_out, logical_energy_out, nullptr);
+  if (st != SQA_OK || logical_out || logical_energy_out) return st;
+  return sqa_sync(h);
 }
 
 // Uniform labelled spanning trees from Pruefer sequences, entry i of tree t =

@@ -95,6 +95,17 @@ int sqa_anneal_occupancy(int move, int waves, size_t lds_bytes);
 hipError_t launch_sqa_init(const HandleDev &H, hipStream_t stream);
 hipError_t launch_me_majority(const int8_t *spins, int R, int N, int n_sites, int L, int slice, const int32_t *J,
                               const int32_t *h, int8_t *logical, int32_t *energy, hipStream_t stream);
+hipError_t launch_lhz_rows(const int8_t *spins, int R, int L, int K, int N, int slice, uint32_t *rows, hipStream_t s);
+hipError_t launch_lhz_mwd(const uint32_t *rows, int R, int N, unsigned long long *best, int8_t *logical,
+                          hipStream_t s);
+hipError_t launch_lhz_mld(const uint32_t *rows, int R, int N, unsigned long long *best, const uint64_t *wtab,
+                          int wlen, unsigned long long *acc, int8_t *logical, hipStream_t s);
+hipError_t launch_lhz_bp(const uint32_t *rows, int R, int N, int iterations, const int8_t *dec, int8_t *pairs,
+                         hipStream_t s);
+hipError_t launch_lhz_trees(const int8_t *pairs, size_t stride, int R, int N, const int32_t *parents,
+                            const int32_t *order, int n_trees, int8_t *logical, hipStream_t s);
+hipError_t launch_logical_energy(const int8_t *logical, int R, int N, const int32_t *J, const int32_t *h,
+                                 int32_t *energy, hipStream_t s);
 hipError_t launch_pt(const PTDev *pts, int count, int waves, int rec_cap, int lat_cap, int mtab_cap,
                      hipStream_t stream);
 hipError_t set_pt_lds_limit(size_t bytes);
@@ -153,5 +164,8 @@ struct sqa_handle {
   size_t device_bytes = 0;
   // pinned staging of the single-handle launch descriptor: HandleDev then R work items
   void *staging = nullptr;
+  // device scratch of the LHZ decoders (grown on demand)
+  void *dec_buf = nullptr;
+  size_t dec_bytes = 0;
   sqa::HandleDev dev(int m0, int m1, int flags) const;
 };

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libsqa.so")
 SQA_OK, SQA_ERR_INVALID, SQA_ERR_OOM, SQA_ERR_DEVICE, SQA_ERR_UNSUPPORTED, SQA_ERR_BUSY, SQA_ERR_NOT_READY = \
     0, -1, -2, -3, -4, -5, -6
 SQA_EMB_ME, SQA_EMB_LHZ = 0, 1
-SQA_DEC_ME_MAJORITY, SQA_DEC_LHZ_TREES, SQA_DEC_LHZ_MWD = 0, 1, 2
+SQA_DEC_ME_MAJORITY, SQA_DEC_LHZ_TREES, SQA_DEC_LHZ_MWD, SQA_DEC_LHZ_MLD, SQA_DEC_LHZ_BP = 0, 1, 2, 3, 4
 SQA_MOVE_METROPOLIS, SQA_MOVE_WOLFF = 0, 1
 
 
@@ -42,6 +42,11 @@ class sqa_schedule(C.Structure):
                 ("gamma_start", C.c_double), ("gamma_end", C.c_double),
                 ("gamma", C.POINTER(C.c_double)), ("bscale", C.POINTER(C.c_double)), ("seed", C.c_uint64),
                 ("move", C.c_int32)]
+
+
+class sqa_decode_params(C.Structure):
+    _fields_ = [("decoder", C.c_int32), ("readout_slice", C.c_int32), ("tree_parents", C.POINTER(C.c_int32)),
+                ("n_trees", C.c_int32), ("error_rate", C.c_double), ("iterations", C.c_int32)]
 
 
 class sqa_launch_config(C.Structure):
@@ -68,6 +73,10 @@ _SIGS = {
     "sqa_device_spins": (_VP, [_VP]),
     "sqa_device_energies": (_VP, [_VP]),
     "sqa_decode": (C.c_int, [_VP, C.c_int32, C.c_int32, _VP, C.c_int32, _VP, _VP]),
+    "sqa_decode_ex": (C.c_int, [_VP, C.POINTER(sqa_decode_params), _VP, _VP, _VP]),
+    "sqa_device_logical": (_VP, [_VP]),
+    "sqa_device_logical_energies": (_VP, [_VP]),
+    "sqa_read_logical": (C.c_int, [_VP, _VP, C.c_size_t, _VP, C.c_size_t]),
     "sqa_random_trees": (C.c_int, [C.c_uint64, C.c_int32, C.c_int32, _VP]),
     "sqa_export_table": (C.c_int, [_VP, _VP, C.c_size_t, C.POINTER(C.c_int32)]),
     "sqa_export_wolff_tables": (C.c_int, [_VP, _VP, C.c_size_t, _VP, C.c_size_t, C.POINTER(C.c_int32),
@@ -221,13 +230,28 @@ class SQA:
                                              C.byref(width)))
         return padd, acc
 
-    def decode(self, decoder: int, readout_slice: int = 0, trees=None):
+    def decode(self, decoder: int, readout_slice: int = 0, trees=None, error_rate: float = 0.2,
+               iterations: int = 10, stream=None, host: bool = True):
+        """Decodes slice `readout_slice` of every replica (sqa_decode_ex).  host=False queues
+        the decoder on `stream` and leaves the results in device memory."""
+        t = None if trees is None else np.ascontiguousarray(trees, dtype=np.int32).reshape(-1, self.N)
+        p = sqa_decode_params(decoder, readout_slice,
+                              t.ctypes.data_as(C.POINTER(C.c_int32)) if t is not None else None,
+                              0 if t is None else t.shape[0], error_rate, iterations)
+        if not host:
+            _check(lib().sqa_decode_ex(self.h, C.byref(p), None, None, _stream(stream)))
+            return None
         logical = np.empty((self.replicas, self.N), dtype=np.int8)
         energy = np.empty(self.replicas, dtype=np.int32)
-        t = None if trees is None else np.ascontiguousarray(trees, dtype=np.int32).reshape(-1, self.N)
-        _check(lib().sqa_decode(self.h, decoder, readout_slice, _ptr(t), 0 if t is None else t.shape[0],
-                                _ptr(logical), _ptr(energy)))
+        _check(lib().sqa_decode_ex(self.h, C.byref(p), _ptr(logical), _ptr(energy), _stream(stream)))
         return logical, energy
+
+    def logical(self):
+        """(logical states, logical energies) of the last decode, after waiting for it."""
+        q = np.empty((self.replicas, self.N), dtype=np.int8)
+        E = np.empty(self.replicas, dtype=np.int32)
+        _check(lib().sqa_read_logical(self.h, _ptr(q), q.size, _ptr(E), E.size))
+        return q, E
 
     def device_spins(self) -> int:
         return lib().sqa_device_spins(self.h)

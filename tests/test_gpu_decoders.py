@@ -1,0 +1,168 @@
+"""GPU parity of the LHZ decoders (trees, MWD, MLD, BP) and ME majority vote
+against the CPU oracle: decoded logical states and energies bit-exact."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1603_03755_amd.workloads import LHZ, ME, sk_instance
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sqa():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1603_03755_amd import sqa as s
+    s.lib()
+    return s
+
+
+def _handle(sqa, N, R, L=8, seed=3, kind=LHZ, sweeps=30):
+    J = sk_instance(N, 900 + N)
+    h = sqa.SQA(kind, J, -2, 5.0, L, sweeps, R, 3.0, 0.05, seed)
+    return h, J
+
+
+def _random_state(h, R, L, rng, p_minus):
+    s = np.where(rng.random((R, L, h.sites)) < p_minus, -1, 1).astype(np.int8)
+    h.write_spins(s)
+    return s
+
+
+def _check(sqa, h, J, spins, slice_, decoder, ref_fn, **kw):
+    logical, E = h.decode(decoder, slice_, **kw)
+    for r in range(spins.shape[0]):
+        q = ref_fn(spins[r, slice_])
+        assert (logical[r] == q).all(), (decoder, r)
+        assert E[r] == O.logical_energy(J, q), (decoder, r)
+
+
+@pytest.mark.parametrize("N,R", [(3, 5), (5, 9), (8, 16), (12, 8), (16, 4)])
+def test_mwd_matches_oracle_on_random_readouts(sqa, N, R):
+    print(f"mwd N={N} R={R}", flush=True)
+    rng = np.random.default_rng(N)
+    h, J = _handle(sqa, N, R)
+    for p_minus in (0.02, 0.3, 0.5):             # near-codewords, noisy, and tie-rich random states
+        spins = _random_state(h, R, 8, rng, p_minus)
+        _check(sqa, h, J, spins, 3, sqa.SQA_DEC_LHZ_MWD, lambda s: O.lhz_mwd(N, s))
+
+
+@pytest.mark.parametrize("N", [20, 24, 29])
+def test_mwd_large_n_sampled(sqa, N):
+    """Larger searches (2^19 .. 2^28 candidates per replica): two replicas against
+    the oracle, the rest checked to be maximisers of the decoding score."""
+    print(f"mwd large N={N}", flush=True)
+    rng = np.random.default_rng(7 + N)
+    R = 6
+    h, J = _handle(sqa, N, R, L=2)
+    spins = _random_state(h, R, 2, rng, 0.1)
+    logical, E = h.decode(sqa.SQA_DEC_LHZ_MWD, 1)
+    n_oracle = 2 if N <= 24 else 0
+    for r in range(R):
+        s = spins[r, 1]
+        if r < n_oracle:
+            assert (logical[r] == O.lhz_mwd(N, s)).all()
+        iu = np.triu_indices(N, 1)
+        score = int((s * logical[r][iu[0]] * logical[r][iu[1]]).sum())
+        # no single logical flip improves a maximiser
+        for b in range(1, N):
+            q = logical[r].copy()
+            q[b] = -q[b]
+            assert int((s * q[iu[0]] * q[iu[1]]).sum()) <= score
+        assert E[r] == O.logical_energy(J, logical[r])
+
+
+@pytest.mark.parametrize("N,R,p", [(3, 4, 0.2), (6, 8, 0.05), (9, 8, 0.2), (13, 6, 0.4), (18, 3, 0.1), (24, 1, 0.2)])
+def test_mld_matches_oracle(sqa, N, R, p):
+    print(f"mld N={N} R={R} p={p}", flush=True)
+    rng = np.random.default_rng(100 + N)
+    h, J = _handle(sqa, N, R, L=4)
+    spins = _random_state(h, R, 4, rng, 0.15)
+    _check(sqa, h, J, spins, 2, sqa.SQA_DEC_LHZ_MLD, lambda s: O.lhz_mld(N, s, p)[0], error_rate=p)
+
+
+@pytest.mark.parametrize("N,iters,p,ntree", [(3, 10, 0.2, 1), (5, 1, 0.2, 1), (8, 10, 0.2, 1), (8, 0, 0.2, 3),
+                                              (16, 10, 0.1, 1), (16, 4, 0.4, 5), (32, 10, 0.2, 1)])
+def test_bp_matches_oracle(sqa, N, iters, p, ntree):
+    print(f"bp N={N} iters={iters} p={p}", flush=True)
+    rng = np.random.default_rng(200 + N + iters)
+    R = 8
+    h, J = _handle(sqa, N, R, L=2)
+    trees = O.random_trees(31 + N, N, ntree)
+    for p_minus in (0.05, 0.4):
+        spins = _random_state(h, R, 2, rng, p_minus)
+        _check(sqa, h, J, spins, 0, sqa.SQA_DEC_LHZ_BP,
+               lambda s: O.lhz_bp(N, s, trees, p, iters)[0], trees=trees, error_rate=p, iterations=iters)
+
+
+@pytest.mark.parametrize("N,ntree", [(3, 1), (8, 5), (24, 100), (40, 7)])
+def test_trees_match_oracle(sqa, N, ntree):
+    print(f"trees N={N} ntree={ntree}", flush=True)
+    rng = np.random.default_rng(300 + N)
+    R = 5
+    h, J = _handle(sqa, N, R, L=2)
+    trees = np.vstack([O.chain_tree(N), O.star_tree(N), O.random_trees(9, N, ntree)])
+    spins = _random_state(h, R, 2, rng, 0.2)
+    _check(sqa, h, J, spins, 1, sqa.SQA_DEC_LHZ_TREES, lambda s: O.lhz_tree_decode(N, s, trees), trees=trees)
+
+
+def test_decoders_after_anneal_and_me_majority(sqa):
+    """Decoding annealed states (both embeddings), every decoder, two readout slices."""
+    N, R, L = 8, 16, 32
+    J = sk_instance(N, 1603)
+    lhz = sqa.SQA(LHZ, J, -2, 10.0, L, 300, R, 3.0, 0.01, 5).anneal()
+    me = sqa.SQA(ME, J, -2, 10.0, L, 300, R, 3.0, 0.01, 5).anneal()
+    ls, ms = lhz.spins(), me.spins()
+    emb = O.Embedding(ME, J, -2)
+    trees = O.random_trees(1, N, 3)
+    for sl in (0, 17):
+        _check(sqa, lhz, J, ls, sl, sqa.SQA_DEC_LHZ_MWD, lambda s: O.lhz_mwd(N, s))
+        _check(sqa, lhz, J, ls, sl, sqa.SQA_DEC_LHZ_MLD, lambda s: O.lhz_mld(N, s, 0.2)[0], error_rate=0.2)
+        _check(sqa, lhz, J, ls, sl, sqa.SQA_DEC_LHZ_BP, lambda s: O.lhz_bp(N, s, trees[:1], 0.2, 10)[0],
+               trees=trees[:1])
+        _check(sqa, lhz, J, ls, sl, sqa.SQA_DEC_LHZ_TREES, lambda s: O.lhz_tree_decode(N, s, trees), trees=trees)
+        _check(sqa, me, J, ms, sl, sqa.SQA_DEC_ME_MAJORITY, lambda s: O.me_majority(emb, s))
+
+
+def test_async_decode_leaves_results_on_device(sqa):
+    import torch
+    N, R = 10, 12
+    rng = np.random.default_rng(1)
+    h, J = _handle(sqa, N, R, L=4)
+    _random_state(h, R, 4, rng, 0.2)
+    ref, Eref = h.decode(sqa.SQA_DEC_LHZ_MWD, 2)
+    h.decode(sqa.SQA_DEC_LHZ_TREES, 0, trees=O.chain_tree(N))      # overwrite the device buffers
+    s = torch.cuda.Stream()
+    assert h.decode(sqa.SQA_DEC_LHZ_MWD, 2, stream=s, host=False) is None
+    assert sqa.lib().sqa_device_logical(h.h) and sqa.lib().sqa_device_logical_energies(h.h)
+    out, E = h.logical()
+    assert (out == ref).all() and (E == Eref).all()
+
+
+def test_decoder_limits_and_errors(sqa):
+    rng = np.random.default_rng(2)
+    h, J = _handle(sqa, 33, 2, L=2)
+    _random_state(h, 2, 2, rng, 0.1)
+    for dec, kw in [(sqa.SQA_DEC_LHZ_MWD, {}), (sqa.SQA_DEC_LHZ_MLD, {}), (sqa.SQA_DEC_LHZ_BP,
+                                                                        {"trees": O.chain_tree(33)})]:
+        with pytest.raises(sqa.SqaError) as e:
+            h.decode(dec, 0, **kw)
+        assert e.value.status == sqa.SQA_ERR_UNSUPPORTED
+    h2, _ = _handle(sqa, 8, 2, L=2)
+    _random_state(h2, 2, 2, rng, 0.1)
+    for kw in [{"error_rate": 0.5}, {"error_rate": 0.0}]:
+        with pytest.raises(sqa.SqaError) as e:
+            h2.decode(sqa.SQA_DEC_LHZ_MLD, 0, **kw)
+        assert e.value.status == sqa.SQA_ERR_INVALID
+    with pytest.raises(sqa.SqaError):
+        h2.decode(sqa.SQA_DEC_LHZ_BP, 0)                           # BP needs a readout tree
+    with pytest.raises(sqa.SqaError):
+        h2.decode(sqa.SQA_DEC_LHZ_BP, 0, trees=O.chain_tree(8), iterations=-1)
+    with pytest.raises(sqa.SqaError):
+        h2.decode(sqa.SQA_DEC_ME_MAJORITY, 0)                      # wrong embedding
+    bad = O.chain_tree(8).copy()
+    bad[3] = 5
+    bad[5] = 3                                                     # a cycle, not a tree
+    with pytest.raises(sqa.SqaError):
+        h2.decode(sqa.SQA_DEC_LHZ_TREES, 0, trees=bad)
