@@ -75,7 +75,7 @@ def parse():
     ap.add_argument("--no-extras", action="store_true", help="only the timed batched steps")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 2 GiB device to device, source evicted from the last-level cache first")
-    ap.add_argument("--legs", default="per_instance,serving,pt,wolff,cpu",
+    ap.add_argument("--legs", default="per_instance,serving,pt,wolff,scan,cpu",
                     help="comma list of the extra legs to run after the timed steps")
     ap.add_argument("--cpu-replicas", type=int, default=2, help="oracle lattices per stratum for cpu_baseline")
     ap.add_argument("--pt-sweeps", type=int, default=10_000, help="sweeps of the parallel-tempering leg")
@@ -169,6 +169,27 @@ def wolff_leg(sqa, O, jobs, stream, metropolis_kernel_s, traffic):
                          "traffic": traffic, "ops_per_site_slice": ops},
             "oracle": {"site_slices_per_s": ocells / odt, "cores": len(sample),
                        "sample": f"one replica lattice per embedding x N stratum ({len(sample)}), full schedule"}}
+
+
+def scan_leg(sqa):
+    """The paper's experiment shape on synthetic K8 instances (J in {+-0.1..+-1}, times 10):
+    8 instances x 6 penalty strengths x {ME, LHZ}, 1000 reads each, L = 64, 10^4 sweeps,
+    Wolff moves, one batched launch; p_s from device decoding against device ground states."""
+    from paper_1603_03755_amd import harness as H
+    from paper_1603_03755_amd.workloads import SEED_BATCH
+    instances = [H.paper_instance(8, SEED_BATCH + 7000 + i) for i in range(8)]
+    penalties = [0.5, 1.0, 1.5, 2.0, 2.5, 3.0]
+    t0 = time.perf_counter()
+    res = H.penalty_scan(instances, penalties, H.ScanConfig())
+    total = time.perf_counter() - t0
+    summary = {}
+    for scheme in res.p_s:
+        pen, ps = res.optimal(scheme)
+        summary[scheme] = {"p_s_at_optimal_penalty_mean": float(np.mean(ps)),
+                           "optimal_penalty_mean": float(np.mean(pen))}
+    return {"instances": len(instances), "n": 8, "penalties": penalties, "reads": 1000, "slices": 64,
+            "sweeps": 10_000, "move": "wolff", "anneal_seconds": res.seconds_anneal, "total_seconds": total,
+            "site_slices_per_s": res.site_slices / res.seconds_anneal, "schemes": summary}
 
 
 def cpu_baseline(jobs, replicas_per_stratum: int = 2):
@@ -370,6 +391,8 @@ def main():
         out["parallel_tempering"] = pt_leg(sqa, args.pt_sweeps)
     if "wolff" in legs:
         out["wolff"] = wolff_leg(sqa, O, jobs, stream, kernel_s, measured_traffic(args, wolff=True))
+    if "scan" in legs:
+        out["penalty_scan"] = scan_leg(sqa)
     if "cpu" in legs:
         out["cpu_baseline"] = cpu_baseline(jobs, args.cpu_replicas)
     print(json.dumps(out), flush=True)

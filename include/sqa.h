@@ -129,7 +129,7 @@ typedef struct {
  * Errors: SQA_ERR_INVALID (null pointers, n out of range, slices odd > 1,
  * sweeps < 1, replicas out of range, beta <= 0, negative Gamma),
  * SQA_ERR_UNSUPPORTED (LHZ with h != 0, slices > 64, a site whose
- * |h| + sum of |incident coefficients| exceeds 63),
+ * |h| + sum of |incident coefficients| exceeds 255),
  * SQA_ERR_OOM, SQA_ERR_DEVICE. */
 SQA_API sqa_status sqa_create(const sqa_problem *problem, const sqa_embedding *embedding,
                       const sqa_schedule *schedule, sqa_handle **out);
@@ -233,6 +233,15 @@ SQA_API void *sqa_device_logical_energies(sqa_handle *h);
  * replicas*n) and logical energies (elen >= replicas); either may be NULL. */
 SQA_API sqa_status sqa_read_logical(sqa_handle *h, int8_t *logical_out, size_t len, int32_t *energy_out,
                             size_t elen);
+
+/* Exact ground state of the logical problem (Eq. (1)) by exhaustive search on
+ * the device over the 2^(n-1) states with s_0 = +1 and their global flips:
+ * the ground energy and one ground state (the first in the order: candidate
+ * index m, bit b set <=> s_{b+1} = -s_0, then unflipped before flipped).
+ * Used to score decoded anneals (success probability).  Blocking.
+ * Errors: SQA_ERR_INVALID (null, n < 2); SQA_ERR_UNSUPPORTED (n > 32,
+ * |J| or |h| >= 2^15).  Either output may be NULL. */
+SQA_API sqa_status sqa_ground_state(const sqa_problem *problem, int32_t *energy_out, int8_t *state_out);
 
 /* Uniform random labelled spanning trees of K_n (Pruefer sequences drawn from
  * the Philox TREE stream keyed by `seed`), as parent arrays rooted at 0:

@@ -739,6 +739,60 @@ sqa_status sqa_decode_ex(sqa_handle *h, const sqa_decode_params *prm, int8_t *lo
   return SQA_OK;
 }
 
+sqa_status sqa_ground_state(const sqa_problem *problem, int32_t *energy_out, int8_t *state_out) {
+  if (!problem || !problem->J) return fail(SQA_ERR_INVALID, "null problem");
+  const int N = problem->n;
+  if (N < 2) return fail(SQA_ERR_INVALID, "n must be >= 2");
+  if (N > 32) return fail(SQA_ERR_UNSUPPORTED, "exhaustive ground-state search limited to n <= 32");
+  int maxabs = 1;
+  for (int i = 0; i < N; ++i) {
+    if (problem->h) maxabs = std::max(maxabs, std::abs(problem->h[i]));
+    for (int j = i + 1; j < N; ++j) maxabs = std::max(maxabs, std::abs(problem->J[i * N + j]));
+  }
+  if (maxabs > 32767) return fail(SQA_ERR_UNSUPPORTED, "couplings and fields limited to |x| < 2^15");
+  int B = 0;
+  while ((1 << B) <= maxabs) ++B;
+  // bit planes of |J| split by sign, c_p = sum_j J_pj, fields
+  std::vector<uint32_t> planes(static_cast<size_t>(2 * B) * N, 0u);
+  std::vector<int32_t> cj(N, 0), hv(N, 0);
+  for (int p = 0; p < N; ++p) {
+    if (problem->h) hv[p] = problem->h[p];
+    for (int j = 0; j < N; ++j) {
+      if (j == p) continue;
+      const int32_t v = p < j ? problem->J[p * N + j] : problem->J[j * N + p];
+      cj[p] += v;
+      const uint32_t a = static_cast<uint32_t>(std::abs(v));
+      for (int b = 0; b < B; ++b)
+        if ((a >> b) & 1u) planes[static_cast<size_t>(2 * b + (v < 0 ? 1 : 0)) * N + p] |= 1u << j;
+    }
+  }
+  const size_t o_c = align256(planes.size() * 4), o_h = align256(o_c + N * 4), o_k = align256(o_h + N * 4);
+  void *dev = nullptr;
+  hipError_t e = hipMalloc(&dev, o_k + 256);
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc (ground state)");
+  char *base = static_cast<char *>(dev);
+  unsigned long long key = 0;
+  e = hipMemcpy(base, planes.data(), planes.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(base + o_c, cj.data(), N * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(base + o_h, hv.data(), N * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = launch_ground(reinterpret_cast<uint32_t *>(base), reinterpret_cast<int32_t *>(base + o_c),
+                      reinterpret_cast<int32_t *>(base + o_h), N, B, reinterpret_cast<unsigned long long *>(base + o_k),
+                      nullptr);
+  if (e == hipSuccess) e = hipMemcpy(&key, base + o_k, 8, hipMemcpyDeviceToHost);
+  (void)hipFree(dev);
+  if (e != hipSuccess) return hip_fail(e, "ground-state search");
+  if (energy_out) *energy_out = static_cast<int32_t>(static_cast<uint32_t>(key >> 32) ^ 0x80000000u);
+  if (state_out) {
+    const uint32_t low = static_cast<uint32_t>(key);
+    const uint32_t m = low >> 1;
+    const int8_t sgn = (low & 1u) ? int8_t(-1) : int8_t(1);
+    state_out[0] = sgn;
+    for (int b = 0; b + 1 < N; ++b) state_out[b + 1] = static_cast<int8_t>(((m >> b) & 1u) ? -sgn : sgn);
+  }
+  return SQA_OK;
+}
+
 sqa_status sqa_read_logical(sqa_handle *h, int8_t *logical_out, size_t len, int32_t *energy_out, size_t elen) {
   sqa_status st = check_handle(h);
   if (st != SQA_OK) return st;

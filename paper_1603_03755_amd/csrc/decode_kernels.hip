@@ -281,6 +281,80 @@ __global__ __launch_bounds__(64) void logical_energy_kernel(const int8_t *__rest
   if (threadIdx.x == 0) energy[r] = e;
 }
 
+
+// Exact ground state of Eq. (1) for integer J, h (n <= 32, |J|, |h| < 2^15):
+// exhaustive search over sigma_0 = +1 (candidate m: sigma_{b+1} = -1 iff bit b
+// of m) in Gray-code chunks, each candidate also taken with all spins flipped.
+// With E_J = sum_{i<j} J_ij s_i s_j and E_h = sum_i h_i s_i, the better of the
+// pair has energy E_J - |E_h|.  Flipping spin p changes E_J by -2 s_p g_p,
+// g_p = sum_j J_pj s_j, and E_h by -2 s_p h_p; g_p is rebuilt from bit planes
+// of |J|: pos[b][p] / neg[b][p] mark the j with J_pj > 0 / < 0 and bit b of
+// |J_pj| set, so g_p = c_p - 2 sum_b 2^b (popc(pos & z) - popc(neg & z)) with
+// c_p = sum_j J_pj and z the bit vector of the -1 spins.
+// best: min over candidates of ((E + 2^31) << 32) | (m << 1 | flipped).
+__global__ __launch_bounds__(256) void ground_kernel(const uint32_t *__restrict__ planes, const int32_t *__restrict__ cj,
+                                                     const int32_t *__restrict__ hv, int N, int B, int c,
+                                                     unsigned long long *__restrict__ best) {
+  __shared__ uint32_t pos[16][32], neg[16][32];
+  __shared__ int32_t cp[32], hp[32];
+  for (int i = threadIdx.x; i < B * N; i += blockDim.x) {
+    const int b = i / N, p = i - b * N;
+    pos[b][p] = planes[(2 * b) * N + p];
+    neg[b][p] = planes[(2 * b + 1) * N + p];
+  }
+  if (threadIdx.x < N) {
+    cp[threadIdx.x] = cj[threadIdx.x];
+    hp[threadIdx.x] = hv[threadIdx.x];
+  }
+  __syncthreads();
+  const uint64_t total = 1ull << (N - 1);
+  const uint64_t chunk = 1ull << c;
+  const uint64_t g0 = (static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x) * chunk;
+  uint64_t key = ~0ull;
+  if (g0 < total) {
+    uint32_t m = static_cast<uint32_t>(g0 ^ (g0 >> 1));
+    uint32_t z = m << 1;
+    // energies of the chunk's first candidate, from scratch
+    int ej = 0, eh = 0;
+    for (int p = 0; p < N; ++p) {
+      const int sp = ((z >> p) & 1u) ? -1 : 1;
+      int g = cp[p];
+      for (int b = 0; b < B; ++b) g -= (2 << b) * (__popc(pos[b][p] & z) - __popc(neg[b][p] & z));
+      ej += sp * g;                        // counts every pair twice
+      eh += sp * hp[p];
+    }
+    ej /= 2;
+    auto make_key = [&](int e, uint32_t mm, uint32_t fl) {
+      return (static_cast<uint64_t>(static_cast<uint32_t>(e) ^ 0x80000000u) << 32) | (mm << 1) | fl;
+    };
+    {
+      const int e = ej - (eh > 0 ? eh : -eh);
+      key = make_key(e, m, eh > 0 ? 1u : 0u);
+    }
+    for (uint64_t t = 1; t < chunk; ++t) {
+      const int bflip = __builtin_ctzll(t);
+      const int p = bflip + 1;
+      const int sp = ((z >> p) & 1u) ? -1 : 1;
+      int g = cp[p];
+      for (int b = 0; b < B; ++b) g -= (2 << b) * (__popc(pos[b][p] & z) - __popc(neg[b][p] & z));
+      ej -= 2 * sp * g;
+      eh -= 2 * sp * hp[p];
+      z ^= 1u << p;
+      m ^= 1u << bflip;
+      const int e = ej - (eh > 0 ? eh : -eh);
+      const uint64_t k = make_key(e, m, eh > 0 ? 1u : 0u);
+      key = k < key ? k : key;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint32_t lo = __shfl_xor(static_cast<uint32_t>(key), off);
+    const uint32_t hi = __shfl_xor(static_cast<uint32_t>(key >> 32), off);
+    const uint64_t o = (static_cast<uint64_t>(hi) << 32) | lo;
+    key = o < key ? o : key;
+  }
+  if ((threadIdx.x & 63) == 0) atomicMin(best, static_cast<unsigned long long>(key));
+}
+
 // ----------------------------------------------------------- host launchers
 static unsigned blocks_for(size_t n, unsigned b) { return static_cast<unsigned>((n + b - 1) / b); }
 
@@ -342,6 +416,16 @@ hipError_t launch_logical_energy(const int8_t *logical, int R, int N, const int3
                                  int32_t *energy, hipStream_t s) {
   (void)hipGetLastError();
   hipLaunchKernelGGL(logical_energy_kernel, dim3(R), dim3(64), 0, s, logical, N, J, h, energy);
+  return hipGetLastError();
+}
+
+hipError_t launch_ground(const uint32_t *planes, const int32_t *cj, const int32_t *hv, int N, int B,
+                         unsigned long long *best, hipStream_t s) {
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(fill_u64_kernel, dim3(1), dim3(64), 0, s, reinterpret_cast<uint64_t *>(best), size_t(1), ~uint64_t(0));
+  const int c = chunk_exponent(N);
+  const uint64_t lanes = (1ull << (N - 1)) >> c;
+  hipLaunchKernelGGL(ground_kernel, dim3(blocks_for(lanes, 256)), dim3(256), 0, s, planes, cj, hv, N, B, c, best);
   return hipGetLastError();
 }
 

@@ -69,6 +69,11 @@ __device__ __forceinline__ uint32_t spread6_hi(uint32_t byte) {
   return (__umul24(byte & 0xF0u, 0x8421u) >> 4) & 0x41041u;
 }
 
+// Bits 0..2 moved to bits 0, 8, 16 (partial products at j + 7i, distinct):
+// three 8-bit fields whose spread value stays below 2^24, so it can be an
+// operand of a 24-bit multiply.
+__device__ __forceinline__ uint32_t spread3(uint32_t bits) { return __umul24(bits & 7u, 0x4081u) & 0x10101u; }
+
 // Four bits of a nibble moved to bit 0 of the four bytes of a word (partial
 // products at bits j + 7i, all distinct: no carries).  The result has bit 24
 // set for nibble bit 3, so it must not be an operand of a 24-bit multiply.

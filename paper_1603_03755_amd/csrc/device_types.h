@@ -35,6 +35,11 @@ constexpr int kKindLHZ = 1;
 // Weights |w|, |h| in the records are stored multiplied by 6 when F <= kSmallF
 // (the sweep kernel then indexes the table with the field sums directly).
 constexpr int kSmallF = 10;
+// Largest per-site field sum of the 6-bit-field sweep path, and of the library.
+constexpr int kMidF = 63;
+constexpr int kLargeF = 255;
+// Field modes of the sweep kernels (see sweep_class).
+constexpr int kFieldSmall = 0, kFieldMid = 1, kFieldLarge = 2;
 constexpr int kRecWordsME = 4;
 constexpr int kRecWordsLHZ = 12;
 

@@ -103,7 +103,7 @@ sqa_status build_embedding(const sqa_problem &p, const sqa_embedding &em, Embedd
   }
   e.fmax = 0;
   for (int32_t f : fsite) e.fmax = std::max(e.fmax, f);
-  if (e.fmax > 63) return fail(SQA_ERR_UNSUPPORTED, "sum of |coefficients| at one site exceeds 63");
+  if (e.fmax > kLargeF) return fail(SQA_ERR_UNSUPPORTED, "sum of |coefficients| at one site exceeds 255");
   if (emax > (1ll << 30)) return fail(SQA_ERR_INVALID, "energy range too large");
   e.emax = static_cast<int32_t>(emax);
   *out = std::move(e);

@@ -104,6 +104,8 @@ hipError_t launch_lhz_bp(const uint32_t *rows, int R, int N, int iterations, con
                          hipStream_t s);
 hipError_t launch_lhz_trees(const int8_t *pairs, size_t stride, int R, int N, const int32_t *parents,
                             const int32_t *order, int n_trees, int8_t *logical, hipStream_t s);
+hipError_t launch_ground(const uint32_t *planes, const int32_t *cj, const int32_t *hv, int N, int B,
+                         unsigned long long *best, hipStream_t s);
 hipError_t launch_logical_energy(const int8_t *logical, int R, int N, const int32_t *J, const int32_t *h,
                                  int32_t *energy, hipStream_t s);
 hipError_t launch_pt(const PTDev *pts, int count, int waves, int rec_cap, int lat_cap, int mtab_cap,

@@ -106,11 +106,14 @@ __device__ __forceinline__ void slice_energies(const HandleDev &H, const uint64_
 //   S = sum_t |w_t| X_t + |h| O   (X_t = 1 iff term t's product with the own
 //       spin disagrees with the sign of w_t; O likewise for the field),
 //   e = number of time neighbours whose spin differs from the own spin;
-// S and e are accumulated four slices at a time in 6-bit fields.
-// SMALLF (F <= 10): the records carry 6|w| and 6|h|, so the fields hold 6 S
-//   directly and 6 S + e < 64 stays inside a field.
+// e is accumulated four slices at a time in 6-bit fields; S by field mode:
+// kFieldSmall (F <= 10): the records carry 6|w| and 6|h|, so 6-bit fields hold
+//   6 S directly and 6 S + e < 64 stays inside a field;
+// kFieldMid (F <= 63): S in 6-bit fields, four slices per word;
+// kFieldLarge (F <= 255): S in 8-bit fields, three slices per word (at bits
+//   0, 8, 16, so both operands of the 24-bit multiplies stay below 2^24).
 // FASTL: L in {16, 32, 64} (whole bytes, replicated-word rotation, L > 1).
-template <int KIND, bool SMALLF, bool FASTL>
+template <int KIND, int MODE, bool FASTL>
 __device__ __forceinline__ void sweep_class(const HandleDev &H, const uint32_t *__restrict__ rec, uint32_t *lat32,
                                             const uint32_t *tab, int c, int p, uint32_t m, uint32_t c3, int lane) {
   using S = Site<KIND>;
@@ -192,8 +195,15 @@ __device__ __forceinline__ void sweep_class(const HandleDev &H, const uint32_t *
     // weighted disagreement counts, slices k = 0..3 in acc_lo and 4..7 in acc_hi
     const uint8_t *lb = latb + (4 * p + b);        // the item's byte in any site word
     const uint32_t ox = (own ^ negh) & 0xFFu;
-    uint32_t acc_lo = __umul24(spread6(__builtin_amdgcn_ubfe(ox, 0, 4)), hw);
-    uint32_t acc_hi = __umul24(spread6(__builtin_amdgcn_ubfe(ox, 4, 4)), hw);
+    uint32_t acc_lo = 0, acc_hi = 0, acc_x = 0;     // kFieldLarge: slices 0-2, 3-5, 6-7
+    if constexpr (MODE == kFieldLarge) {
+      acc_lo = __umul24(spread3(ox), hw);
+      acc_hi = __umul24(spread3(ox >> 3), hw);
+      acc_x = __umul24(spread3(ox >> 6), hw);
+    } else {
+      acc_lo = __umul24(spread6(__builtin_amdgcn_ubfe(ox, 0, 4)), hw);
+      acc_hi = __umul24(spread6(__builtin_amdgcn_ubfe(ox, 4, 4)), hw);
+    }
 #pragma unroll
     for (int t = 0; t < S::T; ++t) {
       uint32_t prod = own;
@@ -201,15 +211,21 @@ __device__ __forceinline__ void sweep_class(const HandleDev &H, const uint32_t *
       for (int q = 0; q < S::P; ++q) prod ^= lb[poff[S::P * t + q]];
       const uint32_t x = prod ^ (0u - ((neg >> t) & 1u));
       const uint32_t wt = (wts >> (8 * t)) & 0xFFu;
-      acc_lo += __umul24(spread6(__builtin_amdgcn_ubfe(x, 0, 4)), wt);
-      acc_hi += __umul24(spread6(__builtin_amdgcn_ubfe(x, 4, 4)), wt);
+      if constexpr (MODE == kFieldLarge) {
+        acc_lo += __umul24(spread3(x), wt);
+        acc_hi += __umul24(spread3(x >> 3), wt);
+        acc_x += __umul24(spread3(x >> 6), wt);
+      } else {
+        acc_lo += __umul24(spread6(__builtin_amdgcn_ubfe(x, 0, 4)), wt);
+        acc_hi += __umul24(spread6(__builtin_amdgcn_ubfe(x, 4, 4)), wt);
+      }
     }
 
     const Words4 u0 = philox4x32_10(site, static_cast<uint32_t>((b << 2) | p), m, c3, H.seed_lo, H.seed_hi);
     const Words4 u1 = philox4x32_10(site, static_cast<uint32_t>((b << 2) | 2 | p), m, c3, H.seed_lo, H.seed_hi);
     const uint32_t *tb = tab + base;                  // thresholds are read at tb[-(6 S + e)]
     uint32_t flip = 0;
-    if constexpr (SMALLF) {
+    if constexpr (MODE == kFieldSmall) {
       const uint32_t f_lo = acc_lo + ev_lo;
       const uint32_t f_hi = acc_hi + ev_hi;
 #pragma unroll
@@ -219,11 +235,22 @@ __device__ __forceinline__ void sweep_class(const HandleDev &H, const uint32_t *
         if (min(u0.v[w], 0xFFFFFFFEu) < R0) flip |= 1u << w;
         if (min(u1.v[w], 0xFFFFFFFEu) < R1) flip |= 16u << w;
       }
-    } else {
+    } else if constexpr (MODE == kFieldMid) {
 #pragma unroll
       for (int w = 0; w < 4; ++w) {
         const uint32_t i0 = 6u * __builtin_amdgcn_ubfe(acc_lo, 6 * w, 6) + __builtin_amdgcn_ubfe(ev_lo, 6 * w, 2);
         const uint32_t i1 = 6u * __builtin_amdgcn_ubfe(acc_hi, 6 * w, 6) + __builtin_amdgcn_ubfe(ev_hi, 6 * w, 2);
+        if (min(u0.v[w], 0xFFFFFFFEu) < *(tb - i0)) flip |= 1u << w;
+        if (min(u1.v[w], 0xFFFFFFFEu) < *(tb - i1)) flip |= 16u << w;
+      }
+    } else {
+      const uint32_t sums[3] = {acc_lo, acc_hi, acc_x};
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        const uint32_t s0 = __builtin_amdgcn_ubfe(sums[w / 3], 8 * (w % 3), 8);
+        const uint32_t s1 = __builtin_amdgcn_ubfe(sums[(w + 4) / 3], 8 * ((w + 4) % 3), 8);
+        const uint32_t i0 = 6u * s0 + __builtin_amdgcn_ubfe(ev_lo, 6 * w, 2);
+        const uint32_t i1 = 6u * s1 + __builtin_amdgcn_ubfe(ev_hi, 6 * w, 2);
         if (min(u0.v[w], 0xFFFFFFFEu) < *(tb - i0)) flip |= 1u << w;
         if (min(u1.v[w], 0xFFFFFFFEu) < *(tb - i1)) flip |= 16u << w;
       }
@@ -245,6 +272,7 @@ __device__ __forceinline__ void anneal_replica(const HandleDev &H, const uint32_
   const uint32_t c3 = (kStreamSQA << 24) | static_cast<uint32_t>(rep);
   const int parities = (H.L == 1) ? 1 : 2;
   const bool smallf = H.F <= kSmallF;
+  const bool midf = H.F <= kMidF;
   const bool fast = smallf && (H.L == 16 || H.L == 32 || H.L == 64);
   // the next sweep's table row is fetched into a register during the current sweep
   const bool row_in_reg = H.tw <= 64;
@@ -262,9 +290,11 @@ __device__ __forceinline__ void anneal_replica(const HandleDev &H, const uint32_
     uint32_t *lat32 = reinterpret_cast<uint32_t *>(lat);
     for (int p = 0; p < parities; ++p)
       for (int c = 0; c < 4; ++c) {
-        if (fast) sweep_class<KIND, true, true>(H, rec, lat32, tab, c, p, static_cast<uint32_t>(m), c3, lane);
-        else if (smallf) sweep_class<KIND, true, false>(H, rec, lat32, tab, c, p, static_cast<uint32_t>(m), c3, lane);
-        else sweep_class<KIND, false, false>(H, rec, lat32, tab, c, p, static_cast<uint32_t>(m), c3, lane);
+        const uint32_t mm = static_cast<uint32_t>(m);
+        if (fast) sweep_class<KIND, kFieldSmall, true>(H, rec, lat32, tab, c, p, mm, c3, lane);
+        else if (smallf) sweep_class<KIND, kFieldSmall, false>(H, rec, lat32, tab, c, p, mm, c3, lane);
+        else if (midf) sweep_class<KIND, kFieldMid, false>(H, rec, lat32, tab, c, p, mm, c3, lane);
+        else sweep_class<KIND, kFieldLarge, false>(H, rec, lat32, tab, c, p, mm, c3, lane);
         wave_sync();
       }
   }
@@ -313,7 +343,7 @@ __device__ __forceinline__ uint64_t ring_cluster(uint64_t jn, int t0, int L) {
   return t0 ? (((cr << t0) | (cr >> (L - t0))) & full) : cr;
 }
 
-template <int KIND>
+template <int KIND, bool LARGE>
 __device__ __forceinline__ void wolff_bonds(const HandleDev &H, const uint32_t *__restrict__ rec, const uint64_t *lat,
                                             uint32_t *scr, int c, uint32_t m, uint32_t c3, uint32_t padd, int lane) {
   using S = Site<KIND>;
@@ -376,14 +406,22 @@ __device__ __forceinline__ void wolff_bonds(const HandleDev &H, const uint32_t *
     }
     jb[8 * j + q] = static_cast<uint8_t>(join & eq);
 
-    // S of slices 8q..8q+3 (acc_lo) and 8q+4..8q+7 (acc_hi) in 6-bit fields; the
-    // 24-bit multiplies need both operands below 2^24, which fields at bits
-    // 0/6/12/18 keep (S <= 63 fits a field).  Repacked to bytes for the store.
+    // S of the eight slices: for F <= 63 in 6-bit fields (slices 8q..8q+3 in
+    // acc_lo, 8q+4..8q+7 in acc_hi), else in 8-bit fields three slices per word
+    // (acc_lo 0-2, acc_hi 3-5, acc_x 6-7); both keep the operands of the 24-bit
+    // multiplies below 2^24.  Repacked to one byte per slice for the store.
     const uint32_t negh = 0u - ((neg >> 4) & 1u);
     const uint8_t *lb = latb + q;
     const uint32_t ox = (own ^ negh) & 0xFFu;
-    uint32_t acc_lo = __umul24(spread6(__builtin_amdgcn_ubfe(ox, 0, 4)), hw);
-    uint32_t acc_hi = __umul24(spread6(__builtin_amdgcn_ubfe(ox, 4, 4)), hw);
+    uint32_t acc_lo, acc_hi, acc_x = 0;
+    if constexpr (LARGE) {
+      acc_lo = __umul24(spread3(ox), hw);
+      acc_hi = __umul24(spread3(ox >> 3), hw);
+      acc_x = __umul24(spread3(ox >> 6), hw);
+    } else {
+      acc_lo = __umul24(spread6(__builtin_amdgcn_ubfe(ox, 0, 4)), hw);
+      acc_hi = __umul24(spread6(__builtin_amdgcn_ubfe(ox, 4, 4)), hw);
+    }
 #pragma unroll
     for (int t = 0; t < S::T; ++t) {
       uint32_t prod = own;
@@ -391,11 +429,22 @@ __device__ __forceinline__ void wolff_bonds(const HandleDev &H, const uint32_t *
       for (int x = 0; x < S::P; ++x) prod ^= lb[poff[S::P * t + x]];
       const uint32_t xt = prod ^ (0u - ((neg >> t) & 1u));
       const uint32_t wt = (wts >> (8 * t)) & 0xFFu;
-      acc_lo += __umul24(spread6(__builtin_amdgcn_ubfe(xt, 0, 4)), wt);
-      acc_hi += __umul24(spread6(__builtin_amdgcn_ubfe(xt, 4, 4)), wt);
+      if constexpr (LARGE) {
+        acc_lo += __umul24(spread3(xt), wt);
+        acc_hi += __umul24(spread3(xt >> 3), wt);
+        acc_x += __umul24(spread3(xt >> 6), wt);
+      } else {
+        acc_lo += __umul24(spread6(__builtin_amdgcn_ubfe(xt, 0, 4)), wt);
+        acc_hi += __umul24(spread6(__builtin_amdgcn_ubfe(xt, 4, 4)), wt);
+      }
     }
-    sb[(2 * q) * nc + j] = fields6_to_bytes(acc_lo);
-    sb[(2 * q + 1) * nc + j] = fields6_to_bytes(acc_hi);
+    if constexpr (LARGE) {
+      sb[(2 * q) * nc + j] = (acc_lo & 0xFFFFFFu) | (acc_hi << 24);
+      sb[(2 * q + 1) * nc + j] = ((acc_hi >> 8) & 0xFFFFu) | (acc_x << 16);
+    } else {
+      sb[(2 * q) * nc + j] = fields6_to_bytes(acc_lo);
+      sb[(2 * q + 1) * nc + j] = fields6_to_bytes(acc_hi);
+    }
   }
 }
 
@@ -439,7 +488,8 @@ __device__ __forceinline__ void wolff_replica(const HandleDev &H, const uint32_t
     const uint32_t padd = H.table[m];
     const uint32_t *arow = H.wacc + static_cast<size_t>(H.wrows > 1 ? m : 0) * H.wwidth + H.L * H.F;
     for (int c = 0; c < 4; ++c) {
-      wolff_bonds<KIND>(H, rec, lat, scr, c, static_cast<uint32_t>(m), c3, padd, lane);
+      if (H.F > kMidF) wolff_bonds<KIND, true>(H, rec, lat, scr, c, static_cast<uint32_t>(m), c3, padd, lane);
+      else wolff_bonds<KIND, false>(H, rec, lat, scr, c, static_cast<uint32_t>(m), c3, padd, lane);
       wave_sync();
       wolff_flips<KIND>(H, rec, lat, scr, c, static_cast<uint32_t>(m), c3, arow, lane);
       wave_sync();

@@ -77,6 +77,7 @@ _SIGS = {
     "sqa_device_logical": (_VP, [_VP]),
     "sqa_device_logical_energies": (_VP, [_VP]),
     "sqa_read_logical": (C.c_int, [_VP, _VP, C.c_size_t, _VP, C.c_size_t]),
+    "sqa_ground_state": (C.c_int, [C.POINTER(sqa_problem), C.POINTER(C.c_int32), _VP]),
     "sqa_random_trees": (C.c_int, [C.c_uint64, C.c_int32, C.c_int32, _VP]),
     "sqa_export_table": (C.c_int, [_VP, _VP, C.c_size_t, C.POINTER(C.c_int32)]),
     "sqa_export_wolff_tables": (C.c_int, [_VP, _VP, C.c_size_t, _VP, C.c_size_t, C.POINTER(C.c_int32),
@@ -261,6 +262,16 @@ def sqa_random_trees(seed: int, n: int, n_trees: int) -> np.ndarray:
     out = np.empty((n_trees, n), dtype=np.int32)
     _check(lib().sqa_random_trees(seed, n, n_trees, _ptr(out)))
     return out
+
+
+def sqa_ground_state(J, h=None):
+    """(ground energy, one ground state) of the logical problem, exhaustive on the device."""
+    prob, keep = make_problem(J, h)
+    n = int(np.asarray(J).shape[0])
+    E = C.c_int32()
+    state = np.empty(n, dtype=np.int8)
+    _check(lib().sqa_ground_state(C.byref(prob), C.byref(E), _ptr(state)))
+    return int(E.value), state
 
 
 def sqa_physical_sites(kind: int, n: int) -> int:

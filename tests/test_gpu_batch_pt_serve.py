@@ -243,3 +243,16 @@ def test_async_anneals_on_torch_streams(sqa):
         _, _, ospins, _ = O.sqa_anneal(s["kind"], s["J"], s["pen"], s["beta"], s["L"], s["M"], s["R"], s["g0"],
                                        s["g1"], s["seed"], nthreads=NTH)
         assert (h.spins() == ospins).all()
+
+
+@pytest.mark.parametrize("kind,N,pen", [(ME, 6, -40), (LHZ, 6, -30)])
+def test_pt_large_field_sums(sqa, kind, N, pen):
+    """PT with couplings in {+-1..+-10} and per-site field sums above 63."""
+    J = sk_instance(N, 650 + N, values=tuple(v for v in range(-10, 11) if v != 0))
+    emb = O.Embedding(kind, J, pen)
+    assert emb.fmax > 63
+    dev = sqa.PT(kind, J, pen, 0.01, 0.5, 8, 60, 1, 99).run()
+    spins, E, rep, acc = dev.read()
+    ospins, oE, orep, oacc = O.pt_run(emb, O.pt_ladder(0.01, 0.5, 8), 60, 1, 99)
+    assert (rep == orep).all() and (spins == ospins[orep]).all() and (E == oE[orep]).all()
+    assert (acc == oacc).all()

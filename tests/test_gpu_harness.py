@@ -1,0 +1,79 @@
+"""GPU tests of the exhaustive ground-state search and the penalty-scan harness:
+success probabilities equal those computed from the oracle's anneals, oracle
+decoders and oracle ground states."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1603_03755_amd.workloads import LHZ, ME, sk_instance
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sqa():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1603_03755_amd import sqa as s
+    s.lib()
+    return s
+
+
+@pytest.mark.parametrize("N,vals,with_h", [(2, (-1, 1), False), (3, (-5, 7), True), (8, (-1, 1), False),
+                                            (12, tuple(range(-10, 0)) + tuple(range(1, 11)), False),
+                                            (16, (-3, -1, 2), True), (21, (-1, 1), False),
+                                            (24, tuple(range(-10, 0)) + tuple(range(1, 11)), True)])
+def test_ground_state_matches_oracle(sqa, N, vals, with_h):
+    print(f"ground N={N}", flush=True)
+    rng = np.random.default_rng(N)
+    J = sk_instance(N, 70 + N, values=vals)
+    h = rng.integers(-6, 7, N).astype(np.int32) if with_h else None
+    E, state = sqa.sqa_ground_state(J, h)
+    E0, states, count = O.ground_states(J, h)
+    assert E == E0
+    assert O.logical_energy(J, state, h) == E0
+
+
+def test_ground_state_limits(sqa):
+    with pytest.raises(sqa.SqaError) as e:
+        sqa.sqa_ground_state(sk_instance(33, 1))
+    assert e.value.status == sqa.SQA_ERR_UNSUPPORTED
+    J = sk_instance(5, 1)
+    J[0, 1] = 40000
+    with pytest.raises(sqa.SqaError):
+        sqa.sqa_ground_state(J)
+
+
+def test_penalty_scan_equals_oracle(sqa):
+    """A small scan (2 instances, 3 penalties, both schemes, Wolff moves): every p_s
+    equals the one computed from the oracle's anneal, decoders and ground state."""
+    from paper_1603_03755_amd import harness as H
+    cfg = H.ScanConfig(sweeps=40, reads=12, slices=8, lhz_decoders=("mvd", "mwd", "bp"), trees=3)
+    instances = [H.paper_instance(5, 11), H.paper_instance(6, 12)]
+    penalties = [0.5, 1.5, 3.0]
+    res = H.penalty_scan(instances, penalties, cfg)
+    beta = cfg.beta_eff / H.SCALE
+    for i, J in enumerate(instances):
+        N = J.shape[0]
+        E0 = O.ground_states(J)[0]
+        assert res.ground_energy[i] == E0
+        trees = O.random_trees(cfg.seed + i, N, cfg.trees)
+        for k, lam in enumerate(penalties):
+            pen = H.penalty_coefficient(lam)
+            for kind in (ME, LHZ):
+                seed = cfg.seed + 1000 * i + 10 * k + kind
+                emb, _, spins, _ = O.sqa_anneal_wolff(kind, J, pen, beta, cfg.slices, cfg.sweeps, cfg.reads,
+                                                      H.SCALE * cfg.gamma_start, H.SCALE * cfg.gamma_end, seed,
+                                                      nthreads=8)
+                if kind == ME:
+                    ok = [O.logical_energy(J, O.me_majority(emb, spins[r, 0])) == E0 for r in range(cfg.reads)]
+                    assert res.p_s["me"][i, k] == np.mean(ok)
+                    continue
+                dec = {"mvd": lambda s: O.lhz_tree_decode(N, s, trees),
+                       "mwd": lambda s: O.lhz_mwd(N, s),
+                       "bp": lambda s: O.lhz_bp(N, s, trees[:1], 0.2, 10)[0]}
+                for d, fn in dec.items():
+                    ok = [O.logical_energy(J, fn(spins[r, 0])) == E0 for r in range(cfg.reads)]
+                    assert res.p_s["lhz_" + d][i, k] == np.mean(ok), (i, k, d)
+    pen_me, ps_me = res.optimal("me")
+    assert len(pen_me) == 2 and all(0 <= p <= 1 for p in ps_me)

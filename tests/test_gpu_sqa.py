@@ -148,3 +148,22 @@ def test_invalid_arguments_are_rejected(sqa):
         dev.anneal_range(5, 3)
     with pytest.raises(sqa.SqaError):
         dev.decode(sqa.SQA_DEC_LHZ_MWD)
+
+
+@pytest.mark.parametrize("kind,N,pen,L", [(ME, 6, -40, 8), (LHZ, 6, -30, 16), (LHZ, 5, -55, 10), (ME, 8, -30, 64)])
+def test_large_field_sums_bit_exact(sqa, kind, N, pen, L):
+    """Couplings in {+-1..+-10} (the paper's J in {+-0.1..+-1} times 10) and large
+    penalties: per-site field sums between 64 and 255 use 8-bit fields."""
+    J = sk_instance(N, 600 + N, values=tuple(v for v in range(-10, 11) if v != 0))
+    emb = O.Embedding(kind, J, pen)
+    assert 63 < emb.fmax <= 255
+    dev, emb, ospins, oE = _run_both(sqa, kind, J, pen, 0.4, L, 40, 5, 30.0, 0.1, 4242 + N)
+    assert (dev.spins() == ospins).all()
+    assert (dev.energies() == oE).all()
+
+
+def test_field_sum_limit(sqa):
+    J = sk_instance(5, 1, values=(-10, 10))
+    with pytest.raises(sqa.SqaError) as e:
+        sqa.SQA(LHZ, J, -70, 1.0, 8, 10, 2, 1.0, 0.1, 1)      # 10 + 4 * 70 > 255
+    assert e.value.status == sqa.SQA_ERR_UNSUPPORTED

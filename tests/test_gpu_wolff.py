@@ -202,3 +202,14 @@ def test_full_size_batched_workload_sampled(sqa):
         assert (E[r] == oE[0]).all(), (i, r)
         assert (O.sqa_energies(emb, spins) == E).all()
     b.close()
+
+
+@pytest.mark.parametrize("kind,N,pen,L", [(ME, 6, -40, 8), (LHZ, 6, -30, 64), (LHZ, 5, -55, 10)])
+def test_large_field_sums_beyond_63(sqa, kind, N, pen, L):
+    """Per-site field sums between 64 and 255 (8-bit fields in phase 1, cluster sums
+    up to L * 255)."""
+    J = sk_instance(N, 600 + N, values=tuple(v for v in range(-10, 11) if v != 0))
+    dev, emb, ospins, oE = _run_both(sqa, kind, J, pen, 0.4, L, 30, 5, 30.0, 0.1, 77 + N)
+    assert 63 < emb.fmax <= 255
+    assert (dev.spins() == ospins).all()
+    assert (dev.energies() == oE).all()
