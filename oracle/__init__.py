@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
-ME, LHZ = 0, 1
+ME, LHZ, MEC = 0, 1, 2
 STREAM_INIT, STREAM_SQA, STREAM_PT, STREAM_SWAP, STREAM_TREE, STREAM_PT_INIT, STREAM_WOLFF = 1, 2, 3, 4, 5, 6, 7
 ALWAYS = 0xFFFFFFFF
 
@@ -143,6 +143,22 @@ class Embedding:
 
 def me_site(N, i, r) -> int:
     return int(lib().oracle_me_site(N, i, r))
+
+
+def chimera_m(N) -> int:
+    return int(lib().oracle_chimera_m(N))
+
+
+def chimera_site(N, i, t) -> int:
+    """Physical site of slot t of chain i in the Chimera ME layout."""
+    return int(lib().oracle_chimera_site(N, i, t))
+
+
+def chimera_qubit(N, i, t):
+    """(row, column, side (0 = vertical, 1 = horizontal), k) of slot t of chain i."""
+    v = [C.c_int32() for _ in range(4)]
+    lib().oracle_chimera_qubit(N, i, t, *[C.byref(x) for x in v])
+    return tuple(int(x.value) for x in v)
 
 
 def lhz_site(N, i, j) -> int:

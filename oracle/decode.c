@@ -7,12 +7,14 @@
 #include "oracle.h"
 
 /* Eq. (4), Sec. II D: majority vote over each ME chain, qbar_i = sign sum_r q_{i,r}.
- * Tie (possible when the chain length N-1 is even) -> +1, a reading. */
+ * Tie (possible when the chain length is even) -> +1, a reading.  Chains of
+ * N-1 spins (clique chains) or ceil(N/4)+1 spins (Chimera). */
 void oracle_me_majority(const OEmb *e, const int8_t *slice, int8_t *logical) {
   int N = e->N;
+  int len = e->kind == OR_MEC ? oracle_chimera_m(N) + 1 : N - 1;
   for (int i = 0; i < N; ++i) {
     int sum = 0;
-    for (int r = 0; r < N - 1; ++r) sum += slice[oracle_me_site(N, i, r)];
+    for (int r = 0; r < len; ++r) sum += slice[i * len + r];
     logical[i] = (sum >= 0) ? (int8_t)1 : (int8_t)-1;
   }
 }

@@ -22,16 +22,47 @@
  * The triangle row along the diagonal is the three-body edge of the LHZ graph.
  * Logical fields need an ancilla qubit (Sec. II B) and are rejected here.
  *
+ * ME on Chimera (Sec. II A).  Chimera C_m is an m x m grid of K_{4,4} cells;
+ * qubit (r, c, side, k) with side V (vertical) or H (horizontal), k = 0..3.
+ * Couplers: inside a cell every V qubit with every H qubit; between cells
+ * V(r,c,k)-V(r+1,c,k) and H(r,c,k)-H(r,c+1,k).  The paper uses Choi's clique
+ * embedding with chains of ceil(N/4)+1 qubits (drawn only in a figure); the
+ * reading here is the triangle construction with m = ceil(N/4): logical spin i
+ * of block b = i/4, k = i%4, owns the H qubits of row b in columns 0..b and the
+ * V qubits of column b in rows b..m-1, m+1 qubits joined at cell (b, b).  Its
+ * chain slots t = 0..m are H(b, t, k) for t <= b and V(t-1, b, k) for t > b,
+ * physical site i(m+1)+t; consecutive slots are coupled with J_F.  Chains of
+ * blocks a < b meet in cell (b, a): J_ij (i in block a, j in block b) sits on
+ * V(b, a, k_i)-H(b, a, k_j), i.e. slot b+1 of chain i and slot a of chain j;
+ * chains of one block (k_i < k_j) meet in cell (a, a): slot a+1 of chain i
+ * (V) with slot a of chain j (H).  h_i sits on slot 0.
+ *
  * Colouring (a reading; the paper fixes no update order): four colours with
  * no term joining two sites of one colour,
  *   ME : colour(p(i,r)) = (r&1) | ((i&1)<<1)
- *   LHZ: colour(k(i,j)) = (i&1) | ((j&1)<<1).
+ *   LHZ: colour(k(i,j)) = (i&1) | ((j&1)<<1)
+ *   ME on Chimera: colour = (row + column + side) & 1, side H = 1 (Chimera is
+ *   bipartite: every coupler joins qubits of different colour).
  */
 #include <stdlib.h>
 #include <string.h>
 #include "oracle.h"
 
 int32_t oracle_me_site(int32_t N, int32_t i, int32_t r) { return i * (N - 1) + r; }
+
+int32_t oracle_chimera_m(int32_t N) { return (N + 3) / 4; }
+
+int32_t oracle_chimera_site(int32_t N, int32_t i, int32_t t) { return i * (oracle_chimera_m(N) + 1) + t; }
+
+/* Cell coordinates of slot t of chain i: row, column, side (0 = V, 1 = H), k. */
+void oracle_chimera_qubit(int32_t N, int32_t i, int32_t t, int32_t *row, int32_t *col, int32_t *side,
+                          int32_t *k) {
+  (void)N;
+  int b = i / 4;
+  *k = i % 4;
+  if (t <= b) { *row = b; *col = t; *side = 1; }
+  else { *row = t - 1; *col = b; *side = 0; }
+}
 
 int32_t oracle_lhz_site(int32_t N, int32_t i, int32_t j) {
   return i * (2 * N - i - 1) / 2 + (j - i - 1);
@@ -124,6 +155,28 @@ int oracle_embed(int32_t kind, int32_t N, const int32_t *J, const int32_t *h,
       for (int j = i + 2; j + 1 < N; ++j)
         add_term(e, penalty, oracle_lhz_site(N, i, j), oracle_lhz_site(N, i, j + 1),
                  oracle_lhz_site(N, i + 1, j), oracle_lhz_site(N, i + 1, j + 1));
+  } else if (kind == OR_MEC) {
+    if (N < 2) return -1;
+    int m = oracle_chimera_m(N);
+    int n = N * (m + 1);
+    alloc_emb(e, n, N * m + N * (N - 1) / 2);
+    for (int i = 0; i < N; ++i)
+      for (int t = 0; t <= m; ++t) {
+        int r, c, sd, k;
+        oracle_chimera_qubit(N, i, t, &r, &c, &sd, &k);
+        e->colour[oracle_chimera_site(N, i, t)] = (r + c + sd) & 1;
+      }
+    for (int i = 0; i < N; ++i)
+      for (int t = 0; t < m; ++t)
+        add_term(e, penalty, oracle_chimera_site(N, i, t), oracle_chimera_site(N, i, t + 1), -1, -1);
+    for (int i = 0; i < N; ++i)
+      for (int j = i + 1; j < N; ++j) {
+        int a = i / 4, b = j / 4;
+        /* V qubit of chain i in row b (slot b+1), H qubit of chain j in column a (slot a) */
+        add_term(e, J[i * N + j], oracle_chimera_site(N, i, b + 1), oracle_chimera_site(N, j, a), -1, -1);
+      }
+    if (h)
+      for (int i = 0; i < N; ++i) e->h[oracle_chimera_site(N, i, 0)] = h[i];
   } else {
     return -1;
   }

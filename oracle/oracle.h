@@ -31,11 +31,11 @@ extern "C" {
 enum { OR_STREAM_INIT = 1, OR_STREAM_SQA = 2, OR_STREAM_PT = 3,
        OR_STREAM_SWAP = 4, OR_STREAM_TREE = 5, OR_STREAM_PT_INIT = 6, OR_STREAM_WOLFF = 7 };
 
-enum { OR_ME = 0, OR_LHZ = 1 };
+enum { OR_ME = 0, OR_LHZ = 1, OR_MEC = 2 };
 
 /* A physical Hamiltonian: integer fields on sites plus k-body terms, k<=4. */
 typedef struct {
-  int32_t kind;       /* OR_ME or OR_LHZ */
+  int32_t kind;       /* OR_ME, OR_LHZ or OR_MEC */
   int32_t N;          /* logical spins */
   int32_t n_sites;
   int32_t n_terms;
@@ -64,6 +64,9 @@ int  oracle_embed(int32_t kind, int32_t N, const int32_t *J, const int32_t *h,
 void oracle_emb_free(OEmb *e);
 int32_t oracle_me_site(int32_t N, int32_t i, int32_t r);
 int32_t oracle_lhz_site(int32_t N, int32_t i, int32_t j);
+int32_t oracle_chimera_m(int32_t N);
+int32_t oracle_chimera_site(int32_t N, int32_t i, int32_t t);
+void oracle_chimera_qubit(int32_t N, int32_t i, int32_t t, int32_t *row, int32_t *col, int32_t *side, int32_t *k);
 int32_t oracle_local_field(const OEmb *e, const int8_t *s, int32_t k);
 int32_t oracle_energy(const OEmb *e, const int8_t *s);
 int32_t oracle_logical_energy(int32_t N, const int32_t *J, const int32_t *h, const int8_t *sigma);

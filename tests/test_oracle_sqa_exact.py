@@ -66,6 +66,8 @@ CASES = [
     (O.ME, 2, -1, (1, 1), 6, 3.0, 2.5, 1.0),
     (O.LHZ, 3, -2, None, 2, 5.0, 0.01, 1.0),   # nearly classical, stiff time bonds
     (O.LHZ, 3, -2, None, 4, 0.5, 20.0, 1.0),   # weak time bonds
+    (O.MEC, 3, -2, (1, 0, -1), 2, 1.1, 0.6, 1.0),   # Chimera chains of two
+    (O.MEC, 2, -1, (2, -1), 2, 1.5, 0.9, 0.8),
 ]
 
 
