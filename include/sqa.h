@@ -24,6 +24,12 @@
  *   - Physical site numbering.  ME: chain i, slot r -> i*(n-1)+r; J_ij (i<j)
  *     couples slot j-1 of chain i with slot i of chain j; h_i sits on slot 0.
  *     LHZ: pair (i,j), i<j -> i*(2n-i-1)/2 + (j-i-1).
+ *     ME on Chimera (Sec. II A, chains of ceil(n/4)+1 on the Chimera graph
+ *     C_m, m = ceil(n/4)): chain i (block b = i/4, k = i%4), slot t ->
+ *     i*(m+1)+t; slot t is the horizontal qubit (row b, column t, k) for
+ *     t <= b and the vertical qubit (row t-1, column b, k) for t > b; J_ij
+ *     (i<j) couples slot j/4+1 of chain i with slot i/4 of chain j (the
+ *     vertical and horizontal qubits of cell (j/4, i/4)); h_i on slot 0.
  *   - SQA state layout in host and device memory: [replica][slice][site]
  *     (slice-major), int8.  Energies: [replica][slice], int32.
  *   - All device work is asynchronous on the HIP stream passed as `stream`
@@ -63,7 +69,7 @@ typedef enum {
   SQA_ERR_NOT_READY = -6    /* server: result not finished yet */
 } sqa_status;
 
-typedef enum { SQA_EMB_ME = 0, SQA_EMB_LHZ = 1 } sqa_emb_kind;
+typedef enum { SQA_EMB_ME = 0, SQA_EMB_LHZ = 1, SQA_EMB_ME_CHIMERA = 2 } sqa_emb_kind;
 
 /* Eq. (1): H_P = sum_i h_i s_i + sum_{i<j} J_ij s_i s_j. */
 typedef struct {

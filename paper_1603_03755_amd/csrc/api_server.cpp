@@ -45,7 +45,7 @@ struct Job {
 size_t estimate_bytes(const Embedded &e, const sqa_schedule &s) {
   const size_t n = e.n, R = s.replicas, L = s.slices, M = s.sweeps;
   const size_t F = e.fmax;
-  const size_t rw = e.kind == SQA_EMB_ME ? kRecWordsME : kRecWordsLHZ;
+  const size_t rw = rec_words_of(e.kind);
   size_t b = R * L * n + R * L * 4 + n * (rw * 4 + 6) + e.terms.size() * 12;
   if (s.move == SQA_MOVE_WOLFF)
     b += M * 4 + (s.bscale ? M : 1) * (2 * L * F + 1) * 4;   // join thresholds, acceptance rows

@@ -153,7 +153,7 @@ static std::string shape_class(const std::vector<const sqa_handle *> &hs) {
   for (const sqa_handle *h : hs) {
     maxcells = std::max(maxcells, h->emb.n * h->L);
     maxrep = std::max(maxrep, h->R);
-    (h->emb.kind == SQA_EMB_ME ? me : lhz) = true;
+    (h->emb.kind == SQA_EMB_LHZ ? lhz : me) = true;
     wolff = wolff || h->move == kMoveWolff;
   }
   auto p2 = [](int v) {
@@ -250,6 +250,7 @@ const char *sqa_version(void) { return "sqa-mi355x 0.1 (gfx950)"; }
 int64_t sqa_physical_sites(int32_t kind, int32_t n) {
   if (kind == SQA_EMB_ME) return n >= 2 ? static_cast<int64_t>(n) * (n - 1) : -1;
   if (kind == SQA_EMB_LHZ) return n >= 3 ? static_cast<int64_t>(n) * (n - 1) / 2 : -1;
+  if (kind == SQA_EMB_ME_CHIMERA) return n >= 2 ? static_cast<int64_t>(n) * ((n + 3) / 4 + 1) : -1;
   return -1;
 }
 
@@ -619,10 +620,12 @@ sqa_status sqa_decode_ex(sqa_handle *h, const sqa_decode_params *prm, int8_t *lo
   const int32_t *dh = h->has_h ? h->arena.at<int32_t>(h->off_h) : nullptr;
   hipError_t e = hipSuccess;
   if (p.decoder == SQA_DEC_ME_MAJORITY) {
-    if (h->emb.kind != SQA_EMB_ME) return fail(SQA_ERR_INVALID, "majority decoding of chains needs an ME handle");
+    if (h->emb.kind != SQA_EMB_ME && h->emb.kind != SQA_EMB_ME_CHIMERA)
+      return fail(SQA_ERR_INVALID, "majority decoding of chains needs an ME handle");
+    const int len = h->emb.kind == SQA_EMB_ME ? N - 1 : (N + 3) / 4 + 1;
     e = hipStreamWaitEvent(s, h->done, 0);
     if (e == hipSuccess)
-      e = launch_me_majority(spins, R, N, n, L, p.readout_slice, dJ, dh, logical, lenergy, s);
+      e = launch_me_majority(spins, R, N, len, n, L, p.readout_slice, dJ, dh, logical, lenergy, s);
   } else {
     if (p.decoder != SQA_DEC_LHZ_TREES && p.decoder != SQA_DEC_LHZ_MWD && p.decoder != SQA_DEC_LHZ_MLD &&
         p.decoder != SQA_DEC_LHZ_BP)

@@ -52,14 +52,40 @@ __device__ __forceinline__ uint32_t bit_at(uint32_t v, int q) { return (v >> q) 
 template <int KIND>
 struct Site;
 
+// T terms per site, P partners per term, RW record words, HB negmask bit of h.
 template <>
 struct Site<kKindME> {
-  static constexpr int T = 3, P = 1, RW = kRecWordsME;
+  static constexpr int T = 3, P = 1, RW = kRecWordsME, HB = 4;
 };
 template <>
 struct Site<kKindLHZ> {
-  static constexpr int T = 4, P = 3, RW = kRecWordsLHZ;
+  static constexpr int T = 4, P = 3, RW = kRecWordsLHZ, HB = 4;
 };
+template <>
+struct Site<kKindMEC> {
+  static constexpr int T = 6, P = 1, RW = kRecWordsMEC, HB = kFieldSignMEC;
+};
+
+// Record of an ME-on-Chimera site: site, base, term weights, |h|, signs, partners.
+__device__ __forceinline__ void load_rec_mec(const uint32_t *r, uint32_t &site, uint32_t &base, uint32_t &wts,
+                                             uint32_t &wts2, uint32_t &hw, uint32_t &neg, uint32_t *poff) {
+  const uint4 r0 = *reinterpret_cast<const uint4 *>(r);
+  const uint2 r1 = *reinterpret_cast<const uint2 *>(r + 4);
+  site = r0.x & 0xFFFFu;
+  base = r0.x >> 16;
+  wts = r0.y;
+  wts2 = r0.z & 0xFFFFu;
+  hw = (r0.z >> 16) & 0xFFu;
+  neg = r0.z >> 24;
+  poff[0] = r0.w & 0xFFFFu; poff[1] = r0.w >> 16;
+  poff[2] = r1.x & 0xFFFFu; poff[3] = r1.x >> 16;
+  poff[4] = r1.y & 0xFFFFu; poff[5] = r1.y >> 16;
+}
+
+// Weight byte of term t (t < 4 from the first weight word, else the second).
+__device__ __forceinline__ uint32_t term_weight(uint32_t wts, uint32_t wts2, int t) {
+  return t < 4 ? ((wts >> (8 * t)) & 0xFFu) : ((wts2 >> (8 * (t - 4))) & 0xFFu);
+}
 
 // Four bits of a nibble moved to bit 0 of four 6-bit fields (bits 0, 6, 12,
 // 18): every partial product of the 24-bit multiply lands on a distinct bit.

@@ -14,6 +14,7 @@ namespace sqa {
 
 constexpr int kKindME = 0;
 constexpr int kKindLHZ = 1;
+constexpr int kKindMEC = 2;     // ME on Chimera
 
 // Per-site records, kind-specific layouts (32-bit words):
 //  ME  (4 words, 16 B): terms T=3, one partner each
@@ -30,7 +31,13 @@ constexpr int kKindLHZ = 1;
 //    w3 = 0
 //    w4..w9 = part[0..11] as u16 pairs (term t partner q at index 3t+q)
 //    w10, w11 = 0
-// negmask bit t (t < 4): weight of term t is negative; bit 4: h < 0.
+//  ME on Chimera (8 words, 32 B): terms T=6, one partner each
+//    w0 = site | base << 16
+//    w1 = |w0..w3| bytes
+//    w2 = |w4| | |w5| << 8 | |h| << 16 | negmask << 24
+//    w3..w5 = part[0..5] as u16 pairs, w6 = w7 = 0
+// negmask bit t (t < T): weight of term t is negative; h < 0 is bit 4 (ME,
+// LHZ) or bit 6 (ME on Chimera).
 // base = 3 * (F_site + F) + 2, F_site = |h| + sum |w_t|.
 // Weights |w|, |h| in the records are stored multiplied by 6 when F <= kSmallF
 // (the sweep kernel then indexes the table with the field sums directly).
@@ -42,6 +49,12 @@ constexpr int kLargeF = 255;
 constexpr int kFieldSmall = 0, kFieldMid = 1, kFieldLarge = 2;
 constexpr int kRecWordsME = 4;
 constexpr int kRecWordsLHZ = 12;
+constexpr int kRecWordsMEC = 8;
+constexpr int kFieldSignMEC = 6;
+
+constexpr int rec_words_of(int kind) {
+  return kind == kKindME ? kRecWordsME : (kind == kKindMEC ? kRecWordsMEC : kRecWordsLHZ);
+}
 
 constexpr uint32_t kStreamInit = 1;
 constexpr uint32_t kStreamSQA = 2;

@@ -89,6 +89,32 @@ sqa_status build_embedding(const sqa_problem &p, const sqa_embedding &em, Embedd
       for (int32_t j = i + 2; j + 1 < N; ++j)
         push_term(&e, em.penalty,
                   {lhz_index(N, i, j), lhz_index(N, i, j + 1), lhz_index(N, i + 1, j), lhz_index(N, i + 1, j + 1)});
+  } else if (em.kind == SQA_EMB_ME_CHIMERA) {
+    // ME on Chimera C_m, m = ceil(N/4) (Sec. II A): logical spin i, block b = i/4,
+    // k = i%4, is the chain of m+1 qubits H(b, 0..b, k) then V(b..m-1, b, k);
+    // site i(m+1)+t is its slot t (t <= b: H(b, t, k); t > b: V(t-1, b, k)).
+    // Chain bonds J_F between consecutive slots; the chains of i < j (blocks
+    // a <= b) meet in cell (b, a), where J_ij couples V(b, a, k_i) (slot b+1 of
+    // chain i) with H(b, a, k_j) (slot a of chain j).  h_i on slot 0.
+    // Colour (row + column + side) & 1, side H = 1: Chimera is bipartite.
+    if (N < 2 || N > 256) return fail(SQA_ERR_INVALID, "ME on Chimera needs 2 <= n <= 256");
+    const int32_t m = (N + 3) / 4, len = m + 1;
+    e.n = N * len;
+    e.h.assign(e.n, 0);
+    e.colour.assign(e.n, 0);
+    for (int32_t i = 0; i < N; ++i) {
+      const int32_t b = i / 4;
+      for (int32_t t = 0; t < len; ++t) {
+        const bool horiz = t <= b;
+        const int32_t row = horiz ? b : t - 1, col = horiz ? t : b;
+        e.colour[i * len + t] = (row + col + (horiz ? 1 : 0)) & 1;
+      }
+      for (int32_t t = 0; t + 1 < len; ++t) push_term(&e, em.penalty, {i * len + t, i * len + t + 1});
+    }
+    for (int32_t i = 0; i < N; ++i)
+      for (int32_t j = i + 1; j < N; ++j) push_term(&e, p.J[i * N + j], {i * len + j / 4 + 1, j * len + i / 4});
+    if (p.h)
+      for (int32_t i = 0; i < N; ++i) e.h[i * len] = p.h[i];
   } else {
     return fail(SQA_ERR_INVALID, "unknown embedding kind");
   }
@@ -113,9 +139,9 @@ sqa_status build_embedding(const sqa_problem &p, const sqa_embedding &em, Embedd
 sqa_status build_layout(const Embedded &emb, int32_t F, bool scale6, DeviceLayout *out) {
   DeviceLayout L;
   const int32_t n = emb.n;
-  const bool me = emb.kind == SQA_EMB_ME;
-  const int T = me ? 3 : 4, P = me ? 1 : 3;
-  L.rec_words = me ? kRecWordsME : kRecWordsLHZ;
+  const bool me = emb.kind == SQA_EMB_ME, mec = emb.kind == SQA_EMB_ME_CHIMERA;
+  const int T = me ? 3 : (mec ? 6 : 4), P = (me || mec) ? 1 : 3;
+  L.rec_words = me ? kRecWordsME : (mec ? kRecWordsMEC : kRecWordsLHZ);
   // colour-sorted device order, increasing physical index within a class
   L.phys_of.reserve(n);
   for (int c = 0; c < 4; ++c) {
@@ -137,7 +163,7 @@ sqa_status build_layout(const Embedded &emb, int32_t F, bool scale6, DeviceLayou
   for (int32_t d = 0; d < n; ++d) {
     const int32_t k = L.phys_of[d];
     if (static_cast<int>(inc[k].size()) > T) return fail(SQA_ERR_UNSUPPORTED, "site with too many terms");
-    uint32_t aw[4] = {0, 0, 0, 0};
+    uint32_t aw[6] = {0, 0, 0, 0, 0, 0};
     uint32_t neg = 0;
     uint32_t part[12];   // byte offsets of the partners' lattice words
     for (int q = 0; q < 12; ++q) part[q] = 8u * zero;
@@ -152,10 +178,10 @@ sqa_status build_layout(const Embedded &emb, int32_t F, bool scale6, DeviceLayou
         if (t.s[z] != k) part[P * a + (q++)] = 8u * L.dev_of[t.s[z]];
       if (q > P) return fail(SQA_ERR_UNSUPPORTED, "term arity above the kernel limit");
     }
-    if (emb.h[k] < 0) neg |= 1u << 4;
+    if (emb.h[k] < 0) neg |= 1u << (mec ? kFieldSignMEC : 4);
     uint32_t ah = static_cast<uint32_t>(std::abs(emb.h[k]));
     if (scale6 && F <= kSmallF) {        // the SQA kernel sums 6|w| directly
-      for (int a = 0; a < 4; ++a) aw[a] *= 6u;
+      for (int a = 0; a < 6; ++a) aw[a] *= 6u;
       ah *= 6u;
     }
     const uint32_t base = static_cast<uint32_t>(3 * (fs + F) + 2);
@@ -165,6 +191,10 @@ sqa_status build_layout(const Embedded &emb, int32_t F, bool scale6, DeviceLayou
       r[1] = aw[0] | (aw[1] << 8) | (aw[2] << 16) | (ah << 24);
       r[2] = neg | (part[0] << 16);
       r[3] = part[1] | (part[2] << 16);
+    } else if (mec) {
+      r[1] = aw[0] | (aw[1] << 8) | (aw[2] << 16) | (aw[3] << 24);
+      r[2] = aw[4] | (aw[5] << 8) | (ah << 16) | (neg << 24);
+      for (int q = 0; q < 3; ++q) r[3 + q] = part[2 * q] | (part[2 * q + 1] << 16);
     } else {
       r[1] = aw[0] | (aw[1] << 8) | (aw[2] << 16) | (aw[3] << 24);
       r[2] = ah | (neg << 8);

@@ -93,8 +93,9 @@ hipError_t launch_sqa_anneal(int move, const HandleDev *hds, const WorkItem *ite
 hipError_t set_sqa_anneal_lds_limit(size_t bytes);
 int sqa_anneal_occupancy(int move, int waves, size_t lds_bytes);
 hipError_t launch_sqa_init(const HandleDev &H, hipStream_t stream);
-hipError_t launch_me_majority(const int8_t *spins, int R, int N, int n_sites, int L, int slice, const int32_t *J,
-                              const int32_t *h, int8_t *logical, int32_t *energy, hipStream_t stream);
+hipError_t launch_me_majority(const int8_t *spins, int R, int N, int len, int n_sites, int L, int slice,
+                              const int32_t *J, const int32_t *h, int8_t *logical, int32_t *energy,
+                              hipStream_t stream);
 hipError_t launch_lhz_rows(const int8_t *spins, int R, int L, int K, int N, int slice, uint32_t *rows, hipStream_t s);
 hipError_t launch_lhz_mwd(const uint32_t *rows, int R, int N, unsigned long long *best, int8_t *logical,
                           hipStream_t s);

@@ -38,12 +38,17 @@ __device__ void pt_ladder(const PTDev &P, const uint32_t *rec, uint64_t *lat, co
         if (!group_live) continue;
         const int d = lo + it / RG;
         const uint32_t *r = rec + d * S::RW;
-        uint32_t site, base, aw[4], ah, neg;
+        uint32_t site, base, aw[S::T], ah, neg;
         uint32_t part[S::T * S::P];
-        if constexpr (KIND == kKindME) {
+        if constexpr (KIND == kKindMEC) {
+          uint32_t w1, w2;
+          load_rec_mec(r, site, base, w1, w2, ah, neg, part);
+#pragma unroll
+          for (int t = 0; t < S::T; ++t) aw[t] = term_weight(w1, w2, t);
+        } else if constexpr (KIND == kKindME) {
           const uint4 r0 = *reinterpret_cast<const uint4 *>(r);
           site = r0.x & 0xFFFFu; base = r0.x >> 16;
-          aw[0] = r0.y & 0xFFu; aw[1] = (r0.y >> 8) & 0xFFu; aw[2] = (r0.y >> 16) & 0xFFu; aw[3] = 0;
+          aw[0] = r0.y & 0xFFu; aw[1] = (r0.y >> 8) & 0xFFu; aw[2] = (r0.y >> 16) & 0xFFu;
           ah = r0.y >> 24;
           neg = r0.z & 0xFFu;
           part[0] = r0.z >> 16; part[1] = r0.w & 0xFFFFu; part[2] = r0.w >> 16;
@@ -74,7 +79,7 @@ __device__ void pt_ladder(const PTDev &P, const uint32_t *rec, uint64_t *lat, co
           for (int q = 0; q < S::P; ++q) prod ^= latb[part[S::P * t + q] + byte];
           X[t] = own ^ (prod >> nsh) ^ (0u - ((neg >> t) & 1u));
         }
-        const uint32_t O = own ^ (0u - ((neg >> 4) & 1u));
+        const uint32_t O = own ^ (0u - ((neg >> S::HB) & 1u));
         const Words4 u = philox4x32_10(site, static_cast<uint32_t>(a), static_cast<uint32_t>(m), kStreamPT << 24,
                                        P.seed_lo, P.seed_hi);
         uint32_t flip = 0;
@@ -148,7 +153,7 @@ __global__ __launch_bounds__(1024) void pt_kernel(const PTDev *__restrict__ pts,
   int32_t *slot_of = rep_at + 64;
   uint32_t *acc = reinterpret_cast<uint32_t *>(slot_of + 64);
   const int tid = threadIdx.x, nth = blockDim.x;
-  const int rw = (P.kind == kKindME) ? kRecWordsME : kRecWordsLHZ;
+  const int rw = rec_words_of(P.kind);
   for (int i = tid; i < P.n * rw; i += nth) rec[i] = P.rec[i];
   const int width = 2 * P.F + 1;
   for (int i = tid; i < P.R * width; i += nth) mtab[i] = P.mtab[i];
@@ -185,7 +190,8 @@ __global__ __launch_bounds__(1024) void pt_kernel(const PTDev *__restrict__ pts,
   }
   __syncthreads();
   if (P.kind == kKindME) pt_ladder<kKindME>(P, rec, lat, mtab, E, rep_at, slot_of, acc);
-  else pt_ladder<kKindLHZ>(P, rec, lat, mtab, E, rep_at, slot_of, acc);
+  else if (P.kind == kKindLHZ) pt_ladder<kKindLHZ>(P, rec, lat, mtab, E, rep_at, slot_of, acc);
+  else pt_ladder<kKindMEC>(P, rec, lat, mtab, E, rep_at, slot_of, acc);
   // results: spins by replica in physical order, energies by replica, slot map, swap counts
   for (size_t i = tid; i < static_cast<size_t>(P.R) * P.n; i += nth) {
     const int rho = static_cast<int>(i / P.n), k = static_cast<int>(i % P.n);

@@ -37,7 +37,7 @@ __device__ __forceinline__ void init_lattice(const HandleDev &H, uint64_t *lat, 
   const int L = H.L, n = H.n;
   const int G = (L + 7) >> 3;
   const uint32_t c3 = (kStreamInit << 24) | static_cast<uint32_t>(rep);
-  const int rw = (H.kind == kKindME) ? kRecWordsME : kRecWordsLHZ;
+  const int rw = rec_words_of(H.kind);
   for (int d = lane; d < n; d += 64) {
     const uint32_t site = H.rec[d * rw] & 0xFFFFu;
     uint64_t w = 0;
@@ -136,7 +136,7 @@ __device__ __forceinline__ void sweep_class(const HandleDev &H, const uint32_t *
     const int d = lo + j;
     const uint32_t *r = rec + d * S::RW;
 
-    uint32_t site, base, wts, hw, neg;
+    uint32_t site, base, wts, wts2 = 0, hw, neg;
     uint32_t poff[S::T * S::P];
     if constexpr (KIND == kKindME) {
       const uint4 r0 = *reinterpret_cast<const uint4 *>(r);
@@ -145,6 +145,8 @@ __device__ __forceinline__ void sweep_class(const HandleDev &H, const uint32_t *
       hw = r0.y >> 24;
       neg = r0.z & 0xFFu;
       poff[0] = r0.z >> 16; poff[1] = r0.w & 0xFFFFu; poff[2] = r0.w >> 16;
+    } else if constexpr (KIND == kKindMEC) {
+      load_rec_mec(r, site, base, wts, wts2, hw, neg, poff);
     } else {
       const uint4 r0 = *reinterpret_cast<const uint4 *>(r);
       const uint4 r1 = *reinterpret_cast<const uint4 *>(r + 4);
@@ -160,7 +162,7 @@ __device__ __forceinline__ void sweep_class(const HandleDev &H, const uint32_t *
         poff[2 * q + 1] = pw[q] >> 16;
       }
     }
-    const uint32_t negh = 0u - ((neg >> 4) & 1u);   // 0 or all ones: field sign
+    const uint32_t negh = 0u - ((neg >> S::HB) & 1u);   // 0 or all ones: field sign
 
     const uint2 word = *reinterpret_cast<const uint2 *>(lat32 + 2 * d);
     const uint32_t own_half = p ? word.y : word.x;
@@ -210,7 +212,7 @@ __device__ __forceinline__ void sweep_class(const HandleDev &H, const uint32_t *
 #pragma unroll
       for (int q = 0; q < S::P; ++q) prod ^= lb[poff[S::P * t + q]];
       const uint32_t x = prod ^ (0u - ((neg >> t) & 1u));
-      const uint32_t wt = (wts >> (8 * t)) & 0xFFu;
+      const uint32_t wt = term_weight(wts, wts2, t);
       if constexpr (MODE == kFieldLarge) {
         acc_lo += __umul24(spread3(x), wt);
         acc_hi += __umul24(spread3(x >> 3), wt);
@@ -363,7 +365,7 @@ __device__ __forceinline__ void wolff_bonds(const HandleDev &H, const uint32_t *
     if (j >= nc) { j -= nc; q += 1; }
     const int d = lo + j;
     const uint32_t *r = rec + d * S::RW;
-    uint32_t site, wts, hw, neg;
+    uint32_t site, wts, wts2 = 0, hw, neg;
     uint32_t poff[S::T * S::P];
     if constexpr (KIND == kKindME) {
       const uint4 r0 = *reinterpret_cast<const uint4 *>(r);
@@ -372,6 +374,9 @@ __device__ __forceinline__ void wolff_bonds(const HandleDev &H, const uint32_t *
       hw = r0.y >> 24;
       neg = r0.z & 0xFFu;
       poff[0] = r0.z >> 16; poff[1] = r0.w & 0xFFFFu; poff[2] = r0.w >> 16;
+    } else if constexpr (KIND == kKindMEC) {
+      uint32_t base_unused;
+      load_rec_mec(r, site, base_unused, wts, wts2, hw, neg, poff);
     } else {
       const uint4 r0 = *reinterpret_cast<const uint4 *>(r);
       const uint4 r1 = *reinterpret_cast<const uint4 *>(r + 4);
@@ -410,7 +415,7 @@ __device__ __forceinline__ void wolff_bonds(const HandleDev &H, const uint32_t *
     // acc_lo, 8q+4..8q+7 in acc_hi), else in 8-bit fields three slices per word
     // (acc_lo 0-2, acc_hi 3-5, acc_x 6-7); both keep the operands of the 24-bit
     // multiplies below 2^24.  Repacked to one byte per slice for the store.
-    const uint32_t negh = 0u - ((neg >> 4) & 1u);
+    const uint32_t negh = 0u - ((neg >> S::HB) & 1u);
     const uint8_t *lb = latb + q;
     const uint32_t ox = (own ^ negh) & 0xFFu;
     uint32_t acc_lo, acc_hi, acc_x = 0;
@@ -428,7 +433,7 @@ __device__ __forceinline__ void wolff_bonds(const HandleDev &H, const uint32_t *
 #pragma unroll
       for (int x = 0; x < S::P; ++x) prod ^= lb[poff[S::P * t + x]];
       const uint32_t xt = prod ^ (0u - ((neg >> t) & 1u));
-      const uint32_t wt = (wts >> (8 * t)) & 0xFFu;
+      const uint32_t wt = term_weight(wts, wts2, t);
       if constexpr (LARGE) {
         acc_lo += __umul24(spread3(xt), wt);
         acc_hi += __umul24(spread3(xt >> 3), wt);
@@ -464,8 +469,11 @@ __device__ __forceinline__ void wolff_flips(const HandleDev &H, const uint32_t *
     const uint4 r0 = *reinterpret_cast<const uint4 *>(rec + d * S::RW);
     const uint32_t site = r0.x & 0xFFFFu;
     // F_site = |h| + sum |w_t|: the bytes of record word 1 (and, for LHZ, |h|)
-    const uint32_t fs = (KIND == kKindME) ? __builtin_amdgcn_sad_u8(r0.y, 0u, 0u)
-                                          : __builtin_amdgcn_sad_u8(r0.y, 0u, r0.z & 0xFFu);
+    // (ME: w0..w2, |h|; LHZ: w0..w3 then |h|; ME on Chimera: w0..w3 then w4, w5, |h|)
+    const uint32_t fs = (KIND == kKindME)    ? __builtin_amdgcn_sad_u8(r0.y, 0u, 0u)
+                        : (KIND == kKindLHZ) ? __builtin_amdgcn_sad_u8(r0.y, 0u, r0.z & 0xFFu)
+                                             : __builtin_amdgcn_sad_u8(r0.y, 0u,
+                                                   __builtin_amdgcn_sad_u8(r0.z & 0xFFFFFFu, 0u, 0u));
     const Words4 u = philox4x32_10(site, kWolffSiteCtr, m, c3, H.seed_lo, H.seed_hi);
     const int t0 = static_cast<int>(__umulhi(u.v[0], static_cast<uint32_t>(L)));
     const uint64_t cl = ring_cluster(jw[j], t0, L);
@@ -529,17 +537,19 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(SQA_WAVES_P
     if (it >= n_items) break;
     const WorkItem wi = items[it];
     const HandleDev &H = hds[wi.handle];      // read in place: uniform fields become scalar loads
-    const int rw = (H.kind == kKindME) ? kRecWordsME : kRecWordsLHZ;
+    const int rw = rec_words_of(H.kind);
     const int nwords = H.n * rw;
     for (int i = threadIdx.x; i < nwords; i += blockDim.x) rec[i] = H.rec[i];
     __syncthreads();
     if (wave < wi.nrep) {
       if constexpr (MOVE == kMoveWolff) {
         if (H.kind == kKindME) wolff_replica<kKindME>(H, rec, lat, tab, wi.rep0 + wave, lane);
-        else wolff_replica<kKindLHZ>(H, rec, lat, tab, wi.rep0 + wave, lane);
+        else if (H.kind == kKindLHZ) wolff_replica<kKindLHZ>(H, rec, lat, tab, wi.rep0 + wave, lane);
+        else wolff_replica<kKindMEC>(H, rec, lat, tab, wi.rep0 + wave, lane);
       } else {
         if (H.kind == kKindME) anneal_replica<kKindME>(H, rec, lat, tab, wi.rep0 + wave, lane);
-        else anneal_replica<kKindLHZ>(H, rec, lat, tab, wi.rep0 + wave, lane);
+        else if (H.kind == kKindLHZ) anneal_replica<kKindLHZ>(H, rec, lat, tab, wi.rep0 + wave, lane);
+        else anneal_replica<kKindMEC>(H, rec, lat, tab, wi.rep0 + wave, lane);
       }
     }
     __syncthreads();
@@ -575,9 +585,11 @@ __global__ void sqa_init_kernel(HandleDev H) {
 }
 
 // ------------------------------------------------------ ME majority vote
-// Eq. (4): qbar_i = sign(sum_r s_{i(N-1)+r}) on slice `slice`, tie -> +1, and
-// the logical energy of Eq. (1).  One workgroup per replica, thread i <-> chain i.
-__global__ void me_majority_kernel(const int8_t *__restrict__ spins, int N, int n_sites, int L, int slice,
+// Eq. (4): qbar_i = sign(sum_r s_{i len + r}) on slice `slice`, tie -> +1, and
+// the logical energy of Eq. (1); chains of len = N-1 (clique chains) or
+// ceil(N/4)+1 (Chimera) consecutive sites.  One workgroup per replica, thread
+// i <-> chain i.
+__global__ void me_majority_kernel(const int8_t *__restrict__ spins, int N, int len, int n_sites, int L, int slice,
                                    const int32_t *__restrict__ J, const int32_t *__restrict__ h,
                                    int8_t *__restrict__ logical, int32_t *__restrict__ energy) {
   __shared__ int8_t q[256];
@@ -586,7 +598,7 @@ __global__ void me_majority_kernel(const int8_t *__restrict__ spins, int N, int 
   const int8_t *s = spins + (static_cast<size_t>(rep) * L + slice) * n_sites;
   for (int i = threadIdx.x; i < N; i += blockDim.x) {
     int sum = 0;
-    for (int r = 0; r < N - 1; ++r) sum += s[i * (N - 1) + r];
+    for (int r = 0; r < len; ++r) sum += s[i * len + r];
     q[i] = (sum >= 0) ? int8_t(1) : int8_t(-1);
     if (logical) logical[static_cast<size_t>(rep) * N + i] = q[i];
   }
@@ -656,10 +668,11 @@ hipError_t launch_sqa_init(const HandleDev &H, hipStream_t stream) {
   return hipGetLastError();
 }
 
-hipError_t launch_me_majority(const int8_t *spins, int R, int N, int n_sites, int L, int slice, const int32_t *J,
-                              const int32_t *h, int8_t *logical, int32_t *energy, hipStream_t stream) {
+hipError_t launch_me_majority(const int8_t *spins, int R, int N, int len, int n_sites, int L, int slice,
+                              const int32_t *J, const int32_t *h, int8_t *logical, int32_t *energy,
+                              hipStream_t stream) {
   (void)hipGetLastError();
-  hipLaunchKernelGGL(me_majority_kernel, dim3(R), dim3(256), 0, stream, spins, N, n_sites, L, slice, J, h,
+  hipLaunchKernelGGL(me_majority_kernel, dim3(R), dim3(256), 0, stream, spins, N, len, n_sites, L, slice, J, h,
                      logical, energy);
   return hipGetLastError();
 }

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libsqa.so")
 
 SQA_OK, SQA_ERR_INVALID, SQA_ERR_OOM, SQA_ERR_DEVICE, SQA_ERR_UNSUPPORTED, SQA_ERR_BUSY, SQA_ERR_NOT_READY = \
     0, -1, -2, -3, -4, -5, -6
-SQA_EMB_ME, SQA_EMB_LHZ = 0, 1
+SQA_EMB_ME, SQA_EMB_LHZ, SQA_EMB_ME_CHIMERA = 0, 1, 2
 SQA_DEC_ME_MAJORITY, SQA_DEC_LHZ_TREES, SQA_DEC_LHZ_MWD, SQA_DEC_LHZ_MLD, SQA_DEC_LHZ_BP = 0, 1, 2, 3, 4
 SQA_MOVE_METROPOLIS, SQA_MOVE_WOLFF = 0, 1
 

@@ -19,6 +19,7 @@ import numpy as np
 
 ME = 0
 LHZ = 1
+MEC = 2          # ME on Chimera, chains of ceil(n/4)+1
 
 SEED_SMALL = 1603          # the N=8 instance shared by the ME and LHZ single runs
 SEED_BATCH = 20_000        # batched workload: instance i uses SEED_BATCH + i
@@ -39,7 +40,10 @@ def sk_instance(n: int, seed: int, values=(-1, 1)) -> np.ndarray:
 
 
 def n_sites(kind: int, n: int) -> int:
-    """Physical spin count of the clique-chain ME (n(n-1)) and LHZ (n(n-1)/2) layouts."""
+    """Physical spin count of the clique-chain ME (n(n-1)), LHZ (n(n-1)/2) and
+    Chimera ME (n(ceil(n/4)+1)) layouts."""
+    if kind == MEC:
+        return n * ((n + 3) // 4 + 1)
     return n * (n - 1) if kind == ME else n * (n - 1) // 2
 
 
