@@ -173,14 +173,15 @@ def wolff_leg(sqa, O, jobs, stream, metropolis_kernel_s, traffic):
 
 def scan_leg(sqa):
     """The paper's experiment shape on synthetic K8 instances (J in {+-0.1..+-1}, times 10):
-    8 instances x 6 penalty strengths x {ME, LHZ}, 1000 reads each, L = 64, 10^4 sweeps,
-    Wolff moves, one batched launch; p_s from device decoding against device ground states."""
+    8 instances x 6 penalty strengths x {ME on Chimera, clique-chain ME, LHZ}, 1000 reads
+    each, L = 64, 10^4 sweeps, Wolff moves, one batched launch; p_s from device decoding
+    against device ground states."""
     from paper_1603_03755_amd import harness as H
     from paper_1603_03755_amd.workloads import SEED_BATCH
     instances = [H.paper_instance(8, SEED_BATCH + 7000 + i) for i in range(8)]
     penalties = [0.5, 1.0, 1.5, 2.0, 2.5, 3.0]
     t0 = time.perf_counter()
-    res = H.penalty_scan(instances, penalties, H.ScanConfig())
+    res = H.penalty_scan(instances, penalties, H.ScanConfig(schemes=("mec", "me", "lhz")))
     total = time.perf_counter() - t0
     summary = {}
     for scheme in res.p_s:

@@ -1,10 +1,11 @@
 """Penalty-scan harness: the experiment shape of Sec. III (Figs. 3-7) on
 synthetic instances.
 
-For every instance and every penalty strength lambda, both embeddings (ME and
-LHZ, Sec. II A / II B) are annealed with SQA, every replica's readout slice is
-decoded, and the success probability p_s is the fraction of replicas whose
-decoded logical state is a ground state of Eq. (1).  The optimal penalty of an
+For every instance and every penalty strength lambda, the embeddings (ME on
+Chimera as in the paper, optionally the clique-chain ME, and LHZ; Sec. II A /
+II B) are annealed with SQA, every replica's readout slice is decoded, and the
+success probability p_s is the fraction of replicas whose decoded logical
+state is a ground state of Eq. (1).  The optimal penalty of an
 instance and scheme is the lambda with the largest p_s (Fig. 5).
 
 Units.  The paper's couplings are J_ij in {+-0.1, ..., +-1} (Sec. III).  The
@@ -31,7 +32,9 @@ from typing import Dict, List, Sequence
 import numpy as np
 
 from . import sqa
-from .workloads import LHZ, ME, sk_instance
+from .workloads import LHZ, ME, MEC, sk_instance
+
+KINDS = {"mec": MEC, "me": ME, "lhz": LHZ}
 
 SCALE = 10
 PAPER_VALUES = tuple(v for v in range(-SCALE, SCALE + 1) if v != 0)   # J * 10, J in {+-0.1..+-1}
@@ -61,6 +64,7 @@ class ScanConfig:
     gamma_start: float = 3.0         # paper units
     gamma_end: float = 0.01
     move: int = sqa.SQA_MOVE_WOLFF
+    schemes: Sequence[str] = ("mec", "lhz")    # ME on Chimera, LHZ; "me" adds the clique-chain ME
     lhz_decoders: Sequence[str] = ("mvd", "mwd", "bp")
     trees: int = 3                   # majority-vote trees (3 for K8, 5 for K16 in Fig. 2)
     seed: int = 0x5EED
@@ -89,10 +93,11 @@ def penalty_scan(instances: Sequence[np.ndarray], penalties: Sequence[float], cf
     beta = cfg.beta_eff / SCALE
     g0, g1 = SCALE * cfg.gamma_start, SCALE * cfg.gamma_end
     handles, keys = [], []
+    kinds = [KINDS[x] for x in cfg.schemes]
     for i, J in enumerate(instances):
         for k, lam in enumerate(penalties):
             pen = penalty_coefficient(lam)
-            for kind in (ME, LHZ):
+            for kind in kinds:
                 seed = cfg.seed + 1000 * i + 10 * k + kind
                 handles.append(sqa.SQA(kind, J, pen, beta, cfg.slices, cfg.sweeps, cfg.reads, g0, g1, seed,
                                        move=cfg.move))
@@ -105,16 +110,20 @@ def penalty_scan(instances: Sequence[np.ndarray], penalties: Sequence[float], cf
     dt = time.perf_counter() - t0
     batch.close()
     nI, nP = len(instances), len(penalties)
-    out = {"me": np.zeros((nI, nP))}
-    for d in cfg.lhz_decoders:
-        out["lhz_" + d] = np.zeros((nI, nP))
+    out = {}
+    for x in cfg.schemes:
+        if x == "lhz":
+            for d in cfg.lhz_decoders:
+                out["lhz_" + d] = np.zeros((nI, nP))
+        else:
+            out[x] = np.zeros((nI, nP))
     site_slices = 0.0
     for h, (i, k, kind) in zip(handles, keys):
         site_slices += float(h.sites) * h.slices * h.replicas * h.sweeps
         N = instances[i].shape[0]
-        if kind == ME:
+        if kind != LHZ:
             _, E = h.decode(sqa.SQA_DEC_ME_MAJORITY, 0)
-            out["me"][i, k] = float(np.mean(E == e0[i]))
+            out["mec" if kind == MEC else "me"][i, k] = float(np.mean(E == e0[i]))
             continue
         trees = sqa.sqa_random_trees(cfg.seed + i, N, cfg.trees)
         for d in cfg.lhz_decoders:

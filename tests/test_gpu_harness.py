@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from paper_1603_03755_amd.workloads import LHZ, ME, sk_instance
+from paper_1603_03755_amd.workloads import LHZ, ME, MEC, sk_instance
 
 pytestmark = pytest.mark.gpu
 
@@ -48,7 +48,8 @@ def test_penalty_scan_equals_oracle(sqa):
     """A small scan (2 instances, 3 penalties, both schemes, Wolff moves): every p_s
     equals the one computed from the oracle's anneal, decoders and ground state."""
     from paper_1603_03755_amd import harness as H
-    cfg = H.ScanConfig(sweeps=40, reads=12, slices=8, lhz_decoders=("mvd", "mwd", "bp"), trees=3)
+    cfg = H.ScanConfig(sweeps=40, reads=12, slices=8, schemes=("mec", "me", "lhz"),
+                       lhz_decoders=("mvd", "mwd", "bp"), trees=3)
     instances = [H.paper_instance(5, 11), H.paper_instance(6, 12)]
     penalties = [0.5, 1.5, 3.0]
     res = H.penalty_scan(instances, penalties, cfg)
@@ -60,14 +61,14 @@ def test_penalty_scan_equals_oracle(sqa):
         trees = O.random_trees(cfg.seed + i, N, cfg.trees)
         for k, lam in enumerate(penalties):
             pen = H.penalty_coefficient(lam)
-            for kind in (ME, LHZ):
+            for kind in (MEC, ME, LHZ):
                 seed = cfg.seed + 1000 * i + 10 * k + kind
                 emb, _, spins, _ = O.sqa_anneal_wolff(kind, J, pen, beta, cfg.slices, cfg.sweeps, cfg.reads,
                                                       H.SCALE * cfg.gamma_start, H.SCALE * cfg.gamma_end, seed,
                                                       nthreads=8)
-                if kind == ME:
+                if kind != LHZ:
                     ok = [O.logical_energy(J, O.me_majority(emb, spins[r, 0])) == E0 for r in range(cfg.reads)]
-                    assert res.p_s["me"][i, k] == np.mean(ok)
+                    assert res.p_s["mec" if kind == MEC else "me"][i, k] == np.mean(ok)
                     continue
                 dec = {"mvd": lambda s: O.lhz_tree_decode(N, s, trees),
                        "mwd": lambda s: O.lhz_mwd(N, s),
@@ -75,5 +76,5 @@ def test_penalty_scan_equals_oracle(sqa):
                 for d, fn in dec.items():
                     ok = [O.logical_energy(J, fn(spins[r, 0])) == E0 for r in range(cfg.reads)]
                     assert res.p_s["lhz_" + d][i, k] == np.mean(ok), (i, k, d)
-    pen_me, ps_me = res.optimal("me")
+    pen_me, ps_me = res.optimal("mec")
     assert len(pen_me) == 2 and all(0 <= p <= 1 for p in ps_me)
