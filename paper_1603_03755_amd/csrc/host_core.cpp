@@ -180,11 +180,17 @@ sqa_status build_layout(const Embedded &emb, int32_t F, bool scale6, DeviceLayou
     }
     if (emb.h[k] < 0) neg |= 1u << (mec ? kFieldSignMEC : 4);
     uint32_t ah = static_cast<uint32_t>(std::abs(emb.h[k]));
-    if (scale6 && F <= kSmallF) {        // the SQA kernel sums 6|w| directly
+    uint32_t base = static_cast<uint32_t>(3 * (fs + F) + 2);
+    if (scale6 && F <= kSmallF) {
+      // The sweep kernel's small-field mode sums 6|w| over the terms that AGREE
+      // with their sign (flipped sign bits) on top of c = 3 (F - F_site); with the
+      // agreeing time neighbours e' this gives c + 6 A + e' = base - (6 S + e).
       for (int a = 0; a < 6; ++a) aw[a] *= 6u;
       ah *= 6u;
+      const uint32_t hbit = 1u << (mec ? kFieldSignMEC : 4);
+      neg ^= ((1u << T) - 1u) | hbit;
+      base = static_cast<uint32_t>(3 * (F - fs));
     }
-    const uint32_t base = static_cast<uint32_t>(3 * (fs + F) + 2);
     uint32_t *r = &L.rec[static_cast<size_t>(d) * L.rec_words];
     r[0] = static_cast<uint32_t>(k) | (base << 16);
     if (me) {

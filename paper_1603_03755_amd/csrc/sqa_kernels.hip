@@ -107,15 +107,22 @@ __device__ __forceinline__ void slice_energies(const HandleDev &H, const uint64_
 //       spin disagrees with the sign of w_t; O likewise for the field),
 //   e = number of time neighbours whose spin differs from the own spin;
 // e is accumulated four slices at a time in 6-bit fields; S by field mode:
-// kFieldSmall (F <= 10): the records carry 6|w| and 6|h|, so 6-bit fields hold
-//   6 S directly and 6 S + e < 64 stays inside a field;
+// kFieldSmall (F <= 10): the records carry 6|w| and 6|h|, flipped sign bits
+//   (so the products count agreements, A = F_site - S) and c = 3 (F - F_site)
+//   in place of base.  A field then holds c + 6 A + e' (e' = 2 - e, the agreeing
+//   neighbours), which equals base - (6 S + e) and is below 64: the field is
+//   the table index itself;
 // kFieldMid (F <= 63): S in 6-bit fields, four slices per word;
 // kFieldLarge (F <= 255): S in 8-bit fields, three slices per word (at bits
 //   0, 8, 16, so both operands of the 24-bit multiplies stay below 2^24).
-// FASTL: L in {16, 32, 64} (whole bytes, replicated-word rotation, L > 1).
-template <int KIND, int MODE, bool FASTL>
+// FASTL: L in {16, 32, 64} (whole bytes, replicated-word rotation, L > 1);
+//   items are then taken site-major (the B = L/16 bytes of one site in
+//   neighbouring lanes share their record and partner words).
+// P: the slice parity.
+template <int KIND, int MODE, bool FASTL, int P>
 __device__ __forceinline__ void sweep_class(const HandleDev &H, const uint32_t *__restrict__ rec, uint32_t *lat32,
-                                            const uint32_t *tab, int c, int p, uint32_t m, uint32_t c3, int lane) {
+                                            const uint32_t *tab, int c, uint32_t m, uint32_t c3, int lane) {
+  constexpr int p = P;
   using S = Site<KIND>;
   const int L = H.L;
   const int Hp = (L == 1) ? 1 : (L >> 1);       // slices of one parity
@@ -127,12 +134,20 @@ __device__ __forceinline__ void sweep_class(const HandleDev &H, const uint32_t *
   uint8_t *latb = reinterpret_cast<uint8_t *>(lat32);
   const bool ring32 = FASTL || (Hp & (Hp - 1)) == 0;   // Hp divides 32: rotate a replicated word
   const bool ragged = !FASTL && (Hp & 7) != 0;          // last byte has fewer than eight slices
-  // item it = b * nc + j; lanes advance by 64 items: (j, b) += (64 % nc, 64 / nc)
+  // FASTL: item it = j * B + b (B a power of two).  Otherwise it = b * nc + j,
+  // lanes advancing by 64 items: (j, b) += (64 % nc, 64 / nc).
+  const int lgB = (B >= 4) ? 2 : (B - 1);
   const int dq = 64 / nc, dr = 64 - dq * nc;
-  int b = lane / nc;
-  int j = lane - b * nc;
+  int b = FASTL ? (lane & (B - 1)) : lane / nc;
+  int j = FASTL ? (lane >> lgB) : lane - b * nc;
   for (int it = lane; it < cnt; it += 64, j += dr, b += dq) {
-    if (j >= nc) { j -= nc; b += 1; }
+    if constexpr (FASTL) {
+      j = it >> lgB;
+      b = it & (B - 1);
+    } else if (j >= nc) {
+      j -= nc;
+      b += 1;
+    }
     const int d = lo + j;
     const uint32_t *r = rec + d * S::RW;
 
@@ -190,7 +205,9 @@ __device__ __forceinline__ void sweep_class(const HandleDev &H, const uint32_t *
       dn = p ? n0 : n1;
       up = p ? n1 : n0;
     }
-    const uint32_t e1 = own ^ dn, e2 = own ^ up;
+    // disagreeing (agreeing, kFieldSmall) time neighbours
+    const uint32_t agree = (MODE == kFieldSmall) ? 0xFFu : 0u;
+    const uint32_t e1 = own ^ dn ^ agree, e2 = own ^ up ^ agree;
     const uint32_t ev_lo = spread6(__builtin_amdgcn_ubfe(e1, 0, 4)) + spread6(__builtin_amdgcn_ubfe(e2, 0, 4));
     const uint32_t ev_hi = spread6_hi(e1) + spread6_hi(e2);
 
@@ -198,7 +215,11 @@ __device__ __forceinline__ void sweep_class(const HandleDev &H, const uint32_t *
     const uint8_t *lb = latb + (4 * p + b);        // the item's byte in any site word
     const uint32_t ox = (own ^ negh) & 0xFFu;
     uint32_t acc_lo = 0, acc_hi = 0, acc_x = 0;     // kFieldLarge: slices 0-2, 3-5, 6-7
-    if constexpr (MODE == kFieldLarge) {
+    if constexpr (MODE == kFieldSmall) {
+      const uint32_t c4 = __umul24(base, 0x41041u);       // c in every field
+      acc_lo = c4 + __umul24(spread6(__builtin_amdgcn_ubfe(ox, 0, 4)), hw);
+      acc_hi = c4 + __umul24(spread6(__builtin_amdgcn_ubfe(ox, 4, 4)), hw);
+    } else if constexpr (MODE == kFieldLarge) {
       acc_lo = __umul24(spread3(ox), hw);
       acc_hi = __umul24(spread3(ox >> 3), hw);
       acc_x = __umul24(spread3(ox >> 6), hw);
@@ -232,8 +253,8 @@ __device__ __forceinline__ void sweep_class(const HandleDev &H, const uint32_t *
       const uint32_t f_hi = acc_hi + ev_hi;
 #pragma unroll
       for (int w = 0; w < 4; ++w) {
-        const uint32_t R0 = *(tb - __builtin_amdgcn_ubfe(f_lo, 6 * w, 6));
-        const uint32_t R1 = *(tb - __builtin_amdgcn_ubfe(f_hi, 6 * w, 6));
+        const uint32_t R0 = tab[__builtin_amdgcn_ubfe(f_lo, 6 * w, 6)];
+        const uint32_t R1 = tab[__builtin_amdgcn_ubfe(f_hi, 6 * w, 6)];
         if (min(u0.v[w], 0xFFFFFFFEu) < R0) flip |= 1u << w;
         if (min(u1.v[w], 0xFFFFFFFEu) < R1) flip |= 16u << w;
       }
@@ -290,13 +311,20 @@ __device__ __forceinline__ void anneal_replica(const HandleDev &H, const uint32_
     }
     wave_sync();
     uint32_t *lat32 = reinterpret_cast<uint32_t *>(lat);
-    for (int p = 0; p < parities; ++p)
+    const uint32_t mm = static_cast<uint32_t>(m);
+    for (int c = 0; c < 4; ++c) {
+      if (fast) sweep_class<KIND, kFieldSmall, true, 0>(H, rec, lat32, tab, c, mm, c3, lane);
+      else if (smallf) sweep_class<KIND, kFieldSmall, false, 0>(H, rec, lat32, tab, c, mm, c3, lane);
+      else if (midf) sweep_class<KIND, kFieldMid, false, 0>(H, rec, lat32, tab, c, mm, c3, lane);
+      else sweep_class<KIND, kFieldLarge, false, 0>(H, rec, lat32, tab, c, mm, c3, lane);
+      wave_sync();
+    }
+    if (parities > 1)
       for (int c = 0; c < 4; ++c) {
-        const uint32_t mm = static_cast<uint32_t>(m);
-        if (fast) sweep_class<KIND, kFieldSmall, true>(H, rec, lat32, tab, c, p, mm, c3, lane);
-        else if (smallf) sweep_class<KIND, kFieldSmall, false>(H, rec, lat32, tab, c, p, mm, c3, lane);
-        else if (midf) sweep_class<KIND, kFieldMid, false>(H, rec, lat32, tab, c, p, mm, c3, lane);
-        else sweep_class<KIND, kFieldLarge, false>(H, rec, lat32, tab, c, p, mm, c3, lane);
+        if (fast) sweep_class<KIND, kFieldSmall, true, 1>(H, rec, lat32, tab, c, mm, c3, lane);
+        else if (smallf) sweep_class<KIND, kFieldSmall, false, 1>(H, rec, lat32, tab, c, mm, c3, lane);
+        else if (midf) sweep_class<KIND, kFieldMid, false, 1>(H, rec, lat32, tab, c, mm, c3, lane);
+        else sweep_class<KIND, kFieldLarge, false, 1>(H, rec, lat32, tab, c, mm, c3, lane);
         wave_sync();
       }
   }
