@@ -66,7 +66,7 @@ static LaunchShape shape_for(const std::vector<const sqa_handle *> &hs, int wave
     if (move == kMoveWolff) {
       int maxclass = 0;
       for (int c = 0; c < 4; ++c) maxclass = std::max(maxclass, h->lay.cls[c + 1] - h->lay.cls[c]);
-      s.tab_cap = std::max(s.tab_cap, kWolffScratchWords * maxclass);
+      s.tab_cap = std::max(s.tab_cap, kWolffScratchWords * std::min(maxclass, kWolffChunk));
     } else {
       s.tab_cap = std::max(s.tab_cap, h->tw);
     }

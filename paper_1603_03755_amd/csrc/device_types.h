@@ -69,9 +69,11 @@ constexpr int kMoveMetropolis = 0;   // single-site Metropolis on the space-time
 constexpr int kMoveWolff = 1;        // time-like Wolff cluster per site (records with plain weights)
 // Counter word 1 of the Philox call that draws a Wolff move's seed slice and acceptance word.
 constexpr uint32_t kWolffSiteCtr = 64;
-// LDS scratch of one wave for Wolff moves, per site of the largest colour class (32-bit words):
-// the 64-bit join mask and the 64 per-slice disagreement sums as bytes.
+// LDS scratch of one wave for Wolff moves, per site of a chunk of a colour class (32-bit words):
+// the 64-bit join mask and the 64 per-slice disagreement sums as bytes; chunks of at most
+// kWolffChunk sites.
 constexpr int kWolffScratchWords = 18;
+constexpr int kWolffChunk = 64;
 
 constexpr uint32_t kAlways = 0xFFFFFFFFu;
 

@@ -351,7 +351,8 @@ __device__ __forceinline__ void anneal_replica(const HandleDev &H, const uint32_
 //     acceptance word passes the threshold at A + L F, and the cluster's bits
 //     are flipped.
 // Sites of one class share no term, so their moves commute and every read in
-// phase 1 sees the state left by the previous class.
+// phase 1 sees the state left by the previous class.  Large classes are
+// processed in chunks of kWolffChunk sites.
 
 // Four 6-bit fields (bits 0, 6, 12, 18) moved to the four bytes of a word.
 __device__ __forceinline__ uint32_t fields6_to_bytes(uint32_t a) {
@@ -375,13 +376,11 @@ __device__ __forceinline__ uint64_t ring_cluster(uint64_t jn, int t0, int L) {
 
 template <int KIND, bool LARGE>
 __device__ __forceinline__ void wolff_bonds(const HandleDev &H, const uint32_t *__restrict__ rec, const uint64_t *lat,
-                                            uint32_t *scr, int c, uint32_t m, uint32_t c3, uint32_t padd, int lane) {
+                                            uint32_t *scr, int lo, int nc, uint32_t m, uint32_t c3, uint32_t padd,
+                                            int lane) {
   using S = Site<KIND>;
   const int L = H.L;
   const int Q = (L + 7) >> 3;
-  const int lo = H.cls[c];
-  const int nc = H.cls[c + 1] - lo;
-  if (nc <= 0) return;
   const int cnt = nc * Q;
   const uint8_t *latb = reinterpret_cast<const uint8_t *>(lat);
   uint8_t *jb = reinterpret_cast<uint8_t *>(scr);        // [nc] 64-bit join masks
@@ -483,12 +482,10 @@ __device__ __forceinline__ void wolff_bonds(const HandleDev &H, const uint32_t *
 
 template <int KIND>
 __device__ __forceinline__ void wolff_flips(const HandleDev &H, const uint32_t *__restrict__ rec, uint64_t *lat,
-                                            const uint32_t *scr, int c, uint32_t m, uint32_t c3,
+                                            const uint32_t *scr, int lo, int nc, uint32_t m, uint32_t c3,
                                             const uint32_t *arow, int lane) {
   using S = Site<KIND>;
   const int L = H.L;
-  const int lo = H.cls[c];
-  const int nc = H.cls[c + 1] - lo;
   const int words = (L + 3) >> 2;
   const uint64_t *jw = reinterpret_cast<const uint64_t *>(scr);
   const uint32_t *sb = scr + 2 * nc;
@@ -523,13 +520,18 @@ __device__ __forceinline__ void wolff_replica(const HandleDev &H, const uint32_t
   for (int m = H.m0; m < H.m1; ++m) {
     const uint32_t padd = H.table[m];
     const uint32_t *arow = H.wacc + static_cast<size_t>(H.wrows > 1 ? m : 0) * H.wwidth + H.L * H.F;
-    for (int c = 0; c < 4; ++c) {
-      if (H.F > kMidF) wolff_bonds<KIND, true>(H, rec, lat, scr, c, static_cast<uint32_t>(m), c3, padd, lane);
-      else wolff_bonds<KIND, false>(H, rec, lat, scr, c, static_cast<uint32_t>(m), c3, padd, lane);
-      wave_sync();
-      wolff_flips<KIND>(H, rec, lat, scr, c, static_cast<uint32_t>(m), c3, arow, lane);
-      wave_sync();
-    }
+    // each colour class in chunks of at most 64 sites (one lane per site in
+    // phase 2; sites of a class commute, so chunking does not change results)
+    for (int c = 0; c < 4; ++c)
+      for (int lo = H.cls[c]; lo < H.cls[c + 1]; lo += kWolffChunk) {
+        const int nc = min(kWolffChunk, H.cls[c + 1] - lo);
+        const uint32_t mm = static_cast<uint32_t>(m);
+        if (H.F > kMidF) wolff_bonds<KIND, true>(H, rec, lat, scr, lo, nc, mm, c3, padd, lane);
+        else wolff_bonds<KIND, false>(H, rec, lat, scr, lo, nc, mm, c3, padd, lane);
+        wave_sync();
+        wolff_flips<KIND>(H, rec, lat, scr, lo, nc, mm, c3, arow, lane);
+        wave_sync();
+      }
   }
   store_lattice<true>(H, lat, rep, lane);
   if (H.flags & kFlagEnergy) slice_energies<true>(H, lat, rep, lane);
