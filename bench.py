@@ -78,7 +78,7 @@ def parse():
     ap.add_argument("--legs", default="per_instance,serving,pt,wolff,scan,cpu",
                     help="comma list of the extra legs to run after the timed steps")
     ap.add_argument("--cpu-replicas", type=int, default=2, help="oracle lattices per stratum for cpu_baseline")
-    ap.add_argument("--pt-sweeps", type=int, default=10_000, help="sweeps of the parallel-tempering leg")
+    ap.add_argument("--pt-sweeps", type=int, default=100_000, help="sweeps of the parallel-tempering leg")
     return ap.parse_args()
 
 
@@ -221,6 +221,52 @@ def cpu_baseline(jobs, replicas_per_stratum: int = 2):
                       f"stratum), full {sample[0].sweeps}-sweep schedule: {attempts:.3e} attempts in {dt:.1f} s"}
 
 
+def serve_run(sqa, stream_jobs, budget, slots, chunk):
+    """Pushes (arrival_time, job) pairs through a continuous-batching server; returns
+    per-job latencies and totals."""
+    srv = sqa.Server(hbm_budget_bytes=budget, max_slots=slots, chunk_sweeps=chunk)
+    t0 = time.perf_counter()
+    tickets = []
+    for arr, j in stream_jobs:
+        now = time.perf_counter() - t0
+        if arr > now:
+            time.sleep(arr - now)
+        tickets.append((srv.submit(j.kind, j.J, j.penalty, j.beta, j.slices, j.sweeps, j.replicas, j.gamma0,
+                                   j.gamma1, j.seed), j))
+    lats, att = [], 0
+    for t, j in tickets:
+        srv.wait(t)
+        _, _, lat = srv.result(t)
+        lats.append(lat)
+        att += j.attempts
+    span = time.perf_counter() - t0
+    completed, launches, peak = srv.stats()
+    srv.close()
+    return {"jobs": len(tickets), "p50_latency_s": float(np.percentile(lats, 50)),
+            "p99_latency_s": float(np.percentile(lats, 99)), "jobs_per_s": len(tickets) / span,
+            "attempts_per_s": att / span, "launches": int(launches), "peak_resident_bytes": int(peak)}
+
+
+def serving_leg(sqa):
+    """Continuous batching under a 64 MB device budget and 32 slots: capacity from a
+    burst of 48 mixed jobs (N 8..32, ME/LHZ, L 32/64, 10^3-10^4 sweeps, 16 replicas),
+    then Poisson arrivals of the same jobs at 0.25, 0.5, 0.75 and 0.9 of capacity."""
+    from paper_1603_03755_amd.workloads import serving_stream
+    budget, slots, chunk, count = 64 << 20, 32, 500, 48
+    burst = [(0.0, j) for _, j in serving_stream(count=count, rate_per_s=1.0)]
+    cap = serve_run(sqa, burst, budget, slots, chunk)
+    capacity = cap["jobs_per_s"]
+    rates = []
+    for f in (0.25, 0.5, 0.75, 0.9):
+        r = serve_run(sqa, serving_stream(count=count, rate_per_s=f * capacity), budget, slots, chunk)
+        r.update({"fraction_of_capacity": f, "arrival_rate_per_s": f * capacity})
+        rates.append(r)
+    head = rates[2]
+    return {"capacity_jobs_per_s": capacity, "burst": cap, "rates": rates,
+            "p50_latency_s": head["p50_latency_s"], "p99_latency_s": head["p99_latency_s"],
+            "at_fraction_of_capacity": 0.75, "budget_bytes": budget, "slots": slots, "chunk_sweeps": chunk}
+
+
 def pt_leg(sqa, sweeps: int):
     """Parallel tempering over 128 N = 24 instances embedded both ways (256 ladders of 32
     temperatures, beta geometric in [0.1, 5], a swap phase after every sweep), one launch."""
@@ -336,6 +382,9 @@ def main():
                      "kernel_ms": kernel_s * 1e3,
                      "ops_per_attempt": ops},
         "kernel_attempts_per_s": attempts_per_step / kernel_s,
+        # the per-sweep streaming view: 1 byte read + 1 byte written per attempt at 8 TB/s
+        "hbm_yardstick": {"bytes_per_attempt": 2, "attempts_per_s_at_peak": 4.0e12,
+                          "frac": (attempts_per_step / kernel_s) / 4.0e12},
         "setup_s": setup_s,
     }
     legs = set() if args.no_extras else {x.strip() for x in args.legs.split(",") if x.strip()}
@@ -364,30 +413,7 @@ def main():
         for h in hs2:
             h.close()
     if "serving" in legs:
-        # serving: a Poisson stream of mixed jobs through the continuous-batching server
-        stream_jobs = serving_stream(count=48, rate_per_s=12.0)
-        srv = sqa.Server(hbm_budget_bytes=64 << 20, max_slots=32, chunk_sweeps=500)
-        t0 = time.perf_counter()
-        tickets = []
-        for arr, j in stream_jobs:
-            now = time.perf_counter() - t0
-            if arr > now:
-                time.sleep(arr - now)
-            tickets.append((srv.submit(j.kind, j.J, j.penalty, j.beta, j.slices, j.sweeps, j.replicas, j.gamma0,
-                                       j.gamma1, j.seed), j))
-        lats, att3 = [], 0
-        for t, j in tickets:
-            srv.wait(t)
-            _, _, lat = srv.result(t)
-            lats.append(lat)
-            att3 += j.attempts
-        span = time.perf_counter() - t0
-        completed, launches, peak = srv.stats()
-        srv.close()
-        out["serving"] = {"jobs": len(tickets), "p50_latency_s": float(np.percentile(lats, 50)),
-                          "p99_latency_s": float(np.percentile(lats, 99)), "jobs_per_s": len(tickets) / span,
-                          "attempts_per_s": att3 / span, "launches": launches, "peak_resident_bytes": peak,
-                          "budget_bytes": 64 << 20, "arrival_rate_per_s": 12.0}
+        out["serving"] = serving_leg(sqa)
     if "pt" in legs:
         out["parallel_tempering"] = pt_leg(sqa, args.pt_sweeps)
     if "wolff" in legs:
