@@ -1094,10 +1094,12 @@ sqa_status sqa_autotune(sqa_handle *const *handles, int32_t count, const char *c
       std::vector<MoveGroup> base;
       size_t bytes = 0;
       if (plan_groups(hs, m0, m1, w, 0, &base, &bytes) != SQA_OK) continue;
-      // groups-per-CU candidates from the occupancy of the first group's kernel
+      // groups-per-CU candidates: every count from half the occupancy of the first
+      // group's kernel up to all of it (the count sets how evenly the work items
+      // divide into rounds of resident workgroups)
       const int occ = occupancy_groups_per_cu(base.front().shape);
-      std::vector<int> gpcs{occ};
-      if (occ >= 2) gpcs.push_back(occ / 2);
+      std::vector<int> gpcs;
+      for (int g = occ; g >= std::max(1, occ / 2); --g) gpcs.push_back(g);
       for (int g : gpcs) {
         std::vector<MoveGroup> groups;
         if (plan_groups(hs, m0, m1, w, g, &groups, &bytes) != SQA_OK) continue;
