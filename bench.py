@@ -129,7 +129,7 @@ def wolff_leg(sqa, O, jobs, stream, metropolis_kernel_s, traffic):
     from concurrent.futures import ThreadPoolExecutor
     hs = [sqa.SQA(j.kind, j.J, j.penalty, j.beta, j.slices, j.sweeps, j.replicas, j.gamma0, j.gamma1, j.seed,
                   move=sqa.SQA_MOVE_WOLFF) for j in jobs]
-    b = sqa.Batch(hs, *sqa.sqa_autotune(hs))
+    b = sqa.Batch(hs)
     waves, gpc = b.config()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     b.run(stream)
@@ -321,8 +321,7 @@ def main():
     t_setup = time.perf_counter()
     handles = [sqa.SQA(j.kind, j.J, j.penalty, j.beta, j.slices, j.sweeps, j.replicas, j.gamma0, j.gamma1, j.seed)
                for j in jobs]
-    tuned = sqa.sqa_autotune(handles)          # launch shape timed on short runs of this batch
-    batch = sqa.Batch(handles, *tuned)
+    batch = sqa.Batch(handles)                 # launch shape from the package's tuning cache
     waves, gpc = batch.config()
     setup_s = time.perf_counter() - t_setup
     attempts_per_step = sum(j.attempts for j in jobs)
@@ -376,7 +375,8 @@ def main():
                                f"64 replicas, L=64, {args.sweeps} sweeps, beta=10, Gamma 3->0.01, penalty -2",
                    "attempts_per_step": attempts_per_step, "launch": {"waves_per_group": waves,
                                                                       "groups_per_cu": gpc,
-                                                                      "chosen_by": "sqa_autotune"},
+                                                                      "tuning_cache": os.path.basename(
+                                                                          sqa.TUNING_CACHE)},
                    "parallelism": "single GPU, one persistent launch"},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
                      "unit": "TOP/s (32-bit VALU lane-op slots)", "frac": achieved / PEAK_LANE_OPS,

@@ -111,10 +111,19 @@ _SIGS = {
 }
 
 
+# Launch shapes chosen by sqa_autotune for this package's benchmark batches on
+# gfx950 (written by `python -m paper_1603_03755_amd.autotune`).  Batches created
+# with an automatic shape look their shape class up here unless the environment
+# names another cache file.
+TUNING_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_gfx950.json")
+
+
 def lib():
     """The loaded library; raises if it has not been built."""
     global _lib
     if _lib is None:
+        if os.path.exists(TUNING_CACHE):
+            os.environ.setdefault("SQA_AUTOTUNE_CACHE", TUNING_CACHE)
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1603_03755_amd.build`")
         L = C.CDLL(LIB_PATH)
