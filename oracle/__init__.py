@@ -18,6 +18,7 @@ _lib = None
 
 ME, LHZ, MEC = 0, 1, 2
 STREAM_INIT, STREAM_SQA, STREAM_PT, STREAM_SWAP, STREAM_TREE, STREAM_PT_INIT, STREAM_WOLFF = 1, 2, 3, 4, 5, 6, 7
+STREAM_SQA_LO, STREAM_WOLFF_LO = 8, 9
 ALWAYS = 0xFFFFFFFF
 
 
@@ -43,6 +44,8 @@ def lib():
         L = _lib
         L.oracle_sqa_word.restype = C.c_uint32
         L.oracle_sqa_word.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32]
+        L.oracle_sqa_uniform.restype = C.c_uint32
+        L.oracle_sqa_uniform.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32]
         L.oracle_pt_word.restype = C.c_uint32
         L.oracle_pt_word.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32]
         L.oracle_threshold.restype = C.c_uint32
@@ -56,8 +59,8 @@ def lib():
         L.oracle_ground_states.restype = C.c_int32
         L.oracle_random_trees.restype = C.c_int
         L.oracle_me_site.restype = C.c_int32
-        L.oracle_wolff_bond_word.restype = C.c_uint32
-        L.oracle_wolff_bond_word.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32]
+        L.oracle_wolff_bond_uniform.restype = C.c_uint32
+        L.oracle_wolff_bond_uniform.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32]
         L.oracle_wolff_site_order.restype = C.c_int32
         L.oracle_lhz_site.restype = C.c_int32
     return _lib
@@ -90,6 +93,11 @@ def philox4x64(ctr, key):
 
 def sqa_word(seed, stream, replica, site, slice_, sweep) -> int:
     return int(lib().oracle_sqa_word(seed, stream, replica, site, slice_, sweep))
+
+
+def sqa_uniform(seed, replica, site, slice_, sweep) -> int:
+    """The 32-bit uniform of one Metropolis attempt (high half stream SQA, low half SQA_LO)."""
+    return int(lib().oracle_sqa_uniform(seed, replica, site, slice_, sweep))
 
 
 def pt_word(seed, stream, replica, site, sweep) -> int:
@@ -273,8 +281,9 @@ def sqa_anneal(kind, J, penalty, beta, L, sweeps, replicas, gamma0, gamma1, seed
 
 
 # ---------------------------------------------------------------- SQA, Wolff moves
-def wolff_bond_word(seed, replica, site, bond, sweep) -> int:
-    return int(lib().oracle_wolff_bond_word(seed, replica, site, bond, sweep))
+def wolff_bond_uniform(seed, replica, site, bond, sweep) -> int:
+    """The 32-bit uniform of one ring bond's join decision (high half stream WOLFF, low half WOLFF_LO)."""
+    return int(lib().oracle_wolff_bond_uniform(seed, replica, site, bond, sweep))
 
 
 def wolff_site_words(seed, replica, site, sweep):

@@ -29,7 +29,8 @@ extern "C" {
 
 /* RNG streams of the counter layout. */
 enum { OR_STREAM_INIT = 1, OR_STREAM_SQA = 2, OR_STREAM_PT = 3,
-       OR_STREAM_SWAP = 4, OR_STREAM_TREE = 5, OR_STREAM_PT_INIT = 6, OR_STREAM_WOLFF = 7 };
+       OR_STREAM_SWAP = 4, OR_STREAM_TREE = 5, OR_STREAM_PT_INIT = 6, OR_STREAM_WOLFF = 7,
+       OR_STREAM_SQA_LO = 8, OR_STREAM_WOLFF_LO = 9 };
 
 enum { OR_ME = 0, OR_LHZ = 1, OR_MEC = 2 };
 
@@ -55,6 +56,7 @@ void oracle_philox4x32(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
 void oracle_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
 uint32_t oracle_sqa_word(uint64_t seed, uint32_t stream, uint32_t replica,
                          uint32_t site, uint32_t slice, uint32_t sweep);
+uint32_t oracle_sqa_uniform(uint64_t seed, uint32_t replica, uint32_t site, uint32_t slice, uint32_t sweep);
 uint32_t oracle_pt_word(uint64_t seed, uint32_t stream, uint32_t replica,
                         uint32_t site, uint32_t sweep);
 
@@ -97,7 +99,7 @@ void oracle_sqa_energies(const OEmb *e, int32_t L, int32_t R, const int8_t *spin
                          int32_t *E);
 
 /* ---- SQA with time-like Wolff cluster updates (Sec. III) ------------------ */
-uint32_t oracle_wolff_bond_word(uint64_t seed, uint32_t r, uint32_t k, uint32_t b, uint32_t m);
+uint32_t oracle_wolff_bond_uniform(uint64_t seed, uint32_t r, uint32_t k, uint32_t b, uint32_t m);
 void oracle_wolff_site_words(uint64_t seed, uint32_t r, uint32_t k, uint32_t m, uint32_t *u_seed,
                              uint32_t *u_acc);
 void oracle_wolff_tables(double beta, int32_t L, int32_t M, const double *gamma,

@@ -9,13 +9,21 @@
  * implements Philox4x64-10.
  *
  * The paper does not say which generator it used (its SQA code is described
- * in another reference).  Counter layout, a reading taken for this build:
- *   SQA attempt (replica r, slice tau, site k, sweep m), stream s:
- *     counter = (k, ((tau>>3)<<1) | (tau&1), m, (s<<24) | r),
- *     key     = (seed low 32 bits, seed high 32 bits),
- *     word    = (tau>>1) & 3.
- *   One Philox call therefore serves the four same-parity slices
- *   8g+p, 8g+p+2, 8g+p+4, 8g+p+6 of one site.
+ * in another reference).  Counter layout, a reading taken for this build
+ * (key = (seed low 32 bits, seed high 32 bits) throughout):
+ *   Initial spin of (replica r, slice tau, site k), stream INIT:
+ *     counter = (k, ((tau>>3)<<1) | (tau&1), 0, (INIT<<24) | r),
+ *     word    = (tau>>1) & 3 (its top bit is used).
+ *   Metropolis uniform of attempt (replica r, slice tau, site k, sweep m): a
+ *     32-bit number u = (hi << 16) | lo.  hi and lo are 16-bit halves taken at
+ *     the same place from two calls that differ only in the stream, SQA for
+ *     hi and SQA_LO for lo:
+ *       counter = (k, ((tau>>4)<<1) | (tau&1), m, (stream<<24) | r),
+ *       j = (tau>>1) & 7, half j>>2 (0 = low, 1 = high) of word j & 3.
+ *     One call thus serves the eight same-parity slices 16b+p+2j (j = 0..7)
+ *     of one site.  u is uniform on 0 .. 2^32-1 because hi and lo are
+ *     independent uniform halves; since lo matters only when hi equals the
+ *     top half of the threshold, an implementation may draw it only then.
  *   PT attempt (replica rho, site k, sweep m), stream s:
  *     counter = (k, rho>>2, m, s<<24), word = rho & 3.
  */
@@ -70,6 +78,26 @@ uint32_t oracle_sqa_word(uint64_t seed, uint32_t stream, uint32_t replica,
   key[1] = (uint32_t)(seed >> 32);
   oracle_philox4x32(ctr, key, out);
   return out[(slice >> 1) & 3u];
+}
+
+static uint32_t sqa_half(uint64_t seed, uint32_t stream, uint32_t replica, uint32_t site,
+                         uint32_t slice, uint32_t sweep) {
+  uint32_t ctr[4], key[2], out[4];
+  ctr[0] = site;
+  ctr[1] = ((slice >> 4) << 1) | (slice & 1u);
+  ctr[2] = sweep;
+  ctr[3] = (stream << 24) | replica;
+  key[0] = (uint32_t)seed;
+  key[1] = (uint32_t)(seed >> 32);
+  oracle_philox4x32(ctr, key, out);
+  uint32_t j = (slice >> 1) & 7u;
+  uint32_t w = out[j & 3u];
+  return (j >> 2) ? (w >> 16) : (w & 0xFFFFu);
+}
+
+uint32_t oracle_sqa_uniform(uint64_t seed, uint32_t replica, uint32_t site, uint32_t slice, uint32_t sweep) {
+  return (sqa_half(seed, OR_STREAM_SQA, replica, site, slice, sweep) << 16) |
+         sqa_half(seed, OR_STREAM_SQA_LO, replica, site, slice, sweep);
 }
 
 uint32_t oracle_pt_word(uint64_t seed, uint32_t stream, uint32_t replica,

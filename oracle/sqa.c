@@ -17,6 +17,9 @@
  *
  * Initial state (paper silent): s = -1 if bit 31 of the INIT-stream word for
  * (replica, slice, site, sweep 0) is set, else +1.
+ *
+ * Metropolis test: flip iff the threshold is the always-code or u < threshold,
+ * with u the attempt's 32-bit uniform (oracle_sqa_uniform, philox.c).
  */
 #include <pthread.h>
 #include <stdlib.h>
@@ -80,8 +83,7 @@ static void run_replica(const OEmb *e, int32_t L, int32_t r, int32_t m0, int32_t
           for (int k = 0; k < n; ++k) {
             if (e->colour[k] != c) continue;
             uint32_t R = oracle_sqa_attempt_threshold(e, L, table, F, lat, k, tau, m);
-            uint32_t u = oracle_sqa_word(seed, OR_STREAM_SQA, (uint32_t)r, (uint32_t)k,
-                                         (uint32_t)tau, (uint32_t)m);
+            uint32_t u = oracle_sqa_uniform(seed, (uint32_t)r, (uint32_t)k, (uint32_t)tau, (uint32_t)m);
             if (R == 0xFFFFFFFFu || u < R) lat[(size_t)tau * n + k] = (int8_t)-lat[(size_t)tau * n + k];
           }
 }

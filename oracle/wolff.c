@@ -26,9 +26,13 @@
  * Readings where the paper is silent: every sweep visits the sites by colour
  * class 0..3 and, inside a class, by increasing site index (sites of one
  * class share no term, so their moves commute); tau0 = floor(u L / 2^32).
- * Random words (Philox4x32-10, stream WOLFF = 7, key = seed):
- *   bond b of site k, sweep m, replica r: word b & 3 of counter (k, b >> 2, m, 7 << 24 | r);
- *   seed word and acceptance word:        words 0 and 1 of counter (k, 64, m, 7 << 24 | r).
+ * Random numbers (Philox4x32-10, key = seed):
+ *   bond b of site k, sweep m, replica r: the 32-bit uniform (hi << 16) | lo,
+ *     hi and lo being the 16-bit half (b >> 2) & 1 (0 = low, 1 = high) of
+ *     word b & 3 of counter (k, b >> 3, m, stream << 24 | r), with stream
+ *     WOLFF = 7 for hi and WOLFF_LO = 9 for lo (one call serves the eight
+ *     bonds 8q..8q+7; lo matters only when hi equals the threshold's top half);
+ *   seed word and acceptance word: words 0 and 1 of counter (k, 64, m, 7 << 24 | r).
  * Decisions use the threshold rule of tables.c (accept iff always-code or
  * u < threshold).  Tables: padd[m] per sweep; acc[row][A + L F] with A in
  * [-L F, L F], one row per sweep when B varies (bscale given), else one row.
@@ -39,26 +43,32 @@
 #include <string.h>
 #include "oracle.h"
 
-static uint32_t wolff_word(uint64_t seed, uint32_t r, uint32_t k, uint32_t c1, uint32_t m, int w) {
+static uint32_t wolff_word(uint64_t seed, uint32_t stream, uint32_t r, uint32_t k, uint32_t c1, uint32_t m,
+                           int w) {
   uint32_t ctr[4], key[2], out[4];
   ctr[0] = k;
   ctr[1] = c1;
   ctr[2] = m;
-  ctr[3] = ((uint32_t)OR_STREAM_WOLFF << 24) | r;
+  ctr[3] = (stream << 24) | r;
   key[0] = (uint32_t)seed;
   key[1] = (uint32_t)(seed >> 32);
   oracle_philox4x32(ctr, key, out);
   return out[w];
 }
 
-uint32_t oracle_wolff_bond_word(uint64_t seed, uint32_t r, uint32_t k, uint32_t b, uint32_t m) {
-  return wolff_word(seed, r, k, b >> 2, m, (int)(b & 3u));
+uint32_t oracle_wolff_bond_uniform(uint64_t seed, uint32_t r, uint32_t k, uint32_t b, uint32_t m) {
+  int half = (int)((b >> 2) & 1u);
+  uint32_t whi = wolff_word(seed, OR_STREAM_WOLFF, r, k, b >> 3, m, (int)(b & 3u));
+  uint32_t wlo = wolff_word(seed, OR_STREAM_WOLFF_LO, r, k, b >> 3, m, (int)(b & 3u));
+  uint32_t hi = half ? (whi >> 16) : (whi & 0xFFFFu);
+  uint32_t lo = half ? (wlo >> 16) : (wlo & 0xFFFFu);
+  return (hi << 16) | lo;
 }
 
 void oracle_wolff_site_words(uint64_t seed, uint32_t r, uint32_t k, uint32_t m, uint32_t *u_seed,
                              uint32_t *u_acc) {
-  *u_seed = wolff_word(seed, r, k, 64u, m, 0);
-  *u_acc = wolff_word(seed, r, k, 64u, m, 1);
+  *u_seed = wolff_word(seed, OR_STREAM_WOLFF, r, k, 64u, m, 0);
+  *u_acc = wolff_word(seed, OR_STREAM_WOLFF, r, k, 64u, m, 1);
 }
 
 void oracle_wolff_tables(double beta, int32_t L, int32_t M, const double *gamma,
@@ -149,7 +159,7 @@ static void *wolff_worker(void *arg) {
         uint32_t us, ua;
         oracle_wolff_site_words(j->seed, rep, (uint32_t)k, (uint32_t)m, &us, &ua);
         int tau0 = (int)(((uint64_t)us * (uint64_t)L) >> 32);
-        for (int b = 0; b < L; ++b) bond_u[b] = oracle_wolff_bond_word(j->seed, rep, (uint32_t)k, (uint32_t)b, (uint32_t)m);
+        for (int b = 0; b < L; ++b) bond_u[b] = oracle_wolff_bond_uniform(j->seed, rep, (uint32_t)k, (uint32_t)b, (uint32_t)m);
         oracle_wolff_move(e, L, 1, lat, k, tau0, bond_u, ua, j->padd[m], row, j->F, NULL, NULL);
       }
     }

@@ -58,16 +58,56 @@ def test_philox4x32_avalanche():
     assert 60 < np.mean(flips) < 68
 
 
-def test_sqa_word_counter_layout():
+def test_init_word_counter_layout():
     seed = 0x0123456789ABCDEF
     key = [seed & 0xFFFFFFFF, seed >> 32]
-    for (r, k, tau, m) in [(0, 0, 0, 0), (3, 17, 13, 999), (63, 551, 63, 9999), (5, 2, 1, 1)]:
+    for (r, k, tau) in [(0, 0, 0), (3, 17, 13), (63, 551, 63), (5, 2, 1)]:
         g, p = tau >> 3, tau & 1
-        out = O.philox4x32([k, (g << 1) | p, m, (O.STREAM_SQA << 24) | r], key)
+        out = O.philox4x32([k, (g << 1) | p, 0, (O.STREAM_INIT << 24) | r], key)
         # the four same-parity slices 8g+p+2w of one site share one call
         for w in range(4):
             t2 = 8 * g + p + 2 * w
-            assert O.sqa_word(seed, O.STREAM_SQA, r, k, t2, m) == int(out[w])
+            assert O.sqa_word(seed, O.STREAM_INIT, r, k, t2, 0) == int(out[w])
+
+
+def test_sqa_uniform_counter_layout():
+    seed = 0x0123456789ABCDEF
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    for (r, k, tau, m) in [(0, 0, 0, 0), (3, 17, 13, 999), (63, 551, 63, 9999), (5, 2, 1, 1), (9, 4, 0, 7)]:
+        b, p = tau >> 4, tau & 1
+        hi = O.philox4x32([k, (b << 1) | p, m, (O.STREAM_SQA << 24) | r], key)
+        lo = O.philox4x32([k, (b << 1) | p, m, (O.STREAM_SQA_LO << 24) | r], key)
+        # the eight same-parity slices 16b+p+2j of one site share one call per stream
+        for j in range(8):
+            t2 = 16 * b + p + 2 * j
+            sh = 16 * (j >> 2)
+            want = (((int(hi[j & 3]) >> sh) & 0xFFFF) << 16) | ((int(lo[j & 3]) >> sh) & 0xFFFF)
+            assert O.sqa_uniform(seed, r, k, t2, m) == want
+
+
+@pytest.mark.parametrize("fn", ["sqa", "wolff"])
+def test_attempt_uniforms_are_uniform_with_independent_halves(fn):
+    """The 32-bit attempt uniforms: both halves uniform, the low half independent of
+    the high half (a low half drawn from the high half's stream would coincide with
+    it), and all 2^32 values reachable in the sense that the top byte and the bottom
+    byte are each uniform."""
+    seed = 0x5EED
+    if fn == "sqa":
+        u = np.array([O.sqa_uniform(seed, r, k, t, m) for r in range(2) for k in range(6)
+                      for t in range(64) for m in range(8)], dtype=np.uint64)
+    else:
+        u = np.array([O.wolff_bond_uniform(seed, r, k, b, m) for r in range(2) for k in range(6)
+                      for b in range(64) for m in range(8)], dtype=np.uint64)
+    n = u.size
+    hi, lo = u >> 16, u & 0xFFFF
+    assert np.mean(hi == lo) < 5.0 / n + 1e-3
+    assert len(np.unique(u)) > n - 3
+    for part in (u >> 24, u & 0xFF, (hi & 0xFF), (lo >> 8)):
+        counts = np.bincount(part.astype(np.int64), minlength=256)
+        chi2 = float(((counts - n / 256.0) ** 2 / (n / 256.0)).sum())
+        assert chi2 < 255 + 6 * np.sqrt(2 * 255)
+    c = np.corrcoef(hi.astype(float), lo.astype(float))[0, 1]
+    assert abs(c) < 5 / np.sqrt(n)
 
 
 def test_pt_word_counter_layout():

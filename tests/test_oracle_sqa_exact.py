@@ -175,7 +175,7 @@ def test_sweep_order_covers_lattice_once(kind, N, L):
 @pytest.mark.parametrize("kind,N,L,R", [(O.ME, 4, 4, 2), (O.LHZ, 5, 2, 3), (O.LHZ, 4, 1, 2), (O.ME, 3, 10, 1)])
 def test_run_is_order_threshold_and_words(kind, N, L, R):
     """The oracle's anneal equals replaying its sweep order with its thresholds and
-    its SQA-stream words (accept iff always-code or word < threshold)."""
+    its attempt uniforms (accept iff always-code or u < threshold)."""
     seed = 0xABCDEF12345
     emb = O.Embedding(kind, sk_instance(N, 70), -2)
     M = 5
@@ -189,7 +189,7 @@ def test_run_is_order_threshold_and_words(kind, N, L, R):
         for m in range(M):
             for k, tau in zip(ks.tolist(), taus.tolist()):
                 T = O.sqa_attempt_threshold(emb, L, table, lat, k, tau, m)
-                u = O.sqa_word(seed, O.STREAM_SQA, r, k, tau, m)
+                u = O.sqa_uniform(seed, r, k, tau, m)
                 if T == O.ALWAYS or u < T:
                     lat[tau, k] = -lat[tau, k]
     assert (spins == ref).all()

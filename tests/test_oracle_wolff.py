@@ -244,18 +244,21 @@ def test_cluster_is_component_of_seed(L):
 def test_words_follow_counter_layout():
     seed = 0x0123456789ABCDEF
     key = [seed & 0xFFFFFFFF, seed >> 32]
-    for (r, k, b, m) in [(0, 0, 0, 0), (3, 17, 63, 9999), (65535, 275, 5, 123456)]:
-        ph = O.philox4x32([k, b >> 2, m, (O.STREAM_WOLFF << 24) | r], key)
-        assert O.wolff_bond_word(seed, r, k, b, m) == int(ph[b & 3])
+    for (r, k, b, m) in [(0, 0, 0, 0), (3, 17, 63, 9999), (65535, 275, 5, 123456), (1, 2, 12, 3)]:
+        # bonds 8q..8q+7 share one call per stream; bond 8q+j takes half j >> 2 of word j & 3
+        hi = int(O.philox4x32([k, b >> 3, m, (O.STREAM_WOLFF << 24) | r], key)[b & 3])
+        lo = int(O.philox4x32([k, b >> 3, m, (O.STREAM_WOLFF_LO << 24) | r], key)[b & 3])
+        sh = 16 * ((b >> 2) & 1)
+        assert O.wolff_bond_uniform(seed, r, k, b, m) == ((((hi >> sh) & 0xFFFF) << 16) | ((lo >> sh) & 0xFFFF))
         ph = O.philox4x32([k, 64, m, (O.STREAM_WOLFF << 24) | r], key)
         assert O.wolff_site_words(seed, r, k, m) == (int(ph[0]), int(ph[1]))
 
 
 @pytest.mark.parametrize("kind,N,L,R", [(O.ME, 4, 4, 2), (O.LHZ, 5, 6, 3), (O.LHZ, 4, 1, 2), (O.ME, 3, 64, 1)])
 def test_run_is_order_words_and_moves(kind, N, L, R):
-    """The oracle's anneal equals replaying its site order with its WOLFF-stream
-    words (seed slice floor(u L / 2^32)), its per-sweep join threshold and its
-    acceptance row."""
+    """The oracle's anneal equals replaying its site order with its bond uniforms and
+    WOLFF-stream site words (seed slice floor(u L / 2^32)), its per-sweep join
+    threshold and its acceptance row."""
     seed = 0xABCDEF12345
     emb = O.Embedding(kind, sk_instance(N, 70), -2)
     M = 4
@@ -271,7 +274,7 @@ def test_run_is_order_words_and_moves(kind, N, L, R):
             for k in order:
                 us, ua = O.wolff_site_words(seed, r, k, m)
                 tau0 = (us * L) >> 32
-                words = np.array([O.wolff_bond_word(seed, r, k, b, m) for b in range(L)], dtype=np.uint32)
+                words = np.array([O.wolff_bond_uniform(seed, r, k, b, m) for b in range(L)], dtype=np.uint32)
                 O.wolff_move(emb, L, ref[r:r + 1], k, tau0, words, ua, padd[m], acc[0])
     assert (spins == ref).all()
 
