@@ -36,15 +36,18 @@ sys.path.insert(0, ROOT)
 # VALU peak in 32-bit lane-op slots: the fp32 vector rate (157.3 TFLOP/s = 2 flops
 # per FMA) is 78.6e12 full-rate lane-ops/s = 256 CUs x 128 lane-ops/clock x 2.4 GHz.
 PEAK_LANE_OPS = 157.3e12 / 2
-# Philox4x32-10 per 32-bit word: 10 rounds x (2 widening 32x32 multiplies, each
-# 4 full-rate slots at quarter rate, + 2 three-input XORs) / 4 words.
-PHILOX_OPS_PER_WORD = 10 * (2 * 4 + 2) / 4
-DECISION_OPS = 4.0   # compare + select of the Metropolis test, time-neighbour term, table index
+# Philox4x32-10 per call: 10 rounds x (2 widening 32x32 multiplies, each 4 full-rate
+# slots at quarter rate, + 2 three-input XORs).  An attempt (a Wolff bond) consumes one
+# 16-bit half of a word, i.e. 1/8 of a call; the second call that supplies the low halves
+# is drawn only on a tie of the high half with the threshold (probability 2^-16 each).
+PHILOX_OPS_PER_CALL = 10 * (2 * 4 + 2)
+PHILOX_OPS_PER_HALF = PHILOX_OPS_PER_CALL / 8
+DECISION_OPS = 4.0   # compare, tie test and select of the Metropolis test, time-neighbour term, table index
 # Wolff moves, per site-slice: bond test (equality, compare, select) and the masked cluster sum;
 # per site and sweep, amortised over the L slices: one Philox call (seed slice and acceptance
 # words), the run search on the ring and the acceptance decision.
 WOLFF_BOND_OPS = 4.0
-WOLFF_SITE_OPS = 4 * PHILOX_OPS_PER_WORD + 24.0
+WOLFF_SITE_OPS = PHILOX_OPS_PER_CALL + 24.0
 
 # HBM bytes of one launch of the sweep kernel on this workload, from rocprofv3 --pmc FETCH_SIZE and
 # WRITE_SIZE passes (KiB per dispatch) scaled by the same counters on a cold 2 GiB copy
@@ -84,7 +87,7 @@ def parse():
 
 def algorithmic_ops_per_attempt(jobs, O) -> float:
     """Method arithmetic per attempt (full-rate lane-op slots), averaged over the
-    workload's sites: the Philox share of the random word, one multiply-add per
+    workload's sites: the Philox share of the random half word, one multiply-add per
     incident term and per nonzero field in the local field, and the decision."""
     tot_ops, tot_w = 0.0, 0.0
     seen = {}
@@ -94,7 +97,7 @@ def algorithmic_ops_per_attempt(jobs, O) -> float:
             emb = O.Embedding(j.kind, j.J, j.penalty)
             terms = np.diff(emb.row).astype(float)
             fields = (emb.h != 0).astype(float)
-            seen[key] = float(np.mean(PHILOX_OPS_PER_WORD + terms + fields + DECISION_OPS))
+            seen[key] = float(np.mean(PHILOX_OPS_PER_HALF + terms + fields + DECISION_OPS))
         w = j.sites * j.slices * j.replicas * j.sweeps
         tot_ops += seen[key] * w
         tot_w += w
@@ -103,7 +106,7 @@ def algorithmic_ops_per_attempt(jobs, O) -> float:
 
 def wolff_ops_per_site_slice(jobs, O) -> float:
     """Method arithmetic of a Wolff sweep per site-slice (full-rate lane-op slots): the
-    Philox share of the bond word, the local-field terms, the bond test and cluster sum,
+    Philox share of the bond's random half word, the local-field terms, the bond test and cluster sum,
     and the per-site work spread over the ring."""
     tot_ops, tot_w = 0.0, 0.0
     seen = {}
@@ -113,7 +116,7 @@ def wolff_ops_per_site_slice(jobs, O) -> float:
             emb = O.Embedding(j.kind, j.J, j.penalty)
             terms = np.diff(emb.row).astype(float)
             fields = (emb.h != 0).astype(float)
-            seen[key] = float(np.mean(PHILOX_OPS_PER_WORD + terms + fields + WOLFF_BOND_OPS
+            seen[key] = float(np.mean(PHILOX_OPS_PER_HALF + terms + fields + WOLFF_BOND_OPS
                                       + WOLFF_SITE_OPS / j.slices))
         w = j.sites * j.slices * j.replicas * j.sweeps
         tot_ops += seen[key] * w

@@ -16,27 +16,57 @@ struct Words4 {
   uint32_t v[4];
 };
 
-__device__ __forceinline__ Words4 philox4x32_10(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
-                                               uint32_t key0, uint32_t key1) {
+// Philox4x32 state between rounds: counter words and the round's key.
+struct PhiloxState {
+  uint32_t x0, x1, x2, x3, key0, key1;
+};
+
+__device__ __forceinline__ PhiloxState philox_start(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
+                                                    uint32_t key0, uint32_t key1) {
+  return PhiloxState{x0, x1, x2, x3, key0, key1};
+}
+
+// N rounds of Philox4x32 on st (a full draw is ten rounds).  Splitting the ten
+// rounds lets a caller place independent work, such as waiting LDS reads,
+// between the halves.
+template <int N>
+__device__ __forceinline__ void philox_rounds(PhiloxState &st) {
   constexpr uint32_t kMulA = 0xD2511F53u, kMulB = 0xCD9E8D57u;
   constexpr uint32_t kWeylA = 0x9E3779B9u, kWeylB = 0xBB67AE85u;
 #pragma unroll
-  for (int round = 0; round < 10; ++round) {
-    const uint64_t pa = static_cast<uint64_t>(kMulA) * x0;
-    const uint64_t pb = static_cast<uint64_t>(kMulB) * x2;
+  for (int round = 0; round < N; ++round) {
+    const uint64_t pa = static_cast<uint64_t>(kMulA) * st.x0;
+    const uint64_t pb = static_cast<uint64_t>(kMulB) * st.x2;
     // three-input XORs (truth table 0x96)
-    const uint32_t y0 = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(pb >> 32), x1, key0, 0x96);
-    const uint32_t y2 = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(pa >> 32), x3, key1, 0x96);
-    x1 = static_cast<uint32_t>(pb);
-    x3 = static_cast<uint32_t>(pa);
-    x0 = y0;
-    x2 = y2;
-    key0 += kWeylA;
-    key1 += kWeylB;
+    const uint32_t y0 = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(pb >> 32), st.x1, st.key0, 0x96);
+    const uint32_t y2 = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(pa >> 32), st.x3, st.key1, 0x96);
+    st.x1 = static_cast<uint32_t>(pb);
+    st.x3 = static_cast<uint32_t>(pa);
+    st.x0 = y0;
+    st.x2 = y2;
+    st.key0 += kWeylA;
+    st.key1 += kWeylB;
   }
+}
+
+// Makes the state's counter words count as used at this point, so that IR
+// passes cannot sink the rounds computed so far past a later scheduling
+// barrier (the empty asm emits no instruction).
+__device__ __forceinline__ void philox_pin(PhiloxState &st) {
+  asm volatile("" : "+v"(st.x0), "+v"(st.x1), "+v"(st.x2), "+v"(st.x3));
+}
+
+__device__ __forceinline__ Words4 philox_words(const PhiloxState &st) {
   Words4 r;
-  r.v[0] = x0; r.v[1] = x1; r.v[2] = x2; r.v[3] = x3;
+  r.v[0] = st.x0; r.v[1] = st.x1; r.v[2] = st.x2; r.v[3] = st.x3;
   return r;
+}
+
+__device__ __forceinline__ Words4 philox4x32_10(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
+                                               uint32_t key0, uint32_t key1) {
+  PhiloxState st = philox_start(x0, x1, x2, x3, key0, key1);
+  philox_rounds<10>(st);
+  return philox_words(st);
 }
 
 // Orders LDS accesses of one wavefront around a phase boundary.  A wave's LDS

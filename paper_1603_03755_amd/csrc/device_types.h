@@ -63,6 +63,11 @@ constexpr uint32_t kStreamSwap = 4;
 constexpr uint32_t kStreamTree = 5;
 constexpr uint32_t kStreamPTInit = 6;
 constexpr uint32_t kStreamWolff = 7;
+// Low 16 bits of the 32-bit uniforms of Metropolis attempts and Wolff bonds:
+// a uniform is (hi << 16) | lo with hi from the SQA (WOLFF) stream and lo from
+// these, at the same counter, word and half.
+constexpr uint32_t kStreamSQALo = 8;
+constexpr uint32_t kStreamWolffLo = 9;
 
 // SQA update move of a handle.
 constexpr int kMoveMetropolis = 0;   // single-site Metropolis on the space-time lattice

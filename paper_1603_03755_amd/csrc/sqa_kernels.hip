@@ -11,11 +11,14 @@
 // half (bit j = slice 2j), odd slices in the high half, a set bit = spin -1.
 // A lane processes one "item": one site, one slice parity p and one byte b of
 // the parity-p half, i.e. the eight same-parity slices 16b+p+2k (k = 0..7).
-// Four same-parity slices 8g+p+2w (w = 0..3) share one Philox4x32-10 call
-// (counter (site, 2g+p, sweep, SQA<<24 | replica), one 32-bit word per
-// slice), so an item uses the calls of groups g = 2b and 2b+1.  All
-// arithmetic is integer; acceptance compares the word with a threshold read
-// from a per-sweep table indexed by (s*f, s*(time-neighbour sum)).
+// Each attempt's uniform is the 32-bit number (hi << 16) | lo; hi is half
+// k >> 2 of word k & 3 of the Philox4x32-10 call with counter
+// (site, 2b+p, sweep, SQA<<24 | replica), and lo the same half of the call
+// with stream SQA_LO.  Acceptance compares u with a threshold R read from a
+// per-sweep table indexed by (s*f, s*(time-neighbour sum)): hi < R >> 16
+// accepts and hi > R >> 16 rejects whatever lo is, so the item draws the
+// SQA_LO call only when some hi equals its threshold's top half (probability
+// 2^-16 per attempt).  All arithmetic is integer.
 #include <hip/hip_runtime.h>
 
 #include "device_common.h"
@@ -115,16 +118,18 @@ __device__ __forceinline__ void slice_energies(const HandleDev &H, const uint64_
 // kFieldMid (F <= 63): S in 6-bit fields, four slices per word;
 // kFieldLarge (F <= 255): S in 8-bit fields, three slices per word (at bits
 //   0, 8, 16, so both operands of the 24-bit multiplies stay below 2^24).
-// FASTL: L in {16, 32, 64} (whole bytes, replicated-word rotation, L > 1);
-//   items are then taken site-major (the B = L/16 bytes of one site in
-//   neighbouring lanes share their record and partner words).
+// FL: 0 for any L, or the compile-time L in {16, 32, 64} (whole bytes,
+//   replicated-word rotation, L > 1); items are then taken site-major (the
+//   B = L/16 bytes of one site in neighbouring lanes share their record and
+//   partner words).
 // P: the slice parity.
-template <int KIND, int MODE, bool FASTL, int P>
+template <int KIND, int MODE, int FL, int P>
 __device__ __forceinline__ void sweep_class(const HandleDev &H, const uint32_t *__restrict__ rec, uint32_t *lat32,
                                             const uint32_t *tab, int c, uint32_t m, uint32_t c3, int lane) {
   constexpr int p = P;
+  constexpr bool FASTL = FL != 0;
   using S = Site<KIND>;
-  const int L = H.L;
+  const int L = FASTL ? FL : H.L;
   const int Hp = (L == 1) ? 1 : (L >> 1);       // slices of one parity
   const int B = (Hp + 7) >> 3;                  // bytes per parity half
   const int lo = H.cls[c];
@@ -180,6 +185,19 @@ __device__ __forceinline__ void sweep_class(const HandleDev &H, const uint32_t *
     const uint32_t negh = 0u - ((neg >> S::HB) & 1u);   // 0 or all ones: field sign
 
     const uint2 word = *reinterpret_cast<const uint2 *>(lat32 + 2 * d);
+    // partner bytes of the terms (LDS reads), then the first half of the Philox
+    // rounds while they are in flight (the scheduling barriers keep that order)
+    const uint8_t *lb = latb + (4 * p + b);        // the item's byte in any site word
+    uint32_t pbyte[S::T * S::P];
+#pragma unroll
+    for (int i = 0; i < S::T * S::P; ++i) pbyte[i] = lb[poff[i]];
+    const uint32_t ctr1 = static_cast<uint32_t>((b << 1) | p);
+    PhiloxState ps = philox_start(site, ctr1, m, c3, H.seed_lo, H.seed_hi);
+    __builtin_amdgcn_sched_barrier(0);
+    philox_rounds<5>(ps);
+    philox_pin(ps);
+    __builtin_amdgcn_sched_barrier(0);
+
     const uint32_t own_half = p ? word.y : word.x;
     const uint32_t oth_half = p ? word.x : word.y;
     const int sh = 8 * b;
@@ -212,7 +230,6 @@ __device__ __forceinline__ void sweep_class(const HandleDev &H, const uint32_t *
     const uint32_t ev_hi = spread6_hi(e1) + spread6_hi(e2);
 
     // weighted disagreement counts, slices k = 0..3 in acc_lo and 4..7 in acc_hi
-    const uint8_t *lb = latb + (4 * p + b);        // the item's byte in any site word
     const uint32_t ox = (own ^ negh) & 0xFFu;
     uint32_t acc_lo = 0, acc_hi = 0, acc_x = 0;     // kFieldLarge: slices 0-2, 3-5, 6-7
     if constexpr (MODE == kFieldSmall) {
@@ -231,7 +248,7 @@ __device__ __forceinline__ void sweep_class(const HandleDev &H, const uint32_t *
     for (int t = 0; t < S::T; ++t) {
       uint32_t prod = own;
 #pragma unroll
-      for (int q = 0; q < S::P; ++q) prod ^= lb[poff[S::P * t + q]];
+      for (int q = 0; q < S::P; ++q) prod ^= pbyte[S::P * t + q];
       const uint32_t x = prod ^ (0u - ((neg >> t) & 1u));
       const uint32_t wt = term_weight(wts, wts2, t);
       if constexpr (MODE == kFieldLarge) {
@@ -244,27 +261,21 @@ __device__ __forceinline__ void sweep_class(const HandleDev &H, const uint32_t *
       }
     }
 
-    const Words4 u0 = philox4x32_10(site, static_cast<uint32_t>((b << 2) | p), m, c3, H.seed_lo, H.seed_hi);
-    const Words4 u1 = philox4x32_10(site, static_cast<uint32_t>((b << 2) | 2 | p), m, c3, H.seed_lo, H.seed_hi);
-    const uint32_t *tb = tab + base;                  // thresholds are read at tb[-(6 S + e)]
-    uint32_t flip = 0;
+    // table index of each of the eight slices
+    uint32_t ix[8];
     if constexpr (MODE == kFieldSmall) {
       const uint32_t f_lo = acc_lo + ev_lo;
       const uint32_t f_hi = acc_hi + ev_hi;
 #pragma unroll
       for (int w = 0; w < 4; ++w) {
-        const uint32_t R0 = tab[__builtin_amdgcn_ubfe(f_lo, 6 * w, 6)];
-        const uint32_t R1 = tab[__builtin_amdgcn_ubfe(f_hi, 6 * w, 6)];
-        if (min(u0.v[w], 0xFFFFFFFEu) < R0) flip |= 1u << w;
-        if (min(u1.v[w], 0xFFFFFFFEu) < R1) flip |= 16u << w;
+        ix[w] = __builtin_amdgcn_ubfe(f_lo, 6 * w, 6);
+        ix[w + 4] = __builtin_amdgcn_ubfe(f_hi, 6 * w, 6);
       }
     } else if constexpr (MODE == kFieldMid) {
 #pragma unroll
       for (int w = 0; w < 4; ++w) {
-        const uint32_t i0 = 6u * __builtin_amdgcn_ubfe(acc_lo, 6 * w, 6) + __builtin_amdgcn_ubfe(ev_lo, 6 * w, 2);
-        const uint32_t i1 = 6u * __builtin_amdgcn_ubfe(acc_hi, 6 * w, 6) + __builtin_amdgcn_ubfe(ev_hi, 6 * w, 2);
-        if (min(u0.v[w], 0xFFFFFFFEu) < *(tb - i0)) flip |= 1u << w;
-        if (min(u1.v[w], 0xFFFFFFFEu) < *(tb - i1)) flip |= 16u << w;
+        ix[w] = base - (6u * __builtin_amdgcn_ubfe(acc_lo, 6 * w, 6) + __builtin_amdgcn_ubfe(ev_lo, 6 * w, 2));
+        ix[w + 4] = base - (6u * __builtin_amdgcn_ubfe(acc_hi, 6 * w, 6) + __builtin_amdgcn_ubfe(ev_hi, 6 * w, 2));
       }
     } else {
       const uint32_t sums[3] = {acc_lo, acc_hi, acc_x};
@@ -272,10 +283,39 @@ __device__ __forceinline__ void sweep_class(const HandleDev &H, const uint32_t *
       for (int w = 0; w < 4; ++w) {
         const uint32_t s0 = __builtin_amdgcn_ubfe(sums[w / 3], 8 * (w % 3), 8);
         const uint32_t s1 = __builtin_amdgcn_ubfe(sums[(w + 4) / 3], 8 * ((w + 4) % 3), 8);
-        const uint32_t i0 = 6u * s0 + __builtin_amdgcn_ubfe(ev_lo, 6 * w, 2);
-        const uint32_t i1 = 6u * s1 + __builtin_amdgcn_ubfe(ev_hi, 6 * w, 2);
-        if (min(u0.v[w], 0xFFFFFFFEu) < *(tb - i0)) flip |= 1u << w;
-        if (min(u1.v[w], 0xFFFFFFFEu) < *(tb - i1)) flip |= 16u << w;
+        ix[w] = base - (6u * s0 + __builtin_amdgcn_ubfe(ev_lo, 6 * w, 2));
+        ix[w + 4] = base - (6u * s1 + __builtin_amdgcn_ubfe(ev_hi, 6 * w, 2));
+      }
+    }
+
+    // top halves of the eight thresholds (LDS reads), the second half of the
+    // Philox rounds while they are in flight, then slice k: random half k >> 2
+    // of word k & 3 against the top half of its threshold
+    const uint16_t *tab16 = reinterpret_cast<const uint16_t *>(tab);
+    uint32_t th[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) th[k] = tab16[2 * ix[k] + 1];
+    __builtin_amdgcn_sched_barrier(0);
+    philox_rounds<5>(ps);
+    __builtin_amdgcn_sched_barrier(0);
+    const Words4 u = philox_words(ps);
+    uint32_t flip = 0;
+    bool tie = false;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const uint32_t hi = (k < 4) ? (u.v[k] & 0xFFFFu) : (u.v[k - 4] >> 16);
+      if (hi < th[k]) flip |= 1u << k;
+      tie |= (hi == th[k]);
+    }
+    if (tie) {     // some hi equals its threshold's top half: decide all eight on the full 32 bits
+      const uint32_t c3lo = (c3 & 0xFFFFFFu) | (kStreamSQALo << 24);
+      const Words4 v = philox4x32_10(site, ctr1, m, c3lo, H.seed_lo, H.seed_hi);
+      flip = 0;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const uint32_t uu = (k < 4) ? ((u.v[k] << 16) | (v.v[k] & 0xFFFFu))
+                                    : ((u.v[k - 4] & 0xFFFF0000u) | (v.v[k - 4] >> 16));
+        if (min(uu, 0xFFFFFFFEu) < tab[ix[k]]) flip |= 1u << k;
       }
     }
     if (ragged) {            // slices beyond the parity's last one stay put
@@ -296,7 +336,7 @@ __device__ __forceinline__ void anneal_replica(const HandleDev &H, const uint32_
   const int parities = (H.L == 1) ? 1 : 2;
   const bool smallf = H.F <= kSmallF;
   const bool midf = H.F <= kMidF;
-  const bool fast = smallf && (H.L == 16 || H.L == 32 || H.L == 64);
+  const int fast = (smallf && (H.L == 16 || H.L == 32 || H.L == 64)) ? H.L : 0;   // compile-time L variants
   // the next sweep's table row is fetched into a register during the current sweep
   const bool row_in_reg = H.tw <= 64;
   uint32_t next_row = 0;
@@ -313,18 +353,22 @@ __device__ __forceinline__ void anneal_replica(const HandleDev &H, const uint32_
     uint32_t *lat32 = reinterpret_cast<uint32_t *>(lat);
     const uint32_t mm = static_cast<uint32_t>(m);
     for (int c = 0; c < 4; ++c) {
-      if (fast) sweep_class<KIND, kFieldSmall, true, 0>(H, rec, lat32, tab, c, mm, c3, lane);
-      else if (smallf) sweep_class<KIND, kFieldSmall, false, 0>(H, rec, lat32, tab, c, mm, c3, lane);
-      else if (midf) sweep_class<KIND, kFieldMid, false, 0>(H, rec, lat32, tab, c, mm, c3, lane);
-      else sweep_class<KIND, kFieldLarge, false, 0>(H, rec, lat32, tab, c, mm, c3, lane);
+      if (fast == 64) sweep_class<KIND, kFieldSmall, 64, 0>(H, rec, lat32, tab, c, mm, c3, lane);
+      else if (fast == 32) sweep_class<KIND, kFieldSmall, 32, 0>(H, rec, lat32, tab, c, mm, c3, lane);
+      else if (fast == 16) sweep_class<KIND, kFieldSmall, 16, 0>(H, rec, lat32, tab, c, mm, c3, lane);
+      else if (smallf) sweep_class<KIND, kFieldSmall, 0, 0>(H, rec, lat32, tab, c, mm, c3, lane);
+      else if (midf) sweep_class<KIND, kFieldMid, 0, 0>(H, rec, lat32, tab, c, mm, c3, lane);
+      else sweep_class<KIND, kFieldLarge, 0, 0>(H, rec, lat32, tab, c, mm, c3, lane);
       wave_sync();
     }
     if (parities > 1)
       for (int c = 0; c < 4; ++c) {
-        if (fast) sweep_class<KIND, kFieldSmall, true, 1>(H, rec, lat32, tab, c, mm, c3, lane);
-        else if (smallf) sweep_class<KIND, kFieldSmall, false, 1>(H, rec, lat32, tab, c, mm, c3, lane);
-        else if (midf) sweep_class<KIND, kFieldMid, false, 1>(H, rec, lat32, tab, c, mm, c3, lane);
-        else sweep_class<KIND, kFieldLarge, false, 1>(H, rec, lat32, tab, c, mm, c3, lane);
+        if (fast == 64) sweep_class<KIND, kFieldSmall, 64, 1>(H, rec, lat32, tab, c, mm, c3, lane);
+        else if (fast == 32) sweep_class<KIND, kFieldSmall, 32, 1>(H, rec, lat32, tab, c, mm, c3, lane);
+        else if (fast == 16) sweep_class<KIND, kFieldSmall, 16, 1>(H, rec, lat32, tab, c, mm, c3, lane);
+        else if (smallf) sweep_class<KIND, kFieldSmall, 0, 1>(H, rec, lat32, tab, c, mm, c3, lane);
+        else if (midf) sweep_class<KIND, kFieldMid, 0, 1>(H, rec, lat32, tab, c, mm, c3, lane);
+        else sweep_class<KIND, kFieldLarge, 0, 1>(H, rec, lat32, tab, c, mm, c3, lane);
         wave_sync();
       }
   }
@@ -338,9 +382,11 @@ __device__ __forceinline__ void anneal_replica(const HandleDev &H, const uint32_
 // each colour class, two phases separated by a wave-level barrier:
 //  1. item = (site of the class, byte q of its word): the eight slices
 //     8q..8q+7 and the ring bonds that start at them.  Bond b = 8q+k joins
-//     when its two spins are equal and its word (word b & 3 of the WOLFF call
-//     with counter word 1 = b >> 2, so calls 2q and 2q+1) passes the sweep's
-//     join threshold.  The item also forms, per slice, the weighted
+//     when its two spins are equal and its 32-bit uniform (hi << 16) | lo
+//     passes the sweep's join threshold; hi is half k >> 2 of word k & 3 of
+//     the WOLFF call with counter word 1 = q, lo the same from the WOLFF_LO
+//     call, drawn only on a tie of hi with the threshold's top half.  The
+//     item also forms, per slice, the weighted
 //     disagreement sum S = sum_t |w_t| X_t + |h| O (as in the Metropolis
 //     kernel; s f = F_site - 2 S) as one byte per slice.  Join bits and S bytes
 //     go to the wave's LDS scratch.
@@ -420,6 +466,14 @@ __device__ __forceinline__ void wolff_bonds(const HandleDev &H, const uint32_t *
       }
     }
     const uint64_t w = lat[d];
+    // partner bytes of the terms (LDS reads) stay in flight during the Philox rounds
+    const uint8_t *lb = latb + q;
+    uint32_t pbyte[S::T * S::P];
+#pragma unroll
+    for (int i = 0; i < S::T * S::P; ++i) pbyte[i] = lb[poff[i]];
+    __builtin_amdgcn_sched_barrier(0);
+    const Words4 u = philox4x32_10(site, static_cast<uint32_t>(q), m, c3, H.seed_lo, H.seed_hi);
+    __builtin_amdgcn_sched_barrier(0);
     const int sh = 8 * q;
     const uint32_t own = static_cast<uint32_t>(w >> sh) & 0xFFu;
     // bit tau of nx: the spin of slice tau + 1 (mod L)
@@ -428,13 +482,28 @@ __device__ __forceinline__ void wolff_bonds(const HandleDev &H, const uint32_t *
     const uint32_t valid = (L - sh >= 8) ? 0xFFu : ((1u << (L - sh)) - 1u);
     const uint32_t eq = ~(own ^ nb) & valid;
 
-    const Words4 u0 = philox4x32_10(site, static_cast<uint32_t>(2 * q), m, c3, H.seed_lo, H.seed_hi);
-    const Words4 u1 = philox4x32_10(site, static_cast<uint32_t>(2 * q + 1), m, c3, H.seed_lo, H.seed_hi);
+    // bond 8q+k: uniform (hi << 16) | lo, hi = half k >> 2 of word k & 3 of the
+    // WOLFF call (site, q, sweep), lo the same from the WOLFF_LO call, drawn only
+    // when some hi equals the top half of the join threshold
+    const uint32_t ph = padd >> 16;
     uint32_t join = 0;
+    bool tie = false;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      if (min(u0.v[k], 0xFFFFFFFEu) < padd) join |= 1u << k;
-      if (min(u1.v[k], 0xFFFFFFFEu) < padd) join |= 16u << k;
+    for (int k = 0; k < 8; ++k) {
+      const uint32_t hi = (k < 4) ? (u.v[k] & 0xFFFFu) : (u.v[k - 4] >> 16);
+      if (hi < ph) join |= 1u << k;
+      tie |= (hi == ph);
+    }
+    if (tie) {
+      const uint32_t c3lo = (c3 & 0xFFFFFFu) | (kStreamWolffLo << 24);
+      const Words4 v = philox4x32_10(site, static_cast<uint32_t>(q), m, c3lo, H.seed_lo, H.seed_hi);
+      join = 0;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const uint32_t uu = (k < 4) ? ((u.v[k] << 16) | (v.v[k] & 0xFFFFu))
+                                    : ((u.v[k - 4] & 0xFFFF0000u) | (v.v[k - 4] >> 16));
+        if (min(uu, 0xFFFFFFFEu) < padd) join |= 1u << k;
+      }
     }
     jb[8 * j + q] = static_cast<uint8_t>(join & eq);
 
@@ -443,7 +512,6 @@ __device__ __forceinline__ void wolff_bonds(const HandleDev &H, const uint32_t *
     // (acc_lo 0-2, acc_hi 3-5, acc_x 6-7); both keep the operands of the 24-bit
     // multiplies below 2^24.  Repacked to one byte per slice for the store.
     const uint32_t negh = 0u - ((neg >> S::HB) & 1u);
-    const uint8_t *lb = latb + q;
     const uint32_t ox = (own ^ negh) & 0xFFu;
     uint32_t acc_lo, acc_hi, acc_x = 0;
     if constexpr (LARGE) {
@@ -458,7 +526,7 @@ __device__ __forceinline__ void wolff_bonds(const HandleDev &H, const uint32_t *
     for (int t = 0; t < S::T; ++t) {
       uint32_t prod = own;
 #pragma unroll
-      for (int x = 0; x < S::P; ++x) prod ^= lb[poff[S::P * t + x]];
+      for (int x = 0; x < S::P; ++x) prod ^= pbyte[S::P * t + x];
       const uint32_t xt = prod ^ (0u - ((neg >> t) & 1u));
       const uint32_t wt = term_weight(wts, wts2, t);
       if constexpr (LARGE) {
