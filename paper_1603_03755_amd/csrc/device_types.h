@@ -66,6 +66,9 @@ constexpr uint32_t kStreamWolff = 7;
 // Low 16 bits of the 32-bit uniforms of Metropolis attempts and Wolff bonds:
 // a uniform is (hi << 16) | lo with hi from the SQA (WOLFF) stream and lo from
 // these, at the same counter, word and half.
+// LDS table at the start of the anneal kernel's dynamic LDS: byte x ->
+// (spread of its low nibble, spread of its high nibble) into 6-bit fields.
+constexpr int kSpreadWords = 512;
 constexpr uint32_t kStreamSQALo = 8;
 constexpr uint32_t kStreamWolffLo = 9;
 

@@ -124,7 +124,8 @@ struct LaunchShape {
   int grid = 0;
   int rec_cap = 0, lat_cap = 0, tab_cap = 0;
   size_t lds_bytes() const {
-    return (static_cast<size_t>(rec_cap) + 2ull * waves * lat_cap + static_cast<size_t>(waves) * tab_cap) * 4;
+    return (static_cast<size_t>(kSpreadWords) + rec_cap + 2ull * waves * lat_cap +
+            static_cast<size_t>(waves) * tab_cap) * 4;
   }
 };
 

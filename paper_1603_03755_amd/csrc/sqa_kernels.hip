@@ -100,6 +100,15 @@ __device__ __forceinline__ void slice_energies(const HandleDev &H, const uint64_
   H.energy[static_cast<size_t>(rep) * H.L + tau] = E;
 }
 
+// Entry x of the byte -> spread table; each word holds bits 0, 6, 12, 18 at
+// most (the assumption lets the multiplies by it be 24-bit ones).
+__device__ __forceinline__ uint2 spread_of(const uint2 *stab, uint32_t x) {
+  const uint2 v = stab[x];
+  __builtin_assume(v.x <= 0x41041u);
+  __builtin_assume(v.y <= 0x41041u);
+  return v;
+}
+
 // ------------------------------------------------------------ SQA sweep
 // 64-lane item loop over one (slice parity p, colour c) class of one replica.
 // Item = (site of colour c, byte b of its parity-p half word): the eight slices
@@ -125,7 +134,8 @@ __device__ __forceinline__ void slice_energies(const HandleDev &H, const uint64_
 // P: the slice parity.
 template <int KIND, int MODE, int FL, int P>
 __device__ __forceinline__ void sweep_class(const HandleDev &H, const uint32_t *__restrict__ rec, uint32_t *lat32,
-                                            const uint32_t *tab, int c, uint32_t m, uint32_t c3, int lane) {
+                                            const uint32_t *tab, const uint2 *stab, int c, uint32_t m, uint32_t c3,
+                                            int lane) {
   constexpr int p = P;
   constexpr bool FASTL = FL != 0;
   using S = Site<KIND>;
@@ -226,38 +236,42 @@ __device__ __forceinline__ void sweep_class(const HandleDev &H, const uint32_t *
     // disagreeing (agreeing, kFieldSmall) time neighbours
     const uint32_t agree = (MODE == kFieldSmall) ? 0xFFu : 0u;
     const uint32_t e1 = own ^ dn ^ agree, e2 = own ^ up ^ agree;
-    const uint32_t ev_lo = spread6(__builtin_amdgcn_ubfe(e1, 0, 4)) + spread6(__builtin_amdgcn_ubfe(e2, 0, 4));
-    const uint32_t ev_hi = spread6_hi(e1) + spread6_hi(e2);
+    const uint2 se1 = spread_of(stab, e1), se2 = spread_of(stab, e2);
+    const uint32_t ev_lo = se1.x + se2.x;
+    const uint32_t ev_hi = se1.y + se2.y;
 
     // weighted disagreement counts, slices k = 0..3 in acc_lo and 4..7 in acc_hi
     const uint32_t ox = (own ^ negh) & 0xFFu;
     uint32_t acc_lo = 0, acc_hi = 0, acc_x = 0;     // kFieldLarge: slices 0-2, 3-5, 6-7
     if constexpr (MODE == kFieldSmall) {
       const uint32_t c4 = __umul24(base, 0x41041u);       // c in every field
-      acc_lo = c4 + __umul24(spread6(__builtin_amdgcn_ubfe(ox, 0, 4)), hw);
-      acc_hi = c4 + __umul24(spread6(__builtin_amdgcn_ubfe(ox, 4, 4)), hw);
+      const uint2 so = spread_of(stab, ox);
+      acc_lo = c4 + __umul24(so.x, hw);
+      acc_hi = c4 + __umul24(so.y, hw);
     } else if constexpr (MODE == kFieldLarge) {
       acc_lo = __umul24(spread3(ox), hw);
       acc_hi = __umul24(spread3(ox >> 3), hw);
       acc_x = __umul24(spread3(ox >> 6), hw);
     } else {
-      acc_lo = __umul24(spread6(__builtin_amdgcn_ubfe(ox, 0, 4)), hw);
-      acc_hi = __umul24(spread6(__builtin_amdgcn_ubfe(ox, 4, 4)), hw);
+      const uint2 so = spread_of(stab, ox);
+      acc_lo = __umul24(so.x, hw);
+      acc_hi = __umul24(so.y, hw);
     }
 #pragma unroll
     for (int t = 0; t < S::T; ++t) {
       uint32_t prod = own;
 #pragma unroll
       for (int q = 0; q < S::P; ++q) prod ^= pbyte[S::P * t + q];
-      const uint32_t x = prod ^ (0u - ((neg >> t) & 1u));
+      const uint32_t x = (prod ^ (0u - ((neg >> t) & 1u))) & 0xFFu;
       const uint32_t wt = term_weight(wts, wts2, t);
       if constexpr (MODE == kFieldLarge) {
         acc_lo += __umul24(spread3(x), wt);
         acc_hi += __umul24(spread3(x >> 3), wt);
         acc_x += __umul24(spread3(x >> 6), wt);
       } else {
-        acc_lo += __umul24(spread6(__builtin_amdgcn_ubfe(x, 0, 4)), wt);
-        acc_hi += __umul24(spread6(__builtin_amdgcn_ubfe(x, 4, 4)), wt);
+        const uint2 sx = spread_of(stab, x);
+        acc_lo += __umul24(sx.x, wt);
+        acc_hi += __umul24(sx.y, wt);
       }
     }
 
@@ -328,7 +342,7 @@ __device__ __forceinline__ void sweep_class(const HandleDev &H, const uint32_t *
 
 template <int KIND>
 __device__ __forceinline__ void anneal_replica(const HandleDev &H, const uint32_t *rec, uint64_t *lat, uint32_t *tab,
-                               int rep, int lane) {
+                                               const uint2 *stab, int rep, int lane) {
   if (H.flags & kFlagInit) init_lattice<false>(H, lat, rep, lane);
   else load_lattice<false>(H, lat, rep, lane);
   wave_sync();
@@ -353,22 +367,22 @@ __device__ __forceinline__ void anneal_replica(const HandleDev &H, const uint32_
     uint32_t *lat32 = reinterpret_cast<uint32_t *>(lat);
     const uint32_t mm = static_cast<uint32_t>(m);
     for (int c = 0; c < 4; ++c) {
-      if (fast == 64) sweep_class<KIND, kFieldSmall, 64, 0>(H, rec, lat32, tab, c, mm, c3, lane);
-      else if (fast == 32) sweep_class<KIND, kFieldSmall, 32, 0>(H, rec, lat32, tab, c, mm, c3, lane);
-      else if (fast == 16) sweep_class<KIND, kFieldSmall, 16, 0>(H, rec, lat32, tab, c, mm, c3, lane);
-      else if (smallf) sweep_class<KIND, kFieldSmall, 0, 0>(H, rec, lat32, tab, c, mm, c3, lane);
-      else if (midf) sweep_class<KIND, kFieldMid, 0, 0>(H, rec, lat32, tab, c, mm, c3, lane);
-      else sweep_class<KIND, kFieldLarge, 0, 0>(H, rec, lat32, tab, c, mm, c3, lane);
+      if (fast == 64) sweep_class<KIND, kFieldSmall, 64, 0>(H, rec, lat32, tab, stab, c, mm, c3, lane);
+      else if (fast == 32) sweep_class<KIND, kFieldSmall, 32, 0>(H, rec, lat32, tab, stab, c, mm, c3, lane);
+      else if (fast == 16) sweep_class<KIND, kFieldSmall, 16, 0>(H, rec, lat32, tab, stab, c, mm, c3, lane);
+      else if (smallf) sweep_class<KIND, kFieldSmall, 0, 0>(H, rec, lat32, tab, stab, c, mm, c3, lane);
+      else if (midf) sweep_class<KIND, kFieldMid, 0, 0>(H, rec, lat32, tab, stab, c, mm, c3, lane);
+      else sweep_class<KIND, kFieldLarge, 0, 0>(H, rec, lat32, tab, stab, c, mm, c3, lane);
       wave_sync();
     }
     if (parities > 1)
       for (int c = 0; c < 4; ++c) {
-        if (fast == 64) sweep_class<KIND, kFieldSmall, 64, 1>(H, rec, lat32, tab, c, mm, c3, lane);
-        else if (fast == 32) sweep_class<KIND, kFieldSmall, 32, 1>(H, rec, lat32, tab, c, mm, c3, lane);
-        else if (fast == 16) sweep_class<KIND, kFieldSmall, 16, 1>(H, rec, lat32, tab, c, mm, c3, lane);
-        else if (smallf) sweep_class<KIND, kFieldSmall, 0, 1>(H, rec, lat32, tab, c, mm, c3, lane);
-        else if (midf) sweep_class<KIND, kFieldMid, 0, 1>(H, rec, lat32, tab, c, mm, c3, lane);
-        else sweep_class<KIND, kFieldLarge, 0, 1>(H, rec, lat32, tab, c, mm, c3, lane);
+        if (fast == 64) sweep_class<KIND, kFieldSmall, 64, 1>(H, rec, lat32, tab, stab, c, mm, c3, lane);
+        else if (fast == 32) sweep_class<KIND, kFieldSmall, 32, 1>(H, rec, lat32, tab, stab, c, mm, c3, lane);
+        else if (fast == 16) sweep_class<KIND, kFieldSmall, 16, 1>(H, rec, lat32, tab, stab, c, mm, c3, lane);
+        else if (smallf) sweep_class<KIND, kFieldSmall, 0, 1>(H, rec, lat32, tab, stab, c, mm, c3, lane);
+        else if (midf) sweep_class<KIND, kFieldMid, 0, 1>(H, rec, lat32, tab, stab, c, mm, c3, lane);
+        else sweep_class<KIND, kFieldLarge, 0, 1>(H, rec, lat32, tab, stab, c, mm, c3, lane);
         wave_sync();
       }
   }
@@ -610,8 +624,8 @@ __device__ __forceinline__ void wolff_replica(const HandleDev &H, const uint32_t
 // each workgroup repeatedly takes the next work item (handle, replica group)
 // from `counter`, stages the handle's site records in LDS, and runs one
 // replica per wavefront through sweeps m0..m1-1.
-// Dynamic LDS: [rec_cap words][waves x lat_cap u64][waves x tab_cap words]
-// (tab: the Metropolis table row, or the Wolff phase scratch).
+// Dynamic LDS: [kSpreadWords: byte -> spread table][rec_cap words][waves x lat_cap u64]
+// [waves x tab_cap words] (tab: the Metropolis table row, or the Wolff phase scratch).
 #ifndef SQA_WAVES_PER_EU
 #define SQA_WAVES_PER_EU 1
 #endif
@@ -625,9 +639,12 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(SQA_WAVES_P
   const int waves = blockDim.x >> 6;
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
-  uint32_t *rec = smem;
-  uint64_t *lat = reinterpret_cast<uint64_t *>(smem + rec_cap) + static_cast<size_t>(wave) * lat_cap;
-  uint32_t *tab = smem + rec_cap + 2 * waves * lat_cap + wave * tab_cap;
+  uint2 *stab = reinterpret_cast<uint2 *>(smem);
+  uint32_t *rec = smem + kSpreadWords;
+  uint64_t *lat = reinterpret_cast<uint64_t *>(rec + rec_cap) + static_cast<size_t>(wave) * lat_cap;
+  uint32_t *tab = rec + rec_cap + 2 * waves * lat_cap + wave * tab_cap;
+  for (int x = threadIdx.x; x < kSpreadWords / 2; x += blockDim.x)
+    stab[x] = make_uint2(spread6(static_cast<uint32_t>(x) & 0xFu), spread6(static_cast<uint32_t>(x) >> 4));
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
     __syncthreads();
@@ -645,9 +662,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(SQA_WAVES_P
         else if (H.kind == kKindLHZ) wolff_replica<kKindLHZ>(H, rec, lat, tab, wi.rep0 + wave, lane);
         else wolff_replica<kKindMEC>(H, rec, lat, tab, wi.rep0 + wave, lane);
       } else {
-        if (H.kind == kKindME) anneal_replica<kKindME>(H, rec, lat, tab, wi.rep0 + wave, lane);
-        else if (H.kind == kKindLHZ) anneal_replica<kKindLHZ>(H, rec, lat, tab, wi.rep0 + wave, lane);
-        else anneal_replica<kKindMEC>(H, rec, lat, tab, wi.rep0 + wave, lane);
+        if (H.kind == kKindME) anneal_replica<kKindME>(H, rec, lat, tab, stab, wi.rep0 + wave, lane);
+        else if (H.kind == kKindLHZ) anneal_replica<kKindLHZ>(H, rec, lat, tab, stab, wi.rep0 + wave, lane);
+        else anneal_replica<kKindMEC>(H, rec, lat, tab, stab, wi.rep0 + wave, lane);
       }
     }
     __syncthreads();
@@ -719,7 +736,8 @@ __global__ void me_majority_kernel(const int8_t *__restrict__ spins, int N, int 
 hipError_t launch_sqa_anneal(int move, const HandleDev *hds, const WorkItem *items, int n_items, int *counter,
                              int grid, int waves, int rec_cap, int lat_cap, int tab_cap,
                              hipStream_t stream) {
-  const size_t lds = (static_cast<size_t>(rec_cap) + 2ull * waves * lat_cap + static_cast<size_t>(waves) * tab_cap) * 4;
+  const size_t lds = (static_cast<size_t>(kSpreadWords) + rec_cap + 2ull * waves * lat_cap +
+                      static_cast<size_t>(waves) * tab_cap) * 4;
   (void)hipGetLastError();
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, stream, counter);
   hipError_t e = hipGetLastError();
