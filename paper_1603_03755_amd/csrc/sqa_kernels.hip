@@ -436,8 +436,8 @@ __device__ __forceinline__ uint64_t ring_cluster(uint64_t jn, int t0, int L) {
 
 template <int KIND, bool LARGE>
 __device__ __forceinline__ void wolff_bonds(const HandleDev &H, const uint32_t *__restrict__ rec, const uint64_t *lat,
-                                            uint32_t *scr, int lo, int nc, uint32_t m, uint32_t c3, uint32_t padd,
-                                            int lane) {
+                                            uint32_t *scr, const uint2 *stab, int lo, int nc, uint32_t m, uint32_t c3,
+                                            uint32_t padd, int lane) {
   using S = Site<KIND>;
   const int L = H.L;
   const int Q = (L + 7) >> 3;
@@ -533,23 +533,25 @@ __device__ __forceinline__ void wolff_bonds(const HandleDev &H, const uint32_t *
       acc_hi = __umul24(spread3(ox >> 3), hw);
       acc_x = __umul24(spread3(ox >> 6), hw);
     } else {
-      acc_lo = __umul24(spread6(__builtin_amdgcn_ubfe(ox, 0, 4)), hw);
-      acc_hi = __umul24(spread6(__builtin_amdgcn_ubfe(ox, 4, 4)), hw);
+      const uint2 so = spread_of(stab, ox);
+      acc_lo = __umul24(so.x, hw);
+      acc_hi = __umul24(so.y, hw);
     }
 #pragma unroll
     for (int t = 0; t < S::T; ++t) {
       uint32_t prod = own;
 #pragma unroll
       for (int x = 0; x < S::P; ++x) prod ^= pbyte[S::P * t + x];
-      const uint32_t xt = prod ^ (0u - ((neg >> t) & 1u));
+      const uint32_t xt = (prod ^ (0u - ((neg >> t) & 1u))) & 0xFFu;
       const uint32_t wt = term_weight(wts, wts2, t);
       if constexpr (LARGE) {
         acc_lo += __umul24(spread3(xt), wt);
         acc_hi += __umul24(spread3(xt >> 3), wt);
         acc_x += __umul24(spread3(xt >> 6), wt);
       } else {
-        acc_lo += __umul24(spread6(__builtin_amdgcn_ubfe(xt, 0, 4)), wt);
-        acc_hi += __umul24(spread6(__builtin_amdgcn_ubfe(xt, 4, 4)), wt);
+        const uint2 sx = spread_of(stab, xt);
+        acc_lo += __umul24(sx.x, wt);
+        acc_hi += __umul24(sx.y, wt);
       }
     }
     if constexpr (LARGE) {
@@ -594,7 +596,7 @@ __device__ __forceinline__ void wolff_flips(const HandleDev &H, const uint32_t *
 
 template <int KIND>
 __device__ __forceinline__ void wolff_replica(const HandleDev &H, const uint32_t *rec, uint64_t *lat, uint32_t *scr,
-                                              int rep, int lane) {
+                                              const uint2 *stab, int rep, int lane) {
   if (H.flags & kFlagInit) init_lattice<true>(H, lat, rep, lane);
   else load_lattice<true>(H, lat, rep, lane);
   wave_sync();
@@ -608,8 +610,8 @@ __device__ __forceinline__ void wolff_replica(const HandleDev &H, const uint32_t
       for (int lo = H.cls[c]; lo < H.cls[c + 1]; lo += kWolffChunk) {
         const int nc = min(kWolffChunk, H.cls[c + 1] - lo);
         const uint32_t mm = static_cast<uint32_t>(m);
-        if (H.F > kMidF) wolff_bonds<KIND, true>(H, rec, lat, scr, lo, nc, mm, c3, padd, lane);
-        else wolff_bonds<KIND, false>(H, rec, lat, scr, lo, nc, mm, c3, padd, lane);
+        if (H.F > kMidF) wolff_bonds<KIND, true>(H, rec, lat, scr, stab, lo, nc, mm, c3, padd, lane);
+        else wolff_bonds<KIND, false>(H, rec, lat, scr, stab, lo, nc, mm, c3, padd, lane);
         wave_sync();
         wolff_flips<KIND>(H, rec, lat, scr, lo, nc, mm, c3, arow, lane);
         wave_sync();
@@ -658,9 +660,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(SQA_WAVES_P
     __syncthreads();
     if (wave < wi.nrep) {
       if constexpr (MOVE == kMoveWolff) {
-        if (H.kind == kKindME) wolff_replica<kKindME>(H, rec, lat, tab, wi.rep0 + wave, lane);
-        else if (H.kind == kKindLHZ) wolff_replica<kKindLHZ>(H, rec, lat, tab, wi.rep0 + wave, lane);
-        else wolff_replica<kKindMEC>(H, rec, lat, tab, wi.rep0 + wave, lane);
+        if (H.kind == kKindME) wolff_replica<kKindME>(H, rec, lat, tab, stab, wi.rep0 + wave, lane);
+        else if (H.kind == kKindLHZ) wolff_replica<kKindLHZ>(H, rec, lat, tab, stab, wi.rep0 + wave, lane);
+        else wolff_replica<kKindMEC>(H, rec, lat, tab, stab, wi.rep0 + wave, lane);
       } else {
         if (H.kind == kKindME) anneal_replica<kKindME>(H, rec, lat, tab, stab, wi.rep0 + wave, lane);
         else if (H.kind == kKindLHZ) anneal_replica<kKindLHZ>(H, rec, lat, tab, stab, wi.rep0 + wave, lane);
