@@ -18,7 +18,7 @@ _lib = None
 
 ME, LHZ, MEC = 0, 1, 2
 STREAM_INIT, STREAM_SQA, STREAM_PT, STREAM_SWAP, STREAM_TREE, STREAM_PT_INIT, STREAM_WOLFF = 1, 2, 3, 4, 5, 6, 7
-STREAM_SQA_LO, STREAM_WOLFF_LO = 8, 9
+STREAM_SQA_LO, STREAM_WOLFF_LO, STREAM_PT_LO = 8, 9, 10
 ALWAYS = 0xFFFFFFFF
 
 
@@ -48,6 +48,8 @@ def lib():
         L.oracle_sqa_uniform.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32]
         L.oracle_pt_word.restype = C.c_uint32
         L.oracle_pt_word.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32]
+        L.oracle_pt_uniform.restype = C.c_uint32
+        L.oracle_pt_uniform.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32]
         L.oracle_threshold.restype = C.c_uint32
         L.oracle_threshold.argtypes = [C.c_double]
         L.oracle_embed.restype = C.c_int
@@ -102,6 +104,11 @@ def sqa_uniform(seed, replica, site, slice_, sweep) -> int:
 
 def pt_word(seed, stream, replica, site, sweep) -> int:
     return int(lib().oracle_pt_word(seed, stream, replica, site, sweep))
+
+
+def pt_uniform(seed, replica, site, sweep) -> int:
+    """The 32-bit uniform of one PT Metropolis attempt (high half stream PT, low half PT_LO)."""
+    return int(lib().oracle_pt_uniform(seed, replica, site, sweep))
 
 
 # ---------------------------------------------------------------- embeddings

@@ -30,7 +30,7 @@ extern "C" {
 /* RNG streams of the counter layout. */
 enum { OR_STREAM_INIT = 1, OR_STREAM_SQA = 2, OR_STREAM_PT = 3,
        OR_STREAM_SWAP = 4, OR_STREAM_TREE = 5, OR_STREAM_PT_INIT = 6, OR_STREAM_WOLFF = 7,
-       OR_STREAM_SQA_LO = 8, OR_STREAM_WOLFF_LO = 9 };
+       OR_STREAM_SQA_LO = 8, OR_STREAM_WOLFF_LO = 9, OR_STREAM_PT_LO = 10 };
 
 enum { OR_ME = 0, OR_LHZ = 1, OR_MEC = 2 };
 
@@ -59,6 +59,7 @@ uint32_t oracle_sqa_word(uint64_t seed, uint32_t stream, uint32_t replica,
 uint32_t oracle_sqa_uniform(uint64_t seed, uint32_t replica, uint32_t site, uint32_t slice, uint32_t sweep);
 uint32_t oracle_pt_word(uint64_t seed, uint32_t stream, uint32_t replica,
                         uint32_t site, uint32_t sweep);
+uint32_t oracle_pt_uniform(uint64_t seed, uint32_t replica, uint32_t site, uint32_t sweep);
 
 /* ---- embeddings ---------------------------------------------------------- */
 int  oracle_embed(int32_t kind, int32_t N, const int32_t *J, const int32_t *h,

@@ -24,8 +24,14 @@
  *     of one site.  u is uniform on 0 .. 2^32-1 because hi and lo are
  *     independent uniform halves; since lo matters only when hi equals the
  *     top half of the threshold, an implementation may draw it only then.
- *   PT attempt (replica rho, site k, sweep m), stream s:
- *     counter = (k, rho>>2, m, s<<24), word = rho & 3.
+ *   PT initial spin (replica rho, site k), stream PT_INIT:
+ *     counter = (k, rho>>2, 0, PT_INIT<<24), word = rho & 3 (its top bit).
+ *   PT Metropolis uniform of attempt (replica rho, site k, sweep m): the
+ *     32-bit u = (hi << 16) | lo with hi and lo the 16-bit half (rho>>2) & 1
+ *     of word rho & 3 of the calls with counter (k, rho>>3, m, stream<<24),
+ *     stream PT for hi and PT_LO for lo: one call per stream serves the eight
+ *     replicas 8g..8g+7 of a site, and lo matters only on a tie of hi with the
+ *     threshold's top half.
  */
 #include "oracle.h"
 
@@ -98,6 +104,24 @@ static uint32_t sqa_half(uint64_t seed, uint32_t stream, uint32_t replica, uint3
 uint32_t oracle_sqa_uniform(uint64_t seed, uint32_t replica, uint32_t site, uint32_t slice, uint32_t sweep) {
   return (sqa_half(seed, OR_STREAM_SQA, replica, site, slice, sweep) << 16) |
          sqa_half(seed, OR_STREAM_SQA_LO, replica, site, slice, sweep);
+}
+
+static uint32_t pt_half(uint64_t seed, uint32_t stream, uint32_t replica, uint32_t site, uint32_t sweep) {
+  uint32_t ctr[4], key[2], out[4];
+  ctr[0] = site;
+  ctr[1] = replica >> 3;
+  ctr[2] = sweep;
+  ctr[3] = stream << 24;
+  key[0] = (uint32_t)seed;
+  key[1] = (uint32_t)(seed >> 32);
+  oracle_philox4x32(ctr, key, out);
+  uint32_t w = out[replica & 3u];
+  return ((replica >> 2) & 1u) ? (w >> 16) : (w & 0xFFFFu);
+}
+
+uint32_t oracle_pt_uniform(uint64_t seed, uint32_t replica, uint32_t site, uint32_t sweep) {
+  return (pt_half(seed, OR_STREAM_PT, replica, site, sweep) << 16) |
+         pt_half(seed, OR_STREAM_PT_LO, replica, site, sweep);
 }
 
 uint32_t oracle_pt_word(uint64_t seed, uint32_t stream, uint32_t replica,

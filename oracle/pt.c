@@ -18,7 +18,9 @@
  *     Philox call with counter (r, 0, q, SWAP<<24);
  *   - energies are kept incrementally: an accepted flip of a site with
  *     a = s*f changes E by -2a.
- *   - replica rho starts in slot rho; its initial spins use the PT_INIT stream.
+ *   - replica rho starts in slot rho; its initial spins use the PT_INIT stream;
+ *   - the Metropolis test flips iff the threshold is the always-code or
+ *     u < threshold, u the attempt's 32-bit uniform (oracle_pt_uniform).
  */
 #include <stdlib.h>
 #include "oracle.h"
@@ -58,7 +60,7 @@ void oracle_pt_run(const OEmb *e, int32_t R, int32_t sweeps, int32_t sweeps_per_
           if (e->colour[k] != c) continue;
           int a = s[k] * oracle_local_field(e, s, k);
           uint32_t T = mtab[(size_t)slot_of[rho] * width + (a + F)];
-          uint32_t u = oracle_pt_word(seed, OR_STREAM_PT, (uint32_t)rho, (uint32_t)k, (uint32_t)m);
+          uint32_t u = oracle_pt_uniform(seed, (uint32_t)rho, (uint32_t)k, (uint32_t)m);
           if (T == 0xFFFFFFFFu || u < T) {
             s[k] = (int8_t)-s[k];
             E[rho] += -2 * a;

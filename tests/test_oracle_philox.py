@@ -85,7 +85,7 @@ def test_sqa_uniform_counter_layout():
             assert O.sqa_uniform(seed, r, k, t2, m) == want
 
 
-@pytest.mark.parametrize("fn", ["sqa", "wolff"])
+@pytest.mark.parametrize("fn", ["sqa", "wolff", "pt"])
 def test_attempt_uniforms_are_uniform_with_independent_halves(fn):
     """The 32-bit attempt uniforms: both halves uniform, the low half independent of
     the high half (a low half drawn from the high half's stream would coincide with
@@ -95,9 +95,12 @@ def test_attempt_uniforms_are_uniform_with_independent_halves(fn):
     if fn == "sqa":
         u = np.array([O.sqa_uniform(seed, r, k, t, m) for r in range(2) for k in range(6)
                       for t in range(64) for m in range(8)], dtype=np.uint64)
-    else:
+    elif fn == "wolff":
         u = np.array([O.wolff_bond_uniform(seed, r, k, b, m) for r in range(2) for k in range(6)
                       for b in range(64) for m in range(8)], dtype=np.uint64)
+    else:
+        u = np.array([O.pt_uniform(seed, rho, k, m) for rho in range(64) for k in range(12)
+                      for m in range(8)], dtype=np.uint64)
     n = u.size
     hi, lo = u >> 16, u & 0xFFFF
     assert np.mean(hi == lo) < 5.0 / n + 1e-3
@@ -110,8 +113,18 @@ def test_attempt_uniforms_are_uniform_with_independent_halves(fn):
     assert abs(c) < 5 / np.sqrt(n)
 
 
-def test_pt_word_counter_layout():
+def test_pt_init_word_counter_layout():
     seed = 77
-    for (rho, k, m) in [(0, 0, 0), (5, 9, 3), (31, 551, 99999)]:
-        out = O.philox4x32([k, rho >> 2, m, O.STREAM_PT << 24], [77, 0])
-        assert O.pt_word(seed, O.STREAM_PT, rho, k, m) == int(out[rho & 3])
+    for (rho, k) in [(0, 0), (5, 9), (31, 551)]:
+        out = O.philox4x32([k, rho >> 2, 0, O.STREAM_PT_INIT << 24], [77, 0])
+        assert O.pt_word(seed, O.STREAM_PT_INIT, rho, k, 0) == int(out[rho & 3])
+
+
+def test_pt_uniform_counter_layout():
+    seed = 77
+    for (rho, k, m) in [(0, 0, 0), (5, 9, 3), (31, 551, 99999), (63, 7, 12), (12, 3, 5)]:
+        hi = O.philox4x32([k, rho >> 3, m, O.STREAM_PT << 24], [77, 0])
+        lo = O.philox4x32([k, rho >> 3, m, O.STREAM_PT_LO << 24], [77, 0])
+        sh = 16 * ((rho >> 2) & 1)
+        want = (((int(hi[rho & 3]) >> sh) & 0xFFFF) << 16) | ((int(lo[rho & 3]) >> sh) & 0xFFFF)
+        assert O.pt_uniform(seed, rho, k, m) == want

@@ -137,7 +137,7 @@ def test_pt_run_replay(kind, N, R, sweeps, sps):
                         continue
                     a = int(s[rho, k]) * emb.local_field(s[rho], k)
                     T = int(mt[perm.index(rho), a + F])
-                    u = O.pt_word(seed, O.STREAM_PT, rho, k, m)
+                    u = O.pt_uniform(seed, rho, k, m)
                     if T == O.ALWAYS or u < T:
                         s[rho, k] = -s[rho, k]
                         Er[rho] -= 2 * a
