@@ -15,9 +15,9 @@ struct pt_handle {
   int32_t R = 0, F = 0, Dmax = 0, sweeps = 0, sps = 1;
   uint64_t seed = 0;
   std::vector<double> betas;
-  std::vector<uint32_t> mtab, stab;
+  std::vector<uint32_t> mtab, stab, spack;
   Arena arena;
-  size_t off_rec = 0, off_devof = 0, off_hfield = 0, off_tw = 0, off_ts = 0, off_mtab = 0, off_stab = 0,
+  size_t off_rec = 0, off_devof = 0, off_hfield = 0, off_tw = 0, off_ts = 0, off_mtab = 0, off_stab = 0, off_spack = 0,
          off_spins = 0, off_energy = 0, off_repat = 0, off_acc = 0, off_pd = 0;
   bool ran = false;
   bool poisoned = false;
@@ -31,6 +31,8 @@ struct pt_handle {
     P.term_s = arena.at<uint32_t>(off_ts);
     P.mtab = arena.at<uint32_t>(off_mtab);
     P.stab = arena.at<uint32_t>(off_stab);
+    P.spack = arena.at<uint32_t>(off_spack);
+    P.spack_words = static_cast<int32_t>(spack.size());
     P.dev_of = arena.at<uint16_t>(off_devof);
     P.spins = arena.at<int8_t>(off_spins);
     P.energy = arena.at<int32_t>(off_energy);
@@ -56,24 +58,37 @@ namespace {
 struct PTShape {
   int waves = 4;
   int rec_cap = 0, lat_cap = 0, mtab_cap = 0;
-  size_t lds() const { return (static_cast<size_t>(rec_cap) + 2ull * lat_cap + mtab_cap + 256) * 4; }
+  int spack_cap = 0;   // packed swap table staged in LDS (0: read from device memory)
+  size_t lds() const {
+    return (static_cast<size_t>(rec_cap) + 2ull * lat_cap + mtab_cap + 5 * 64 + spack_cap) * 4;
+  }
 };
 
 PTShape pt_shape(const std::vector<const pt_handle *> &hs) {
   PTShape s;
-  int maxn = 0;
+  int max_items = 0;
   for (const pt_handle *h : hs) {
     s.rec_cap = std::max(s.rec_cap, h->emb.n * h->lay.rec_words);
     s.lat_cap = std::max(s.lat_cap, h->emb.n + 1);
     s.mtab_cap = std::max(s.mtab_cap, h->R * (2 * h->F + 1));
-    maxn = std::max(maxn, h->emb.n);
+    // items of a colour class: its sites x the replica bytes (rounded up to a power of two)
+    int rg = 1;
+    while (rg * 8 < h->R) rg <<= 1;
+    for (int c = 0; c < 4; ++c) max_items = std::max(max_items, (h->lay.cls[c + 1] - h->lay.cls[c]) * rg);
   }
   s.rec_cap = (s.rec_cap + 3) & ~3;
   s.lat_cap = (s.lat_cap + 1) & ~1;
   s.mtab_cap = (s.mtab_cap + 3) & ~3;
-  // one workgroup owns a ladder: use many waves so that LDS and Philox latency is hidden
+  // the packed swap tables go to LDS when the largest one fits beside the rest
+  int spack = 0;
+  for (const pt_handle *h : hs) spack = std::max(spack, static_cast<int>(h->spack.size()));
+  s.spack_cap = (spack + 3) & ~3;
+  if (s.lds() > kMaxLds) s.spack_cap = 0;
+  // one workgroup owns a ladder: enough waves that the largest colour class is one
+  // pass, at most kPTMaxWaves (the kernel's launch bound; larger classes loop)
   const char *env = std::getenv("SQA_PT_WAVES");
-  s.waves = env ? std::max(1, std::min(16, std::atoi(env))) : (maxn > 300 ? 12 : 8);
+  s.waves = env ? std::max(1, std::min(kPTMaxWaves, std::atoi(env)))
+                : std::max(2, std::min(kPTMaxWaves, (max_items + 63) / 64));
   return s;
 }
 
@@ -96,7 +111,7 @@ sqa_status pt_launch(const std::vector<pt_handle *> &hs, hipStream_t stream) {
   e = hipMemcpy(dev, pds.data(), sizeof(PTDev) * pds.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess)
     e = launch_pt(static_cast<const PTDev *>(dev), static_cast<int>(pds.size()), s.waves, s.rec_cap, s.lat_cap,
-                  s.mtab_cap, stream);
+                  s.mtab_cap, s.spack_cap, stream);
   if (e == hipSuccess)
     for (pt_handle *h : hs) {
       e = hipEventRecord(h->done, stream);
@@ -143,6 +158,7 @@ sqa_status pt_create(const sqa_problem *problem, const sqa_embedding *embedding,
   h->betas = pt_betas(p.beta_min, p.beta_max, p.temps);
   h->mtab = pt_metropolis_table(h->betas, h->F);
   h->stab = pt_swap_table(h->betas, h->Dmax);
+  h->spack = pt_swap_pack(h->stab, h->R, h->Dmax);
   const int n = h->emb.n;
   const size_t nt = h->emb.terms.size();
   Arena &A = h->arena;
@@ -153,6 +169,7 @@ sqa_status pt_create(const sqa_problem *problem, const sqa_embedding *embedding,
   h->off_ts = A.take(std::max<size_t>(nt, 1) * 8);
   h->off_mtab = A.take(h->mtab.size() * 4);
   h->off_stab = A.take(h->stab.size() * 4);
+  h->off_spack = A.take(h->spack.size() * 4);
   h->off_spins = A.take(static_cast<size_t>(h->R) * n);
   h->off_energy = A.take(static_cast<size_t>(h->R) * 4);
   h->off_repat = A.take(static_cast<size_t>(h->R) * 4);
@@ -173,7 +190,8 @@ sqa_status pt_create(const sqa_problem *problem, const sqa_embedding *embedding,
              {h->off_tw, h->lay.term_w.data(), nt * 4},
              {h->off_ts, h->lay.term_s.data(), nt * 8},
              {h->off_mtab, h->mtab.data(), h->mtab.size() * 4},
-             {h->off_stab, h->stab.data(), h->stab.size() * 4}};
+             {h->off_stab, h->stab.data(), h->stab.size() * 4},
+             {h->off_spack, h->spack.data(), h->spack.size() * 4}};
   for (const Up &u : ups) {
     if (!u.bytes) continue;
     e = hipMemcpy(A.at<char>(u.off), u.ptr, u.bytes, hipMemcpyHostToDevice);

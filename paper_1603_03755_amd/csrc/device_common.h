@@ -135,4 +135,13 @@ __device__ __forceinline__ uint32_t spread3(uint32_t bits) { return __umul24(bit
 // set for nibble bit 3, so it must not be an operand of a 24-bit multiply.
 __device__ __forceinline__ uint32_t spread8(uint32_t nib) { return __umul24(nib & 0xFu, 0x204081u) & 0x01010101u; }
 
+// Entry x of the byte -> spread table; each word holds bits 0, 6, 12, 18 at
+// most (the assumption lets the multiplies by it be 24-bit ones).
+__device__ __forceinline__ uint2 spread_of(const uint2 *stab, uint32_t x) {
+  const uint2 v = stab[x];
+  __builtin_assume(v.x <= 0x41041u);
+  __builtin_assume(v.y <= 0x41041u);
+  return v;
+}
+
 }  // namespace sqa

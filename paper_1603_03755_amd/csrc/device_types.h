@@ -71,6 +71,9 @@ constexpr uint32_t kStreamWolff = 7;
 constexpr int kSpreadWords = 512;
 constexpr uint32_t kStreamSQALo = 8;
 constexpr uint32_t kStreamWolffLo = 9;
+constexpr uint32_t kStreamPTLo = 10;
+// Waves per PT workgroup at most (the PT kernel's launch bound is 64 x this).
+constexpr int kPTMaxWaves = 10;
 
 // SQA update move of a handle.
 constexpr int kMoveMetropolis = 0;   // single-site Metropolis on the space-time lattice
@@ -121,12 +124,13 @@ struct PTDev {
   const uint32_t *term_s;
   const uint32_t *mtab;     // [R][2F+1]  Metropolis thresholds by slot
   const uint32_t *stab;     // [R-1][Dmax+1] swap thresholds
+  const uint32_t *spack;    // the same without trailing zeros: R offsets, then the rows
   const uint16_t *dev_of;
   int8_t *spins;            // [R][n] by replica, physical order
   int32_t *energy;          // [R] by replica
   int32_t *rep_at;          // [R] slot -> replica
   uint64_t *swap_acc;       // [R-1]
-  int32_t kind, n, n_terms, R, F, Dmax, sweeps, sweeps_per_swap;
+  int32_t kind, n, n_terms, R, F, Dmax, sweeps, sweeps_per_swap, spack_words;
   uint32_t seed_lo, seed_hi;
   int32_t cls[5];
 };

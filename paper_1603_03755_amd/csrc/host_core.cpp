@@ -325,6 +325,20 @@ std::vector<uint32_t> pt_swap_table(const std::vector<double> &betas, int32_t Dm
   return T;
 }
 
+std::vector<uint32_t> pt_swap_pack(const std::vector<uint32_t> &stab, int32_t R, int32_t Dmax) {
+  const int pairs = R > 1 ? R - 1 : 0;
+  std::vector<uint32_t> out(static_cast<size_t>(std::max(R, 1)), 0u);
+  for (int r = 0; r < pairs; ++r) {
+    const uint32_t *row = stab.data() + static_cast<size_t>(r) * (Dmax + 1);
+    int len = Dmax + 1;
+    while (len > 0 && row[len - 1] == 0u) --len;
+    out[r] = static_cast<uint32_t>(out.size());
+    out.insert(out.end(), row, row + len);
+  }
+  out[std::max(pairs, 0)] = static_cast<uint32_t>(out.size());
+  return out;
+}
+
 // ---------------------------------------------------------- host Philox
 void host_philox4x32(const uint32_t ctr[4], uint32_t k0, uint32_t k1, uint32_t out[4]) {
   uint32_t x[4] = {ctr[0], ctr[1], ctr[2], ctr[3]};

@@ -68,6 +68,9 @@ std::vector<uint32_t> wolff_accept_table(double beta, int32_t L, const std::vect
 std::vector<double> pt_betas(double beta_min, double beta_max, int32_t R);
 std::vector<uint32_t> pt_metropolis_table(const std::vector<double> &betas, int32_t F);
 std::vector<uint32_t> pt_swap_table(const std::vector<double> &betas, int32_t Dmax);
+// Swap table without the trailing zeros of each pair's row: words 0..R-1 hold
+// the offsets (within the packed array) of rows 0..R-2 and the end, then the rows.
+std::vector<uint32_t> pt_swap_pack(const std::vector<uint32_t> &stab, int32_t R, int32_t Dmax);
 
 // ---------------------------------------------------------- host Philox
 void host_philox4x32(const uint32_t ctr[4], uint32_t k0, uint32_t k1, uint32_t out[4]);
@@ -109,7 +112,7 @@ hipError_t launch_ground(const uint32_t *planes, const int32_t *cj, const int32_
                          unsigned long long *best, hipStream_t s);
 hipError_t launch_logical_energy(const int8_t *logical, int R, int N, const int32_t *J, const int32_t *h,
                                  int32_t *energy, hipStream_t s);
-hipError_t launch_pt(const PTDev *pts, int count, int waves, int rec_cap, int lat_cap, int mtab_cap,
+hipError_t launch_pt(const PTDev *pts, int count, int waves, int rec_cap, int lat_cap, int mtab_cap, int spack_cap,
                      hipStream_t stream);
 hipError_t set_pt_lds_limit(size_t bytes);
 

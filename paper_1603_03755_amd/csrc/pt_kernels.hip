@@ -9,154 +9,344 @@ namespace sqa {
 // ------------------------------------------------------ parallel tempering
 // Appendix B: `R` replicas of the classical embedded Hamiltonian, replica rho
 // at the inverse temperature of its slot.  One workgroup owns a whole ladder.
-// LDS word of site d: bit rho = 1 <=> replica rho has spin -1 there.  An item
-// is (site of colour c, replica group a = 4 replicas) and uses one Philox call
-// (counter (site, a, sweep, PT<<24)).  Flips are applied with an LDS atomic
-// XOR, so items of neighbouring replica groups never overwrite each other.
-// Energies are kept incrementally (a flip with a = s*f changes E by -2a).
+// LDS word of site d: bit rho = 1 <=> replica rho has spin -1 there.
+//
+// An item is (site of colour c, replica byte a = replicas 8a..8a+7); a thread
+// keeps one byte a for the whole run (a = thread index mod RG, RG = the number
+// of bytes rounded up to a power of two), so the table rows of its eight
+// replicas' slots stay in registers between swap phases.  Random numbers:
+// replica 8a+w takes the 16-bit half w >> 2 of word w & 3 of the PT call with
+// counter (site, a, sweep, PT<<24) and is accepted when that half is below the
+// top half of its threshold, rejected when above; only on a tie does the item
+// draw the PT_LO call and decide on the full 32 bits.  The item owns its byte,
+// so flips go back with one byte store.  Energies: per-thread deltas of the
+// eight replicas (a flip with a = s*f changes E by -2a), summed at a swap phase
+// over the threads of a byte (DPP row sums, one LDS atomic per 16-lane row and
+// replica).  The swap phase runs on wave 0: its lane r draws the swap word
+// of pair r during the sweep; the even pairs, then the odd pairs, are decided
+// with wave-level ordering only.
+//
+// SWAR: the weighted disagreement sums s_w of the eight replicas are formed in
+// two words of four 6-bit fields (needs F <= 63); otherwise per replica.
+// Sum of v over the lanes l, l - g, l - 2g, ... of a 16-lane row (G = g a power
+// of two below 16): DPP row shifts, so lane l with l % 16 >= 16 - G ends with
+// the row's total for its residue l % G.
+template <int G>
+__device__ __forceinline__ int32_t row_sum_stride(int32_t v) {
+  if constexpr (G < 2) v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, true);   // row_shr:1
+  if constexpr (G < 4) v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, true);   // row_shr:2
+  if constexpr (G < 8) v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, true);   // row_shr:4
+  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, true);                        // row_shr:8
+  return v;
+}
+
+// Adds the eight per-thread energy deltas of replica byte a into E: row sums by
+// DPP, then one LDS atomic per row, residue and replica.
+template <int G>
+__device__ __forceinline__ void flush_deltas(int32_t *dE, int32_t *E, int a, int nvalid, int lane) {
+#pragma unroll
+  for (int w = 0; w < 8; ++w) dE[w] = row_sum_stride<G>(dE[w]);
+  if ((lane & 15) >= 16 - G && nvalid > 0)
+#pragma unroll
+    for (int w = 0; w < 8; ++w)
+      if (w < nvalid && dE[w] != 0) atomicAdd(&E[8 * a + w], dE[w]);
+#pragma unroll
+  for (int w = 0; w < 8; ++w) dE[w] = 0;
+}
+
+// Raw record words of one site (4 words ME, 10 LHZ, 6 ME on Chimera).
+template <int KIND> struct PTRec;
+template <> struct PTRec<kKindME> { uint4 a; };
+template <> struct PTRec<kKindLHZ> { uint4 a, b; uint2 c; };
+template <> struct PTRec<kKindMEC> { uint4 a; uint2 b; };
+
 template <int KIND>
-__device__ void pt_ladder(const PTDev &P, const uint32_t *rec, uint64_t *lat, const uint32_t *mtab, int32_t *E,
-                          int32_t *rep_at, int32_t *slot_of, uint32_t *acc) {
+__device__ __forceinline__ PTRec<KIND> load_pt_rec(const uint32_t *r) {
+  PTRec<KIND> x;
+  if constexpr (KIND == kKindME) {
+    x.a = *reinterpret_cast<const uint4 *>(r);
+  } else if constexpr (KIND == kKindMEC) {
+    x.a = *reinterpret_cast<const uint4 *>(r);
+    x.b = *reinterpret_cast<const uint2 *>(r + 4);
+  } else {
+    x.a = *reinterpret_cast<const uint4 *>(r);
+    x.b = *reinterpret_cast<const uint4 *>(r + 4);
+    x.c = *reinterpret_cast<const uint2 *>(r + 8);
+  }
+  return x;
+}
+
+// One item: site d (record x), replica byte a, sweep m.  row: the table row
+// offsets of the byte's eight replicas; dE: their energy deltas.
+template <int KIND, bool SWAR>
+__device__ __forceinline__ void pt_item(const PTDev &P, const PTRec<KIND> &x, int d, uint8_t *latb,
+                                        const uint32_t *mtab, int a, uint32_t vmask, const int32_t *row,
+                                        int32_t *dE, uint32_t m) {
+  using S = Site<KIND>;
+  const int F = P.F;
+  const uint16_t *mtab16 = reinterpret_cast<const uint16_t *>(mtab);
+  uint32_t site, wts, wts2 = 0, ah, neg;
+  uint32_t part[S::T * S::P];
+  if constexpr (KIND == kKindME) {
+    site = x.a.x & 0xFFFFu;
+    wts = x.a.y & 0xFFFFFFu;
+    ah = x.a.y >> 24;
+    neg = x.a.z & 0xFFu;
+    part[0] = x.a.z >> 16; part[1] = x.a.w & 0xFFFFu; part[2] = x.a.w >> 16;
+  } else if constexpr (KIND == kKindMEC) {
+    site = x.a.x & 0xFFFFu;
+    wts = x.a.y;
+    wts2 = x.a.z & 0xFFFFu;
+    ah = (x.a.z >> 16) & 0xFFu;
+    neg = x.a.z >> 24;
+    part[0] = x.a.w & 0xFFFFu; part[1] = x.a.w >> 16;
+    part[2] = x.b.x & 0xFFFFu; part[3] = x.b.x >> 16;
+    part[4] = x.b.y & 0xFFFFu; part[5] = x.b.y >> 16;
+  } else {
+    site = x.a.x & 0xFFFFu;
+    wts = x.a.y;
+    ah = x.a.z & 0xFFu;
+    neg = (x.a.z >> 8) & 0xFFu;
+    const uint32_t pw[6] = {x.b.x, x.b.y, x.b.z, x.b.w, x.c.x, x.c.y};
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      part[2 * q] = pw[q] & 0xFFFFu;
+      part[2 * q + 1] = pw[q] >> 16;
+    }
+  }
+  // own and partner bytes (LDS reads), the first Philox rounds while they are in flight
+  const uint32_t own = latb[8 * d + a];
+  uint32_t pbyte[S::T * S::P];
+#pragma unroll
+  for (int i = 0; i < S::T * S::P; ++i) pbyte[i] = latb[part[i] + a];
+  PhiloxState ps = philox_start(site, static_cast<uint32_t>(a), m, kStreamPT << 24, P.seed_lo, P.seed_hi);
+  __builtin_amdgcn_sched_barrier(0);
+  philox_rounds<5>(ps);
+  philox_pin(ps);
+  __builtin_amdgcn_sched_barrier(0);
+
+  // F_site = |h| + sum of the term weights
+  uint32_t fs = __builtin_amdgcn_sad_u8(wts, 0u, ah);
+  if constexpr (KIND == kKindMEC) fs = __builtin_amdgcn_sad_u8(wts2, 0u, fs);
+  const uint32_t ox = (own ^ (0u - ((neg >> S::HB) & 1u))) & 0xFFu;
+  uint32_t sw[8];                                  // weighted disagreement sum of replica 8a+w
+  if constexpr (SWAR) {
+    // four 6-bit fields per word; the spreads are computed (no table round trip:
+    // this kernel is bound by latency, not by issue)
+    uint32_t acc_lo = __umul24(spread6(ox & 0xFu), ah), acc_hi = __umul24(spread6(ox >> 4), ah);
+#pragma unroll
+    for (int t = 0; t < S::T; ++t) {
+      uint32_t prod = own;
+#pragma unroll
+      for (int q = 0; q < S::P; ++q) prod ^= pbyte[S::P * t + q];
+      const uint32_t xt = (prod ^ (0u - ((neg >> t) & 1u))) & 0xFFu;
+      const uint32_t wt = term_weight(wts, wts2, t);
+      acc_lo += __umul24(spread6(xt & 0xFu), wt);
+      acc_hi += __umul24(spread6(xt >> 4), wt);
+    }
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      sw[w] = __builtin_amdgcn_ubfe(acc_lo, 6 * w, 6);
+      sw[w + 4] = __builtin_amdgcn_ubfe(acc_hi, 6 * w, 6);
+    }
+  } else {
+    uint32_t X[S::T];
+#pragma unroll
+    for (int t = 0; t < S::T; ++t) {
+      uint32_t prod = own;
+#pragma unroll
+      for (int q = 0; q < S::P; ++q) prod ^= pbyte[S::P * t + q];
+      X[t] = prod ^ (0u - ((neg >> t) & 1u));
+    }
+#pragma unroll
+    for (int w = 0; w < 8; ++w) {
+      uint32_t v = ah * bit_at(ox, w);
+#pragma unroll
+      for (int t = 0; t < S::T; ++t) v += term_weight(wts, wts2, t) * bit_at(X[t], w);
+      sw[w] = v;
+    }
+  }
+  // thresholds: T = mtab[slot row + (F_site - 2 s) + F]; top halves first
+  int32_t ix[8];
+  uint32_t th[8];
+#pragma unroll
+  for (int w = 0; w < 8; ++w) {
+    ix[w] = row[w] + static_cast<int32_t>(fs) + F - 2 * static_cast<int32_t>(sw[w]);
+    th[w] = mtab16[2 * ix[w] + 1];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  philox_rounds<5>(ps);
+  __builtin_amdgcn_sched_barrier(0);
+  const Words4 u = philox_words(ps);
+  uint32_t flip = 0;
+  bool tie = false;
+#pragma unroll
+  for (int w = 0; w < 8; ++w) {
+    const uint32_t hi = (w < 4) ? (u.v[w] & 0xFFFFu) : (u.v[w - 4] >> 16);
+    if (hi < th[w]) flip |= 1u << w;
+    tie |= (hi == th[w]);
+  }
+  if (tie) {     // some half equals its threshold's top half: decide all eight on 32 bits
+    const Words4 v = philox4x32_10(site, static_cast<uint32_t>(a), m, kStreamPTLo << 24, P.seed_lo, P.seed_hi);
+    flip = 0;
+#pragma unroll
+    for (int w = 0; w < 8; ++w) {
+      const uint32_t uu = (w < 4) ? ((u.v[w] << 16) | (v.v[w] & 0xFFFFu))
+                                  : ((u.v[w - 4] & 0xFFFF0000u) | (v.v[w - 4] >> 16));
+      if (min(uu, 0xFFFFFFFEu) < mtab[ix[w]]) flip |= 1u << w;
+    }
+  }
+  flip &= vmask;
+  latb[8 * d + a] = static_cast<uint8_t>(own ^ flip);
+#pragma unroll
+  for (int w = 0; w < 8; ++w)
+    if ((flip >> w) & 1u) dE[w] += 4 * static_cast<int32_t>(sw[w]) - 2 * static_cast<int32_t>(fs);
+}
+
+template <int KIND, bool SWAR>
+__device__ __forceinline__ void pt_ladder(const PTDev &P, const uint32_t *rec, uint64_t *lat, const uint32_t *mtab,
+                                          int32_t *E, int32_t *rep_at, int32_t *slot_of, uint32_t *acc,
+                                          uint32_t *swapw, const uint32_t *spk) {
   using S = Site<KIND>;
   const int R = P.R, F = P.F;
   const int width = 2 * F + 1;
   const int tid = threadIdx.x, nth = blockDim.x;
-  int RG = 1;
-  while (RG * 4 < R) RG <<= 1;      // replica groups, padded to a power of two (divides nth)
-  const int a = tid & (RG - 1);     // this thread's replica group never changes
-  const bool group_live = 4 * a < R;
-  uint32_t *lat32 = reinterpret_cast<uint32_t *>(lat);
-  const uint8_t *latb = reinterpret_cast<const uint8_t *>(lat);
-  int32_t dE[4] = {0, 0, 0, 0};
+  const int lane = tid & 63, wave = tid >> 6;
+  int RG = 1, lgRG = 0;
+  while (RG * 8 < R) {
+    RG <<= 1;
+    ++lgRG;
+  }
+  const int a = tid & (RG - 1);                    // this thread's replica byte never changes
+  const bool group_live = 8 * a < R;
+  const int nvalid = group_live ? min(8, R - 8 * a) : 0;
+  const uint32_t vmask = (1u << nvalid) - 1u;
+  uint8_t *latb = reinterpret_cast<uint8_t *>(lat);
+  int32_t dE[8];
+  int32_t row[8];                                  // table row offsets of the byte's replicas
+#pragma unroll
+  for (int w = 0; w < 8; ++w) {
+    dE[w] = 0;
+    row[w] = (w < nvalid) ? slot_of[8 * a + w] * width : 0;
+  }
+  // The record of a thread's first item in the next colour class is read into
+  // registers before the current class is processed, so its LDS latency overlaps
+  // the current item and the class barrier (records are read-only).
+  int cls[5];
+#pragma unroll
+  for (int c = 0; c < 5; ++c) cls[c] = P.cls[c];
+  bool has_first[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) has_first[c] = group_live && tid < ((cls[c + 1] - cls[c]) << lgRG);
+  PTRec<KIND> nxt;
+  if (has_first[0]) nxt = load_pt_rec<KIND>(rec + (cls[0] + (tid >> lgRG)) * S::RW);
+  // energy deltas into E (RG is a power of two up to 8, so it divides the 16-lane rows)
+  auto flush = [&](int32_t *d) {
+    if (RG == 1) flush_deltas<1>(d, E, a, nvalid, lane);
+    else if (RG == 2) flush_deltas<2>(d, E, a, nvalid, lane);
+    else if (RG == 4) flush_deltas<4>(d, E, a, nvalid, lane);
+    else flush_deltas<8>(d, E, a, nvalid, lane);
+  };
+  // Swap words (word 0 of the SWAP call (pair r, 0, phase q)) live in LDS: the
+  // first phase's are drawn here, each later phase's by the drawing wave while
+  // wave 0 decides the current phase.
+  const int draw_wave = (nth > 64) ? 1 : 0;
+  if (wave == draw_wave && lane + 1 < R)
+    swapw[lane] = philox4x32_10(static_cast<uint32_t>(lane), 0u, 0u, kStreamSwap << 24, P.seed_lo, P.seed_hi).v[0];
   uint32_t phase = 0;
   for (int m = 0; m < P.sweeps; ++m) {
+    const bool swap_now = (m + 1) % P.sweeps_per_swap == 0;
+    const uint32_t mm = static_cast<uint32_t>(m);
+#pragma unroll
     for (int c = 0; c < 4; ++c) {
-      const int lo = P.cls[c];
-      const int nc = P.cls[c + 1] - lo;
-      const int cnt = nc * RG;
-      for (int it = tid; it < cnt; it += nth) {
-        if (!group_live) continue;
-        const int d = lo + it / RG;
-        const uint32_t *r = rec + d * S::RW;
-        uint32_t site, base, aw[S::T], ah, neg;
-        uint32_t part[S::T * S::P];
-        if constexpr (KIND == kKindMEC) {
-          uint32_t w1, w2;
-          load_rec_mec(r, site, base, w1, w2, ah, neg, part);
-#pragma unroll
-          for (int t = 0; t < S::T; ++t) aw[t] = term_weight(w1, w2, t);
-        } else if constexpr (KIND == kKindME) {
-          const uint4 r0 = *reinterpret_cast<const uint4 *>(r);
-          site = r0.x & 0xFFFFu; base = r0.x >> 16;
-          aw[0] = r0.y & 0xFFu; aw[1] = (r0.y >> 8) & 0xFFu; aw[2] = (r0.y >> 16) & 0xFFu;
-          ah = r0.y >> 24;
-          neg = r0.z & 0xFFu;
-          part[0] = r0.z >> 16; part[1] = r0.w & 0xFFFFu; part[2] = r0.w >> 16;
-        } else {
-          const uint4 r0 = *reinterpret_cast<const uint4 *>(r);
-          const uint4 r1 = *reinterpret_cast<const uint4 *>(r + 4);
-          const uint2 r2 = *reinterpret_cast<const uint2 *>(r + 8);
-          site = r0.x & 0xFFFFu; base = r0.x >> 16;
-          aw[0] = r0.y & 0xFFu; aw[1] = (r0.y >> 8) & 0xFFu; aw[2] = (r0.y >> 16) & 0xFFu; aw[3] = r0.y >> 24;
-          ah = r0.z & 0xFFu;
-          neg = (r0.z >> 8) & 0xFFu;
-          const uint32_t pw[6] = {r1.x, r1.y, r1.z, r1.w, r2.x, r2.y};
-#pragma unroll
-          for (int q = 0; q < 6; ++q) {
-            part[2 * q] = pw[q] & 0xFFFFu;
-            part[2 * q + 1] = pw[q] >> 16;
-          }
-        }
-        const int pbase = static_cast<int>((base - 2u) / 3u);   // F_site + F
-        const int fsite = pbase - F;
-        const int byte = a >> 1, nsh = (a & 1) * 4;
-        const uint32_t own = (latb[d * 8 + byte] >> nsh) & 0xFu;
-        uint32_t X[S::T];
-#pragma unroll
-        for (int t = 0; t < S::T; ++t) {
-          uint32_t prod = 0;
-#pragma unroll
-          for (int q = 0; q < S::P; ++q) prod ^= latb[part[S::P * t + q] + byte];
-          X[t] = own ^ (prod >> nsh) ^ (0u - ((neg >> t) & 1u));
-        }
-        const uint32_t O = own ^ (0u - ((neg >> S::HB) & 1u));
-        const Words4 u = philox4x32_10(site, static_cast<uint32_t>(a), static_cast<uint32_t>(m), kStreamPT << 24,
-                                       P.seed_lo, P.seed_hi);
-        uint32_t flip = 0;
-#pragma unroll
-        for (int w = 0; w < 4; ++w) {
-          const int rho = 4 * a + w;
-          if (rho >= R) break;
-          uint32_t s = ah * bit_at(O, w);
-#pragma unroll
-          for (int t = 0; t < S::T; ++t) s += aw[t] * bit_at(X[t], w);
-          const int idx = slot_of[rho] * width + pbase - 2 * static_cast<int>(s);
-          const uint32_t T = mtab[idx];
-          if (min(u.v[w], 0xFFFFFFFEu) < T) {
-            flip |= 1u << w;
-            dE[w] += 4 * static_cast<int32_t>(s) - 2 * fsite;
-          }
-        }
-        if (flip) atomicXor(&lat32[2 * d + (a >> 3)], flip << (4 * (a & 7)));
+      const int lo = cls[c];
+      const int cnt = (cls[c + 1] - lo) << lgRG;
+      const PTRec<KIND> cur = nxt;
+      const int cn = (c + 1) & 3;
+      if (has_first[cn]) nxt = load_pt_rec<KIND>(rec + (cls[cn] + (tid >> lgRG)) * S::RW);
+      if (has_first[c]) pt_item<KIND, SWAR>(P, cur, lo + (tid >> lgRG), latb, mtab, a, vmask, row, dE, mm);
+      for (int it = tid + nth; group_live && it < cnt; it += nth) {
+        const int d = lo + (it >> lgRG);
+        pt_item<KIND, SWAR>(P, load_pt_rec<KIND>(rec + d * S::RW), d, latb, mtab, a, vmask, row, dE, mm);
       }
       __syncthreads();
     }
-    if ((m + 1) % P.sweeps_per_swap == 0) {
-      if (group_live)
-        for (int w = 0; w < 4; ++w)
-          if (dE[w] != 0 && 4 * a + w < R) {
-            atomicAdd(&E[4 * a + w], dE[w]);
-            dE[w] = 0;
-          }
+    if (swap_now) {
+      flush(dE);
       __syncthreads();
-      for (int q = 0; q < 2; ++q) {
-        const int r = 2 * tid + q;
-        if (r + 1 < R) {
-          const int lo_rep = rep_at[r], hi_rep = rep_at[r + 1];
-          const int D = E[hi_rep] - E[lo_rep];
-          bool ok = D <= 0;
-          if (!ok) {
-            const Words4 u = philox4x32_10(static_cast<uint32_t>(r), 0u, phase, kStreamSwap << 24, P.seed_lo,
-                                           P.seed_hi);
-            const uint32_t T = P.stab[static_cast<size_t>(r) * (P.Dmax + 1) + min(D, P.Dmax)];
-            ok = min(u.v[0], 0xFFFFFFFEu) < T;
+      if (wave == 0) {
+        for (int q = 0; q < 2; ++q) {
+          const int rr = 2 * lane + q;
+          if (rr + 1 < R) {
+            const int lo_rep = rep_at[rr], hi_rep = rep_at[rr + 1];
+            const int D = E[hi_rep] - E[lo_rep];
+            bool ok = D <= 0;
+            if (!ok) {
+              const int Dc = min(D, P.Dmax);
+              uint32_t T;
+              if (spk) {      // packed row in LDS: entries past its end are 0
+                const uint32_t o0 = spk[rr], o1 = spk[rr + 1];
+                T = (static_cast<uint32_t>(Dc) < o1 - o0) ? spk[o0 + Dc] : 0u;
+              } else {
+                T = P.stab[static_cast<size_t>(rr) * (P.Dmax + 1) + Dc];
+              }
+              ok = min(swapw[rr], 0xFFFFFFFEu) < T;
+            }
+            if (ok) {
+              rep_at[rr] = hi_rep;
+              rep_at[rr + 1] = lo_rep;
+              slot_of[hi_rep] = rr;
+              slot_of[lo_rep] = rr + 1;
+              acc[rr] += 1;
+            }
           }
-          if (ok) {
-            rep_at[r] = hi_rep;
-            rep_at[r + 1] = lo_rep;
-            slot_of[hi_rep] = r;
-            slot_of[lo_rep] = r + 1;
-            acc[r] += 1;
-          }
+          wave_sync();
         }
-        __syncthreads();
       }
+      // the words of the next swap phase, drawn while wave 0 decides this one
+      if (wave == draw_wave && draw_wave != 0 && lane + 1 < R)
+        swapw[64 + lane] = philox4x32_10(static_cast<uint32_t>(lane), 0u, phase + 1, kStreamSwap << 24, P.seed_lo,
+                                         P.seed_hi).v[0];
+      __syncthreads();
+      if (wave == draw_wave && lane + 1 < R) {
+        if (draw_wave == 0)
+          swapw[lane] = philox4x32_10(static_cast<uint32_t>(lane), 0u, phase + 1, kStreamSwap << 24, P.seed_lo,
+                                      P.seed_hi).v[0];
+        else
+          swapw[lane] = swapw[64 + lane];
+      }
+#pragma unroll
+      for (int w = 0; w < 8; ++w) row[w] = (w < nvalid) ? slot_of[8 * a + w] * width : 0;
       ++phase;
     }
   }
-  if (group_live)
-    for (int w = 0; w < 4; ++w)
-      if (dE[w] != 0 && 4 * a + w < R) atomicAdd(&E[4 * a + w], dE[w]);
+  flush(dE);                                 // deltas of the sweeps after the last swap phase
   __syncthreads();
 }
 
-// Dynamic LDS: [rec_cap words][lat_cap u64][mtab_cap words][E, rep_at, slot_of, acc: 64 each].
-__global__ __launch_bounds__(1024) void pt_kernel(const PTDev *__restrict__ pts, int rec_cap, int lat_cap,
-                                                 int mtab_cap) {
+// Dynamic LDS: [rec_cap words][lat_cap u64][mtab_cap words][E, rep_at, slot_of, acc: 64 each]
+// [swap words: 2 x 64][spack_cap words: the packed swap table when it is staged].
+__global__ __launch_bounds__(64 * kPTMaxWaves) void pt_kernel(const PTDev *__restrict__ pts, int rec_cap, int lat_cap,
+                                                              int mtab_cap, int spack_cap) {
   extern __shared__ __align__(16) uint32_t smem[];
-  const PTDev P = pts[blockIdx.x];
+  const PTDev &P = pts[blockIdx.x];       // read in place: uniform fields become scalar loads
   uint32_t *rec = smem;
-  uint64_t *lat = reinterpret_cast<uint64_t *>(smem + rec_cap);
-  uint32_t *mtab = smem + rec_cap + 2 * lat_cap;
+  uint64_t *lat = reinterpret_cast<uint64_t *>(rec + rec_cap);
+  uint32_t *mtab = rec + rec_cap + 2 * lat_cap;
   int32_t *E = reinterpret_cast<int32_t *>(mtab + mtab_cap);
   int32_t *rep_at = E + 64;
   int32_t *slot_of = rep_at + 64;
   uint32_t *acc = reinterpret_cast<uint32_t *>(slot_of + 64);
+  uint32_t *swapw = acc + 64;
+  uint32_t *spk = swapw + 128;
   const int tid = threadIdx.x, nth = blockDim.x;
   const int rw = rec_words_of(P.kind);
   for (int i = tid; i < P.n * rw; i += nth) rec[i] = P.rec[i];
   const int width = 2 * P.F + 1;
   for (int i = tid; i < P.R * width; i += nth) mtab[i] = P.mtab[i];
+  const bool staged = spack_cap > 0 && P.spack_words <= spack_cap;
+  if (staged)
+    for (int i = tid; i < P.spack_words; i += nth) spk[i] = P.spack[i];
   for (int r = tid; r < 64; r += nth) {
     rep_at[r] = r;
     slot_of[r] = r;
@@ -164,11 +354,11 @@ __global__ __launch_bounds__(1024) void pt_kernel(const PTDev *__restrict__ pts,
     E[r] = 0;
   }
   // initial spins from the PT_INIT stream: replica rho, site k -> word rho&3 of (k, rho>>2, 0, PT_INIT<<24)
-  const int RG = (P.R + 3) >> 2;
+  const int RG4 = (P.R + 3) >> 2;
   for (int d = tid; d < P.n; d += nth) {
     const uint32_t site = P.rec[d * rw] & 0xFFFFu;
     uint64_t w = 0;
-    for (int a = 0; a < RG; ++a) {
+    for (int a = 0; a < RG4; ++a) {
       const Words4 u = philox4x32_10(site, static_cast<uint32_t>(a), 0u, kStreamPTInit << 24, P.seed_lo, P.seed_hi);
       for (int k = 0; k < 4; ++k)
         if (4 * a + k < P.R) w |= static_cast<uint64_t>(u.v[k] >> 31) << (4 * a + k);
@@ -189,9 +379,17 @@ __global__ __launch_bounds__(1024) void pt_kernel(const PTDev *__restrict__ pts,
     E[tid] = e;
   }
   __syncthreads();
-  if (P.kind == kKindME) pt_ladder<kKindME>(P, rec, lat, mtab, E, rep_at, slot_of, acc);
-  else if (P.kind == kKindLHZ) pt_ladder<kKindLHZ>(P, rec, lat, mtab, E, rep_at, slot_of, acc);
-  else pt_ladder<kKindMEC>(P, rec, lat, mtab, E, rep_at, slot_of, acc);
+  const bool swar = P.F <= kMidF;
+  if (P.kind == kKindME) {
+    if (swar) pt_ladder<kKindME, true>(P, rec, lat, mtab, E, rep_at, slot_of, acc, swapw, staged ? spk : nullptr);
+    else pt_ladder<kKindME, false>(P, rec, lat, mtab, E, rep_at, slot_of, acc, swapw, staged ? spk : nullptr);
+  } else if (P.kind == kKindLHZ) {
+    if (swar) pt_ladder<kKindLHZ, true>(P, rec, lat, mtab, E, rep_at, slot_of, acc, swapw, staged ? spk : nullptr);
+    else pt_ladder<kKindLHZ, false>(P, rec, lat, mtab, E, rep_at, slot_of, acc, swapw, staged ? spk : nullptr);
+  } else {
+    if (swar) pt_ladder<kKindMEC, true>(P, rec, lat, mtab, E, rep_at, slot_of, acc, swapw, staged ? spk : nullptr);
+    else pt_ladder<kKindMEC, false>(P, rec, lat, mtab, E, rep_at, slot_of, acc, swapw, staged ? spk : nullptr);
+  }
   // results: spins by replica in physical order, energies by replica, slot map, swap counts
   for (size_t i = tid; i < static_cast<size_t>(P.R) * P.n; i += nth) {
     const int rho = static_cast<int>(i / P.n), k = static_cast<int>(i % P.n);
@@ -202,14 +400,16 @@ __global__ __launch_bounds__(1024) void pt_kernel(const PTDev *__restrict__ pts,
     P.rep_at[tid] = rep_at[tid];
     if (tid + 1 < P.R) P.swap_acc[tid] = acc[tid];
   }
+
 }
 
 // ----------------------------------------------------------- host launchers
-hipError_t launch_pt(const PTDev *pts, int count, int waves, int rec_cap, int lat_cap, int mtab_cap,
+hipError_t launch_pt(const PTDev *pts, int count, int waves, int rec_cap, int lat_cap, int mtab_cap, int spack_cap,
                      hipStream_t stream) {
-  const size_t lds = (static_cast<size_t>(rec_cap) + 2ull * lat_cap + mtab_cap + 4 * 64) * 4;
+  const size_t lds = (static_cast<size_t>(rec_cap) + 2ull * lat_cap + mtab_cap + 5 * 64 + spack_cap) * 4;
   (void)hipGetLastError();
-  hipLaunchKernelGGL(pt_kernel, dim3(count), dim3(64 * waves), lds, stream, pts, rec_cap, lat_cap, mtab_cap);
+  hipLaunchKernelGGL(pt_kernel, dim3(count), dim3(64 * waves), lds, stream, pts, rec_cap, lat_cap, mtab_cap,
+                     spack_cap);
   return hipGetLastError();
 }
 

@@ -100,15 +100,6 @@ __device__ __forceinline__ void slice_energies(const HandleDev &H, const uint64_
   H.energy[static_cast<size_t>(rep) * H.L + tau] = E;
 }
 
-// Entry x of the byte -> spread table; each word holds bits 0, 6, 12, 18 at
-// most (the assumption lets the multiplies by it be 24-bit ones).
-__device__ __forceinline__ uint2 spread_of(const uint2 *stab, uint32_t x) {
-  const uint2 v = stab[x];
-  __builtin_assume(v.x <= 0x41041u);
-  __builtin_assume(v.y <= 0x41041u);
-  return v;
-}
-
 // ------------------------------------------------------------ SQA sweep
 // 64-lane item loop over one (slice parity p, colour c) class of one replica.
 // Item = (site of colour c, byte b of its parity-p half word): the eight slices
