@@ -86,8 +86,9 @@ __device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
 
 // Minimum-weight decoding: for replica blockIdx.x, lanes take Gray chunks of
 // 2^c indices; best[r] receives max over candidates of the key
-// (O + K) << 32 | (0xFFFFFFFF - m): the highest score, then the smallest m.
-// best[] must start at 0.  Block: 256 threads.
+// (O + K) << 32 | (0xFFFFFFFF - m): the highest score, then the smallest m
+// (one atomic per block after a wave and a block reduction).  best[] must
+// start at 0.  Block: 256 threads.
 __global__ __launch_bounds__(256) void lhz_mwd_kernel(const uint32_t *__restrict__ rows_all, int N, int c,
                                                       unsigned long long *__restrict__ best) {
   __shared__ uint32_t rows[32];
@@ -117,7 +118,14 @@ __global__ __launch_bounds__(256) void lhz_mwd_kernel(const uint32_t *__restrict
     }
   }
   key = wave_max_u64(key);
-  if ((threadIdx.x & 63) == 0) atomicMax(best + r, static_cast<unsigned long long>(key));
+  __shared__ uint64_t wbest[4];
+  if ((threadIdx.x & 63) == 0) wbest[threadIdx.x >> 6] = key;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t k = wbest[0];
+    for (int w = 1; w < static_cast<int>(blockDim.x >> 6); ++w) k = wbest[w] > k ? wbest[w] : k;
+    atomicMax(best + r, static_cast<unsigned long long>(k));
+  }
 }
 
 // Maximum-likelihood decoding: with O_max from the MWD keys, every candidate's
@@ -360,6 +368,13 @@ static unsigned blocks_for(size_t n, unsigned b) { return static_cast<unsigned>(
 
 // Gray chunk exponent: 2^c candidates per lane, c <= N - 1.
 static int chunk_exponent(int N) { return (N - 1) < 12 ? (N - 1) : 12; }
+// MWD walks chunks of 2^6 candidates per lane (short serial walks, many lanes
+// even for small N), larger from N = 31 on so that the 2^(N-1-c) / 256 blocks
+// per replica stay within the grid's y limit (c >= N - 24).
+static int mwd_chunk_exponent(int N) {
+  const int c = (N - 24) > 6 ? (N - 24) : 6;
+  return (N - 1) < c ? (N - 1) : c;
+}
 
 hipError_t launch_lhz_rows(const int8_t *spins, int R, int L, int K, int N, int slice, uint32_t *rows,
                            hipStream_t s) {
@@ -374,7 +389,7 @@ hipError_t launch_lhz_mwd(const uint32_t *rows, int R, int N, unsigned long long
   (void)hipGetLastError();
   hipLaunchKernelGGL(fill_u64_kernel, dim3(blocks_for(R, 256)), dim3(256), 0, s, reinterpret_cast<uint64_t *>(best),
                      static_cast<size_t>(R), uint64_t(0));
-  const int c = chunk_exponent(N);
+  const int c = mwd_chunk_exponent(N);
   const uint64_t lanes = (1ull << (N - 1)) >> c;
   hipLaunchKernelGGL(lhz_mwd_kernel, dim3(R, blocks_for(lanes, 256)), dim3(256), 0, s, rows, N, c, best);
   if (logical)
