@@ -121,7 +121,12 @@ typedef struct pt_handle pt_handle;
 typedef struct sqa_server sqa_server;
 
 /* Launch shape of the persistent sweep kernel.  Every field 0 = choose
- * automatically (the autotuner's cached choice for this device and shape). */
+ * automatically (the autotuner's cached choice for this device and shape).
+ * Chosen automatically, a set of Metropolis handles holding at most 1024
+ * replicas in all runs in team mode instead: each workgroup anneals a single
+ * replica with up to 8 waves that share its colour classes (lower latency when
+ * few replicas are resident; results are identical).  A nonzero
+ * waves_per_group keeps one wave per replica. */
 typedef struct {
   int32_t waves_per_group;    /* replicas processed together by one workgroup: 1..8 */
   int32_t groups_per_cu;      /* resident workgroups per compute unit targeted by the grid */

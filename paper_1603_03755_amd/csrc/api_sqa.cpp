@@ -55,10 +55,11 @@ static std::vector<WorkItem> plan_items(const std::vector<const sqa_handle *> &h
 }
 
 static LaunchShape shape_for(const std::vector<const sqa_handle *> &hs, int waves, int groups_per_cu,
-                             size_t n_items, int move) {
+                             size_t n_items, int move, bool team = false) {
   LaunchShape s;
   s.move = move;
   s.waves = waves;
+  s.team = team && move == kMoveMetropolis;
   for (const sqa_handle *h : hs) {
     if (h->move != move) continue;
     s.rec_cap = std::max(s.rec_cap, h->emb.n * h->lay.rec_words);
@@ -80,6 +81,25 @@ static LaunchShape shape_for(const std::vector<const sqa_handle *> &hs, int wave
   return s;
 }
 
+// Team mode (see kTeamMaxReplicas): applies to the Metropolis handles of a set
+// that hold at most kTeamMaxReplicas replicas in all; *team_waves is then the
+// number of waves that makes the largest colour class about one pass.
+static bool use_team(const std::vector<const sqa_handle *> &hs, int move, int *team_waves) {
+  if (move != kMoveMetropolis) return false;
+  long long replicas = 0;
+  int max_items = 1;
+  for (const sqa_handle *h : hs) {
+    if (h->move != move) continue;
+    replicas += h->R;
+    const int half = (h->L == 1) ? 1 : (h->L >> 1);
+    const int bytes = (half + 7) >> 3;
+    for (int c = 0; c < 4; ++c) max_items = std::max(max_items, (h->lay.cls[c + 1] - h->lay.cls[c]) * bytes);
+  }
+  if (replicas == 0 || replicas > kTeamMaxReplicas) return false;
+  *team_waves = std::max(1, std::min(8, (max_items + 63) / 64));
+  return true;
+}
+
 // One persistent launch per update move present in a handle set.  Device
 // buffer of a set: [HandleDev x handles][items of each group][a counter per group].
 struct MoveGroup {
@@ -91,15 +111,17 @@ struct MoveGroup {
 
 static sqa_status plan_groups(const std::vector<const sqa_handle *> &hs, const std::vector<int> &m0,
                               const std::vector<int> &m1, int waves, int gpc, std::vector<MoveGroup> *out,
-                              size_t *bytes) {
+                              size_t *bytes, bool allow_team = true) {
   out->clear();
   size_t off = (sizeof(HandleDev) * hs.size() + 255) & ~size_t(255);
   for (int move : {kMoveMetropolis, kMoveWolff}) {
     MoveGroup g;
     g.move = move;
-    g.items = plan_items(hs, m0, m1, waves, move);
+    int tw = 0;
+    const bool team = allow_team && use_team(hs, move, &tw);
+    g.items = plan_items(hs, m0, m1, team ? 1 : waves, move);
     if (g.items.empty()) continue;
-    g.shape = shape_for(hs, waves, gpc, g.items.size(), move);
+    g.shape = team ? shape_for(hs, tw, 0, g.items.size(), move, true) : shape_for(hs, waves, gpc, g.items.size(), move);
     if (g.shape.lds_bytes() > kMaxLds) return fail(SQA_ERR_UNSUPPORTED, "lattices do not fit in LDS");
     g.items_off = off;
     off = (off + sizeof(WorkItem) * g.items.size() + 255) & ~size_t(255);
@@ -129,7 +151,7 @@ static hipError_t launch_groups(char *base, const std::vector<MoveGroup> &gs, hi
   for (const MoveGroup &g : gs) {
     e = launch_sqa_anneal(g.move, reinterpret_cast<HandleDev *>(base), reinterpret_cast<WorkItem *>(base + g.items_off),
                           static_cast<int>(g.items.size()), reinterpret_cast<int *>(base + g.counter_off), g.shape.grid,
-                          g.shape.waves, g.shape.rec_cap, g.shape.lat_cap, g.shape.tab_cap, stream);
+                          g.shape.waves, g.shape.rec_cap, g.shape.lat_cap, g.shape.tab_cap, g.shape.team, stream);
     if (e != hipSuccess) break;
   }
   return e;
@@ -400,8 +422,11 @@ static sqa_status run_single(sqa_handle *h, int m0, int m1, int flags, hipStream
   std::vector<const sqa_handle *> hs{h};
   int waves = 4, gpc = 0;
   resolve_config(hs, nullptr, &waves, &gpc);
-  std::vector<WorkItem> items = plan_items(hs, {m0}, {m1}, waves, h->move);
-  LaunchShape shape = shape_for(hs, waves, gpc, items.size(), h->move);
+  int tw = 0;
+  const bool team = use_team(hs, h->move, &tw);
+  std::vector<WorkItem> items = plan_items(hs, {m0}, {m1}, team ? 1 : waves, h->move);
+  LaunchShape shape = team ? shape_for(hs, tw, 0, items.size(), h->move, true)
+                           : shape_for(hs, waves, gpc, items.size(), h->move);
   if (shape.lds_bytes() > kMaxLds) return fail(SQA_ERR_UNSUPPORTED, "lattice does not fit in LDS");
   // previous work on this handle must have consumed the pinned staging copy
   e = hipEventSynchronize(h->done);
@@ -420,7 +445,7 @@ static sqa_status run_single(sqa_handle *h, int m0, int m1, int flags, hipStream
   if (e == hipSuccess)
     e = launch_sqa_anneal(h->move, h->arena.at<HandleDev>(h->off_hd), h->arena.at<WorkItem>(h->off_items),
                           static_cast<int>(items.size()), h->arena.at<int>(h->off_counter), shape.grid, shape.waves,
-                          shape.rec_cap, shape.lat_cap, shape.tab_cap, stream);
+                          shape.rec_cap, shape.lat_cap, shape.tab_cap, shape.team, stream);
   if (e == hipSuccess) e = hipEventRecord(h->done, stream);
   if (e != hipSuccess) {
     h->poisoned = true;
@@ -929,13 +954,14 @@ struct sqa_batch {
   hipGraphExec_t exec = nullptr;
 };
 
-static sqa_status batch_build(sqa_handle *const *handles, int32_t count, int waves, int gpc, sqa_batch **out) {
+static sqa_status batch_build(sqa_handle *const *handles, int32_t count, int waves, int gpc, bool allow_team,
+                              sqa_batch **out) {
   std::vector<const sqa_handle *> hs(handles, handles + count);
   std::vector<int> m0(count, 0), m1(count);
   for (int i = 0; i < count; ++i) m1[i] = handles[i]->M;
   std::vector<MoveGroup> groups;
   size_t bytes = 0;
-  sqa_status st = plan_groups(hs, m0, m1, waves, gpc, &groups, &bytes);
+  sqa_status st = plan_groups(hs, m0, m1, waves, gpc, &groups, &bytes, allow_team);
   if (st != SQA_OK) return st;
   std::vector<HandleDev> hds(count);
   for (int i = 0; i < count; ++i) hds[i] = handles[i]->dev(0, handles[i]->M, kFlagInit | kFlagEnergy);
@@ -1002,7 +1028,9 @@ sqa_status sqa_batch_create(sqa_handle *const *handles, int32_t count, const sqa
   int waves = 4, gpc = 0;
   resolve_config(hs, config, &waves, &gpc);
   sqa_batch *b = nullptr;
-  sqa_status st = batch_build(handles, count, waves, gpc, &b);
+  // an explicit waves_per_group keeps one wave per replica; otherwise team mode may apply
+  const bool allow_team = !(config && config->waves_per_group > 0);
+  sqa_status st = batch_build(handles, count, waves, gpc, allow_team, &b);
   if (st != SQA_OK) return st;
   st = batch_capture(b);
   if (st != SQA_OK) {
@@ -1093,7 +1121,7 @@ sqa_status sqa_autotune(sqa_handle *const *handles, int32_t count, const char *c
       for (int i = 0; i < count; ++i) m1[i] = std::min(handles[i]->M, trial_sweeps);
       std::vector<MoveGroup> base;
       size_t bytes = 0;
-      if (plan_groups(hs, m0, m1, w, 0, &base, &bytes) != SQA_OK) continue;
+      if (plan_groups(hs, m0, m1, w, 0, &base, &bytes, false) != SQA_OK) continue;
       // groups-per-CU candidates: every count from half the occupancy of the first
       // group's kernel up to all of it (the count sets how evenly the work items
       // divide into rounds of resident workgroups)
@@ -1102,7 +1130,7 @@ sqa_status sqa_autotune(sqa_handle *const *handles, int32_t count, const char *c
       for (int g = occ; g >= std::max(1, occ / 2); --g) gpcs.push_back(g);
       for (int g : gpcs) {
         std::vector<MoveGroup> groups;
-        if (plan_groups(hs, m0, m1, w, g, &groups, &bytes) != SQA_OK) continue;
+        if (plan_groups(hs, m0, m1, w, g, &groups, &bytes, false) != SQA_OK) continue;
         std::vector<HandleDev> hds(count);
         for (int i = 0; i < count; ++i) hds[i] = handles[i]->dev(0, m1[i], kFlagInit);
         void *dev = nullptr;

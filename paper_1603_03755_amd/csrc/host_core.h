@@ -92,7 +92,7 @@ struct Arena {
 
 // Kernel launchers (sqa_kernels.hip, pt_kernels.hip).
 hipError_t launch_sqa_anneal(int move, const HandleDev *hds, const WorkItem *items, int n_items, int *counter, int grid,
-                             int waves, int rec_cap, int lat_cap, int tab_cap, hipStream_t stream);
+                             int waves, int rec_cap, int lat_cap, int tab_cap, bool team, hipStream_t stream);
 hipError_t set_sqa_anneal_lds_limit(size_t bytes);
 int sqa_anneal_occupancy(int move, int waves, size_t lds_bytes);
 hipError_t launch_sqa_init(const HandleDev &H, hipStream_t stream);
@@ -126,11 +126,20 @@ struct LaunchShape {
   int waves = 4;
   int grid = 0;
   int rec_cap = 0, lat_cap = 0, tab_cap = 0;
+  bool team = false;   // Metropolis: the workgroup's waves run one replica together
   size_t lds_bytes() const {
-    return (static_cast<size_t>(kSpreadWords) + rec_cap + 2ull * waves * lat_cap +
+    const int lattices = team ? 1 : waves;
+    return (static_cast<size_t>(kSpreadWords) + rec_cap + 2ull * lattices * lat_cap +
             static_cast<size_t>(waves) * tab_cap) * 4;
   }
 };
+
+// Team mode for a Metropolis launch: when the handles hold few replicas in all
+// (at most kTeamMaxReplicas), one wave per replica leaves most of the GPU idle
+// and a replica's anneal time is the launch's latency, so each workgroup runs a
+// single replica with enough waves (up to 8) that a colour class takes about
+// one pass.
+constexpr int kTeamMaxReplicas = 1024;
 
 int device_cu_count();
 int occupancy_groups_per_cu(const LaunchShape &s);

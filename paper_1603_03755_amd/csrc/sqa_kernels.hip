@@ -36,12 +36,12 @@ __device__ __forceinline__ int slice_bit(int tau) { return NAT ? tau : (tau >> 1
 // Builds the initial lattice in LDS: s = -1 iff bit 31 of the INIT-stream word
 // of (replica, slice, site, sweep 0).
 template <bool NAT>
-__device__ __forceinline__ void init_lattice(const HandleDev &H, uint64_t *lat, int rep, int lane) {
+__device__ __forceinline__ void init_lattice(const HandleDev &H, uint64_t *lat, int rep, int lane, int nthr) {
   const int L = H.L, n = H.n;
   const int G = (L + 7) >> 3;
   const uint32_t c3 = (kStreamInit << 24) | static_cast<uint32_t>(rep);
   const int rw = rec_words_of(H.kind);
-  for (int d = lane; d < n; d += 64) {
+  for (int d = lane; d < n; d += nthr) {
     const uint32_t site = H.rec[d * rw] & 0xFFFFu;
     uint64_t w = 0;
     for (int g = 0; g < G; ++g) {
@@ -61,10 +61,10 @@ __device__ __forceinline__ void init_lattice(const HandleDev &H, uint64_t *lat, 
 
 // Loads [L][n] int8 spins of one replica (physical order) into LDS words.
 template <bool NAT>
-__device__ __forceinline__ void load_lattice(const HandleDev &H, uint64_t *lat, int rep, int lane) {
+__device__ __forceinline__ void load_lattice(const HandleDev &H, uint64_t *lat, int rep, int lane, int nthr) {
   const int L = H.L, n = H.n;
   const int8_t *src = H.spins + static_cast<size_t>(rep) * L * n;
-  for (int k = lane; k < n; k += 64) {
+  for (int k = lane; k < n; k += nthr) {
     uint64_t w = 0;
     for (int tau = 0; tau < L; ++tau)
       w |= static_cast<uint64_t>(src[static_cast<size_t>(tau) * n + k] < 0) << slice_bit<NAT>(tau);
@@ -74,10 +74,10 @@ __device__ __forceinline__ void load_lattice(const HandleDev &H, uint64_t *lat, 
 }
 
 template <bool NAT>
-__device__ __forceinline__ void store_lattice(const HandleDev &H, const uint64_t *lat, int rep, int lane) {
+__device__ __forceinline__ void store_lattice(const HandleDev &H, const uint64_t *lat, int rep, int lane, int nthr) {
   const int L = H.L, n = H.n;
   int8_t *dst = H.spins + static_cast<size_t>(rep) * L * n;
-  for (int k = lane; k < n; k += 64) {
+  for (int k = lane; k < n; k += nthr) {
     const uint64_t w = lat[H.dev_of[k]];
     for (int tau = 0; tau < L; ++tau)
       dst[static_cast<size_t>(tau) * n + k] = ((w >> slice_bit<NAT>(tau)) & 1ull) ? int8_t(-1) : int8_t(1);
@@ -101,7 +101,8 @@ __device__ __forceinline__ void slice_energies(const HandleDev &H, const uint64_
 }
 
 // ------------------------------------------------------------ SQA sweep
-// 64-lane item loop over one (slice parity p, colour c) class of one replica.
+// Item loop over one (slice parity p, colour c) class of one replica, by the
+// nthr threads of its team (one wave, or the whole workgroup).
 // Item = (site of colour c, byte b of its parity-p half word): the eight slices
 // tau = 16b + 2k + p (k = 0..7), served by the two Philox calls of slice groups
 // 2b and 2b+1 (four words each).  For each slice the acceptance index is
@@ -126,7 +127,7 @@ __device__ __forceinline__ void slice_energies(const HandleDev &H, const uint64_
 template <int KIND, int MODE, int FL, int P>
 __device__ __forceinline__ void sweep_class(const HandleDev &H, const uint32_t *__restrict__ rec, uint32_t *lat32,
                                             const uint32_t *tab, const uint2 *stab, int c, uint32_t m, uint32_t c3,
-                                            int lane) {
+                                            int tid, int nthr) {
   constexpr int p = P;
   constexpr bool FASTL = FL != 0;
   using S = Site<KIND>;
@@ -141,12 +142,12 @@ __device__ __forceinline__ void sweep_class(const HandleDev &H, const uint32_t *
   const bool ring32 = FASTL || (Hp & (Hp - 1)) == 0;   // Hp divides 32: rotate a replicated word
   const bool ragged = !FASTL && (Hp & 7) != 0;          // last byte has fewer than eight slices
   // FASTL: item it = j * B + b (B a power of two).  Otherwise it = b * nc + j,
-  // lanes advancing by 64 items: (j, b) += (64 % nc, 64 / nc).
+  // threads advancing by nthr items: (j, b) += (nthr % nc, nthr / nc).
   const int lgB = (B >= 4) ? 2 : (B - 1);
-  const int dq = 64 / nc, dr = 64 - dq * nc;
-  int b = FASTL ? (lane & (B - 1)) : lane / nc;
-  int j = FASTL ? (lane >> lgB) : lane - b * nc;
-  for (int it = lane; it < cnt; it += 64, j += dr, b += dq) {
+  const int dq = nthr / nc, dr = nthr - dq * nc;
+  int b = FASTL ? (tid & (B - 1)) : tid / nc;
+  int j = FASTL ? (tid >> lgB) : tid - b * nc;
+  for (int it = tid; it < cnt; it += nthr, j += dr, b += dq) {
     if constexpr (FASTL) {
       j = it >> lgB;
       b = it & (B - 1);
@@ -331,12 +332,20 @@ __device__ __forceinline__ void sweep_class(const HandleDev &H, const uint32_t *
   }
 }
 
+// One replica through sweeps m0..m1-1 by a team: one wave (team = false; tid
+// = lane, nthr = 64) or the whole workgroup (team = true; tid = thread index,
+// nthr = block size), which then synchronises with workgroup barriers.  Each
+// wave keeps its own copy of the sweep's table row in `tab`.
 template <int KIND>
 __device__ __forceinline__ void anneal_replica(const HandleDev &H, const uint32_t *rec, uint64_t *lat, uint32_t *tab,
-                                               const uint2 *stab, int rep, int lane) {
-  if (H.flags & kFlagInit) init_lattice<false>(H, lat, rep, lane);
-  else load_lattice<false>(H, lat, rep, lane);
-  wave_sync();
+                                               const uint2 *stab, int rep, int lane, int tid, int nthr, bool team) {
+  auto team_sync = [&]() {
+    if (team) __syncthreads();
+    else wave_sync();
+  };
+  if (H.flags & kFlagInit) init_lattice<false>(H, lat, rep, tid, nthr);
+  else load_lattice<false>(H, lat, rep, tid, nthr);
+  team_sync();
   const uint32_t c3 = (kStreamSQA << 24) | static_cast<uint32_t>(rep);
   const int parities = (H.L == 1) ? 1 : 2;
   const bool smallf = H.F <= kSmallF;
@@ -354,32 +363,32 @@ __device__ __forceinline__ void anneal_replica(const HandleDev &H, const uint32_
       const uint32_t *row = H.table + static_cast<size_t>(m) * H.tw;
       for (int i = lane; i < H.tw; i += 64) tab[i] = row[i];
     }
-    wave_sync();
+    team_sync();
     uint32_t *lat32 = reinterpret_cast<uint32_t *>(lat);
     const uint32_t mm = static_cast<uint32_t>(m);
     for (int c = 0; c < 4; ++c) {
-      if (fast == 64) sweep_class<KIND, kFieldSmall, 64, 0>(H, rec, lat32, tab, stab, c, mm, c3, lane);
-      else if (fast == 32) sweep_class<KIND, kFieldSmall, 32, 0>(H, rec, lat32, tab, stab, c, mm, c3, lane);
-      else if (fast == 16) sweep_class<KIND, kFieldSmall, 16, 0>(H, rec, lat32, tab, stab, c, mm, c3, lane);
-      else if (smallf) sweep_class<KIND, kFieldSmall, 0, 0>(H, rec, lat32, tab, stab, c, mm, c3, lane);
-      else if (midf) sweep_class<KIND, kFieldMid, 0, 0>(H, rec, lat32, tab, stab, c, mm, c3, lane);
-      else sweep_class<KIND, kFieldLarge, 0, 0>(H, rec, lat32, tab, stab, c, mm, c3, lane);
-      wave_sync();
+      if (fast == 64) sweep_class<KIND, kFieldSmall, 64, 0>(H, rec, lat32, tab, stab, c, mm, c3, tid, nthr);
+      else if (fast == 32) sweep_class<KIND, kFieldSmall, 32, 0>(H, rec, lat32, tab, stab, c, mm, c3, tid, nthr);
+      else if (fast == 16) sweep_class<KIND, kFieldSmall, 16, 0>(H, rec, lat32, tab, stab, c, mm, c3, tid, nthr);
+      else if (smallf) sweep_class<KIND, kFieldSmall, 0, 0>(H, rec, lat32, tab, stab, c, mm, c3, tid, nthr);
+      else if (midf) sweep_class<KIND, kFieldMid, 0, 0>(H, rec, lat32, tab, stab, c, mm, c3, tid, nthr);
+      else sweep_class<KIND, kFieldLarge, 0, 0>(H, rec, lat32, tab, stab, c, mm, c3, tid, nthr);
+      team_sync();
     }
     if (parities > 1)
       for (int c = 0; c < 4; ++c) {
-        if (fast == 64) sweep_class<KIND, kFieldSmall, 64, 1>(H, rec, lat32, tab, stab, c, mm, c3, lane);
-        else if (fast == 32) sweep_class<KIND, kFieldSmall, 32, 1>(H, rec, lat32, tab, stab, c, mm, c3, lane);
-        else if (fast == 16) sweep_class<KIND, kFieldSmall, 16, 1>(H, rec, lat32, tab, stab, c, mm, c3, lane);
-        else if (smallf) sweep_class<KIND, kFieldSmall, 0, 1>(H, rec, lat32, tab, stab, c, mm, c3, lane);
-        else if (midf) sweep_class<KIND, kFieldMid, 0, 1>(H, rec, lat32, tab, stab, c, mm, c3, lane);
-        else sweep_class<KIND, kFieldLarge, 0, 1>(H, rec, lat32, tab, stab, c, mm, c3, lane);
-        wave_sync();
+        if (fast == 64) sweep_class<KIND, kFieldSmall, 64, 1>(H, rec, lat32, tab, stab, c, mm, c3, tid, nthr);
+        else if (fast == 32) sweep_class<KIND, kFieldSmall, 32, 1>(H, rec, lat32, tab, stab, c, mm, c3, tid, nthr);
+        else if (fast == 16) sweep_class<KIND, kFieldSmall, 16, 1>(H, rec, lat32, tab, stab, c, mm, c3, tid, nthr);
+        else if (smallf) sweep_class<KIND, kFieldSmall, 0, 1>(H, rec, lat32, tab, stab, c, mm, c3, tid, nthr);
+        else if (midf) sweep_class<KIND, kFieldMid, 0, 1>(H, rec, lat32, tab, stab, c, mm, c3, tid, nthr);
+        else sweep_class<KIND, kFieldLarge, 0, 1>(H, rec, lat32, tab, stab, c, mm, c3, tid, nthr);
+        team_sync();
       }
   }
-  store_lattice<false>(H, lat, rep, lane);
-  if (H.flags & kFlagEnergy) slice_energies<false>(H, lat, rep, lane);
-  wave_sync();
+  store_lattice<false>(H, lat, rep, tid, nthr);
+  if (H.flags & kFlagEnergy) slice_energies<false>(H, lat, rep, tid);
+  team_sync();
 }
 
 // ------------------------------------------------------ SQA, Wolff moves
@@ -588,8 +597,8 @@ __device__ __forceinline__ void wolff_flips(const HandleDev &H, const uint32_t *
 template <int KIND>
 __device__ __forceinline__ void wolff_replica(const HandleDev &H, const uint32_t *rec, uint64_t *lat, uint32_t *scr,
                                               const uint2 *stab, int rep, int lane) {
-  if (H.flags & kFlagInit) init_lattice<true>(H, lat, rep, lane);
-  else load_lattice<true>(H, lat, rep, lane);
+  if (H.flags & kFlagInit) init_lattice<true>(H, lat, rep, lane, 64);
+  else load_lattice<true>(H, lat, rep, lane, 64);
   wave_sync();
   const uint32_t c3 = (kStreamWolff << 24) | static_cast<uint32_t>(rep);
   for (int m = H.m0; m < H.m1; ++m) {
@@ -608,7 +617,7 @@ __device__ __forceinline__ void wolff_replica(const HandleDev &H, const uint32_t
         wave_sync();
       }
   }
-  store_lattice<true>(H, lat, rep, lane);
+  store_lattice<true>(H, lat, rep, lane, 64);
   if (H.flags & kFlagEnergy) slice_energies<true>(H, lat, rep, lane);
   wave_sync();
 }
@@ -617,8 +626,9 @@ __device__ __forceinline__ void wolff_replica(const HandleDev &H, const uint32_t
 // each workgroup repeatedly takes the next work item (handle, replica group)
 // from `counter`, stages the handle's site records in LDS, and runs one
 // replica per wavefront through sweeps m0..m1-1.
-// Dynamic LDS: [kSpreadWords: byte -> spread table][rec_cap words][waves x lat_cap u64]
-// [waves x tab_cap words] (tab: the Metropolis table row, or the Wolff phase scratch).
+// Dynamic LDS: [kSpreadWords: byte -> spread table][rec_cap words][waves x lat_cap u64, or one
+// lattice in team mode][waves x tab_cap words] (tab: the Metropolis table row, or the Wolff
+// phase scratch).
 #ifndef SQA_WAVES_PER_EU
 #define SQA_WAVES_PER_EU 1
 #endif
@@ -626,7 +636,7 @@ template <int MOVE>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(SQA_WAVES_PER_EU, 8))) void sqa_anneal_kernel(const HandleDev *__restrict__ hds,
                                                          const WorkItem *__restrict__ items, int n_items,
                                                          int *__restrict__ counter, int rec_cap,
-                                                         int lat_cap, int tab_cap) {
+                                                         int lat_cap, int tab_cap, int team) {
   extern __shared__ __align__(16) uint32_t smem[];
   __shared__ int s_item;
   const int waves = blockDim.x >> 6;
@@ -634,8 +644,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(SQA_WAVES_P
   const int lane = threadIdx.x & 63;
   uint2 *stab = reinterpret_cast<uint2 *>(smem);
   uint32_t *rec = smem + kSpreadWords;
-  uint64_t *lat = reinterpret_cast<uint64_t *>(rec + rec_cap) + static_cast<size_t>(wave) * lat_cap;
-  uint32_t *tab = rec + rec_cap + 2 * waves * lat_cap + wave * tab_cap;
+  // team mode (Metropolis only): the workgroup runs one replica in one lattice
+  uint64_t *lat = reinterpret_cast<uint64_t *>(rec + rec_cap) + static_cast<size_t>(team ? 0 : wave) * lat_cap;
+  uint32_t *tab = rec + rec_cap + 2 * (team ? 1 : waves) * lat_cap + wave * tab_cap;
   for (int x = threadIdx.x; x < kSpreadWords / 2; x += blockDim.x)
     stab[x] = make_uint2(spread6(static_cast<uint32_t>(x) & 0xFu), spread6(static_cast<uint32_t>(x) >> 4));
   for (;;) {
@@ -649,15 +660,24 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(SQA_WAVES_P
     const int nwords = H.n * rw;
     for (int i = threadIdx.x; i < nwords; i += blockDim.x) rec[i] = H.rec[i];
     __syncthreads();
-    if (wave < wi.nrep) {
+    if (!team && wave < wi.nrep) {
       if constexpr (MOVE == kMoveWolff) {
         if (H.kind == kKindME) wolff_replica<kKindME>(H, rec, lat, tab, stab, wi.rep0 + wave, lane);
         else if (H.kind == kKindLHZ) wolff_replica<kKindLHZ>(H, rec, lat, tab, stab, wi.rep0 + wave, lane);
         else wolff_replica<kKindMEC>(H, rec, lat, tab, stab, wi.rep0 + wave, lane);
       } else {
-        if (H.kind == kKindME) anneal_replica<kKindME>(H, rec, lat, tab, stab, wi.rep0 + wave, lane);
-        else if (H.kind == kKindLHZ) anneal_replica<kKindLHZ>(H, rec, lat, tab, stab, wi.rep0 + wave, lane);
-        else anneal_replica<kKindMEC>(H, rec, lat, tab, stab, wi.rep0 + wave, lane);
+        const int rep = wi.rep0 + wave;
+        if (H.kind == kKindME) anneal_replica<kKindME>(H, rec, lat, tab, stab, rep, lane, lane, 64, false);
+        else if (H.kind == kKindLHZ) anneal_replica<kKindLHZ>(H, rec, lat, tab, stab, rep, lane, lane, 64, false);
+        else anneal_replica<kKindMEC>(H, rec, lat, tab, stab, rep, lane, lane, 64, false);
+      }
+    }
+    if constexpr (MOVE == kMoveMetropolis) {
+      if (team) {
+        const int tid = threadIdx.x, nthr = blockDim.x;
+        if (H.kind == kKindME) anneal_replica<kKindME>(H, rec, lat, tab, stab, wi.rep0, lane, tid, nthr, true);
+        else if (H.kind == kKindLHZ) anneal_replica<kKindLHZ>(H, rec, lat, tab, stab, wi.rep0, lane, tid, nthr, true);
+        else anneal_replica<kKindMEC>(H, rec, lat, tab, stab, wi.rep0, lane, tid, nthr, true);
       }
     }
     __syncthreads();
@@ -727,20 +747,22 @@ __global__ void me_majority_kernel(const int8_t *__restrict__ spins, int N, int 
 
 // ----------------------------------------------------------- host launchers
 hipError_t launch_sqa_anneal(int move, const HandleDev *hds, const WorkItem *items, int n_items, int *counter,
-                             int grid, int waves, int rec_cap, int lat_cap, int tab_cap,
+                             int grid, int waves, int rec_cap, int lat_cap, int tab_cap, bool team,
                              hipStream_t stream) {
-  const size_t lds = (static_cast<size_t>(kSpreadWords) + rec_cap + 2ull * waves * lat_cap +
+  const int lattices = team ? 1 : waves;
+  const size_t lds = (static_cast<size_t>(kSpreadWords) + rec_cap + 2ull * lattices * lat_cap +
                       static_cast<size_t>(waves) * tab_cap) * 4;
+  const int tm = (team && move == kMoveMetropolis) ? 1 : 0;
   (void)hipGetLastError();
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, stream, counter);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (move == kMoveWolff)
     hipLaunchKernelGGL(sqa_anneal_kernel<kMoveWolff>, dim3(grid), dim3(64 * waves), lds, stream, hds, items, n_items,
-                       counter, rec_cap, lat_cap, tab_cap);
+                       counter, rec_cap, lat_cap, tab_cap, 0);
   else
     hipLaunchKernelGGL(sqa_anneal_kernel<kMoveMetropolis>, dim3(grid), dim3(64 * waves), lds, stream, hds, items,
-                       n_items, counter, rec_cap, lat_cap, tab_cap);
+                       n_items, counter, rec_cap, lat_cap, tab_cap, tm);
   return hipGetLastError();
 }
 

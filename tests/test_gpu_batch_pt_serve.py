@@ -54,6 +54,43 @@ def test_batch_equals_oracle_for_every_handle(sqa, waves):
     b.close()
 
 
+def test_team_and_wave_modes_agree(sqa):
+    """Team mode (a workgroup's waves share one replica) and one wave per replica give
+    identical lattices and energies: the same handles in an automatic batch above the
+    team-mode replica limit (one wave per replica), alone (team mode), and in a small
+    automatic batch (team mode), including ragged classes, L = 1, 2 and odd bytes."""
+    spec = [(ME, 7, 64), (LHZ, 9, 32), (ME, 5, 2), (LHZ, 6, 1), (ME, 10, 22), (LHZ, 8, 64), (ME, 4, 10),
+            (LHZ, 11, 16), (ME, 12, 64)]
+    specs = []
+    for q, (kind, N, L) in enumerate(spec):
+        specs.append(dict(kind=kind, J=sk_instance(N, 300 + q), pen=-2, beta=8.0, L=L, M=25, R=64, g0=3.0,
+                          g1=0.05, seed=0x7EA00 + q))
+    # pad with extra handles so that the batch holds more than 1024 replicas
+    pad = [dict(kind=LHZ, J=sk_instance(5, 400 + q), pen=-2, beta=6.0, L=16, M=10, R=64, g0=2.0, g1=0.1,
+                seed=0x7EB00 + q) for q in range(9)]
+    mk = lambda s: sqa.SQA(s["kind"], s["J"], s["pen"], s["beta"], s["L"], s["M"], s["R"], s["g0"], s["g1"],
+                           s["seed"])
+    print(f"wave-mode batch of {len(specs) + len(pad)} handles x 64 replicas", flush=True)
+    big = [mk(s) for s in specs + pad]
+    b = sqa.Batch(big)
+    b.run()
+    wave = [(h.spins(), h.energies()) for h in big[:len(specs)]]
+    b.close()
+    print("same handles alone and as a small batch (team mode)", flush=True)
+    alone = [mk(s).anneal() for s in specs]
+    small = [mk(s) for s in specs[:4]]
+    b2 = sqa.Batch(small)
+    b2.run()
+    for (ws, we), a in zip(wave, alone):
+        assert (a.spins() == ws).all() and (a.energies() == we).all()
+    for (ws, we), h in zip(wave, small):
+        assert (h.spins() == ws).all() and (h.energies() == we).all()
+    b2.close()
+    _, _, ospins, oE = O.sqa_anneal(specs[0]["kind"], specs[0]["J"], -2, 8.0, 64, 25, 64, 3.0, 0.05,
+                                    specs[0]["seed"], nthreads=NTH)
+    assert (wave[0][0] == ospins).all() and (wave[0][1] == oE).all()
+
+
 def test_batch_graph_replays_with_eager_work_between(sqa):
     specs = _mixed_jobs()[:4]
     hs = [sqa.SQA(s["kind"], s["J"], s["pen"], s["beta"], s["L"], s["M"], s["R"], s["g0"], s["g1"], s["seed"])
