@@ -52,9 +52,9 @@ WOLFF_SITE_OPS = PHILOX_OPS_PER_CALL + 24.0
 # HBM bytes of one launch of the sweep kernel on this workload, from rocprofv3 --pmc FETCH_SIZE and
 # WRITE_SIZE passes (KiB per dispatch) scaled by the same counters on a cold 2 GiB copy
 # (profiles/sqa_anneal_kernel_batched512_L64.md).  Valid only for the kernel source it was taken on.
-TRAFFIC_PROFILE = {"kernel_sha256_prefix": "e61ccab22857dd16", "instances": 512, "sweeps": 10_000,
-                   "fetch_kib": 1024833.0, "write_kib": 509216.4, "fetch_scale": 2.0, "write_scale": 1.0,
-                   "wolff_fetch_kib": 26911.62, "wolff_write_kib": 509208.0}
+TRAFFIC_PROFILE = {"kernel_sha256_prefix": "63bb0ab47a10c4a7", "instances": 512, "sweeps": 10_000,
+                   "fetch_kib": 965387.0, "write_kib": 509216.0, "fetch_scale": 2.0, "write_scale": 1.0,
+                   "wolff_fetch_kib": 25193.9, "wolff_write_kib": 509208.0}
 
 
 def measured_traffic(args, wolff=False):
