@@ -80,10 +80,12 @@ PTShape pt_shape(const std::vector<const pt_handle *> &hs) {
   s.lat_cap = (s.lat_cap + 1) & ~1;
   s.mtab_cap = (s.mtab_cap + 3) & ~3;
   // the packed swap tables go to LDS when the largest one fits beside the rest
+  // (SQA_PT_STAGE_SWAPS=0 keeps them in device memory)
   int spack = 0;
   for (const pt_handle *h : hs) spack = std::max(spack, static_cast<int>(h->spack.size()));
   s.spack_cap = (spack + 3) & ~3;
-  if (s.lds() > kMaxLds) s.spack_cap = 0;
+  const char *stage = std::getenv("SQA_PT_STAGE_SWAPS");
+  if (s.lds() > kMaxLds || (stage && std::atoi(stage) == 0)) s.spack_cap = 0;
   // one workgroup owns a ladder: enough waves that the largest colour class is one
   // pass, at most kPTMaxWaves (the kernel's launch bound; larger classes loop)
   const char *env = std::getenv("SQA_PT_WAVES");

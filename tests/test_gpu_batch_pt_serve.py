@@ -175,6 +175,24 @@ def test_pt_bit_exact(sqa, kind, N, R, sweeps, sps):
     assert (acc == oacc).all()
 
 
+@pytest.mark.parametrize("stage", ["1", "0"])
+def test_pt_swap_table_in_lds_or_device_memory(sqa, monkeypatch, stage):
+    """The swap thresholds read from the packed table staged in LDS and from device
+    memory give the same ladder (and the oracle's), on swaps that happen every sweep."""
+    monkeypatch.setenv("SQA_PT_STAGE_SWAPS", stage)
+    print(f"PT swap table staged={stage}", flush=True)
+    for kind, N, R in ((ME, 7, 32), (LHZ, 6, 13)):
+        J = sk_instance(N, 750 + N)
+        seed = 0x9800 + N
+        dev = sqa.PT(kind, J, -2, 0.2, 4.0, R, 120, 1, seed).run()
+        spins, E, rep, acc = dev.read()
+        emb = O.Embedding(kind, J, -2)
+        ospins, oE, orep, oacc = O.pt_run(emb, O.pt_ladder(0.2, 4.0, R), 120, 1, seed)
+        assert (rep == orep).all() and (spins == ospins[orep]).all()
+        assert (E == oE[orep]).all() and (acc == oacc).all()
+        assert acc.sum() > 0
+
+
 def test_pt_workload_shape_sampled(sqa):
     """PT workload shape (N = 24, 32 temperatures, both embeddings) in one batched
     launch, at a reduced sweep count the oracle can finish: two instances exact."""
