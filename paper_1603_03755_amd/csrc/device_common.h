@@ -135,6 +135,18 @@ __device__ __forceinline__ uint32_t spread3(uint32_t bits) { return __umul24(bit
 // set for nibble bit 3, so it must not be an operand of a 24-bit multiply.
 __device__ __forceinline__ uint32_t spread8(uint32_t nib) { return __umul24(nib & 0xFu, 0x204081u) & 0x01010101u; }
 
+// Two 16-bit lanes of one register, for packed 16-bit integer arithmetic
+// (v_pk_* instructions: both lanes in one operation).
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ u16x2 as_u16x2(uint32_t x) { return __builtin_bit_cast(u16x2, x); }
+__device__ __forceinline__ uint32_t as_u32(u16x2 x) { return __builtin_bit_cast(uint32_t, x); }
+// {byte B0 of src, byte B1 of src} as two 16-bit lanes (one byte permute;
+// selector 0x0C yields a zero byte).
+template <int B0, int B1>
+__device__ __forceinline__ u16x2 byte_pair(uint32_t src) {
+  return as_u16x2(__builtin_amdgcn_perm(src, src, 0x0C000C00u | (B1 << 16) | B0));
+}
+
 // Entry x of the byte -> spread table; each word holds bits 0, 6, 12, 18 at
 // most (the assumption lets the multiplies by it be 24-bit ones).
 __device__ __forceinline__ uint2 spread_of(const uint2 *stab, uint32_t x) {

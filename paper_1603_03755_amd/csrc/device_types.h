@@ -40,7 +40,8 @@ constexpr int kKindMEC = 2;     // ME on Chimera
 // LHZ) or bit 6 (ME on Chimera).
 // base = 3 * (F_site + F) + 2, F_site = |h| + sum |w_t|.
 // Weights |w|, |h| in the records are stored multiplied by 6 when F <= kSmallF
-// (the sweep kernel then indexes the table with the field sums directly).
+// (the sweep kernel then indexes the table with the field sums directly), and
+// base is then 4c | 4c << 8 with c = 3 (F - F_site).
 constexpr int kSmallF = 10;
 // Largest per-site field sum of the 6-bit-field sweep path, and of the library.
 constexpr int kMidF = 63;
@@ -66,9 +67,13 @@ constexpr uint32_t kStreamWolff = 7;
 // Low 16 bits of the 32-bit uniforms of Metropolis attempts and Wolff bonds:
 // a uniform is (hi << 16) | lo with hi from the SQA (WOLFF) stream and lo from
 // these, at the same counter, word and half.
-// LDS table at the start of the anneal kernel's dynamic LDS: byte x ->
-// (spread of its low nibble, spread of its high nibble) into 6-bit fields.
-constexpr int kSpreadWords = 512;
+// LDS table at the start of the anneal kernel's dynamic LDS, two halves of
+// kSpreadEntries uint2 each: entry x maps byte x to (spread of its low nibble,
+// spread of its high nibble) into 6-bit fields (bit 0 of fields at bits 0, 6,
+// 12, 18); entry kSpreadEntries + x does the same into bytes at value 4 (bit 2
+// of each byte), for the small-field sweep mode.
+constexpr int kSpreadEntries = 256;
+constexpr int kSpreadWords = 4 * kSpreadEntries;
 constexpr uint32_t kStreamSQALo = 8;
 constexpr uint32_t kStreamWolffLo = 9;
 constexpr uint32_t kStreamPTLo = 10;

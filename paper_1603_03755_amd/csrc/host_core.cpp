@@ -185,11 +185,13 @@ sqa_status build_layout(const Embedded &emb, int32_t F, bool scale6, DeviceLayou
       // The sweep kernel's small-field mode sums 6|w| over the terms that AGREE
       // with their sign (flipped sign bits) on top of c = 3 (F - F_site); with the
       // agreeing time neighbours e' this gives c + 6 A + e' = base - (6 S + e).
+      // The kernel keeps 4 (c + 6 A + e') per byte, so base carries 4c twice.
       for (int a = 0; a < 6; ++a) aw[a] *= 6u;
       ah *= 6u;
       const uint32_t hbit = 1u << (mec ? kFieldSignMEC : 4);
       neg ^= ((1u << T) - 1u) | hbit;
-      base = static_cast<uint32_t>(3 * (F - fs));
+      const uint32_t c = static_cast<uint32_t>(3 * (F - fs));   // at most 30: 4c fits a byte
+      base = (4u * c) | ((4u * c) << 8);
     }
     uint32_t *r = &L.rec[static_cast<size_t>(d) * L.rec_words];
     r[0] = static_cast<uint32_t>(k) | (base << 16);

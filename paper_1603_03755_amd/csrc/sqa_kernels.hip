@@ -228,100 +228,162 @@ __device__ __forceinline__ void sweep_class(const HandleDev &H, const uint32_t *
     // disagreeing (agreeing, kFieldSmall) time neighbours
     const uint32_t agree = (MODE == kFieldSmall) ? 0xFFu : 0u;
     const uint32_t e1 = own ^ dn ^ agree, e2 = own ^ up ^ agree;
-    const uint2 se1 = spread_of(stab, e1), se2 = spread_of(stab, e2);
-    const uint32_t ev_lo = se1.x + se2.x;
-    const uint32_t ev_hi = se1.y + se2.y;
-
-    // weighted disagreement counts, slices k = 0..3 in acc_lo and 4..7 in acc_hi
     const uint32_t ox = (own ^ negh) & 0xFFu;
-    uint32_t acc_lo = 0, acc_hi = 0, acc_x = 0;     // kFieldLarge: slices 0-2, 3-5, 6-7
-    if constexpr (MODE == kFieldSmall) {
-      const uint32_t c4 = __umul24(base, 0x41041u);       // c in every field
-      const uint2 so = spread_of(stab, ox);
-      acc_lo = c4 + __umul24(so.x, hw);
-      acc_hi = c4 + __umul24(so.y, hw);
-    } else if constexpr (MODE == kFieldLarge) {
-      acc_lo = __umul24(spread3(ox), hw);
-      acc_hi = __umul24(spread3(ox >> 3), hw);
-      acc_x = __umul24(spread3(ox >> 6), hw);
-    } else {
-      const uint2 so = spread_of(stab, ox);
-      acc_lo = __umul24(so.x, hw);
-      acc_hi = __umul24(so.y, hw);
-    }
-#pragma unroll
-    for (int t = 0; t < S::T; ++t) {
-      uint32_t prod = own;
-#pragma unroll
-      for (int q = 0; q < S::P; ++q) prod ^= pbyte[S::P * t + q];
-      const uint32_t x = (prod ^ (0u - ((neg >> t) & 1u))) & 0xFFu;
-      const uint32_t wt = term_weight(wts, wts2, t);
-      if constexpr (MODE == kFieldLarge) {
-        acc_lo += __umul24(spread3(x), wt);
-        acc_hi += __umul24(spread3(x >> 3), wt);
-        acc_x += __umul24(spread3(x >> 6), wt);
-      } else {
-        const uint2 sx = spread_of(stab, x);
-        acc_lo += __umul24(sx.x, wt);
-        acc_hi += __umul24(sx.y, wt);
-      }
-    }
-
-    // table index of each of the eight slices
-    uint32_t ix[8];
-    if constexpr (MODE == kFieldSmall) {
-      const uint32_t f_lo = acc_lo + ev_lo;
-      const uint32_t f_hi = acc_hi + ev_hi;
-#pragma unroll
-      for (int w = 0; w < 4; ++w) {
-        ix[w] = __builtin_amdgcn_ubfe(f_lo, 6 * w, 6);
-        ix[w + 4] = __builtin_amdgcn_ubfe(f_hi, 6 * w, 6);
-      }
-    } else if constexpr (MODE == kFieldMid) {
-#pragma unroll
-      for (int w = 0; w < 4; ++w) {
-        ix[w] = base - (6u * __builtin_amdgcn_ubfe(acc_lo, 6 * w, 6) + __builtin_amdgcn_ubfe(ev_lo, 6 * w, 2));
-        ix[w + 4] = base - (6u * __builtin_amdgcn_ubfe(acc_hi, 6 * w, 6) + __builtin_amdgcn_ubfe(ev_hi, 6 * w, 2));
-      }
-    } else {
-      const uint32_t sums[3] = {acc_lo, acc_hi, acc_x};
-#pragma unroll
-      for (int w = 0; w < 4; ++w) {
-        const uint32_t s0 = __builtin_amdgcn_ubfe(sums[w / 3], 8 * (w % 3), 8);
-        const uint32_t s1 = __builtin_amdgcn_ubfe(sums[(w + 4) / 3], 8 * ((w + 4) % 3), 8);
-        ix[w] = base - (6u * s0 + __builtin_amdgcn_ubfe(ev_lo, 6 * w, 2));
-        ix[w + 4] = base - (6u * s1 + __builtin_amdgcn_ubfe(ev_hi, 6 * w, 2));
-      }
-    }
-
-    // top halves of the eight thresholds (LDS reads), the second half of the
-    // Philox rounds while they are in flight, then slice k: random half k >> 2
-    // of word k & 3 against the top half of its threshold
-    const uint16_t *tab16 = reinterpret_cast<const uint16_t *>(tab);
-    uint32_t th[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) th[k] = tab16[2 * ix[k] + 1];
-    __builtin_amdgcn_sched_barrier(0);
-    philox_rounds<5>(ps);
-    __builtin_amdgcn_sched_barrier(0);
-    const Words4 u = philox_words(ps);
     uint32_t flip = 0;
-    bool tie = false;
+    if constexpr (MODE == kFieldSmall) {
+      // Byte fields, slices k = 0..3 in f_lo and 4..7 in f_hi, each holding
+      // 4 (c + 6 A + e') < 256: the byte offset of the slice's table entry.
+      // Spreads come from the second half of the spread table (bit 2 of each
+      // byte); the weighted sums are packed 16-bit multiply-adds, one 16-bit
+      // lane per two fields (every field sum stays below 256: no carries).
+      const uint2 *st8 = stab + kSpreadEntries;
+      const uint32_t r0x = r[0], r0y = r[1], r0z = r[2];
+      const u16x2 wp0 = byte_pair<0, 1>(r0y), wp1 = byte_pair<2, 3>(r0y);
+      u16x2 wh;
+      if constexpr (KIND == kKindME) wh = wp1.yy;
+      else if constexpr (KIND == kKindLHZ) wh = byte_pair<0, 0>(r0z);
+      else wh = byte_pair<2, 2>(r0z);
+      const u16x2 c4 = as_u16x2(r0x).yy;            // record base: 4c in both bytes of the high half
+      const uint2 so = st8[ox];
+      u16x2 a_lo = as_u16x2(so.x) * wh + c4;
+      u16x2 a_hi = as_u16x2(so.y) * wh + c4;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const uint32_t hi = (k < 4) ? (u.v[k] & 0xFFFFu) : (u.v[k - 4] >> 16);
-      if (hi < th[k]) flip |= 1u << k;
-      tie |= (hi == th[k]);
-    }
-    if (tie) {     // some hi equals its threshold's top half: decide all eight on the full 32 bits
-      const uint32_t c3lo = (c3 & 0xFFFFFFu) | (kStreamSQALo << 24);
-      const Words4 v = philox4x32_10(site, ctr1, m, c3lo, H.seed_lo, H.seed_hi);
-      flip = 0;
+      for (int t = 0; t < S::T; ++t) {
+        uint32_t prod = own;
+#pragma unroll
+        for (int q = 0; q < S::P; ++q) prod ^= pbyte[S::P * t + q];
+        const uint32_t x = (prod ^ (0u - ((neg >> t) & 1u))) & 0xFFu;
+        u16x2 wt;
+        if (t == 0) wt = wp0.xx;
+        else if (t == 1) wt = wp0.yy;
+        else if (t == 2) wt = wp1.xx;
+        else if (t == 3) wt = wp1.yy;
+        else if (t == 4) wt = byte_pair<0, 0>(r0z);
+        else wt = byte_pair<1, 1>(r0z);
+        const uint2 sx = st8[x];
+        a_lo = as_u16x2(sx.x) * wt + a_lo;
+        a_hi = as_u16x2(sx.y) * wt + a_hi;
+      }
+      const uint2 se1 = st8[e1], se2 = st8[e2];
+      const uint32_t f_lo = as_u32(a_lo) + se1.x + se2.x;
+      const uint32_t f_hi = as_u32(a_hi) + se1.y + se2.y;
+
+      // top halves of the eight thresholds (LDS reads), the second half of the
+      // Philox rounds while they are in flight, then slice k: D = hi - top half
+      // (hi: half k >> 2 of word k & 3), negative iff the flip is accepted on hi
+      // alone, zero on a tie; the sign bits are shifted into `flip` from slice 7
+      // down, and a tie shows as a zero minimum of the D taken unsigned
+      const uint8_t *tabb = reinterpret_cast<const uint8_t *>(tab);
+      uint32_t th[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        th[k] = *reinterpret_cast<const uint16_t *>(tabb + (((k < 4 ? f_lo : f_hi) >> (8 * (k & 3))) & 0xFFu) + 2);
+      __builtin_amdgcn_sched_barrier(0);
+      philox_rounds<5>(ps);
+      __builtin_amdgcn_sched_barrier(0);
+      const Words4 u = philox_words(ps);
+      uint32_t dmin = 0xFFFFFFFFu;
+#pragma unroll
+      for (int k = 7; k >= 0; --k) {
+        const uint32_t hi = (k < 4) ? (u.v[k] & 0xFFFFu) : (u.v[k - 4] >> 16);
+        const uint32_t D = hi - th[k];
+        flip = __builtin_amdgcn_alignbit(flip, D, 31);
+        dmin = min(dmin, D);
+      }
+      if (dmin == 0) {     // some hi equals its threshold's top half: decide all eight on the full 32 bits
+        const uint32_t c3lo = (c3 & 0xFFFFFFu) | (kStreamSQALo << 24);
+        const Words4 v = philox4x32_10(site, ctr1, m, c3lo, H.seed_lo, H.seed_hi);
+        flip = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const uint32_t fb = ((k < 4 ? f_lo : f_hi) >> (8 * (k & 3))) & 0xFFu;
+          const uint32_t R = *reinterpret_cast<const uint32_t *>(tabb + fb);
+          const uint32_t uu = (k < 4) ? ((u.v[k] << 16) | (v.v[k] & 0xFFFFu))
+                                      : ((u.v[k - 4] & 0xFFFF0000u) | (v.v[k - 4] >> 16));
+          if (min(uu, 0xFFFFFFFEu) < R) flip |= 1u << k;
+        }
+      }
+    } else {
+      const uint2 se1 = spread_of(stab, e1), se2 = spread_of(stab, e2);
+      const uint32_t ev_lo = se1.x + se2.x;
+      const uint32_t ev_hi = se1.y + se2.y;
+
+      // weighted disagreement counts, slices k = 0..3 in acc_lo and 4..7 in acc_hi
+      uint32_t acc_lo = 0, acc_hi = 0, acc_x = 0;     // kFieldLarge: slices 0-2, 3-5, 6-7
+      if constexpr (MODE == kFieldLarge) {
+        acc_lo = __umul24(spread3(ox), hw);
+        acc_hi = __umul24(spread3(ox >> 3), hw);
+        acc_x = __umul24(spread3(ox >> 6), hw);
+      } else {
+        const uint2 so = spread_of(stab, ox);
+        acc_lo = __umul24(so.x, hw);
+        acc_hi = __umul24(so.y, hw);
+      }
+#pragma unroll
+      for (int t = 0; t < S::T; ++t) {
+        uint32_t prod = own;
+#pragma unroll
+        for (int q = 0; q < S::P; ++q) prod ^= pbyte[S::P * t + q];
+        const uint32_t x = (prod ^ (0u - ((neg >> t) & 1u))) & 0xFFu;
+        const uint32_t wt = term_weight(wts, wts2, t);
+        if constexpr (MODE == kFieldLarge) {
+          acc_lo += __umul24(spread3(x), wt);
+          acc_hi += __umul24(spread3(x >> 3), wt);
+          acc_x += __umul24(spread3(x >> 6), wt);
+        } else {
+          const uint2 sx = spread_of(stab, x);
+          acc_lo += __umul24(sx.x, wt);
+          acc_hi += __umul24(sx.y, wt);
+        }
+      }
+
+      // table index of each of the eight slices
+      uint32_t ix[8];
+      if constexpr (MODE == kFieldMid) {
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+          ix[w] = base - (6u * __builtin_amdgcn_ubfe(acc_lo, 6 * w, 6) + __builtin_amdgcn_ubfe(ev_lo, 6 * w, 2));
+          ix[w + 4] = base - (6u * __builtin_amdgcn_ubfe(acc_hi, 6 * w, 6) + __builtin_amdgcn_ubfe(ev_hi, 6 * w, 2));
+        }
+      } else {
+        const uint32_t sums[3] = {acc_lo, acc_hi, acc_x};
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+          const uint32_t s0 = __builtin_amdgcn_ubfe(sums[w / 3], 8 * (w % 3), 8);
+          const uint32_t s1 = __builtin_amdgcn_ubfe(sums[(w + 4) / 3], 8 * ((w + 4) % 3), 8);
+          ix[w] = base - (6u * s0 + __builtin_amdgcn_ubfe(ev_lo, 6 * w, 2));
+          ix[w + 4] = base - (6u * s1 + __builtin_amdgcn_ubfe(ev_hi, 6 * w, 2));
+        }
+      }
+
+      // top halves of the eight thresholds (LDS reads), the second half of the
+      // Philox rounds while they are in flight, then slice k: random half k >> 2
+      // of word k & 3 against the top half of its threshold
+      const uint16_t *tab16 = reinterpret_cast<const uint16_t *>(tab);
+      uint32_t th[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) th[k] = tab16[2 * ix[k] + 1];
+      __builtin_amdgcn_sched_barrier(0);
+      philox_rounds<5>(ps);
+      __builtin_amdgcn_sched_barrier(0);
+      const Words4 u = philox_words(ps);
+      bool tie = false;
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
-        const uint32_t uu = (k < 4) ? ((u.v[k] << 16) | (v.v[k] & 0xFFFFu))
-                                    : ((u.v[k - 4] & 0xFFFF0000u) | (v.v[k - 4] >> 16));
-        if (min(uu, 0xFFFFFFFEu) < tab[ix[k]]) flip |= 1u << k;
+        const uint32_t hi = (k < 4) ? (u.v[k] & 0xFFFFu) : (u.v[k - 4] >> 16);
+        if (hi < th[k]) flip |= 1u << k;
+        tie |= (hi == th[k]);
+      }
+      if (tie) {     // some hi equals its threshold's top half: decide all eight on the full 32 bits
+        const uint32_t c3lo = (c3 & 0xFFFFFFu) | (kStreamSQALo << 24);
+        const Words4 v = philox4x32_10(site, ctr1, m, c3lo, H.seed_lo, H.seed_hi);
+        flip = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const uint32_t uu = (k < 4) ? ((u.v[k] << 16) | (v.v[k] & 0xFFFFu))
+                                      : ((u.v[k - 4] & 0xFFFF0000u) | (v.v[k - 4] >> 16));
+          if (min(uu, 0xFFFFFFFEu) < tab[ix[k]]) flip |= 1u << k;
+        }
       }
     }
     if (ragged) {            // slices beyond the parity's last one stay put
@@ -647,8 +709,11 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(SQA_WAVES_P
   // team mode (Metropolis only): the workgroup runs one replica in one lattice
   uint64_t *lat = reinterpret_cast<uint64_t *>(rec + rec_cap) + static_cast<size_t>(team ? 0 : wave) * lat_cap;
   uint32_t *tab = rec + rec_cap + 2 * (team ? 1 : waves) * lat_cap + wave * tab_cap;
-  for (int x = threadIdx.x; x < kSpreadWords / 2; x += blockDim.x)
-    stab[x] = make_uint2(spread6(static_cast<uint32_t>(x) & 0xFu), spread6(static_cast<uint32_t>(x) >> 4));
+  for (int x = threadIdx.x; x < kSpreadEntries; x += blockDim.x) {
+    const uint32_t lo = static_cast<uint32_t>(x) & 0xFu, hi = static_cast<uint32_t>(x) >> 4;
+    stab[x] = make_uint2(spread6(lo), spread6(hi));
+    stab[kSpreadEntries + x] = make_uint2(spread8(lo) << 2, spread8(hi) << 2);
+  }
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
     __syncthreads();
