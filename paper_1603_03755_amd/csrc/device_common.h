@@ -96,6 +96,14 @@ struct Site<kKindMEC> {
   static constexpr int T = 6, P = 1, RW = kRecWordsMEC, HB = kFieldSignMEC;
 };
 
+// Four record words from an 8-byte aligned address (ME records are 24 bytes
+// long, so only every other one is 16-byte aligned).
+__device__ __forceinline__ uint4 load_rec4(const uint32_t *r) {
+  const uint2 a = *reinterpret_cast<const uint2 *>(r);
+  const uint2 b = *reinterpret_cast<const uint2 *>(r + 2);
+  return make_uint4(a.x, a.y, b.x, b.y);
+}
+
 // Record of an ME-on-Chimera site: site, base, term weights, |h|, signs, partners.
 __device__ __forceinline__ void load_rec_mec(const uint32_t *r, uint32_t &site, uint32_t &base, uint32_t &wts,
                                              uint32_t &wts2, uint32_t &hw, uint32_t &neg, uint32_t *poff) {
@@ -140,13 +148,6 @@ __device__ __forceinline__ uint32_t spread8(uint32_t nib) { return __umul24(nib 
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ u16x2 as_u16x2(uint32_t x) { return __builtin_bit_cast(u16x2, x); }
 __device__ __forceinline__ uint32_t as_u32(u16x2 x) { return __builtin_bit_cast(uint32_t, x); }
-// {byte B0 of src, byte B1 of src} as two 16-bit lanes (one byte permute;
-// selector 0x0C yields a zero byte).
-template <int B0, int B1>
-__device__ __forceinline__ u16x2 byte_pair(uint32_t src) {
-  return as_u16x2(__builtin_amdgcn_perm(src, src, 0x0C000C00u | (B1 << 16) | B0));
-}
-
 // Entry x of the byte -> spread table; each word holds bits 0, 6, 12, 18 at
 // most (the assumption lets the multiplies by it be 24-bit ones).
 __device__ __forceinline__ uint2 spread_of(const uint2 *stab, uint32_t x) {

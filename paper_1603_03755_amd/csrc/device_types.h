@@ -16,12 +16,14 @@ constexpr int kKindME = 0;
 constexpr int kKindLHZ = 1;
 constexpr int kKindMEC = 2;     // ME on Chimera
 
-// Per-site records, kind-specific layouts (32-bit words):
-//  ME  (4 words, 16 B): terms T=3, one partner each
+// Per-site records, kind-specific layouts (32-bit words).  Plain layout
+// (Wolff and PT records, and SQA Metropolis records when F > kSmallF):
+//  ME  (6 words, 24 B, 8-byte aligned): terms T=3, one partner each
 //    w0 = site | base << 16
 //    w1 = |w0| | |w1| << 8 | |w2| << 16 | |h| << 24
 //    w2 = negmask | part0 << 16
 //    w3 = part1 | part2 << 16
+//    w4 = w5 = 0
 //  (part = byte offset 8*d of the partner's lattice word)
 //  LHZ (12 words, 48 B): terms T=4, three partners each (a 3-body term's
 //  third partner is the zero word)
@@ -39,16 +41,28 @@ constexpr int kKindMEC = 2;     // ME on Chimera
 // negmask bit t (t < T): weight of term t is negative; h < 0 is bit 4 (ME,
 // LHZ) or bit 6 (ME on Chimera).
 // base = 3 * (F_site + F) + 2, F_site = |h| + sum |w_t|.
-// Weights |w|, |h| in the records are stored multiplied by 6 when F <= kSmallF
-// (the sweep kernel then indexes the table with the field sums directly), and
-// base is then 4c | 4c << 8 with c = 3 (F - F_site).
+//
+// Small-field layout (SQA Metropolis records when F <= kSmallF): the sweep
+// kernel sums, per slice, c + 6 A + e' (A: weight of the terms that agree
+// with their sign, e': agreeing time neighbours, c = 3 (F - F_site)), which
+// is the table index itself.  Term t contributes 6|w_t| where its product
+// agrees; written with y = the plain product bit (own spin ^ partners) this
+// is 6|w_t| y for w_t < 0 and 6|w_t| - 6|w_t| y for w_t > 0 (likewise h with
+// y = the own spin bit).  The records carry the signed 16-bit weights
+// W = -6|w| (mod 2^16) or +6|w| and fold the constants into
+// c' = c + sum over positive weights of 6|w|:
+//    w0 = site | (4c' | 4c' << 8) << 16
+//  ME:  w1 = W0 | W1 << 16, w2 = W2 | Wh << 16, w3 = part0 | part1 << 16,
+//       w4 = part2, w5 = 0
+//  LHZ: w1 = W0 | W1 << 16, w2 = W2 | W3 << 16, w3 = Wh, w4..w9 as above
+//  ME on Chimera: w1..w3 = W0..W5 as pairs, w4 = Wh, w5..w7 = part[0..5]
 constexpr int kSmallF = 10;
 // Largest per-site field sum of the 6-bit-field sweep path, and of the library.
 constexpr int kMidF = 63;
 constexpr int kLargeF = 255;
 // Field modes of the sweep kernels (see sweep_class).
 constexpr int kFieldSmall = 0, kFieldMid = 1, kFieldLarge = 2;
-constexpr int kRecWordsME = 4;
+constexpr int kRecWordsME = 6;
 constexpr int kRecWordsLHZ = 12;
 constexpr int kRecWordsMEC = 8;
 constexpr int kFieldSignMEC = 6;

@@ -180,20 +180,42 @@ sqa_status build_layout(const Embedded &emb, int32_t F, bool scale6, DeviceLayou
     }
     if (emb.h[k] < 0) neg |= 1u << (mec ? kFieldSignMEC : 4);
     uint32_t ah = static_cast<uint32_t>(std::abs(emb.h[k]));
-    uint32_t base = static_cast<uint32_t>(3 * (fs + F) + 2);
-    if (scale6 && F <= kSmallF) {
-      // The sweep kernel's small-field mode sums 6|w| over the terms that AGREE
-      // with their sign (flipped sign bits) on top of c = 3 (F - F_site); with the
-      // agreeing time neighbours e' this gives c + 6 A + e' = base - (6 S + e).
-      // The kernel keeps 4 (c + 6 A + e') per byte, so base carries 4c twice.
-      for (int a = 0; a < 6; ++a) aw[a] *= 6u;
-      ah *= 6u;
-      const uint32_t hbit = 1u << (mec ? kFieldSignMEC : 4);
-      neg ^= ((1u << T) - 1u) | hbit;
-      const uint32_t c = static_cast<uint32_t>(3 * (F - fs));   // at most 30: 4c fits a byte
-      base = (4u * c) | ((4u * c) << 8);
-    }
     uint32_t *r = &L.rec[static_cast<size_t>(d) * L.rec_words];
+    if (scale6 && F <= kSmallF) {
+      // Small-field layout: signed 16-bit weights of the plain product bits,
+      // the constants of the positive weights folded into c' (at most
+      // 3 F + 3 F_site <= 60, so 4c' fits a byte).
+      uint32_t W[7];
+      int32_t cc = 3 * (F - fs);
+      for (int a = 0; a < T; ++a) {
+        const bool pos = !((neg >> a) & 1u);     // also unused slots (weight 0)
+        W[a] = pos ? ((0x10000u - 6u * aw[a]) & 0xFFFFu) : 6u * aw[a];
+        if (pos) cc += static_cast<int32_t>(6u * aw[a]);
+      }
+      const bool hpos = emb.h[k] >= 0;
+      W[T] = hpos ? ((0x10000u - 6u * ah) & 0xFFFFu) : 6u * ah;
+      if (hpos) cc += static_cast<int32_t>(6u * ah);
+      const uint32_t c4 = 4u * static_cast<uint32_t>(cc);
+      r[0] = static_cast<uint32_t>(k) | ((c4 | (c4 << 8)) << 16);
+      if (me) {
+        r[1] = W[0] | (W[1] << 16);
+        r[2] = W[2] | (W[3] << 16);
+        r[3] = part[0] | (part[1] << 16);
+        r[4] = part[2];
+      } else if (mec) {
+        for (int q = 0; q < 3; ++q) r[1 + q] = W[2 * q] | (W[2 * q + 1] << 16);
+        r[4] = W[6];
+        for (int q = 0; q < 3; ++q) r[5 + q] = part[2 * q] | (part[2 * q + 1] << 16);
+      } else {
+        r[1] = W[0] | (W[1] << 16);
+        r[2] = W[2] | (W[3] << 16);
+        r[3] = W[4];
+        for (int q = 0; q < 6; ++q) r[4 + q] = part[2 * q] | (part[2 * q + 1] << 16);
+      }
+      L.hfield[d] = emb.h[k];
+      continue;
+    }
+    const uint32_t base = static_cast<uint32_t>(3 * (fs + F) + 2);
     r[0] = static_cast<uint32_t>(k) | (base << 16);
     if (me) {
       r[1] = aw[0] | (aw[1] << 8) | (aw[2] << 16) | (ah << 24);

@@ -54,7 +54,7 @@ __device__ __forceinline__ void flush_deltas(int32_t *dE, int32_t *E, int a, int
   for (int w = 0; w < 8; ++w) dE[w] = 0;
 }
 
-// Raw record words of one site (4 words ME, 10 LHZ, 6 ME on Chimera).
+// Raw record words of one site (4 of the 6 words ME, 10 LHZ, 6 ME on Chimera).
 template <int KIND> struct PTRec;
 template <> struct PTRec<kKindME> { uint4 a; };
 template <> struct PTRec<kKindLHZ> { uint4 a, b; uint2 c; };
@@ -64,7 +64,7 @@ template <int KIND>
 __device__ __forceinline__ PTRec<KIND> load_pt_rec(const uint32_t *r) {
   PTRec<KIND> x;
   if constexpr (KIND == kKindME) {
-    x.a = *reinterpret_cast<const uint4 *>(r);
+    x.a = load_rec4(r);     // 24-byte records: 8-byte aligned
   } else if constexpr (KIND == kKindMEC) {
     x.a = *reinterpret_cast<const uint4 *>(r);
     x.b = *reinterpret_cast<const uint2 *>(r + 4);

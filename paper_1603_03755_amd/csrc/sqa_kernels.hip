@@ -158,10 +158,47 @@ __device__ __forceinline__ void sweep_class(const HandleDev &H, const uint32_t *
     const int d = lo + j;
     const uint32_t *r = rec + d * S::RW;
 
-    uint32_t site, base, wts, wts2 = 0, hw, neg;
+    uint32_t site, base = 0, wts = 0, wts2 = 0, hw = 0, neg = 0;
     uint32_t poff[S::T * S::P];
-    if constexpr (KIND == kKindME) {
-      const uint4 r0 = *reinterpret_cast<const uint4 *>(r);
+    uint32_t wsg[S::T + 1] = {};     // small-field layout: record words holding the signed weights
+    int wsh[S::T + 1] = {};          // and the half (0 low, 1 high) of each
+    uint32_t c4w = 0;                // its word 0 (4c' in both bytes of the high half)
+    if constexpr (MODE == kFieldSmall) {
+      const uint4 r0 = load_rec4(r);
+      site = r0.x & 0xFFFFu;
+      c4w = r0.x;
+      if constexpr (KIND == kKindME) {
+        const uint32_t r4 = r[4];
+        const uint32_t ws[4] = {r0.y, r0.y, r0.z, r0.z};
+#pragma unroll
+        for (int t = 0; t < 4; ++t) { wsg[t] = ws[t]; wsh[t] = t & 1; }
+        poff[0] = r0.w & 0xFFFFu; poff[1] = r0.w >> 16; poff[2] = r4 & 0xFFFFu;
+      } else if constexpr (KIND == kKindMEC) {
+        const uint4 r1 = load_rec4(r + 4);
+        const uint32_t ws[7] = {r0.y, r0.y, r0.z, r0.z, r0.w, r0.w, r1.x};
+#pragma unroll
+        for (int t = 0; t < 7; ++t) { wsg[t] = ws[t]; wsh[t] = t & 1; }
+        const uint32_t pw[3] = {r1.y, r1.z, r1.w};
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          poff[2 * q] = pw[q] & 0xFFFFu;
+          poff[2 * q + 1] = pw[q] >> 16;
+        }
+      } else {
+        const uint4 r1 = load_rec4(r + 4);
+        const uint2 r2 = *reinterpret_cast<const uint2 *>(r + 8);
+        const uint32_t ws[5] = {r0.y, r0.y, r0.z, r0.z, r0.w};
+#pragma unroll
+        for (int t = 0; t < 5; ++t) { wsg[t] = ws[t]; wsh[t] = t & 1; }
+        const uint32_t pw[6] = {r1.x, r1.y, r1.z, r1.w, r2.x, r2.y};
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+          poff[2 * q] = pw[q] & 0xFFFFu;
+          poff[2 * q + 1] = pw[q] >> 16;
+        }
+      }
+    } else if constexpr (KIND == kKindME) {
+      const uint4 r0 = load_rec4(r);
       site = r0.x & 0xFFFFu; base = r0.x >> 16;
       wts = r0.y & 0xFFFFFFu;
       hw = r0.y >> 24;
@@ -234,35 +271,30 @@ __device__ __forceinline__ void sweep_class(const HandleDev &H, const uint32_t *
       // Byte fields, slices k = 0..3 in f_lo and 4..7 in f_hi, each holding
       // 4 (c + 6 A + e') < 256: the byte offset of the slice's table entry.
       // Spreads come from the second half of the spread table (bit 2 of each
-      // byte); the weighted sums are packed 16-bit multiply-adds, one 16-bit
-      // lane per two fields (every field sum stays below 256: no carries).
+      // byte) and are indexed by the plain product bits (own ^ partners; the
+      // own spin for h); the records' signed 16-bit weights and constant c'
+      // turn them into agreement sums.  The sums are packed 16-bit
+      // multiply-adds, one 16-bit lane per two fields, exact modulo 2^16 per
+      // lane: every final field lies in [0, 256), so the lane values, and the
+      // 32-bit additions of the time-neighbour spreads after them, carry
+      // nothing between fields.
       const uint2 *st8 = stab + kSpreadEntries;
-      const uint32_t r0x = r[0], r0y = r[1], r0z = r[2];
-      const u16x2 wp0 = byte_pair<0, 1>(r0y), wp1 = byte_pair<2, 3>(r0y);
-      u16x2 wh;
-      if constexpr (KIND == kKindME) wh = wp1.yy;
-      else if constexpr (KIND == kKindLHZ) wh = byte_pair<0, 0>(r0z);
-      else wh = byte_pair<2, 2>(r0z);
-      const u16x2 c4 = as_u16x2(r0x).yy;            // record base: 4c in both bytes of the high half
-      const uint2 so = st8[ox];
-      u16x2 a_lo = as_u16x2(so.x) * wh + c4;
-      u16x2 a_hi = as_u16x2(so.y) * wh + c4;
+      auto wsel = [&](int t) {
+        const u16x2 w = as_u16x2(wsg[t]);
+        return wsh[t] ? w.yy : w.xx;
+      };
+      const u16x2 c4 = as_u16x2(c4w).yy;
+      const uint2 so = st8[own];
+      u16x2 a_lo = as_u16x2(so.x) * wsel(S::T) + c4;
+      u16x2 a_hi = as_u16x2(so.y) * wsel(S::T) + c4;
 #pragma unroll
       for (int t = 0; t < S::T; ++t) {
         uint32_t prod = own;
 #pragma unroll
         for (int q = 0; q < S::P; ++q) prod ^= pbyte[S::P * t + q];
-        const uint32_t x = (prod ^ (0u - ((neg >> t) & 1u))) & 0xFFu;
-        u16x2 wt;
-        if (t == 0) wt = wp0.xx;
-        else if (t == 1) wt = wp0.yy;
-        else if (t == 2) wt = wp1.xx;
-        else if (t == 3) wt = wp1.yy;
-        else if (t == 4) wt = byte_pair<0, 0>(r0z);
-        else wt = byte_pair<1, 1>(r0z);
-        const uint2 sx = st8[x];
-        a_lo = as_u16x2(sx.x) * wt + a_lo;
-        a_hi = as_u16x2(sx.y) * wt + a_hi;
+        const uint2 sx = st8[prod];
+        a_lo = as_u16x2(sx.x) * wsel(t) + a_lo;
+        a_hi = as_u16x2(sx.y) * wsel(t) + a_hi;
       }
       const uint2 se1 = st8[e1], se2 = st8[e2];
       const uint32_t f_lo = as_u32(a_lo) + se1.x + se2.x;
@@ -517,7 +549,7 @@ __device__ __forceinline__ void wolff_bonds(const HandleDev &H, const uint32_t *
     uint32_t site, wts, wts2 = 0, hw, neg;
     uint32_t poff[S::T * S::P];
     if constexpr (KIND == kKindME) {
-      const uint4 r0 = *reinterpret_cast<const uint4 *>(r);
+      const uint4 r0 = load_rec4(r);
       site = r0.x & 0xFFFFu;
       wts = r0.y & 0xFFFFFFu;
       hw = r0.y >> 24;
@@ -637,7 +669,7 @@ __device__ __forceinline__ void wolff_flips(const HandleDev &H, const uint32_t *
   const uint32_t *sb = scr + 2 * nc;
   for (int j = lane; j < nc; j += 64) {
     const int d = lo + j;
-    const uint4 r0 = *reinterpret_cast<const uint4 *>(rec + d * S::RW);
+    const uint4 r0 = load_rec4(rec + d * S::RW);
     const uint32_t site = r0.x & 0xFFFFu;
     // F_site = |h| + sum |w_t|: the bytes of record word 1 (and, for LHZ, |h|)
     // (ME: w0..w2, |h|; LHZ: w0..w3 then |h|; ME on Chimera: w0..w3 then w4, w5, |h|)
