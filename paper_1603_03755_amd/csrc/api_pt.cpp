@@ -146,7 +146,7 @@ sqa_status pt_create(const sqa_problem *problem, const sqa_embedding *embedding,
   pt_handle *h = new (std::nothrow) pt_handle();
   if (!h) return fail(SQA_ERR_OOM, "host allocation");
   sqa_status st = build_embedding(*problem, *embedding, &h->emb);
-  if (st == SQA_OK) st = build_layout(h->emb, h->emb.fmax, false, &h->lay);
+  if (st == SQA_OK) st = build_layout(h->emb, h->emb.fmax, kLayoutPlain, &h->lay);
   if (st != SQA_OK) {
     delete h;
     return st;

@@ -323,7 +323,7 @@ sqa_status sqa_create(const sqa_problem *problem, const sqa_embedding *embedding
     std::copy(problem->h, problem->h + h->N, h->h.begin());
   }
   // Wolff moves sum plain weights per slice; Metropolis records carry 6|w| when F is small
-  st = build_layout(h->emb, h->F, h->move != kMoveWolff, &h->lay);
+  st = build_layout(h->emb, h->F, h->move == kMoveWolff ? kLayoutWolff : kLayoutMetropolis, &h->lay);
   if (st != SQA_OK) {
     delete h;
     return st;

@@ -42,20 +42,23 @@ constexpr int kKindMEC = 2;     // ME on Chimera
 // LHZ) or bit 6 (ME on Chimera).
 // base = 3 * (F_site + F) + 2, F_site = |h| + sum |w_t|.
 //
-// Small-field layout (SQA Metropolis records when F <= kSmallF): the sweep
-// kernel sums, per slice, c + 6 A + e' (A: weight of the terms that agree
-// with their sign, e': agreeing time neighbours, c = 3 (F - F_site)), which
-// is the table index itself.  Term t contributes 6|w_t| where its product
-// agrees; written with y = the plain product bit (own spin ^ partners) this
-// is 6|w_t| y for w_t < 0 and 6|w_t| - 6|w_t| y for w_t > 0 (likewise h with
-// y = the own spin bit).  The records carry the signed 16-bit weights
-// W = -6|w| (mod 2^16) or +6|w| and fold the constants into
-// c' = c + sum over positive weights of 6|w|:
+// Signed-weight layouts (SQA Metropolis records when F <= kSmallF, Wolff
+// records when F <= kMidF): each term t (and h) enters its site's per-slice sum
+// as W_t y_t plus a constant, y_t being the plain product bit (own spin ^
+// partners; the own spin for h).  Metropolis: the sum is c + 6 A (A: weight of
+// the terms whose product bit equals their sign bit, c = 3 (F - F_site)), the
+// table index itself; W = -6|w| (its 6|w| in the constant c') for w >= 0 and
+// +6|w| for w < 0.  Wolff: the sum is S = sum |w| X (X: the product bit
+// differs from the sign bit); W = +|w| for w >= 0 and -|w| (|w| in c') for
+// w < 0.  W is stored modulo 2^16; the kernels keep 4 (c' + sum W y) per byte.
 //    w0 = site | (4c' | 4c' << 8) << 16
 //  ME:  w1 = W0 | W1 << 16, w2 = W2 | Wh << 16, w3 = part0 | part1 << 16,
-//       w4 = part2, w5 = 0
-//  LHZ: w1 = W0 | W1 << 16, w2 = W2 | W3 << 16, w3 = Wh, w4..w9 as above
-//  ME on Chimera: w1..w3 = W0..W5 as pairs, w4 = Wh, w5..w7 = part[0..5]
+//       w4 = part2 | X << 16, w5 = 0
+//  LHZ: w1 = W0 | W1 << 16, w2 = W2 | W3 << 16, w3 = Wh | X << 16, w4..w9 as
+//       above
+//  ME on Chimera: w1..w3 = W0..W5 as pairs, w4 = Wh | X << 16, w5..w7 =
+//       part[0..5]
+//  X = F_site for Wolff records, 0 for Metropolis records.
 constexpr int kSmallF = 10;
 // Largest per-site field sum of the 6-bit-field sweep path, and of the library.
 constexpr int kMidF = 63;

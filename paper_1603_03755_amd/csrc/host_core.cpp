@@ -136,7 +136,7 @@ sqa_status build_embedding(const sqa_problem &p, const sqa_embedding &em, Embedd
   return SQA_OK;
 }
 
-sqa_status build_layout(const Embedded &emb, int32_t F, bool scale6, DeviceLayout *out) {
+sqa_status build_layout(const Embedded &emb, int32_t F, RecordLayout layout, DeviceLayout *out) {
   DeviceLayout L;
   const int32_t n = emb.n;
   const bool me = emb.kind == SQA_EMB_ME, mec = emb.kind == SQA_EMB_ME_CHIMERA;
@@ -181,35 +181,45 @@ sqa_status build_layout(const Embedded &emb, int32_t F, bool scale6, DeviceLayou
     if (emb.h[k] < 0) neg |= 1u << (mec ? kFieldSignMEC : 4);
     uint32_t ah = static_cast<uint32_t>(std::abs(emb.h[k]));
     uint32_t *r = &L.rec[static_cast<size_t>(d) * L.rec_words];
-    if (scale6 && F <= kSmallF) {
-      // Small-field layout: signed 16-bit weights of the plain product bits,
-      // the constants of the positive weights folded into c' (at most
-      // 3 F + 3 F_site <= 60, so 4c' fits a byte).
+    const bool metro = layout == kLayoutMetropolis && F <= kSmallF;
+    const bool wolff = layout == kLayoutWolff && F <= kMidF;
+    if (metro || wolff) {
+      // Signed-weight layout: each term (and h) enters as W y with y the plain
+      // product bit (own spin ^ partners; the own spin for h), and a constant.
+      // Metropolis (small fields): the sum is c + 6 A (A: agreeing weight,
+      // c = 3 (F - F_site)); a term agrees when its product bit equals its sign
+      // bit, so W = -6|w| and the constant takes 6|w| where w >= 0, W = +6|w|
+      // where w < 0.  c' <= 3 F + 3 F_site <= 60.
+      // Wolff: the sum is S = sum |w| X (X: the term disagrees, its product bit
+      // differs from its sign bit), so W = +|w| where w >= 0 and W = -|w|, with
+      // |w| in the constant, where w < 0.  c' <= F_site <= 63.
+      // The kernels accumulate 4 (c' + sum W y) per byte, so 4c' fits a byte.
+      const uint32_t s = metro ? 6u : 1u;
       uint32_t W[7];
-      int32_t cc = 3 * (F - fs);
-      for (int a = 0; a < T; ++a) {
-        const bool pos = !((neg >> a) & 1u);     // also unused slots (weight 0)
-        W[a] = pos ? ((0x10000u - 6u * aw[a]) & 0xFFFFu) : 6u * aw[a];
-        if (pos) cc += static_cast<int32_t>(6u * aw[a]);
-      }
-      const bool hpos = emb.h[k] >= 0;
-      W[T] = hpos ? ((0x10000u - 6u * ah) & 0xFFFFu) : 6u * ah;
-      if (hpos) cc += static_cast<int32_t>(6u * ah);
+      int32_t cc = metro ? 3 * (F - fs) : 0;
+      auto put = [&](uint32_t a, bool negative_weight, int slot) {
+        const bool flip = metro ? !negative_weight : negative_weight;   // weight enters as s|w| (1 - y)
+        W[slot] = flip ? ((0x10000u - s * a) & 0xFFFFu) : s * a;
+        if (flip) cc += static_cast<int32_t>(s * a);
+      };
+      for (int a = 0; a < T; ++a) put(aw[a], (neg >> a) & 1u, a);
+      put(ah, emb.h[k] < 0, T);
       const uint32_t c4 = 4u * static_cast<uint32_t>(cc);
+      const uint32_t fsh = metro ? 0u : (static_cast<uint32_t>(fs) << 16);   // Wolff: F_site
       r[0] = static_cast<uint32_t>(k) | ((c4 | (c4 << 8)) << 16);
       if (me) {
         r[1] = W[0] | (W[1] << 16);
         r[2] = W[2] | (W[3] << 16);
         r[3] = part[0] | (part[1] << 16);
-        r[4] = part[2];
+        r[4] = part[2] | fsh;
       } else if (mec) {
         for (int q = 0; q < 3; ++q) r[1 + q] = W[2 * q] | (W[2 * q + 1] << 16);
-        r[4] = W[6];
+        r[4] = W[6] | fsh;
         for (int q = 0; q < 3; ++q) r[5 + q] = part[2 * q] | (part[2 * q + 1] << 16);
       } else {
         r[1] = W[0] | (W[1] << 16);
         r[2] = W[2] | (W[3] << 16);
-        r[3] = W[4];
+        r[3] = W[4] | fsh;
         for (int q = 0; q < 6; ++q) r[4 + q] = part[2 * q] | (part[2 * q + 1] << 16);
       }
       L.hfield[d] = emb.h[k];

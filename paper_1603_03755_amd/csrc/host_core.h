@@ -50,8 +50,13 @@ struct DeviceLayout {
   int32_t cls[5] = {0, 0, 0, 0, 0};
 };
 
-// scale6: store 6|w| and 6|h| when F <= kSmallF (SQA records; PT uses plain weights).
-sqa_status build_layout(const Embedded &emb, int32_t F, bool scale6, DeviceLayout *out);
+// Record layouts (the word layouts are documented with the kernel structures):
+// kLayoutPlain: byte weights and sign masks (PT; SQA records whose kernel path
+// takes them); kLayoutMetropolis: the signed-weight small-field layout when
+// F <= kSmallF, else plain; kLayoutWolff: the signed-weight layout of the
+// Wolff bond phase when F <= kMidF, else plain.
+enum RecordLayout { kLayoutPlain = 0, kLayoutMetropolis = 1, kLayoutWolff = 2 };
+sqa_status build_layout(const Embedded &emb, int32_t F, RecordLayout layout, DeviceLayout *out);
 
 // ---------------------------------------------------------- tables
 uint32_t threshold_from_log(double x);

@@ -100,6 +100,94 @@ __device__ __forceinline__ void slice_energies(const HandleDev &H, const uint64_
   H.energy[static_cast<size_t>(rep) * H.L + tau] = E;
 }
 
+// ------------------------------------------------- signed-weight records
+// Site record in the signed-weight layout (Metropolis records with F <= 10,
+// Wolff records with F <= 63): the site, record word 0 (4c' in both bytes of
+// its high half), for each weight (terms, then h) the record word holding it
+// and its half, the partners' byte offsets, and the high half of the word
+// after the weights (F_site in Wolff records).
+template <int KIND>
+struct SignedRec {
+  static constexpr int NW = Site<KIND>::T + 1, NP = Site<KIND>::T * Site<KIND>::P;
+  uint32_t site, c4w, xtra;
+  uint32_t wsg[NW];
+  int wsh[NW];
+  uint32_t poff[NP];
+  // term t's weight (t = T: h's) in both 16-bit lanes
+  __device__ __forceinline__ u16x2 weight(int t) const {
+    const u16x2 w = as_u16x2(wsg[t]);
+    return wsh[t] ? w.yy : w.xx;
+  }
+  // 4c' in all four bytes, as two 16-bit lanes
+  __device__ __forceinline__ u16x2 c4() const { return as_u16x2(c4w).yy; }
+};
+
+template <int KIND>
+__device__ __forceinline__ SignedRec<KIND> load_signed_rec(const uint32_t *r) {
+  SignedRec<KIND> x;
+  const uint4 r0 = load_rec4(r);
+  x.site = r0.x & 0xFFFFu;
+  x.c4w = r0.x;
+  if constexpr (KIND == kKindME) {
+    const uint32_t r4 = r[4];
+    const uint32_t ws[4] = {r0.y, r0.y, r0.z, r0.z};
+#pragma unroll
+    for (int t = 0; t < 4; ++t) { x.wsg[t] = ws[t]; x.wsh[t] = t & 1; }
+    x.poff[0] = r0.w & 0xFFFFu; x.poff[1] = r0.w >> 16; x.poff[2] = r4 & 0xFFFFu;
+    x.xtra = r4 >> 16;
+  } else if constexpr (KIND == kKindMEC) {
+    const uint4 r1 = load_rec4(r + 4);
+    const uint32_t ws[7] = {r0.y, r0.y, r0.z, r0.z, r0.w, r0.w, r1.x};
+#pragma unroll
+    for (int t = 0; t < 7; ++t) { x.wsg[t] = ws[t]; x.wsh[t] = t & 1; }
+    x.xtra = r1.x >> 16;
+    const uint32_t pw[3] = {r1.y, r1.z, r1.w};
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      x.poff[2 * q] = pw[q] & 0xFFFFu;
+      x.poff[2 * q + 1] = pw[q] >> 16;
+    }
+  } else {
+    const uint4 r1 = load_rec4(r + 4);
+    const uint2 r2 = *reinterpret_cast<const uint2 *>(r + 8);
+    const uint32_t ws[5] = {r0.y, r0.y, r0.z, r0.z, r0.w};
+#pragma unroll
+    for (int t = 0; t < 5; ++t) { x.wsg[t] = ws[t]; x.wsh[t] = t & 1; }
+    x.xtra = r0.w >> 16;
+    const uint32_t pw[6] = {r1.x, r1.y, r1.z, r1.w, r2.x, r2.y};
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      x.poff[2 * q] = pw[q] & 0xFFFFu;
+      x.poff[2 * q + 1] = pw[q] >> 16;
+    }
+  }
+  return x;
+}
+
+// 4 (c' + sum_t W_t y_t + W_h own) of the eight slices of one byte, slices
+// 0..3 in the bytes of .x and 4..7 in .y: packed 16-bit multiply-adds of the
+// spreads (bit 2 of each byte, second half of the spread table) of the plain
+// product bytes.  Exact modulo 2^16 per lane; the caller's sums lie in [0, 256)
+// per byte, so the lanes hold them without carries between bytes.
+template <int KIND>
+__device__ __forceinline__ uint2 signed_sums(const SignedRec<KIND> &x, const uint2 *st8, uint32_t own,
+                                             const uint32_t *pbyte) {
+  using S = Site<KIND>;
+  const uint2 so = st8[own];
+  u16x2 a_lo = as_u16x2(so.x) * x.weight(S::T) + x.c4();
+  u16x2 a_hi = as_u16x2(so.y) * x.weight(S::T) + x.c4();
+#pragma unroll
+  for (int t = 0; t < S::T; ++t) {
+    uint32_t prod = own;
+#pragma unroll
+    for (int q = 0; q < S::P; ++q) prod ^= pbyte[S::P * t + q];
+    const uint2 sx = st8[prod];
+    a_lo = as_u16x2(sx.x) * x.weight(t) + a_lo;
+    a_hi = as_u16x2(sx.y) * x.weight(t) + a_hi;
+  }
+  return make_uint2(as_u32(a_lo), as_u32(a_hi));
+}
+
 // ------------------------------------------------------------ SQA sweep
 // Item loop over one (slice parity p, colour c) class of one replica, by the
 // nthr threads of its team (one wave, or the whole workgroup).
@@ -160,43 +248,12 @@ __device__ __forceinline__ void sweep_class(const HandleDev &H, const uint32_t *
 
     uint32_t site, base = 0, wts = 0, wts2 = 0, hw = 0, neg = 0;
     uint32_t poff[S::T * S::P];
-    uint32_t wsg[S::T + 1] = {};     // small-field layout: record words holding the signed weights
-    int wsh[S::T + 1] = {};          // and the half (0 low, 1 high) of each
-    uint32_t c4w = 0;                // its word 0 (4c' in both bytes of the high half)
+    SignedRec<KIND> sr;
     if constexpr (MODE == kFieldSmall) {
-      const uint4 r0 = load_rec4(r);
-      site = r0.x & 0xFFFFu;
-      c4w = r0.x;
-      if constexpr (KIND == kKindME) {
-        const uint32_t r4 = r[4];
-        const uint32_t ws[4] = {r0.y, r0.y, r0.z, r0.z};
+      sr = load_signed_rec<KIND>(r);
+      site = sr.site;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) { wsg[t] = ws[t]; wsh[t] = t & 1; }
-        poff[0] = r0.w & 0xFFFFu; poff[1] = r0.w >> 16; poff[2] = r4 & 0xFFFFu;
-      } else if constexpr (KIND == kKindMEC) {
-        const uint4 r1 = load_rec4(r + 4);
-        const uint32_t ws[7] = {r0.y, r0.y, r0.z, r0.z, r0.w, r0.w, r1.x};
-#pragma unroll
-        for (int t = 0; t < 7; ++t) { wsg[t] = ws[t]; wsh[t] = t & 1; }
-        const uint32_t pw[3] = {r1.y, r1.z, r1.w};
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-          poff[2 * q] = pw[q] & 0xFFFFu;
-          poff[2 * q + 1] = pw[q] >> 16;
-        }
-      } else {
-        const uint4 r1 = load_rec4(r + 4);
-        const uint2 r2 = *reinterpret_cast<const uint2 *>(r + 8);
-        const uint32_t ws[5] = {r0.y, r0.y, r0.z, r0.z, r0.w};
-#pragma unroll
-        for (int t = 0; t < 5; ++t) { wsg[t] = ws[t]; wsh[t] = t & 1; }
-        const uint32_t pw[6] = {r1.x, r1.y, r1.z, r1.w, r2.x, r2.y};
-#pragma unroll
-        for (int q = 0; q < 6; ++q) {
-          poff[2 * q] = pw[q] & 0xFFFFu;
-          poff[2 * q + 1] = pw[q] >> 16;
-        }
-      }
+      for (int q = 0; q < S::T * S::P; ++q) poff[q] = sr.poff[q];
     } else if constexpr (KIND == kKindME) {
       const uint4 r0 = load_rec4(r);
       site = r0.x & 0xFFFFu; base = r0.x >> 16;
@@ -270,35 +327,14 @@ __device__ __forceinline__ void sweep_class(const HandleDev &H, const uint32_t *
     if constexpr (MODE == kFieldSmall) {
       // Byte fields, slices k = 0..3 in f_lo and 4..7 in f_hi, each holding
       // 4 (c + 6 A + e') < 256: the byte offset of the slice's table entry.
-      // Spreads come from the second half of the spread table (bit 2 of each
-      // byte) and are indexed by the plain product bits (own ^ partners; the
-      // own spin for h); the records' signed 16-bit weights and constant c'
-      // turn them into agreement sums.  The sums are packed 16-bit
-      // multiply-adds, one 16-bit lane per two fields, exact modulo 2^16 per
-      // lane: every final field lies in [0, 256), so the lane values, and the
-      // 32-bit additions of the time-neighbour spreads after them, carry
-      // nothing between fields.
+      // 4 (c + 6 A) comes from the signed-weight record; the spreads of the
+      // agreeing time neighbours are added as plain 32-bit sums (no field
+      // reaches 256, so nothing carries between fields).
       const uint2 *st8 = stab + kSpreadEntries;
-      auto wsel = [&](int t) {
-        const u16x2 w = as_u16x2(wsg[t]);
-        return wsh[t] ? w.yy : w.xx;
-      };
-      const u16x2 c4 = as_u16x2(c4w).yy;
-      const uint2 so = st8[own];
-      u16x2 a_lo = as_u16x2(so.x) * wsel(S::T) + c4;
-      u16x2 a_hi = as_u16x2(so.y) * wsel(S::T) + c4;
-#pragma unroll
-      for (int t = 0; t < S::T; ++t) {
-        uint32_t prod = own;
-#pragma unroll
-        for (int q = 0; q < S::P; ++q) prod ^= pbyte[S::P * t + q];
-        const uint2 sx = st8[prod];
-        a_lo = as_u16x2(sx.x) * wsel(t) + a_lo;
-        a_hi = as_u16x2(sx.y) * wsel(t) + a_hi;
-      }
+      const uint2 a = signed_sums<KIND>(sr, st8, own, pbyte);
       const uint2 se1 = st8[e1], se2 = st8[e2];
-      const uint32_t f_lo = as_u32(a_lo) + se1.x + se2.x;
-      const uint32_t f_hi = as_u32(a_hi) + se1.y + se2.y;
+      const uint32_t f_lo = a.x + se1.x + se2.x;
+      const uint32_t f_hi = a.y + se1.y + se2.y;
 
       // top halves of the eight thresholds (LDS reads), the second half of the
       // Philox rounds while they are in flight, then slice k: D = hi - top half
@@ -494,10 +530,10 @@ __device__ __forceinline__ void anneal_replica(const HandleDev &H, const uint32_
 //     passes the sweep's join threshold; hi is half k >> 2 of word k & 3 of
 //     the WOLFF call with counter word 1 = q, lo the same from the WOLFF_LO
 //     call, drawn only on a tie of hi with the threshold's top half.  The
-//     item also forms, per slice, the weighted
-//     disagreement sum S = sum_t |w_t| X_t + |h| O (as in the Metropolis
-//     kernel; s f = F_site - 2 S) as one byte per slice.  Join bits and S bytes
-//     go to the wave's LDS scratch.
+//     item also forms, per slice, the weighted disagreement sum
+//     S = sum_t |w_t| X_t + |h| O (s f = F_site - 2 S) as one byte per slice:
+//     4 S from the signed-weight record when F <= 63, else S from the plain
+//     record.  Join bits and S bytes go to the wave's LDS scratch.
 //  2. one lane per site: the seed slice tau0 = floor(u L / 2^32) and the
 //     acceptance word (counter word 1 = 64); the cluster is the run of joined
 //     bonds through tau0 (ring rotation, trailing and leading ones); with
@@ -507,12 +543,6 @@ __device__ __forceinline__ void anneal_replica(const HandleDev &H, const uint32_
 // Sites of one class share no term, so their moves commute and every read in
 // phase 1 sees the state left by the previous class.  Large classes are
 // processed in chunks of kWolffChunk sites.
-
-// Four 6-bit fields (bits 0, 6, 12, 18) moved to the four bytes of a word.
-__device__ __forceinline__ uint32_t fields6_to_bytes(uint32_t a) {
-  return __builtin_amdgcn_ubfe(a, 0, 6) | (__builtin_amdgcn_ubfe(a, 6, 6) << 8) |
-         (__builtin_amdgcn_ubfe(a, 12, 6) << 16) | (__builtin_amdgcn_ubfe(a, 18, 6) << 24);
-}
 
 // Cluster through slice t0 of a ring of L slices whose joined bonds are the
 // bits of jn (bit b: slices b and b+1 mod L; bits L..63 are ignored).
@@ -546,9 +576,15 @@ __device__ __forceinline__ void wolff_bonds(const HandleDev &H, const uint32_t *
     if (j >= nc) { j -= nc; q += 1; }
     const int d = lo + j;
     const uint32_t *r = rec + d * S::RW;
-    uint32_t site, wts, wts2 = 0, hw, neg;
+    uint32_t site, wts = 0, wts2 = 0, hw = 0, neg = 0;
     uint32_t poff[S::T * S::P];
-    if constexpr (KIND == kKindME) {
+    SignedRec<KIND> sr;
+    if constexpr (!LARGE) {
+      sr = load_signed_rec<KIND>(r);
+      site = sr.site;
+#pragma unroll
+      for (int x = 0; x < S::T * S::P; ++x) poff[x] = sr.poff[x];
+    } else if constexpr (KIND == kKindME) {
       const uint4 r0 = load_rec4(r);
       site = r0.x & 0xFFFFu;
       wts = r0.y & 0xFFFFFFu;
@@ -592,17 +628,19 @@ __device__ __forceinline__ void wolff_bonds(const HandleDev &H, const uint32_t *
 
     // bond 8q+k: uniform (hi << 16) | lo, hi = half k >> 2 of word k & 3 of the
     // WOLFF call (site, q, sweep), lo the same from the WOLFF_LO call, drawn only
-    // when some hi equals the top half of the join threshold
+    // when some hi equals the top half of the join threshold.  D = hi - top
+    // half is negative iff the bond joins on hi alone and zero on a tie; the
+    // sign bits are shifted into `join` from bond 7 down.
     const uint32_t ph = padd >> 16;
-    uint32_t join = 0;
-    bool tie = false;
+    uint32_t join = 0, dmin = 0xFFFFFFFFu;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
+    for (int k = 7; k >= 0; --k) {
       const uint32_t hi = (k < 4) ? (u.v[k] & 0xFFFFu) : (u.v[k - 4] >> 16);
-      if (hi < ph) join |= 1u << k;
-      tie |= (hi == ph);
+      const uint32_t D = hi - ph;
+      join = __builtin_amdgcn_alignbit(join, D, 31);
+      dmin = min(dmin, D);
     }
-    if (tie) {
+    if (dmin == 0) {
       const uint32_t c3lo = (c3 & 0xFFFFFFu) | (kStreamWolffLo << 24);
       const Words4 v = philox4x32_10(site, static_cast<uint32_t>(q), m, c3lo, H.seed_lo, H.seed_hi);
       join = 0;
@@ -615,74 +653,86 @@ __device__ __forceinline__ void wolff_bonds(const HandleDev &H, const uint32_t *
     }
     jb[8 * j + q] = static_cast<uint8_t>(join & eq);
 
-    // S of the eight slices: for F <= 63 in 6-bit fields (slices 8q..8q+3 in
-    // acc_lo, 8q+4..8q+7 in acc_hi), else in 8-bit fields three slices per word
-    // (acc_lo 0-2, acc_hi 3-5, acc_x 6-7); both keep the operands of the 24-bit
-    // multiplies below 2^24.  Repacked to one byte per slice for the store.
-    const uint32_t negh = 0u - ((neg >> S::HB) & 1u);
-    const uint32_t ox = (own ^ negh) & 0xFFu;
-    uint32_t acc_lo, acc_hi, acc_x = 0;
-    if constexpr (LARGE) {
-      acc_lo = __umul24(spread3(ox), hw);
-      acc_hi = __umul24(spread3(ox >> 3), hw);
-      acc_x = __umul24(spread3(ox >> 6), hw);
+    if constexpr (!LARGE) {
+      // 4 S of the eight slices, one byte each (F <= 63), from the record's
+      // signed weights: slices 8q..8q+3 in word 2q, 8q+4..8q+7 in word 2q+1
+      const uint2 a = signed_sums<KIND>(sr, stab + kSpreadEntries, own, pbyte);
+      sb[(2 * q) * nc + j] = a.x;
+      sb[(2 * q + 1) * nc + j] = a.y;
     } else {
-      const uint2 so = spread_of(stab, ox);
-      acc_lo = __umul24(so.x, hw);
-      acc_hi = __umul24(so.y, hw);
-    }
+      // S of the eight slices in 8-bit fields, three slices per word (acc_lo
+      // 0-2, acc_hi 3-5, acc_x 6-7; the operands of the 24-bit multiplies stay
+      // below 2^24), repacked to one byte per slice for the store
+      const uint32_t negh = 0u - ((neg >> S::HB) & 1u);
+      const uint32_t ox = (own ^ negh) & 0xFFu;
+      uint32_t acc_lo = __umul24(spread3(ox), hw);
+      uint32_t acc_hi = __umul24(spread3(ox >> 3), hw);
+      uint32_t acc_x = __umul24(spread3(ox >> 6), hw);
 #pragma unroll
-    for (int t = 0; t < S::T; ++t) {
-      uint32_t prod = own;
+      for (int t = 0; t < S::T; ++t) {
+        uint32_t prod = own;
 #pragma unroll
-      for (int x = 0; x < S::P; ++x) prod ^= pbyte[S::P * t + x];
-      const uint32_t xt = (prod ^ (0u - ((neg >> t) & 1u))) & 0xFFu;
-      const uint32_t wt = term_weight(wts, wts2, t);
-      if constexpr (LARGE) {
+        for (int x = 0; x < S::P; ++x) prod ^= pbyte[S::P * t + x];
+        const uint32_t xt = (prod ^ (0u - ((neg >> t) & 1u))) & 0xFFu;
+        const uint32_t wt = term_weight(wts, wts2, t);
         acc_lo += __umul24(spread3(xt), wt);
         acc_hi += __umul24(spread3(xt >> 3), wt);
         acc_x += __umul24(spread3(xt >> 6), wt);
-      } else {
-        const uint2 sx = spread_of(stab, xt);
-        acc_lo += __umul24(sx.x, wt);
-        acc_hi += __umul24(sx.y, wt);
       }
-    }
-    if constexpr (LARGE) {
       sb[(2 * q) * nc + j] = (acc_lo & 0xFFFFFFu) | (acc_hi << 24);
       sb[(2 * q + 1) * nc + j] = ((acc_hi >> 8) & 0xFFFFu) | (acc_x << 16);
-    } else {
-      sb[(2 * q) * nc + j] = fields6_to_bytes(acc_lo);
-      sb[(2 * q + 1) * nc + j] = fields6_to_bytes(acc_hi);
     }
   }
 }
 
-template <int KIND>
+template <int KIND, bool LARGE>
 __device__ __forceinline__ void wolff_flips(const HandleDev &H, const uint32_t *__restrict__ rec, uint64_t *lat,
-                                            const uint32_t *scr, int lo, int nc, uint32_t m, uint32_t c3,
-                                            const uint32_t *arow, int lane) {
+                                            const uint32_t *scr, const uint2 *stab, int lo, int nc, uint32_t m,
+                                            uint32_t c3, const uint32_t *arow, int lane) {
   using S = Site<KIND>;
   const int L = H.L;
-  const int words = (L + 3) >> 2;
   const uint64_t *jw = reinterpret_cast<const uint64_t *>(scr);
   const uint32_t *sb = scr + 2 * nc;
   for (int j = lane; j < nc; j += 64) {
     const int d = lo + j;
-    const uint4 r0 = load_rec4(rec + d * S::RW);
-    const uint32_t site = r0.x & 0xFFFFu;
-    // F_site = |h| + sum |w_t|: the bytes of record word 1 (and, for LHZ, |h|)
+    const uint32_t *r = rec + d * S::RW;
+    const uint32_t r0x = r[0];
+    const uint32_t site = r0x & 0xFFFFu;
+    // F_site = |h| + sum |w_t|: stored in the signed-weight records; in the
+    // plain ones the bytes of record word 1 (and, for LHZ, |h|)
     // (ME: w0..w2, |h|; LHZ: w0..w3 then |h|; ME on Chimera: w0..w3 then w4, w5, |h|)
-    const uint32_t fs = (KIND == kKindME)    ? __builtin_amdgcn_sad_u8(r0.y, 0u, 0u)
-                        : (KIND == kKindLHZ) ? __builtin_amdgcn_sad_u8(r0.y, 0u, r0.z & 0xFFu)
-                                             : __builtin_amdgcn_sad_u8(r0.y, 0u,
-                                                   __builtin_amdgcn_sad_u8(r0.z & 0xFFFFFFu, 0u, 0u));
+    uint32_t fs;
+    if constexpr (!LARGE) {
+      fs = r[KIND == kKindLHZ ? 3 : 4] >> 16;
+    } else {
+      const uint32_t r1 = r[1], r2 = r[2];
+      fs = (KIND == kKindME)    ? __builtin_amdgcn_sad_u8(r1, 0u, 0u)
+           : (KIND == kKindLHZ) ? __builtin_amdgcn_sad_u8(r1, 0u, r2 & 0xFFu)
+                                : __builtin_amdgcn_sad_u8(r1, 0u, __builtin_amdgcn_sad_u8(r2 & 0xFFFFFFu, 0u, 0u));
+    }
     const Words4 u = philox4x32_10(site, kWolffSiteCtr, m, c3, H.seed_lo, H.seed_hi);
     const int t0 = static_cast<int>(__umulhi(u.v[0], static_cast<uint32_t>(L)));
     const uint64_t cl = ring_cluster(jw[j], t0, L);
-    uint32_t ssum = 0;
-    for (int i = 0; i < words; ++i)
-      ssum = __builtin_amdgcn_udot4(sb[i * nc + j], spread8(static_cast<uint32_t>(cl >> (4 * i))), ssum, false);
+    const uint32_t clh[2] = {static_cast<uint32_t>(cl), static_cast<uint32_t>(cl >> 32)};
+    uint32_t ssum;
+    if constexpr (!LARGE) {
+      // bytes of 4 S, masked by the spreads (value 4 per slice) of each cluster
+      // byte: the dot products sum 16 S over the cluster
+      const uint2 *st8 = stab + kSpreadEntries;
+      const int Q = (L + 7) >> 3;
+      uint32_t s16 = 0;
+      for (int k = 0; k < Q; ++k) {
+        const uint2 mk = st8[(clh[k >> 2] >> (8 * (k & 3))) & 0xFFu];
+        s16 = __builtin_amdgcn_udot4(sb[(2 * k) * nc + j], mk.x, s16, false);
+        s16 = __builtin_amdgcn_udot4(sb[(2 * k + 1) * nc + j], mk.y, s16, false);
+      }
+      ssum = s16 >> 4;
+    } else {
+      const int words = (L + 3) >> 2;
+      ssum = 0;
+      for (int i = 0; i < words; ++i)
+        ssum = __builtin_amdgcn_udot4(sb[i * nc + j], spread8(clh[i >> 3] >> (4 * (i & 7))), ssum, false);
+    }
     const int a = __popcll(cl) * static_cast<int>(fs) - 2 * static_cast<int>(ssum);
     if (min(u.v[1], 0xFFFFFFFEu) < arow[a]) lat[d] ^= cl;
   }
@@ -704,10 +754,15 @@ __device__ __forceinline__ void wolff_replica(const HandleDev &H, const uint32_t
       for (int lo = H.cls[c]; lo < H.cls[c + 1]; lo += kWolffChunk) {
         const int nc = min(kWolffChunk, H.cls[c + 1] - lo);
         const uint32_t mm = static_cast<uint32_t>(m);
-        if (H.F > kMidF) wolff_bonds<KIND, true>(H, rec, lat, scr, stab, lo, nc, mm, c3, padd, lane);
-        else wolff_bonds<KIND, false>(H, rec, lat, scr, stab, lo, nc, mm, c3, padd, lane);
-        wave_sync();
-        wolff_flips<KIND>(H, rec, lat, scr, lo, nc, mm, c3, arow, lane);
+        if (H.F > kMidF) {
+          wolff_bonds<KIND, true>(H, rec, lat, scr, stab, lo, nc, mm, c3, padd, lane);
+          wave_sync();
+          wolff_flips<KIND, true>(H, rec, lat, scr, stab, lo, nc, mm, c3, arow, lane);
+        } else {
+          wolff_bonds<KIND, false>(H, rec, lat, scr, stab, lo, nc, mm, c3, padd, lane);
+          wave_sync();
+          wolff_flips<KIND, false>(H, rec, lat, scr, stab, lo, nc, mm, c3, arow, lane);
+        }
         wave_sync();
       }
   }
