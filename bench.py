@@ -18,7 +18,10 @@ paper's time-like Wolff cluster moves, the roofline of the sweep kernels and
 the CPU oracle on a bounded sample of the workload.
 
 `--copy-calibration` instead runs only a cold 2 GiB device-to-device copy, the
-reference for scaling the FETCH_SIZE / WRITE_SIZE counters to bytes.
+reference for scaling the FETCH_SIZE / WRITE_SIZE counters to bytes;
+`--valu-calibration` measures the issue rate of the three VALU instruction
+kinds the sweep loops are built from (three-input XOR, widening multiply-add,
+packed 16-bit multiply-add) against the integer-ALU peak used by the roofline.
 """
 from __future__ import annotations
 
@@ -33,14 +36,17 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# VALU peak in 32-bit lane-op slots: the fp32 vector rate (157.3 TFLOP/s = 2 flops
-# per FMA) is 78.6e12 full-rate lane-ops/s = 256 CUs x 128 lane-ops/clock x 2.4 GHz.
-PEAK_LANE_OPS = 157.3e12 / 2
-# Philox4x32-10 per call: 10 rounds x (2 widening 32x32 multiplies, each 4 full-rate
-# slots at quarter rate, + 2 three-input XORs).  An attempt (a Wolff bond) consumes one
-# 16-bit half of a word, i.e. 1/8 of a call; the second call that supplies the low halves
-# is drawn only on a tie of the high half with the threshold (probability 2^-16 each).
-PHILOX_OPS_PER_CALL = 10 * (2 * 4 + 2)
+# Integer VALU peak in 32-bit lane-op slots: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz =
+# 39.3e12/s, one wave64 instruction per SIMD every 4 clocks.  (The fp32 vector rate of
+# 157.3 TFLOP/s is this x 2 flops per FMA x 2 for packed FP32, which 32-bit integer
+# code has no form of.)  `--valu-calibration` measures the instruction kinds of the
+# sweep loops at this issue rate, the widening multiply included.
+PEAK_LANE_OPS = 256 * 64 * 2.4e9
+# Philox4x32-10 per call: 10 rounds x (2 widening 32x32 multiplies, one full-rate slot
+# each on gfx950, + 2 three-input XORs).  An attempt (a Wolff bond) consumes one 16-bit
+# half of a word, i.e. 1/8 of a call; the second call that supplies the low halves is
+# drawn only on a tie of the high half with the threshold (probability 2^-16 each).
+PHILOX_OPS_PER_CALL = 10 * (2 + 2)
 PHILOX_OPS_PER_HALF = PHILOX_OPS_PER_CALL / 8
 DECISION_OPS = 4.0   # compare, tie test and select of the Metropolis test, time-neighbour term, table index
 # Wolff moves, per site-slice: bond test (equality, compare, select) and the masked cluster sum;
@@ -52,9 +58,9 @@ WOLFF_SITE_OPS = PHILOX_OPS_PER_CALL + 24.0
 # HBM bytes of one launch of the sweep kernel on this workload, from rocprofv3 --pmc FETCH_SIZE and
 # WRITE_SIZE passes (KiB per dispatch) scaled by the same counters on a cold 2 GiB copy
 # (profiles/sqa_anneal_kernel_batched512_L64.md).  Valid only for the kernel source it was taken on.
-TRAFFIC_PROFILE = {"kernel_sha256_prefix": "63bb0ab47a10c4a7", "instances": 512, "sweeps": 10_000,
-                   "fetch_kib": 965387.0, "write_kib": 509216.0, "fetch_scale": 2.0, "write_scale": 1.0,
-                   "wolff_fetch_kib": 25193.9, "wolff_write_kib": 509208.0}
+TRAFFIC_PROFILE = {"kernel_sha256_prefix": "4049bf84985af62a", "instances": 512, "sweeps": 10_000,
+                   "fetch_kib": 1156340.6, "write_kib": 509216.0, "fetch_scale": 2.0, "write_scale": 1.0,
+                   "wolff_fetch_kib": 30245.5, "wolff_write_kib": 509208.0}
 
 
 def measured_traffic(args, wolff=False):
@@ -76,6 +82,8 @@ def parse():
     ap.add_argument("--instances", type=int, default=512)
     ap.add_argument("--sweeps", type=int, default=10_000)
     ap.add_argument("--no-extras", action="store_true", help="only the timed batched steps")
+    ap.add_argument("--valu-calibration", action="store_true",
+                    help="only measure the VALU issue rate of the sweep loops' instruction kinds")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 2 GiB device to device, source evicted from the last-level cache first")
     ap.add_argument("--legs", default="per_instance,serving,pt,wolff,scan,cpu",
@@ -303,14 +311,34 @@ def copy_calibration():
     print(json.dumps({"copy_calibration_bytes": n}), flush=True)
 
 
+def valu_calibration():
+    """Issue rate of each instruction kind, in wave-instructions per SIMD per clock at
+    2.4 GHz and in 32-bit lane-ops/s, against PEAK_LANE_OPS (0.25 per SIMD per clock)."""
+    import torch
+    from paper_1603_03755_amd import sqa as S
+    torch.cuda.set_device(0)
+    simds = 4 * torch.cuda.get_device_properties(0).multi_processor_count
+    out = {}
+    for op, name in S.VALU_CALIB_OPS.items():
+        ms, instr = S.sqa_valu_calibrate(op, 100_000)
+        rate = instr / (ms * 1e-3)
+        out[name] = {"kernel_ms": ms, "wave_instructions": instr,
+                     "per_simd_per_clock_at_2p4GHz": rate / (simds * 2.4e9),
+                     "lane_ops_per_s": 64 * rate, "frac_of_peak": 64 * rate / PEAK_LANE_OPS}
+    print(json.dumps({"valu_calibration": out, "peak_lane_ops_per_s": PEAK_LANE_OPS, "simds": simds}), flush=True)
+
+
 def main():
     args = parse()
     if args.copy_calibration:
         copy_calibration()
         return
+    if args.valu_calibration:
+        valu_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (instances and replicas are "
-              f"independent, see DESIGN.md for how the batch would shard).", file=sys.stderr)
+              f"independent: several GPUs would each take their own share of the batch).", file=sys.stderr)
         sys.exit(2)
     import torch
 

@@ -370,6 +370,21 @@ SQA_API sqa_status sqa_server_stats(sqa_server *s, uint64_t *completed, uint64_t
 SQA_API void sqa_server_destroy(sqa_server *s);
 
 /* ------------------------------------------------------------- misc */
+/* ---------------------------------------------------------- calibration */
+/* Measures the VALU issue rate of one instruction type on the current device,
+ * for the integer-ALU roofline of the sweep kernels (their peak is derived from
+ * the CU count and clock; this checks that the instruction kinds the loops are
+ * built from issue at that rate).  op: 0 = three-input XOR (v_bitop3_b32),
+ * 1 = widening 32x32 -> 64-bit multiply-add (v_mad_u64_u32, Philox's multiply),
+ * 2 = packed 16-bit multiply-add (v_pk_mad_u16).  Launches eight waves per SIMD
+ * on every CU, each lane running `iters` iterations of eight independent
+ * chains; synchronous (device-wide).  Returns the timed launch's duration in
+ * *ms_out and its VALU wave-instructions of the chains in
+ * *wave_instructions_out.  Allocates and frees a small device buffer.
+ * Errors: SQA_ERR_INVALID (op outside 0..2, iters <= 0, null outputs),
+ * SQA_ERR_OOM, SQA_ERR_DEVICE. */
+SQA_API sqa_status sqa_valu_calibrate(int32_t op, int32_t iters, float *ms_out, double *wave_instructions_out);
+
 SQA_API const char *sqa_last_error(void);
 SQA_API const char *sqa_version(void);
 

@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsqa.so")
-SOURCES = ["sqa_kernels.hip", "pt_kernels.hip", "decode_kernels.hip", "host_core.cpp", "api_sqa.cpp", "api_pt.cpp", "api_server.cpp"]
+SOURCES = ["sqa_kernels.hip", "pt_kernels.hip", "decode_kernels.hip", "calib_kernels.hip", "host_core.cpp", "api_sqa.cpp", "api_pt.cpp", "api_server.cpp"]
 ARCH = "gfx950"
 
 

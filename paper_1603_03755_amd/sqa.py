@@ -106,6 +106,7 @@ _SIGS = {
     "sqa_server_result": (C.c_int, [_VP, C.c_uint64, _VP, C.c_size_t, _VP, C.c_size_t, C.POINTER(C.c_double)]),
     "sqa_server_stats": (C.c_int, [_VP] + [C.POINTER(C.c_uint64)] * 3),
     "sqa_server_destroy": (None, [_VP]),
+    "sqa_valu_calibrate": (C.c_int, [C.c_int32, C.c_int32, C.POINTER(C.c_float), C.POINTER(C.c_double)]),
     "sqa_last_error": (C.c_char_p, []),
     "sqa_version": (C.c_char_p, []),
 }
@@ -428,3 +429,14 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------- calibration
+VALU_CALIB_OPS = {0: "v_bitop3_b32", 1: "v_mad_u64_u32", 2: "v_pk_mad_u16"}
+
+
+def sqa_valu_calibrate(op: int, iters: int = 100_000):
+    """(kernel ms, VALU wave-instructions) of one issue-rate calibration launch."""
+    ms, instr = C.c_float(), C.c_double()
+    _check(lib().sqa_valu_calibrate(op, iters, C.byref(ms), C.byref(instr)))
+    return ms.value, instr.value

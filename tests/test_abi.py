@@ -55,3 +55,13 @@ def test_random_trees_match_oracle_on_host():
     from paper_1603_03755_amd import sqa
     for n in (2, 3, 8, 17):
         assert (sqa.sqa_random_trees(99, n, 12) == O.random_trees(99, n, 12)).all()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_valu_calibration_rejects_bad_arguments_on_host():
+    """Argument errors are reported before any device call."""
+    from paper_1603_03755_amd import sqa
+    for op, iters in ((3, 10), (-1, 10), (0, 0)):
+        with pytest.raises(sqa.SqaError) as e:
+            sqa.sqa_valu_calibrate(op, iters)
+        assert e.value.status == sqa.SQA_ERR_INVALID

@@ -78,3 +78,15 @@ def test_penalty_scan_equals_oracle(sqa):
                     assert res.p_s["lhz_" + d][i, k] == np.mean(ok), (i, k, d)
     pen_me, ps_me = res.optimal("mec")
     assert len(pen_me) == 2 and all(0 <= p <= 1 for p in ps_me)
+
+
+def test_valu_calibration_launch(sqa):
+    """The issue-rate calibration runs on every CU (eight waves per SIMD) and counts its
+    chains' instructions; the rate itself is the benchmark's business, not a test bound."""
+    import torch
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    for op in (0, 1, 2):
+        print(f"valu calibration op={op}", flush=True)
+        ms, instr = sqa.sqa_valu_calibrate(op, 2000)
+        assert ms > 0.0
+        assert instr == cus * 8 * 4 * 2000 * 8
