@@ -57,16 +57,26 @@ WOLFF_SITE_OPS = PHILOX_OPS_PER_CALL + 24.0
 
 # HBM bytes of one launch of the sweep kernel on this workload, from rocprofv3 --pmc FETCH_SIZE and
 # WRITE_SIZE passes (KiB per dispatch) scaled by the same counters on a cold 2 GiB copy
-# (profiles/sqa_anneal_kernel_batched512_L64.md).  Valid only for the kernel source it was taken on.
+# (profiles/sqa_anneal_kernel_batched512_L64.md).  Valid only for the kernel sources it was taken on.
 TRAFFIC_PROFILE = {"kernel_sha256_prefix": "4049bf84985af62a", "instances": 512, "sweeps": 10_000,
                    "fetch_kib": 1156340.6, "write_kib": 509216.0, "fetch_scale": 2.0, "write_scale": 1.0,
                    "wolff_fetch_kib": 30245.5, "wolff_write_kib": 509208.0}
 
 
-def measured_traffic(args, wolff=False):
+# Sources the sweep kernels are compiled from; the traffic figures hold for one hash of them.
+KERNEL_SOURCES = ("sqa_kernels.hip", "device_common.h", "device_types.h")
+
+
+def kernel_sources_sha256() -> str:
     import hashlib
-    src = os.path.join(ROOT, "paper_1603_03755_amd", "csrc", "sqa_kernels.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_1603_03755_amd", "csrc", name), "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(args, wolff=False):
+    sha = kernel_sources_sha256()
     t = TRAFFIC_PROFILE
     if not sha.startswith(t["kernel_sha256_prefix"]) or args.instances != t["instances"] or args.sweeps != t["sweeps"]:
         return None

@@ -60,7 +60,7 @@ struct PTShape {
   int rec_cap = 0, lat_cap = 0, mtab_cap = 0;
   int spack_cap = 0;   // packed swap table staged in LDS (0: read from device memory)
   size_t lds() const {
-    return (static_cast<size_t>(rec_cap) + 2ull * lat_cap + mtab_cap + 5 * 64 + spack_cap) * 4;
+    return (static_cast<size_t>(kPTSpreadWords) + rec_cap + 2ull * lat_cap + mtab_cap + 5 * 64 + spack_cap) * 4;
   }
 };
 
@@ -146,7 +146,7 @@ sqa_status pt_create(const sqa_problem *problem, const sqa_embedding *embedding,
   pt_handle *h = new (std::nothrow) pt_handle();
   if (!h) return fail(SQA_ERR_OOM, "host allocation");
   sqa_status st = build_embedding(*problem, *embedding, &h->emb);
-  if (st == SQA_OK) st = build_layout(h->emb, h->emb.fmax, kLayoutPlain, &h->lay);
+  if (st == SQA_OK) st = build_layout(h->emb, h->emb.fmax, kLayoutPT, &h->lay);
   if (st != SQA_OK) {
     delete h;
     return st;

@@ -58,7 +58,11 @@ constexpr int kKindMEC = 2;     // ME on Chimera
 //       above
 //  ME on Chimera: w1..w3 = W0..W5 as pairs, w4 = Wh | X << 16, w5..w7 =
 //       part[0..5]
-//  X = F_site for Wolff records, 0 for Metropolis records.
+//  X = F_site for Wolff records, 0 for Metropolis and PT records.
+// PT records (byte mode, F <= kPTByteF): W = +2|w| for w >= 0 and -2|w| (2|w|
+// in c') for w < 0, c' = F - F_site + sum of those 2|w|: the kernel's byte for
+// a replica, 4 (c' + sum W y) = 4F - 4F_site + 8S, addresses its threshold
+// entry directly.
 constexpr int kSmallF = 10;
 // Largest per-site field sum of the 6-bit-field sweep path, and of the library.
 constexpr int kMidF = 63;
@@ -96,6 +100,11 @@ constexpr uint32_t kStreamWolffLo = 9;
 constexpr uint32_t kStreamPTLo = 10;
 // Waves per PT workgroup at most (the PT kernel's launch bound is 64 x this).
 constexpr int kPTMaxWaves = 10;
+// Largest field sum of the PT kernel's byte mode (signed-weight records, one
+// byte per replica holding 4F - 4F_site + 8S <= 8F).
+constexpr int kPTByteF = 31;
+// LDS words of the PT kernel's byte-spread table (kSpreadEntries uint2).
+constexpr int kPTSpreadWords = 2 * kSpreadEntries;
 
 // SQA update move of a handle.
 constexpr int kMoveMetropolis = 0;   // single-site Metropolis on the space-time lattice

@@ -183,7 +183,8 @@ sqa_status build_layout(const Embedded &emb, int32_t F, RecordLayout layout, Dev
     uint32_t *r = &L.rec[static_cast<size_t>(d) * L.rec_words];
     const bool metro = layout == kLayoutMetropolis && F <= kSmallF;
     const bool wolff = layout == kLayoutWolff && F <= kMidF;
-    if (metro || wolff) {
+    const bool ptb = layout == kLayoutPT && F <= kPTByteF;
+    if (metro || wolff || ptb) {
       // Signed-weight layout: each term (and h) enters as W y with y the plain
       // product bit (own spin ^ partners; the own spin for h), and a constant.
       // Metropolis (small fields): the sum is c + 6 A (A: agreeing weight,
@@ -193,10 +194,11 @@ sqa_status build_layout(const Embedded &emb, int32_t F, RecordLayout layout, Dev
       // Wolff: the sum is S = sum |w| X (X: the term disagrees, its product bit
       // differs from its sign bit), so W = +|w| where w >= 0 and W = -|w|, with
       // |w| in the constant, where w < 0.  c' <= F_site <= 63.
+      // PT: like Wolff with 2|w| and c' = F - F_site + those 2|w| (at most 2F).
       // The kernels accumulate 4 (c' + sum W y) per byte, so 4c' fits a byte.
-      const uint32_t s = metro ? 6u : 1u;
+      const uint32_t s = metro ? 6u : (ptb ? 2u : 1u);
       uint32_t W[7];
-      int32_t cc = metro ? 3 * (F - fs) : 0;
+      int32_t cc = metro ? 3 * (F - fs) : (ptb ? F - fs : 0);
       auto put = [&](uint32_t a, bool negative_weight, int slot) {
         const bool flip = metro ? !negative_weight : negative_weight;   // weight enters as s|w| (1 - y)
         W[slot] = flip ? ((0x10000u - s * a) & 0xFFFFu) : s * a;

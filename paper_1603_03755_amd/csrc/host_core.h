@@ -54,8 +54,9 @@ struct DeviceLayout {
 // kLayoutPlain: byte weights and sign masks (PT; SQA records whose kernel path
 // takes them); kLayoutMetropolis: the signed-weight small-field layout when
 // F <= kSmallF, else plain; kLayoutWolff: the signed-weight layout of the
-// Wolff bond phase when F <= kMidF, else plain.
-enum RecordLayout { kLayoutPlain = 0, kLayoutMetropolis = 1, kLayoutWolff = 2 };
+// Wolff bond phase when F <= kMidF, else plain; kLayoutPT: the signed-weight
+// layout of the PT kernel's byte mode when F <= kPTByteF, else plain.
+enum RecordLayout { kLayoutPlain = 0, kLayoutMetropolis = 1, kLayoutWolff = 2, kLayoutPT = 3 };
 sqa_status build_layout(const Embedded &emb, int32_t F, RecordLayout layout, DeviceLayout *out);
 
 // ---------------------------------------------------------- tables

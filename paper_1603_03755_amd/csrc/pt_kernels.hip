@@ -26,8 +26,10 @@ namespace sqa {
 // of pair r during the sweep; the even pairs, then the odd pairs, are decided
 // with wave-level ordering only.
 //
-// SWAR: the weighted disagreement sums s_w of the eight replicas are formed in
-// two words of four 6-bit fields (needs F <= 63); otherwise per replica.
+// Field sums: F <= 31 (byte mode): the records are in the signed-weight layout
+// and packed 16-bit multiply-adds form, per replica, a byte that addresses its
+// threshold directly; F <= 63: the weighted disagreement sums s_w of the eight
+// replicas in two words of four 6-bit fields; otherwise per replica.
 // Sum of v over the lanes l, l - g, l - 2g, ... of a 16-lane row (G = g a power
 // of two below 16): DPP row shifts, so lane l with l % 16 >= 16 - G ends with
 // the row's total for its residue l % G.
@@ -54,20 +56,31 @@ __device__ __forceinline__ void flush_deltas(int32_t *dE, int32_t *E, int a, int
   for (int w = 0; w < 8; ++w) dE[w] = 0;
 }
 
-// Raw record words of one site (4 of the 6 words ME, 10 LHZ, 6 ME on Chimera).
-template <int KIND> struct PTRec;
-template <> struct PTRec<kKindME> { uint4 a; };
-template <> struct PTRec<kKindLHZ> { uint4 a, b; uint2 c; };
-template <> struct PTRec<kKindMEC> { uint4 a; uint2 b; };
+// Field modes of the PT kernel: byte mode (F <= kPTByteF, signed-weight
+// records), four 6-bit fields per word (F <= kMidF), or per replica.
+constexpr int kPTBytes = 0, kPTSwar = 1, kPTWide = 2;
 
-template <int KIND>
+// Raw record words of one site (ME: the first 4 of its 6 words, 5 in byte mode;
+// LHZ: 10; ME on Chimera: 6, 8 in byte mode).
+template <int KIND> struct PTRec;
+template <> struct PTRec<kKindME> { uint4 a; uint32_t b; };
+template <> struct PTRec<kKindLHZ> { uint4 a, b; uint2 c; };
+template <> struct PTRec<kKindMEC> { uint4 a, b; };
+
+template <int KIND, int MODE>
 __device__ __forceinline__ PTRec<KIND> load_pt_rec(const uint32_t *r) {
   PTRec<KIND> x;
   if constexpr (KIND == kKindME) {
     x.a = load_rec4(r);     // 24-byte records: 8-byte aligned
+    x.b = (MODE == kPTBytes) ? r[4] : 0u;
   } else if constexpr (KIND == kKindMEC) {
     x.a = *reinterpret_cast<const uint4 *>(r);
-    x.b = *reinterpret_cast<const uint2 *>(r + 4);
+    if constexpr (MODE == kPTBytes) {
+      x.b = *reinterpret_cast<const uint4 *>(r + 4);
+    } else {
+      const uint2 b = *reinterpret_cast<const uint2 *>(r + 4);
+      x.b = make_uint4(b.x, b.y, 0u, 0u);
+    }
   } else {
     x.a = *reinterpret_cast<const uint4 *>(r);
     x.b = *reinterpret_cast<const uint4 *>(r + 4);
@@ -76,8 +89,105 @@ __device__ __forceinline__ PTRec<KIND> load_pt_rec(const uint32_t *r) {
   return x;
 }
 
+// The signed-weight record (byte mode) held in a PTRec.
+template <int KIND>
+__device__ __forceinline__ SignedRec<KIND> signed_from_pt(const PTRec<KIND> &x) {
+  SignedRec<KIND> s;
+  s.site = x.a.x & 0xFFFFu;
+  s.c4w = x.a.x;
+  s.xtra = 0;
+  if constexpr (KIND == kKindME) {
+    const uint32_t ws[4] = {x.a.y, x.a.y, x.a.z, x.a.z};
+#pragma unroll
+    for (int t = 0; t < 4; ++t) { s.wsg[t] = ws[t]; s.wsh[t] = t & 1; }
+    s.poff[0] = x.a.w & 0xFFFFu; s.poff[1] = x.a.w >> 16; s.poff[2] = x.b & 0xFFFFu;
+  } else if constexpr (KIND == kKindMEC) {
+    const uint32_t ws[7] = {x.a.y, x.a.y, x.a.z, x.a.z, x.a.w, x.a.w, x.b.x};
+#pragma unroll
+    for (int t = 0; t < 7; ++t) { s.wsg[t] = ws[t]; s.wsh[t] = t & 1; }
+    const uint32_t pw[3] = {x.b.y, x.b.z, x.b.w};
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      s.poff[2 * q] = pw[q] & 0xFFFFu;
+      s.poff[2 * q + 1] = pw[q] >> 16;
+    }
+  } else {
+    const uint32_t ws[5] = {x.a.y, x.a.y, x.a.z, x.a.z, x.a.w};
+#pragma unroll
+    for (int t = 0; t < 5; ++t) { s.wsg[t] = ws[t]; s.wsh[t] = t & 1; }
+    const uint32_t pw[6] = {x.b.x, x.b.y, x.b.z, x.b.w, x.c.x, x.c.y};
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      s.poff[2 * q] = pw[q] & 0xFFFFu;
+      s.poff[2 * q + 1] = pw[q] >> 16;
+    }
+  }
+  return s;
+}
+
 // One item: site d (record x), replica byte a, sweep m.  row: the table row
 // offsets of the byte's eight replicas; dE: their energy deltas.
+// Byte mode: the signed-weight sums give, per replica w, the byte
+// V_w = 4F - 4F_site + 8 S_w in [0, 8F]; its threshold's top half is the u16 at
+// thb[w] - V_w (thb[w] = the table's byte address + 4 row[w] + 8F + 2, so this is
+// entry row[w] + F_site + F - 2 S_w), and a flip changes the energy by
+// 4 S_w - 2 F_site = V_w / 2 - 2F.
+template <int KIND>
+__device__ __forceinline__ void pt_item_bytes(const PTDev &P, const PTRec<KIND> &x, int d, uint8_t *latb,
+                                              const uint2 *st8, int a, uint32_t vmask, const uint8_t *const *thb,
+                                              int32_t *dE, uint32_t m) {
+  using S = Site<KIND>;
+  const SignedRec<KIND> sr = signed_from_pt<KIND>(x);
+  // own and partner bytes (LDS reads), the first Philox rounds while they are in flight
+  const uint32_t own = latb[8 * d + a];
+  uint32_t pbyte[S::T * S::P];
+#pragma unroll
+  for (int i = 0; i < S::T * S::P; ++i) pbyte[i] = latb[sr.poff[i] + a];
+  PhiloxState ps = philox_start(sr.site, static_cast<uint32_t>(a), m, kStreamPT << 24, P.seed_lo, P.seed_hi);
+  __builtin_amdgcn_sched_barrier(0);
+  philox_rounds<5>(ps);
+  philox_pin(ps);
+  __builtin_amdgcn_sched_barrier(0);
+  const uint2 V = signed_sums<KIND>(sr, st8, own, pbyte);
+  uint32_t th[8];
+#pragma unroll
+  for (int w = 0; w < 8; ++w)
+    th[w] = *reinterpret_cast<const uint16_t *>(thb[w] - (((w < 4 ? V.x : V.y) >> (8 * (w & 3))) & 0xFFu));
+  __builtin_amdgcn_sched_barrier(0);
+  philox_rounds<5>(ps);
+  __builtin_amdgcn_sched_barrier(0);
+  const Words4 u = philox_words(ps);
+  // D = hi - top half: negative iff accepted on hi alone, zero on a tie; the
+  // sign bits are shifted into `flip` from replica 7 down
+  uint32_t flip = 0, dmin = 0xFFFFFFFFu;
+#pragma unroll
+  for (int w = 7; w >= 0; --w) {
+    const uint32_t hi = (w < 4) ? (u.v[w] & 0xFFFFu) : (u.v[w - 4] >> 16);
+    const uint32_t D = hi - th[w];
+    flip = __builtin_amdgcn_alignbit(flip, D, 31);
+    dmin = min(dmin, D);
+  }
+  if (dmin == 0) {     // some half equals its threshold's top half: decide all eight on 32 bits
+    const Words4 v = philox4x32_10(sr.site, static_cast<uint32_t>(a), m, kStreamPTLo << 24, P.seed_lo, P.seed_hi);
+    flip = 0;
+#pragma unroll
+    for (int w = 0; w < 8; ++w) {
+      const uint32_t vb = ((w < 4 ? V.x : V.y) >> (8 * (w & 3))) & 0xFFu;
+      const uint32_t R = *reinterpret_cast<const uint32_t *>(thb[w] - 2 - vb);
+      const uint32_t uu = (w < 4) ? ((u.v[w] << 16) | (v.v[w] & 0xFFFFu))
+                                  : ((u.v[w - 4] & 0xFFFF0000u) | (v.v[w - 4] >> 16));
+      if (min(uu, 0xFFFFFFFEu) < R) flip |= 1u << w;
+    }
+  }
+  flip &= vmask;
+  latb[8 * d + a] = static_cast<uint8_t>(own ^ flip);
+  const int32_t F2 = 2 * P.F;
+#pragma unroll
+  for (int w = 0; w < 8; ++w)
+    if ((flip >> w) & 1u)
+      dE[w] += static_cast<int32_t>((((w < 4 ? V.x : V.y) >> (8 * (w & 3))) & 0xFFu) >> 1) - F2;
+}
+
 template <int KIND, bool SWAR>
 __device__ __forceinline__ void pt_item(const PTDev &P, const PTRec<KIND> &x, int d, uint8_t *latb,
                                         const uint32_t *mtab, int a, uint32_t vmask, const int32_t *row,
@@ -203,10 +313,11 @@ __device__ __forceinline__ void pt_item(const PTDev &P, const PTRec<KIND> &x, in
     if ((flip >> w) & 1u) dE[w] += 4 * static_cast<int32_t>(sw[w]) - 2 * static_cast<int32_t>(fs);
 }
 
-template <int KIND, bool SWAR>
+template <int KIND, int MODE>
 __device__ __forceinline__ void pt_ladder(const PTDev &P, const uint32_t *rec, uint64_t *lat, const uint32_t *mtab,
-                                          int32_t *E, int32_t *rep_at, int32_t *slot_of, uint32_t *acc,
-                                          uint32_t *swapw, const uint32_t *spk) {
+                                          const uint2 *st8, int32_t *E, int32_t *rep_at, int32_t *slot_of,
+                                          uint32_t *acc, uint32_t *swapw, const uint32_t *spk) {
+  constexpr bool SWAR = MODE == kPTSwar;
   using S = Site<KIND>;
   const int R = P.R, F = P.F;
   const int width = 2 * F + 1;
@@ -224,10 +335,13 @@ __device__ __forceinline__ void pt_ladder(const PTDev &P, const uint32_t *rec, u
   uint8_t *latb = reinterpret_cast<uint8_t *>(lat);
   int32_t dE[8];
   int32_t row[8];                                  // table row offsets of the byte's replicas
+  const uint8_t *thb[8];                           // byte mode: their threshold base addresses
+  const uint8_t *mtabb = reinterpret_cast<const uint8_t *>(mtab) + 8 * F + 2;
 #pragma unroll
   for (int w = 0; w < 8; ++w) {
     dE[w] = 0;
     row[w] = (w < nvalid) ? slot_of[8 * a + w] * width : 0;
+    thb[w] = mtabb + 4 * row[w];
   }
   // The record of a thread's first item in the next colour class is read into
   // registers before the current class is processed, so its LDS latency overlaps
@@ -239,7 +353,7 @@ __device__ __forceinline__ void pt_ladder(const PTDev &P, const uint32_t *rec, u
 #pragma unroll
   for (int c = 0; c < 4; ++c) has_first[c] = group_live && tid < ((cls[c + 1] - cls[c]) << lgRG);
   PTRec<KIND> nxt;
-  if (has_first[0]) nxt = load_pt_rec<KIND>(rec + (cls[0] + (tid >> lgRG)) * S::RW);
+  if (has_first[0]) nxt = load_pt_rec<KIND, MODE>(rec + (cls[0] + (tid >> lgRG)) * S::RW);
   // energy deltas into E (RG is a power of two up to 8, so it divides the 16-lane rows)
   auto flush = [&](int32_t *d) {
     if (RG == 1) flush_deltas<1>(d, E, a, nvalid, lane);
@@ -263,11 +377,19 @@ __device__ __forceinline__ void pt_ladder(const PTDev &P, const uint32_t *rec, u
       const int cnt = (cls[c + 1] - lo) << lgRG;
       const PTRec<KIND> cur = nxt;
       const int cn = (c + 1) & 3;
-      if (has_first[cn]) nxt = load_pt_rec<KIND>(rec + (cls[cn] + (tid >> lgRG)) * S::RW);
-      if (has_first[c]) pt_item<KIND, SWAR>(P, cur, lo + (tid >> lgRG), latb, mtab, a, vmask, row, dE, mm);
-      for (int it = tid + nth; group_live && it < cnt; it += nth) {
-        const int d = lo + (it >> lgRG);
-        pt_item<KIND, SWAR>(P, load_pt_rec<KIND>(rec + d * S::RW), d, latb, mtab, a, vmask, row, dE, mm);
+      if (has_first[cn]) nxt = load_pt_rec<KIND, MODE>(rec + (cls[cn] + (tid >> lgRG)) * S::RW);
+      if constexpr (MODE == kPTBytes) {
+        if (has_first[c]) pt_item_bytes<KIND>(P, cur, lo + (tid >> lgRG), latb, st8, a, vmask, thb, dE, mm);
+        for (int it = tid + nth; group_live && it < cnt; it += nth) {
+          const int d = lo + (it >> lgRG);
+          pt_item_bytes<KIND>(P, load_pt_rec<KIND, MODE>(rec + d * S::RW), d, latb, st8, a, vmask, thb, dE, mm);
+        }
+      } else {
+        if (has_first[c]) pt_item<KIND, SWAR>(P, cur, lo + (tid >> lgRG), latb, mtab, a, vmask, row, dE, mm);
+        for (int it = tid + nth; group_live && it < cnt; it += nth) {
+          const int d = lo + (it >> lgRG);
+          pt_item<KIND, SWAR>(P, load_pt_rec<KIND, MODE>(rec + d * S::RW), d, latb, mtab, a, vmask, row, dE, mm);
+        }
       }
       __syncthreads();
     }
@@ -316,7 +438,10 @@ __device__ __forceinline__ void pt_ladder(const PTDev &P, const uint32_t *rec, u
           swapw[lane] = swapw[64 + lane];
       }
 #pragma unroll
-      for (int w = 0; w < 8; ++w) row[w] = (w < nvalid) ? slot_of[8 * a + w] * width : 0;
+      for (int w = 0; w < 8; ++w) {
+        row[w] = (w < nvalid) ? slot_of[8 * a + w] * width : 0;
+        thb[w] = mtabb + 4 * row[w];
+      }
       ++phase;
     }
   }
@@ -324,13 +449,15 @@ __device__ __forceinline__ void pt_ladder(const PTDev &P, const uint32_t *rec, u
   __syncthreads();
 }
 
-// Dynamic LDS: [rec_cap words][lat_cap u64][mtab_cap words][E, rep_at, slot_of, acc: 64 each]
-// [swap words: 2 x 64][spack_cap words: the packed swap table when it is staged].
+// Dynamic LDS: [byte-spread table: kPTSpreadWords][rec_cap words][lat_cap u64][mtab_cap words]
+// [E, rep_at, slot_of, acc: 64 each][swap words: 2 x 64][spack_cap words: the packed swap
+// table when it is staged].
 __global__ __launch_bounds__(64 * kPTMaxWaves) void pt_kernel(const PTDev *__restrict__ pts, int rec_cap, int lat_cap,
                                                               int mtab_cap, int spack_cap) {
   extern __shared__ __align__(16) uint32_t smem[];
   const PTDev &P = pts[blockIdx.x];       // read in place: uniform fields become scalar loads
-  uint32_t *rec = smem;
+  uint2 *st8 = reinterpret_cast<uint2 *>(smem);
+  uint32_t *rec = smem + kPTSpreadWords;
   uint64_t *lat = reinterpret_cast<uint64_t *>(rec + rec_cap);
   uint32_t *mtab = rec + rec_cap + 2 * lat_cap;
   int32_t *E = reinterpret_cast<int32_t *>(mtab + mtab_cap);
@@ -341,6 +468,8 @@ __global__ __launch_bounds__(64 * kPTMaxWaves) void pt_kernel(const PTDev *__res
   uint32_t *spk = swapw + 128;
   const int tid = threadIdx.x, nth = blockDim.x;
   const int rw = rec_words_of(P.kind);
+  for (int x = tid; x < kSpreadEntries; x += nth)
+    st8[x] = make_uint2(spread8(static_cast<uint32_t>(x) & 0xFu) << 2, spread8(static_cast<uint32_t>(x) >> 4) << 2);
   for (int i = tid; i < P.n * rw; i += nth) rec[i] = P.rec[i];
   const int width = 2 * P.F + 1;
   for (int i = tid; i < P.R * width; i += nth) mtab[i] = P.mtab[i];
@@ -379,16 +508,20 @@ __global__ __launch_bounds__(64 * kPTMaxWaves) void pt_kernel(const PTDev *__res
     E[tid] = e;
   }
   __syncthreads();
-  const bool swar = P.F <= kMidF;
+  const int mode = (P.F <= kPTByteF) ? kPTBytes : (P.F <= kMidF ? kPTSwar : kPTWide);
+  const uint32_t *sp = staged ? spk : nullptr;
   if (P.kind == kKindME) {
-    if (swar) pt_ladder<kKindME, true>(P, rec, lat, mtab, E, rep_at, slot_of, acc, swapw, staged ? spk : nullptr);
-    else pt_ladder<kKindME, false>(P, rec, lat, mtab, E, rep_at, slot_of, acc, swapw, staged ? spk : nullptr);
+    if (mode == kPTBytes) pt_ladder<kKindME, kPTBytes>(P, rec, lat, mtab, st8, E, rep_at, slot_of, acc, swapw, sp);
+    else if (mode == kPTSwar) pt_ladder<kKindME, kPTSwar>(P, rec, lat, mtab, st8, E, rep_at, slot_of, acc, swapw, sp);
+    else pt_ladder<kKindME, kPTWide>(P, rec, lat, mtab, st8, E, rep_at, slot_of, acc, swapw, sp);
   } else if (P.kind == kKindLHZ) {
-    if (swar) pt_ladder<kKindLHZ, true>(P, rec, lat, mtab, E, rep_at, slot_of, acc, swapw, staged ? spk : nullptr);
-    else pt_ladder<kKindLHZ, false>(P, rec, lat, mtab, E, rep_at, slot_of, acc, swapw, staged ? spk : nullptr);
+    if (mode == kPTBytes) pt_ladder<kKindLHZ, kPTBytes>(P, rec, lat, mtab, st8, E, rep_at, slot_of, acc, swapw, sp);
+    else if (mode == kPTSwar) pt_ladder<kKindLHZ, kPTSwar>(P, rec, lat, mtab, st8, E, rep_at, slot_of, acc, swapw, sp);
+    else pt_ladder<kKindLHZ, kPTWide>(P, rec, lat, mtab, st8, E, rep_at, slot_of, acc, swapw, sp);
   } else {
-    if (swar) pt_ladder<kKindMEC, true>(P, rec, lat, mtab, E, rep_at, slot_of, acc, swapw, staged ? spk : nullptr);
-    else pt_ladder<kKindMEC, false>(P, rec, lat, mtab, E, rep_at, slot_of, acc, swapw, staged ? spk : nullptr);
+    if (mode == kPTBytes) pt_ladder<kKindMEC, kPTBytes>(P, rec, lat, mtab, st8, E, rep_at, slot_of, acc, swapw, sp);
+    else if (mode == kPTSwar) pt_ladder<kKindMEC, kPTSwar>(P, rec, lat, mtab, st8, E, rep_at, slot_of, acc, swapw, sp);
+    else pt_ladder<kKindMEC, kPTWide>(P, rec, lat, mtab, st8, E, rep_at, slot_of, acc, swapw, sp);
   }
   // results: spins by replica in physical order, energies by replica, slot map, swap counts
   for (size_t i = tid; i < static_cast<size_t>(P.R) * P.n; i += nth) {
@@ -406,7 +539,8 @@ __global__ __launch_bounds__(64 * kPTMaxWaves) void pt_kernel(const PTDev *__res
 // ----------------------------------------------------------- host launchers
 hipError_t launch_pt(const PTDev *pts, int count, int waves, int rec_cap, int lat_cap, int mtab_cap, int spack_cap,
                      hipStream_t stream) {
-  const size_t lds = (static_cast<size_t>(rec_cap) + 2ull * lat_cap + mtab_cap + 5 * 64 + spack_cap) * 4;
+  const size_t lds =
+      (static_cast<size_t>(kPTSpreadWords) + rec_cap + 2ull * lat_cap + mtab_cap + 5 * 64 + spack_cap) * 4;
   (void)hipGetLastError();
   hipLaunchKernelGGL(pt_kernel, dim3(count), dim3(64 * waves), lds, stream, pts, rec_cap, lat_cap, mtab_cap,
                      spack_cap);

@@ -100,94 +100,6 @@ __device__ __forceinline__ void slice_energies(const HandleDev &H, const uint64_
   H.energy[static_cast<size_t>(rep) * H.L + tau] = E;
 }
 
-// ------------------------------------------------- signed-weight records
-// Site record in the signed-weight layout (Metropolis records with F <= 10,
-// Wolff records with F <= 63): the site, record word 0 (4c' in both bytes of
-// its high half), for each weight (terms, then h) the record word holding it
-// and its half, the partners' byte offsets, and the high half of the word
-// after the weights (F_site in Wolff records).
-template <int KIND>
-struct SignedRec {
-  static constexpr int NW = Site<KIND>::T + 1, NP = Site<KIND>::T * Site<KIND>::P;
-  uint32_t site, c4w, xtra;
-  uint32_t wsg[NW];
-  int wsh[NW];
-  uint32_t poff[NP];
-  // term t's weight (t = T: h's) in both 16-bit lanes
-  __device__ __forceinline__ u16x2 weight(int t) const {
-    const u16x2 w = as_u16x2(wsg[t]);
-    return wsh[t] ? w.yy : w.xx;
-  }
-  // 4c' in all four bytes, as two 16-bit lanes
-  __device__ __forceinline__ u16x2 c4() const { return as_u16x2(c4w).yy; }
-};
-
-template <int KIND>
-__device__ __forceinline__ SignedRec<KIND> load_signed_rec(const uint32_t *r) {
-  SignedRec<KIND> x;
-  const uint4 r0 = load_rec4(r);
-  x.site = r0.x & 0xFFFFu;
-  x.c4w = r0.x;
-  if constexpr (KIND == kKindME) {
-    const uint32_t r4 = r[4];
-    const uint32_t ws[4] = {r0.y, r0.y, r0.z, r0.z};
-#pragma unroll
-    for (int t = 0; t < 4; ++t) { x.wsg[t] = ws[t]; x.wsh[t] = t & 1; }
-    x.poff[0] = r0.w & 0xFFFFu; x.poff[1] = r0.w >> 16; x.poff[2] = r4 & 0xFFFFu;
-    x.xtra = r4 >> 16;
-  } else if constexpr (KIND == kKindMEC) {
-    const uint4 r1 = load_rec4(r + 4);
-    const uint32_t ws[7] = {r0.y, r0.y, r0.z, r0.z, r0.w, r0.w, r1.x};
-#pragma unroll
-    for (int t = 0; t < 7; ++t) { x.wsg[t] = ws[t]; x.wsh[t] = t & 1; }
-    x.xtra = r1.x >> 16;
-    const uint32_t pw[3] = {r1.y, r1.z, r1.w};
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      x.poff[2 * q] = pw[q] & 0xFFFFu;
-      x.poff[2 * q + 1] = pw[q] >> 16;
-    }
-  } else {
-    const uint4 r1 = load_rec4(r + 4);
-    const uint2 r2 = *reinterpret_cast<const uint2 *>(r + 8);
-    const uint32_t ws[5] = {r0.y, r0.y, r0.z, r0.z, r0.w};
-#pragma unroll
-    for (int t = 0; t < 5; ++t) { x.wsg[t] = ws[t]; x.wsh[t] = t & 1; }
-    x.xtra = r0.w >> 16;
-    const uint32_t pw[6] = {r1.x, r1.y, r1.z, r1.w, r2.x, r2.y};
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
-      x.poff[2 * q] = pw[q] & 0xFFFFu;
-      x.poff[2 * q + 1] = pw[q] >> 16;
-    }
-  }
-  return x;
-}
-
-// 4 (c' + sum_t W_t y_t + W_h own) of the eight slices of one byte, slices
-// 0..3 in the bytes of .x and 4..7 in .y: packed 16-bit multiply-adds of the
-// spreads (bit 2 of each byte, second half of the spread table) of the plain
-// product bytes.  Exact modulo 2^16 per lane; the caller's sums lie in [0, 256)
-// per byte, so the lanes hold them without carries between bytes.
-template <int KIND>
-__device__ __forceinline__ uint2 signed_sums(const SignedRec<KIND> &x, const uint2 *st8, uint32_t own,
-                                             const uint32_t *pbyte) {
-  using S = Site<KIND>;
-  const uint2 so = st8[own];
-  u16x2 a_lo = as_u16x2(so.x) * x.weight(S::T) + x.c4();
-  u16x2 a_hi = as_u16x2(so.y) * x.weight(S::T) + x.c4();
-#pragma unroll
-  for (int t = 0; t < S::T; ++t) {
-    uint32_t prod = own;
-#pragma unroll
-    for (int q = 0; q < S::P; ++q) prod ^= pbyte[S::P * t + q];
-    const uint2 sx = st8[prod];
-    a_lo = as_u16x2(sx.x) * x.weight(t) + a_lo;
-    a_hi = as_u16x2(sx.y) * x.weight(t) + a_hi;
-  }
-  return make_uint2(as_u32(a_lo), as_u32(a_hi));
-}
-
 // ------------------------------------------------------------ SQA sweep
 // Item loop over one (slice parity p, colour c) class of one replica, by the
 // nthr threads of its team (one wave, or the whole workgroup).

@@ -311,3 +311,19 @@ def test_pt_large_field_sums(sqa, kind, N, pen):
     ospins, oE, orep, oacc = O.pt_run(emb, O.pt_ladder(0.01, 0.5, 8), 60, 1, 99)
     assert (rep == orep).all() and (spins == ospins[orep]).all() and (E == oE[orep]).all()
     assert (acc == oacc).all()
+
+
+@pytest.mark.parametrize("kind,N,pen,fmin,fmax", [(ME, 6, -8, 11, 31), (LHZ, 6, -4, 11, 31),
+                                                  (ME, 6, -15, 32, 63), (LHZ, 6, -8, 32, 63)])
+def test_pt_field_sum_modes(sqa, kind, N, pen, fmin, fmax):
+    """PT in its byte mode (field sums up to 31, signed-weight records) and its 6-bit
+    mode (32..63): couplings in {+-1..+-10}, identical to the oracle."""
+    J = sk_instance(N, 660 + N, values=tuple(v for v in range(-10, 11) if v != 0))
+    emb = O.Embedding(kind, J, pen)
+    assert fmin <= emb.fmax <= fmax
+    print(f"PT modes kind={kind} F={emb.fmax}", flush=True)
+    dev = sqa.PT(kind, J, pen, 0.02, 1.0, 16, 80, 2, 77).run()
+    spins, E, rep, acc = dev.read()
+    ospins, oE, orep, oacc = O.pt_run(emb, O.pt_ladder(0.02, 1.0, 16), 80, 2, 77)
+    assert (rep == orep).all() and (spins == ospins[orep]).all() and (E == oE[orep]).all()
+    assert (acc == oacc).all()
