@@ -104,19 +104,19 @@ __device__ __forceinline__ void slice_energies(const HandleDev &H, const uint64_
 // Item loop over one (slice parity p, colour c) class of one replica, by the
 // nthr threads of its team (one wave, or the whole workgroup).
 // Item = (site of colour c, byte b of its parity-p half word): the eight slices
-// tau = 16b + 2k + p (k = 0..7), served by the two Philox calls of slice groups
-// 2b and 2b+1 (four words each).  For each slice the acceptance index is
+// tau = 16b + 2k + p (k = 0..7), whose random halves come from one Philox call
+// (counter word 1 = 2b + p).  For each slice the acceptance index is
 // base - (6 S + e), with
 //   S = sum_t |w_t| X_t + |h| O   (X_t = 1 iff term t's product with the own
 //       spin disagrees with the sign of w_t; O likewise for the field),
 //   e = number of time neighbours whose spin differs from the own spin;
-// e is accumulated four slices at a time in 6-bit fields; S by field mode:
-// kFieldSmall (F <= 10): the records carry 6|w| and 6|h|, flipped sign bits
-//   (so the products count agreements, A = F_site - S) and c = 3 (F - F_site)
-//   in place of base.  A field then holds c + 6 A + e' (e' = 2 - e, the agreeing
-//   neighbours), which equals base - (6 S + e) and is below 64: the field is
-//   the table index itself;
-// kFieldMid (F <= 63): S in 6-bit fields, four slices per word;
+// S and e by field mode:
+// kFieldSmall (F <= 10): signed-weight records (see device_types.h); packed
+//   16-bit multiply-adds form 4 (c + 6 A) per slice in byte fields (A = F_site
+//   - S, the agreeing weight; c = 3 (F - F_site)), and the spreads of the
+//   agreeing time neighbours add 4 e' (e' = 2 - e).  4 (c + 6 A + e') =
+//   4 (base - (6 S + e)) < 256 is the byte offset of the slice's table entry;
+// kFieldMid (F <= 63): S and e in 6-bit fields, four slices per word;
 // kFieldLarge (F <= 255): S in 8-bit fields, three slices per word (at bits
 //   0, 8, 16, so both operands of the 24-bit multiplies stay below 2^24).
 // FL: 0 for any L, or the compile-time L in {16, 32, 64} (whole bytes,
