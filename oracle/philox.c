@@ -9,7 +9,7 @@
  * implements Philox4x64-10.
  *
  * The paper does not say which generator it used (its SQA code is described
- * in another reference).  Counter layout, a reading taken for this build
+ * in another reference).  Counter layout, a reading taken here
  * (key = (seed low 32 bits, seed high 32 bits) throughout):
  *   Initial spin of (replica r, slice tau, site k), stream INIT:
  *     counter = (k, ((tau>>3)<<1) | (tau&1), 0, (INIT<<24) | r),

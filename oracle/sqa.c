@@ -4,9 +4,9 @@
  * Discrete-time path-integral Monte Carlo (Sec. III; Appendix B): L Trotter
  * slices of the embedded physical system, periodic in imaginary time, updated
  * by single-site Metropolis moves with the acceptance tables of tables.c while
- * Gamma is annealed, one schedule step per sweep.  (The paper's own move is a
- * time-like Wolff cluster update; this build's hot path is single-site
- * Metropolis on the space-time lattice.)
+ * Gamma is annealed, one schedule step per sweep.  (The paper's own move, a
+ * time-like Wolff cluster update, is in wolff.c; this file is the single-site
+ * Metropolis move on the space-time lattice.)
  *
  * Sweep order, a reading (the paper only says "sweep"): for slice parity
  * p = 0, 1; for colour c = 0..3; for every slice tau with tau = p (mod 2); for
