@@ -60,7 +60,7 @@ struct PTShape {
   int rec_cap = 0, lat_cap = 0, mtab_cap = 0;
   int spack_cap = 0;   // packed swap table staged in LDS (0: read from device memory)
   size_t lds() const {
-    return (static_cast<size_t>(kPTSpreadWords) + rec_cap + 2ull * lat_cap + mtab_cap + 5 * 64 + spack_cap) * 4;
+    return (static_cast<size_t>(kPTSpreadWords) + rec_cap + 2ull * lat_cap + mtab_cap + kPTLadderWords + spack_cap) * 4;
   }
 };
 

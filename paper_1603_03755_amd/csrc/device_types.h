@@ -103,8 +103,14 @@ constexpr int kPTMaxWaves = 10;
 // Largest field sum of the PT kernel's byte mode (signed-weight records, one
 // byte per replica holding 4F - 4F_site + 8S <= 8F).
 constexpr int kPTByteF = 31;
-// LDS words of the PT kernel's byte-spread table (kSpreadEntries uint2).
-constexpr int kPTSpreadWords = 2 * kSpreadEntries;
+// LDS words of the PT kernel's per-ladder arrays after its table: E, rep_at,
+// slot_of, acc (64 each) and the swap words of two phases (2 x 64).
+constexpr int kPTLadderWords = 4 * 64 + 2 * 64;
+// LDS words of the PT kernel's byte tables: kSpreadEntries uint2 spreads (bit i
+// of the byte -> value 4 in byte i of a nibble's word), then kSpreadEntries
+// uint2 byte-permute selectors (byte i of a nibble's word selects byte i where
+// bit i is set, zero elsewhere).
+constexpr int kPTSpreadWords = 4 * kSpreadEntries;
 
 // SQA update move of a handle.
 constexpr int kMoveMetropolis = 0;   // single-site Metropolis on the space-time lattice

@@ -131,11 +131,13 @@ __device__ __forceinline__ SignedRec<KIND> signed_from_pt(const PTRec<KIND> &x) 
 // V_w = 4F - 4F_site + 8 S_w in [0, 8F]; its threshold's top half is the u16 at
 // thb[w] - V_w (thb[w] = the table's byte address + 4 row[w] + 8F + 2, so this is
 // entry row[w] + F_site + F - 2 S_w), and a flip changes the energy by
-// 4 S_w - 2 F_site = V_w / 2 - 2F.
+// 4 S_w - 2 F_site = (V_w - 4F) / 2.  The thread sums V_w over its flips in
+// vsum[w] (the flipped replicas' bytes picked by a byte permute) and 4 x their
+// number in cnt4[w]; the deltas are (vsum - F cnt4) / 2 at a flush.
 template <int KIND>
 __device__ __forceinline__ void pt_item_bytes(const PTDev &P, const PTRec<KIND> &x, int d, uint8_t *latb,
                                               const uint2 *st8, int a, uint32_t vmask, const uint8_t *const *thb,
-                                              int32_t *dE, uint32_t m) {
+                                              uint32_t *vsum, uint32_t *cnt4, uint32_t m) {
   using S = Site<KIND>;
   const SignedRec<KIND> sr = signed_from_pt<KIND>(x);
   // own and partner bytes (LDS reads), the first Philox rounds while they are in flight
@@ -181,11 +183,15 @@ __device__ __forceinline__ void pt_item_bytes(const PTDev &P, const PTRec<KIND> 
   }
   flip &= vmask;
   latb[8 * d + a] = static_cast<uint8_t>(own ^ flip);
-  const int32_t F2 = 2 * P.F;
+  const uint2 fsp = st8[flip], fsel = st8[kSpreadEntries + flip];
+  const uint32_t t_lo = __builtin_amdgcn_perm(V.x, V.x, fsel.x), t_hi = __builtin_amdgcn_perm(V.y, V.y, fsel.y);
 #pragma unroll
-  for (int w = 0; w < 8; ++w)
-    if ((flip >> w) & 1u)
-      dE[w] += static_cast<int32_t>((((w < 4 ? V.x : V.y) >> (8 * (w & 3))) & 0xFFu) >> 1) - F2;
+  for (int w = 0; w < 4; ++w) {
+    vsum[w] += (t_lo >> (8 * w)) & 0xFFu;
+    vsum[w + 4] += (t_hi >> (8 * w)) & 0xFFu;
+    cnt4[w] += (fsp.x >> (8 * w)) & 0xFFu;
+    cnt4[w + 4] += (fsp.y >> (8 * w)) & 0xFFu;
+  }
 }
 
 template <int KIND, bool SWAR>
@@ -334,12 +340,15 @@ __device__ __forceinline__ void pt_ladder(const PTDev &P, const uint32_t *rec, u
   const uint32_t vmask = (1u << nvalid) - 1u;
   uint8_t *latb = reinterpret_cast<uint8_t *>(lat);
   int32_t dE[8];
+  uint32_t vsum[8], cnt4[8];                       // byte mode: flip sums (see pt_item_bytes)
   int32_t row[8];                                  // table row offsets of the byte's replicas
   const uint8_t *thb[8];                           // byte mode: their threshold base addresses
   const uint8_t *mtabb = reinterpret_cast<const uint8_t *>(mtab) + 8 * F + 2;
 #pragma unroll
   for (int w = 0; w < 8; ++w) {
     dE[w] = 0;
+    vsum[w] = 0;
+    cnt4[w] = 0;
     row[w] = (w < nvalid) ? slot_of[8 * a + w] * width : 0;
     thb[w] = mtabb + 4 * row[w];
   }
@@ -356,6 +365,14 @@ __device__ __forceinline__ void pt_ladder(const PTDev &P, const uint32_t *rec, u
   if (has_first[0]) nxt = load_pt_rec<KIND, MODE>(rec + (cls[0] + (tid >> lgRG)) * S::RW);
   // energy deltas into E (RG is a power of two up to 8, so it divides the 16-lane rows)
   auto flush = [&](int32_t *d) {
+    if constexpr (MODE == kPTBytes) {
+#pragma unroll
+      for (int w = 0; w < 8; ++w) {
+        d[w] = (static_cast<int32_t>(vsum[w]) - F * static_cast<int32_t>(cnt4[w])) / 2;
+        vsum[w] = 0;
+        cnt4[w] = 0;
+      }
+    }
     if (RG == 1) flush_deltas<1>(d, E, a, nvalid, lane);
     else if (RG == 2) flush_deltas<2>(d, E, a, nvalid, lane);
     else if (RG == 4) flush_deltas<4>(d, E, a, nvalid, lane);
@@ -379,10 +396,11 @@ __device__ __forceinline__ void pt_ladder(const PTDev &P, const uint32_t *rec, u
       const int cn = (c + 1) & 3;
       if (has_first[cn]) nxt = load_pt_rec<KIND, MODE>(rec + (cls[cn] + (tid >> lgRG)) * S::RW);
       if constexpr (MODE == kPTBytes) {
-        if (has_first[c]) pt_item_bytes<KIND>(P, cur, lo + (tid >> lgRG), latb, st8, a, vmask, thb, dE, mm);
+        if (has_first[c]) pt_item_bytes<KIND>(P, cur, lo + (tid >> lgRG), latb, st8, a, vmask, thb, vsum, cnt4, mm);
         for (int it = tid + nth; group_live && it < cnt; it += nth) {
           const int d = lo + (it >> lgRG);
-          pt_item_bytes<KIND>(P, load_pt_rec<KIND, MODE>(rec + d * S::RW), d, latb, st8, a, vmask, thb, dE, mm);
+          pt_item_bytes<KIND>(P, load_pt_rec<KIND, MODE>(rec + d * S::RW), d, latb, st8, a, vmask, thb, vsum, cnt4,
+                              mm);
         }
       } else {
         if (has_first[c]) pt_item<KIND, SWAR>(P, cur, lo + (tid >> lgRG), latb, mtab, a, vmask, row, dE, mm);
@@ -465,11 +483,20 @@ __global__ __launch_bounds__(64 * kPTMaxWaves) void pt_kernel(const PTDev *__res
   int32_t *slot_of = rep_at + 64;
   uint32_t *acc = reinterpret_cast<uint32_t *>(slot_of + 64);
   uint32_t *swapw = acc + 64;
-  uint32_t *spk = swapw + 128;
+  uint32_t *spk = reinterpret_cast<uint32_t *>(E) + kPTLadderWords;   // after swapw[2 x 64]
+  static_assert(kPTLadderWords == 4 * 64 + 2 * 64, "E, rep_at, slot_of, acc, then two phases of swap words");
   const int tid = threadIdx.x, nth = blockDim.x;
   const int rw = rec_words_of(P.kind);
-  for (int x = tid; x < kSpreadEntries; x += nth)
-    st8[x] = make_uint2(spread8(static_cast<uint32_t>(x) & 0xFu) << 2, spread8(static_cast<uint32_t>(x) >> 4) << 2);
+  for (int x = tid; x < kSpreadEntries; x += nth) {
+    const uint32_t lo = static_cast<uint32_t>(x) & 0xFu, hi = static_cast<uint32_t>(x) >> 4;
+    st8[x] = make_uint2(spread8(lo) << 2, spread8(hi) << 2);
+    uint32_t sl = 0, sh = 0;
+    for (int i = 0; i < 4; ++i) {
+      sl |= (((lo >> i) & 1u) ? static_cast<uint32_t>(i) : 0x0Cu) << (8 * i);
+      sh |= (((hi >> i) & 1u) ? static_cast<uint32_t>(i) : 0x0Cu) << (8 * i);
+    }
+    st8[kSpreadEntries + x] = make_uint2(sl, sh);
+  }
   for (int i = tid; i < P.n * rw; i += nth) rec[i] = P.rec[i];
   const int width = 2 * P.F + 1;
   for (int i = tid; i < P.R * width; i += nth) mtab[i] = P.mtab[i];
@@ -540,7 +567,7 @@ __global__ __launch_bounds__(64 * kPTMaxWaves) void pt_kernel(const PTDev *__res
 hipError_t launch_pt(const PTDev *pts, int count, int waves, int rec_cap, int lat_cap, int mtab_cap, int spack_cap,
                      hipStream_t stream) {
   const size_t lds =
-      (static_cast<size_t>(kPTSpreadWords) + rec_cap + 2ull * lat_cap + mtab_cap + 5 * 64 + spack_cap) * 4;
+      (static_cast<size_t>(kPTSpreadWords) + rec_cap + 2ull * lat_cap + mtab_cap + kPTLadderWords + spack_cap) * 4;
   (void)hipGetLastError();
   hipLaunchKernelGGL(pt_kernel, dim3(count), dim3(64 * waves), lds, stream, pts, rec_cap, lat_cap, mtab_cap,
                      spack_cap);
