@@ -327,3 +327,33 @@ def test_pt_field_sum_modes(sqa, kind, N, pen, fmin, fmax):
     ospins, oE, orep, oacc = O.pt_run(emb, O.pt_ladder(0.02, 1.0, 16), 80, 2, 77)
     assert (rep == orep).all() and (spins == ospins[orep]).all() and (E == oE[orep]).all()
     assert (acc == oacc).all()
+
+
+def test_pt_many_ladder_shapes_in_one_batch(sqa):
+    """Ladders of many sizes (every LDS layout size between them, swap tables staged)
+    in one batched launch, each identical to the oracle."""
+    cases = [(kind, N, R) for kind in (ME, LHZ) for N, R in ((3, 2), (4, 5), (5, 8), (6, 13), (7, 20), (5, 31),
+                                                              (8, 32), (6, 47), (4, 64))]
+    hs, refs, emb_J = [], [], []
+    for i, (kind, N, R) in enumerate(cases):
+        J = sk_instance(N, 900 + i)
+        emb_J.append(J)
+        hs.append(sqa.PT(kind, J, -2, 0.1, 5.0, R, 25, 1, 0x5A00 + i))
+        refs.append((O.Embedding(kind, J, -2), O.pt_ladder(0.1, 5.0, R), 0x5A00 + i))
+    print(f"PT batch of {len(hs)} ladders", flush=True)
+    sqa.pt_run_batch(hs)
+    for h, (emb, betas, seed) in zip(hs, refs):
+        spins, E, rep, acc = h.read()
+        ospins, oE, orep, oacc = O.pt_run(emb, betas, 25, 1, seed)
+        assert (rep == orep).all() and (spins == ospins[orep]).all() and (E == oE[orep]).all()
+        assert (acc == oacc).all()
+    for h in hs:
+        h.close()
+    # the same ladders one launch each: every one with its own LDS size
+    for i, (kind, N, R) in enumerate(cases):
+        emb, betas, seed = refs[i]
+        h = sqa.PT(kind, emb_J[i], -2, 0.1, 5.0, R, 25, 1, seed).run()
+        spins, E, rep, acc = h.read()
+        ospins, oE, orep, oacc = O.pt_run(emb, betas, 25, 1, seed)
+        assert (rep == orep).all() and (spins == ospins[orep]).all() and (E == oE[orep]).all()
+        h.close()
