@@ -104,8 +104,9 @@ constexpr int kPTMaxWaves = 10;
 // byte per replica holding 4F - 4F_site + 8S <= 8F).
 constexpr int kPTByteF = 31;
 // LDS words of the PT kernel's per-ladder arrays after its table: E, rep_at,
-// slot_of, acc (64 each) and the swap words of two phases (2 x 64).
-constexpr int kPTLadderWords = 4 * 64 + 2 * 64;
+// slot_of, acc (64 each), the swap words of two phases (2 x 64), and per wave a
+// 64-word slot-of-replica scratch and 64 words of energy partials.
+constexpr int kPTLadderWords = 4 * 64 + 2 * 64 + 2 * kPTMaxWaves * 64;
 // LDS words of the PT kernel's byte tables: kSpreadEntries uint2 spreads (bit i
 // of the byte -> value 4 in byte i of a nibble's word), then kSpreadEntries
 // uint2 byte-permute selectors (byte i of a nibble's word selects byte i where

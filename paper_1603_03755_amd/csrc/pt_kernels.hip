@@ -20,11 +20,14 @@ namespace sqa {
 // top half of its threshold, rejected when above; only on a tie does the item
 // draw the PT_LO call and decide on the full 32 bits.  The item owns its byte,
 // so flips go back with one byte store.  Energies: per-thread deltas of the
-// eight replicas (a flip with a = s*f changes E by -2a), summed at a swap phase
-// over the threads of a byte (DPP row sums, one LDS atomic per 16-lane row and
-// replica).  The swap phase runs on wave 0: its lane r draws the swap word
-// of pair r during the sweep; the even pairs, then the odd pairs, are decided
-// with wave-level ordering only.
+// eight replicas (a flip with a = s*f changes E by -2a), summed over each wave
+// (DPP row sums, lane permutes across rows) into the wave's own LDS partials
+// before the last class barrier of a sweep that ends in a swap phase.  Every
+// wave then decides the whole swap phase on its own: lane s holds the replica
+// at slot s and its energy, adds every wave's partial of that replica, and the
+// lanes of a pair exchange both (DPP for the even pairs, a lane permute for the
+// odd ones); a wave's own LDS scratch turns the new slot map into its threads'
+// table rows, so no barrier follows the swap phase.
 //
 // Field sums: F <= 31 (byte mode): the records are in the signed-weight layout
 // and packed 16-bit multiply-adds form, per replica, a byte that addresses its
@@ -42,19 +45,32 @@ __device__ __forceinline__ int32_t row_sum_stride(int32_t v) {
   return v;
 }
 
-// Adds the eight per-thread energy deltas of replica byte a into E: row sums by
-// DPP, then one LDS atomic per row, residue and replica.
+// Sums the eight per-thread energy deltas of replica byte a over the wave (DPP
+// row sums, then two lane permutes that fold the four rows) and stores the
+// wave's totals in its own array: word 8a + w holds replica 8a + w's.
 template <int G>
-__device__ __forceinline__ void flush_deltas(int32_t *dE, int32_t *E, int a, int nvalid, int lane) {
+__device__ __forceinline__ void flush_partials(int32_t *dE, int32_t *part, int a, int lane) {
 #pragma unroll
   for (int w = 0; w < 8; ++w) dE[w] = row_sum_stride<G>(dE[w]);
-  if ((lane & 15) >= 16 - G && nvalid > 0)
 #pragma unroll
-    for (int w = 0; w < 8; ++w)
-      if (w < nvalid && dE[w] != 0) atomicAdd(&E[8 * a + w], dE[w]);
+  for (int w = 0; w < 8; ++w) dE[w] += __builtin_amdgcn_ds_bpermute(4 * ((lane + 32) & 63), dE[w]);
+#pragma unroll
+  for (int w = 0; w < 8; ++w) dE[w] += __builtin_amdgcn_ds_bpermute(4 * ((lane + 16) & 63), dE[w]);
+  if (lane >= 16 - G && lane < 16)
+#pragma unroll
+    for (int w = 0; w < 8; ++w) part[8 * a + w] = dE[w];
 #pragma unroll
   for (int w = 0; w < 8; ++w) dE[w] = 0;
 }
+
+// Explicit LDS and global address spaces: pointers that are updated inside the
+// sweep loop (the byte-mode threshold bases) or passed out of line would
+// otherwise become generic, and their loads flat loads.
+using lds_u8 = __attribute__((address_space(3))) const uint8_t;
+using lds_u16 = __attribute__((address_space(3))) const uint16_t;
+using lds_u32 = __attribute__((address_space(3))) uint32_t;
+using lds_i32 = __attribute__((address_space(3))) int32_t;
+using glb_u32 = __attribute__((address_space(1))) const uint32_t;
 
 // Field modes of the PT kernel: byte mode (F <= kPTByteF, signed-weight
 // records), four 6-bit fields per word (F <= kMidF), or per replica.
@@ -136,7 +152,7 @@ __device__ __forceinline__ SignedRec<KIND> signed_from_pt(const PTRec<KIND> &x) 
 // number in cnt4[w]; the deltas are (vsum - F cnt4) / 2 at a flush.
 template <int KIND>
 __device__ __forceinline__ void pt_item_bytes(const PTDev &P, const PTRec<KIND> &x, int d, uint8_t *latb,
-                                              const uint2 *st8, int a, uint32_t vmask, const uint8_t *const *thb,
+                                              const uint2 *st8, int a, uint32_t vmask, const lds_u8 *const *thb,
                                               uint32_t *vsum, uint32_t *cnt4, uint32_t m) {
   using S = Site<KIND>;
   const SignedRec<KIND> sr = signed_from_pt<KIND>(x);
@@ -154,7 +170,7 @@ __device__ __forceinline__ void pt_item_bytes(const PTDev &P, const PTRec<KIND> 
   uint32_t th[8];
 #pragma unroll
   for (int w = 0; w < 8; ++w)
-    th[w] = *reinterpret_cast<const uint16_t *>(thb[w] - (((w < 4 ? V.x : V.y) >> (8 * (w & 3))) & 0xFFu));
+    th[w] = *reinterpret_cast<const lds_u16 *>(thb[w] - (((w < 4 ? V.x : V.y) >> (8 * (w & 3))) & 0xFFu));
   __builtin_amdgcn_sched_barrier(0);
   philox_rounds<5>(ps);
   __builtin_amdgcn_sched_barrier(0);
@@ -175,7 +191,7 @@ __device__ __forceinline__ void pt_item_bytes(const PTDev &P, const PTRec<KIND> 
 #pragma unroll
     for (int w = 0; w < 8; ++w) {
       const uint32_t vb = ((w < 4 ? V.x : V.y) >> (8 * (w & 3))) & 0xFFu;
-      const uint32_t R = *reinterpret_cast<const uint32_t *>(thb[w] - 2 - vb);
+      const uint32_t R = *reinterpret_cast<const lds_u32 *>(thb[w] - 2 - vb);
       const uint32_t uu = (w < 4) ? ((u.v[w] << 16) | (v.v[w] & 0xFFFFu))
                                   : ((u.v[w - 4] & 0xFFFF0000u) | (v.v[w - 4] >> 16));
       if (min(uu, 0xFFFFFFFEu) < R) flip |= 1u << w;
@@ -319,6 +335,64 @@ __device__ __forceinline__ void pt_item(const PTDev &P, const PTRec<KIND> &x, in
     if ((flip >> w) & 1u) dE[w] += 4 * static_cast<int32_t>(sw[w]) - 2 * static_cast<int32_t>(fs);
 }
 
+struct SwapSlot {
+  int rep;    // replica at this lane's slot
+  int e;      // its energy
+};
+
+// One swap phase (Eq. (B1)) as one wave sees it: lane s holds the replica at
+// slot s and its energy as of the last phase; it adds every wave's energy
+// partial of that replica, then the even pairs (r, r + 1), then the odd ones,
+// are decided by both of their lanes from the same inputs.  Wave 0 counts the
+// accepted swaps of pair r in acc[r].  Kept out of line so that its registers
+// do not weigh on the sweep's.
+__device__ __noinline__ SwapSlot swap_phase(int rep_s, int e, int R, int Dmax, bool staged, const lds_u32 *spk,
+                                            glb_u32 *stab, const lds_u32 *sw, const lds_i32 *parts, lds_u32 *acc) {
+  const int lane = static_cast<int>(threadIdx.x & 63u);
+  const bool counts = threadIdx.x < 64u;
+  int32_t de = 0;
+#pragma unroll
+  for (int v = 0; v < kPTMaxWaves; ++v) de += parts[64 * v + (rep_s & 63)];
+  e += de;
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const bool low = ((lane - q) & 1) == 0;       // this lane is slot r of its pair (r, r + 1)
+    const int r = lane - ((lane - q) & 1);
+    const bool valid = r >= 0 && r + 1 < R;
+    const int rc = valid ? r : 0;
+    uint32_t o0 = 0, len = 0;                     // the pair's packed row in LDS: entries past its end are 0
+    if (staged) {
+      o0 = spk[rc];
+      len = spk[rc + 1] - o0;
+    }
+    int pe, prep;                                 // the partner lane's energy and replica
+    if (q == 0) {
+      pe = __builtin_amdgcn_mov_dpp(e, 0xB1, 0xF, 0xF, true);        // quad_perm [1,0,3,2]
+      prep = __builtin_amdgcn_mov_dpp(rep_s, 0xB1, 0xF, 0xF, true);
+    } else {
+      const int src = 4 * (low ? min(lane + 1, 63) : max(lane - 1, 0));
+      pe = __builtin_amdgcn_ds_bpermute(src, e);
+      prep = __builtin_amdgcn_ds_bpermute(src, rep_s);
+    }
+    if (valid) {
+      const int D = low ? pe - e : e - pe;        // E(slot r + 1) - E(slot r)
+      bool ok = D <= 0;
+      if (!ok) {
+        const int Dc = min(D, Dmax);
+        const uint32_t T = staged ? ((static_cast<uint32_t>(Dc) < len) ? spk[o0 + Dc] : 0u)
+                               : stab[static_cast<size_t>(r) * (Dmax + 1) + Dc];
+        ok = min(sw[r], 0xFFFFFFFEu) < T;
+      }
+      if (ok) {
+        e = pe;
+        rep_s = prep;
+        if (low && counts) acc[r] += 1u;
+      }
+    }
+  }
+  return SwapSlot{rep_s, e};
+}
+
 template <int KIND, int MODE>
 __device__ __forceinline__ void pt_ladder(const PTDev &P, const uint32_t *rec, uint64_t *lat, const uint32_t *mtab,
                                           const uint2 *st8, int32_t *E, int32_t *rep_at, int32_t *slot_of,
@@ -342,8 +416,8 @@ __device__ __forceinline__ void pt_ladder(const PTDev &P, const uint32_t *rec, u
   int32_t dE[8];
   uint32_t vsum[8], cnt4[8];                       // byte mode: flip sums (see pt_item_bytes)
   int32_t row[8];                                  // table row offsets of the byte's replicas
-  const uint8_t *thb[8];                           // byte mode: their threshold base addresses
-  const uint8_t *mtabb = reinterpret_cast<const uint8_t *>(mtab) + 8 * F + 2;
+  const lds_u8 *thb[8];                            // byte mode: their threshold base addresses
+  const lds_u8 *mtabb = (const lds_u8 *)(reinterpret_cast<const uint8_t *>(mtab)) + 8 * F + 2;
 #pragma unroll
   for (int w = 0; w < 8; ++w) {
     dE[w] = 0;
@@ -364,24 +438,38 @@ __device__ __forceinline__ void pt_ladder(const PTDev &P, const uint32_t *rec, u
   PTRec<KIND> nxt;
   if (has_first[0]) nxt = load_pt_rec<KIND, MODE>(rec + (cls[0] + (tid >> lgRG)) * S::RW);
   // energy deltas into E (RG is a power of two up to 8, so it divides the 16-lane rows)
+  int32_t *parts = reinterpret_cast<int32_t *>(swapw) + 2 * 64 + kPTMaxWaves * 64;   // 64 words per wave
+  int32_t *part = parts + 64 * wave;
   auto flush = [&](int32_t *d) {
     if constexpr (MODE == kPTBytes) {
 #pragma unroll
-      for (int w = 0; w < 8; ++w) {
-        d[w] = (static_cast<int32_t>(vsum[w]) - F * static_cast<int32_t>(cnt4[w])) / 2;
+      for (int w = 0; w < 8; ++w) {     // vsum - F cnt4 is a multiple of 4
+        d[w] = (static_cast<int32_t>(vsum[w]) - F * static_cast<int32_t>(cnt4[w])) >> 1;
         vsum[w] = 0;
         cnt4[w] = 0;
       }
     }
-    if (RG == 1) flush_deltas<1>(d, E, a, nvalid, lane);
-    else if (RG == 2) flush_deltas<2>(d, E, a, nvalid, lane);
-    else if (RG == 4) flush_deltas<4>(d, E, a, nvalid, lane);
-    else flush_deltas<8>(d, E, a, nvalid, lane);
+    if (RG == 1) flush_partials<1>(d, part, a, lane);
+    else if (RG == 2) flush_partials<2>(d, part, a, lane);
+    else if (RG == 4) flush_partials<4>(d, part, a, lane);
+    else flush_partials<8>(d, part, a, lane);
   };
-  // Swap words (word 0 of the SWAP call (pair r, 0, phase q)) live in LDS: the
-  // first phase's are drawn here, each later phase's by the drawing wave while
-  // wave 0 decides the current phase.
-  const int draw_wave = (nth > 64) ? 1 : 0;
+  // energy change of replica rho since the last swap phase: every wave's partial
+  auto gathered = [&](int rho) {
+    int32_t s = 0;
+#pragma unroll
+    for (int v = 0; v < kPTMaxWaves; ++v) s += parts[64 * v + rho];
+    return s;
+  };
+  // Swap state.  Every wave keeps the whole slot map in registers (lane s: the
+  // replica at slot s, and its energy) and decides every pair itself, from the
+  // same LDS inputs, so no barrier follows the decisions.  Swap words (word 0
+  // of the SWAP call (pair r, 0, phase q)) live in LDS, two phases apart; the
+  // last wave, which has the fewest sweep items, draws them.
+  const int draw_wave = nth / 64 - 1;
+  uint32_t *slotw = swapw + 2 * 64 + 64 * wave;    // this wave's slot-of-replica scratch
+  int rep_s = lane;                                 // replica at slot `lane`
+  int e = E[lane];                                  // and its energy as of the last swap phase
   if (wave == draw_wave && lane + 1 < R)
     swapw[lane] = philox4x32_10(static_cast<uint32_t>(lane), 0u, 0u, kStreamSwap << 24, P.seed_lo, P.seed_hi).v[0];
   uint32_t phase = 0;
@@ -409,55 +497,30 @@ __device__ __forceinline__ void pt_ladder(const PTDev &P, const uint32_t *rec, u
           pt_item<KIND, SWAR>(P, load_pt_rec<KIND, MODE>(rec + d * S::RW), d, latb, mtab, a, vmask, row, dE, mm);
         }
       }
+      // In a sweep that ends in a swap phase: the last wave draws the next phase's
+      // words in class 1 (their buffer was last read in the previous swap phase,
+      // which ended before this sweep's class-0 barrier), and every wave stores
+      // its energy deltas ahead of the class-3 barrier (their array was last read
+      // in the previous swap phase too).
+      if (c == 1 && swap_now && wave == draw_wave && lane + 1 < R)
+        swapw[64 * ((phase + 1) & 1) + lane] =
+            philox4x32_10(static_cast<uint32_t>(lane), 0u, phase + 1, kStreamSwap << 24, P.seed_lo, P.seed_hi).v[0];
+      if (c == 3 && swap_now) flush(dE);
       __syncthreads();
     }
     if (swap_now) {
-      flush(dE);
-      __syncthreads();
-      if (wave == 0) {
-        for (int q = 0; q < 2; ++q) {
-          const int rr = 2 * lane + q;
-          if (rr + 1 < R) {
-            const int lo_rep = rep_at[rr], hi_rep = rep_at[rr + 1];
-            const int D = E[hi_rep] - E[lo_rep];
-            bool ok = D <= 0;
-            if (!ok) {
-              const int Dc = min(D, P.Dmax);
-              uint32_t T;
-              if (spk) {      // packed row in LDS: entries past its end are 0
-                const uint32_t o0 = spk[rr], o1 = spk[rr + 1];
-                T = (static_cast<uint32_t>(Dc) < o1 - o0) ? spk[o0 + Dc] : 0u;
-              } else {
-                T = P.stab[static_cast<size_t>(rr) * (P.Dmax + 1) + Dc];
-              }
-              ok = min(swapw[rr], 0xFFFFFFFEu) < T;
-            }
-            if (ok) {
-              rep_at[rr] = hi_rep;
-              rep_at[rr + 1] = lo_rep;
-              slot_of[hi_rep] = rr;
-              slot_of[lo_rep] = rr + 1;
-              acc[rr] += 1;
-            }
-          }
-          wave_sync();
-        }
-      }
-      // the words of the next swap phase, drawn while wave 0 decides this one
-      if (wave == draw_wave && draw_wave != 0 && lane + 1 < R)
-        swapw[64 + lane] = philox4x32_10(static_cast<uint32_t>(lane), 0u, phase + 1, kStreamSwap << 24, P.seed_lo,
-                                         P.seed_hi).v[0];
-      __syncthreads();
-      if (wave == draw_wave && lane + 1 < R) {
-        if (draw_wave == 0)
-          swapw[lane] = philox4x32_10(static_cast<uint32_t>(lane), 0u, phase + 1, kStreamSwap << 24, P.seed_lo,
-                                      P.seed_hi).v[0];
-        else
-          swapw[lane] = swapw[64 + lane];
-      }
+      // (an LDS null pointer is not zero: the staging flag travels on its own)
+      const SwapSlot ns = swap_phase(rep_s, e, R, P.Dmax, spk != nullptr, (const lds_u32 *)(spk ? spk : swapw),
+                                     (glb_u32 *)P.stab, (const lds_u32 *)(swapw + 64 * (phase & 1)),
+                                     (const lds_i32 *)parts, (lds_u32 *)acc);
+      rep_s = ns.rep;
+      e = ns.e;
+      // this thread's replicas' new slots, through the wave's own scratch
+      if (lane < R) slotw[rep_s & 63] = static_cast<uint32_t>(lane);
+      wave_sync();
 #pragma unroll
       for (int w = 0; w < 8; ++w) {
-        row[w] = (w < nvalid) ? slot_of[8 * a + w] * width : 0;
+        row[w] = (w < nvalid) ? static_cast<int32_t>(slotw[8 * a + w]) * width : 0;
         thb[w] = mtabb + 4 * row[w];
       }
       ++phase;
@@ -465,11 +528,19 @@ __device__ __forceinline__ void pt_ladder(const PTDev &P, const uint32_t *rec, u
   }
   flush(dE);                                 // deltas of the sweeps after the last swap phase
   __syncthreads();
+  if (wave == 0) {                           // energies, slot map and swap counts for the results
+    e += gathered(rep_s & 63);
+    if (lane < R) E[rep_s] = e;
+    rep_at[lane] = rep_s;
+    slot_of[rep_s & 63] = lane;
+  }
+  __syncthreads();
 }
 
 // Dynamic LDS: [byte-spread table: kPTSpreadWords][rec_cap words][lat_cap u64][mtab_cap words]
-// [E, rep_at, slot_of, acc: 64 each][swap words: 2 x 64][spack_cap words: the packed swap
-// table when it is staged].
+// [E, rep_at, slot_of, acc: 64 each][swap words: 2 x 64][slot scratch: 64 per wave]
+// [energy partials: 64 per wave]
+// [spack_cap words: the packed swap table when it is staged].
 __global__ __launch_bounds__(64 * kPTMaxWaves) void pt_kernel(const PTDev *__restrict__ pts, int rec_cap, int lat_cap,
                                                               int mtab_cap, int spack_cap) {
   extern __shared__ __align__(16) uint32_t smem[];
@@ -483,8 +554,9 @@ __global__ __launch_bounds__(64 * kPTMaxWaves) void pt_kernel(const PTDev *__res
   int32_t *slot_of = rep_at + 64;
   uint32_t *acc = reinterpret_cast<uint32_t *>(slot_of + 64);
   uint32_t *swapw = acc + 64;
-  uint32_t *spk = reinterpret_cast<uint32_t *>(E) + kPTLadderWords;   // after swapw[2 x 64]
-  static_assert(kPTLadderWords == 4 * 64 + 2 * 64, "E, rep_at, slot_of, acc, then two phases of swap words");
+  uint32_t *spk = reinterpret_cast<uint32_t *>(E) + kPTLadderWords;   // after the wave scratch
+  static_assert(kPTLadderWords == 4 * 64 + 2 * 64 + 2 * kPTMaxWaves * 64,
+                "E, rep_at, slot_of, acc, two phases of swap words, a slot scratch and an energy partial per wave");
   const int tid = threadIdx.x, nth = blockDim.x;
   const int rw = rec_words_of(P.kind);
   for (int x = tid; x < kSpreadEntries; x += nth) {
@@ -503,6 +575,8 @@ __global__ __launch_bounds__(64 * kPTMaxWaves) void pt_kernel(const PTDev *__res
   const bool staged = spack_cap > 0 && P.spack_words <= spack_cap;
   if (staged)
     for (int i = tid; i < P.spack_words; i += nth) spk[i] = P.spack[i];
+  for (int r = tid; r < kPTMaxWaves * 64; r += nth)      // the waves' energy partials
+    reinterpret_cast<int32_t *>(swapw)[2 * 64 + kPTMaxWaves * 64 + r] = 0;
   for (int r = tid; r < 64; r += nth) {
     rep_at[r] = r;
     slot_of[r] = r;
