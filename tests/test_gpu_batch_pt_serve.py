@@ -193,6 +193,26 @@ def test_pt_swap_table_in_lds_or_device_memory(sqa, monkeypatch, stage):
         assert acc.sum() > 0
 
 
+@pytest.mark.parametrize("waves", ["1", "3", "10"])
+def test_pt_results_do_not_depend_on_wave_count(sqa, monkeypatch, waves):
+    """Every wave decides the swap phases itself and keeps its own energy partials:
+    one wave (several items per thread), three, or the most a ladder may use give
+    the oracle's ladder, with replica bytes from one to eight and swap intervals of
+    one and three sweeps."""
+    monkeypatch.setenv("SQA_PT_WAVES", waves)
+    print(f"PT waves={waves}", flush=True)
+    for kind, N, R, sps in ((ME, 7, 32, 1), (LHZ, 8, 64, 1), (ME, 5, 9, 3), (LHZ, 6, 5, 1)):
+        J = sk_instance(N, 770 + N)
+        seed = 0x9900 + 7 * N + R
+        dev = sqa.PT(kind, J, -2, 0.2, 4.0, R, 90, sps, seed).run()
+        spins, E, rep, acc = dev.read()
+        emb = O.Embedding(kind, J, -2)
+        ospins, oE, orep, oacc = O.pt_run(emb, O.pt_ladder(0.2, 4.0, R), 90, sps, seed)
+        assert (rep == orep).all() and (spins == ospins[orep]).all()
+        assert (E == oE[orep]).all() and (acc == oacc).all()
+        assert acc.sum() > 0
+
+
 def test_pt_workload_shape_sampled(sqa):
     """PT workload shape (N = 24, 32 temperatures, both embeddings) in one batched
     launch, at a reduced sweep count the oracle can finish: two instances exact."""
