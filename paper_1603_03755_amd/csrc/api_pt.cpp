@@ -91,6 +91,10 @@ PTShape pt_shape(const std::vector<const pt_handle *> &hs) {
   const char *env = std::getenv("SQA_PT_WAVES");
   s.waves = env ? std::max(1, std::min(kPTMaxWaves, std::atoi(env)))
                 : std::max(2, std::min(kPTMaxWaves, (max_items + 63) / 64));
+  // the byte mode sums a thread's items in 16-bit halves, emptied before any
+  // colour class that could take them past 256 items: a class gives a thread at
+  // most 256 of them
+  s.waves = std::max(s.waves, std::min(kPTMaxWaves, (max_items + 256 * 64 - 1) / (256 * 64)));
   return s;
 }
 

@@ -109,8 +109,8 @@ constexpr int kPTByteF = 31;
 constexpr int kPTLadderWords = 4 * 64 + 2 * 64 + 2 * kPTMaxWaves * 64;
 // LDS words of the PT kernel's byte tables: kSpreadEntries uint2 spreads (bit i
 // of the byte -> value 4 in byte i of a nibble's word), then kSpreadEntries
-// uint2 byte-permute selectors (byte i of a nibble's word selects byte i where
-// bit i is set, zero elsewhere).
+// uint2 byte-permute selectors (byte i of a nibble's word selects byte i of the
+// second source where bit i is set, byte i of the first elsewhere).
 constexpr int kPTSpreadWords = 4 * kSpreadEntries;
 
 // SQA update move of a handle.

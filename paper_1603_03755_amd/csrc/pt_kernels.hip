@@ -147,13 +147,15 @@ __device__ __forceinline__ SignedRec<KIND> signed_from_pt(const PTRec<KIND> &x) 
 // V_w = 4F - 4F_site + 8 S_w in [0, 8F]; its threshold's top half is the u16 at
 // thb[w] - V_w (thb[w] = the table's byte address + 4 row[w] + 8F + 2, so this is
 // entry row[w] + F_site + F - 2 S_w), and a flip changes the energy by
-// 4 S_w - 2 F_site = (V_w - 4F) / 2.  The thread sums V_w over its flips in
-// vsum[w] (the flipped replicas' bytes picked by a byte permute) and 4 x their
-// number in cnt4[w]; the deltas are (vsum - F cnt4) / 2 at a flush.
+// 4 S_w - 2 F_site = (V_w - 4F) / 2.  One byte permute per word takes V_w for
+// the flipped replicas and 4F for the others (selectors from a table); the
+// thread adds those bytes into 16-bit halves (vpk: replicas 0 and 2, 1 and 3,
+// 4 and 6, 5 and 7) and counts its items in nit, so the sum of the byte of
+// replica w minus 4F nit is the sum of V_w - 4F over its flips.
 template <int KIND>
 __device__ __forceinline__ void pt_item_bytes(const PTDev &P, const PTRec<KIND> &x, int d, uint8_t *latb,
                                               const uint2 *st8, int a, uint32_t vmask, const lds_u8 *const *thb,
-                                              uint32_t *vsum, uint32_t *cnt4, uint32_t m) {
+                                              uint32_t f4, uint32_t *vpk, uint32_t &nit, uint32_t m) {
   using S = Site<KIND>;
   const SignedRec<KIND> sr = signed_from_pt<KIND>(x);
   // own and partner bytes (LDS reads), the first Philox rounds while they are in flight
@@ -199,15 +201,13 @@ __device__ __forceinline__ void pt_item_bytes(const PTDev &P, const PTRec<KIND> 
   }
   flip &= vmask;
   latb[8 * d + a] = static_cast<uint8_t>(own ^ flip);
-  const uint2 fsp = st8[flip], fsel = st8[kSpreadEntries + flip];
-  const uint32_t t_lo = __builtin_amdgcn_perm(V.x, V.x, fsel.x), t_hi = __builtin_amdgcn_perm(V.y, V.y, fsel.y);
-#pragma unroll
-  for (int w = 0; w < 4; ++w) {
-    vsum[w] += (t_lo >> (8 * w)) & 0xFFu;
-    vsum[w + 4] += (t_hi >> (8 * w)) & 0xFFu;
-    cnt4[w] += (fsp.x >> (8 * w)) & 0xFFu;
-    cnt4[w + 4] += (fsp.y >> (8 * w)) & 0xFFu;
-  }
+  const uint2 fsel = st8[kSpreadEntries + flip];
+  const uint32_t t_lo = __builtin_amdgcn_perm(f4, V.x, fsel.x), t_hi = __builtin_amdgcn_perm(f4, V.y, fsel.y);
+  vpk[0] += t_lo & 0x00FF00FFu;
+  vpk[1] += (t_lo >> 8) & 0x00FF00FFu;
+  vpk[2] += t_hi & 0x00FF00FFu;
+  vpk[3] += (t_hi >> 8) & 0x00FF00FFu;
+  ++nit;
 }
 
 template <int KIND, bool SWAR>
@@ -414,15 +414,19 @@ __device__ __forceinline__ void pt_ladder(const PTDev &P, const uint32_t *rec, u
   const uint32_t vmask = (1u << nvalid) - 1u;
   uint8_t *latb = reinterpret_cast<uint8_t *>(lat);
   int32_t dE[8];
-  uint32_t vsum[8], cnt4[8];                       // byte mode: flip sums (see pt_item_bytes)
+  uint32_t vsum[8], vpk[4], nit = 0;                // byte mode: byte sums (see pt_item_bytes)
+  int pend = 0;                                     // byte mode: most items per thread since vpk was emptied
+  int pmax = 0;                                     // most items of a thread in one colour class (<= 256)
+  const uint32_t f4 = static_cast<uint32_t>(4 * F) * 0x01010101u;
   int32_t row[8];                                  // table row offsets of the byte's replicas
   const lds_u8 *thb[8];                            // byte mode: their threshold base addresses
   const lds_u8 *mtabb = (const lds_u8 *)(reinterpret_cast<const uint8_t *>(mtab)) + 8 * F + 2;
 #pragma unroll
+  for (int w = 0; w < 4; ++w) vpk[w] = 0;
+#pragma unroll
   for (int w = 0; w < 8; ++w) {
     dE[w] = 0;
     vsum[w] = 0;
-    cnt4[w] = 0;
     row[w] = (w < nvalid) ? slot_of[8 * a + w] * width : 0;
     thb[w] = mtabb + 4 * row[w];
   }
@@ -434,20 +438,37 @@ __device__ __forceinline__ void pt_ladder(const PTDev &P, const uint32_t *rec, u
   for (int c = 0; c < 5; ++c) cls[c] = P.cls[c];
   bool has_first[4];
 #pragma unroll
-  for (int c = 0; c < 4; ++c) has_first[c] = group_live && tid < ((cls[c + 1] - cls[c]) << lgRG);
+  for (int c = 0; c < 4; ++c) {
+    has_first[c] = group_live && tid < ((cls[c + 1] - cls[c]) << lgRG);
+    pmax = max(pmax, (((cls[c + 1] - cls[c]) << lgRG) + nth - 1) / nth);
+  }
   PTRec<KIND> nxt;
   if (has_first[0]) nxt = load_pt_rec<KIND, MODE>(rec + (cls[0] + (tid >> lgRG)) * S::RW);
   // energy deltas into E (RG is a power of two up to 8, so it divides the 16-lane rows)
   int32_t *parts = reinterpret_cast<int32_t *>(swapw) + 2 * 64 + kPTMaxWaves * 64;   // 64 words per wave
   int32_t *part = parts + 64 * wave;
+  // byte mode: the 16-bit halves into the per-replica sums (a half gains at most
+  // 8F <= 248 per item, so 256 items fit)
+  auto widen = [&]() {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int w = (k & 1) + 4 * (k >> 1);      // halves of vpk[k]: replicas w and w + 2
+      vsum[w] += vpk[k] & 0xFFFFu;
+      vsum[w + 2] += vpk[k] >> 16;
+      vpk[k] = 0;
+    }
+    pend = 0;
+  };
   auto flush = [&](int32_t *d) {
     if constexpr (MODE == kPTBytes) {
+      widen();
+      const uint32_t bias = 4u * static_cast<uint32_t>(F) * nit;
 #pragma unroll
-      for (int w = 0; w < 8; ++w) {     // vsum - F cnt4 is a multiple of 4
-        d[w] = (static_cast<int32_t>(vsum[w]) - F * static_cast<int32_t>(cnt4[w])) >> 1;
+      for (int w = 0; w < 8; ++w) {     // vsum - 4F nit is a multiple of 4
+        d[w] = static_cast<int32_t>(vsum[w] - bias) >> 1;
         vsum[w] = 0;
-        cnt4[w] = 0;
       }
+      nit = 0;
     }
     if (RG == 1) flush_partials<1>(d, part, a, lane);
     else if (RG == 2) flush_partials<2>(d, part, a, lane);
@@ -484,11 +505,13 @@ __device__ __forceinline__ void pt_ladder(const PTDev &P, const uint32_t *rec, u
       const int cn = (c + 1) & 3;
       if (has_first[cn]) nxt = load_pt_rec<KIND, MODE>(rec + (cls[cn] + (tid >> lgRG)) * S::RW);
       if constexpr (MODE == kPTBytes) {
-        if (has_first[c]) pt_item_bytes<KIND>(P, cur, lo + (tid >> lgRG), latb, st8, a, vmask, thb, vsum, cnt4, mm);
+        if (pend + pmax > 256) widen();
+        pend += pmax;
+        if (has_first[c]) pt_item_bytes<KIND>(P, cur, lo + (tid >> lgRG), latb, st8, a, vmask, thb, f4, vpk, nit, mm);
         for (int it = tid + nth; group_live && it < cnt; it += nth) {
           const int d = lo + (it >> lgRG);
-          pt_item_bytes<KIND>(P, load_pt_rec<KIND, MODE>(rec + d * S::RW), d, latb, st8, a, vmask, thb, vsum, cnt4,
-                              mm);
+          pt_item_bytes<KIND>(P, load_pt_rec<KIND, MODE>(rec + d * S::RW), d, latb, st8, a, vmask, thb, f4, vpk,
+                              nit, mm);
         }
       } else {
         if (has_first[c]) pt_item<KIND, SWAR>(P, cur, lo + (tid >> lgRG), latb, mtab, a, vmask, row, dE, mm);
@@ -564,8 +587,8 @@ __global__ __launch_bounds__(64 * kPTMaxWaves) void pt_kernel(const PTDev *__res
     st8[x] = make_uint2(spread8(lo) << 2, spread8(hi) << 2);
     uint32_t sl = 0, sh = 0;
     for (int i = 0; i < 4; ++i) {
-      sl |= (((lo >> i) & 1u) ? static_cast<uint32_t>(i) : 0x0Cu) << (8 * i);
-      sh |= (((hi >> i) & 1u) ? static_cast<uint32_t>(i) : 0x0Cu) << (8 * i);
+      sl |= (((lo >> i) & 1u) ? static_cast<uint32_t>(i) : 4u + i) << (8 * i);
+      sh |= (((hi >> i) & 1u) ? static_cast<uint32_t>(i) : 4u + i) << (8 * i);
     }
     st8[kSpreadEntries + x] = make_uint2(sl, sh);
   }
