@@ -87,10 +87,11 @@ PTShape pt_shape(const std::vector<const pt_handle *> &hs) {
   const char *stage = std::getenv("SQA_PT_STAGE_SWAPS");
   if (s.lds() > kMaxLds || (stage && std::atoi(stage) == 0)) s.spack_cap = 0;
   // one workgroup owns a ladder: enough waves that the largest colour class is one
-  // pass, at most kPTMaxWaves (the kernel's launch bound; larger classes loop)
+  // pass, and one more without items (the last wave draws the swap words, off the
+  // sweep's path), at most kPTMaxWaves (the kernel's launch bound; larger classes loop)
   const char *env = std::getenv("SQA_PT_WAVES");
   s.waves = env ? std::max(1, std::min(kPTMaxWaves, std::atoi(env)))
-                : std::max(2, std::min(kPTMaxWaves, (max_items + 63) / 64));
+                : std::max(2, std::min(kPTMaxWaves, (max_items + 63) / 64 + 1));
   // the byte mode sums a thread's items in 16-bit halves, emptied before any
   // colour class that could take them past 256 items: a class gives a thread at
   // most 256 of them
