@@ -213,6 +213,27 @@ def test_pt_results_do_not_depend_on_wave_count(sqa, monkeypatch, waves):
         assert acc.sum() > 0
 
 
+@pytest.mark.parametrize("kind,N,R,sweeps,sps,waves", [(LHZ, 6, 16, 400, 150, None), (ME, 5, 32, 300, 1000, None),
+                                                       (LHZ, 10, 64, 300, 120, "1"), (ME, 7, 24, 260, 97, "1")])
+def test_pt_long_intervals_between_swaps(sqa, monkeypatch, kind, N, R, sweeps, sps, waves):
+    """Many sweeps between swap phases (and none at all when the interval exceeds the
+    run): a thread's 16-bit flip sums are emptied into 32-bit sums many times before
+    an energy reduction; with one wave a thread also takes several items per class."""
+    if waves is None:
+        monkeypatch.delenv("SQA_PT_WAVES", raising=False)
+    else:
+        monkeypatch.setenv("SQA_PT_WAVES", waves)
+    print(f"PT long swap interval kind={kind} N={N} R={R} sweeps={sweeps} sps={sps} waves={waves}", flush=True)
+    J = sk_instance(N, 790 + N)
+    seed = 0x9A00 + 3 * N + R
+    dev = sqa.PT(kind, J, -2, 0.2, 4.0, R, sweeps, sps, seed).run()
+    spins, E, rep, acc = dev.read()
+    emb = O.Embedding(kind, J, -2)
+    ospins, oE, orep, oacc = O.pt_run(emb, O.pt_ladder(0.2, 4.0, R), sweeps, sps, seed)
+    assert (rep == orep).all() and (spins == ospins[orep]).all()
+    assert (E == oE[orep]).all() and (acc == oacc).all()
+
+
 def test_pt_workload_shape_sampled(sqa):
     """PT workload shape (N = 24, 32 temperatures, both embeddings) in one batched
     launch, at a reduced sweep count the oracle can finish: two instances exact."""
