@@ -549,6 +549,10 @@ __device__ __forceinline__ void pt_ladder(const PTDev &P, const uint32_t *rec, u
       ++phase;
     }
   }
+  // Every wave reads all waves' partials inside a swap phase, and no barrier
+  // follows it: the last phase must be over in every wave before any wave
+  // overwrites its partials with the deltas of the sweeps after it.
+  __syncthreads();
   flush(dE);                                 // deltas of the sweeps after the last swap phase
   __syncthreads();
   if (wave == 0) {                           // energies, slot map and swap counts for the results
