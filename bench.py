@@ -321,16 +321,41 @@ def copy_calibration():
     print(json.dumps({"copy_calibration_bytes": n}), flush=True)
 
 
+VALU_CALIB_OPS = {0: "v_bitop3_b32", 1: "v_mad_u64_u32", 2: "v_pk_mad_u16"}
+
+
+def calib_lib():
+    """The VALU issue-rate probe, libsqa_calib.so (built beside libsqa.so; not part of
+    the library's interface)."""
+    import ctypes as C
+    path = os.path.join(ROOT, "paper_1603_03755_amd", "libsqa_calib.so")
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_1603_03755_amd.build`")
+    L = C.CDLL(path)
+    L.sqa_calib_valu_issue.restype = C.c_int
+    L.sqa_calib_valu_issue.argtypes = [C.c_int32, C.c_int32, C.POINTER(C.c_float), C.POINTER(C.c_double)]
+    return L
+
+
+def valu_issue(op: int, iters: int):
+    """(kernel ms, VALU wave-instructions) of one issue-rate launch of instruction kind `op`."""
+    import ctypes as C
+    ms, instr = C.c_float(), C.c_double()
+    rc = calib_lib().sqa_calib_valu_issue(op, iters, C.byref(ms), C.byref(instr))
+    if rc != 0:
+        raise RuntimeError(f"sqa_calib_valu_issue({op}, {iters}) failed with code {rc}")
+    return ms.value, instr.value
+
+
 def valu_calibration():
     """Issue rate of each instruction kind, in wave-instructions per SIMD per clock at
     2.4 GHz and in 32-bit lane-ops/s, against PEAK_LANE_OPS (0.25 per SIMD per clock)."""
     import torch
-    from paper_1603_03755_amd import sqa as S
     torch.cuda.set_device(0)
     simds = 4 * torch.cuda.get_device_properties(0).multi_processor_count
     out = {}
-    for op, name in S.VALU_CALIB_OPS.items():
-        ms, instr = S.sqa_valu_calibrate(op, 100_000)
+    for op, name in VALU_CALIB_OPS.items():
+        ms, instr = valu_issue(op, 100_000)
         rate = instr / (ms * 1e-3)
         out[name] = {"kernel_ms": ms, "wave_instructions": instr,
                      "per_simd_per_clock_at_2p4GHz": rate / (simds * 2.4e9),

@@ -66,7 +66,8 @@ typedef enum {
   SQA_ERR_DEVICE = -3,      /* a HIP call failed; the handle is poisoned */
   SQA_ERR_UNSUPPORTED = -4, /* valid for the method, outside this library's limits */
   SQA_ERR_BUSY = -5,        /* server: no slot / memory right now */
-  SQA_ERR_NOT_READY = -6    /* server: result not finished yet */
+  SQA_ERR_NOT_READY = -6,   /* server: result not finished yet */
+  SQA_ERR_CANCELLED = -7    /* server: the job was cancelled before it finished */
 } sqa_status;
 
 typedef enum { SQA_EMB_ME = 0, SQA_EMB_LHZ = 1, SQA_EMB_ME_CHIMERA = 2 } sqa_emb_kind;
@@ -115,6 +116,20 @@ typedef struct {
   int32_t move;          /* sqa_move; 0 = SQA_MOVE_METROPOLIS */
 } sqa_schedule;
 
+/* Device-memory provider.  alloc(bytes, ctx) returns device memory of at least
+ * `bytes` bytes on the current device, aligned to 256 bytes, or NULL when it has
+ * none; free(ptr, ctx) gives it back.  A handle takes all of its device buffers
+ * from it (site records, tables, lattice, energies, logical problem, decoder
+ * scratch) and frees them in sqa_destroy, after its queued work has finished;
+ * the server also takes its launch scratch from it.  The callbacks may be called
+ * from the server's worker thread.  The struct is copied; `ctx` must stay valid
+ * while anything created with it lives.  NULL = hipMalloc / hipFree. */
+typedef struct {
+  void *(*alloc)(size_t bytes, void *ctx);
+  void (*free)(void *ptr, void *ctx);
+  void *ctx;
+} sqa_allocator;
+
 typedef struct sqa_handle sqa_handle;
 typedef struct sqa_batch sqa_batch;
 typedef struct pt_handle pt_handle;
@@ -135,15 +150,18 @@ typedef struct {
 /* ---------------------------------------------------------------- SQA */
 
 /* Builds the embedding (Sec. II A / II B), its four-colour update classes,
- * the per-sweep acceptance-threshold table and the device buffers.  No
- * device work is queued; the lattice is initialised by the first anneal.
+ * the per-sweep acceptance-threshold table and the device buffers, which come
+ * from `allocator` (NULL = hipMalloc): one block for the handle, and a second
+ * one later for the scratch of the LHZ decoders.  No device work is queued;
+ * the lattice is initialised by the first anneal.
  * Errors: SQA_ERR_INVALID (null pointers, n out of range, slices odd > 1,
- * sweeps < 1, replicas out of range, beta <= 0, negative Gamma),
- * SQA_ERR_UNSUPPORTED (LHZ with h != 0, slices > 64, a site whose
- * |h| + sum of |incident coefficients| exceeds 255),
- * SQA_ERR_OOM, SQA_ERR_DEVICE. */
+ * sweeps < 1, replicas out of range, beta <= 0, negative Gamma, an allocator
+ * without both callbacks), SQA_ERR_UNSUPPORTED (LHZ with h != 0, slices > 64,
+ * a site whose |h| + sum of |incident coefficients| exceeds 255),
+ * SQA_ERR_OOM (the allocator returned NULL or hipMalloc failed: nothing is
+ * left allocated and *out is NULL), SQA_ERR_DEVICE. */
 SQA_API sqa_status sqa_create(const sqa_problem *problem, const sqa_embedding *embedding,
-                      const sqa_schedule *schedule, sqa_handle **out);
+                      const sqa_schedule *schedule, const sqa_allocator *allocator, sqa_handle **out);
 
 /* Runs sweeps 0..M-1 from the seeded initial state (Philox INIT stream) and
  * computes per-slice energies.  Asynchronous on `stream`. */
@@ -272,6 +290,10 @@ SQA_API sqa_status sqa_export_table(sqa_handle *h, uint32_t *out, size_t len, in
 SQA_API sqa_status sqa_export_wolff_tables(sqa_handle *h, uint32_t *padd_out, size_t padd_len, uint32_t *acc_out,
                                    size_t acc_len, int32_t *rows_out, int32_t *width_out);
 
+/* Device bytes the handle holds through its allocator: its own block plus the
+ * decoder scratch allocated so far. */
+SQA_API sqa_status sqa_handle_device_bytes(sqa_handle *h, size_t *bytes_out);
+
 /* Shape queries. */
 SQA_API int64_t sqa_physical_sites(int32_t kind, int32_t n);
 SQA_API sqa_status sqa_handle_info(sqa_handle *h, int32_t *sites, int32_t *slices, int32_t *replicas,
@@ -342,49 +364,57 @@ SQA_API sqa_status pt_run(const sqa_problem *problem, const sqa_embedding *embed
 
 /* ------------------------------------------------------------- serving */
 
-/* Continuous batching.  Jobs are admitted while their device bytes fit in
- * `hbm_budget_bytes` and fewer than `max_slots` are resident; admitted jobs
- * advance together, `chunk_sweeps` sweeps per persistent launch, and a job
- * that finishes frees its slot and memory for the next waiting job at the
+/* Continuous batching.  Jobs wait in FIFO order and are admitted while their
+ * device bytes fit in `hbm_budget_bytes` and fewer than `max_slots` are
+ * resident; admitted jobs advance together, `chunk_sweeps` sweeps per
+ * persistent launch, and a job that finishes is decoded on the device, copied
+ * to the host, and frees its slot and memory for the next waiting job at the
  * following launch boundary.  Results are bit-identical to running the job
- * alone.  A server thread owns the device work. */
+ * alone.  Device memory (job handles, decoder scratch, the shared launch
+ * scratch) comes from `allocator` (NULL = hipMalloc).  Admission counts it
+ * exactly: a job is charged its handle's block, its decoder's scratch and its
+ * entries in the launch scratch, each rounded up to 4 KiB
+ * (sqa_server_job_bytes), and the launch scratch's fixed part (4 KiB) is
+ * charged once; the sum of what the allocator holds never exceeds the budget.
+ * A server thread owns the device work. */
 SQA_API sqa_status sqa_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t chunk_sweeps,
-                             sqa_server **out);
-/* Queues a job (inputs deep-copied).  SQA_ERR_INVALID for a bad job,
- * SQA_ERR_BUSY if the job alone exceeds the budget. */
+                             const sqa_allocator *allocator, sqa_server **out);
+/* Queues a job (inputs deep-copied; the embedding, layout and tables are built
+ * here, on the caller's thread).  `decode` picks the decoder run on the device
+ * when the job finishes (Eq. (4), Eq. (5), Sec. IV A-D; tree parents are
+ * copied); NULL = majority vote of the chains (ME, ME on Chimera) or
+ * minimum-weight decoding (LHZ, n <= 32; chain-tree decoding, Eq. (A1), above),
+ * on slice 0.  SQA_ERR_INVALID for a bad job or decoder, SQA_ERR_BUSY if the
+ * job alone exceeds the budget. */
 SQA_API sqa_status sqa_server_submit(sqa_server *s, const sqa_problem *problem,
                              const sqa_embedding *embedding, const sqa_schedule *schedule,
-                             uint64_t *ticket);
-/* *done = 1 once the result is on the host. */
+                             const sqa_decode_params *decode, uint64_t *ticket);
+/* Device bytes admission charges for a queued or running job. */
+SQA_API sqa_status sqa_server_job_bytes(sqa_server *s, uint64_t ticket, size_t *bytes_out);
+/* Cancels a job: a waiting job is dropped at once, a running one at the next
+ * launch boundary (its device memory is then freed).  Its wait and result then
+ * return SQA_ERR_CANCELLED (result releases the ticket).  SQA_ERR_INVALID for an
+ * unknown ticket or a job that has already finished. */
+SQA_API sqa_status sqa_server_cancel(sqa_server *s, uint64_t ticket);
+/* *done = 1 once the job has finished (or been cancelled, or failed). */
 SQA_API sqa_status sqa_server_poll(sqa_server *s, uint64_t ticket, int32_t *done);
-/* Blocks until done (timeout_ms < 0: forever); SQA_ERR_NOT_READY on timeout. */
+/* Blocks until done (timeout_ms < 0: forever); SQA_ERR_NOT_READY on timeout,
+ * else the job's status. */
 SQA_API sqa_status sqa_server_wait(sqa_server *s, uint64_t ticket, int32_t timeout_ms);
-/* Copies a finished job's spins [replica][slice][site] and energies
- * [replica][slice]; either may be NULL.  Latency in seconds from submit to
- * result-on-host goes to *latency_s (may be NULL).  The ticket is released. */
+/* Copies a finished job's spins [replica][slice][site], energies
+ * [replica][slice], decoded logical states [replica][n] and their energies
+ * under Eq. (1) [replica]; any output may be NULL.  Latency in seconds from
+ * submit to result-on-host goes to *latency_s (may be NULL).  The ticket is
+ * released. */
 SQA_API sqa_status sqa_server_result(sqa_server *s, uint64_t ticket, int8_t *spins, size_t spins_len,
-                             int32_t *energies, size_t energies_len, double *latency_s);
+                             int32_t *energies, size_t energies_len, int8_t *logical, size_t logical_len,
+                             int32_t *logical_energies, size_t logical_energies_len, double *latency_s);
 /* Counters: completed jobs, device launches, peak resident bytes. */
 SQA_API sqa_status sqa_server_stats(sqa_server *s, uint64_t *completed, uint64_t *launches,
                             uint64_t *peak_bytes);
 SQA_API void sqa_server_destroy(sqa_server *s);
 
 /* ------------------------------------------------------------- misc */
-/* ---------------------------------------------------------- calibration */
-/* Measures the VALU issue rate of one instruction type on the current device,
- * for the integer-ALU roofline of the sweep kernels (their peak is derived from
- * the CU count and clock; this checks that the instruction kinds the loops are
- * built from issue at that rate).  op: 0 = three-input XOR (v_bitop3_b32),
- * 1 = widening 32x32 -> 64-bit multiply-add (v_mad_u64_u32, Philox's multiply),
- * 2 = packed 16-bit multiply-add (v_pk_mad_u16).  Launches eight waves per SIMD
- * on every CU, each lane running `iters` iterations of eight independent
- * chains; synchronous (device-wide).  Returns the timed launch's duration in
- * *ms_out and its VALU wave-instructions of the chains in
- * *wave_instructions_out.  Allocates and frees a small device buffer.
- * Errors: SQA_ERR_INVALID (op outside 0..2, iters <= 0, null outputs),
- * SQA_ERR_OOM, SQA_ERR_DEVICE. */
-SQA_API sqa_status sqa_valu_calibrate(int32_t op, int32_t iters, float *ms_out, double *wave_instructions_out);
-
 SQA_API const char *sqa_last_error(void);
 SQA_API const char *sqa_version(void);
 

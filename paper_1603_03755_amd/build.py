@@ -1,4 +1,6 @@
-"""Builds the gfx950 library paper_1603_03755_amd/libsqa.so with hipcc.
+"""Builds the gfx950 library paper_1603_03755_amd/libsqa.so with hipcc, and
+beside it libsqa_calib.so, the benchmark's VALU issue-rate probe (not part of
+the library's interface).
 
 Usage: python -m paper_1603_03755_amd.build   (or build() from Python)
 """
@@ -12,7 +14,10 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsqa.so")
-SOURCES = ["sqa_kernels.hip", "pt_kernels.hip", "decode_kernels.hip", "calib_kernels.hip", "host_core.cpp", "api_sqa.cpp", "api_pt.cpp", "api_server.cpp"]
+CALIB_LIB = os.path.join(HERE, "libsqa_calib.so")
+SOURCES = ["sqa_kernels.hip", "pt_kernels.hip", "decode_kernels.hip", "host_core.cpp", "api_sqa.cpp", "api_pt.cpp",
+           "api_server.cpp"]
+CALIB_SOURCES = ["calib_kernels.hip"]
 ARCH = "gfx950"
 
 
@@ -23,13 +28,9 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False) -> str:
+def _link(sources, lib, build_dir, common, verbose):
     objs = []
-    build_dir = os.path.join(HERE, "_build")
-    os.makedirs(build_dir, exist_ok=True)
-    common = ["-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden", "-Wall", "-Wno-unused-result", f"--offload-arch={ARCH}",
-              "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-    for src in SOURCES:
+    for src in sources:
         path = os.path.join(CSRC, src)
         obj = os.path.join(build_dir, src + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
@@ -38,12 +39,21 @@ def build(verbose: bool = False) -> str:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
         objs.append(obj)
-    tmp = LIB + ".tmp"
+    tmp = lib + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+
+
+def build(verbose: bool = False) -> str:
+    build_dir = os.path.join(HERE, "_build")
+    os.makedirs(build_dir, exist_ok=True)
+    common = ["-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden", "-Wall", "-Wno-unused-result", f"--offload-arch={ARCH}",
+              "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+    _link(SOURCES, LIB, build_dir, common, verbose)
+    _link(CALIB_SOURCES, CALIB_LIB, build_dir, common, verbose)
     return LIB
 
 

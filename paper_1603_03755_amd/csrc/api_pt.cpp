@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <new>
 #include <vector>
 
 #include "host_core.h"
@@ -116,6 +117,7 @@ sqa_status pt_launch(const std::vector<pt_handle *> &hs, hipStream_t stream) {
   e = hipMalloc(&dev, sizeof(PTDev) * pds.size());
   if (e != hipSuccess) return hip_fail(e, "hipMalloc (PT descriptors)");
   e = hipMemcpy(dev, pds.data(), sizeof(PTDev) * pds.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = injected_launch_fault();
   if (e == hipSuccess)
     e = launch_pt(static_cast<const PTDev *>(dev), static_cast<int>(pds.size()), s.waves, s.rec_cap, s.lat_cap,
                   s.mtab_cap, s.spack_cap, stream);
@@ -139,8 +141,48 @@ sqa_status pt_launch(const std::vector<pt_handle *> &hs, hipStream_t stream) {
 
 extern "C" {
 
+// Eq. (B1) for a pair with beta_{r+1} < beta_r: the threshold of the energy
+// gap D falls with D and is 0 once exp(D (beta_{r+1} - beta_r)) < 2^-32.  The
+// swap table needs its columns only up to the first D at which every pair's
+// threshold is 0; larger gaps clamp to that column.  Pairs of equal
+// temperatures always swap, so their rows never reach 0 and the table keeps
+// the whole range 0..2 E_max.
+static int64_t swap_table_width(const std::vector<double> &betas, int64_t dfull) {
+  int64_t cut = 0;
+  for (size_t r = 0; r + 1 < betas.size(); ++r) {
+    const double db = betas[r + 1] - betas[r];
+    if (!(db < 0.0)) return dfull;
+    // first D in [0, dfull] whose threshold is 0 (the thresholds do not rise with D)
+    if (threshold_from_log(static_cast<double>(dfull) * db) != 0u) return dfull;
+    int64_t lo = 0, hi = dfull;
+    while (lo < hi) {
+      const int64_t mid = lo + (hi - lo) / 2;
+      if (threshold_from_log(static_cast<double>(mid) * db) == 0u) hi = mid;
+      else lo = mid + 1;
+    }
+    cut = std::max(cut, lo);
+  }
+  return std::min(cut, dfull);
+}
+
+// Widest swap-table row accepted (entries).
+constexpr int64_t kMaxSwapRow = int64_t(1) << 22;
+
+static sqa_status pt_create_impl(const sqa_problem *problem, const sqa_embedding *embedding, const pt_params *params,
+                                 pt_handle **out);
+
 sqa_status pt_create(const sqa_problem *problem, const sqa_embedding *embedding, const pt_params *params,
                      pt_handle **out) {
+  try {
+    return pt_create_impl(problem, embedding, params, out);
+  } catch (const std::bad_alloc &) {
+    if (out) *out = nullptr;
+    return fail(SQA_ERR_OOM, "host allocation (PT tables)");
+  }
+}
+
+static sqa_status pt_create_impl(const sqa_problem *problem, const sqa_embedding *embedding, const pt_params *params,
+                                 pt_handle **out) {
   if (!problem || !embedding || !params || !out || !problem->J) return fail(SQA_ERR_INVALID, "null argument");
   *out = nullptr;
   const pt_params &p = *params;
@@ -158,11 +200,16 @@ sqa_status pt_create(const sqa_problem *problem, const sqa_embedding *embedding,
   }
   h->R = p.temps;
   h->F = h->emb.fmax;
-  h->Dmax = 2 * h->emb.emax;
   h->sweeps = p.sweeps;
   h->sps = p.sweeps_per_swap;
   h->seed = p.seed;
   h->betas = pt_betas(p.beta_min, p.beta_max, p.temps);
+  const int64_t dmax = swap_table_width(h->betas, 2 * static_cast<int64_t>(h->emb.emax));
+  if (dmax + 1 > kMaxSwapRow) {
+    delete h;
+    return fail(SQA_ERR_UNSUPPORTED, "swap table too wide (energy range too large for equal temperatures)");
+  }
+  h->Dmax = static_cast<int32_t>(dmax);
   h->mtab = pt_metropolis_table(h->betas, h->F);
   h->stab = pt_swap_table(h->betas, h->Dmax);
   h->spack = pt_swap_pack(h->stab, h->R, h->Dmax);

@@ -7,6 +7,7 @@
 #include <fstream>
 #include <map>
 #include <mutex>
+#include <new>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -146,8 +147,17 @@ static hipError_t upload_groups(char *base, const std::vector<HandleDev> &hds, c
   return e;
 }
 
+// Fault injection for tests of the error paths: with SQA_FAULT_INJECT=launch in
+// the environment, every sweep-kernel launch reports hipErrorLaunchFailure
+// instead of being queued (nothing runs on the device).
+hipError_t injected_launch_fault() {
+  const char *f = std::getenv("SQA_FAULT_INJECT");
+  return (f && std::strcmp(f, "launch") == 0) ? hipErrorLaunchFailure : hipSuccess;
+}
+
 static hipError_t launch_groups(char *base, const std::vector<MoveGroup> &gs, hipStream_t stream) {
-  hipError_t e = hipSuccess;
+  hipError_t e = injected_launch_fault();
+  if (e != hipSuccess) return e;
   for (const MoveGroup &g : gs) {
     e = launch_sqa_anneal(g.move, reinterpret_cast<HandleDev *>(base), reinterpret_cast<WorkItem *>(base + g.items_off),
                           static_cast<int>(g.items.size()), reinterpret_cast<int *>(base + g.counter_off), g.shape.grid,
@@ -261,27 +271,10 @@ static void resolve_config(const std::vector<const sqa_handle *> &hs, const sqa_
 
 static bool valid_waves(int w) { return w >= 1 && w <= 8; }
 
-}  // namespace sqa
-
-// =================================================================== C ABI
-extern "C" {
-
-const char *sqa_last_error(void) { return sqa::last_error_cstr(); }
-const char *sqa_version(void) { return "sqa-mi355x 0.1 (gfx950)"; }
-
-int64_t sqa_physical_sites(int32_t kind, int32_t n) {
-  if (kind == SQA_EMB_ME) return n >= 2 ? static_cast<int64_t>(n) * (n - 1) : -1;
-  if (kind == SQA_EMB_LHZ) return n >= 3 ? static_cast<int64_t>(n) * (n - 1) / 2 : -1;
-  if (kind == SQA_EMB_ME_CHIMERA) return n >= 2 ? static_cast<int64_t>(n) * ((n + 3) / 4 + 1) : -1;
-  return -1;
-}
-
-sqa_status sqa_create(const sqa_problem *problem, const sqa_embedding *embedding, const sqa_schedule *schedule,
-                      sqa_handle **out) {
-  if (!problem || !embedding || !schedule || !out) return fail(SQA_ERR_INVALID, "null argument");
+sqa_status handle_prepare(const sqa_problem &problem, const sqa_embedding &embedding, const sqa_schedule &s,
+                          sqa_handle **out) {
   *out = nullptr;
-  if (!problem->J) return fail(SQA_ERR_INVALID, "J is null");
-  const sqa_schedule &s = *schedule;
+  if (!problem.J) return fail(SQA_ERR_INVALID, "J is null");
   if (!(s.beta > 0.0) || !std::isfinite(s.beta)) return fail(SQA_ERR_INVALID, "beta must be positive and finite");
   if (s.slices < 1 || (s.slices > 1 && (s.slices & 1))) return fail(SQA_ERR_INVALID, "slices must be 1 or even");
   if (s.slices > 64) return fail(SQA_ERR_UNSUPPORTED, "at most 64 Trotter slices");
@@ -302,12 +295,12 @@ sqa_status sqa_create(const sqa_problem *problem, const sqa_embedding *embedding
 
   sqa_handle *h = new (std::nothrow) sqa_handle();
   if (!h) return fail(SQA_ERR_OOM, "host allocation");
-  sqa_status st = build_embedding(*problem, *embedding, &h->emb);
+  sqa_status st = build_embedding(problem, embedding, &h->emb);
   if (st != SQA_OK) {
     delete h;
     return st;
   }
-  h->N = problem->n;
+  h->N = problem.n;
   h->L = s.slices;
   h->M = s.sweeps;
   h->R = s.replicas;
@@ -316,11 +309,11 @@ sqa_status sqa_create(const sqa_problem *problem, const sqa_embedding *embedding
   h->F = h->emb.fmax;
   h->move = s.move;
   h->tw = (h->move == kMoveWolff) ? 1 : 3 * (2 * h->F + 1);
-  h->J.assign(problem->J, problem->J + static_cast<size_t>(h->N) * h->N);
+  h->J.assign(problem.J, problem.J + static_cast<size_t>(h->N) * h->N);
   h->h.assign(h->N, 0);
-  if (problem->h) {
+  if (problem.h) {
     h->has_h = true;
-    std::copy(problem->h, problem->h + h->N, h->h.begin());
+    std::copy(problem.h, problem.h + h->N, h->h.begin());
   }
   // Wolff moves sum plain weights per slice; Metropolis records carry 6|w| when F is small
   st = build_layout(h->emb, h->F, h->move == kMoveWolff ? kLayoutWolff : kLayoutMetropolis, &h->lay);
@@ -356,12 +349,20 @@ sqa_status sqa_create(const sqa_problem *problem, const sqa_embedding *embedding
   h->off_items = A.take(sizeof(WorkItem) * static_cast<size_t>(R));
   h->off_counter = A.take(256);
   A.size = A.used;
-  hipError_t e = hipMalloc(&A.base, A.size);
-  if (e != hipSuccess) {
-    delete h;
-    return hip_fail(e, "hipMalloc (handle)");
-  }
+  *out = h;
+  return SQA_OK;
+}
+
+size_t handle_block_bytes(const sqa_handle *h) { return h->arena.size; }
+
+sqa_status handle_upload(sqa_handle *h, const sqa_allocator *alloc) {
+  if (alloc) h->alloc = *alloc;
+  Arena &A = h->arena;
+  sqa_status st = device_alloc(&h->alloc, &A.base, A.size, "device block of the handle");
+  if (st != SQA_OK) return st;
   h->device_bytes = A.size;
+  const int n = h->emb.n, R = h->R, N = h->N;
+  const size_t nt = h->emb.terms.size();
   struct Up {
     size_t off;
     const void *p;
@@ -377,22 +378,58 @@ sqa_status sqa_create(const sqa_problem *problem, const sqa_embedding *embedding
       {h->off_J, h->J.data(), static_cast<size_t>(N) * N * 4},
       {h->off_h, h->h.data(), static_cast<size_t>(N) * 4},
   };
+  hipError_t e = hipSuccess;
   for (const Up &u : ups) {
     if (u.bytes == 0) continue;
     e = hipMemcpy(A.at<char>(u.off), u.p, u.bytes, hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-      (void)hipFree(A.base);
-      delete h;
-      return hip_fail(e, "hipMemcpy (handle setup)");
-    }
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy (handle setup)");
   }
   e = hipEventCreateWithFlags(&h->done, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipHostMalloc(&h->staging, sizeof(HandleDev) + sizeof(WorkItem) * static_cast<size_t>(R), 0);
   if (e != hipSuccess) {
-    if (h->done) (void)hipEventDestroy(h->done);
-    (void)hipFree(A.base);
-    delete h;
-    return hip_fail(e, "handle setup (event / pinned staging)");
+    h->done = nullptr;
+    return hip_fail(e, "hipEventCreate (handle setup)");
+  }
+  e = hipHostMalloc(&h->staging, sizeof(HandleDev) + sizeof(WorkItem) * static_cast<size_t>(R), 0);
+  if (e != hipSuccess) {
+    h->staging = nullptr;
+    return hip_fail(e, "hipHostMalloc (handle staging)");
+  }
+  return SQA_OK;
+}
+
+}  // namespace sqa
+
+// =================================================================== C ABI
+extern "C" {
+
+const char *sqa_last_error(void) { return sqa::last_error_cstr(); }
+const char *sqa_version(void) { return "sqa-mi355x 0.1 (gfx950)"; }
+
+int64_t sqa_physical_sites(int32_t kind, int32_t n) {
+  if (kind == SQA_EMB_ME) return n >= 2 ? static_cast<int64_t>(n) * (n - 1) : -1;
+  if (kind == SQA_EMB_LHZ) return n >= 3 ? static_cast<int64_t>(n) * (n - 1) / 2 : -1;
+  if (kind == SQA_EMB_ME_CHIMERA) return n >= 2 ? static_cast<int64_t>(n) * ((n + 3) / 4 + 1) : -1;
+  return -1;
+}
+
+sqa_status sqa_create(const sqa_problem *problem, const sqa_embedding *embedding, const sqa_schedule *schedule,
+                      const sqa_allocator *allocator, sqa_handle **out) {
+  if (!problem || !embedding || !schedule || !out) return fail(SQA_ERR_INVALID, "null argument");
+  *out = nullptr;
+  if (allocator && (!allocator->alloc || !allocator->free))
+    return fail(SQA_ERR_INVALID, "an allocator needs both callbacks");
+  sqa_handle *h = nullptr;
+  sqa_status st;
+  try {
+    st = handle_prepare(*problem, *embedding, *schedule, &h);
+  } catch (const std::bad_alloc &) {
+    return fail(SQA_ERR_OOM, "host allocation (tables)");
+  }
+  if (st != SQA_OK) return st;
+  st = handle_upload(h, allocator);
+  if (st != SQA_OK) {
+    sqa_destroy(h);
+    return st;
   }
   *out = h;
   return SQA_OK;
@@ -404,10 +441,16 @@ void sqa_destroy(sqa_handle *h) {
     (void)hipEventSynchronize(h->done);
     (void)hipEventDestroy(h->done);
   }
-  if (h->arena.base) (void)hipFree(h->arena.base);
-  if (h->dec_buf) (void)hipFree(h->dec_buf);
+  device_free(&h->alloc, h->arena.base);
+  device_free(&h->alloc, h->dec_buf);
   if (h->staging) (void)hipHostFree(h->staging);
   delete h;
+}
+
+sqa_status sqa_handle_device_bytes(sqa_handle *h, size_t *bytes_out) {
+  if (!h || !bytes_out) return fail(SQA_ERR_INVALID, "null argument");
+  *bytes_out = (h->arena.base ? h->arena.size : 0) + h->dec_bytes;
+  return SQA_OK;
 }
 
 static sqa_status check_handle(sqa_handle *h) {
@@ -442,6 +485,7 @@ static sqa_status run_single(sqa_handle *h, int m0, int m1, int flags, hipStream
   if (e == hipSuccess)
     e = hipMemcpyAsync(h->arena.at<void>(h->off_items), st_items, items.size() * sizeof(WorkItem),
                        hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = injected_launch_fault();
   if (e == hipSuccess)
     e = launch_sqa_anneal(h->move, h->arena.at<HandleDev>(h->off_hd), h->arena.at<WorkItem>(h->off_items),
                           static_cast<int>(items.size()), h->arena.at<int>(h->off_counter), shape.grid, shape.waves,
@@ -586,11 +630,11 @@ sqa_status decode_scratch(sqa_handle *h, size_t bytes) {
     h->poisoned = true;
     return hip_fail(e, "hipEventSynchronize");
   }
-  if (h->dec_buf) (void)hipFree(h->dec_buf);
+  device_free(&h->alloc, h->dec_buf);
   h->dec_buf = nullptr;
   h->dec_bytes = 0;
-  e = hipMalloc(&h->dec_buf, bytes);
-  if (e != hipSuccess) return hip_fail(e, "hipMalloc (decode scratch)");
+  sqa_status st = device_alloc(&h->alloc, &h->dec_buf, bytes, "decoder scratch");
+  if (st != SQA_OK) return st;
   h->dec_bytes = bytes;
   return SQA_OK;
 }
@@ -624,7 +668,34 @@ sqa_status tree_orders(int N, const int32_t *tree_parents, int n_trees, std::vec
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Decoder scratch of the LHZ decoders: packed rows, best keys, MLD sums, BP pair
+// values, MLD weight table, BP vote table, tree parents and orders.
+struct DecodeLayout {
+  size_t rows = 0, best = 0, acc = 0, pairs = 0, wtab = 0, dec = 0, par = 0, ord = 0, bytes = 0;
+};
+
+DecodeLayout decode_layout(int R, int N, int K, size_t tree_entries) {
+  DecodeLayout d;
+  d.rows = 0;
+  d.best = align256(d.rows + static_cast<size_t>(R) * N * 4);
+  d.acc = align256(d.best + static_cast<size_t>(R) * 8);
+  d.pairs = align256(d.acc + static_cast<size_t>(R) * N * 8);
+  d.wtab = align256(d.pairs + static_cast<size_t>(R) * K);
+  d.dec = align256(d.wtab + static_cast<size_t>(2 * K + 1) * 8);
+  d.par = align256(d.dec + static_cast<size_t>(2 * (2 * N - 3) + 1));
+  d.ord = align256(d.par + tree_entries * 4);
+  d.bytes = align256(d.ord + tree_entries * 4);
+  return d;
+}
+
 }  // namespace
+
+namespace sqa {
+size_t decode_scratch_bytes(const sqa_handle *h, int decoder, size_t tree_entries) {
+  if (decoder == SQA_DEC_ME_MAJORITY) return 0;
+  return decode_layout(h->R, h->N, h->emb.n, tree_entries).bytes;
+}
+}  // namespace sqa
 
 extern "C" {
 
@@ -672,17 +743,10 @@ sqa_status sqa_decode_ex(sqa_handle *h, const sqa_decode_params *prm, int8_t *lo
       st = tree_orders(N, p.tree_parents, p.n_trees, &order);
       if (st != SQA_OK) return st;
     }
-    // scratch: rows, best keys, sums, BP pair values, weight table, vote table, trees
-    const size_t o_rows = 0;
-    const size_t o_best = align256(o_rows + static_cast<size_t>(R) * N * 4);
-    const size_t o_acc = align256(o_best + static_cast<size_t>(R) * 8);
-    const size_t o_pairs = align256(o_acc + static_cast<size_t>(R) * N * 8);
-    const size_t o_wtab = align256(o_pairs + static_cast<size_t>(R) * K);
-    const size_t o_dec = align256(o_wtab + static_cast<size_t>(2 * K + 1) * 8);
-    const size_t o_par = align256(o_dec + static_cast<size_t>(2 * (2 * N - 3) + 1));
-    const size_t o_ord = align256(o_par + order.size() * 4);
-    const size_t need = align256(o_ord + order.size() * 4);
-    st = decode_scratch(h, need);
+    const DecodeLayout dl = decode_layout(R, N, K, order.size());
+    const size_t o_rows = dl.rows, o_best = dl.best, o_acc = dl.acc, o_pairs = dl.pairs, o_wtab = dl.wtab,
+                 o_dec = dl.dec, o_par = dl.par, o_ord = dl.ord;
+    st = decode_scratch(h, dl.bytes);
     if (st != SQA_OK) return st;
     char *base = static_cast<char *>(h->dec_buf);
     auto *rows = reinterpret_cast<uint32_t *>(base + o_rows);
@@ -902,10 +966,21 @@ sqa_status sqa_random_trees(uint64_t seed, int32_t n, int32_t n_trees, int32_t *
 
 namespace sqa {
 
-size_t handle_device_bytes(const sqa_handle *h) { return h->device_bytes; }
+// The launch scratch of a set (plan_groups): the HandleDev array and at most one
+// work item per replica, each part 256-aligned, and a 256-byte counter per move.
+size_t launch_scratch_share(const sqa_handle *h) {
+  return sizeof(HandleDev) + sizeof(WorkItem) * static_cast<size_t>(h->R);
+}
+
+size_t launch_scratch_bytes(const std::vector<sqa_handle *> &hs) {
+  size_t b = kLaunchScratchFixed;
+  for (const sqa_handle *h : hs) b += launch_scratch_share(h);
+  return b;
+}
 
 sqa_status run_handles(const std::vector<sqa_handle *> &hs, const std::vector<int> &m0, const std::vector<int> &m1,
-                       const std::vector<int> &flags, hipStream_t stream, void **scratch, size_t *scratch_bytes) {
+                       const std::vector<int> &flags, hipStream_t stream, const sqa_allocator *alloc, void **scratch,
+                       size_t *scratch_bytes) {
   hipError_t e = ensure_lds_limits();
   if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
   std::vector<const sqa_handle *> ch(hs.begin(), hs.end());
@@ -917,12 +992,13 @@ sqa_status run_handles(const std::vector<sqa_handle *> &hs, const std::vector<in
   if (st != SQA_OK) return st;
   std::vector<HandleDev> hds(hs.size());
   for (size_t i = 0; i < hs.size(); ++i) hds[i] = hs[i]->dev(m0[i], m1[i], flags[i]);
+  if (need > launch_scratch_bytes(hs)) return fail(SQA_ERR_DEVICE, "launch scratch above its bound");
   if (*scratch_bytes < need) {
-    if (*scratch) (void)hipFree(*scratch);
+    device_free(alloc, *scratch);
     *scratch = nullptr;
     *scratch_bytes = 0;
-    e = hipMalloc(scratch, need);
-    if (e != hipSuccess) return hip_fail(e, "hipMalloc (launch scratch)");
+    st = device_alloc(alloc, scratch, need, "launch scratch");
+    if (st != SQA_OK) return st;
     *scratch_bytes = need;
   }
   char *base = static_cast<char *>(*scratch);

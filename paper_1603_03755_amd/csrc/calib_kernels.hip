@@ -5,11 +5,12 @@
 // the Metropolis and Wolff loops are built from: a three-input XOR
 // (v_bitop3_b32), a widening 32x32 -> 64-bit multiply-add (v_mad_u64_u32,
 // Philox's multiply) and a packed 16-bit multiply-add (v_pk_mad_u16).
+//
+// Built on its own as libsqa_calib.so, a measurement tool of the benchmark and
+// not part of the library's interface: one C entry point, loaded by ctypes.
 #include <hip/hip_runtime.h>
 
-#include "../../include/sqa.h"
 #include "device_common.h"
-#include "host_core.h"
 
 namespace sqa {
 
@@ -61,19 +62,24 @@ __global__ __launch_bounds__(256) void calib_pkmad_kernel(uint32_t *out, int ite
 
 }  // namespace sqa
 
-extern "C" SQA_API sqa_status sqa_valu_calibrate(int32_t op, int32_t iters, float *ms_out,
-                                                 double *wave_instructions_out) {
+// op: 0 = three-input XOR, 1 = widening multiply-add, 2 = packed 16-bit
+// multiply-add.  Launches eight waves per SIMD on every CU, each lane running
+// `iters` iterations of eight independent chains; synchronous.  Returns 0 and
+// the timed launch's duration (*ms_out) and its VALU wave-instructions of the
+// chains (*wave_instructions_out); 1 for bad arguments (before any device
+// call), 2 when a HIP call failed.
+extern "C" __attribute__((visibility("default"))) int sqa_calib_valu_issue(int32_t op, int32_t iters, float *ms_out,
+                                                                         double *wave_instructions_out) {
   using namespace sqa;
-  if (op < 0 || op > 2 || iters <= 0 || !ms_out || !wave_instructions_out)
-    return fail(SQA_ERR_INVALID, "sqa_valu_calibrate: op must be 0..2, iters > 0, outputs non-null");
+  if (op < 0 || op > 2 || iters <= 0 || !ms_out || !wave_instructions_out) return 1;
   int dev = 0, cus = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (e != hipSuccess) return hip_fail(e, "sqa_valu_calibrate: device query");
+  if (e != hipSuccess) return 2;
   const int blocks = cus * 8;                  // 8 workgroups of 4 waves: 8 waves per SIMD
   uint32_t *out = nullptr;
   e = hipMalloc(&out, static_cast<size_t>(blocks) * 256 * sizeof(uint32_t));
-  if (e != hipSuccess) return fail(SQA_ERR_OOM, "sqa_valu_calibrate: output buffer");
+  if (e != hipSuccess) return 2;
   hipEvent_t t0 = nullptr, t1 = nullptr;
   e = hipEventCreate(&t0);
   if (e == hipSuccess) e = hipEventCreate(&t1);
@@ -94,8 +100,8 @@ extern "C" SQA_API sqa_status sqa_valu_calibrate(int32_t op, int32_t iters, floa
   if (t0) (void)hipEventDestroy(t0);
   if (t1) (void)hipEventDestroy(t1);
   (void)hipFree(out);
-  if (e != hipSuccess) return hip_fail(e, "sqa_valu_calibrate");
+  if (e != hipSuccess) return 2;
   *ms_out = ms;
   *wave_instructions_out = static_cast<double>(blocks) * 4.0 * iters * kCalibChains;
-  return SQA_OK;
+  return 0;
 }

@@ -28,6 +28,29 @@ sqa_status hip_fail(hipError_t e, const char *what) {
 
 const char *last_error_cstr() { return g_last_error.c_str(); }
 
+// ------------------------------------------------------ device memory
+sqa_status device_alloc(const sqa_allocator *a, void **p, size_t bytes, const char *what) {
+  *p = nullptr;
+  if (a && a->alloc) {
+    *p = a->alloc(bytes, a->ctx);
+    if (!*p) return fail(SQA_ERR_OOM, std::string(what) + ": the allocator returned NULL");
+    return SQA_OK;
+  }
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return hip_fail(e, what);
+  }
+  return SQA_OK;
+}
+
+void device_free(const sqa_allocator *a, void *p) {
+  if (!p) return;
+  if (a && a->alloc) a->free(p, a->ctx);
+  else (void)hipFree(p);
+}
+
 // -------------------------------------------------------- embeddings
 static int32_t me_index(int32_t N, int32_t chain, int32_t slot) { return chain * (N - 1) + slot; }
 

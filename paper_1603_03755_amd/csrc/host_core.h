@@ -81,6 +81,16 @@ std::vector<uint32_t> pt_swap_pack(const std::vector<uint32_t> &stab, int32_t R,
 // ---------------------------------------------------------- host Philox
 void host_philox4x32(const uint32_t ctr[4], uint32_t k0, uint32_t k1, uint32_t out[4]);
 
+// ------------------------------------------------------ device memory
+// Device memory from a caller's allocator (sqa_allocator with both callbacks
+// set) or, for a null allocator, hipMalloc / hipFree.  device_alloc returns
+// SQA_ERR_OOM when the allocator returns NULL or hipMalloc runs out.
+sqa_status device_alloc(const sqa_allocator *a, void **p, size_t bytes, const char *what);
+void device_free(const sqa_allocator *a, void *p);
+// Granularity in which the server counts a job's device bytes.
+constexpr size_t kServerGranule = 4096;
+inline size_t round_granule(size_t b) { return (b + kServerGranule - 1) & ~(kServerGranule - 1); }
+
 // --------------------------------------------------------- device arena
 // One device allocation carved into aligned sub-buffers.
 struct Arena {
@@ -122,6 +132,10 @@ hipError_t launch_pt(const PTDev *pts, int count, int waves, int rec_cap, int la
                      hipStream_t stream);
 hipError_t set_pt_lds_limit(size_t bytes);
 
+// hipErrorLaunchFailure when the environment asks for injected launch faults
+// (SQA_FAULT_INJECT=launch), else hipSuccess.
+hipError_t injected_launch_fault();
+
 // LDS budget of one workgroup on gfx950 (160 KiB, less room for the kernels'
 // static LDS variables).
 constexpr size_t kMaxLds = 160 * 1024 - 512;
@@ -156,11 +170,28 @@ struct sqa_handle;
 
 namespace sqa {
 // One persistent launch over several handles, each advancing sweeps
-// [m0[i], m1[i]) with its own flags.  `scratch` is a device buffer grown on
-// demand and owned by the caller.  Blocks until the launch has finished.
+// [m0[i], m1[i]) with its own flags.  `scratch` is a device buffer owned by the
+// caller, taken from `alloc` and grown on demand.  Blocks until the launch has
+// finished.
 sqa_status run_handles(const std::vector<sqa_handle *> &hs, const std::vector<int> &m0, const std::vector<int> &m1,
-                       const std::vector<int> &flags, hipStream_t stream, void **scratch, size_t *scratch_bytes);
-size_t handle_device_bytes(const sqa_handle *h);
+                       const std::vector<int> &flags, hipStream_t stream, const sqa_allocator *alloc, void **scratch,
+                       size_t *scratch_bytes);
+// Bytes of the launch scratch of run_handles for a set of handles: at most
+// kLaunchScratchFixed plus launch_scratch_share() of each handle.
+constexpr size_t kLaunchScratchFixed = 4096;
+size_t launch_scratch_share(const sqa_handle *h);
+size_t launch_scratch_bytes(const std::vector<sqa_handle *> &hs);
+
+// A handle in two steps: prepare (host only: validation, embedding, layout,
+// tables, the sizes of its device block) and upload (device block from the
+// allocator, site data and tables copied in, event and pinned staging).
+sqa_status handle_prepare(const sqa_problem &problem, const sqa_embedding &embedding, const sqa_schedule &schedule,
+                          sqa_handle **out);
+sqa_status handle_upload(sqa_handle *h, const sqa_allocator *alloc);
+// Bytes of the handle's device block, and of the scratch its decoder needs
+// (`tree_entries` = n_trees * n for the tree decoders).
+size_t handle_block_bytes(const sqa_handle *h);
+size_t decode_scratch_bytes(const sqa_handle *h, int decoder, size_t tree_entries);
 }  // namespace sqa
 
 // Handle: one problem x embedding x schedule, its device buffers and state.
@@ -180,6 +211,7 @@ struct sqa_handle {
   size_t off_rec = 0, off_devof = 0, off_hfield = 0, off_tw = 0, off_ts = 0, off_table = 0, off_spins = 0,
          off_energy = 0, off_wacc = 0, off_J = 0, off_h = 0, off_logical = 0, off_lenergy = 0, off_hd = 0, off_items = 0,
          off_counter = 0;
+  sqa_allocator alloc{};             // device-memory provider (null callbacks: hipMalloc)
   bool initialised = false;          // device lattice holds a state
   bool poisoned = false;
   hipEvent_t done = nullptr;

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libsqa.so")
 
 SQA_OK, SQA_ERR_INVALID, SQA_ERR_OOM, SQA_ERR_DEVICE, SQA_ERR_UNSUPPORTED, SQA_ERR_BUSY, SQA_ERR_NOT_READY = \
     0, -1, -2, -3, -4, -5, -6
+SQA_ERR_CANCELLED = -7
 SQA_EMB_ME, SQA_EMB_LHZ, SQA_EMB_ME_CHIMERA = 0, 1, 2
 SQA_DEC_ME_MAJORITY, SQA_DEC_LHZ_TREES, SQA_DEC_LHZ_MWD, SQA_DEC_LHZ_MLD, SQA_DEC_LHZ_BP = 0, 1, 2, 3, 4
 SQA_MOVE_METROPOLIS, SQA_MOVE_WOLFF = 0, 1
@@ -53,6 +54,14 @@ class sqa_launch_config(C.Structure):
     _fields_ = [("waves_per_group", C.c_int32), ("groups_per_cu", C.c_int32)]
 
 
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class sqa_allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", C.c_void_p)]
+
+
 class pt_params(C.Structure):
     _fields_ = [("beta_min", C.c_double), ("beta_max", C.c_double), ("temps", C.c_int32), ("sweeps", C.c_int32),
                 ("sweeps_per_swap", C.c_int32), ("seed", C.c_uint64)]
@@ -62,7 +71,9 @@ _lib = None
 _VP = C.c_void_p
 _PVP = C.POINTER(C.c_void_p)
 _SIGS = {
-    "sqa_create": (C.c_int, [C.POINTER(sqa_problem), C.POINTER(sqa_embedding), C.POINTER(sqa_schedule), _PVP]),
+    "sqa_create": (C.c_int, [C.POINTER(sqa_problem), C.POINTER(sqa_embedding), C.POINTER(sqa_schedule),
+                             C.POINTER(sqa_allocator), _PVP]),
+    "sqa_handle_device_bytes": (C.c_int, [_VP, C.POINTER(C.c_size_t)]),
     "sqa_anneal": (C.c_int, [_VP, _VP]),
     "sqa_anneal_range": (C.c_int, [_VP, C.c_int32, C.c_int32, _VP]),
     "sqa_reset": (C.c_int, [_VP, _VP]),
@@ -98,15 +109,17 @@ _SIGS = {
     "pt_destroy": (None, [_VP]),
     "pt_run": (C.c_int, [C.POINTER(sqa_problem), C.POINTER(sqa_embedding), C.POINTER(pt_params), _VP, _VP,
                          C.c_size_t, _VP, _VP, _VP]),
-    "sqa_server_create": (C.c_int, [C.c_size_t, C.c_int32, C.c_int32, _PVP]),
+    "sqa_server_create": (C.c_int, [C.c_size_t, C.c_int32, C.c_int32, C.POINTER(sqa_allocator), _PVP]),
     "sqa_server_submit": (C.c_int, [_VP, C.POINTER(sqa_problem), C.POINTER(sqa_embedding), C.POINTER(sqa_schedule),
-                                    C.POINTER(C.c_uint64)]),
+                                    C.POINTER(sqa_decode_params), C.POINTER(C.c_uint64)]),
+    "sqa_server_job_bytes": (C.c_int, [_VP, C.c_uint64, C.POINTER(C.c_size_t)]),
+    "sqa_server_cancel": (C.c_int, [_VP, C.c_uint64]),
     "sqa_server_poll": (C.c_int, [_VP, C.c_uint64, C.POINTER(C.c_int32)]),
     "sqa_server_wait": (C.c_int, [_VP, C.c_uint64, C.c_int32]),
-    "sqa_server_result": (C.c_int, [_VP, C.c_uint64, _VP, C.c_size_t, _VP, C.c_size_t, C.POINTER(C.c_double)]),
+    "sqa_server_result": (C.c_int, [_VP, C.c_uint64, _VP, C.c_size_t, _VP, C.c_size_t, _VP, C.c_size_t, _VP,
+                                    C.c_size_t, C.POINTER(C.c_double)]),
     "sqa_server_stats": (C.c_int, [_VP] + [C.POINTER(C.c_uint64)] * 3),
     "sqa_server_destroy": (None, [_VP]),
-    "sqa_valu_calibrate": (C.c_int, [C.c_int32, C.c_int32, C.POINTER(C.c_float), C.POINTER(C.c_double)]),
     "sqa_last_error": (C.c_char_p, []),
     "sqa_version": (C.c_char_p, []),
 }
@@ -163,14 +176,69 @@ def make_problem(J, h=None):
     return p, (J, hh)
 
 
+# ---------------------------------------------------------------- allocators
+class CallbackAllocator:
+    """An sqa_allocator whose callbacks are Python functions: alloc(nbytes) -> device
+    address (int) or None, free(address).  It counts live allocations and bytes.
+    Keep the object alive while anything created with it lives."""
+
+    def __init__(self, alloc, free):
+        self._alloc_py, self._free_py = alloc, free
+        self.live = {}
+        self.calls = 0
+        self.failures = 0
+
+        def _a(nbytes, ctx):
+            self.calls += 1
+            try:
+                p = self._alloc_py(int(nbytes))
+            except Exception:
+                p = None
+            if not p:
+                self.failures += 1
+                return None
+            self.live[int(p)] = int(nbytes)
+            return int(p)
+
+        def _f(ptr, ctx):
+            if ptr:
+                self.live.pop(int(ptr), None)
+                self._free_py(int(ptr))
+
+        self._afn, self._ffn = ALLOC_FN(_a), FREE_FN(_f)
+        self.struct = sqa_allocator(self._afn, self._ffn, None)
+
+    @property
+    def live_bytes(self) -> int:
+        return sum(self.live.values())
+
+
+class TorchAllocator(CallbackAllocator):
+    """Device memory from torch's caching allocator on `device` (default: the
+    current one), tied to that device's default stream; the library frees a
+    buffer only after its own queued work on it has finished."""
+
+    def __init__(self, device=None):
+        import torch
+        dev = torch.cuda.current_device() if device is None else int(device)
+        stream = torch.cuda.default_stream(dev)
+        super().__init__(lambda n: torch.cuda.caching_allocator_alloc(n, dev, stream),
+                         lambda p: torch.cuda.caching_allocator_delete(p))
+
+
+def _alloc_ptr(allocator):
+    return None if allocator is None else C.byref(allocator.struct)
+
+
 # ---------------------------------------------------------------- SQA handle
 class SQA:
     """One problem x embedding x schedule on the GPU (sqa_create / sqa_destroy)."""
 
     def __init__(self, kind: int, J, penalty: int, beta: float, slices: int, sweeps: int, replicas: int,
                  gamma_start: float, gamma_end: float, seed: int, h=None, gamma=None, bscale=None,
-                 move: int = SQA_MOVE_METROPOLIS):
+                 move: int = SQA_MOVE_METROPOLIS, allocator: Optional[CallbackAllocator] = None):
         prob, self._keep = make_problem(J, h)
+        self.allocator = allocator
         g = None if gamma is None else np.ascontiguousarray(gamma, dtype=np.float64)
         b = None if bscale is None else np.ascontiguousarray(bscale, dtype=np.float64)
         sched = sqa_schedule(beta, slices, sweeps, replicas, gamma_start, gamma_end,
@@ -178,7 +246,7 @@ class SQA:
                              b.ctypes.data_as(C.POINTER(C.c_double)) if b is not None else None, seed, move)
         emb = sqa_embedding(kind, penalty)
         out = C.c_void_p()
-        _check(lib().sqa_create(C.byref(prob), C.byref(emb), C.byref(sched), C.byref(out)))
+        _check(lib().sqa_create(C.byref(prob), C.byref(emb), C.byref(sched), _alloc_ptr(allocator), C.byref(out)))
         self.h = out
         self.kind, self.N, self.move = kind, int(np.asarray(J).shape[0]), move
         vals = [C.c_int32() for _ in range(5)]
@@ -266,6 +334,12 @@ class SQA:
 
     def device_spins(self) -> int:
         return lib().sqa_device_spins(self.h)
+
+    def device_bytes(self) -> int:
+        """Device bytes the handle holds through its allocator."""
+        b = C.c_size_t()
+        _check(lib().sqa_handle_device_bytes(self.h, C.byref(b)))
+        return b.value
 
 
 def sqa_random_trees(seed: int, n: int, n_trees: int) -> np.ndarray:
@@ -381,22 +455,45 @@ def pt_run_batch(handles: Sequence[PT], stream=None):
 
 # ---------------------------------------------------------------- server
 class Server:
-    def __init__(self, hbm_budget_bytes: int, max_slots: int, chunk_sweeps: int):
+    """Continuous-batching server (sqa_server_*).  `allocator` supplies its device
+    memory (None = hipMalloc)."""
+
+    def __init__(self, hbm_budget_bytes: int, max_slots: int, chunk_sweeps: int,
+                 allocator: Optional[CallbackAllocator] = None):
         out = C.c_void_p()
-        _check(lib().sqa_server_create(hbm_budget_bytes, max_slots, chunk_sweeps, C.byref(out)))
+        self.allocator = allocator
+        _check(lib().sqa_server_create(hbm_budget_bytes, max_slots, chunk_sweeps, _alloc_ptr(allocator),
+                                       C.byref(out)))
         self.s = out
         self._keep = {}
 
     def submit(self, kind, J, penalty, beta, slices, sweeps, replicas, gamma_start, gamma_end, seed, h=None,
-               move: int = SQA_MOVE_METROPOLIS) -> int:
+               move: int = SQA_MOVE_METROPOLIS, decoder: Optional[int] = None, readout_slice: int = 0,
+               trees=None, error_rate: float = 0.2, iterations: int = 10) -> int:
+        """Queues a job; `decoder` None = the default decoder for the embedding."""
         prob, keep = make_problem(J, h)
+        n = int(np.asarray(J).shape[0])
         emb = sqa_embedding(kind, penalty)
         sched = sqa_schedule(beta, slices, sweeps, replicas, gamma_start, gamma_end, None, None, seed, move)
+        dp = None
+        if decoder is not None:
+            t = None if trees is None else np.ascontiguousarray(trees, dtype=np.int32).reshape(-1, n)
+            dp = sqa_decode_params(decoder, readout_slice,
+                                   t.ctypes.data_as(C.POINTER(C.c_int32)) if t is not None else None,
+                                   0 if t is None else t.shape[0], error_rate, iterations)
         t = C.c_uint64()
-        _check(lib().sqa_server_submit(self.s, C.byref(prob), C.byref(emb), C.byref(sched), C.byref(t)))
-        n = sqa_physical_sites(kind, int(np.asarray(J).shape[0]))
-        self._keep[t.value] = (replicas, slices, n)
+        _check(lib().sqa_server_submit(self.s, C.byref(prob), C.byref(emb), C.byref(sched),
+                                       C.byref(dp) if dp is not None else None, C.byref(t)))
+        self._keep[t.value] = (replicas, slices, sqa_physical_sites(kind, n), n)
         return t.value
+
+    def job_bytes(self, ticket: int) -> int:
+        b = C.c_size_t()
+        _check(lib().sqa_server_job_bytes(self.s, ticket, C.byref(b)))
+        return b.value
+
+    def cancel(self, ticket: int):
+        _check(lib().sqa_server_cancel(self.s, ticket))
 
     def poll(self, ticket: int) -> bool:
         d = C.c_int32()
@@ -406,13 +503,21 @@ class Server:
     def wait(self, ticket: int, timeout_ms: int = -1):
         _check(lib().sqa_server_wait(self.s, ticket, timeout_ms))
 
-    def result(self, ticket: int):
-        R, L, n = self._keep.pop(ticket)
+    def result(self, ticket: int, logical: bool = False):
+        """(spins, energies, latency) or, with logical=True, (spins, energies, decoded
+        logical states, their energies, latency)."""
+        R, L, n, N = self._keep[ticket]
         spins = np.empty((R, L, n), dtype=np.int8)
         E = np.empty((R, L), dtype=np.int32)
+        q = np.empty((R, N), dtype=np.int8)
+        qE = np.empty(R, dtype=np.int32)
         lat = C.c_double()
-        _check(lib().sqa_server_result(self.s, ticket, _ptr(spins), spins.size, _ptr(E), E.size, C.byref(lat)))
-        return spins, E, lat.value
+        st = lib().sqa_server_result(self.s, ticket, _ptr(spins), spins.size, _ptr(E), E.size, _ptr(q), q.size,
+                                     _ptr(qE), qE.size, C.byref(lat))
+        if st != SQA_ERR_NOT_READY:
+            self._keep.pop(ticket, None)
+        _check(st)
+        return (spins, E, q, qE, lat.value) if logical else (spins, E, lat.value)
 
     def stats(self):
         v = [C.c_uint64() for _ in range(3)]
@@ -429,14 +534,3 @@ class Server:
             self.close()
         except Exception:
             pass
-
-
-# ---------------------------------------------------------------- calibration
-VALU_CALIB_OPS = {0: "v_bitop3_b32", 1: "v_mad_u64_u32", 2: "v_pk_mad_u16"}
-
-
-def sqa_valu_calibrate(op: int, iters: int = 100_000):
-    """(kernel ms, VALU wave-instructions) of one issue-rate calibration launch."""
-    ms, instr = C.c_float(), C.c_double()
-    _check(lib().sqa_valu_calibrate(op, iters, C.byref(ms), C.byref(instr)))
-    return ms.value, instr.value

@@ -57,11 +57,19 @@ def test_random_trees_match_oracle_on_host():
         assert (sqa.sqa_random_trees(99, n, 12) == O.random_trees(99, n, 12)).all()
 
 
-@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
-def test_valu_calibration_rejects_bad_arguments_on_host():
-    """Argument errors are reported before any device call."""
-    from paper_1603_03755_amd import sqa
+CALIB_LIB = os.path.join(ROOT, "paper_1603_03755_amd", "libsqa_calib.so")
+
+
+@pytest.mark.skipif(not os.path.exists(CALIB_LIB), reason="calibration probe not built")
+def test_valu_calibration_probe_is_separate_and_rejects_bad_arguments_on_host():
+    """The benchmark's issue-rate probe lives in its own library, not in the
+    library's interface; argument errors are reported before any device call."""
+    import ctypes as C
+    import bench
+    assert "sqa_valu_calibrate" not in declared()
+    out = os.popen(f"nm -D --defined-only {LIB}").read()
+    assert "calib" not in out
+    L = bench.calib_lib()
+    ms, instr = C.c_float(), C.c_double()
     for op, iters in ((3, 10), (-1, 10), (0, 0)):
-        with pytest.raises(sqa.SqaError) as e:
-            sqa.sqa_valu_calibrate(op, iters)
-        assert e.value.status == sqa.SQA_ERR_INVALID
+        assert L.sqa_calib_valu_issue(op, iters, C.byref(ms), C.byref(instr)) == 1

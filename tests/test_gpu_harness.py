@@ -84,9 +84,10 @@ def test_valu_calibration_launch(sqa):
     """The issue-rate calibration runs on every CU (eight waves per SIMD) and counts its
     chains' instructions; the rate itself is the benchmark's business, not a test bound."""
     import torch
+    import bench
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     for op in (0, 1, 2):
         print(f"valu calibration op={op}", flush=True)
-        ms, instr = sqa.sqa_valu_calibrate(op, 2000)
+        ms, instr = bench.valu_issue(op, 2000)
         assert ms > 0.0
         assert instr == cus * 8 * 4 * 2000 * 8
