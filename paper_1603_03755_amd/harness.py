@@ -141,3 +141,109 @@ def penalty_scan(instances: Sequence[np.ndarray], penalties: Sequence[float], cf
     for h in handles:
         h.close()
     return ScanResult(list(penalties), e0, out, dt, site_slices)
+
+
+# ------------------------------------------------------------- PT penalty scan
+@dataclasses.dataclass
+class PTScanConfig:
+    """PT parameters of Appendix B: 64 temperatures with beta geometric from 20 down to
+    0.1 (paper units, Eq. (B2)), 10 sweeps per swap.  The paper runs 10^5 swaps; the
+    default here is 10^4.  Every (instance, penalty, scheme) runs `runs` independent
+    ladders; the final state of each ladder's slot at a temperature is one sample of
+    that temperature (reading: the paper does not say how it sampled p_s)."""
+    temps: int = 64
+    beta_max: float = 20.0           # paper units
+    beta_min: float = 0.1
+    sweeps_per_swap: int = 10
+    swaps: int = 10_000
+    runs: int = 32
+    schemes: Sequence[str] = ("mec", "lhz")
+    lhz_decoder: str = "mvd"          # majority vote over spanning trees (Eq. (5)), as for Fig. 7; or "mwd"
+    trees: int = 3
+    seed: int = 0x97
+
+    @property
+    def sweeps(self) -> int:
+        return self.swaps * self.sweeps_per_swap
+
+
+@dataclasses.dataclass
+class PTScanResult:
+    penalties: List[float]
+    betas: np.ndarray                              # ladder, paper units, slot 0 coldest
+    ground_energy: List[int]
+    p_s: Dict[str, np.ndarray]                     # scheme -> [instance][penalty][slot]
+    seconds_pt: float = 0.0
+    attempts: float = 0.0
+
+    def critical(self, scheme: str, slot: int = 0) -> List[float]:
+        """Per instance, the penalty at which p_s at `slot` (slot 0: beta = 20) first
+        reaches 0.5 (Fig. 7), linearly interpolated between the two scan points around
+        the crossing; the first penalty if p_s is already >= 0.5 there, NaN if it never
+        gets there."""
+        out = []
+        for ps in self.p_s[scheme][:, :, slot]:
+            lam = float("nan")
+            for k, p in enumerate(ps):
+                if p >= 0.5:
+                    if k == 0:
+                        lam = self.penalties[0]
+                    else:
+                        l0, l1, p0 = self.penalties[k - 1], self.penalties[k], ps[k - 1]
+                        lam = l0 + (0.5 - p0) * (l1 - l0) / (p - p0)
+                    break
+            out.append(lam)
+        return out
+
+
+def pt_seed(cfg: PTScanConfig, i: int, k: int, kind: int, run: int) -> int:
+    return cfg.seed + (((i * 64 + k) * 4 + kind) << 16) + run
+
+
+def pt_penalty_scan(instances: Sequence[np.ndarray], penalties: Sequence[float], cfg: PTScanConfig | None = None,
+                    stream=None) -> PTScanResult:
+    """Runs every ladder of the scan in one batched PT launch, then decodes each
+    ladder's final states on the device (ME: majority vote of the chains, Eq. (4);
+    LHZ: spanning-tree majority vote, Eq. (5), or minimum-weight decoding) and
+    scores them against the exhaustive ground state."""
+    import time
+    cfg = cfg or PTScanConfig()
+    bmin, bmax = cfg.beta_min / SCALE, cfg.beta_max / SCALE
+    kinds = [KINDS[x] for x in cfg.schemes]
+    ladders, keys = [], []
+    for i, J in enumerate(instances):
+        for k, lam in enumerate(penalties):
+            pen = penalty_coefficient(lam)
+            for kind in kinds:
+                for run in range(cfg.runs):
+                    ladders.append(sqa.PT(kind, J, pen, bmin, bmax, cfg.temps, cfg.sweeps, cfg.sweeps_per_swap,
+                                          pt_seed(cfg, i, k, kind, run)))
+                keys.append((i, k, kind))
+    e0 = [sqa.sqa_ground_state(J)[0] for J in instances]
+    t0 = time.perf_counter()
+    sqa.pt_run_batch(ladders, stream)
+    dt = time.perf_counter() - t0
+    attempts = float(sum(h.sites * h.temps for h in ladders)) * cfg.sweeps
+    nI, nP, T = len(instances), len(penalties), cfg.temps
+    out = {x: np.zeros((nI, nP, T)) for x in cfg.schemes}
+    names = {v: k for k, v in KINDS.items()}
+    for q, (i, k, kind) in enumerate(keys):
+        J = instances[i]
+        N = J.shape[0]
+        group = ladders[q * cfg.runs:(q + 1) * cfg.runs]
+        states = np.stack([h.read()[0] for h in group])          # [run][slot][site]
+        # the samples as the replicas of a one-slice handle of the same embedding, decoded on the device
+        dec = sqa.SQA(kind, J, penalty_coefficient(penalties[k]), 1.0, 1, 1, cfg.runs * T, 1.0, 1.0, 0)
+        dec.write_spins(states.reshape(cfg.runs * T, 1, -1))
+        if kind != LHZ:
+            _, E = dec.decode(sqa.SQA_DEC_ME_MAJORITY, 0)
+        elif cfg.lhz_decoder == "mwd":
+            _, E = dec.decode(sqa.SQA_DEC_LHZ_MWD, 0)
+        else:
+            _, E = dec.decode(sqa.SQA_DEC_LHZ_TREES, 0, trees=sqa.sqa_random_trees(cfg.seed + i, N, cfg.trees))
+        dec.close()
+        out[names[kind]][i, k] = np.mean((E == e0[i]).reshape(cfg.runs, T), axis=0)
+    for h in ladders:
+        h.close()
+    betas = bmax * np.power(bmin / bmax, np.arange(T) / max(T - 1, 1)) * SCALE
+    return PTScanResult(list(penalties), betas, e0, out, dt, attempts)

@@ -91,3 +91,42 @@ def test_valu_calibration_launch(sqa):
         ms, instr = bench.valu_issue(op, 2000)
         assert ms > 0.0
         assert instr == cus * 8 * 4 * 2000 * 8
+
+
+def test_pt_penalty_scan_equals_oracle(sqa):
+    """A small PT scan (2 instances, 3 penalties, ME on Chimera, clique-chain ME and LHZ,
+    6 ladders of 8 temperatures each): every p_s, at every temperature, equals the one
+    computed from the oracle's ladders, the oracle's decoders and the exhaustive ground
+    state; the critical penalties follow from those p_s."""
+    from paper_1603_03755_amd import harness as H
+    cfg = H.PTScanConfig(temps=8, swaps=60, sweeps_per_swap=2, runs=6, schemes=("mec", "me", "lhz"), trees=3)
+    instances = [H.paper_instance(5, 21), H.paper_instance(6, 22)]
+    penalties = [0.5, 1.5, 3.0]
+    res = H.pt_penalty_scan(instances, penalties, cfg)
+    betas = O.pt_ladder(cfg.beta_min / H.SCALE, cfg.beta_max / H.SCALE, cfg.temps)
+    assert np.allclose(res.betas / H.SCALE, betas, rtol=1e-12, atol=0)
+    for i, J in enumerate(instances):
+        N = J.shape[0]
+        E0 = O.ground_states(J)[0]
+        assert res.ground_energy[i] == E0
+        trees = O.random_trees(cfg.seed + i, N, cfg.trees)
+        for k, lam in enumerate(penalties):
+            pen = H.penalty_coefficient(lam)
+            for scheme in cfg.schemes:
+                kind = H.KINDS[scheme]
+                emb = O.Embedding(kind, J, pen)
+                hits = np.zeros(cfg.temps)
+                for run in range(cfg.runs):
+                    ospins, _, orep, _ = O.pt_run(emb, betas, cfg.sweeps, cfg.sweeps_per_swap,
+                                                  H.pt_seed(cfg, i, k, kind, run))
+                    for slot in range(cfg.temps):
+                        s = ospins[orep[slot]]
+                        q = O.me_majority(emb, s) if kind != LHZ else O.lhz_tree_decode(N, s, trees)
+                        hits[slot] += O.logical_energy(J, q) == E0
+                assert (res.p_s[scheme][i, k] == hits / cfg.runs).all(), (scheme, i, k)
+    for scheme in cfg.schemes:
+        crit = res.critical(scheme)
+        assert len(crit) == len(instances)
+        for i, c in enumerate(crit):
+            ps = res.p_s[scheme][i, :, 0]
+            assert np.isnan(c) == (ps.max() < 0.5)
