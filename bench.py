@@ -84,6 +84,11 @@ def measured_traffic(args, wolff=False):
     return (f * t["fetch_scale"] + w * t["write_scale"]) * 1024
 
 
+def log(msg: str):
+    """Progress on stderr (the JSON result line is the only stdout output)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,9 +101,8 @@ def parse():
                     help="only measure the VALU issue rate of the sweep loops' instruction kinds")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 2 GiB device to device, source evicted from the last-level cache first")
-    ap.add_argument("--legs", default="per_instance,serving,pt,wolff,scan,cpu",
+    ap.add_argument("--legs", default="per_instance,serving,pt,wolff,scan,ptscan,cpu",
                     help="comma list of the extra legs to run after the timed steps")
-    ap.add_argument("--cpu-replicas", type=int, default=2, help="oracle lattices per stratum for cpu_baseline")
     ap.add_argument("--pt-sweeps", type=int, default=100_000, help="sweeps of the parallel-tempering leg")
     return ap.parse_args()
 
@@ -167,18 +171,17 @@ def wolff_leg(sqa, O, jobs, stream, metropolis_kernel_s, traffic):
     b.close()
     for h in hs:
         h.close()
-    strata = {}
-    for j in jobs:
-        strata.setdefault((j.kind, j.n), j)
-    sample = list(strata.values())
+    threads = oracle_threads()
+    sample = stratified_lattices(jobs, threads)
 
-    def run(j):
+    def run(jr):
+        j, r = jr
         O.sqa_anneal_wolff(j.kind, j.J, j.penalty, j.beta, j.slices, j.sweeps, 1, j.gamma0, j.gamma1, j.seed,
-                           nthreads=1)
+                           nthreads=1, r0=r)
         return j.sites * j.slices * j.sweeps
 
     t0 = time.perf_counter()
-    with ThreadPoolExecutor(max_workers=min(len(sample), os.cpu_count() or 1)) as ex:
+    with ThreadPoolExecutor(max_workers=threads) as ex:
         ocells = sum(ex.map(run, sample))
     odt = time.perf_counter() - t0
     return {"kernel": "sqa_anneal_kernel<Wolff>", "kernel_ms": kernel_s * 1e3,
@@ -188,8 +191,9 @@ def wolff_leg(sqa, O, jobs, stream, metropolis_kernel_s, traffic):
             "roofline": {"bound": "alu", "achieved": ops * cells / kernel_s / 1e12, "peak": PEAK_LANE_OPS / 1e12,
                          "unit": "TOP/s (32-bit VALU lane-op slots)", "frac": ops * cells / kernel_s / PEAK_LANE_OPS,
                          "traffic": traffic, "ops_per_site_slice": ops},
-            "oracle": {"site_slices_per_s": ocells / odt, "cores": len(sample),
-                       "sample": f"one replica lattice per embedding x N stratum ({len(sample)}), full schedule"}}
+            "oracle": {"site_slices_per_s": ocells / odt, "cores": threads,
+                       "sample": f"{len(sample)} replica lattices, one per thread, dealt over the embedding x N "
+                                 f"strata, full schedule"}}
 
 
 def scan_leg(sqa):
@@ -214,18 +218,79 @@ def scan_leg(sqa):
             "site_slices_per_s": res.site_slices / res.seconds_anneal, "schemes": summary}
 
 
-def cpu_baseline(jobs, replicas_per_stratum: int = 2):
-    """The oracle, as it stands, on a bounded sample of the same workload: for
-    every (embedding, N) stratum its first instance, `replicas_per_stratum`
-    replica lattices, the full sweep schedule; one host thread per lattice."""
-    import oracle as O
-    from concurrent.futures import ThreadPoolExecutor
+def host_info():
+    """The host the oracle is timed on: logical CPUs, those this process may use, CPU
+    model, C library."""
+    import platform
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return {"nproc": os.cpu_count(), "usable_cpus": usable, "cpu_model": model,
+            "libc": " ".join(x for x in platform.libc_ver() if x)}
+
+
+def oracle_threads() -> int:
+    """One oracle thread per usable host CPU, at most 16 (the CPU share of one GPU)."""
+    return max(1, min(host_info()["usable_cpus"], 16))
+
+
+def stratified_lattices(jobs, count):
+    """`count` (job, replica) lattices dealt round-robin over the workload's (embedding, N)
+    strata: lattice q is replica q // strata of the stratum's first instance."""
     strata = {}
     for j in jobs:
         strata.setdefault((j.kind, j.n), j)
-    sample = list(strata.values())
-    lattices = [(j, r) for j in sample for r in range(replicas_per_stratum)]
-    threads = min(len(lattices), os.cpu_count() or 1)
+    first = list(strata.values())
+    return [(first[q % len(first)], q // len(first)) for q in range(count)]
+
+
+def pt_scan_leg(sqa, scan):
+    """The paper's PT experiment shape (Sec. III, Figs. 5-7, Appendix B) on the scan's 8
+    synthetic K8 instances: 6 penalty strengths x {ME on Chimera, clique-chain ME, LHZ},
+    32 independent ladders each of 64 temperatures (beta 20 -> 0.1, paper units), 10
+    sweeps per swap, 10^4 swaps, all in one batched launch; every ladder's final states
+    decoded on the device (chain majority, three-tree majority for LHZ).  Reports p_s at
+    beta = 20 and the critical penalty (p_s = 0.5 crossing, Fig. 7) beside the SQA scan's
+    optimal penalty (Fig. 5)."""
+    from paper_1603_03755_amd import harness as H
+    from paper_1603_03755_amd.workloads import SEED_BATCH
+    instances = [H.paper_instance(8, SEED_BATCH + 7000 + i) for i in range(8)]
+    penalties = [0.5, 1.0, 1.5, 2.0, 2.5, 3.0]
+    cfg = H.PTScanConfig(schemes=("mec", "me", "lhz"))
+    t0 = time.perf_counter()
+    res = H.pt_penalty_scan(instances, penalties, cfg)
+    total = time.perf_counter() - t0
+    schemes = {}
+    for x in cfg.schemes:
+        crit = res.critical(x)
+        ok = [c for c in crit if c == c]
+        schemes[x] = {"p_s_beta20_by_penalty": [float(v) for v in np.mean(res.p_s[x][:, :, 0], axis=0)],
+                      "critical_penalty_mean": float(np.mean(ok)) if ok else None,
+                      "critical_penalty_found": len(ok)}
+        sq = (scan or {}).get("schemes", {}).get("lhz_mvd" if x == "lhz" else x)
+        if sq:
+            schemes[x]["sqa_optimal_penalty_mean"] = sq["optimal_penalty_mean"]
+    return {"instances": len(instances), "n": 8, "penalties": penalties, "runs": cfg.runs, "temps": cfg.temps,
+            "beta": [cfg.beta_max, cfg.beta_min], "sweeps_per_swap": cfg.sweeps_per_swap, "swaps": cfg.swaps,
+            "pt_seconds": res.seconds_pt, "total_seconds": total, "attempts_per_s": res.attempts / res.seconds_pt,
+            "schemes": schemes}
+
+
+def cpu_baseline(jobs):
+    """The oracle, as it stands, on a bounded sample of the same workload: one replica
+    lattice per host thread (one thread per usable CPU, at most 16), dealt over the
+    (embedding, N) strata, each over the full sweep schedule."""
+    import oracle as O
+    from concurrent.futures import ThreadPoolExecutor
+    threads = oracle_threads()
+    lattices = stratified_lattices(jobs, threads)
 
     def run(jr):
         j, r = jr
@@ -238,8 +303,10 @@ def cpu_baseline(jobs, replicas_per_stratum: int = 2):
         attempts = sum(ex.map(run, lattices))
     dt = time.perf_counter() - t0
     return {"value": attempts / dt, "unit": "spin-flip attempts/s", "cores": threads, "kind": "oracle",
-            "sample": f"{len(lattices)} of the workload's replica lattices ({replicas_per_stratum} per embedding x N "
-                      f"stratum), full {sample[0].sweeps}-sweep schedule: {attempts:.3e} attempts in {dt:.1f} s"}
+            "host": host_info(),
+            "sample": f"{len(lattices)} of the workload's replica lattices, one per thread, dealt over the 8 "
+                      f"embedding x N strata, full {jobs[0].sweeps}-sweep schedule: {attempts:.3e} attempts "
+                      f"in {dt:.1f} s"}
 
 
 def serve_run(sqa, stream_jobs, budget, slots, chunk):
@@ -257,7 +324,7 @@ def serve_run(sqa, stream_jobs, budget, slots, chunk):
     lats, att = [], 0
     for t, j in tickets:
         srv.wait(t)
-        _, _, lat = srv.result(t)
+        _, _, _, _, lat = srv.result(t, logical=True)      # spins, energies, decoded states and their energies
         lats.append(lat)
         att += j.attempts
     span = time.perf_counter() - t0
@@ -269,7 +336,9 @@ def serve_run(sqa, stream_jobs, budget, slots, chunk):
 
 
 def serving_leg(sqa):
-    """Continuous batching under a 64 MB device budget and 32 slots: capacity from a
+    """Continuous batching under a 64 MB device budget and 32 slots, each job decoded on
+    the device when it finishes (majority vote for ME, minimum-weight decoding for LHZ)
+    and returned with its logical states: capacity from a
     burst of 48 mixed jobs (N 8..32, ME/LHZ, L 32/64, 10^3-10^4 sweeps, 16 replicas),
     then Poisson arrivals of the same jobs at 0.25, 0.5, 0.75 and 0.9 of capacity."""
     from paper_1603_03755_amd.workloads import serving_stream
@@ -283,27 +352,66 @@ def serving_leg(sqa):
         r.update({"fraction_of_capacity": f, "arrival_rate_per_s": f * capacity})
         rates.append(r)
     head = rates[2]
-    return {"capacity_jobs_per_s": capacity, "burst": cap, "rates": rates,
+    import oracle as O
+    jobs = [j for _, j in burst]
+    ops = algorithmic_ops_per_attempt(jobs, O)
+    roof = {"bound": "alu", "achieved": ops * cap["attempts_per_s"] / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+            "unit": "TOP/s (32-bit VALU lane-op slots)", "frac": ops * cap["attempts_per_s"] / PEAK_LANE_OPS,
+            "traffic": None, "ops_per_attempt": ops,
+            "over": "the capacity burst's whole span (admission, launches, decoding, copies to the host)"}
+    return {"capacity_jobs_per_s": capacity, "burst": cap, "rates": rates, "roofline": roof,
             "p50_latency_s": head["p50_latency_s"], "p99_latency_s": head["p99_latency_s"],
             "at_fraction_of_capacity": 0.75, "budget_bytes": budget, "slots": slots, "chunk_sweeps": chunk}
 
 
-def pt_leg(sqa, sweeps: int):
+def pt_ops_per_attempt(jobs, O) -> float:
+    """Method arithmetic of a PT attempt (full-rate lane-op slots), averaged over the
+    ladders' sites: the Philox share of the random half word, one multiply-add per
+    incident term and per nonzero field, and the decision (compare, tie test, select,
+    table index).  The swap phases are counted apart (per swap attempt, not here)."""
+    tot_ops, tot_w, seen = 0.0, 0.0, {}
+    for j in jobs:
+        key = (j.kind, j.n)
+        if key not in seen:
+            emb = O.Embedding(j.kind, j.J, j.penalty)
+            terms = np.diff(emb.row).astype(float)
+            fields = (emb.h != 0).astype(float)
+            seen[key] = float(np.mean(PHILOX_OPS_PER_HALF + terms + fields + DECISION_OPS))
+        w = j.sites * j.temps * j.sweeps
+        tot_ops += seen[key] * w
+        tot_w += w
+    return tot_ops / tot_w
+
+
+def pt_leg(sqa, O, sweeps: int):
     """Parallel tempering over 128 N = 24 instances embedded both ways (256 ladders of 32
-    temperatures, beta geometric in [0.1, 5], a swap phase after every sweep), one launch."""
+    temperatures, beta geometric in [0.1, 5], a swap phase after every sweep), one launch;
+    its duration from HIP events on the launch stream."""
+    import torch
     from paper_1603_03755_amd.workloads import pt_jobs
     jobs = pt_jobs(sweeps=sweeps)
     hs = [sqa.PT(j.kind, j.J, j.penalty, j.beta_min, j.beta_max, j.temps, j.sweeps, j.sweeps_per_swap, j.seed)
           for j in jobs]
+    stream = torch.cuda.Stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
-    sqa.pt_run_batch(hs)
-    dt = time.perf_counter() - t0
+    e0.record(stream)
+    sqa.pt_run_batch(hs, stream)
+    e1.record(stream)
+    stream.synchronize()
+    wall = time.perf_counter() - t0
+    dt = e0.elapsed_time(e1) / 1e3
     attempts = sum(j.sites * j.temps * j.sweeps for j in jobs)
     swaps = sum((j.temps - 1) * (j.sweeps // j.sweeps_per_swap) for j in jobs)
+    ops = pt_ops_per_attempt(jobs, O)
     for h in hs:
         h.close()
-    return {"ladders": len(jobs), "temps": 32, "sweeps": sweeps, "attempts": attempts,
-            "attempts_per_s": attempts / dt, "swap_attempts_per_s": swaps / dt, "seconds": dt}
+    return {"kernel": "pt_kernel", "ladders": len(jobs), "temps": 32, "sweeps": sweeps, "attempts": attempts,
+            "attempts_per_s": attempts / dt, "swap_attempts_per_s": swaps / dt, "kernel_seconds": dt,
+            "wall_seconds": wall, "hbm_yardstick_frac": attempts / dt / 4.0e12,
+            "roofline": {"bound": "alu", "achieved": ops * attempts / dt / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+                         "unit": "TOP/s (32-bit VALU lane-op slots)", "frac": ops * attempts / dt / PEAK_LANE_OPS,
+                         "traffic": None, "ops_per_attempt": ops}}
 
 
 def copy_calibration():
@@ -387,38 +495,37 @@ def main():
     t_setup = time.perf_counter()
     handles = [sqa.SQA(j.kind, j.J, j.penalty, j.beta, j.slices, j.sweeps, j.replicas, j.gamma0, j.gamma1, j.seed)
                for j in jobs]
-    batch = sqa.Batch(handles)                 # launch shape from the package's tuning cache
+    # one graph per step: init -> sweeps -> energies -> decoding of every replica's slice 0
+    # (majority vote of the ME chains, exhaustive minimum-weight decoding of the LHZ states)
+    decoders = [(sqa.SQA_DEC_ME_MAJORITY if j.kind == ME else sqa.SQA_DEC_LHZ_MWD, 0) for j in jobs]
+    batch = sqa.Batch(handles, decoders=decoders)     # launch shape from the package's tuning cache
     waves, gpc = batch.config()
     setup_s = time.perf_counter() - t_setup
     attempts_per_step = sum(j.attempts for j in jobs)
-    decoders = [(h, sqa.SQA_DEC_ME_MAJORITY if j.kind == ME else sqa.SQA_DEC_LHZ_MWD) for h, j in zip(handles, jobs)]
+    log(f"setup {setup_s:.1f} s: {len(handles)} handles, {attempts_per_step:.3e} attempts per step")
 
     stream = torch.cuda.Stream()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
 
-    def step(timed_kernel):
-        with torch.cuda.stream(stream):
-            if timed_kernel:
-                ev[0].record(stream)
-            batch.run(stream)
-            if timed_kernel:
-                ev[1].record(stream)
-            for h, dec in decoders:
-                h.decode(dec, 0, stream=stream, host=False)
+    def step():
+        batch.run(stream)
         stream.synchronize()
 
     for _ in range(args.warmup):
-        step(False)
+        step()
     torch.cuda.synchronize()
-    kernel_ms = []
+    log("warm-up done")
+    kernel_ms, decode_ms = [], []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        step(True)
-        kernel_ms.append(ev[0].elapsed_time(ev[1]))
+        step()
+        a_ms, d_ms = batch.timing()      # HIP events on the launch stream, around and inside the graph
+        kernel_ms.append(a_ms)
+        decode_ms.append(d_ms)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     value = attempts_per_step * args.steps / wall
     kernel_s = float(np.mean(kernel_ms)) / 1e3
+    log(f"timed steps done: {wall / args.steps * 1e3:.1f} ms per step")
 
     ops = algorithmic_ops_per_attempt(jobs, O)
     achieved = ops * attempts_per_step / kernel_s
@@ -447,7 +554,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
                      "unit": "TOP/s (32-bit VALU lane-op slots)", "frac": achieved / PEAK_LANE_OPS,
                      "traffic": measured_traffic(args), "kernel": "sqa_anneal_kernel",
-                     "kernel_ms": kernel_s * 1e3,
+                     "kernel_ms": kernel_s * 1e3, "decode_ms": float(np.mean(decode_ms)),
                      "ops_per_attempt": ops},
         "kernel_attempts_per_s": attempts_per_step / kernel_s,
         # the per-sweep streaming view: 1 byte read + 1 byte written per attempt at 8 TB/s
@@ -457,6 +564,7 @@ def main():
     }
     legs = set() if args.no_extras else {x.strip() for x in args.legs.split(",") if x.strip()}
     if "per_instance" in legs:
+        log("leg per_instance")
         # one launch per instance vs one batched launch, same instances, reduced sweeps
         short = 200
         hs2 = [sqa.SQA(j.kind, j.J, j.penalty, j.beta, j.slices, short, j.replicas, j.gamma0, j.gamma1, j.seed)
@@ -481,15 +589,24 @@ def main():
         for h in hs2:
             h.close()
     if "serving" in legs:
+        log("leg serving")
         out["serving"] = serving_leg(sqa)
     if "pt" in legs:
-        out["parallel_tempering"] = pt_leg(sqa, args.pt_sweeps)
+        log("leg pt")
+        out["parallel_tempering"] = pt_leg(sqa, O, args.pt_sweeps)
     if "wolff" in legs:
+        log("leg wolff")
         out["wolff"] = wolff_leg(sqa, O, jobs, stream, kernel_s, measured_traffic(args, wolff=True))
     if "scan" in legs:
+        log("leg scan")
         out["penalty_scan"] = scan_leg(sqa)
+    if "ptscan" in legs:
+        log("leg ptscan")
+        out["pt_penalty_scan"] = pt_scan_leg(sqa, out.get("penalty_scan"))
     if "cpu" in legs:
-        out["cpu_baseline"] = cpu_baseline(jobs, args.cpu_replicas)
+        log("leg cpu")
+        out["cpu_baseline"] = cpu_baseline(jobs)
+    log("done")
     print(json.dumps(out), flush=True)
 
 

@@ -311,7 +311,24 @@ SQA_API void sqa_destroy(sqa_handle *h);
  * batch and must not be used concurrently with it. */
 SQA_API sqa_status sqa_batch_create(sqa_handle *const *handles, int32_t count,
                             const sqa_launch_config *config, sqa_batch **out);
+/* sqa_batch_create with a decoder per handle, captured in a second graph that
+ * sqa_batch_run replays right after the anneal's on the same stream: every run
+ * does init -> sweeps -> energies -> decoding (Eq. (4), Eq. (5), Sec. IV A-D)
+ * and leaves each handle's logical states and their energies in its device
+ * buffers (sqa_read_logical, sqa_device_logical).
+ * decoders[count], one per handle; an entry whose decoder is -1 decodes
+ * nothing.  The decoders' host tables (tree orders, MLD weights, BP votes) are
+ * copied at creation into scratch the batch owns; tree parents are copied.
+ * Errors: those of sqa_batch_create and of sqa_decode_ex's checks. */
+SQA_API sqa_status sqa_batch_create_decoded(sqa_handle *const *handles, int32_t count,
+                                    const sqa_launch_config *config, const sqa_decode_params *decoders,
+                                    sqa_batch **out);
 SQA_API sqa_status sqa_batch_run(sqa_batch *b, void *stream);
+/* Durations of the last sqa_batch_run, from HIP events recorded on its stream
+ * before the anneal graph, between it and the decoder graph, and after both:
+ * the anneal's and the decoders' (0 without decoders).  Waits for the run.
+ * SQA_ERR_INVALID before any run. */
+SQA_API sqa_status sqa_batch_timing(sqa_batch *b, float *anneal_ms, float *decode_ms);
 SQA_API sqa_status sqa_batch_config(sqa_batch *b, sqa_launch_config *out);
 SQA_API void sqa_batch_destroy(sqa_batch *b);
 

@@ -695,6 +695,117 @@ size_t decode_scratch_bytes(const sqa_handle *h, int decoder, size_t tree_entrie
   if (decoder == SQA_DEC_ME_MAJORITY) return 0;
   return decode_layout(h->R, h->N, h->emb.n, tree_entries).bytes;
 }
+
+// Checks a decoder against the handle and, for the tree decoders, lists each
+// tree's vertices parents-first.  No device work.
+sqa_status decode_check(const sqa_handle *h, const sqa_decode_params &p, std::vector<int32_t> *order) {
+  const int N = h->N;
+  if (p.readout_slice < 0 || p.readout_slice >= h->L) return fail(SQA_ERR_INVALID, "readout slice out of range");
+  if (p.decoder == SQA_DEC_ME_MAJORITY) {
+    if (h->emb.kind != SQA_EMB_ME && h->emb.kind != SQA_EMB_ME_CHIMERA)
+      return fail(SQA_ERR_INVALID, "majority decoding of chains needs an ME handle");
+    return SQA_OK;
+  }
+  if (p.decoder != SQA_DEC_LHZ_TREES && p.decoder != SQA_DEC_LHZ_MWD && p.decoder != SQA_DEC_LHZ_MLD &&
+      p.decoder != SQA_DEC_LHZ_BP)
+    return fail(SQA_ERR_INVALID, "unknown decoder");
+  if (h->emb.kind != SQA_EMB_LHZ) return fail(SQA_ERR_INVALID, "LHZ decoders need an LHZ handle");
+  if (p.decoder == SQA_DEC_LHZ_MWD && N > 32)
+    return fail(SQA_ERR_UNSUPPORTED, "exhaustive minimum-weight decoding limited to n <= 32");
+  if (p.decoder == SQA_DEC_LHZ_MLD && N > 24)
+    return fail(SQA_ERR_UNSUPPORTED, "exhaustive maximum-likelihood decoding limited to n <= 24");
+  if (p.decoder == SQA_DEC_LHZ_BP && N > 32) return fail(SQA_ERR_UNSUPPORTED, "parity-check decoding limited to n <= 32");
+  if ((p.decoder == SQA_DEC_LHZ_MLD || p.decoder == SQA_DEC_LHZ_BP) && !(p.error_rate > 0.0 && p.error_rate < 0.5))
+    return fail(SQA_ERR_INVALID, "error rate must be in (0, 1/2)");
+  if (p.decoder == SQA_DEC_LHZ_BP && p.iterations < 0) return fail(SQA_ERR_INVALID, "negative iteration count");
+  if (p.decoder == SQA_DEC_LHZ_TREES || p.decoder == SQA_DEC_LHZ_BP) return tree_orders(N, p.tree_parents, p.n_trees, order);
+  order->clear();
+  return SQA_OK;
+}
+
+// Copies the decoder's host tables into its scratch `base` (laid out by
+// decode_layout): tree parents and orders, MLD weights, BP votes.  Synchronous;
+// the scratch must not be in use by queued work.
+sqa_status decode_tables(const sqa_handle *h, const sqa_decode_params &p, const std::vector<int32_t> &order, char *base) {
+  const int N = h->N, K = h->emb.n;
+  const DecodeLayout dl = decode_layout(h->R, N, K, order.size());
+  hipError_t e = hipSuccess;
+  if (p.decoder == SQA_DEC_LHZ_TREES || p.decoder == SQA_DEC_LHZ_BP) {
+    e = hipMemcpy(base + dl.par, p.tree_parents, order.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(base + dl.ord, order.data(), order.size() * 4, hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess && p.decoder == SQA_DEC_LHZ_MLD) {
+    // Sec. IV B: weights round(2^36 exp(-beta_N d)), d = O_max - O, beta_N = ln((1-p)/p) / 2
+    const double beta = 0.5 * std::log((1.0 - p.error_rate) / p.error_rate);
+    std::vector<uint64_t> w(2 * K + 1);
+    for (int d = 0; d <= 2 * K; ++d)
+      w[d] = static_cast<uint64_t>(std::llround(std::ldexp(std::exp(-beta * static_cast<double>(d)), 36)));
+    e = hipMemcpy(base + dl.wtab, w.data(), w.size() * 8, hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess && p.decoder == SQA_DEC_LHZ_BP) {
+    // Sec. IV D: x_ij <- sign(w0 s_ij + w1 c), tie keeps s_ij; w0 = ln((1-p)/p), w1 = ln((1-p2)/p2), p2 = 2p(1-p)
+    const double q = p.error_rate, q2 = 2.0 * q * (1.0 - q);
+    const double w0 = std::log((1.0 - q) / q), w1 = std::log((1.0 - q2) / q2);
+    std::vector<int8_t> d(2 * (2 * N - 3) + 1, 1);
+    for (int neg = 0; neg < 2; ++neg)
+      for (int c = -(N - 2); c <= N - 2; ++c) {
+        const int sv = neg ? -1 : 1;
+        const double v = w0 * static_cast<double>(sv) + w1 * static_cast<double>(c);
+        d[neg * (2 * N - 3) + c + N - 2] = static_cast<int8_t>(v > 0.0 ? 1 : (v < 0.0 ? -1 : sv));
+      }
+    e = hipMemcpy(base + dl.dec, d.data(), d.size(), hipMemcpyHostToDevice);
+  }
+  return e == hipSuccess ? SQA_OK : hip_fail(e, "hipMemcpy (decoder tables)");
+}
+
+// Queues the decoder's kernels on `s` (readout slice, decoder, logical
+// energies), reading the scratch `base` (LHZ decoders) that decode_tables
+// filled.  Kernels only: no host work and no copies, so a graph can hold it.
+hipError_t decode_enqueue(const sqa_handle *h, const sqa_decode_params &p, size_t tree_entries, char *base,
+                          hipStream_t s) {
+  const int N = h->N, R = h->R, n = h->emb.n, L = h->L, K = n;
+  const int8_t *spins = h->arena.at<int8_t>(h->off_spins);
+  int8_t *logical = h->arena.at<int8_t>(h->off_logical);
+  int32_t *lenergy = h->arena.at<int32_t>(h->off_lenergy);
+  const int32_t *dJ = h->arena.at<int32_t>(h->off_J);
+  const int32_t *dh = h->has_h ? h->arena.at<int32_t>(h->off_h) : nullptr;
+  if (p.decoder == SQA_DEC_ME_MAJORITY) {
+    const int len = h->emb.kind == SQA_EMB_ME ? N - 1 : (N + 3) / 4 + 1;
+    return launch_me_majority(spins, R, N, len, n, L, p.readout_slice, dJ, dh, logical, lenergy, s);
+  }
+  const DecodeLayout dl = decode_layout(R, N, K, tree_entries);
+  auto *rows = reinterpret_cast<uint32_t *>(base + dl.rows);
+  auto *best = reinterpret_cast<unsigned long long *>(base + dl.best);
+  auto *acc = reinterpret_cast<unsigned long long *>(base + dl.acc);
+  auto *pairs = reinterpret_cast<int8_t *>(base + dl.pairs);
+  auto *wtab = reinterpret_cast<uint64_t *>(base + dl.wtab);
+  auto *dec = reinterpret_cast<int8_t *>(base + dl.dec);
+  auto *par = reinterpret_cast<int32_t *>(base + dl.par);
+  auto *ord = reinterpret_cast<int32_t *>(base + dl.ord);
+  hipError_t e = hipSuccess;
+  if (p.decoder != SQA_DEC_LHZ_TREES) e = launch_lhz_rows(spins, R, L, K, N, p.readout_slice, rows, s);
+  if (e == hipSuccess) {
+    switch (p.decoder) {
+      case SQA_DEC_LHZ_TREES:
+        e = launch_lhz_trees(spins + static_cast<size_t>(p.readout_slice) * K, static_cast<size_t>(L) * K, R, N, par,
+                             ord, p.n_trees, logical, s);
+        break;
+      case SQA_DEC_LHZ_MWD:
+        e = launch_lhz_mwd(rows, R, N, best, logical, s);
+        break;
+      case SQA_DEC_LHZ_MLD:
+        e = launch_lhz_mld(rows, R, N, best, wtab, 2 * K + 1, acc, logical, s);
+        break;
+      default:
+        e = launch_lhz_bp(rows, R, N, p.iterations, dec, pairs, s);
+        if (e == hipSuccess) e = launch_lhz_trees(pairs, static_cast<size_t>(K), R, N, par, ord, p.n_trees, logical, s);
+        break;
+    }
+  }
+  if (e == hipSuccess) e = launch_logical_energy(logical, R, N, dJ, dh, lenergy, s);
+  return e;
+}
+
 }  // namespace sqa
 
 extern "C" {
@@ -705,121 +816,38 @@ sqa_status sqa_decode_ex(sqa_handle *h, const sqa_decode_params *prm, int8_t *lo
   if (st != SQA_OK) return st;
   if (!prm) return fail(SQA_ERR_INVALID, "null decode parameters");
   const sqa_decode_params p = *prm;
-  if (p.readout_slice < 0 || p.readout_slice >= h->L) return fail(SQA_ERR_INVALID, "readout slice out of range");
   if (!h->initialised) return fail(SQA_ERR_INVALID, "no state yet: anneal first");
-  const int N = h->N, R = h->R, n = h->emb.n, L = h->L;
+  std::vector<int32_t> order;
+  st = decode_check(h, p, &order);
+  if (st != SQA_OK) return st;
+  const int N = h->N, R = h->R;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  int8_t *spins = h->arena.at<int8_t>(h->off_spins);
-  int8_t *logical = h->arena.at<int8_t>(h->off_logical);
-  int32_t *lenergy = h->arena.at<int32_t>(h->off_lenergy);
-  const int32_t *dJ = h->arena.at<int32_t>(h->off_J);
-  const int32_t *dh = h->has_h ? h->arena.at<int32_t>(h->off_h) : nullptr;
-  hipError_t e = hipSuccess;
-  if (p.decoder == SQA_DEC_ME_MAJORITY) {
-    if (h->emb.kind != SQA_EMB_ME && h->emb.kind != SQA_EMB_ME_CHIMERA)
-      return fail(SQA_ERR_INVALID, "majority decoding of chains needs an ME handle");
-    const int len = h->emb.kind == SQA_EMB_ME ? N - 1 : (N + 3) / 4 + 1;
-    e = hipStreamWaitEvent(s, h->done, 0);
-    if (e == hipSuccess)
-      e = launch_me_majority(spins, R, N, len, n, L, p.readout_slice, dJ, dh, logical, lenergy, s);
-  } else {
-    if (p.decoder != SQA_DEC_LHZ_TREES && p.decoder != SQA_DEC_LHZ_MWD && p.decoder != SQA_DEC_LHZ_MLD &&
-        p.decoder != SQA_DEC_LHZ_BP)
-      return fail(SQA_ERR_INVALID, "unknown decoder");
-    if (h->emb.kind != SQA_EMB_LHZ) return fail(SQA_ERR_INVALID, "LHZ decoders need an LHZ handle");
-    const int K = n;
-    const bool trees = p.decoder == SQA_DEC_LHZ_TREES || p.decoder == SQA_DEC_LHZ_BP;
-    if (p.decoder == SQA_DEC_LHZ_MWD && N > 32)
-      return fail(SQA_ERR_UNSUPPORTED, "exhaustive minimum-weight decoding limited to n <= 32");
-    if (p.decoder == SQA_DEC_LHZ_MLD && N > 24)
-      return fail(SQA_ERR_UNSUPPORTED, "exhaustive maximum-likelihood decoding limited to n <= 24");
-    if (p.decoder == SQA_DEC_LHZ_BP && N > 32)
-      return fail(SQA_ERR_UNSUPPORTED, "parity-check decoding limited to n <= 32");
-    if ((p.decoder == SQA_DEC_LHZ_MLD || p.decoder == SQA_DEC_LHZ_BP) && !(p.error_rate > 0.0 && p.error_rate < 0.5))
-      return fail(SQA_ERR_INVALID, "error rate must be in (0, 1/2)");
-    if (p.decoder == SQA_DEC_LHZ_BP && p.iterations < 0) return fail(SQA_ERR_INVALID, "negative iteration count");
-    std::vector<int32_t> order;
-    if (trees) {
-      st = tree_orders(N, p.tree_parents, p.n_trees, &order);
-      if (st != SQA_OK) return st;
-    }
-    const DecodeLayout dl = decode_layout(R, N, K, order.size());
-    const size_t o_rows = dl.rows, o_best = dl.best, o_acc = dl.acc, o_pairs = dl.pairs, o_wtab = dl.wtab,
-                 o_dec = dl.dec, o_par = dl.par, o_ord = dl.ord;
-    st = decode_scratch(h, dl.bytes);
+  char *base = nullptr;
+  if (p.decoder != SQA_DEC_ME_MAJORITY) {
+    st = decode_scratch(h, decode_layout(R, N, h->emb.n, order.size()).bytes);
     if (st != SQA_OK) return st;
-    char *base = static_cast<char *>(h->dec_buf);
-    auto *rows = reinterpret_cast<uint32_t *>(base + o_rows);
-    auto *best = reinterpret_cast<unsigned long long *>(base + o_best);
-    auto *acc = reinterpret_cast<unsigned long long *>(base + o_acc);
-    auto *pairs = reinterpret_cast<int8_t *>(base + o_pairs);
-    auto *wtab = reinterpret_cast<uint64_t *>(base + o_wtab);
-    auto *dec = reinterpret_cast<int8_t *>(base + o_dec);
-    auto *par = reinterpret_cast<int32_t *>(base + o_par);
-    auto *ord = reinterpret_cast<int32_t *>(base + o_ord);
+    base = static_cast<char *>(h->dec_buf);
     // host tables (the earlier decodes that read this scratch have finished first)
-    if (trees || p.decoder == SQA_DEC_LHZ_MLD) {
-      e = hipEventSynchronize(h->done);
+    if (p.decoder != SQA_DEC_LHZ_MWD) {
+      hipError_t e = hipEventSynchronize(h->done);
       if (e != hipSuccess) {
         h->poisoned = true;
         return hip_fail(e, "hipEventSynchronize");
       }
+      st = decode_tables(h, p, order, base);
+      if (st != SQA_OK) return st;
     }
-    if (trees) {
-      e = hipMemcpy(par, p.tree_parents, order.size() * 4, hipMemcpyHostToDevice);
-      if (e == hipSuccess) e = hipMemcpy(ord, order.data(), order.size() * 4, hipMemcpyHostToDevice);
-    }
-    if (e == hipSuccess && p.decoder == SQA_DEC_LHZ_MLD) {
-      // Sec. IV B: weights round(2^36 exp(-beta_N d)), d = O_max - O, beta_N = ln((1-p)/p) / 2
-      const double beta = 0.5 * std::log((1.0 - p.error_rate) / p.error_rate);
-      std::vector<uint64_t> w(2 * K + 1);
-      for (int d = 0; d <= 2 * K; ++d)
-        w[d] = static_cast<uint64_t>(std::llround(std::ldexp(std::exp(-beta * static_cast<double>(d)), 36)));
-      e = hipMemcpy(wtab, w.data(), w.size() * 8, hipMemcpyHostToDevice);
-    }
-    if (e == hipSuccess && p.decoder == SQA_DEC_LHZ_BP) {
-      // Sec. IV D: x_ij <- sign(w0 s_ij + w1 c), tie keeps s_ij; w0 = ln((1-p)/p), w1 = ln((1-p2)/p2), p2 = 2p(1-p)
-      const double q = p.error_rate, q2 = 2.0 * q * (1.0 - q);
-      const double w0 = std::log((1.0 - q) / q), w1 = std::log((1.0 - q2) / q2);
-      std::vector<int8_t> d(2 * (2 * N - 3) + 1, 1);
-      for (int neg = 0; neg < 2; ++neg)
-        for (int c = -(N - 2); c <= N - 2; ++c) {
-          const int sv = neg ? -1 : 1;
-          const double v = w0 * static_cast<double>(sv) + w1 * static_cast<double>(c);
-          d[neg * (2 * N - 3) + c + N - 2] = static_cast<int8_t>(v > 0.0 ? 1 : (v < 0.0 ? -1 : sv));
-        }
-      e = hipMemcpy(dec, d.data(), d.size(), hipMemcpyHostToDevice);
-    }
-    if (e == hipSuccess) e = hipStreamWaitEvent(s, h->done, 0);
-    if (e == hipSuccess && p.decoder != SQA_DEC_LHZ_TREES)
-      e = launch_lhz_rows(spins, R, L, K, N, p.readout_slice, rows, s);
-    if (e == hipSuccess) {
-      switch (p.decoder) {
-        case SQA_DEC_LHZ_TREES:
-          e = launch_lhz_trees(spins + static_cast<size_t>(p.readout_slice) * K, static_cast<size_t>(L) * K, R, N,
-                               par, ord, p.n_trees, logical, s);
-          break;
-        case SQA_DEC_LHZ_MWD:
-          e = launch_lhz_mwd(rows, R, N, best, logical, s);
-          break;
-        case SQA_DEC_LHZ_MLD:
-          e = launch_lhz_mld(rows, R, N, best, wtab, 2 * K + 1, acc, logical, s);
-          break;
-        default:
-          e = launch_lhz_bp(rows, R, N, p.iterations, dec, pairs, s);
-          if (e == hipSuccess)
-            e = launch_lhz_trees(pairs, static_cast<size_t>(K), R, N, par, ord, p.n_trees, logical, s);
-          break;
-      }
-    }
-    if (e == hipSuccess) e = launch_logical_energy(logical, R, N, dJ, dh, lenergy, s);
   }
+  hipError_t e = hipStreamWaitEvent(s, h->done, 0);
+  if (e == hipSuccess) e = decode_enqueue(h, p, order.size(), base, s);
   if (e == hipSuccess) e = hipEventRecord(h->done, s);
   if (e != hipSuccess) {
     h->poisoned = true;
     return hip_fail(e, "decode launch");
   }
   if (!logical_out && !logical_energy_out) return SQA_OK;    // results stay on the device
+  int8_t *logical = h->arena.at<int8_t>(h->off_logical);
+  int32_t *lenergy = h->arena.at<int32_t>(h->off_lenergy);
   e = hipEventSynchronize(h->done);
   if (e == hipSuccess && logical_out) e = hipMemcpy(logical_out, logical, static_cast<size_t>(R) * N, hipMemcpyDeviceToHost);
   if (e == hipSuccess && logical_energy_out)
@@ -1026,8 +1054,18 @@ struct sqa_batch {
   std::vector<sqa::MoveGroup> groups;
   void *dev = nullptr;
   hipStream_t capture_stream = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr, graph_dec = nullptr;
+  hipGraphExec_t exec = nullptr, exec_dec = nullptr;
+  // decoders captured after the anneal: per handle its parameters (decoder -1:
+  // none), tree copies and orders, and a scratch the batch owns
+  std::vector<sqa_decode_params> dec;
+  std::vector<std::vector<int32_t>> trees, orders;
+  std::vector<void *> dec_buf;
+  bool decodes = false;
+  // timing of the last run: before the anneal graph, between it and the decoder
+  // graph, after both
+  hipEvent_t ev0 = nullptr, ev_mid = nullptr, ev1 = nullptr;
+  bool ran = false;
 };
 
 static sqa_status batch_build(sqa_handle *const *handles, int32_t count, int waves, int gpc, bool allow_team,
@@ -1063,8 +1101,46 @@ static sqa_status batch_build(sqa_handle *const *handles, int32_t count, int wav
   return SQA_OK;
 }
 
+// Checks each handle's decoder, copies its trees, gives it a scratch of its own
+// and fills the scratch's host tables, all before capture.
+static sqa_status batch_decoders(sqa_batch *b, const sqa_decode_params *decoders) {
+  const size_t n = b->handles.size();
+  b->dec.assign(n, sqa_decode_params{});
+  b->trees.assign(n, {});
+  b->orders.assign(n, {});
+  b->dec_buf.assign(n, nullptr);
+  for (size_t i = 0; i < n; ++i) {
+    sqa_decode_params p = decoders[i];
+    b->dec[i] = p;
+    if (p.decoder == -1) continue;
+    const sqa_handle *h = b->handles[i];
+    sqa_status st = decode_check(h, p, &b->orders[i]);
+    if (st != SQA_OK) return st;
+    if (p.decoder == SQA_DEC_LHZ_TREES || p.decoder == SQA_DEC_LHZ_BP) {
+      b->trees[i].assign(p.tree_parents, p.tree_parents + static_cast<size_t>(p.n_trees) * h->N);
+      b->dec[i].tree_parents = b->trees[i].data();
+    } else {
+      b->dec[i].tree_parents = nullptr;
+    }
+    b->decodes = true;
+    if (p.decoder == SQA_DEC_ME_MAJORITY) continue;
+    hipError_t e = hipMalloc(&b->dec_buf[i], decode_layout(h->R, h->N, h->emb.n, b->orders[i].size()).bytes);
+    if (e != hipSuccess) {
+      b->dec_buf[i] = nullptr;
+      return hip_fail(e, "hipMalloc (batch decoder scratch)");
+    }
+    st = decode_tables(h, b->dec[i], b->orders[i], static_cast<char *>(b->dec_buf[i]));
+    if (st != SQA_OK) return st;
+  }
+  return SQA_OK;
+}
+
 static sqa_status batch_capture(sqa_batch *b) {
-  hipError_t e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking);
+  hipError_t e = hipEventCreate(&b->ev0);
+  if (e == hipSuccess) e = hipEventCreate(&b->ev_mid);
+  if (e == hipSuccess) e = hipEventCreate(&b->ev1);
+  if (e != hipSuccess) return hip_fail(e, "hipEventCreate (batch timing)");
+  e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking);
   if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
   e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
@@ -1074,6 +1150,20 @@ static sqa_status batch_capture(sqa_batch *b) {
   if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
   e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
   if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+  if (!b->decodes) return SQA_OK;
+  // the decoders in a second graph, replayed right after the first on the same stream
+  e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+  le = hipSuccess;
+  for (size_t i = 0; i < b->handles.size() && le == hipSuccess; ++i)
+    if (b->dec[i].decoder != -1)
+      le = decode_enqueue(b->handles[i], b->dec[i], b->orders[i].size(), static_cast<char *>(b->dec_buf[i]),
+                          b->capture_stream);
+  e = hipStreamEndCapture(b->capture_stream, &b->graph_dec);
+  if (le != hipSuccess) return hip_fail(le, "capture decoder launch");
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  e = hipGraphInstantiate(&b->exec_dec, b->graph_dec, nullptr, nullptr, 0);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
   return SQA_OK;
 }
 
@@ -1081,8 +1171,14 @@ static void batch_free(sqa_batch *b) {
   if (!b) return;
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->exec_dec) (void)hipGraphExecDestroy(b->exec_dec);
+  if (b->graph_dec) (void)hipGraphDestroy(b->graph_dec);
   if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
   if (b->dev) (void)hipFree(b->dev);
+  for (void *p : b->dec_buf)
+    if (p) (void)hipFree(p);
+  for (hipEvent_t ev : {b->ev0, b->ev_mid, b->ev1})
+    if (ev) (void)hipEventDestroy(ev);
   delete b;
 }
 
@@ -1090,6 +1186,11 @@ extern "C" {
 
 sqa_status sqa_batch_create(sqa_handle *const *handles, int32_t count, const sqa_launch_config *config,
                             sqa_batch **out) {
+  return sqa_batch_create_decoded(handles, count, config, nullptr, out);
+}
+
+sqa_status sqa_batch_create_decoded(sqa_handle *const *handles, int32_t count, const sqa_launch_config *config,
+                                    const sqa_decode_params *decoders, sqa_batch **out) {
   if (!handles || count < 1 || !out) return fail(SQA_ERR_INVALID, "bad batch arguments");
   *out = nullptr;
   for (int i = 0; i < count; ++i) {
@@ -1108,7 +1209,8 @@ sqa_status sqa_batch_create(sqa_handle *const *handles, int32_t count, const sqa
   const bool allow_team = !(config && config->waves_per_group > 0);
   sqa_status st = batch_build(handles, count, waves, gpc, allow_team, &b);
   if (st != SQA_OK) return st;
-  st = batch_capture(b);
+  if (decoders) st = batch_decoders(b, decoders);
+  if (st == SQA_OK) st = batch_capture(b);
   if (st != SQA_OK) {
     batch_free(b);
     return st;
@@ -1125,7 +1227,13 @@ sqa_status sqa_batch_run(sqa_batch *b, void *stream) {
     hipError_t e = hipStreamWaitEvent(s, h->done, 0);
     if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
   }
-  hipError_t e = hipGraphLaunch(b->exec, s);
+  hipError_t e = hipEventRecord(b->ev0, s);
+  if (e == hipSuccess) e = hipGraphLaunch(b->exec, s);
+  if (e == hipSuccess && b->decodes) {
+    e = hipEventRecord(b->ev_mid, s);
+    if (e == hipSuccess) e = hipGraphLaunch(b->exec_dec, s);
+  }
+  if (e == hipSuccess) e = hipEventRecord(b->ev1, s);
   if (e != hipSuccess) {
     for (sqa_handle *h : b->handles) h->poisoned = true;
     return hip_fail(e, "hipGraphLaunch");
@@ -1135,6 +1243,20 @@ sqa_status sqa_batch_run(sqa_batch *b, void *stream) {
     if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
     h->initialised = true;
   }
+  b->ran = true;
+  return SQA_OK;
+}
+
+sqa_status sqa_batch_timing(sqa_batch *b, float *anneal_ms, float *decode_ms) {
+  if (!b) return fail(SQA_ERR_INVALID, "null batch");
+  if (!b->ran) return fail(SQA_ERR_INVALID, "the batch has not run yet");
+  hipError_t e = hipEventSynchronize(b->ev1);
+  float a = 0.0f, d = 0.0f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&a, b->ev0, b->decodes ? b->ev_mid : b->ev1);
+  if (e == hipSuccess && b->decodes) e = hipEventElapsedTime(&d, b->ev_mid, b->ev1);
+  if (e != hipSuccess) return hip_fail(e, "batch timing");
+  if (anneal_ms) *anneal_ms = a;
+  if (decode_ms) *decode_ms = d;
   return SQA_OK;
 }
 

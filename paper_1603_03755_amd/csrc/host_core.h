@@ -192,6 +192,14 @@ sqa_status handle_upload(sqa_handle *h, const sqa_allocator *alloc);
 // (`tree_entries` = n_trees * n for the tree decoders).
 size_t handle_block_bytes(const sqa_handle *h);
 size_t decode_scratch_bytes(const sqa_handle *h, int decoder, size_t tree_entries);
+
+// A decoder in three steps: check it against the handle (and order the trees'
+// vertices), copy its host tables into a scratch laid out for it (synchronous),
+// and queue its kernels (kernels only, so a graph can hold them).
+sqa_status decode_check(const sqa_handle *h, const sqa_decode_params &p, std::vector<int32_t> *order);
+sqa_status decode_tables(const sqa_handle *h, const sqa_decode_params &p, const std::vector<int32_t> &order, char *base);
+hipError_t decode_enqueue(const sqa_handle *h, const sqa_decode_params &p, size_t tree_entries, char *base,
+                          hipStream_t s);
 }  // namespace sqa
 
 // Handle: one problem x embedding x schedule, its device buffers and state.

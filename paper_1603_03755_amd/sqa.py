@@ -97,7 +97,10 @@ _SIGS = {
     "sqa_handle_info": (C.c_int, [_VP] + [C.POINTER(C.c_int32)] * 5),
     "sqa_destroy": (None, [_VP]),
     "sqa_batch_create": (C.c_int, [_PVP, C.c_int32, C.POINTER(sqa_launch_config), _PVP]),
+    "sqa_batch_create_decoded": (C.c_int, [_PVP, C.c_int32, C.POINTER(sqa_launch_config),
+                                           C.POINTER(sqa_decode_params), _PVP]),
     "sqa_batch_run": (C.c_int, [_VP, _VP]),
+    "sqa_batch_timing": (C.c_int, [_VP, C.POINTER(C.c_float), C.POINTER(C.c_float)]),
     "sqa_batch_config": (C.c_int, [_VP, C.POINTER(sqa_launch_config)]),
     "sqa_batch_destroy": (None, [_VP]),
     "sqa_anneal_batch": (C.c_int, [_PVP, C.c_int32, _VP]),
@@ -367,15 +370,39 @@ def _handle_array(handles: Sequence[SQA]):
     return arr
 
 
-class Batch:
-    """All handles' full anneals in one persistent launch, replayed from a HIP graph."""
+def decode_params(decoder: int, readout_slice: int = 0, trees=None, n: int = 0, error_rate: float = 0.2,
+                  iterations: int = 10):
+    """An sqa_decode_params (decoder -1 = none) and the tree array it points into."""
+    t = None if trees is None else np.ascontiguousarray(trees, dtype=np.int32).reshape(-1, n)
+    p = sqa_decode_params(decoder, readout_slice, t.ctypes.data_as(C.POINTER(C.c_int32)) if t is not None else None,
+                          0 if t is None else t.shape[0], error_rate, iterations)
+    return p, t
 
-    def __init__(self, handles: Sequence[SQA], waves_per_group: int = 0, groups_per_cu: int = 0):
+
+class Batch:
+    """All handles' full anneals in one persistent launch, replayed from a HIP graph;
+    with `decoders` (one (decoder, readout slice[, trees]) per handle, or None for a
+    handle), each handle's decoder runs in the same graph after the anneal."""
+
+    def __init__(self, handles: Sequence[SQA], waves_per_group: int = 0, groups_per_cu: int = 0, decoders=None):
         self.handles = list(handles)
         self._arr = _handle_array(self.handles)
         cfg = sqa_launch_config(waves_per_group, groups_per_cu)
         out = C.c_void_p()
-        _check(lib().sqa_batch_create(C.cast(self._arr, _PVP), len(self.handles), C.byref(cfg), C.byref(out)))
+        if decoders is None:
+            _check(lib().sqa_batch_create(C.cast(self._arr, _PVP), len(self.handles), C.byref(cfg), C.byref(out)))
+        else:
+            arr = (sqa_decode_params * len(self.handles))()
+            keep = []
+            for i, (h, d) in enumerate(zip(self.handles, decoders)):
+                if d is None:
+                    arr[i] = sqa_decode_params(-1, 0, None, 0, 0.2, 10)
+                    continue
+                p, t = decode_params(d[0], d[1] if len(d) > 1 else 0, d[2] if len(d) > 2 else None, h.N)
+                arr[i] = p
+                keep.append(t)
+            _check(lib().sqa_batch_create_decoded(C.cast(self._arr, _PVP), len(self.handles), C.byref(cfg), arr,
+                                                  C.byref(out)))
         self.b = out
 
     def run(self, stream=None):
@@ -385,6 +412,12 @@ class Batch:
         c = sqa_launch_config()
         _check(lib().sqa_batch_config(self.b, C.byref(c)))
         return c.waves_per_group, c.groups_per_cu
+
+    def timing(self):
+        """(anneal ms, decode ms) of the last run, from HIP events on its stream."""
+        a, d = C.c_float(), C.c_float()
+        _check(lib().sqa_batch_timing(self.b, C.byref(a), C.byref(d)))
+        return a.value, d.value
 
     def close(self):
         if getattr(self, "b", None):
