@@ -335,6 +335,18 @@ SQA_API void sqa_batch_destroy(sqa_batch *b);
 /* One-shot convenience: create, run on `stream`, destroy (no graph reuse). */
 SQA_API sqa_status sqa_anneal_batch(sqa_handle *const *handles, int32_t count, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): sqa_anneal_batch with
+ * the same results, whose launch scratch (handle descriptors, work items, work
+ * counters) is a file-scope device array of the library, 4 MiB per GPU, held by
+ * every GPU the library runs on until the process ends, instead of a fresh
+ * allocation.  It calls no allocating routine and captures no graph; it returns
+ * after the launch on `stream` has finished.  Every call on one GPU shares that
+ * GPU's array: calls that overlap on one GPU (from several host threads) race.
+ * SQA_ERR_UNSUPPORTED when the batch's scratch (descriptors of `count` handles
+ * plus at most one work item per replica) exceeds the array. */
+SQA_API sqa_status sqa_anneal_batch_noalloc(sqa_handle *const *handles, int32_t count, void *stream);
+
 /* Autotuner: times candidate launch shapes on the given handles (short
  * sweep ranges, device state restored afterwards) and stores the best per
  * (device architecture, shape class) in the JSON cache at `cache_path`

@@ -1282,6 +1282,53 @@ sqa_status sqa_anneal_batch(sqa_handle *const *handles, int32_t count, void *str
   return st;
 }
 
+// The one-shot batch without allocations: the same plan and kernels, with the
+// descriptors, work items and counters in the library's file-scope launch
+// scratch (this device's copy) instead of a fresh device buffer, and no graph.
+sqa_status sqa_anneal_batch_noalloc(sqa_handle *const *handles, int32_t count, void *stream) {
+  if (!handles || count < 1) return fail(SQA_ERR_INVALID, "bad batch arguments");
+  for (int i = 0; i < count; ++i) {
+    sqa_status st = check_handle(handles[i]);
+    if (st != SQA_OK) return st;
+  }
+  hipError_t e = ensure_lds_limits();
+  if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
+  std::vector<const sqa_handle *> hs(handles, handles + count);
+  int waves = 4, gpc = 0;
+  resolve_config(hs, nullptr, &waves, &gpc);
+  std::vector<int> m0(count, 0), m1(count);
+  for (int i = 0; i < count; ++i) m1[i] = handles[i]->M;
+  std::vector<MoveGroup> groups;
+  size_t bytes = 0;
+  sqa_status st = plan_groups(hs, m0, m1, waves, gpc, &groups, &bytes, true);
+  if (st != SQA_OK) return st;
+  if (bytes > kNoAllocScratchBytes)
+    return fail(SQA_ERR_UNSUPPORTED, "launch scratch of " + std::to_string(bytes) + " bytes exceeds the " +
+                                         std::to_string(kNoAllocScratchBytes) +
+                                         "-byte static scratch: use sqa_anneal_batch");
+  void *base = nullptr;
+  st = noalloc_scratch(&base);
+  if (st != SQA_OK) return st;
+  std::vector<HandleDev> hds(count);
+  for (int i = 0; i < count; ++i) hds[i] = handles[i]->dev(0, handles[i]->M, kFlagInit | kFlagEnergy);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  for (sqa_handle *h : std::vector<sqa_handle *>(handles, handles + count)) {
+    e = hipStreamWaitEvent(s, h->done, 0);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
+  }
+  e = upload_groups(static_cast<char *>(base), hds, groups, s);
+  if (e == hipSuccess) e = launch_groups(static_cast<char *>(base), groups, s);
+  if (e == hipSuccess)
+    for (int i = 0; i < count && e == hipSuccess; ++i) e = hipEventRecord(handles[i]->done, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    for (int i = 0; i < count; ++i) handles[i]->poisoned = true;
+    return hip_fail(e, "batch launch (static scratch)");
+  }
+  for (int i = 0; i < count; ++i) handles[i]->initialised = true;
+  return SQA_OK;
+}
+
 // Times each candidate shape on a short sweep range of the handles' full
 // batch (state saved and restored), keeps the fastest.
 sqa_status sqa_autotune(sqa_handle *const *handles, int32_t count, const char *cache_path, sqa_launch_config *best) {

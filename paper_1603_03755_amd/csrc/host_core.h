@@ -132,6 +132,11 @@ hipError_t launch_pt(const PTDev *pts, int count, int waves, int rec_cap, int la
                      hipStream_t stream);
 hipError_t set_pt_lds_limit(size_t bytes);
 
+// Size of the file-scope launch scratch of sqa_anneal_batch_noalloc (per GPU),
+// and the current device's address of it (looked up once per device).
+constexpr size_t kNoAllocScratchBytes = size_t(4) << 20;
+sqa_status noalloc_scratch(void **ptr_out);
+
 // hipErrorLaunchFailure when the environment asks for injected launch faults
 // (SQA_FAULT_INJECT=launch), else hipSuccess.
 hipError_t injected_launch_fault();

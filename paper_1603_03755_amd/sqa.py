@@ -104,6 +104,7 @@ _SIGS = {
     "sqa_batch_config": (C.c_int, [_VP, C.POINTER(sqa_launch_config)]),
     "sqa_batch_destroy": (None, [_VP]),
     "sqa_anneal_batch": (C.c_int, [_PVP, C.c_int32, _VP]),
+    "sqa_anneal_batch_noalloc": (C.c_int, [_PVP, C.c_int32, _VP]),
     "sqa_autotune": (C.c_int, [_PVP, C.c_int32, C.c_char_p, C.POINTER(sqa_launch_config)]),
     "pt_create": (C.c_int, [C.POINTER(sqa_problem), C.POINTER(sqa_embedding), C.POINTER(pt_params), _PVP]),
     "pt_run_handle": (C.c_int, [_VP, _VP]),
@@ -434,6 +435,12 @@ class Batch:
 def sqa_anneal_batch(handles: Sequence[SQA], stream=None):
     arr = _handle_array(handles)
     _check(lib().sqa_anneal_batch(C.cast(arr, _PVP), len(handles), _stream(stream)))
+
+
+def sqa_anneal_batch_noalloc(handles: Sequence[SQA], stream=None):
+    """sqa_anneal_batch without allocating: the launch scratch is the library's static array."""
+    arr = _handle_array(handles)
+    _check(lib().sqa_anneal_batch_noalloc(C.cast(arr, _PVP), len(handles), _stream(stream)))
 
 
 def sqa_autotune(handles: Sequence[SQA], cache_path: Optional[str] = None):
