@@ -13,7 +13,9 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# SQA_ORACLE_LIB names another build of the same sources (the sanitizer build of
+# oracle/build_sanitized.sh); default: liboracle.so beside this file.
+_LIB_PATH = os.environ.get("SQA_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 ME, LHZ, MEC = 0, 1, 2

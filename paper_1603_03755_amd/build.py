@@ -57,6 +57,40 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+HOST_SOURCES = ["host_core.cpp", "api_sqa.cpp", "api_pt.cpp", "api_server.cpp"]
+
+
+def build_host_sanitized(out_dir: str, verbose: bool = False) -> str:
+    """libsqa_asan.so in out_dir: the library's host code (embedding, layout, tables,
+    handle and server bookkeeping) built with AddressSanitizer and
+    UndefinedBehaviorSanitizer, linked with the device objects of the last build()
+    (the kernels are not instrumented).  Load it through SQA_LIBRARY with clang's
+    ASan runtime preloaded."""
+    build_dir = os.path.join(HERE, "_build")
+    dev_objs = [os.path.join(build_dir, s + ".o") for s in SOURCES if s.endswith(".hip")]
+    missing = [o for o in dev_objs if not os.path.exists(o)]
+    if missing:
+        raise RuntimeError(f"run build() first: missing {missing}")
+    san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+           "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer"]
+    common = ["-O1", "-g", "-std=c++17", "-fPIC", "-fvisibility=hidden", f"--offload-arch={ARCH}", "-ffp-contract=off"]
+    objs = []
+    for src in HOST_SOURCES:
+        obj = os.path.join(out_dir, src + ".asan.o")
+        cmd = [hipcc()] + common + san + ["-c", os.path.join(CSRC, src), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        objs.append(obj)
+    lib = os.path.join(out_dir, "libsqa_asan.so")
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-shared-libsan"] + san + ["-o", lib] + objs + \
+        dev_objs + ["-lpthread"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    return lib
+
+
 if __name__ == "__main__":
     build(verbose="-v" in sys.argv)
     print(LIB)

@@ -14,7 +14,9 @@ from typing import Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libsqa.so")
+# SQA_LIBRARY names another build of the library (the sanitizer build of the host
+# code, build.build_host_sanitized); default: libsqa.so beside this file.
+LIB_PATH = os.environ.get("SQA_LIBRARY") or os.path.join(_HERE, "libsqa.so")
 
 SQA_OK, SQA_ERR_INVALID, SQA_ERR_OOM, SQA_ERR_DEVICE, SQA_ERR_UNSUPPORTED, SQA_ERR_BUSY, SQA_ERR_NOT_READY = \
     0, -1, -2, -3, -4, -5, -6
