@@ -22,12 +22,14 @@ namespace sqa {
 // so flips go back with one byte store.  Energies: per-thread deltas of the
 // eight replicas (a flip with a = s*f changes E by -2a), summed over each wave
 // (DPP row sums, lane permutes across rows) into the wave's own LDS partials
-// before the last class barrier of a sweep that ends in a swap phase.  Every
-// wave then decides the whole swap phase on its own: lane s holds the replica
-// at slot s and its energy, adds every wave's partial of that replica, and the
-// lanes of a pair exchange both (DPP for the even pairs, a lane permute for the
-// odd ones); a wave's own LDS scratch turns the new slot map into its threads'
-// table rows, so no barrier follows the swap phase.
+// before the last class barrier of a sweep that ends in a swap phase.  One
+// wave, the last, decides that swap phase at the start of the next sweep's
+// colour class 0, while the others compute what their first item of the class
+// needs before its thresholds (partner bytes, field sums, Philox words): lane s
+// holds the replica at slot s and its energy, adds every wave's partial of that
+// replica, and the lanes of a pair exchange both (DPP for the even pairs, a lane
+// permute for the odd ones).  The new slot of every replica goes to LDS, and
+// after one barrier each thread reads its replicas' table rows and finishes.
 //
 // Field sums: F <= 31 (byte mode): the records are in the signed-weight layout
 // and packed 16-bit multiply-adds form, per replica, a byte that addresses its
@@ -141,8 +143,54 @@ __device__ __forceinline__ SignedRec<KIND> signed_from_pt(const PTRec<KIND> &x) 
   return s;
 }
 
-// One item: site d (record x), replica byte a, sweep m.  row: the table row
-// offsets of the byte's eight replicas; dE: their energy deltas.
+// Threshold top halves of the byte's eight replicas, addressed by their V bytes.
+__device__ __forceinline__ void pt_thresholds(const lds_u8 *const *thb, uint2 V, uint32_t *th) {
+#pragma unroll
+  for (int w = 0; w < 8; ++w)
+    th[w] = *reinterpret_cast<const lds_u16 *>(thb[w] - (((w < 4 ? V.x : V.y) >> (8 * (w & 3))) & 0xFFu));
+}
+
+// The decisions of a byte-mode item from its Philox words u and threshold top
+// halves th: D = hi - top half is negative iff accepted on hi alone, zero on a
+// tie (the sign bits are shifted into `flip` from replica 7 down); a tie decides
+// all eight on 32 bits with the PT_LO call.  Then the byte store and the flip sums.
+__device__ __forceinline__ void pt_item_bytes_decide(const PTDev &P, uint32_t site, int d, uint8_t *latb,
+                                                     const uint2 *st8, int a, uint32_t vmask,
+                                                     const lds_u8 *const *thb, uint32_t f4, uint32_t *vpk,
+                                                     uint32_t &nit, uint32_t m, uint32_t own, uint2 V,
+                                                     const Words4 &u, const uint32_t *th) {
+  uint32_t flip = 0, dmin = 0xFFFFFFFFu;
+#pragma unroll
+  for (int w = 7; w >= 0; --w) {
+    const uint32_t hi = (w < 4) ? (u.v[w] & 0xFFFFu) : (u.v[w - 4] >> 16);
+    const uint32_t D = hi - th[w];
+    flip = __builtin_amdgcn_alignbit(flip, D, 31);
+    dmin = min(dmin, D);
+  }
+  if (dmin == 0) {     // some half equals its threshold's top half: decide all eight on 32 bits
+    const Words4 v = philox4x32_10(site, static_cast<uint32_t>(a), m, kStreamPTLo << 24, P.seed_lo, P.seed_hi);
+    flip = 0;
+#pragma unroll
+    for (int w = 0; w < 8; ++w) {
+      const uint32_t vb = ((w < 4 ? V.x : V.y) >> (8 * (w & 3))) & 0xFFu;
+      const uint32_t R = *reinterpret_cast<const lds_u32 *>(thb[w] - 2 - vb);
+      const uint32_t uu = (w < 4) ? ((u.v[w] << 16) | (v.v[w] & 0xFFFFu))
+                                  : ((u.v[w - 4] & 0xFFFF0000u) | (v.v[w - 4] >> 16));
+      if (min(uu, 0xFFFFFFFEu) < R) flip |= 1u << w;
+    }
+  }
+  flip &= vmask;
+  latb[8 * d + a] = static_cast<uint8_t>(own ^ flip);
+  const uint2 fsel = st8[kSpreadEntries + flip];
+  const uint32_t t_lo = __builtin_amdgcn_perm(f4, V.x, fsel.x), t_hi = __builtin_amdgcn_perm(f4, V.y, fsel.y);
+  vpk[0] += t_lo & 0x00FF00FFu;
+  vpk[1] += (t_lo >> 8) & 0x00FF00FFu;
+  vpk[2] += t_hi & 0x00FF00FFu;
+  vpk[3] += (t_hi >> 8) & 0x00FF00FFu;
+  ++nit;
+}
+
+// One item: site d (record x), replica byte a, sweep m.
 // Byte mode: the signed-weight sums give, per replica w, the byte
 // V_w = 4F - 4F_site + 8 S_w in [0, 8F]; its threshold's top half is the u16 at
 // thb[w] - V_w (thb[w] = the table's byte address + 4 row[w] + 8F + 2, so this is
@@ -170,46 +218,48 @@ __device__ __forceinline__ void pt_item_bytes(const PTDev &P, const PTRec<KIND> 
   __builtin_amdgcn_sched_barrier(0);
   const uint2 V = signed_sums<KIND>(sr, st8, own, pbyte);
   uint32_t th[8];
-#pragma unroll
-  for (int w = 0; w < 8; ++w)
-    th[w] = *reinterpret_cast<const lds_u16 *>(thb[w] - (((w < 4 ? V.x : V.y) >> (8 * (w & 3))) & 0xFFu));
+  pt_thresholds(thb, V, th);
   __builtin_amdgcn_sched_barrier(0);
   philox_rounds<5>(ps);
   __builtin_amdgcn_sched_barrier(0);
   const Words4 u = philox_words(ps);
-  // D = hi - top half: negative iff accepted on hi alone, zero on a tie; the
-  // sign bits are shifted into `flip` from replica 7 down
-  uint32_t flip = 0, dmin = 0xFFFFFFFFu;
-#pragma unroll
-  for (int w = 7; w >= 0; --w) {
-    const uint32_t hi = (w < 4) ? (u.v[w] & 0xFFFFu) : (u.v[w - 4] >> 16);
-    const uint32_t D = hi - th[w];
-    flip = __builtin_amdgcn_alignbit(flip, D, 31);
-    dmin = min(dmin, D);
-  }
-  if (dmin == 0) {     // some half equals its threshold's top half: decide all eight on 32 bits
-    const Words4 v = philox4x32_10(sr.site, static_cast<uint32_t>(a), m, kStreamPTLo << 24, P.seed_lo, P.seed_hi);
-    flip = 0;
-#pragma unroll
-    for (int w = 0; w < 8; ++w) {
-      const uint32_t vb = ((w < 4 ? V.x : V.y) >> (8 * (w & 3))) & 0xFFu;
-      const uint32_t R = *reinterpret_cast<const lds_u32 *>(thb[w] - 2 - vb);
-      const uint32_t uu = (w < 4) ? ((u.v[w] << 16) | (v.v[w] & 0xFFFFu))
-                                  : ((u.v[w - 4] & 0xFFFF0000u) | (v.v[w - 4] >> 16));
-      if (min(uu, 0xFFFFFFFEu) < R) flip |= 1u << w;
-    }
-  }
-  flip &= vmask;
-  latb[8 * d + a] = static_cast<uint8_t>(own ^ flip);
-  const uint2 fsel = st8[kSpreadEntries + flip];
-  const uint32_t t_lo = __builtin_amdgcn_perm(f4, V.x, fsel.x), t_hi = __builtin_amdgcn_perm(f4, V.y, fsel.y);
-  vpk[0] += t_lo & 0x00FF00FFu;
-  vpk[1] += (t_lo >> 8) & 0x00FF00FFu;
-  vpk[2] += t_hi & 0x00FF00FFu;
-  vpk[3] += (t_hi >> 8) & 0x00FF00FFu;
-  ++nit;
+  pt_item_bytes_decide(P, sr.site, d, latb, st8, a, vmask, thb, f4, vpk, nit, m, own, V, u, th);
 }
 
+// The part of a byte-mode item that does not depend on the replicas'
+// temperatures (own and partner bytes, the sums V, the Philox words), for the
+// first item of a colour class that begins while a swap phase is decided.
+struct PTItemHead {
+  uint32_t own, site;
+  uint2 V;
+  Words4 u;
+};
+
+template <int KIND>
+__device__ __forceinline__ PTItemHead pt_item_bytes_head(const PTDev &P, const PTRec<KIND> &x, int d,
+                                                         const uint8_t *latb, const uint2 *st8, int a, uint32_t m) {
+  using S = Site<KIND>;
+  const SignedRec<KIND> sr = signed_from_pt<KIND>(x);
+  PTItemHead hd;
+  hd.own = latb[8 * d + a];
+  hd.site = sr.site;
+  uint32_t pbyte[S::T * S::P];
+#pragma unroll
+  for (int i = 0; i < S::T * S::P; ++i) pbyte[i] = latb[sr.poff[i] + a];
+  PhiloxState ps = philox_start(sr.site, static_cast<uint32_t>(a), m, kStreamPT << 24, P.seed_lo, P.seed_hi);
+  __builtin_amdgcn_sched_barrier(0);
+  philox_rounds<5>(ps);
+  philox_pin(ps);
+  __builtin_amdgcn_sched_barrier(0);
+  hd.V = signed_sums<KIND>(sr, st8, hd.own, pbyte);
+  philox_rounds<5>(ps);
+  hd.u = philox_words(ps);
+  return hd;
+}
+
+// One item of the 6-bit-field or per-replica modes: site d (record x), replica
+// byte a, sweep m; row: the table row offsets of the byte's eight replicas; dE:
+// their energy deltas.
 template <int KIND, bool SWAR>
 __device__ __forceinline__ void pt_item(const PTDev &P, const PTRec<KIND> &x, int d, uint8_t *latb,
                                         const uint32_t *mtab, int a, uint32_t vmask, const int32_t *row,
@@ -343,13 +393,12 @@ struct SwapSlot {
 // One swap phase (Eq. (B1)) as one wave sees it: lane s holds the replica at
 // slot s and its energy as of the last phase; it adds every wave's energy
 // partial of that replica, then the even pairs (r, r + 1), then the odd ones,
-// are decided by both of their lanes from the same inputs.  Wave 0 counts the
+// are decided by both of their lanes from the same inputs.  The wave counts the
 // accepted swaps of pair r in acc[r].  Kept out of line so that its registers
 // do not weigh on the sweep's.
 __device__ __noinline__ SwapSlot swap_phase(int rep_s, int e, int R, int Dmax, bool staged, const lds_u32 *spk,
                                             glb_u32 *stab, const lds_u32 *sw, const lds_i32 *parts, lds_u32 *acc) {
   const int lane = static_cast<int>(threadIdx.x & 63u);
-  const bool counts = threadIdx.x < 64u;
   int32_t de = 0;
 #pragma unroll
   for (int v = 0; v < kPTMaxWaves; ++v) de += parts[64 * v + (rep_s & 63)];
@@ -386,7 +435,7 @@ __device__ __noinline__ SwapSlot swap_phase(int rep_s, int e, int R, int Dmax, b
       if (ok) {
         e = pe;
         rep_s = prep;
-        if (low && counts) acc[r] += 1u;
+        if (low) acc[r] += 1u;
       }
     }
   }
@@ -482,18 +531,40 @@ __device__ __forceinline__ void pt_ladder(const PTDev &P, const uint32_t *rec, u
     for (int v = 0; v < kPTMaxWaves; ++v) s += parts[64 * v + rho];
     return s;
   };
-  // Swap state.  Every wave keeps the whole slot map in registers (lane s: the
-  // replica at slot s, and its energy) and decides every pair itself, from the
-  // same LDS inputs, so no barrier follows the decisions.  Swap words (word 0
-  // of the SWAP call (pair r, 0, phase q)) live in LDS, two phases apart; the
-  // last wave, which has the fewest sweep items, draws them.
-  const int draw_wave = nth / 64 - 1;
-  uint32_t *slotw = swapw + 2 * 64 + 64 * wave;    // this wave's slot-of-replica scratch
-  int rep_s = lane;                                 // replica at slot `lane`
+  // Swap state.  One wave, the last (it has the fewest sweep items, none when the
+  // ladder has a wave to spare), keeps the slot map in registers (lane s: the
+  // replica at slot s, and its energy as of the last swap phase), draws the swap
+  // words (word 0 of the SWAP call (pair r, 0, phase q), in LDS two phases apart)
+  // and decides each swap phase at the start of the next sweep's colour class 0,
+  // while the other waves compute the part of their first item of that class
+  // that does not depend on temperatures.  It publishes every replica's new slot
+  // in slot_of; after a barrier each thread takes its replicas' table rows from
+  // there and finishes the item.
+  const int swap_wave = nth / 64 - 1;
+  const bool swapper = wave == swap_wave;
+  int rep_s = lane;                                 // replica at slot `lane` (swap wave)
   int e = E[lane];                                  // and its energy as of the last swap phase
-  if (wave == draw_wave && lane + 1 < R)
+  if (swapper && lane + 1 < R)
     swapw[lane] = philox4x32_10(static_cast<uint32_t>(lane), 0u, 0u, kStreamSwap << 24, P.seed_lo, P.seed_hi).v[0];
   uint32_t phase = 0;
+  bool pending = false;                             // a swap phase is due before class 0's thresholds
+  auto decide_swaps = [&]() {
+    // (an LDS null pointer is not zero: the staging flag travels on its own)
+    const SwapSlot ns = swap_phase(rep_s, e, R, P.Dmax, spk != nullptr, (const lds_u32 *)(spk ? spk : swapw),
+                                   (glb_u32 *)P.stab, (const lds_u32 *)(swapw + 64 * (phase & 1)),
+                                   (const lds_i32 *)parts, (lds_u32 *)acc);
+    rep_s = ns.rep;
+    e = ns.e;
+    if (lane < R) slot_of[rep_s & 63] = lane;
+    ++phase;
+  };
+  auto take_rows = [&]() {
+#pragma unroll
+    for (int w = 0; w < 8; ++w) {
+      row[w] = (w < nvalid) ? slot_of[8 * a + w] * width : 0;
+      thb[w] = mtabb + 4 * row[w];
+    }
+  };
   for (int m = 0; m < P.sweeps; ++m) {
     const bool swap_now = (m + 1) % P.sweeps_per_swap == 0;
     const uint32_t mm = static_cast<uint32_t>(m);
@@ -507,55 +578,57 @@ __device__ __forceinline__ void pt_ladder(const PTDev &P, const uint32_t *rec, u
       if constexpr (MODE == kPTBytes) {
         if (pend + pmax > 256) widen();
         pend += pmax;
-        if (has_first[c]) pt_item_bytes<KIND>(P, cur, lo + (tid >> lgRG), latb, st8, a, vmask, thb, f4, vpk, nit, mm);
+        if (c == 0 && pending) {
+          // the previous sweep's swap phase beside the first item's head
+          PTItemHead hd;
+          if (swapper) decide_swaps();
+          if (has_first[0]) hd = pt_item_bytes_head<KIND>(P, cur, lo + (tid >> lgRG), latb, st8, a, mm);
+          __syncthreads();
+          take_rows();
+          if (has_first[0]) {
+            uint32_t th[8];
+            pt_thresholds(thb, hd.V, th);
+            pt_item_bytes_decide(P, hd.site, lo + (tid >> lgRG), latb, st8, a, vmask, thb, f4, vpk, nit, mm, hd.own,
+                                 hd.V, hd.u, th);
+          }
+        } else if (has_first[c]) {
+          pt_item_bytes<KIND>(P, cur, lo + (tid >> lgRG), latb, st8, a, vmask, thb, f4, vpk, nit, mm);
+        }
         for (int it = tid + nth; group_live && it < cnt; it += nth) {
           const int d = lo + (it >> lgRG);
           pt_item_bytes<KIND>(P, load_pt_rec<KIND, MODE>(rec + d * S::RW), d, latb, st8, a, vmask, thb, f4, vpk,
                               nit, mm);
         }
       } else {
+        if (c == 0 && pending) {
+          if (swapper) decide_swaps();
+          __syncthreads();
+          take_rows();
+        }
         if (has_first[c]) pt_item<KIND, SWAR>(P, cur, lo + (tid >> lgRG), latb, mtab, a, vmask, row, dE, mm);
         for (int it = tid + nth; group_live && it < cnt; it += nth) {
           const int d = lo + (it >> lgRG);
           pt_item<KIND, SWAR>(P, load_pt_rec<KIND, MODE>(rec + d * S::RW), d, latb, mtab, a, vmask, row, dE, mm);
         }
       }
-      // In a sweep that ends in a swap phase: the last wave draws the next phase's
-      // words in class 1 (their buffer was last read in the previous swap phase,
-      // which ended before this sweep's class-0 barrier), and every wave stores
-      // its energy deltas ahead of the class-3 barrier (their array was last read
-      // in the previous swap phase too).
-      if (c == 1 && swap_now && wave == draw_wave && lane + 1 < R)
+      if (c == 0) pending = false;
+      // In a sweep that ends in a swap phase: the swap wave draws the next phase's
+      // words in class 1 (their buffer was last read by that wave in class 0), and
+      // every wave stores its energy deltas ahead of the class-3 barrier (their
+      // array was last read in class 0, before that class's barrier).
+      if (c == 1 && swap_now && swapper && lane + 1 < R)
         swapw[64 * ((phase + 1) & 1) + lane] =
             philox4x32_10(static_cast<uint32_t>(lane), 0u, phase + 1, kStreamSwap << 24, P.seed_lo, P.seed_hi).v[0];
       if (c == 3 && swap_now) flush(dE);
       __syncthreads();
     }
-    if (swap_now) {
-      // (an LDS null pointer is not zero: the staging flag travels on its own)
-      const SwapSlot ns = swap_phase(rep_s, e, R, P.Dmax, spk != nullptr, (const lds_u32 *)(spk ? spk : swapw),
-                                     (glb_u32 *)P.stab, (const lds_u32 *)(swapw + 64 * (phase & 1)),
-                                     (const lds_i32 *)parts, (lds_u32 *)acc);
-      rep_s = ns.rep;
-      e = ns.e;
-      // this thread's replicas' new slots, through the wave's own scratch
-      if (lane < R) slotw[rep_s & 63] = static_cast<uint32_t>(lane);
-      wave_sync();
-#pragma unroll
-      for (int w = 0; w < 8; ++w) {
-        row[w] = (w < nvalid) ? static_cast<int32_t>(slotw[8 * a + w]) * width : 0;
-        thb[w] = mtabb + 4 * row[w];
-      }
-      ++phase;
-    }
+    pending = swap_now;
   }
-  // Every wave reads all waves' partials inside a swap phase, and no barrier
-  // follows it: the last phase must be over in every wave before any wave
-  // overwrites its partials with the deltas of the sweeps after it.
+  if (pending && swapper) decide_swaps();    // the last sweep's swap phase (reads every wave's partials)
   __syncthreads();
   flush(dE);                                 // deltas of the sweeps after the last swap phase
   __syncthreads();
-  if (wave == 0) {                           // energies, slot map and swap counts for the results
+  if (swapper) {                             // energies, slot map and swap counts for the results
     e += gathered(rep_s & 63);
     if (lane < R) E[rep_s] = e;
     rep_at[lane] = rep_s;
