@@ -47,20 +47,32 @@ __device__ __forceinline__ int32_t row_sum_stride(int32_t v) {
   return v;
 }
 
-// Sums the eight per-thread energy deltas of replica byte a over the wave (DPP
-// row sums, then two lane permutes that fold the four rows) and stores the
-// wave's totals in its own array: word 8a + w holds replica 8a + w's.
+// Sums the eight per-thread energy deltas of replica byte a over the wave and
+// stores the wave's totals in its own array: word 8a + w holds replica 8a + w's.
+// DPP row sums first; then the four rows of four deltas at a time are folded by
+// row swaps: v_permlane16_swap(A, B) yields rows (A0, B0, A2, B2) and
+// (A1, B1, A3, B3), so one add merges two deltas' row pairs, and
+// v_permlane32_swap of two such merged values yields (X0, X1, Y0, Y1) and
+// (X2, X3, Y2, Y3), whose sum holds in row k the wave total of delta 4g + k.
 template <int G>
 __device__ __forceinline__ void flush_partials(int32_t *dE, int32_t *part, int a, int lane) {
 #pragma unroll
   for (int w = 0; w < 8; ++w) dE[w] = row_sum_stride<G>(dE[w]);
+  int32_t tot[2];
 #pragma unroll
-  for (int w = 0; w < 8; ++w) dE[w] += __builtin_amdgcn_ds_bpermute(4 * ((lane + 32) & 63), dE[w]);
-#pragma unroll
-  for (int w = 0; w < 8; ++w) dE[w] += __builtin_amdgcn_ds_bpermute(4 * ((lane + 16) & 63), dE[w]);
-  if (lane >= 16 - G && lane < 16)
-#pragma unroll
-    for (int w = 0; w < 8; ++w) part[8 * a + w] = dE[w];
+  for (int g = 0; g < 2; ++g) {
+    const auto p01 = __builtin_amdgcn_permlane16_swap(dE[4 * g], dE[4 * g + 1], false, false);
+    const auto p23 = __builtin_amdgcn_permlane16_swap(dE[4 * g + 2], dE[4 * g + 3], false, false);
+    const int32_t s01 = static_cast<int32_t>(p01[0]) + static_cast<int32_t>(p01[1]);
+    const int32_t s23 = static_cast<int32_t>(p23[0]) + static_cast<int32_t>(p23[1]);
+    const auto q = __builtin_amdgcn_permlane32_swap(s01, s23, false, false);
+    tot[g] = static_cast<int32_t>(q[0]) + static_cast<int32_t>(q[1]);
+  }
+  if ((lane & 15) >= 16 - G) {               // row k = lane / 16 holds deltas k and 4 + k
+    const int k = lane >> 4;
+    part[8 * a + k] = tot[0];
+    part[8 * a + 4 + k] = tot[1];
+  }
 #pragma unroll
   for (int w = 0; w < 8; ++w) dE[w] = 0;
 }
@@ -390,15 +402,43 @@ struct SwapSlot {
   int e;      // its energy
 };
 
+// The staged row of pair r of the two swap phases of a lane (o0[q]: its first
+// entry in the packed table, len[q]: its length; entries past the end are 0).
+struct SwapRows {
+  uint32_t o0[2], len[2];
+};
+
+__device__ __forceinline__ SwapRows swap_rows(const lds_u32 *spk, bool staged, int R) {
+  const int lane = static_cast<int>(threadIdx.x & 63u);
+  SwapRows sr{};
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int r = lane - ((lane - q) & 1);
+    const int rc = (r >= 0 && r + 1 < R) ? r : 0;
+    if (staged) {
+      sr.o0[q] = spk[rc];
+      sr.len[q] = spk[rc + 1] - sr.o0[q];
+    }
+  }
+  return sr;
+}
+
 // One swap phase (Eq. (B1)) as one wave sees it: lane s holds the replica at
 // slot s and its energy as of the last phase; it adds every wave's energy
 // partial of that replica, then the even pairs (r, r + 1), then the odd ones,
 // are decided by both of their lanes from the same inputs.  The wave counts the
 // accepted swaps of pair r in acc[r].  Kept out of line so that its registers
 // do not weigh on the sweep's.
-__device__ __noinline__ SwapSlot swap_phase(int rep_s, int e, int R, int Dmax, bool staged, const lds_u32 *spk,
-                                            glb_u32 *stab, const lds_u32 *sw, const lds_i32 *parts, lds_u32 *acc) {
+__device__ __noinline__ SwapSlot swap_phase(int rep_s, int e, int R, int Dmax, bool staged, SwapRows rows,
+                                            const lds_u32 *spk, glb_u32 *stab, const lds_u32 *sw,
+                                            const lds_i32 *parts, lds_u32 *acc) {
   const int lane = static_cast<int>(threadIdx.x & 63u);
+  uint32_t word[2];                               // both phases' swap words, read ahead of the energies
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int r = lane - ((lane - q) & 1);
+    word[q] = sw[(r >= 0 && r + 1 < R) ? r : 0];
+  }
   int32_t de = 0;
 #pragma unroll
   for (int v = 0; v < kPTMaxWaves; ++v) de += parts[64 * v + (rep_s & 63)];
@@ -408,20 +448,20 @@ __device__ __noinline__ SwapSlot swap_phase(int rep_s, int e, int R, int Dmax, b
     const bool low = ((lane - q) & 1) == 0;       // this lane is slot r of its pair (r, r + 1)
     const int r = lane - ((lane - q) & 1);
     const bool valid = r >= 0 && r + 1 < R;
-    const int rc = valid ? r : 0;
-    uint32_t o0 = 0, len = 0;                     // the pair's packed row in LDS: entries past its end are 0
-    if (staged) {
-      o0 = spk[rc];
-      len = spk[rc + 1] - o0;
-    }
+    const uint32_t o0 = rows.o0[q], len = rows.len[q];
     int pe, prep;                                 // the partner lane's energy and replica
     if (q == 0) {
       pe = __builtin_amdgcn_mov_dpp(e, 0xB1, 0xF, 0xF, true);        // quad_perm [1,0,3,2]
       prep = __builtin_amdgcn_mov_dpp(rep_s, 0xB1, 0xF, 0xF, true);
     } else {
-      const int src = 4 * (low ? min(lane + 1, 63) : max(lane - 1, 0));
-      pe = __builtin_amdgcn_ds_bpermute(src, e);
-      prep = __builtin_amdgcn_ds_bpermute(src, rep_s);
+      // odd pairs: a low lane takes lane + 1 (wave_shl:1), a high lane lane - 1
+      // (wave_shr:1), across row boundaries; lanes 0 and 63 have no pair
+      const int up_e = __builtin_amdgcn_update_dpp(0, e, 0x130, 0xF, 0xF, false);
+      const int up_r = __builtin_amdgcn_update_dpp(0, rep_s, 0x130, 0xF, 0xF, false);
+      const int dn_e = __builtin_amdgcn_update_dpp(0, e, 0x138, 0xF, 0xF, false);
+      const int dn_r = __builtin_amdgcn_update_dpp(0, rep_s, 0x138, 0xF, 0xF, false);
+      pe = low ? up_e : dn_e;
+      prep = low ? up_r : dn_r;
     }
     if (valid) {
       const int D = low ? pe - e : e - pe;        // E(slot r + 1) - E(slot r)
@@ -430,7 +470,7 @@ __device__ __noinline__ SwapSlot swap_phase(int rep_s, int e, int R, int Dmax, b
         const int Dc = min(D, Dmax);
         const uint32_t T = staged ? ((static_cast<uint32_t>(Dc) < len) ? spk[o0 + Dc] : 0u)
                                : stab[static_cast<size_t>(r) * (Dmax + 1) + Dc];
-        ok = min(sw[r], 0xFFFFFFFEu) < T;
+        ok = min(word[q], 0xFFFFFFFEu) < T;
       }
       if (ok) {
         e = pe;
@@ -548,11 +588,14 @@ __device__ __forceinline__ void pt_ladder(const PTDev &P, const uint32_t *rec, u
     swapw[lane] = philox4x32_10(static_cast<uint32_t>(lane), 0u, 0u, kStreamSwap << 24, P.seed_lo, P.seed_hi).v[0];
   uint32_t phase = 0;
   bool pending = false;                             // a swap phase is due before class 0's thresholds
+  // (an LDS null pointer is not zero: the staging flag travels on its own)
+  const lds_u32 *spk_lds = (const lds_u32 *)(spk ? spk : swapw);
+  SwapRows srows{};
+  if (swapper) srows = swap_rows(spk_lds, spk != nullptr, R);
   auto decide_swaps = [&]() {
-    // (an LDS null pointer is not zero: the staging flag travels on its own)
-    const SwapSlot ns = swap_phase(rep_s, e, R, P.Dmax, spk != nullptr, (const lds_u32 *)(spk ? spk : swapw),
-                                   (glb_u32 *)P.stab, (const lds_u32 *)(swapw + 64 * (phase & 1)),
-                                   (const lds_i32 *)parts, (lds_u32 *)acc);
+    const SwapSlot ns = swap_phase(rep_s, e, R, P.Dmax, spk != nullptr, srows, spk_lds, (glb_u32 *)P.stab,
+                                   (const lds_u32 *)(swapw + 64 * (phase & 1)), (const lds_i32 *)parts,
+                                   (lds_u32 *)acc);
     rep_s = ns.rep;
     e = ns.e;
     if (lane < R) slot_of[rep_s & 63] = lane;
