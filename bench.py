@@ -101,7 +101,7 @@ def parse():
                     help="only measure the VALU issue rate of the sweep loops' instruction kinds")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 2 GiB device to device, source evicted from the last-level cache first")
-    ap.add_argument("--legs", default="per_instance,serving,pt,wolff,scan,ptscan,cpu",
+    ap.add_argument("--legs", default="single,per_instance,serving,pt,wolff,scan,ptscan,cpu",
                     help="comma list of the extra legs to run after the timed steps")
     ap.add_argument("--pt-sweeps", type=int, default=100_000, help="sweeps of the parallel-tempering leg")
     return ap.parse_args()
@@ -364,6 +364,37 @@ def serving_leg(sqa):
             "at_fraction_of_capacity": 0.75, "budget_bytes": budget, "slots": slots, "chunk_sweeps": chunk}
 
 
+def single_leg(sqa):
+    """The two single-instance configurations: the N = 8 instance as clique-chain ME (56
+    sites) and as LHZ (28 sites), 16 replicas, L = 32, 10^3 sweeps, one handle each; a
+    call is sqa_anneal (init, sweeps, energies) on a stream, timed with HIP events there
+    and on the host clock around launch and synchronisation; median of 20 calls."""
+    import torch
+    from paper_1603_03755_amd.workloads import LHZ, ME, single_job
+    out = {}
+    stream = torch.cuda.Stream()
+    for kind, name in ((ME, "me_n8"), (LHZ, "lhz_n8")):
+        j = single_job(kind)
+        h = sqa.SQA(j.kind, j.J, j.penalty, j.beta, j.slices, j.sweeps, j.replicas, j.gamma0, j.gamma1, j.seed)
+        dev_ms, host_ms = [], []
+        for rep in range(21):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            t0 = time.perf_counter()
+            e0.record(stream)
+            h.anneal(stream)
+            e1.record(stream)
+            stream.synchronize()
+            if rep:                                  # the first call loads code and sets up
+                host_ms.append((time.perf_counter() - t0) * 1e3)
+                dev_ms.append(e0.elapsed_time(e1))
+        h.close()
+        med_dev, med_host = float(np.median(dev_ms)), float(np.median(host_ms))
+        out[name] = {"sites": j.sites, "attempts": j.attempts, "device_ms": med_dev, "host_ms": med_host,
+                     "attempts_per_s": j.attempts / (med_dev / 1e3),
+                     "attempts_per_s_incl_launch": j.attempts / (med_host / 1e3)}
+    return out
+
+
 def pt_ops_per_attempt(jobs, O) -> float:
     """Method arithmetic of a PT attempt (full-rate lane-op slots), averaged over the
     ladders' sites: the Philox share of the random half word, one multiply-add per
@@ -588,6 +619,9 @@ def main():
         b2.close()
         for h in hs2:
             h.close()
+    if "single" in legs:
+        log("leg single")
+        out["single_instance"] = single_leg(sqa)
     if "serving" in legs:
         log("leg serving")
         out["serving"] = serving_leg(sqa)

@@ -52,6 +52,20 @@ static std::vector<WorkItem> plan_items(const std::vector<const sqa_handle *> &h
   std::vector<WorkItem> out;
   out.reserve(v.size());
   for (auto &p : v) out.push_back(p.second);
+  // Race check: results must not depend on which workgroup takes which item or
+  // when; SQA_DEBUG_ITEM_ORDER=reverse or =shuffle hands the items out in
+  // another order (shuffle: a fixed permutation from a 64-bit LCG).
+  if (const char *o = std::getenv("SQA_DEBUG_ITEM_ORDER")) {
+    if (std::strcmp(o, "reverse") == 0) {
+      std::reverse(out.begin(), out.end());
+    } else if (std::strcmp(o, "shuffle") == 0) {
+      uint64_t x = 0x9E3779B97F4A7C15ull;
+      for (size_t i = out.size(); i > 1; --i) {
+        x = x * 6364136223846793005ull + 1442695040888963407ull;
+        std::swap(out[i - 1], out[(x >> 33) % i]);
+      }
+    }
+  }
   return out;
 }
 

@@ -398,3 +398,29 @@ def test_pt_many_ladder_shapes_in_one_batch(sqa):
         ospins, oE, orep, oacc = O.pt_run(emb, betas, 25, 1, seed)
         assert (rep == orep).all() and (spins == ospins[orep]).all() and (E == oE[orep]).all()
         h.close()
+
+
+@pytest.mark.parametrize("order", ["reverse", "shuffle"])
+def test_results_do_not_depend_on_work_item_order(sqa, monkeypatch, order):
+    """Race check: the batch's work items handed out in another order (host-side debug
+    switch) give identical spins and energies for every handle, both moves, one wave
+    per replica and team mode."""
+    specs = _mixed_jobs()
+    mk = lambda s, move: sqa.SQA(s["kind"], s["J"], s["pen"], s["beta"], s["L"], s["M"], s["R"], s["g0"], s["g1"],
+                                 s["seed"], move=move)
+    for move in (sqa.SQA_MOVE_METROPOLIS, sqa.SQA_MOVE_WOLFF):
+        for waves in (0, 2):
+            print(f"item order {order} move={move} waves={waves}", flush=True)
+            monkeypatch.delenv("SQA_DEBUG_ITEM_ORDER", raising=False)
+            ref = [mk(s, move) for s in specs]
+            b = sqa.Batch(ref, waves_per_group=waves)
+            b.run()
+            want = [(h.spins(), h.energies()) for h in ref]
+            b.close()
+            monkeypatch.setenv("SQA_DEBUG_ITEM_ORDER", order)
+            hs = [mk(s, move) for s in specs]
+            b = sqa.Batch(hs, waves_per_group=waves)
+            b.run()
+            for (ws, we), h in zip(want, hs):
+                assert (h.spins() == ws).all() and (h.energies() == we).all()
+            b.close()
