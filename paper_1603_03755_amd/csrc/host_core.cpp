@@ -230,7 +230,8 @@ sqa_status build_layout(const Embedded &emb, int32_t F, RecordLayout layout, Dev
       for (int a = 0; a < T; ++a) put(aw[a], (neg >> a) & 1u, a);
       put(ah, emb.h[k] < 0, T);
       const uint32_t c4 = 4u * static_cast<uint32_t>(cc);
-      const uint32_t fsh = metro ? 0u : (static_cast<uint32_t>(fs) << 16);   // Wolff: F_site
+      // Wolff: F_site (PT does not read it: ME's last partner offset is then the whole word)
+      const uint32_t fsh = (metro || ptb) ? 0u : (static_cast<uint32_t>(fs) << 16);
       r[0] = static_cast<uint32_t>(k) | ((c4 | (c4 << 8)) << 16);
       if (me) {
         r[1] = W[0] | (W[1] << 16);

@@ -38,43 +38,66 @@ namespace sqa {
 // Sum of v over the lanes l, l - g, l - 2g, ... of a 16-lane row (G = g a power
 // of two below 16): DPP row shifts, so lane l with l % 16 >= 16 - G ends with
 // the row's total for its residue l % G.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_row_shr(uint32_t x) {
+  return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), CTRL, 0xF, 0xF, true));
+}
+
 template <int G>
-__device__ __forceinline__ int32_t row_sum_stride(int32_t v) {
-  if constexpr (G < 2) v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, true);   // row_shr:1
-  if constexpr (G < 4) v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, true);   // row_shr:2
-  if constexpr (G < 8) v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, true);   // row_shr:4
-  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, true);                        // row_shr:8
+__device__ __forceinline__ uint32_t row_sum_stride(uint32_t v) {
+  if constexpr (G < 2) v += dpp_row_shr<0x111>(v);   // row_shr:1
+  if constexpr (G < 4) v += dpp_row_shr<0x112>(v);   // row_shr:2
+  if constexpr (G < 8) v += dpp_row_shr<0x114>(v);   // row_shr:4
+  v += dpp_row_shr<0x118>(v);                        // row_shr:8
   return v;
 }
 
-// Sums the eight per-thread energy deltas of replica byte a over the wave and
-// stores the wave's totals in its own array: word 8a + w holds replica 8a + w's.
-// DPP row sums first; then the four rows of four deltas at a time are folded by
-// row swaps: v_permlane16_swap(A, B) yields rows (A0, B0, A2, B2) and
-// (A1, B1, A3, B3), so one add merges two deltas' row pairs, and
+// Row folds of four values: v_permlane16_swap(A, B) yields rows (A0, B0, A2, B2)
+// and (A1, B1, A3, B3), so one add merges two values' row pairs, and
 // v_permlane32_swap of two such merged values yields (X0, X1, Y0, Y1) and
-// (X2, X3, Y2, Y3), whose sum holds in row k the wave total of delta 4g + k.
+// (X2, X3, Y2, Y3), whose sum holds in row k the four rows' total of value k.
+__device__ __forceinline__ uint32_t fold_rows4(uint32_t v0, uint32_t v1, uint32_t v2, uint32_t v3) {
+  const auto p01 = __builtin_amdgcn_permlane16_swap(v0, v1, false, false);
+  const auto p23 = __builtin_amdgcn_permlane16_swap(v2, v3, false, false);
+  const uint32_t s01 = static_cast<uint32_t>(p01[0]) + static_cast<uint32_t>(p01[1]);
+  const uint32_t s23 = static_cast<uint32_t>(p23[0]) + static_cast<uint32_t>(p23[1]);
+  const auto q = __builtin_amdgcn_permlane32_swap(s01, s23, false, false);
+  return static_cast<uint32_t>(q[0]) + static_cast<uint32_t>(q[1]);
+}
+
+// Sums the eight per-thread values of replica byte a over the wave (modulo
+// 2^32) and stores the wave's totals in its own array: word 8a + w holds
+// replica 8a + w's.  DPP row sums, then two four-value row folds.
 template <int G>
-__device__ __forceinline__ void flush_partials(int32_t *dE, int32_t *part, int a, int lane) {
+__device__ __forceinline__ void flush_partials(uint32_t *dE, uint32_t *part, int a, int lane) {
 #pragma unroll
   for (int w = 0; w < 8; ++w) dE[w] = row_sum_stride<G>(dE[w]);
-  int32_t tot[2];
-#pragma unroll
-  for (int g = 0; g < 2; ++g) {
-    const auto p01 = __builtin_amdgcn_permlane16_swap(dE[4 * g], dE[4 * g + 1], false, false);
-    const auto p23 = __builtin_amdgcn_permlane16_swap(dE[4 * g + 2], dE[4 * g + 3], false, false);
-    const int32_t s01 = static_cast<int32_t>(p01[0]) + static_cast<int32_t>(p01[1]);
-    const int32_t s23 = static_cast<int32_t>(p23[0]) + static_cast<int32_t>(p23[1]);
-    const auto q = __builtin_amdgcn_permlane32_swap(s01, s23, false, false);
-    tot[g] = static_cast<int32_t>(q[0]) + static_cast<int32_t>(q[1]);
-  }
-  if ((lane & 15) >= 16 - G) {               // row k = lane / 16 holds deltas k and 4 + k
+  const uint32_t t0 = fold_rows4(dE[0], dE[1], dE[2], dE[3]), t1 = fold_rows4(dE[4], dE[5], dE[6], dE[7]);
+  if ((lane & 15) >= 16 - G) {               // row k = lane / 16 holds values k and 4 + k
     const int k = lane >> 4;
-    part[8 * a + k] = tot[0];
-    part[8 * a + 4 + k] = tot[1];
+    part[8 * a + k] = t0;
+    part[8 * a + 4 + k] = t1;
   }
 #pragma unroll
   for (int w = 0; w < 8; ++w) dE[w] = 0;
+}
+
+// Byte mode, while each 16-bit half of the packed sums vpk stays below 2^16
+// over the wave: the four packed words are summed instead of eight values
+// (halves of vpk[k]: replicas (k & 1) + 4 (k >> 1) and that + 2).
+template <int G>
+__device__ __forceinline__ void flush_packed(uint32_t *vpk, uint32_t *part, int a, int lane) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) vpk[k] = row_sum_stride<G>(vpk[k]);
+  const uint32_t t = fold_rows4(vpk[0], vpk[1], vpk[2], vpk[3]);
+  if ((lane & 15) >= 16 - G) {               // row k holds packed word k
+    const int k = lane >> 4;
+    const int w = (k & 1) + 4 * (k >> 1);
+    part[8 * a + w] = t & 0xFFFFu;
+    part[8 * a + w + 2] = t >> 16;
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) vpk[k] = 0;
 }
 
 // Explicit LDS and global address spaces: pointers that are updated inside the
@@ -92,6 +115,12 @@ constexpr int kPTBytes = 0, kPTSwar = 1, kPTWide = 2;
 
 // Raw record words of one site (ME: the first 4 of its 6 words, 5 in byte mode;
 // LHZ: 10; ME on Chimera: 6, 8 in byte mode).
+// The ladder's Philox key, held in scalar registers for the whole run (a
+// scalar reload per item would make each item's LDS reads wait with it).
+struct PTKey {
+  uint32_t lo, hi;
+};
+
 template <int KIND> struct PTRec;
 template <> struct PTRec<kKindME> { uint4 a; uint32_t b; };
 template <> struct PTRec<kKindLHZ> { uint4 a, b; uint2 c; };
@@ -130,7 +159,7 @@ __device__ __forceinline__ SignedRec<KIND> signed_from_pt(const PTRec<KIND> &x) 
     const uint32_t ws[4] = {x.a.y, x.a.y, x.a.z, x.a.z};
 #pragma unroll
     for (int t = 0; t < 4; ++t) { s.wsg[t] = ws[t]; s.wsh[t] = t & 1; }
-    s.poff[0] = x.a.w & 0xFFFFu; s.poff[1] = x.a.w >> 16; s.poff[2] = x.b & 0xFFFFu;
+    s.poff[0] = x.a.w & 0xFFFFu; s.poff[1] = x.a.w >> 16; s.poff[2] = x.b;   // the host leaves x.b's top half 0
   } else if constexpr (KIND == kKindMEC) {
     const uint32_t ws[7] = {x.a.y, x.a.y, x.a.z, x.a.z, x.a.w, x.a.w, x.b.x};
 #pragma unroll
@@ -166,10 +195,10 @@ __device__ __forceinline__ void pt_thresholds(const lds_u8 *const *thb, uint2 V,
 // halves th: D = hi - top half is negative iff accepted on hi alone, zero on a
 // tie (the sign bits are shifted into `flip` from replica 7 down); a tie decides
 // all eight on 32 bits with the PT_LO call.  Then the byte store and the flip sums.
-__device__ __forceinline__ void pt_item_bytes_decide(const PTDev &P, uint32_t site, int d, uint8_t *latb,
+__device__ __forceinline__ void pt_item_bytes_decide(PTKey K, uint32_t site, int d, uint8_t *latb,
                                                      const uint2 *st8, int a, uint32_t vmask,
                                                      const lds_u8 *const *thb, uint32_t f4, uint32_t *vpk,
-                                                     uint32_t &nit, uint32_t m, uint32_t own, uint2 V,
+                                                     uint32_t m, uint32_t own, uint2 V,
                                                      const Words4 &u, const uint32_t *th) {
   uint32_t flip = 0, dmin = 0xFFFFFFFFu;
 #pragma unroll
@@ -180,7 +209,7 @@ __device__ __forceinline__ void pt_item_bytes_decide(const PTDev &P, uint32_t si
     dmin = min(dmin, D);
   }
   if (dmin == 0) {     // some half equals its threshold's top half: decide all eight on 32 bits
-    const Words4 v = philox4x32_10(site, static_cast<uint32_t>(a), m, kStreamPTLo << 24, P.seed_lo, P.seed_hi);
+    const Words4 v = philox4x32_10(site, static_cast<uint32_t>(a), m, kStreamPTLo << 24, K.lo, K.hi);
     flip = 0;
 #pragma unroll
     for (int w = 0; w < 8; ++w) {
@@ -199,7 +228,6 @@ __device__ __forceinline__ void pt_item_bytes_decide(const PTDev &P, uint32_t si
   vpk[1] += (t_lo >> 8) & 0x00FF00FFu;
   vpk[2] += t_hi & 0x00FF00FFu;
   vpk[3] += (t_hi >> 8) & 0x00FF00FFu;
-  ++nit;
 }
 
 // One item: site d (record x), replica byte a, sweep m.
@@ -210,32 +238,66 @@ __device__ __forceinline__ void pt_item_bytes_decide(const PTDev &P, uint32_t si
 // 4 S_w - 2 F_site = (V_w - 4F) / 2.  One byte permute per word takes V_w for
 // the flipped replicas and 4F for the others (selectors from a table); the
 // thread adds those bytes into 16-bit halves (vpk: replicas 0 and 2, 1 and 3,
-// 4 and 6, 5 and 7) and counts its items in nit, so the sum of the byte of
-// replica w minus 4F nit is the sum of V_w - 4F over its flips.
+// 4 and 6, 5 and 7).  Every site is an item of every replica byte once per
+// sweep, so over k sweeps the sum for replica w less 4F n k (n sites) is the
+// sum of V_w - 4F over its flips: twice its energy change.
+// The temperature-free front of a byte-mode item: own and partner bytes, the
+// spread-table rows of the own byte and of each term's product byte, and V.
+// The first six Philox rounds run in two parts while those two rounds of LDS
+// reads are in flight; the last four are left to the caller.
 template <int KIND>
-__device__ __forceinline__ void pt_item_bytes(const PTDev &P, const PTRec<KIND> &x, int d, uint8_t *latb,
-                                              const uint2 *st8, int a, uint32_t vmask, const lds_u8 *const *thb,
-                                              uint32_t f4, uint32_t *vpk, uint32_t &nit, uint32_t m) {
+__device__ __forceinline__ uint2 pt_item_front(PTKey K, const SignedRec<KIND> &sr, int d, const uint8_t *latb,
+                                               const uint2 *st8, int a, uint32_t m, uint32_t &own,
+                                               PhiloxState &ps) {
   using S = Site<KIND>;
-  const SignedRec<KIND> sr = signed_from_pt<KIND>(x);
-  // own and partner bytes (LDS reads), the first Philox rounds while they are in flight
-  const uint32_t own = latb[8 * d + a];
+  own = latb[8 * d + a];
   uint32_t pbyte[S::T * S::P];
 #pragma unroll
   for (int i = 0; i < S::T * S::P; ++i) pbyte[i] = latb[sr.poff[i] + a];
-  PhiloxState ps = philox_start(sr.site, static_cast<uint32_t>(a), m, kStreamPT << 24, P.seed_lo, P.seed_hi);
+  ps = philox_start(sr.site, static_cast<uint32_t>(a), m, kStreamPT << 24, K.lo, K.hi);
   __builtin_amdgcn_sched_barrier(0);
-  philox_rounds<5>(ps);
+  philox_rounds<3>(ps);
+  philox_pin(ps);
+  asm volatile("" : "+v"(own));                   // nothing derived from own ahead of the rounds
+  __builtin_amdgcn_sched_barrier(0);
+  uint2 sx[S::T + 1];                             // spread rows: terms 0..T-1, then h's (the own byte)
+#pragma unroll
+  for (int t = 0; t < S::T; ++t) {
+    uint32_t prod = own;
+#pragma unroll
+    for (int q = 0; q < S::P; ++q) prod ^= pbyte[S::P * t + q];
+    sx[t] = st8[prod];
+  }
+  sx[S::T] = st8[own];
+  __builtin_amdgcn_sched_barrier(0);
+  philox_rounds<3>(ps);
   philox_pin(ps);
   __builtin_amdgcn_sched_barrier(0);
-  const uint2 V = signed_sums<KIND>(sr, st8, own, pbyte);
+  u16x2 a_lo = as_u16x2(sx[S::T].x) * sr.weight(S::T) + sr.c4();
+  u16x2 a_hi = as_u16x2(sx[S::T].y) * sr.weight(S::T) + sr.c4();
+#pragma unroll
+  for (int t = 0; t < S::T; ++t) {
+    a_lo = as_u16x2(sx[t].x) * sr.weight(t) + a_lo;
+    a_hi = as_u16x2(sx[t].y) * sr.weight(t) + a_hi;
+  }
+  return make_uint2(as_u32(a_lo), as_u32(a_hi));
+}
+
+template <int KIND>
+__device__ __forceinline__ void pt_item_bytes(PTKey K, const PTRec<KIND> &x, int d, uint8_t *latb,
+                                              const uint2 *st8, int a, uint32_t vmask, const lds_u8 *const *thb,
+                                              uint32_t f4, uint32_t *vpk, uint32_t m) {
+  const SignedRec<KIND> sr = signed_from_pt<KIND>(x);
+  uint32_t own;
+  PhiloxState ps;
+  const uint2 V = pt_item_front<KIND>(K, sr, d, latb, st8, a, m, own, ps);
   uint32_t th[8];
   pt_thresholds(thb, V, th);
   __builtin_amdgcn_sched_barrier(0);
-  philox_rounds<5>(ps);
+  philox_rounds<4>(ps);
   __builtin_amdgcn_sched_barrier(0);
   const Words4 u = philox_words(ps);
-  pt_item_bytes_decide(P, sr.site, d, latb, st8, a, vmask, thb, f4, vpk, nit, m, own, V, u, th);
+  pt_item_bytes_decide(K, sr.site, d, latb, st8, a, vmask, thb, f4, vpk, m, own, V, u, th);
 }
 
 // The part of a byte-mode item that does not depend on the replicas'
@@ -248,23 +310,14 @@ struct PTItemHead {
 };
 
 template <int KIND>
-__device__ __forceinline__ PTItemHead pt_item_bytes_head(const PTDev &P, const PTRec<KIND> &x, int d,
+__device__ __forceinline__ PTItemHead pt_item_bytes_head(PTKey K, const PTRec<KIND> &x, int d,
                                                          const uint8_t *latb, const uint2 *st8, int a, uint32_t m) {
-  using S = Site<KIND>;
   const SignedRec<KIND> sr = signed_from_pt<KIND>(x);
   PTItemHead hd;
-  hd.own = latb[8 * d + a];
   hd.site = sr.site;
-  uint32_t pbyte[S::T * S::P];
-#pragma unroll
-  for (int i = 0; i < S::T * S::P; ++i) pbyte[i] = latb[sr.poff[i] + a];
-  PhiloxState ps = philox_start(sr.site, static_cast<uint32_t>(a), m, kStreamPT << 24, P.seed_lo, P.seed_hi);
-  __builtin_amdgcn_sched_barrier(0);
-  philox_rounds<5>(ps);
-  philox_pin(ps);
-  __builtin_amdgcn_sched_barrier(0);
-  hd.V = signed_sums<KIND>(sr, st8, hd.own, pbyte);
-  philox_rounds<5>(ps);
+  PhiloxState ps;
+  hd.V = pt_item_front<KIND>(K, sr, d, latb, st8, a, m, hd.own, ps);
+  philox_rounds<4>(ps);
   hd.u = philox_words(ps);
   return hd;
 }
@@ -273,9 +326,9 @@ __device__ __forceinline__ PTItemHead pt_item_bytes_head(const PTDev &P, const P
 // byte a, sweep m; row: the table row offsets of the byte's eight replicas; dE:
 // their energy deltas.
 template <int KIND, bool SWAR>
-__device__ __forceinline__ void pt_item(const PTDev &P, const PTRec<KIND> &x, int d, uint8_t *latb,
+__device__ __forceinline__ void pt_item(const PTDev &P, PTKey K, const PTRec<KIND> &x, int d, uint8_t *latb,
                                         const uint32_t *mtab, int a, uint32_t vmask, const int32_t *row,
-                                        int32_t *dE, uint32_t m) {
+                                        uint32_t *dE, uint32_t m) {
   using S = Site<KIND>;
   const int F = P.F;
   const uint16_t *mtab16 = reinterpret_cast<const uint16_t *>(mtab);
@@ -313,7 +366,7 @@ __device__ __forceinline__ void pt_item(const PTDev &P, const PTRec<KIND> &x, in
   uint32_t pbyte[S::T * S::P];
 #pragma unroll
   for (int i = 0; i < S::T * S::P; ++i) pbyte[i] = latb[part[i] + a];
-  PhiloxState ps = philox_start(site, static_cast<uint32_t>(a), m, kStreamPT << 24, P.seed_lo, P.seed_hi);
+  PhiloxState ps = philox_start(site, static_cast<uint32_t>(a), m, kStreamPT << 24, K.lo, K.hi);
   __builtin_amdgcn_sched_barrier(0);
   philox_rounds<5>(ps);
   philox_pin(ps);
@@ -381,7 +434,7 @@ __device__ __forceinline__ void pt_item(const PTDev &P, const PTRec<KIND> &x, in
     tie |= (hi == th[w]);
   }
   if (tie) {     // some half equals its threshold's top half: decide all eight on 32 bits
-    const Words4 v = philox4x32_10(site, static_cast<uint32_t>(a), m, kStreamPTLo << 24, P.seed_lo, P.seed_hi);
+    const Words4 v = philox4x32_10(site, static_cast<uint32_t>(a), m, kStreamPTLo << 24, K.lo, K.hi);
     flip = 0;
 #pragma unroll
     for (int w = 0; w < 8; ++w) {
@@ -394,12 +447,13 @@ __device__ __forceinline__ void pt_item(const PTDev &P, const PTRec<KIND> &x, in
   latb[8 * d + a] = static_cast<uint8_t>(own ^ flip);
 #pragma unroll
   for (int w = 0; w < 8; ++w)
-    if ((flip >> w) & 1u) dE[w] += 4 * static_cast<int32_t>(sw[w]) - 2 * static_cast<int32_t>(fs);
+    if ((flip >> w) & 1u) dE[w] += static_cast<uint32_t>(4 * static_cast<int32_t>(sw[w]) - 2 * static_cast<int32_t>(fs));
 }
 
 struct SwapSlot {
-  int rep;    // replica at this lane's slot
-  int e;      // its energy
+  int rep;        // replica at this lane's slot
+  int e;          // its energy
+  uint32_t acc;   // accepted swaps of pair (lane, lane + 1)
 };
 
 // The staged row of pair r of the two swap phases of a lane (o0[q]: its first
@@ -424,14 +478,15 @@ __device__ __forceinline__ SwapRows swap_rows(const lds_u32 *spk, bool staged, i
 }
 
 // One swap phase (Eq. (B1)) as one wave sees it: lane s holds the replica at
-// slot s and its energy as of the last phase; it adds every wave's energy
-// partial of that replica, then the even pairs (r, r + 1), then the odd ones,
-// are decided by both of their lanes from the same inputs.  The wave counts the
-// accepted swaps of pair r in acc[r].  Kept out of line so that its registers
-// do not weigh on the sweep's.
-__device__ __noinline__ SwapSlot swap_phase(int rep_s, int e, int R, int Dmax, bool staged, SwapRows rows,
-                                            const lds_u32 *spk, glb_u32 *stab, const lds_u32 *sw,
-                                            const lds_i32 *parts, lds_u32 *acc) {
+// slot s and its energy as of the last phase; it adds every wave's partial of
+// that replica (their sum less `off`, shifted right by `sh`, is the energy
+// change), then the even pairs (r, r + 1), then the odd ones, are decided by
+// both of their lanes from the same inputs.  Lane r counts the accepted swaps
+// of pair r in `acc`.  Kept out of line so that its registers do not weigh on
+// the sweep's.
+__device__ __noinline__ SwapSlot swap_phase(int rep_s, int e, uint32_t acc, uint32_t off, int sh, int R, int Dmax,
+                                            bool staged, SwapRows rows, const lds_u32 *spk, glb_u32 *stab,
+                                            const lds_u32 *sw, const lds_u32 *parts) {
   const int lane = static_cast<int>(threadIdx.x & 63u);
   uint32_t word[2];                               // both phases' swap words, read ahead of the energies
 #pragma unroll
@@ -439,10 +494,10 @@ __device__ __noinline__ SwapSlot swap_phase(int rep_s, int e, int R, int Dmax, b
     const int r = lane - ((lane - q) & 1);
     word[q] = sw[(r >= 0 && r + 1 < R) ? r : 0];
   }
-  int32_t de = 0;
+  uint32_t de = 0;
 #pragma unroll
   for (int v = 0; v < kPTMaxWaves; ++v) de += parts[64 * v + (rep_s & 63)];
-  e += de;
+  e += static_cast<int32_t>(de - off) >> sh;
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
     const bool low = ((lane - q) & 1) == 0;       // this lane is slot r of its pair (r, r + 1)
@@ -475,11 +530,11 @@ __device__ __noinline__ SwapSlot swap_phase(int rep_s, int e, int R, int Dmax, b
       if (ok) {
         e = pe;
         rep_s = prep;
-        if (low) acc[r] += 1u;
+        if (low) ++acc;
       }
     }
   }
-  return SwapSlot{rep_s, e};
+  return SwapSlot{rep_s, e, acc};
 }
 
 template <int KIND, int MODE>
@@ -492,6 +547,8 @@ __device__ __forceinline__ void pt_ladder(const PTDev &P, const uint32_t *rec, u
   const int width = 2 * F + 1;
   const int tid = threadIdx.x, nth = blockDim.x;
   const int lane = tid & 63, wave = tid >> 6;
+  PTKey K{P.seed_lo, P.seed_hi};
+  asm volatile("" : "+s"(K.lo), "+s"(K.hi));      // not re-read from P inside the sweep loop
   int RG = 1, lgRG = 0;
   while (RG * 8 < R) {
     RG <<= 1;
@@ -502,9 +559,10 @@ __device__ __forceinline__ void pt_ladder(const PTDev &P, const uint32_t *rec, u
   const int nvalid = group_live ? min(8, R - 8 * a) : 0;
   const uint32_t vmask = (1u << nvalid) - 1u;
   uint8_t *latb = reinterpret_cast<uint8_t *>(lat);
-  int32_t dE[8];
-  uint32_t vsum[8], vpk[4], nit = 0;                // byte mode: byte sums (see pt_item_bytes)
+  uint32_t dE[8];                                   // energy deltas (modulo 2^32; byte mode: see pt_item_bytes)
+  uint32_t vsum[8], vpk[4];                         // byte mode: byte sums (see pt_item_bytes)
   int pend = 0;                                     // byte mode: most items per thread since vpk was emptied
+  bool widened = false;                             // byte mode: vsum holds sums since the last flush
   int pmax = 0;                                     // most items of a thread in one colour class (<= 256)
   const uint32_t f4 = static_cast<uint32_t>(4 * F) * 0x01010101u;
   int32_t row[8];                                  // table row offsets of the byte's replicas
@@ -534,8 +592,8 @@ __device__ __forceinline__ void pt_ladder(const PTDev &P, const uint32_t *rec, u
   PTRec<KIND> nxt;
   if (has_first[0]) nxt = load_pt_rec<KIND, MODE>(rec + (cls[0] + (tid >> lgRG)) * S::RW);
   // energy deltas into E (RG is a power of two up to 8, so it divides the 16-lane rows)
-  int32_t *parts = reinterpret_cast<int32_t *>(swapw) + 2 * 64 + kPTMaxWaves * 64;   // 64 words per wave
-  int32_t *part = parts + 64 * wave;
+  uint32_t *parts = swapw + 2 * 64 + kPTMaxWaves * 64;   // 64 words per wave
+  uint32_t *part = parts + 64 * wave;
   // byte mode: the 16-bit halves into the per-replica sums (a half gains at most
   // 8F <= 248 per item, so 256 items fit)
   auto widen = [&]() {
@@ -547,29 +605,44 @@ __device__ __forceinline__ void pt_ladder(const PTDev &P, const uint32_t *rec, u
       vpk[k] = 0;
     }
     pend = 0;
+    widened = true;
   };
-  auto flush = [&](int32_t *d) {
+  // Every wave's sums into its partials.  Byte mode: the packed halves when a
+  // half of the wave total stays below 2^16 (8F per item, 64 / RG lanes per
+  // replica byte), else the widened sums; the 4F n k offset is removed where
+  // the partials are gathered.
+  auto flush = [&](uint32_t *d) {
     if constexpr (MODE == kPTBytes) {
+      if (!widened && pend * 8 * F * (64 >> lgRG) <= 0xFFFF) {
+        if (RG == 1) flush_packed<1>(vpk, part, a, lane);
+        else if (RG == 2) flush_packed<2>(vpk, part, a, lane);
+        else if (RG == 4) flush_packed<4>(vpk, part, a, lane);
+        else flush_packed<8>(vpk, part, a, lane);
+        pend = 0;
+        return;
+      }
       widen();
-      const uint32_t bias = 4u * static_cast<uint32_t>(F) * nit;
 #pragma unroll
-      for (int w = 0; w < 8; ++w) {     // vsum - 4F nit is a multiple of 4
-        d[w] = static_cast<int32_t>(vsum[w] - bias) >> 1;
+      for (int w = 0; w < 8; ++w) {
+        d[w] = vsum[w];
         vsum[w] = 0;
       }
-      nit = 0;
+      widened = false;
     }
     if (RG == 1) flush_partials<1>(d, part, a, lane);
     else if (RG == 2) flush_partials<2>(d, part, a, lane);
     else if (RG == 4) flush_partials<4>(d, part, a, lane);
     else flush_partials<8>(d, part, a, lane);
   };
-  // energy change of replica rho since the last swap phase: every wave's partial
-  auto gathered = [&](int rho) {
-    int32_t s = 0;
+  // Gathering every wave's partials of a replica over k sweeps: the sum less
+  // `off` k, shifted right by `sh` (byte mode: 4F n and 1, else 0 and 0).
+  const uint32_t off = (MODE == kPTBytes) ? 4u * static_cast<uint32_t>(F) * static_cast<uint32_t>(P.n) : 0u;
+  const int sh = (MODE == kPTBytes) ? 1 : 0;
+  auto gathered = [&](int rho, uint32_t k) {
+    uint32_t s = 0;
 #pragma unroll
     for (int v = 0; v < kPTMaxWaves; ++v) s += parts[64 * v + rho];
-    return s;
+    return static_cast<int32_t>(s - off * k) >> sh;
   };
   // Swap state.  One wave, the last (it has the fewest sweep items, none when the
   // ladder has a wave to spare), keeps the slot map in registers (lane s: the
@@ -585,27 +658,46 @@ __device__ __forceinline__ void pt_ladder(const PTDev &P, const uint32_t *rec, u
   int rep_s = lane;                                 // replica at slot `lane` (swap wave)
   int e = E[lane];                                  // and its energy as of the last swap phase
   if (swapper && lane + 1 < R)
-    swapw[lane] = philox4x32_10(static_cast<uint32_t>(lane), 0u, 0u, kStreamSwap << 24, P.seed_lo, P.seed_hi).v[0];
+    swapw[lane] = philox4x32_10(static_cast<uint32_t>(lane), 0u, 0u, kStreamSwap << 24, K.lo, K.hi).v[0];
   uint32_t phase = 0;
   bool pending = false;                             // a swap phase is due before class 0's thresholds
   // (an LDS null pointer is not zero: the staging flag travels on its own)
   const lds_u32 *spk_lds = (const lds_u32 *)(spk ? spk : swapw);
   SwapRows srows{};
   if (swapper) srows = swap_rows(spk_lds, spk != nullptr, R);
+  uint32_t acc_r = 0;                               // swaps accepted by pair (lane, lane + 1)
+  const uint32_t off_swap = off * static_cast<uint32_t>(P.sweeps_per_swap);
+  // During the sweeps slot_of[rho] holds what a thread needs of replica rho's
+  // slot s: byte mode the LDS address of its threshold base (thb), else the
+  // row offset s (2F + 1).  The slot map itself is written back at the end.
+  const uint32_t pub0 = static_cast<uint32_t>(reinterpret_cast<uintptr_t>(mtabb));
   auto decide_swaps = [&]() {
-    const SwapSlot ns = swap_phase(rep_s, e, R, P.Dmax, spk != nullptr, srows, spk_lds, (glb_u32 *)P.stab,
-                                   (const lds_u32 *)(swapw + 64 * (phase & 1)), (const lds_i32 *)parts,
-                                   (lds_u32 *)acc);
+    __builtin_amdgcn_s_setprio(3);               // ahead of the item waves on its SIMD
+    const SwapSlot ns = swap_phase(rep_s, e, acc_r, off_swap, sh, R, P.Dmax, spk != nullptr, srows, spk_lds,
+                                   (glb_u32 *)P.stab, (const lds_u32 *)(swapw + 64 * (phase & 1)),
+                                   (const lds_u32 *)parts);
     rep_s = ns.rep;
     e = ns.e;
-    if (lane < R) slot_of[rep_s & 63] = lane;
+    acc_r = ns.acc;
+    if (lane < R)
+      slot_of[rep_s & 63] = static_cast<int32_t>(MODE == kPTBytes ? pub0 + 4u * static_cast<uint32_t>(lane * width)
+                                                                  : static_cast<uint32_t>(lane * width));
+    __builtin_amdgcn_s_setprio(0);
     ++phase;
   };
+  // the byte's eight entries in two 16-byte reads (slot_of has 64 entries and
+  // 8a + 7 < 64; entries of absent replicas are read and not used)
   auto take_rows = [&]() {
+    const int4 s0 = *reinterpret_cast<const int4 *>(slot_of + 8 * a);
+    const int4 s1 = *reinterpret_cast<const int4 *>(slot_of + 8 * a + 4);
+    const int32_t sl[8] = {s0.x, s0.y, s0.z, s0.w, s1.x, s1.y, s1.z, s1.w};
 #pragma unroll
     for (int w = 0; w < 8; ++w) {
-      row[w] = (w < nvalid) ? slot_of[8 * a + w] * width : 0;
-      thb[w] = mtabb + 4 * row[w];
+      if constexpr (MODE == kPTBytes)
+        thb[w] = (w < nvalid) ? reinterpret_cast<const lds_u8 *>(static_cast<uintptr_t>(static_cast<uint32_t>(sl[w])))
+                              : mtabb;
+      else
+        row[w] = (w < nvalid) ? sl[w] : 0;
     }
   };
   for (int m = 0; m < P.sweeps; ++m) {
@@ -625,22 +717,22 @@ __device__ __forceinline__ void pt_ladder(const PTDev &P, const uint32_t *rec, u
           // the previous sweep's swap phase beside the first item's head
           PTItemHead hd;
           if (swapper) decide_swaps();
-          if (has_first[0]) hd = pt_item_bytes_head<KIND>(P, cur, lo + (tid >> lgRG), latb, st8, a, mm);
+          if (has_first[0]) hd = pt_item_bytes_head<KIND>(K, cur, lo + (tid >> lgRG), latb, st8, a, mm);
           __syncthreads();
           take_rows();
           if (has_first[0]) {
             uint32_t th[8];
             pt_thresholds(thb, hd.V, th);
-            pt_item_bytes_decide(P, hd.site, lo + (tid >> lgRG), latb, st8, a, vmask, thb, f4, vpk, nit, mm, hd.own,
+            pt_item_bytes_decide(K, hd.site, lo + (tid >> lgRG), latb, st8, a, vmask, thb, f4, vpk, mm, hd.own,
                                  hd.V, hd.u, th);
           }
         } else if (has_first[c]) {
-          pt_item_bytes<KIND>(P, cur, lo + (tid >> lgRG), latb, st8, a, vmask, thb, f4, vpk, nit, mm);
+          pt_item_bytes<KIND>(K, cur, lo + (tid >> lgRG), latb, st8, a, vmask, thb, f4, vpk, mm);
         }
         for (int it = tid + nth; group_live && it < cnt; it += nth) {
           const int d = lo + (it >> lgRG);
-          pt_item_bytes<KIND>(P, load_pt_rec<KIND, MODE>(rec + d * S::RW), d, latb, st8, a, vmask, thb, f4, vpk,
-                              nit, mm);
+          pt_item_bytes<KIND>(K, load_pt_rec<KIND, MODE>(rec + d * S::RW), d, latb, st8, a, vmask, thb, f4, vpk,
+                              mm);
         }
       } else {
         if (c == 0 && pending) {
@@ -648,10 +740,10 @@ __device__ __forceinline__ void pt_ladder(const PTDev &P, const uint32_t *rec, u
           __syncthreads();
           take_rows();
         }
-        if (has_first[c]) pt_item<KIND, SWAR>(P, cur, lo + (tid >> lgRG), latb, mtab, a, vmask, row, dE, mm);
+        if (has_first[c]) pt_item<KIND, SWAR>(P, K, cur, lo + (tid >> lgRG), latb, mtab, a, vmask, row, dE, mm);
         for (int it = tid + nth; group_live && it < cnt; it += nth) {
           const int d = lo + (it >> lgRG);
-          pt_item<KIND, SWAR>(P, load_pt_rec<KIND, MODE>(rec + d * S::RW), d, latb, mtab, a, vmask, row, dE, mm);
+          pt_item<KIND, SWAR>(P, K, load_pt_rec<KIND, MODE>(rec + d * S::RW), d, latb, mtab, a, vmask, row, dE, mm);
         }
       }
       if (c == 0) pending = false;
@@ -661,7 +753,7 @@ __device__ __forceinline__ void pt_ladder(const PTDev &P, const uint32_t *rec, u
       // array was last read in class 0, before that class's barrier).
       if (c == 1 && swap_now && swapper && lane + 1 < R)
         swapw[64 * ((phase + 1) & 1) + lane] =
-            philox4x32_10(static_cast<uint32_t>(lane), 0u, phase + 1, kStreamSwap << 24, P.seed_lo, P.seed_hi).v[0];
+            philox4x32_10(static_cast<uint32_t>(lane), 0u, phase + 1, kStreamSwap << 24, K.lo, K.hi).v[0];
       if (c == 3 && swap_now) flush(dE);
       __syncthreads();
     }
@@ -672,10 +764,11 @@ __device__ __forceinline__ void pt_ladder(const PTDev &P, const uint32_t *rec, u
   flush(dE);                                 // deltas of the sweeps after the last swap phase
   __syncthreads();
   if (swapper) {                             // energies, slot map and swap counts for the results
-    e += gathered(rep_s & 63);
+    e += gathered(rep_s & 63, static_cast<uint32_t>(P.sweeps % P.sweeps_per_swap));
     if (lane < R) E[rep_s] = e;
     rep_at[lane] = rep_s;
     slot_of[rep_s & 63] = lane;
+    acc[lane] = acc_r;
   }
   __syncthreads();
 }
