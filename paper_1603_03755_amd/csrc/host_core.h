@@ -10,6 +10,7 @@
 
 #include "../../include/sqa.h"
 #include "device_types.h"
+#include "pt_types.h"
 
 namespace sqa {
 

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include "device_common.h"
+#include "pt_types.h"
 
 namespace sqa {
 
@@ -222,12 +223,11 @@ __device__ __forceinline__ void pt_item_bytes_decide(PTKey K, uint32_t site, int
   }
   flip &= vmask;
   latb[8 * d + a] = static_cast<uint8_t>(own ^ flip);
-  const uint2 fsel = st8[kSpreadEntries + flip];
-  const uint32_t t_lo = __builtin_amdgcn_perm(f4, V.x, fsel.x), t_hi = __builtin_amdgcn_perm(f4, V.y, fsel.y);
-  vpk[0] += t_lo & 0x00FF00FFu;
-  vpk[1] += (t_lo >> 8) & 0x00FF00FFu;
-  vpk[2] += t_hi & 0x00FF00FFu;
-  vpk[3] += (t_hi >> 8) & 0x00FF00FFu;
+  const uint4 fsel = reinterpret_cast<const uint4 *>(st8 + kSpreadEntries)[flip];
+  vpk[0] += __builtin_amdgcn_perm(f4, V.x, fsel.x);
+  vpk[1] += __builtin_amdgcn_perm(f4, V.x, fsel.y);
+  vpk[2] += __builtin_amdgcn_perm(f4, V.y, fsel.z);
+  vpk[3] += __builtin_amdgcn_perm(f4, V.y, fsel.w);
 }
 
 // One item: site d (record x), replica byte a, sweep m.
@@ -241,25 +241,64 @@ __device__ __forceinline__ void pt_item_bytes_decide(PTKey K, uint32_t site, int
 // 4 and 6, 5 and 7).  Every site is an item of every replica byte once per
 // sweep, so over k sweeps the sum for replica w less 4F n k (n sites) is the
 // sum of V_w - 4F over its flips: twice its energy change.
+// The item stream's counter is (site, replica byte a, sweep m, PT << 24).  In
+// the first two Philox rounds only the products with the site depend on the
+// item: what depends on (a, m) and the key alone is computed once per thread
+// and sweep (uniform parts in scalar registers).
+struct PTSweepWords {
+  uint32_t c1;   // (PT << 24) ^ key1: round 1's x2 = hi(A site) ^ c1
+  uint32_t c2;   // lo(B m) ^ (key0 + Weyl0): round 2's x0 = hi(B x2) ^ c2
+  uint32_t d;    // hi(A x0') ^ (key1 + Weyl1), x0' = hi(B m) ^ a ^ key0: round 2's x2 = d ^ lo(A site)
+  uint32_t l;    // lo(A x0'): round 2's x3
+  uint32_t k0, k1;   // the key after two rounds
+};
+
+__device__ __forceinline__ PTSweepWords pt_sweep_words(PTKey K, int a, uint32_t m) {
+  constexpr uint32_t kA = 0xD2511F53u, kB = 0xCD9E8D57u;   // Philox4x32 multipliers
+  constexpr uint32_t kW0 = 0x9E3779B9u, kW1 = 0xBB67AE85u; // and Weyl increments
+  const uint64_t pb = static_cast<uint64_t>(kB) * m;
+  const uint32_t x0 = static_cast<uint32_t>(pb >> 32) ^ static_cast<uint32_t>(a) ^ K.lo;
+  const uint64_t pa2 = static_cast<uint64_t>(kA) * x0;
+  PTSweepWords w;
+  w.c1 = (kStreamPT << 24) ^ K.hi;
+  w.c2 = static_cast<uint32_t>(pb) ^ (K.lo + kW0);
+  w.d = static_cast<uint32_t>(pa2 >> 32) ^ (K.hi + kW1);
+  w.l = static_cast<uint32_t>(pa2);
+  w.k0 = K.lo + 2u * kW0;
+  w.k1 = K.hi + 2u * kW1;
+  return w;
+}
+
+// The Philox state of item (site, a, m) after two rounds.
+__device__ __forceinline__ PhiloxState pt_philox_two(uint32_t site, const PTSweepWords &w) {
+  constexpr uint32_t kA = 0xD2511F53u, kB = 0xCD9E8D57u;
+  const uint64_t pa = static_cast<uint64_t>(kA) * site;
+  const uint32_t x2 = static_cast<uint32_t>(pa >> 32) ^ w.c1;
+  const uint64_t pb = static_cast<uint64_t>(kB) * x2;
+  return PhiloxState{static_cast<uint32_t>(pb >> 32) ^ w.c2, static_cast<uint32_t>(pb), w.d ^ static_cast<uint32_t>(pa),
+                     w.l, w.k0, w.k1};
+}
+
 // The temperature-free front of a byte-mode item: own and partner bytes, the
 // spread-table rows of the own byte and of each term's product byte, and V.
 // The first six Philox rounds run in two parts while those two rounds of LDS
 // reads are in flight; the last four are left to the caller.
 template <int KIND>
-__device__ __forceinline__ uint2 pt_item_front(PTKey K, const SignedRec<KIND> &sr, int d, const uint8_t *latb,
-                                               const uint2 *st8, int a, uint32_t m, uint32_t &own,
+__device__ __forceinline__ uint2 pt_item_front(const PTSweepWords &sw, const SignedRec<KIND> &sr, int d,
+                                               const uint8_t *latb, const uint2 *st8, int a, uint32_t &own,
                                                PhiloxState &ps) {
   using S = Site<KIND>;
   own = latb[8 * d + a];
   uint32_t pbyte[S::T * S::P];
 #pragma unroll
   for (int i = 0; i < S::T * S::P; ++i) pbyte[i] = latb[sr.poff[i] + a];
-  ps = philox_start(sr.site, static_cast<uint32_t>(a), m, kStreamPT << 24, K.lo, K.hi);
   __builtin_amdgcn_sched_barrier(0);
-  philox_rounds<3>(ps);
+  ps = pt_philox_two(sr.site, sw);
+  philox_rounds<1>(ps);
   philox_pin(ps);
   asm volatile("" : "+v"(own));                   // nothing derived from own ahead of the rounds
   __builtin_amdgcn_sched_barrier(0);
+  own &= 0xFFu;                                   // (a byte again for the compiler: no masks on the products)
   uint2 sx[S::T + 1];                             // spread rows: terms 0..T-1, then h's (the own byte)
 #pragma unroll
   for (int t = 0; t < S::T; ++t) {
@@ -284,13 +323,13 @@ __device__ __forceinline__ uint2 pt_item_front(PTKey K, const SignedRec<KIND> &s
 }
 
 template <int KIND>
-__device__ __forceinline__ void pt_item_bytes(PTKey K, const PTRec<KIND> &x, int d, uint8_t *latb,
-                                              const uint2 *st8, int a, uint32_t vmask, const lds_u8 *const *thb,
-                                              uint32_t f4, uint32_t *vpk, uint32_t m) {
+__device__ __forceinline__ void pt_item_bytes(PTKey K, const PTSweepWords &sw, const PTRec<KIND> &x, int d,
+                                              uint8_t *latb, const uint2 *st8, int a, uint32_t vmask,
+                                              const lds_u8 *const *thb, uint32_t f4, uint32_t *vpk, uint32_t m) {
   const SignedRec<KIND> sr = signed_from_pt<KIND>(x);
   uint32_t own;
   PhiloxState ps;
-  const uint2 V = pt_item_front<KIND>(K, sr, d, latb, st8, a, m, own, ps);
+  const uint2 V = pt_item_front<KIND>(sw, sr, d, latb, st8, a, own, ps);
   uint32_t th[8];
   pt_thresholds(thb, V, th);
   __builtin_amdgcn_sched_barrier(0);
@@ -310,13 +349,13 @@ struct PTItemHead {
 };
 
 template <int KIND>
-__device__ __forceinline__ PTItemHead pt_item_bytes_head(PTKey K, const PTRec<KIND> &x, int d,
-                                                         const uint8_t *latb, const uint2 *st8, int a, uint32_t m) {
+__device__ __forceinline__ PTItemHead pt_item_bytes_head(const PTSweepWords &sw, const PTRec<KIND> &x, int d,
+                                                         const uint8_t *latb, const uint2 *st8, int a) {
   const SignedRec<KIND> sr = signed_from_pt<KIND>(x);
   PTItemHead hd;
   hd.site = sr.site;
   PhiloxState ps;
-  hd.V = pt_item_front<KIND>(K, sr, d, latb, st8, a, m, hd.own, ps);
+  hd.V = pt_item_front<KIND>(sw, sr, d, latb, st8, a, hd.own, ps);
   philox_rounds<4>(ps);
   hd.u = philox_words(ps);
   return hd;
@@ -589,10 +628,10 @@ __device__ __forceinline__ void pt_ladder(const PTDev &P, const uint32_t *rec, u
     has_first[c] = group_live && tid < ((cls[c + 1] - cls[c]) << lgRG);
     pmax = max(pmax, (((cls[c + 1] - cls[c]) << lgRG) + nth - 1) / nth);
   }
-  PTRec<KIND> nxt;
-  if (has_first[0]) nxt = load_pt_rec<KIND, MODE>(rec + (cls[0] + (tid >> lgRG)) * S::RW);
+  PTRec<KIND> rb[2];                               // class c's first record in rb[c & 1]
+  if (has_first[0]) rb[0] = load_pt_rec<KIND, MODE>(rec + (cls[0] + (tid >> lgRG)) * S::RW);
   // energy deltas into E (RG is a power of two up to 8, so it divides the 16-lane rows)
-  uint32_t *parts = swapw + 2 * 64 + kPTMaxWaves * 64;   // 64 words per wave
+  uint32_t *parts = swapw + 2 * 64;   // 64 words per wave
   uint32_t *part = parts + 64 * wave;
   // byte mode: the 16-bit halves into the per-replica sums (a half gains at most
   // 8F <= 248 per item, so 256 items fit)
@@ -703,13 +742,14 @@ __device__ __forceinline__ void pt_ladder(const PTDev &P, const uint32_t *rec, u
   for (int m = 0; m < P.sweeps; ++m) {
     const bool swap_now = (m + 1) % P.sweeps_per_swap == 0;
     const uint32_t mm = static_cast<uint32_t>(m);
+    const PTSweepWords swd = pt_sweep_words(K, a, mm);
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const int lo = cls[c];
       const int cnt = (cls[c + 1] - lo) << lgRG;
-      const PTRec<KIND> cur = nxt;
+      const PTRec<KIND> &cur = rb[c & 1];
       const int cn = (c + 1) & 3;
-      if (has_first[cn]) nxt = load_pt_rec<KIND, MODE>(rec + (cls[cn] + (tid >> lgRG)) * S::RW);
+      if (has_first[cn]) rb[(c + 1) & 1] = load_pt_rec<KIND, MODE>(rec + (cls[cn] + (tid >> lgRG)) * S::RW);
       if constexpr (MODE == kPTBytes) {
         if (pend + pmax > 256) widen();
         pend += pmax;
@@ -717,7 +757,7 @@ __device__ __forceinline__ void pt_ladder(const PTDev &P, const uint32_t *rec, u
           // the previous sweep's swap phase beside the first item's head
           PTItemHead hd;
           if (swapper) decide_swaps();
-          if (has_first[0]) hd = pt_item_bytes_head<KIND>(K, cur, lo + (tid >> lgRG), latb, st8, a, mm);
+          if (has_first[0]) hd = pt_item_bytes_head<KIND>(swd, cur, lo + (tid >> lgRG), latb, st8, a);
           __syncthreads();
           take_rows();
           if (has_first[0]) {
@@ -727,12 +767,12 @@ __device__ __forceinline__ void pt_ladder(const PTDev &P, const uint32_t *rec, u
                                  hd.V, hd.u, th);
           }
         } else if (has_first[c]) {
-          pt_item_bytes<KIND>(K, cur, lo + (tid >> lgRG), latb, st8, a, vmask, thb, f4, vpk, mm);
+          pt_item_bytes<KIND>(K, swd, cur, lo + (tid >> lgRG), latb, st8, a, vmask, thb, f4, vpk, mm);
         }
         for (int it = tid + nth; group_live && it < cnt; it += nth) {
           const int d = lo + (it >> lgRG);
-          pt_item_bytes<KIND>(K, load_pt_rec<KIND, MODE>(rec + d * S::RW), d, latb, st8, a, vmask, thb, f4, vpk,
-                              mm);
+          pt_item_bytes<KIND>(K, swd, load_pt_rec<KIND, MODE>(rec + d * S::RW), d, latb, st8, a, vmask, thb, f4,
+                              vpk, mm);
         }
       } else {
         if (c == 0 && pending) {
@@ -774,8 +814,7 @@ __device__ __forceinline__ void pt_ladder(const PTDev &P, const uint32_t *rec, u
 }
 
 // Dynamic LDS: [byte-spread table: kPTSpreadWords][rec_cap words][lat_cap u64][mtab_cap words]
-// [E, rep_at, slot_of, acc: 64 each][swap words: 2 x 64][slot scratch: 64 per wave]
-// [energy partials: 64 per wave]
+// [E, rep_at, slot_of, acc: 64 each][swap words: 2 x 64][energy partials: 64 per wave]
 // [spack_cap words: the packed swap table when it is staged].
 __global__ __launch_bounds__(64 * kPTMaxWaves) void pt_kernel(const PTDev *__restrict__ pts, int rec_cap, int lat_cap,
                                                               int mtab_cap, int spack_cap) {
@@ -791,19 +830,21 @@ __global__ __launch_bounds__(64 * kPTMaxWaves) void pt_kernel(const PTDev *__res
   uint32_t *acc = reinterpret_cast<uint32_t *>(slot_of + 64);
   uint32_t *swapw = acc + 64;
   uint32_t *spk = reinterpret_cast<uint32_t *>(E) + kPTLadderWords;   // after the wave scratch
-  static_assert(kPTLadderWords == 4 * 64 + 2 * 64 + 2 * kPTMaxWaves * 64,
-                "E, rep_at, slot_of, acc, two phases of swap words, a slot scratch and an energy partial per wave");
+  static_assert(kPTLadderWords == 4 * 64 + 2 * 64 + kPTMaxWaves * 64,
+                "E, rep_at, slot_of, acc, two phases of swap words and an energy partial per wave");
   const int tid = threadIdx.x, nth = blockDim.x;
   const int rw = rec_words_of(P.kind);
   for (int x = tid; x < kSpreadEntries; x += nth) {
     const uint32_t lo = static_cast<uint32_t>(x) & 0xFu, hi = static_cast<uint32_t>(x) >> 4;
     st8[x] = make_uint2(spread8(lo) << 2, spread8(hi) << 2);
-    uint32_t sl = 0, sh = 0;
-    for (int i = 0; i < 4; ++i) {
-      sl |= (((lo >> i) & 1u) ? static_cast<uint32_t>(i) : 4u + i) << (8 * i);
-      sh |= (((hi >> i) & 1u) ? static_cast<uint32_t>(i) : 4u + i) << (8 * i);
-    }
-    st8[kSpreadEntries + x] = make_uint2(sl, sh);
+    // v_perm selector of the byte pair (i, i + 2) of a word: i where flipped
+    // (second source, the V byte), 4 + i elsewhere (first source, 4F); 0x0C: zero
+    auto pair_sel = [](uint32_t nib, uint32_t i) {
+      const uint32_t s0 = ((nib >> i) & 1u) ? i : 4u + i, s2 = ((nib >> (i + 2)) & 1u) ? i + 2 : 6u + i;
+      return s0 | (0x0Cu << 8) | (s2 << 16) | (0x0Cu << 24);
+    };
+    reinterpret_cast<uint4 *>(st8 + kSpreadEntries)[x] =
+        make_uint4(pair_sel(lo, 0), pair_sel(lo, 1), pair_sel(hi, 0), pair_sel(hi, 1));
   }
   for (int i = tid; i < P.n * rw; i += nth) rec[i] = P.rec[i];
   const int width = 2 * P.F + 1;
@@ -812,7 +853,7 @@ __global__ __launch_bounds__(64 * kPTMaxWaves) void pt_kernel(const PTDev *__res
   if (staged)
     for (int i = tid; i < P.spack_words; i += nth) spk[i] = P.spack[i];
   for (int r = tid; r < kPTMaxWaves * 64; r += nth)      // the waves' energy partials
-    reinterpret_cast<int32_t *>(swapw)[2 * 64 + kPTMaxWaves * 64 + r] = 0;
+    swapw[2 * 64 + r] = 0;
   for (int r = tid; r < 64; r += nth) {
     rep_at[r] = r;
     slot_of[r] = r;
