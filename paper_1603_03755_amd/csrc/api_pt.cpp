@@ -14,6 +14,7 @@ struct pt_handle {
   Embedded emb;
   DeviceLayout lay;
   int32_t R = 0, F = 0, Dmax = 0, sweeps = 0, sps = 1;
+  bool swap_falling = false;   // every row of stab is non-increasing in D
   uint64_t seed = 0;
   std::vector<double> betas;
   std::vector<uint32_t> mtab, stab, spack;
@@ -45,6 +46,13 @@ struct pt_handle {
     P.R = R;
     P.F = F;
     P.Dmax = Dmax;
+    // 1: swap phases compare gaps with precomputed acceptance bounds; 0: they
+    // read the threshold of each gap.  For the tests, SQA_DEBUG_PT_SWAP=table
+    // forces 0 and =bisect (2) starts every bound's search from 0 instead of
+    // the estimate, so that most bounds are found by bisection.
+    const char *dbg = std::getenv("SQA_DEBUG_PT_SWAP");
+    P.swap_falling = !swap_falling ? 0 : (dbg && std::strcmp(dbg, "table") == 0) ? 0
+                                         : (dbg && std::strcmp(dbg, "bisect") == 0) ? 2 : 1;
     P.sweeps = sweeps;
     P.sweeps_per_swap = sps;
     P.seed_lo = static_cast<uint32_t>(seed);
@@ -212,6 +220,11 @@ static sqa_status pt_create_impl(const sqa_problem *problem, const sqa_embedding
   h->Dmax = static_cast<int32_t>(dmax);
   h->mtab = pt_metropolis_table(h->betas, h->F);
   h->stab = pt_swap_table(h->betas, h->Dmax);
+  h->swap_falling = true;
+  for (int32_t r = 0; r + 1 < h->R; ++r)
+    for (int32_t D = 1; D <= h->Dmax; ++D)
+      if (h->stab[static_cast<size_t>(r) * (h->Dmax + 1) + D] > h->stab[static_cast<size_t>(r) * (h->Dmax + 1) + D - 1])
+        h->swap_falling = false;
   h->spack = pt_swap_pack(h->stab, h->R, h->Dmax);
   const int n = h->emb.n;
   const size_t nt = h->emb.terms.size();

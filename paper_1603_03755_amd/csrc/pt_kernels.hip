@@ -516,13 +516,93 @@ __device__ __forceinline__ SwapRows swap_rows(const lds_u32 *spk, bool staged, i
   return sr;
 }
 
+// ln(t 2^-32) for 0 < t < 2^32, as log1p(-(2^32 - t) 2^-32): full float
+// precision also where t is close to 2^32.
+__device__ __forceinline__ float log1m_frac32(uint32_t t) {
+  return log1pf(-static_cast<float>(0xFFFFFFFFu - t + 1u) * 0x1p-32f);
+}
+
+// Pair r's acceptance bound for its swap word u: with the staged row T of pair
+// r non-increasing in D (thresholds of exp(D (beta_{r+1} - beta_r)), a gap D >
+// Dmax clamping to Dmax), the test min(u, 2^32 - 2) < T(min(D, Dmax)) holds
+// exactly for D <= D*, and D* = 2^32 - 1 when it holds at Dmax.  A float
+// estimate from ln(u 2^-32) / ln(T(1) 2^-32) (T(1) ~ 2^32 exp(beta_{r+1} - beta_r)) is
+// checked against the table at D* and D* + 1; a bisection over the table
+// settles any estimate that misses.  `inv` is 1 / ln(T(1) 2^-32).
+__device__ __forceinline__ uint32_t swap_bound(uint32_t u, uint32_t o0, uint32_t len, int Dmax, float inv,
+                                               const lds_u32 *spk) {
+  const uint32_t uq = min(u, 0xFFFFFFFEu);
+  auto T = [&](int i) { return static_cast<uint32_t>(i) < len ? spk[o0 + i] : 0u; };
+  const float x = log1m_frac32(uq) * inv;   // gaps below x pass
+  const int d0 = static_cast<int>(fminf(fmaxf(ceilf(x) - 1.0f, 0.0f), static_cast<float>(max(Dmax - 1, 0))));
+  const uint32_t t_max = T(Dmax), t0 = T(d0), t1 = T(d0 + 1);
+  if (uq < t_max) return 0xFFFFFFFFu;
+  if (uq < t0 && !(uq < t1)) return static_cast<uint32_t>(d0);
+  int lo = 0, hi = Dmax;                          // T(0) passes, T(Dmax) does not
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (uq < T(mid)) lo = mid;
+    else hi = mid;
+  }
+  return static_cast<uint32_t>(lo);
+}
+
+// The partner lane's energy and replica in swap phase q (0: even pairs, quad
+// perm [1,0,3,2]; 1: odd pairs, a low lane takes lane + 1 (wave_shl:1) and a
+// high lane lane - 1 (wave_shr:1), across row boundaries; lanes 0 and 63 have
+// no pair).
+__device__ __forceinline__ void swap_partner(int q, bool low, int e, int rep_s, int &pe, int &prep) {
+  if (q == 0) {
+    pe = __builtin_amdgcn_mov_dpp(e, 0xB1, 0xF, 0xF, true);
+    prep = __builtin_amdgcn_mov_dpp(rep_s, 0xB1, 0xF, 0xF, true);
+  } else {
+    const int up_e = __builtin_amdgcn_update_dpp(0, e, 0x130, 0xF, 0xF, false);
+    const int up_r = __builtin_amdgcn_update_dpp(0, rep_s, 0x130, 0xF, 0xF, false);
+    const int dn_e = __builtin_amdgcn_update_dpp(0, e, 0x138, 0xF, 0xF, false);
+    const int dn_r = __builtin_amdgcn_update_dpp(0, rep_s, 0x138, 0xF, 0xF, false);
+    pe = low ? up_e : dn_e;
+    prep = low ? up_r : dn_r;
+  }
+}
+
 // One swap phase (Eq. (B1)) as one wave sees it: lane s holds the replica at
 // slot s and its energy as of the last phase; it adds every wave's partial of
 // that replica (their sum less `off`, shifted right by `sh`, is the energy
 // change), then the even pairs (r, r + 1), then the odd ones, are decided by
-// both of their lanes from the same inputs.  Lane r counts the accepted swaps
-// of pair r in `acc`.  Kept out of line so that its registers do not weigh on
-// the sweep's.
+// both of their lanes from the same inputs, here by comparing the gap with
+// pair r's bound (lane r's `bound`, see swap_bound).  Lane r counts the
+// accepted swaps of pair r in `acc`.  Kept out of line so that its registers
+// do not weigh on the sweep's.
+__device__ __noinline__ SwapSlot swap_phase_bounded(int rep_s, int e, uint32_t acc, uint32_t off, int sh, int R,
+                                                    uint32_t bound, const lds_u32 *parts) {
+  const int lane = static_cast<int>(threadIdx.x & 63u);
+  uint32_t de = 0;
+#pragma unroll
+  for (int v = 0; v < kPTMaxWaves; ++v) de += parts[64 * v + (rep_s & 63)];
+  e += static_cast<int32_t>(de - off) >> sh;
+  // the bounds of this lane's pairs: (lane & ~1) in the even phase, from that
+  // lane (quad_perm [0,0,2,2]); in the odd phase its own (odd lanes) or lane - 1's
+  const uint32_t b_even = static_cast<uint32_t>(__builtin_amdgcn_mov_dpp(static_cast<int>(bound), 0xA0, 0xF, 0xF, true));
+  const uint32_t b_dn = static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(bound), 0x138, 0xF, 0xF, false));
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const bool low = ((lane - q) & 1) == 0;       // this lane is slot r of its pair (r, r + 1)
+    const int r = lane - ((lane - q) & 1);
+    int pe, prep;
+    swap_partner(q, low, e, rep_s, pe, prep);
+    const int D = low ? pe - e : e - pe;          // E(slot r + 1) - E(slot r)
+    const uint32_t b = (q == 0) ? b_even : (low ? bound : b_dn);
+    if (r >= 0 && r + 1 < R && (D <= 0 || static_cast<uint32_t>(D) <= b)) {
+      e = pe;
+      rep_s = prep;
+      if (low) ++acc;
+    }
+  }
+  return SwapSlot{rep_s, e, acc};
+}
+
+// The same with each gap's threshold read from the swap table (staged in LDS,
+// else in device memory) and compared with the pair's swap word.
 __device__ __noinline__ SwapSlot swap_phase(int rep_s, int e, uint32_t acc, uint32_t off, int sh, int R, int Dmax,
                                             bool staged, SwapRows rows, const lds_u32 *spk, glb_u32 *stab,
                                             const lds_u32 *sw, const lds_u32 *parts) {
@@ -539,26 +619,14 @@ __device__ __noinline__ SwapSlot swap_phase(int rep_s, int e, uint32_t acc, uint
   e += static_cast<int32_t>(de - off) >> sh;
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
-    const bool low = ((lane - q) & 1) == 0;       // this lane is slot r of its pair (r, r + 1)
+    const bool low = ((lane - q) & 1) == 0;
     const int r = lane - ((lane - q) & 1);
     const bool valid = r >= 0 && r + 1 < R;
     const uint32_t o0 = rows.o0[q], len = rows.len[q];
-    int pe, prep;                                 // the partner lane's energy and replica
-    if (q == 0) {
-      pe = __builtin_amdgcn_mov_dpp(e, 0xB1, 0xF, 0xF, true);        // quad_perm [1,0,3,2]
-      prep = __builtin_amdgcn_mov_dpp(rep_s, 0xB1, 0xF, 0xF, true);
-    } else {
-      // odd pairs: a low lane takes lane + 1 (wave_shl:1), a high lane lane - 1
-      // (wave_shr:1), across row boundaries; lanes 0 and 63 have no pair
-      const int up_e = __builtin_amdgcn_update_dpp(0, e, 0x130, 0xF, 0xF, false);
-      const int up_r = __builtin_amdgcn_update_dpp(0, rep_s, 0x130, 0xF, 0xF, false);
-      const int dn_e = __builtin_amdgcn_update_dpp(0, e, 0x138, 0xF, 0xF, false);
-      const int dn_r = __builtin_amdgcn_update_dpp(0, rep_s, 0x138, 0xF, 0xF, false);
-      pe = low ? up_e : dn_e;
-      prep = low ? up_r : dn_r;
-    }
+    int pe, prep;
+    swap_partner(q, low, e, rep_s, pe, prep);
     if (valid) {
-      const int D = low ? pe - e : e - pe;        // E(slot r + 1) - E(slot r)
+      const int D = low ? pe - e : e - pe;
       bool ok = D <= 0;
       if (!ok) {
         const int Dc = min(D, Dmax);
@@ -696,14 +764,31 @@ __device__ __forceinline__ void pt_ladder(const PTDev &P, const uint32_t *rec, u
   const bool swapper = wave == swap_wave;
   int rep_s = lane;                                 // replica at slot `lane` (swap wave)
   int e = E[lane];                                  // and its energy as of the last swap phase
-  if (swapper && lane + 1 < R)
-    swapw[lane] = philox4x32_10(static_cast<uint32_t>(lane), 0u, 0u, kStreamSwap << 24, K.lo, K.hi).v[0];
+  uint32_t word0 = 0;
+  if (swapper && lane + 1 < R) {
+    word0 = philox4x32_10(static_cast<uint32_t>(lane), 0u, 0u, kStreamSwap << 24, K.lo, K.hi).v[0];
+    swapw[lane] = word0;
+  }
   uint32_t phase = 0;
   bool pending = false;                             // a swap phase is due before class 0's thresholds
   // (an LDS null pointer is not zero: the staging flag travels on its own)
   const lds_u32 *spk_lds = (const lds_u32 *)(spk ? spk : swapw);
   SwapRows srows{};
   if (swapper) srows = swap_rows(spk_lds, spk != nullptr, R);
+  // With the table staged and its rows non-increasing, the swap wave turns each
+  // swap word into its pair's acceptance bound (swap_bound) when it draws it,
+  // two phases ahead, so that a swap phase reads no table.
+  const bool bounded = spk != nullptr && P.swap_falling != 0;
+  uint32_t bnd0 = 0u, bnd1 = 0u, w_next = 0u;       // bounds of the phases of parity 0 and 1
+  uint32_t b_o0 = 0, b_len = 0;                     // pair `lane`'s staged row
+  float b_inv = 0.0f;
+  if (swapper && bounded && lane + 1 < R) {
+    b_o0 = spk_lds[lane];
+    b_len = spk_lds[lane + 1] - b_o0;
+    const uint32_t t1 = (1u < b_len) ? spk_lds[b_o0 + 1] : 0u;
+    b_inv = (t1 == 0u || P.swap_falling == 2) ? 0.0f : 1.0f / log1m_frac32(t1);
+    bnd0 = swap_bound(word0, b_o0, b_len, P.Dmax, b_inv, spk_lds);
+  }
   uint32_t acc_r = 0;                               // swaps accepted by pair (lane, lane + 1)
   const uint32_t off_swap = off * static_cast<uint32_t>(P.sweeps_per_swap);
   // During the sweeps slot_of[rho] holds what a thread needs of replica rho's
@@ -712,9 +797,11 @@ __device__ __forceinline__ void pt_ladder(const PTDev &P, const uint32_t *rec, u
   const uint32_t pub0 = static_cast<uint32_t>(reinterpret_cast<uintptr_t>(mtabb));
   auto decide_swaps = [&]() {
     __builtin_amdgcn_s_setprio(3);               // ahead of the item waves on its SIMD
-    const SwapSlot ns = swap_phase(rep_s, e, acc_r, off_swap, sh, R, P.Dmax, spk != nullptr, srows, spk_lds,
-                                   (glb_u32 *)P.stab, (const lds_u32 *)(swapw + 64 * (phase & 1)),
-                                   (const lds_u32 *)parts);
+    const SwapSlot ns =
+        bounded ? swap_phase_bounded(rep_s, e, acc_r, off_swap, sh, R, (phase & 1) ? bnd1 : bnd0,
+                                     (const lds_u32 *)parts)
+                : swap_phase(rep_s, e, acc_r, off_swap, sh, R, P.Dmax, spk != nullptr, srows, spk_lds,
+                             (glb_u32 *)P.stab, (const lds_u32 *)(swapw + 64 * (phase & 1)), (const lds_u32 *)parts);
     rep_s = ns.rep;
     e = ns.e;
     acc_r = ns.acc;
@@ -791,9 +878,15 @@ __device__ __forceinline__ void pt_ladder(const PTDev &P, const uint32_t *rec, u
       // words in class 1 (their buffer was last read by that wave in class 0), and
       // every wave stores its energy deltas ahead of the class-3 barrier (their
       // array was last read in class 0, before that class's barrier).
-      if (c == 1 && swap_now && swapper && lane + 1 < R)
-        swapw[64 * ((phase + 1) & 1) + lane] =
-            philox4x32_10(static_cast<uint32_t>(lane), 0u, phase + 1, kStreamSwap << 24, K.lo, K.hi).v[0];
+      if (c == 1 && swap_now && swapper && lane + 1 < R) {
+        w_next = philox4x32_10(static_cast<uint32_t>(lane), 0u, phase + 1, kStreamSwap << 24, K.lo, K.hi).v[0];
+        swapw[64 * ((phase + 1) & 1) + lane] = w_next;
+      }
+      if (c == 2 && swap_now && swapper && bounded && lane + 1 < R) {   // its bound, a class later
+        const uint32_t b = swap_bound(w_next, b_o0, b_len, P.Dmax, b_inv, spk_lds);
+        if ((phase + 1) & 1) bnd1 = b;
+        else bnd0 = b;
+      }
       if (c == 3 && swap_now) flush(dE);
       __syncthreads();
     }

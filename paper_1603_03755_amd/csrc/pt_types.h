@@ -40,6 +40,7 @@ struct PTDev {
   int32_t *rep_at;          // [R] slot -> replica
   uint64_t *swap_acc;       // [R-1]
   int32_t kind, n, n_terms, R, F, Dmax, sweeps, sweeps_per_swap, spack_words;
+  int32_t swap_falling;     // rows non-increasing in D: 1 bounds, 2 bounds by bisection only; 0 table reads
   uint32_t seed_lo, seed_hi;
   int32_t cls[5];
 };

@@ -193,12 +193,37 @@ def test_pt_swap_table_in_lds_or_device_memory(sqa, monkeypatch, stage):
         assert acc.sum() > 0
 
 
+@pytest.mark.parametrize("mode", ["bounds", "bisect", "table"])
+def test_pt_swap_decisions_by_bounds_or_thresholds(sqa, monkeypatch, mode):
+    """A swap phase compares each pair's energy gap with the pair's acceptance
+    bound, found from a float estimate checked against the staged table
+    (default) or by bisection from 0 (bisect), or it reads the gap's threshold
+    (table): each gives the oracle's ladder, with swaps every sweep over wide,
+    narrow and zero temperature spans."""
+    if mode == "bounds":
+        monkeypatch.delenv("SQA_DEBUG_PT_SWAP", raising=False)
+    else:
+        monkeypatch.setenv("SQA_DEBUG_PT_SWAP", mode)
+    for kind, N, R, bmin, bmax in ((ME, 8, 32, 0.1, 5.0), (LHZ, 7, 20, 0.05, 20.0), (ME, 5, 64, 1.0, 1.2),
+                                   (LHZ, 4, 8, 2.0, 2.0)):
+        print(f"PT swap decisions mode={mode} kind={kind} N={N} R={R} beta=[{bmin},{bmax}]", flush=True)
+        J = sk_instance(N, 760 + N)
+        seed = 0x9900 + N + R
+        dev = sqa.PT(kind, J, -2, bmin, bmax, R, 150, 1, seed).run()
+        spins, E, rep, acc = dev.read()
+        emb = O.Embedding(kind, J, -2)
+        ospins, oE, orep, oacc = O.pt_run(emb, O.pt_ladder(bmin, bmax, R), 150, 1, seed)
+        assert (rep == orep).all() and (spins == ospins[orep]).all()
+        assert (E == oE[orep]).all() and (acc == oacc).all()
+        assert acc.sum() > 0
+
+
 @pytest.mark.parametrize("waves", ["1", "3", "10"])
 def test_pt_results_do_not_depend_on_wave_count(sqa, monkeypatch, waves):
-    """Every wave decides the swap phases itself and keeps its own energy partials:
-    one wave (several items per thread), three, or the most a ladder may use give
-    the oracle's ladder, with replica bytes from one to eight and swap intervals of
-    one and three sweeps."""
+    """The last wave decides the swap phases and every wave keeps its own energy
+    partials: one wave (several items per thread, and the swap decisions), three,
+    or the most a ladder may use give the oracle's ladder, with replica bytes from
+    one to eight and swap intervals of one and three sweeps."""
     monkeypatch.setenv("SQA_PT_WAVES", waves)
     print(f"PT waves={waves}", flush=True)
     for kind, N, R, sps in ((ME, 7, 32, 1), (LHZ, 8, 64, 1), (ME, 5, 9, 3), (LHZ, 6, 5, 1)):
