@@ -15,6 +15,7 @@ struct pt_handle {
   DeviceLayout lay;
   int32_t R = 0, F = 0, Dmax = 0, sweeps = 0, sps = 1;
   bool swap_falling = false;   // every row of stab is non-increasing in D
+  int32_t nph = 4, ph[5] = {0, 0, 0, 0, 0};   // sweep phases (see pt_phases)
   uint64_t seed = 0;
   std::vector<double> betas;
   std::vector<uint32_t> mtab, stab, spack;
@@ -58,6 +59,11 @@ struct pt_handle {
     P.seed_lo = static_cast<uint32_t>(seed);
     P.seed_hi = static_cast<uint32_t>(seed >> 32);
     for (int c = 0; c < 5; ++c) P.cls[c] = lay.cls[c];
+    // SQA_DEBUG_PT_PHASES=4 keeps the four classes (for the tests)
+    const char *phs = std::getenv("SQA_DEBUG_PT_PHASES");
+    const bool classes = phs && std::strcmp(phs, "4") == 0;
+    P.nph = classes ? 4 : nph;
+    for (int c = 0; c < 5; ++c) P.ph[c] = classes ? lay.cls[c] : ph[c];
     return P;
   }
 };
@@ -173,6 +179,36 @@ static int64_t swap_table_width(const std::vector<double> &betas, int64_t dfull)
   return std::min(cut, dfull);
 }
 
+// A sweep updates the colour classes in order (sites of one class share no
+// term).  Two consecutive classes that share no term either update together in
+// one phase: each site's field reads only sites of the other classes, so the
+// spins, energies and random words are those of the class-by-class sweep.  The
+// byte-mode kernel of the ME kinds merges the first such pair (clique-chain ME:
+// classes 1 and 2); every other ladder sweeps the four classes.
+static void pt_phases(const Embedded &emb, const DeviceLayout &lay, int32_t F, int32_t *nph, int32_t ph[5]) {
+  for (int c = 0; c < 5; ++c) ph[c] = lay.cls[c];
+  *nph = 4;
+  if (F > kPTByteF || (emb.kind != kKindME && emb.kind != kKindMEC)) return;
+  auto cls_of = [&](int s) {
+    const int d = lay.dev_of[s];
+    int c = 0;
+    while (c < 3 && d >= lay.cls[c + 1]) ++c;
+    return c;
+  };
+  bool joined[4][4] = {};
+  for (const Term &t : emb.terms)
+    for (int i = 0; i < t.arity; ++i)
+      for (int j = 0; j < t.arity; ++j)
+        if (i != j) joined[cls_of(t.s[i])][cls_of(t.s[j])] = true;
+  for (int c = 0; c < 3; ++c)
+    if (!joined[c][c + 1]) {
+      for (int k = c + 1; k < 4; ++k) ph[k] = lay.cls[k + 1];
+      ph[4] = lay.cls[4];
+      *nph = 3;
+      return;
+    }
+}
+
 // Widest swap-table row accepted (entries).
 constexpr int64_t kMaxSwapRow = int64_t(1) << 22;
 
@@ -219,6 +255,7 @@ static sqa_status pt_create_impl(const sqa_problem *problem, const sqa_embedding
   }
   h->Dmax = static_cast<int32_t>(dmax);
   h->mtab = pt_metropolis_table(h->betas, h->F);
+  pt_phases(h->emb, h->lay, h->F, &h->nph, h->ph);
   h->stab = pt_swap_table(h->betas, h->Dmax);
   h->swap_falling = true;
   for (int32_t r = 0; r + 1 < h->R; ++r)

@@ -644,7 +644,10 @@ __device__ __noinline__ SwapSlot swap_phase(int rep_s, int e, uint32_t acc, uint
   return SwapSlot{rep_s, e, acc};
 }
 
-template <int KIND, int MODE>
+// NPH: phases per sweep, each a run of consecutive colour classes with no term
+// between them (updated together, they give what one class after the other
+// gives); 4 (the classes) or 3 (one pair merged).
+template <int KIND, int MODE, int NPH>
 __device__ __forceinline__ void pt_ladder(const PTDev &P, const uint32_t *rec, uint64_t *lat, const uint32_t *mtab,
                                           const uint2 *st8, int32_t *E, int32_t *rep_at, int32_t *slot_of,
                                           uint32_t *acc, uint32_t *swapw, const uint32_t *spk) {
@@ -684,20 +687,21 @@ __device__ __forceinline__ void pt_ladder(const PTDev &P, const uint32_t *rec, u
     row[w] = (w < nvalid) ? slot_of[8 * a + w] * width : 0;
     thb[w] = mtabb + 4 * row[w];
   }
-  // The record of a thread's first item in the next colour class is read into
-  // registers before the current class is processed, so its LDS latency overlaps
-  // the current item and the class barrier (records are read-only).
-  int cls[5];
+  // The record of a thread's first item in the next phase is read into
+  // registers before the current phase is processed, so its LDS latency overlaps
+  // the current item and the phase barrier (records are read-only).
+  int ph[NPH + 1];                                  // phase c: device sites [ph[c], ph[c + 1])
 #pragma unroll
-  for (int c = 0; c < 5; ++c) cls[c] = P.cls[c];
-  bool has_first[4];
+  for (int c = 0; c <= NPH; ++c) ph[c] = P.ph[c];
+  bool has_first[NPH];
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    has_first[c] = group_live && tid < ((cls[c + 1] - cls[c]) << lgRG);
-    pmax = max(pmax, (((cls[c + 1] - cls[c]) << lgRG) + nth - 1) / nth);
+  for (int c = 0; c < NPH; ++c) {
+    has_first[c] = group_live && tid < ((ph[c + 1] - ph[c]) << lgRG);
+    pmax = max(pmax, (((ph[c + 1] - ph[c]) << lgRG) + nth - 1) / nth);
   }
-  PTRec<KIND> rb[2];                               // class c's first record in rb[c & 1]
-  if (has_first[0]) rb[0] = load_pt_rec<KIND, MODE>(rec + (cls[0] + (tid >> lgRG)) * S::RW);
+  constexpr int NB = (NPH % 2 == 0) ? 2 : NPH;      // record buffers: phase c's in rb[c % NB]
+  PTRec<KIND> rb[NB];
+  if (has_first[0]) rb[0] = load_pt_rec<KIND, MODE>(rec + (ph[0] + (tid >> lgRG)) * S::RW);
   // energy deltas into E (RG is a power of two up to 8, so it divides the 16-lane rows)
   uint32_t *parts = swapw + 2 * 64;   // 64 words per wave
   uint32_t *part = parts + 64 * wave;
@@ -831,12 +835,12 @@ __device__ __forceinline__ void pt_ladder(const PTDev &P, const uint32_t *rec, u
     const uint32_t mm = static_cast<uint32_t>(m);
     const PTSweepWords swd = pt_sweep_words(K, a, mm);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int lo = cls[c];
-      const int cnt = (cls[c + 1] - lo) << lgRG;
-      const PTRec<KIND> &cur = rb[c & 1];
-      const int cn = (c + 1) & 3;
-      if (has_first[cn]) rb[(c + 1) & 1] = load_pt_rec<KIND, MODE>(rec + (cls[cn] + (tid >> lgRG)) * S::RW);
+    for (int c = 0; c < NPH; ++c) {
+      const int lo = ph[c];
+      const int cnt = (ph[c + 1] - lo) << lgRG;
+      const PTRec<KIND> &cur = rb[c % NB];
+      const int cn = (c + 1) % NPH;
+      if (has_first[cn]) rb[(c + 1) % NB] = load_pt_rec<KIND, MODE>(rec + (ph[cn] + (tid >> lgRG)) * S::RW);
       if constexpr (MODE == kPTBytes) {
         if (pend + pmax > 256) widen();
         pend += pmax;
@@ -874,20 +878,21 @@ __device__ __forceinline__ void pt_ladder(const PTDev &P, const uint32_t *rec, u
         }
       }
       if (c == 0) pending = false;
-      // In a sweep that ends in a swap phase: the swap wave draws the next phase's
-      // words in class 1 (their buffer was last read by that wave in class 0), and
-      // every wave stores its energy deltas ahead of the class-3 barrier (their
-      // array was last read in class 0, before that class's barrier).
+      // In a sweep that ends in a swap phase: the swap wave draws the next swap
+      // phase's words in phase 1 (their buffer was last read by that wave in
+      // phase 0) and their bounds in phase 2, and every wave stores its energy
+      // deltas ahead of the last phase's barrier (their array was last read in
+      // phase 0, before that phase's barrier).
       if (c == 1 && swap_now && swapper && lane + 1 < R) {
         w_next = philox4x32_10(static_cast<uint32_t>(lane), 0u, phase + 1, kStreamSwap << 24, K.lo, K.hi).v[0];
         swapw[64 * ((phase + 1) & 1) + lane] = w_next;
       }
-      if (c == 2 && swap_now && swapper && bounded && lane + 1 < R) {   // its bound, a class later
+      if (c == 2 && swap_now && swapper && bounded && lane + 1 < R) {
         const uint32_t b = swap_bound(w_next, b_o0, b_len, P.Dmax, b_inv, spk_lds);
         if ((phase + 1) & 1) bnd1 = b;
         else bnd0 = b;
       }
-      if (c == 3 && swap_now) flush(dE);
+      if (c == NPH - 1 && swap_now) flush(dE);
       __syncthreads();
     }
     pending = swap_now;
@@ -981,18 +986,28 @@ __global__ __launch_bounds__(64 * kPTMaxWaves) void pt_kernel(const PTDev *__res
   __syncthreads();
   const int mode = (P.F <= kPTByteF) ? kPTBytes : (P.F <= kMidF ? kPTSwar : kPTWide);
   const uint32_t *sp = staged ? spk : nullptr;
+  // three phases only where the host merged two classes (byte mode, ME kinds)
   if (P.kind == kKindME) {
-    if (mode == kPTBytes) pt_ladder<kKindME, kPTBytes>(P, rec, lat, mtab, st8, E, rep_at, slot_of, acc, swapw, sp);
-    else if (mode == kPTSwar) pt_ladder<kKindME, kPTSwar>(P, rec, lat, mtab, st8, E, rep_at, slot_of, acc, swapw, sp);
-    else pt_ladder<kKindME, kPTWide>(P, rec, lat, mtab, st8, E, rep_at, slot_of, acc, swapw, sp);
+    if (mode == kPTBytes && P.nph == 3)
+      pt_ladder<kKindME, kPTBytes, 3>(P, rec, lat, mtab, st8, E, rep_at, slot_of, acc, swapw, sp);
+    else if (mode == kPTBytes)
+      pt_ladder<kKindME, kPTBytes, 4>(P, rec, lat, mtab, st8, E, rep_at, slot_of, acc, swapw, sp);
+    else if (mode == kPTSwar)
+      pt_ladder<kKindME, kPTSwar, 4>(P, rec, lat, mtab, st8, E, rep_at, slot_of, acc, swapw, sp);
+    else pt_ladder<kKindME, kPTWide, 4>(P, rec, lat, mtab, st8, E, rep_at, slot_of, acc, swapw, sp);
   } else if (P.kind == kKindLHZ) {
-    if (mode == kPTBytes) pt_ladder<kKindLHZ, kPTBytes>(P, rec, lat, mtab, st8, E, rep_at, slot_of, acc, swapw, sp);
-    else if (mode == kPTSwar) pt_ladder<kKindLHZ, kPTSwar>(P, rec, lat, mtab, st8, E, rep_at, slot_of, acc, swapw, sp);
-    else pt_ladder<kKindLHZ, kPTWide>(P, rec, lat, mtab, st8, E, rep_at, slot_of, acc, swapw, sp);
+    if (mode == kPTBytes) pt_ladder<kKindLHZ, kPTBytes, 4>(P, rec, lat, mtab, st8, E, rep_at, slot_of, acc, swapw, sp);
+    else if (mode == kPTSwar)
+      pt_ladder<kKindLHZ, kPTSwar, 4>(P, rec, lat, mtab, st8, E, rep_at, slot_of, acc, swapw, sp);
+    else pt_ladder<kKindLHZ, kPTWide, 4>(P, rec, lat, mtab, st8, E, rep_at, slot_of, acc, swapw, sp);
   } else {
-    if (mode == kPTBytes) pt_ladder<kKindMEC, kPTBytes>(P, rec, lat, mtab, st8, E, rep_at, slot_of, acc, swapw, sp);
-    else if (mode == kPTSwar) pt_ladder<kKindMEC, kPTSwar>(P, rec, lat, mtab, st8, E, rep_at, slot_of, acc, swapw, sp);
-    else pt_ladder<kKindMEC, kPTWide>(P, rec, lat, mtab, st8, E, rep_at, slot_of, acc, swapw, sp);
+    if (mode == kPTBytes && P.nph == 3)
+      pt_ladder<kKindMEC, kPTBytes, 3>(P, rec, lat, mtab, st8, E, rep_at, slot_of, acc, swapw, sp);
+    else if (mode == kPTBytes)
+      pt_ladder<kKindMEC, kPTBytes, 4>(P, rec, lat, mtab, st8, E, rep_at, slot_of, acc, swapw, sp);
+    else if (mode == kPTSwar)
+      pt_ladder<kKindMEC, kPTSwar, 4>(P, rec, lat, mtab, st8, E, rep_at, slot_of, acc, swapw, sp);
+    else pt_ladder<kKindMEC, kPTWide, 4>(P, rec, lat, mtab, st8, E, rep_at, slot_of, acc, swapw, sp);
   }
   // results: spins by replica in physical order, energies by replica, slot map, swap counts
   for (size_t i = tid; i < static_cast<size_t>(P.R) * P.n; i += nth) {

@@ -43,6 +43,8 @@ struct PTDev {
   int32_t swap_falling;     // rows non-increasing in D: 1 bounds, 2 bounds by bisection only; 0 table reads
   uint32_t seed_lo, seed_hi;
   int32_t cls[5];
+  int32_t nph;              // sweep phases: 4 (the colour classes) or 3 (byte mode, two classes merged)
+  int32_t ph[5];            // phase c: device sites [ph[c], ph[c + 1])
 };
 
 }  // namespace sqa
