@@ -69,6 +69,45 @@ __device__ __forceinline__ Words4 philox4x32_10(uint32_t x0, uint32_t x1, uint32
   return philox_words(st);
 }
 
+// Philox4x32 on counters (site, x1, x2, x3) whose words x1..x3 and key are
+// fixed over many sites: in the first two rounds only the products with the
+// site depend on it, so the rest is prepared once (philox_two_prep) and each
+// site's state after two rounds costs two multiplies and three XORs
+// (philox_two).
+struct PhiloxTwo {
+  uint32_t c1;       // x3 ^ key1: round 1's x2 = hi(A site) ^ c1
+  uint32_t c2;       // lo(B x2) ^ (key0 + Weyl0): round 2's x0 = hi(B x2') ^ c2
+  uint32_t d;        // hi(A x0') ^ (key1 + Weyl1), x0' = hi(B x2) ^ x1 ^ key0: round 2's x2 = d ^ lo(A site)
+  uint32_t l;        // lo(A x0'): round 2's x3
+  uint32_t k0, k1;   // the key after two rounds
+};
+
+__device__ __forceinline__ PhiloxTwo philox_two_prep(uint32_t x1, uint32_t x2, uint32_t x3, uint32_t key0,
+                                                     uint32_t key1) {
+  constexpr uint32_t kMulA = 0xD2511F53u, kMulB = 0xCD9E8D57u;
+  constexpr uint32_t kWeylA = 0x9E3779B9u, kWeylB = 0xBB67AE85u;
+  const uint64_t pb = static_cast<uint64_t>(kMulB) * x2;
+  const uint32_t x0 = static_cast<uint32_t>(pb >> 32) ^ x1 ^ key0;
+  const uint64_t pa2 = static_cast<uint64_t>(kMulA) * x0;
+  PhiloxTwo w;
+  w.c1 = x3 ^ key1;
+  w.c2 = static_cast<uint32_t>(pb) ^ (key0 + kWeylA);
+  w.d = static_cast<uint32_t>(pa2 >> 32) ^ (key1 + kWeylB);
+  w.l = static_cast<uint32_t>(pa2);
+  w.k0 = key0 + 2u * kWeylA;
+  w.k1 = key1 + 2u * kWeylB;
+  return w;
+}
+
+__device__ __forceinline__ PhiloxState philox_two(uint32_t site, const PhiloxTwo &w) {
+  constexpr uint32_t kMulA = 0xD2511F53u, kMulB = 0xCD9E8D57u;
+  const uint64_t pa = static_cast<uint64_t>(kMulA) * site;
+  const uint32_t x2 = static_cast<uint32_t>(pa >> 32) ^ w.c1;
+  const uint64_t pb = static_cast<uint64_t>(kMulB) * x2;
+  return PhiloxState{static_cast<uint32_t>(pb >> 32) ^ w.c2, static_cast<uint32_t>(pb), w.d ^ static_cast<uint32_t>(pa),
+                     w.l, w.k0, w.k1};
+}
+
 // Orders LDS accesses of one wavefront around a phase boundary.  A wave's LDS
 // operations are executed in program order, so only the compiler needs fencing.
 __device__ __forceinline__ void wave_sync() {

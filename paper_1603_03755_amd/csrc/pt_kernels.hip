@@ -241,42 +241,12 @@ __device__ __forceinline__ void pt_item_bytes_decide(PTKey K, uint32_t site, int
 // 4 and 6, 5 and 7).  Every site is an item of every replica byte once per
 // sweep, so over k sweeps the sum for replica w less 4F n k (n sites) is the
 // sum of V_w - 4F over its flips: twice its energy change.
-// The item stream's counter is (site, replica byte a, sweep m, PT << 24).  In
-// the first two Philox rounds only the products with the site depend on the
-// item: what depends on (a, m) and the key alone is computed once per thread
-// and sweep (uniform parts in scalar registers).
-struct PTSweepWords {
-  uint32_t c1;   // (PT << 24) ^ key1: round 1's x2 = hi(A site) ^ c1
-  uint32_t c2;   // lo(B m) ^ (key0 + Weyl0): round 2's x0 = hi(B x2) ^ c2
-  uint32_t d;    // hi(A x0') ^ (key1 + Weyl1), x0' = hi(B m) ^ a ^ key0: round 2's x2 = d ^ lo(A site)
-  uint32_t l;    // lo(A x0'): round 2's x3
-  uint32_t k0, k1;   // the key after two rounds
-};
+// The item stream's counter is (site, replica byte a, sweep m, PT << 24): its
+// first two rounds prepared once per thread and sweep (philox_two_prep).
+using PTSweepWords = PhiloxTwo;
 
 __device__ __forceinline__ PTSweepWords pt_sweep_words(PTKey K, int a, uint32_t m) {
-  constexpr uint32_t kA = 0xD2511F53u, kB = 0xCD9E8D57u;   // Philox4x32 multipliers
-  constexpr uint32_t kW0 = 0x9E3779B9u, kW1 = 0xBB67AE85u; // and Weyl increments
-  const uint64_t pb = static_cast<uint64_t>(kB) * m;
-  const uint32_t x0 = static_cast<uint32_t>(pb >> 32) ^ static_cast<uint32_t>(a) ^ K.lo;
-  const uint64_t pa2 = static_cast<uint64_t>(kA) * x0;
-  PTSweepWords w;
-  w.c1 = (kStreamPT << 24) ^ K.hi;
-  w.c2 = static_cast<uint32_t>(pb) ^ (K.lo + kW0);
-  w.d = static_cast<uint32_t>(pa2 >> 32) ^ (K.hi + kW1);
-  w.l = static_cast<uint32_t>(pa2);
-  w.k0 = K.lo + 2u * kW0;
-  w.k1 = K.hi + 2u * kW1;
-  return w;
-}
-
-// The Philox state of item (site, a, m) after two rounds.
-__device__ __forceinline__ PhiloxState pt_philox_two(uint32_t site, const PTSweepWords &w) {
-  constexpr uint32_t kA = 0xD2511F53u, kB = 0xCD9E8D57u;
-  const uint64_t pa = static_cast<uint64_t>(kA) * site;
-  const uint32_t x2 = static_cast<uint32_t>(pa >> 32) ^ w.c1;
-  const uint64_t pb = static_cast<uint64_t>(kB) * x2;
-  return PhiloxState{static_cast<uint32_t>(pb >> 32) ^ w.c2, static_cast<uint32_t>(pb), w.d ^ static_cast<uint32_t>(pa),
-                     w.l, w.k0, w.k1};
+  return philox_two_prep(static_cast<uint32_t>(a), m, kStreamPT << 24, K.lo, K.hi);
 }
 
 // The temperature-free front of a byte-mode item: own and partner bytes, the
@@ -293,7 +263,7 @@ __device__ __forceinline__ uint2 pt_item_front(const PTSweepWords &sw, const Sig
 #pragma unroll
   for (int i = 0; i < S::T * S::P; ++i) pbyte[i] = latb[sr.poff[i] + a];
   __builtin_amdgcn_sched_barrier(0);
-  ps = pt_philox_two(sr.site, sw);
+  ps = philox_two(sr.site, sw);
   philox_rounds<1>(ps);
   philox_pin(ps);
   asm volatile("" : "+v"(own));                   // nothing derived from own ahead of the rounds

@@ -470,7 +470,18 @@ __device__ __forceinline__ uint64_t ring_cluster(uint64_t jn, int t0, int L) {
   return t0 ? (((cr << t0) | (cr >> (L - t0))) & full) : cr;
 }
 
-template <int KIND, bool LARGE>
+// The same for L = 64 (rotations by t0 without masks).
+__device__ __forceinline__ uint64_t ring_cluster64(uint64_t jn, int t0) {
+  const uint64_t r = (jn >> t0) | (jn << ((64 - t0) & 63));   // bond t0 at bit 0
+  if (r == ~0ull) return ~0ull;
+  const int f = __builtin_ctzll(~r);                         // joined bonds forward of t0
+  const int g = __builtin_clzll(~r);                         // joined bonds backward of t0
+  uint64_t cr = (2ull << f) - 1ull;                          // slices t0 .. t0+f
+  if (g) cr |= ~(~0ull >> g);                                // slices t0-g .. t0-1
+  return (cr << t0) | (cr >> ((64 - t0) & 63));
+}
+
+template <int KIND, bool LARGE, bool L64>
 __device__ __forceinline__ void wolff_bonds(const HandleDev &H, const uint32_t *__restrict__ rec, const uint64_t *lat,
                                             uint32_t *scr, const uint2 *stab, int lo, int nc, uint32_t m, uint32_t c3,
                                             uint32_t padd, int lane) {
@@ -481,11 +492,8 @@ __device__ __forceinline__ void wolff_bonds(const HandleDev &H, const uint32_t *
   const uint8_t *latb = reinterpret_cast<const uint8_t *>(lat);
   uint8_t *jb = reinterpret_cast<uint8_t *>(scr);        // [nc] 64-bit join masks
   uint32_t *sb = scr + 2 * nc;                            // [16][nc] S bytes of slices 4i..4i+3
-  const int dq = 64 / nc, dr = 64 - dq * nc;
-  int q = lane / nc;
-  int j = lane - q * nc;
-  for (int it = lane; it < cnt; it += 64, j += dr, q += dq) {
-    if (j >= nc) { j -= nc; q += 1; }
+  // item it = q nc + j: site lo + j, slices 8q .. 8q + 7
+  auto item = [&](int it, int j, int q) {
     const int d = lo + j;
     const uint32_t *r = rec + d * S::RW;
     uint32_t site, wts = 0, wts2 = 0, hw = 0, neg = 0;
@@ -530,13 +538,25 @@ __device__ __forceinline__ void wolff_bonds(const HandleDev &H, const uint32_t *
     __builtin_amdgcn_sched_barrier(0);
     const Words4 u = philox4x32_10(site, static_cast<uint32_t>(q), m, c3, H.seed_lo, H.seed_hi);
     __builtin_amdgcn_sched_barrier(0);
-    const int sh = 8 * q;
-    const uint32_t own = static_cast<uint32_t>(w >> sh) & 0xFFu;
-    // bit tau of nx: the spin of slice tau + 1 (mod L)
-    const uint64_t nx = (w >> 1) | ((w & 1ull) << (L - 1));
-    const uint32_t nb = static_cast<uint32_t>(nx >> sh) & 0xFFu;
-    const uint32_t valid = (L - sh >= 8) ? 0xFFu : ((1u << (L - sh)) - 1u);
-    const uint32_t eq = ~(own ^ nb) & valid;
+    uint32_t own, eq;                               // the byte's spins; its bonds between equal spins
+    if constexpr (L64) {
+      // bytes q < 4 in the low word, q >= 4 in the high one; the next slices are
+      // a funnel shift by one (slice 63's next is slice 0, bit 0 of the low word)
+      const uint32_t lo32 = static_cast<uint32_t>(w), hi32 = static_cast<uint32_t>(w >> 32);
+      const bool upper = q >= 4;
+      const uint32_t wa = upper ? hi32 : lo32, wb = upper ? lo32 : hi32;
+      const uint32_t s8 = static_cast<uint32_t>(8 * q) & 31u;
+      own = __builtin_amdgcn_ubfe(wa, s8, 8);
+      eq = ~(own ^ __builtin_amdgcn_alignbit(wb, wa, s8 + 1u)) & 0xFFu;
+    } else {
+      const int sh = 8 * q;
+      own = static_cast<uint32_t>(w >> sh) & 0xFFu;
+      // bit tau of nx: the spin of slice tau + 1 (mod L)
+      const uint64_t nx = (w >> 1) | ((w & 1ull) << (L - 1));
+      const uint32_t nb = static_cast<uint32_t>(nx >> sh) & 0xFFu;
+      const uint32_t valid = (L - sh >= 8) ? 0xFFu : ((1u << (L - sh)) - 1u);
+      eq = ~(own ^ nb) & valid;
+    }
 
     // bond 8q+k: uniform (hi << 16) | lo, hi = half k >> 2 of word k & 3 of the
     // WOLFF call (site, q, sweep), lo the same from the WOLFF_LO call, drawn only
@@ -569,8 +589,8 @@ __device__ __forceinline__ void wolff_bonds(const HandleDev &H, const uint32_t *
       // 4 S of the eight slices, one byte each (F <= 63), from the record's
       // signed weights: slices 8q..8q+3 in word 2q, 8q+4..8q+7 in word 2q+1
       const uint2 a = signed_sums<KIND>(sr, stab + kSpreadEntries, own, pbyte);
-      sb[(2 * q) * nc + j] = a.x;
-      sb[(2 * q + 1) * nc + j] = a.y;
+      sb[2 * it - j] = a.x;                           // (2q) nc + j, with it = q nc + j
+      sb[2 * it - j + nc] = a.y;
     } else {
       // S of the eight slices in 8-bit fields, three slices per word (acc_lo
       // 0-2, acc_hi 3-5, acc_x 6-7; the operands of the 24-bit multiplies stay
@@ -591,16 +611,29 @@ __device__ __forceinline__ void wolff_bonds(const HandleDev &H, const uint32_t *
         acc_hi += __umul24(spread3(xt >> 3), wt);
         acc_x += __umul24(spread3(xt >> 6), wt);
       }
-      sb[(2 * q) * nc + j] = (acc_lo & 0xFFFFFFu) | (acc_hi << 24);
-      sb[(2 * q + 1) * nc + j] = ((acc_hi >> 8) & 0xFFFFu) | (acc_x << 16);
+      sb[2 * it - j] = (acc_lo & 0xFFFFFFu) | (acc_hi << 24);
+      sb[2 * it - j + nc] = ((acc_hi >> 8) & 0xFFFFu) | (acc_x << 16);
+    }
+  };
+  if (L64 && nc == 64) {
+    // a full chunk: lane j takes site j, and the byte q is the same in every lane
+    // (a uniform loop counter, so its part of the counter words stays scalar)
+    for (int q = 0; q < 8; ++q) item(64 * q + lane, lane, q);
+  } else {
+    const int dq = 64 / nc, dr = 64 - dq * nc;
+    int q = lane / nc;
+    int j = lane - q * nc;
+    for (int it = lane; it < cnt; it += 64, j += dr, q += dq) {
+      if (j >= nc) { j -= nc; q += 1; }
+      item(it, j, q);
     }
   }
 }
 
-template <int KIND, bool LARGE>
+template <int KIND, bool LARGE, bool L64>
 __device__ __forceinline__ void wolff_flips(const HandleDev &H, const uint32_t *__restrict__ rec, uint64_t *lat,
-                                            const uint32_t *scr, const uint2 *stab, int lo, int nc, uint32_t m,
-                                            uint32_t c3, const uint32_t *arow, int lane) {
+                                            const uint32_t *scr, const uint2 *stab, int lo, int nc,
+                                            const PhiloxTwo &sw2, const uint32_t *arow, int lane) {
   using S = Site<KIND>;
   const int L = H.L;
   const uint64_t *jw = reinterpret_cast<const uint64_t *>(scr);
@@ -622,21 +655,32 @@ __device__ __forceinline__ void wolff_flips(const HandleDev &H, const uint32_t *
            : (KIND == kKindLHZ) ? __builtin_amdgcn_sad_u8(r1, 0u, r2 & 0xFFu)
                                 : __builtin_amdgcn_sad_u8(r1, 0u, __builtin_amdgcn_sad_u8(r2 & 0xFFFFFFu, 0u, 0u));
     }
-    const Words4 u = philox4x32_10(site, kWolffSiteCtr, m, c3, H.seed_lo, H.seed_hi);
+    PhiloxState ps = philox_two(site, sw2);
+    philox_rounds<8>(ps);
+    const Words4 u = philox_words(ps);
     const int t0 = static_cast<int>(__umulhi(u.v[0], static_cast<uint32_t>(L)));
-    const uint64_t cl = ring_cluster(jw[j], t0, L);
+    const uint64_t cl = L64 ? ring_cluster64(jw[j], t0) : ring_cluster(jw[j], t0, L);
     const uint32_t clh[2] = {static_cast<uint32_t>(cl), static_cast<uint32_t>(cl >> 32)};
     uint32_t ssum;
     if constexpr (!LARGE) {
       // bytes of 4 S, masked by the spreads (value 4 per slice) of each cluster
       // byte: the dot products sum 16 S over the cluster
       const uint2 *st8 = stab + kSpreadEntries;
-      const int Q = (L + 7) >> 3;
       uint32_t s16 = 0;
-      for (int k = 0; k < Q; ++k) {
-        const uint2 mk = st8[(clh[k >> 2] >> (8 * (k & 3))) & 0xFFu];
-        s16 = __builtin_amdgcn_udot4(sb[(2 * k) * nc + j], mk.x, s16, false);
-        s16 = __builtin_amdgcn_udot4(sb[(2 * k + 1) * nc + j], mk.y, s16, false);
+      if constexpr (L64) {      // eight cluster bytes: every read issued before the sums
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const uint2 mk = st8[(clh[k >> 2] >> (8 * (k & 3))) & 0xFFu];
+          s16 = __builtin_amdgcn_udot4(sb[(2 * k) * nc + j], mk.x, s16, false);
+          s16 = __builtin_amdgcn_udot4(sb[(2 * k + 1) * nc + j], mk.y, s16, false);
+        }
+      } else {
+        const int Q = (L + 7) >> 3;
+        for (int k = 0; k < Q; ++k) {
+          const uint2 mk = st8[(clh[k >> 2] >> (8 * (k & 3))) & 0xFFu];
+          s16 = __builtin_amdgcn_udot4(sb[(2 * k) * nc + j], mk.x, s16, false);
+          s16 = __builtin_amdgcn_udot4(sb[(2 * k + 1) * nc + j], mk.y, s16, false);
+        }
       }
       ssum = s16 >> 4;
     } else {
@@ -646,7 +690,9 @@ __device__ __forceinline__ void wolff_flips(const HandleDev &H, const uint32_t *
         ssum = __builtin_amdgcn_udot4(sb[i * nc + j], spread8(clh[i >> 3] >> (4 * (i & 7))), ssum, false);
     }
     const int a = __popcll(cl) * static_cast<int>(fs) - 2 * static_cast<int>(ssum);
-    if (min(u.v[1], 0xFFFFFFFEu) < arow[a]) lat[d] ^= cl;
+    // (a global load: the table row is read in place)
+    const uint32_t thr = ((const __attribute__((address_space(1))) uint32_t *)arow)[a];
+    if (min(u.v[1], 0xFFFFFFFEu) < thr) lat[d] ^= cl;
   }
 }
 
@@ -659,6 +705,8 @@ __device__ __forceinline__ void wolff_replica(const HandleDev &H, const uint32_t
   const uint32_t c3 = (kStreamWolff << 24) | static_cast<uint32_t>(rep);
   for (int m = H.m0; m < H.m1; ++m) {
     const uint32_t padd = H.table[m];
+    // the site call's counter (site, kWolffSiteCtr, m, c3): its first two rounds' site-free part
+    const PhiloxTwo sw2 = philox_two_prep(kWolffSiteCtr, static_cast<uint32_t>(m), c3, H.seed_lo, H.seed_hi);
     const uint32_t *arow = H.wacc + static_cast<size_t>(H.wrows > 1 ? m : 0) * H.wwidth + H.L * H.F;
     // each colour class in chunks of at most 64 sites (one lane per site in
     // phase 2; sites of a class commute, so chunking does not change results)
@@ -667,13 +715,17 @@ __device__ __forceinline__ void wolff_replica(const HandleDev &H, const uint32_t
         const int nc = min(kWolffChunk, H.cls[c + 1] - lo);
         const uint32_t mm = static_cast<uint32_t>(m);
         if (H.F > kMidF) {
-          wolff_bonds<KIND, true>(H, rec, lat, scr, stab, lo, nc, mm, c3, padd, lane);
+          wolff_bonds<KIND, true, false>(H, rec, lat, scr, stab, lo, nc, mm, c3, padd, lane);
           wave_sync();
-          wolff_flips<KIND, true>(H, rec, lat, scr, stab, lo, nc, mm, c3, arow, lane);
+          wolff_flips<KIND, true, false>(H, rec, lat, scr, stab, lo, nc, sw2, arow, lane);
+        } else if (H.L == 64) {
+          wolff_bonds<KIND, false, true>(H, rec, lat, scr, stab, lo, nc, mm, c3, padd, lane);
+          wave_sync();
+          wolff_flips<KIND, false, true>(H, rec, lat, scr, stab, lo, nc, sw2, arow, lane);
         } else {
-          wolff_bonds<KIND, false>(H, rec, lat, scr, stab, lo, nc, mm, c3, padd, lane);
+          wolff_bonds<KIND, false, false>(H, rec, lat, scr, stab, lo, nc, mm, c3, padd, lane);
           wave_sync();
-          wolff_flips<KIND, false>(H, rec, lat, scr, stab, lo, nc, mm, c3, arow, lane);
+          wolff_flips<KIND, false, false>(H, rec, lat, scr, stab, lo, nc, sw2, arow, lane);
         }
         wave_sync();
       }
