@@ -493,7 +493,8 @@ __device__ __forceinline__ void wolff_bonds(const HandleDev &H, const uint32_t *
   uint8_t *jb = reinterpret_cast<uint8_t *>(scr);        // [nc] 64-bit join masks
   uint32_t *sb = scr + 2 * nc;                            // [16][nc] S bytes of slices 4i..4i+3
   // item it = q nc + j: site lo + j, slices 8q .. 8q + 7
-  auto item = [&](int it, int j, int q) {
+  // pq: the site-free part of the item call's first two rounds (counter (site, q, m, c3))
+  auto item = [&](int it, int j, int q, const PhiloxTwo &pq) {
     const int d = lo + j;
     const uint32_t *r = rec + d * S::RW;
     uint32_t site, wts = 0, wts2 = 0, hw = 0, neg = 0;
@@ -536,7 +537,9 @@ __device__ __forceinline__ void wolff_bonds(const HandleDev &H, const uint32_t *
 #pragma unroll
     for (int i = 0; i < S::T * S::P; ++i) pbyte[i] = lb[poff[i]];
     __builtin_amdgcn_sched_barrier(0);
-    const Words4 u = philox4x32_10(site, static_cast<uint32_t>(q), m, c3, H.seed_lo, H.seed_hi);
+    PhiloxState ps = philox_two(site, pq);
+    philox_rounds<8>(ps);
+    const Words4 u = philox_words(ps);
     __builtin_amdgcn_sched_barrier(0);
     uint32_t own, eq;                               // the byte's spins; its bonds between equal spins
     if constexpr (L64) {
@@ -618,14 +621,17 @@ __device__ __forceinline__ void wolff_bonds(const HandleDev &H, const uint32_t *
   if (L64 && nc == 64) {
     // a full chunk: lane j takes site j, and the byte q is the same in every lane
     // (a uniform loop counter, so its part of the counter words stays scalar)
-    for (int q = 0; q < 8; ++q) item(64 * q + lane, lane, q);
+    for (int q = 0; q < 8; ++q) {
+      const int qs = __builtin_amdgcn_readfirstlane(q);   // uniform: its two-round part in scalar registers
+      item(64 * qs + lane, lane, qs, philox_two_prep(static_cast<uint32_t>(qs), m, c3, H.seed_lo, H.seed_hi));
+    }
   } else {
     const int dq = 64 / nc, dr = 64 - dq * nc;
     int q = lane / nc;
     int j = lane - q * nc;
     for (int it = lane; it < cnt; it += 64, j += dr, q += dq) {
       if (j >= nc) { j -= nc; q += 1; }
-      item(it, j, q);
+      item(it, j, q, philox_two_prep(static_cast<uint32_t>(q), m, c3, H.seed_lo, H.seed_hi));
     }
   }
 }
