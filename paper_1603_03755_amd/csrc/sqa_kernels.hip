@@ -674,11 +674,23 @@ __device__ __forceinline__ void wolff_flips(const HandleDev &H, const uint32_t *
       const uint2 *st8 = stab + kSpreadEntries;
       uint32_t s16 = 0;
       if constexpr (L64) {      // eight cluster bytes: every read issued before the sums
+        // (a full chunk's stride is a constant: the sums' reads take immediate offsets)
+        const uint32_t *sbj = sb + j;
+        uint2 mk[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          const uint2 mk = st8[(clh[k >> 2] >> (8 * (k & 3))) & 0xFFu];
-          s16 = __builtin_amdgcn_udot4(sb[(2 * k) * nc + j], mk.x, s16, false);
-          s16 = __builtin_amdgcn_udot4(sb[(2 * k + 1) * nc + j], mk.y, s16, false);
+        for (int k = 0; k < 8; ++k) mk[k] = st8[(clh[k >> 2] >> (8 * (k & 3))) & 0xFFu];
+        if (nc == kWolffChunk) {
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            s16 = __builtin_amdgcn_udot4(sbj[(2 * k) * kWolffChunk], mk[k].x, s16, false);
+            s16 = __builtin_amdgcn_udot4(sbj[(2 * k + 1) * kWolffChunk], mk[k].y, s16, false);
+          }
+        } else {
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            s16 = __builtin_amdgcn_udot4(sbj[(2 * k) * nc], mk[k].x, s16, false);
+            s16 = __builtin_amdgcn_udot4(sbj[(2 * k + 1) * nc], mk[k].y, s16, false);
+          }
         }
       } else {
         const int Q = (L + 7) >> 3;
