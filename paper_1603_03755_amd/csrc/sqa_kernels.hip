@@ -494,14 +494,15 @@ __device__ __forceinline__ void wolff_bonds(const HandleDev &H, const uint32_t *
   uint32_t *sb = scr + 2 * nc;                            // [16][nc] S bytes of slices 4i..4i+3
   // item it = q nc + j: site lo + j, slices 8q .. 8q + 7
   // pq: the site-free part of the item call's first two rounds (counter (site, q, m, c3))
-  auto item = [&](int it, int j, int q, const PhiloxTwo &pq) {
+  // srp, wp: the site's record and lattice word when the caller has them
+  auto item = [&](int it, int j, int q, const PhiloxTwo &pq, const SignedRec<KIND> *srp, const uint64_t *wp) {
     const int d = lo + j;
     const uint32_t *r = rec + d * S::RW;
     uint32_t site, wts = 0, wts2 = 0, hw = 0, neg = 0;
     uint32_t poff[S::T * S::P];
     SignedRec<KIND> sr;
     if constexpr (!LARGE) {
-      sr = load_signed_rec<KIND>(r);
+      sr = srp ? *srp : load_signed_rec<KIND>(r);
       site = sr.site;
 #pragma unroll
       for (int x = 0; x < S::T * S::P; ++x) poff[x] = sr.poff[x];
@@ -530,7 +531,7 @@ __device__ __forceinline__ void wolff_bonds(const HandleDev &H, const uint32_t *
         poff[2 * x + 1] = pw[x] >> 16;
       }
     }
-    const uint64_t w = lat[d];
+    const uint64_t w = wp ? *wp : lat[d];
     // partner bytes of the terms (LDS reads) stay in flight during the Philox rounds
     const uint8_t *lb = latb + q;
     uint32_t pbyte[S::T * S::P];
@@ -621,9 +622,14 @@ __device__ __forceinline__ void wolff_bonds(const HandleDev &H, const uint32_t *
   if (L64 && nc == 64) {
     // a full chunk: lane j takes site j, and the byte q is the same in every lane
     // (a uniform loop counter, so its part of the counter words stays scalar)
+    // (the site's record and lattice word are read once for its eight bytes)
+    SignedRec<KIND> sr0{};
+    if constexpr (!LARGE) sr0 = load_signed_rec<KIND>(rec + (lo + lane) * S::RW);
+    const uint64_t w0 = lat[lo + lane];
     for (int q = 0; q < 8; ++q) {
       const int qs = __builtin_amdgcn_readfirstlane(q);   // uniform: its two-round part in scalar registers
-      item(64 * qs + lane, lane, qs, philox_two_prep(static_cast<uint32_t>(qs), m, c3, H.seed_lo, H.seed_hi));
+      item(64 * qs + lane, lane, qs, philox_two_prep(static_cast<uint32_t>(qs), m, c3, H.seed_lo, H.seed_hi),
+           LARGE ? nullptr : &sr0, &w0);
     }
   } else {
     const int dq = 64 / nc, dr = 64 - dq * nc;
@@ -631,7 +637,7 @@ __device__ __forceinline__ void wolff_bonds(const HandleDev &H, const uint32_t *
     int j = lane - q * nc;
     for (int it = lane; it < cnt; it += 64, j += dr, q += dq) {
       if (j >= nc) { j -= nc; q += 1; }
-      item(it, j, q, philox_two_prep(static_cast<uint32_t>(q), m, c3, H.seed_lo, H.seed_hi));
+      item(it, j, q, philox_two_prep(static_cast<uint32_t>(q), m, c3, H.seed_lo, H.seed_hi), nullptr, nullptr);
     }
   }
 }
