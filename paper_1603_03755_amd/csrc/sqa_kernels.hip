@@ -484,7 +484,7 @@ __device__ __forceinline__ uint64_t ring_cluster64(uint64_t jn, int t0) {
 template <int KIND, bool LARGE, bool L64>
 __device__ __forceinline__ void wolff_bonds(const HandleDev &H, const uint32_t *__restrict__ rec, const uint64_t *lat,
                                             uint32_t *scr, const uint2 *stab, int lo, int nc, uint32_t m, uint32_t c3,
-                                            uint32_t padd, int lane) {
+                                            uint32_t padd, const PhiloxTwo &pql, int lane) {
   using S = Site<KIND>;
   const int L = H.L;
   const int Q = (L + 7) >> 3;
@@ -492,10 +492,11 @@ __device__ __forceinline__ void wolff_bonds(const HandleDev &H, const uint32_t *
   const uint8_t *latb = reinterpret_cast<const uint8_t *>(lat);
   uint8_t *jb = reinterpret_cast<uint8_t *>(scr);        // [nc] 64-bit join masks
   uint32_t *sb = scr + 2 * nc;                            // [16][nc] S bytes of slices 4i..4i+3
-  // item it = q nc + j: site lo + j, slices 8q .. 8q + 7
+  // item (j, q): site lo + j, slices 8q .. 8q + 7; its S bytes go to words 2q nc + j
+  // and (2q + 1) nc + j of sb
   // pq: the site-free part of the item call's first two rounds (counter (site, q, m, c3))
   // srp, wp: the site's record and lattice word when the caller has them
-  auto item = [&](int it, int j, int q, const PhiloxTwo &pq, const SignedRec<KIND> *srp, const uint64_t *wp) {
+  auto item = [&](int j, int q, const PhiloxTwo &pq, const SignedRec<KIND> *srp, const uint64_t *wp) {
     const int d = lo + j;
     const uint32_t *r = rec + d * S::RW;
     uint32_t site, wts = 0, wts2 = 0, hw = 0, neg = 0;
@@ -593,8 +594,8 @@ __device__ __forceinline__ void wolff_bonds(const HandleDev &H, const uint32_t *
       // 4 S of the eight slices, one byte each (F <= 63), from the record's
       // signed weights: slices 8q..8q+3 in word 2q, 8q+4..8q+7 in word 2q+1
       const uint2 a = signed_sums<KIND>(sr, stab + kSpreadEntries, own, pbyte);
-      sb[2 * it - j] = a.x;                           // (2q) nc + j, with it = q nc + j
-      sb[2 * it - j + nc] = a.y;
+      sb[2 * q * nc + j] = a.x;
+      sb[2 * q * nc + j + nc] = a.y;
     } else {
       // S of the eight slices in 8-bit fields, three slices per word (acc_lo
       // 0-2, acc_hi 3-5, acc_x 6-7; the operands of the 24-bit multiplies stay
@@ -615,8 +616,8 @@ __device__ __forceinline__ void wolff_bonds(const HandleDev &H, const uint32_t *
         acc_hi += __umul24(spread3(xt >> 3), wt);
         acc_x += __umul24(spread3(xt >> 6), wt);
       }
-      sb[2 * it - j] = (acc_lo & 0xFFFFFFu) | (acc_hi << 24);
-      sb[2 * it - j + nc] = ((acc_hi >> 8) & 0xFFFFu) | (acc_x << 16);
+      sb[2 * q * nc + j] = (acc_lo & 0xFFFFFFu) | (acc_hi << 24);
+      sb[2 * q * nc + j + nc] = ((acc_hi >> 8) & 0xFFFFu) | (acc_x << 16);
     }
   };
   if (L64 && nc == 64) {
@@ -628,16 +629,21 @@ __device__ __forceinline__ void wolff_bonds(const HandleDev &H, const uint32_t *
     const uint64_t w0 = lat[lo + lane];
     for (int q = 0; q < 8; ++q) {
       const int qs = __builtin_amdgcn_readfirstlane(q);   // uniform: its two-round part in scalar registers
-      item(64 * qs + lane, lane, qs, philox_two_prep(static_cast<uint32_t>(qs), m, c3, H.seed_lo, H.seed_hi),
+      item(lane, qs, philox_two_prep(static_cast<uint32_t>(qs), m, c3, H.seed_lo, H.seed_hi),
            LARGE ? nullptr : &sr0, &w0);
     }
+  } else if (L64) {
+    // a partial chunk: items site-major (8 j + q), so a lane keeps the byte
+    // q = lane & 7, whose two-round part the caller prepared once per sweep (pql),
+    // and the eight lanes of a site read the same partner words
+    for (int it = lane; it < cnt; it += 64) item(it >> 3, lane & 7, pql, nullptr, nullptr);
   } else {
     const int dq = 64 / nc, dr = 64 - dq * nc;
     int q = lane / nc;
     int j = lane - q * nc;
     for (int it = lane; it < cnt; it += 64, j += dr, q += dq) {
       if (j >= nc) { j -= nc; q += 1; }
-      item(it, j, q, philox_two_prep(static_cast<uint32_t>(q), m, c3, H.seed_lo, H.seed_hi), nullptr, nullptr);
+      item(j, q, philox_two_prep(static_cast<uint32_t>(q), m, c3, H.seed_lo, H.seed_hi), nullptr, nullptr);
     }
   }
 }
@@ -731,6 +737,9 @@ __device__ __forceinline__ void wolff_replica(const HandleDev &H, const uint32_t
     const uint32_t padd = H.table[m];
     // the site call's counter (site, kWolffSiteCtr, m, c3): its first two rounds' site-free part
     const PhiloxTwo sw2 = philox_two_prep(kWolffSiteCtr, static_cast<uint32_t>(m), c3, H.seed_lo, H.seed_hi);
+    // the bond calls of a lane's byte lane & 7 in partial chunks (L = 64): the same per sweep
+    const PhiloxTwo pql = philox_two_prep(static_cast<uint32_t>(lane & 7), static_cast<uint32_t>(m), c3, H.seed_lo,
+                                          H.seed_hi);
     const uint32_t *arow = H.wacc + static_cast<size_t>(H.wrows > 1 ? m : 0) * H.wwidth + H.L * H.F;
     // each colour class in chunks of at most 64 sites (one lane per site in
     // phase 2; sites of a class commute, so chunking does not change results)
@@ -739,15 +748,15 @@ __device__ __forceinline__ void wolff_replica(const HandleDev &H, const uint32_t
         const int nc = min(kWolffChunk, H.cls[c + 1] - lo);
         const uint32_t mm = static_cast<uint32_t>(m);
         if (H.F > kMidF) {
-          wolff_bonds<KIND, true, false>(H, rec, lat, scr, stab, lo, nc, mm, c3, padd, lane);
+          wolff_bonds<KIND, true, false>(H, rec, lat, scr, stab, lo, nc, mm, c3, padd, pql, lane);
           wave_sync();
           wolff_flips<KIND, true, false>(H, rec, lat, scr, stab, lo, nc, sw2, arow, lane);
         } else if (H.L == 64) {
-          wolff_bonds<KIND, false, true>(H, rec, lat, scr, stab, lo, nc, mm, c3, padd, lane);
+          wolff_bonds<KIND, false, true>(H, rec, lat, scr, stab, lo, nc, mm, c3, padd, pql, lane);
           wave_sync();
           wolff_flips<KIND, false, true>(H, rec, lat, scr, stab, lo, nc, sw2, arow, lane);
         } else {
-          wolff_bonds<KIND, false, false>(H, rec, lat, scr, stab, lo, nc, mm, c3, padd, lane);
+          wolff_bonds<KIND, false, false>(H, rec, lat, scr, stab, lo, nc, mm, c3, padd, pql, lane);
           wave_sync();
           wolff_flips<KIND, false, false>(H, rec, lat, scr, stab, lo, nc, sw2, arow, lane);
         }
