@@ -346,17 +346,18 @@ sqa_status handle_prepare(const sqa_problem &problem, const sqa_embedding &embed
   const int n = h->emb.n, R = h->R, L = h->L, N = h->N;
   const size_t nt = h->emb.terms.size();
   Arena &A = h->arena;
+  // the uploaded regions first: the small ones (one copy from a host image), then the table
   h->off_rec = A.take(h->lay.rec.size() * 4);
   h->off_devof = A.take(static_cast<size_t>(n) * 2);
   h->off_hfield = A.take(static_cast<size_t>(n) * 4);
   h->off_tw = A.take(std::max<size_t>(nt, 1) * 4);
   h->off_ts = A.take(std::max<size_t>(nt, 1) * 8);
-  h->off_table = A.take(h->table.size() * 4);
   h->off_wacc = A.take(std::max<size_t>(h->wacc.size(), 1) * 4);
-  h->off_spins = A.take(static_cast<size_t>(R) * L * n);
-  h->off_energy = A.take(static_cast<size_t>(R) * L * 4);
   h->off_J = A.take(static_cast<size_t>(N) * N * 4);
   h->off_h = A.take(static_cast<size_t>(N) * 4);
+  h->off_table = A.take(h->table.size() * 4);
+  h->off_spins = A.take(static_cast<size_t>(R) * L * n);
+  h->off_energy = A.take(static_cast<size_t>(R) * L * 4);
   h->off_logical = A.take(static_cast<size_t>(R) * N);
   h->off_lenergy = A.take(static_cast<size_t>(R) * 4);
   h->off_hd = A.take(sizeof(HandleDev));
@@ -375,7 +376,7 @@ sqa_status handle_upload(sqa_handle *h, const sqa_allocator *alloc) {
   sqa_status st = device_alloc(&h->alloc, &A.base, A.size, "device block of the handle");
   if (st != SQA_OK) return st;
   h->device_bytes = A.size;
-  const int n = h->emb.n, R = h->R, N = h->N;
+  const int n = h->emb.n, N = h->N;
   const size_t nt = h->emb.terms.size();
   struct Up {
     size_t off;
@@ -387,26 +388,28 @@ sqa_status handle_upload(sqa_handle *h, const sqa_allocator *alloc) {
       {h->off_hfield, h->lay.hfield.data(), static_cast<size_t>(n) * 4},
       {h->off_tw, h->lay.term_w.data(), nt * 4},
       {h->off_ts, h->lay.term_s.data(), nt * 8},
-      {h->off_table, h->table.data(), h->table.size() * 4},
       {h->off_wacc, h->wacc.data(), h->wacc.size() * 4},
       {h->off_J, h->J.data(), static_cast<size_t>(N) * N * 4},
       {h->off_h, h->h.data(), static_cast<size_t>(N) * 4},
   };
-  hipError_t e = hipSuccess;
-  for (const Up &u : ups) {
-    if (u.bytes == 0) continue;
-    e = hipMemcpy(A.at<char>(u.off), u.p, u.bytes, hipMemcpyHostToDevice);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpy (handle setup)");
+  // the small regions (they precede the table in the block) in one copy from a host
+  // image, the table in a second
+  std::vector<char> img;
+  try {
+    img.assign(h->off_table, 0);
+  } catch (const std::bad_alloc &) {
+    return fail(SQA_ERR_OOM, "host allocation (handle upload)");
   }
+  for (const Up &u : ups)
+    if (u.bytes) std::memcpy(img.data() + u.off, u.p, u.bytes);
+  hipError_t e = hipMemcpy(A.base, img.data(), img.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !h->table.empty())
+    e = hipMemcpy(A.at<char>(h->off_table), h->table.data(), h->table.size() * 4, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy (handle setup)");
   e = hipEventCreateWithFlags(&h->done, hipEventDisableTiming);
   if (e != hipSuccess) {
     h->done = nullptr;
     return hip_fail(e, "hipEventCreate (handle setup)");
-  }
-  e = hipHostMalloc(&h->staging, sizeof(HandleDev) + sizeof(WorkItem) * static_cast<size_t>(R), 0);
-  if (e != hipSuccess) {
-    h->staging = nullptr;
-    return hip_fail(e, "hipHostMalloc (handle staging)");
   }
   return SQA_OK;
 }
@@ -490,6 +493,13 @@ static sqa_status run_single(sqa_handle *h, int m0, int m1, int flags, hipStream
   if (e != hipSuccess) {
     h->poisoned = true;
     return hip_fail(e, "hipEventSynchronize");
+  }
+  if (!h->staging) {     // taken at the first single-handle launch (batches and the server do not use it)
+    e = hipHostMalloc(&h->staging, sizeof(HandleDev) + sizeof(WorkItem) * static_cast<size_t>(h->R), 0);
+    if (e != hipSuccess) {
+      h->staging = nullptr;
+      return hip_fail(e, "hipHostMalloc (handle staging)");
+    }
   }
   HandleDev *hd = static_cast<HandleDev *>(h->staging);
   WorkItem *st_items = reinterpret_cast<WorkItem *>(hd + 1);

@@ -190,7 +190,8 @@ size_t launch_scratch_bytes(const std::vector<sqa_handle *> &hs);
 
 // A handle in two steps: prepare (host only: validation, embedding, layout,
 // tables, the sizes of its device block) and upload (device block from the
-// allocator, site data and tables copied in, event and pinned staging).
+// allocator, site data and tables copied in, event).  The pinned staging of
+// single-handle launches is taken at the first such launch.
 sqa_status handle_prepare(const sqa_problem &problem, const sqa_embedding &embedding, const sqa_schedule &schedule,
                           sqa_handle **out);
 sqa_status handle_upload(sqa_handle *h, const sqa_allocator *alloc);
