@@ -12,6 +12,8 @@
 #include <string>
 #include <vector>
 
+#include <sys/stat.h>
+
 #include "host_core.h"
 
 using namespace sqa;
@@ -242,8 +244,36 @@ static std::map<std::string, std::pair<int, int>> read_cache(const char *path) {
   return m;
 }
 
+// The parsed cache file of the last lookup, reused while the file's path, size and
+// modification time are unchanged (every launch looks its shape up; the tuner's writes
+// drop it).  Used under the cache mutex.
+struct CacheMemo {
+  std::string path;
+  off_t size = -1;
+  struct timespec mtime {};
+  std::map<std::string, std::pair<int, int>> m;
+};
+static CacheMemo g_cache_memo;
+
+static const std::map<std::string, std::pair<int, int>> &read_cache_memo(const char *path) {
+  struct stat st {};
+  if (stat(path, &st) != 0) {
+    g_cache_memo = CacheMemo{};
+    return g_cache_memo.m;
+  }
+  if (g_cache_memo.path != path || g_cache_memo.size != st.st_size ||
+      g_cache_memo.mtime.tv_sec != st.st_mtim.tv_sec || g_cache_memo.mtime.tv_nsec != st.st_mtim.tv_nsec) {
+    g_cache_memo.m = read_cache(path);
+    g_cache_memo.path = path;
+    g_cache_memo.size = st.st_size;
+    g_cache_memo.mtime = st.st_mtim;
+  }
+  return g_cache_memo.m;
+}
+
 static void write_cache(const char *path, const std::map<std::string, std::pair<int, int>> &m) {
   if (!path) return;
+  g_cache_memo = CacheMemo{};
   std::ofstream f(path);
   f << "{\n";
   size_t k = 0;
@@ -256,11 +286,12 @@ static void write_cache(const char *path, const std::map<std::string, std::pair<
 
 static std::mutex g_cache_mu;
 
+
 static bool cached_config(const std::vector<const sqa_handle *> &hs, sqa_launch_config *out) {
   const char *path = cache_path_or_env(nullptr);
   if (!path) return false;
   std::lock_guard<std::mutex> lk(g_cache_mu);
-  auto m = read_cache(path);
+  const auto &m = read_cache_memo(path);
   auto it = m.find(device_arch() + "/" + shape_class(hs));
   if (it == m.end()) return false;
   out->waves_per_group = it->second.first;
