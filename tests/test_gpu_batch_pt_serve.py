@@ -91,6 +91,26 @@ def test_team_and_wave_modes_agree(sqa):
     assert (wave[0][0] == ospins).all() and (wave[0][1] == oE).all()
 
 
+def test_team_mode_mixed_sizes(sqa):
+    """Team mode over handles of very different sizes in one launch: the workgroup's
+    waves (capped at 8) are set by the largest handle (N = 32 ME, L = 64, colour classes
+    of 992 items, two passes each), and the small handles' replicas run on the same
+    wide workgroups, with replica counts of 3 to 16: every handle equals the oracle."""
+    spec = [(ME, 32, 64, 3), (ME, 16, 64, 5), (LHZ, 12, 64, 7), (ME, 8, 32, 16), (LHZ, 6, 16, 3)]
+    specs = [dict(kind=kind, J=sk_instance(N, 330 + q), pen=-2, beta=8.0, L=L, M=20, R=R, g0=3.0, g1=0.05,
+                  seed=0x7EC00 + q) for q, (kind, N, L, R) in enumerate(spec)]
+    print("team mode, handles of mixed sizes in one launch", flush=True)
+    hs = [sqa.SQA(s["kind"], s["J"], s["pen"], s["beta"], s["L"], s["M"], s["R"], s["g0"], s["g1"], s["seed"])
+          for s in specs]
+    b = sqa.Batch(hs)
+    b.run()
+    for s, h in zip(specs, hs):
+        _, _, ospins, oE = O.sqa_anneal(s["kind"], s["J"], s["pen"], s["beta"], s["L"], s["M"], s["R"], s["g0"],
+                                        s["g1"], s["seed"], nthreads=NTH)
+        assert (h.spins() == ospins).all() and (h.energies() == oE).all()
+    b.close()
+
+
 def test_batch_graph_replays_with_eager_work_between(sqa):
     specs = _mixed_jobs()[:4]
     hs = [sqa.SQA(s["kind"], s["J"], s["pen"], s["beta"], s["L"], s["M"], s["R"], s["g0"], s["g1"], s["seed"])
