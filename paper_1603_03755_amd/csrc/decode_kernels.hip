@@ -106,15 +106,38 @@ __global__ __launch_bounds__(256) void lhz_mwd_kernel(const uint32_t *__restrict
     uint32_t z = m << 1;
     int o = full_score(rows, z, N, K, maskN);
     key = (static_cast<uint64_t>(o + K) << 32) | (0xFFFFFFFFu - m);
-    for (uint64_t t = 1; t < chunk; ++t) {
-      const int b = __builtin_ctzll(t);        // the same in every lane: chunks are aligned
-      const int p = b + 1;
-      const int d = row_disagreements(rows[p], z, p, maskN);
-      o += 4 * d - 2 * (N - 1);                 // every pair (p, j) changes sign
+    // step t of the chunk flips logical bit b = ctz(t) (spin p = b + 1): every pair
+    // (p, j) changes sign
+    auto step = [&](uint32_t row, int p) {
+      const int d = row_disagreements(row, z, p, maskN);
+      o += 4 * d - 2 * (N - 1);
       z ^= 1u << p;
-      m ^= 1u << b;
+      m ^= 1u << (p - 1);
       const uint64_t k = (static_cast<uint64_t>(o + K) << 32) | (0xFFFFFFFFu - m);
       key = k > key ? k : key;
+    };
+    if (chunk >= 8) {
+      // eight steps at a time: t = u + 1 .. u + 7 flip bits 0, 1, 0, 2, 0, 1, 0 (rows 1..3
+      // in registers), t = u (u > 0) bit ctz(u) >= 3, the same in every lane (chunks are aligned)
+      const uint32_t r1 = rows[1], r2 = rows[2], r3 = rows[3];
+      for (uint64_t u = 0; u < chunk; u += 8) {
+        if (u) {
+          const int p = __builtin_ctzll(u) + 1;
+          step(rows[p], p);
+        }
+        step(r1, 1);
+        step(r2, 2);
+        step(r1, 1);
+        step(r3, 3);
+        step(r1, 1);
+        step(r2, 2);
+        step(r1, 1);
+      }
+    } else {
+      for (uint64_t t = 1; t < chunk; ++t) {
+        const int p = __builtin_ctzll(t) + 1;
+        step(rows[p], p);
+      }
     }
   }
   key = wave_max_u64(key);
