@@ -58,13 +58,13 @@ WOLFF_SITE_OPS = PHILOX_OPS_PER_CALL + 24.0
 # HBM bytes of one launch of the sweep kernel on this workload, from rocprofv3 --pmc FETCH_SIZE and
 # WRITE_SIZE passes (KiB per dispatch) scaled by the same counters on a cold 2 GiB copy
 # (profiles/sqa_anneal_kernel_batched512_L64.md).  Valid only for the kernel sources it was taken on.
-TRAFFIC_PROFILE = {"kernel_sha256_prefix": "fc00b92b7562b5ba", "instances": 512, "sweeps": 10_000,
-                   "fetch_kib": 965767.0, "write_kib": 509216.0, "fetch_scale": 2.0, "write_scale": 1.0,
-                   "wolff_fetch_kib": 30480.6, "wolff_write_kib": 509208.0}
+TRAFFIC_PROFILE = {"kernel_sha256_prefix": "f0ebdb131c2a1443", "instances": 512, "sweeps": 10_000,
+                   "fetch_kib": 1087481.5, "write_kib": 509217.6, "fetch_scale": 2.0, "write_scale": 1.0,
+                   "wolff_fetch_kib": 29838.2, "wolff_write_kib": 509208.0}
 
 
 # Sources the sweep kernels are compiled from; the traffic figures hold for one hash of them.
-KERNEL_SOURCES = ("sqa_kernels.hip", "device_common.h", "device_types.h")
+KERNEL_SOURCES = ("sqa_kernels.hip", "sqa_sweep.h", "device_common.h", "device_types.h")
 
 
 def kernel_sources_sha256() -> str:

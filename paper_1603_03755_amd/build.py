@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsqa.so")
 CALIB_LIB = os.path.join(HERE, "libsqa_calib.so")
-SOURCES = ["sqa_kernels.hip", "pt_kernels.hip", "decode_kernels.hip", "noalloc.hip", "host_core.cpp", "api_sqa.cpp",
+SOURCES = ["sqa_kernels.hip", "team_kernels.hip", "pt_kernels.hip", "decode_kernels.hip", "noalloc.hip", "host_core.cpp", "api_sqa.cpp",
            "api_pt.cpp", "api_server.cpp"]
 CALIB_SOURCES = ["calib_kernels.hip"]
 ARCH = "gfx950"

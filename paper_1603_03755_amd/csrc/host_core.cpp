@@ -433,7 +433,7 @@ int device_cu_count() {
 // Resident groups per CU: the runtime's occupancy calculation for the sweep
 // kernel (registers, LDS, wave slots), else an LDS / wave-slot estimate.
 int occupancy_groups_per_cu(const LaunchShape &s) {
-  const int rt = sqa_anneal_occupancy(s.move, s.waves, s.lds_bytes());
+  const int rt = sqa_anneal_occupancy(s.move, s.waves, s.lds_bytes(), s.team);
   if (rt > 0) return rt;
   const size_t lds = s.lds_bytes() + 64;
   int by_lds = static_cast<int>(kMaxLds / std::max<size_t>(lds, 1));

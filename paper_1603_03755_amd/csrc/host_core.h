@@ -107,11 +107,12 @@ struct Arena {
   T *at(size_t off) const { return reinterpret_cast<T *>(static_cast<char *>(base) + off); }
 };
 
-// Kernel launchers (sqa_kernels.hip, pt_kernels.hip).
+// Kernel launchers (sqa_kernels.hip, which hands team-mode launches to
+// team_kernels.hip; pt_kernels.hip; decode_kernels.hip).
 hipError_t launch_sqa_anneal(int move, const HandleDev *hds, const WorkItem *items, int n_items, int *counter, int grid,
                              int waves, int rec_cap, int lat_cap, int tab_cap, bool team, hipStream_t stream);
 hipError_t set_sqa_anneal_lds_limit(size_t bytes);
-int sqa_anneal_occupancy(int move, int waves, size_t lds_bytes);
+int sqa_anneal_occupancy(int move, int waves, size_t lds_bytes, bool team);
 hipError_t launch_sqa_init(const HandleDev &H, hipStream_t stream);
 hipError_t launch_me_majority(const int8_t *spins, int R, int N, int len, int n_sites, int L, int slice,
                               const int32_t *J, const int32_t *h, int8_t *logical, int32_t *energy,
