@@ -41,9 +41,17 @@ __global__ __launch_bounds__(512) void sqa_team_kernel(const HandleDev *__restri
     const int nwords = H.n * rec_words_of(H.kind);
     for (int i = threadIdx.x; i < nwords; i += blockDim.x) rec[i] = H.rec[i];
     __syncthreads();
-    if (H.kind == kKindME) anneal_replica<kKindME>(H, rec, lat, tab, stab, wi.rep0, lane, tid, nthr, true);
-    else if (H.kind == kKindLHZ) anneal_replica<kKindLHZ>(H, rec, lat, tab, stab, wi.rep0, lane, tid, nthr, true);
-    else anneal_replica<kKindMEC>(H, rec, lat, tab, stab, wi.rep0, lane, tid, nthr, true);
+    if (nthr == 64) {
+      // a one-wave team synchronises as a wave: no workgroup barrier, whose memory fence would wait
+      // for the next sweep's table-row load at the first class boundary
+      if (H.kind == kKindME) anneal_replica<kKindME>(H, rec, lat, tab, stab, wi.rep0, lane, lane, 64, false);
+      else if (H.kind == kKindLHZ) anneal_replica<kKindLHZ>(H, rec, lat, tab, stab, wi.rep0, lane, lane, 64, false);
+      else anneal_replica<kKindMEC>(H, rec, lat, tab, stab, wi.rep0, lane, lane, 64, false);
+    } else {
+      if (H.kind == kKindME) anneal_replica<kKindME>(H, rec, lat, tab, stab, wi.rep0, lane, tid, nthr, true);
+      else if (H.kind == kKindLHZ) anneal_replica<kKindLHZ>(H, rec, lat, tab, stab, wi.rep0, lane, tid, nthr, true);
+      else anneal_replica<kKindMEC>(H, rec, lat, tab, stab, wi.rep0, lane, tid, nthr, true);
+    }
     __syncthreads();
   }
 }
