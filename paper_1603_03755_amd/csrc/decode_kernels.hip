@@ -102,19 +102,24 @@ __global__ __launch_bounds__(256) void lhz_mwd_kernel(const uint32_t *__restrict
   const uint64_t g0 = (static_cast<uint64_t>(blockIdx.y) * blockDim.x + threadIdx.x) * chunk;
   uint64_t key = 0;
   if (g0 < total) {
-    uint32_t m = static_cast<uint32_t>(g0 ^ (g0 >> 1));
-    uint32_t z = m << 1;
-    int o = full_score(rows, z, N, K, maskN);
-    key = (static_cast<uint64_t>(o + K) << 32) | (0xFFFFFFFFu - m);
-    // step t of the chunk flips logical bit b = ctz(t) (spin p = b + 1): every pair
-    // (p, j) changes sign
+    const uint32_t m0 = static_cast<uint32_t>(g0 ^ (g0 >> 1));
+    uint32_t z = m0 << 1;
+    // Within a chunk (aligned, 2^c candidates) the bits of m from c up stay those of m0, so the
+    // chunk's candidates compare by the 32-bit key (bad << (c + 1)) | (z mod 2^(c+1)), smallest
+    // first (z = 2 m): bad = (K - O) / 2 <= 496 disagreeing pairs, c <= 22.
+    const uint32_t lowz = (2u << c) - 2u;
+    const int sb = c + 1;
+    int bsh = ((K - full_score(rows, z, N, K, maskN)) >> 1) << sb;     // bad << (c + 1)
+    uint32_t kmin = static_cast<uint32_t>(bsh) | (z & lowz);
+    const int cst = (N - 1) << sb, dsc = -(4 << c);
+    // step t of the chunk flips logical bit b = ctz(t) < c (spin p = b + 1): every pair (p, j)
+    // changes sign, so bad gains the N - 1 - d pairs that agreed and loses the d that did not
     auto step = [&](uint32_t row, int p) {
       const int d = row_disagreements(row, z, p, maskN);
-      o += 4 * d - 2 * (N - 1);
+      bsh = __mul24(d, dsc) + (bsh + cst);
       z ^= 1u << p;
-      m ^= 1u << (p - 1);
-      const uint64_t k = (static_cast<uint64_t>(o + K) << 32) | (0xFFFFFFFFu - m);
-      key = k > key ? k : key;
+      const uint32_t k = static_cast<uint32_t>(bsh) | (z & lowz);
+      kmin = k < kmin ? k : kmin;
     };
     if (chunk >= 8) {
       // eight steps at a time: t = u + 1 .. u + 7 flip bits 0, 1, 0, 2, 0, 1, 0 (rows 1..3
@@ -139,6 +144,10 @@ __global__ __launch_bounds__(256) void lhz_mwd_kernel(const uint32_t *__restrict
         step(rows[p], p);
       }
     }
+    // the chunk's best as the global key (O + K) << 32 | (0xFFFFFFFF - m)
+    const uint32_t mb = (m0 & ~(lowz >> 1)) | ((kmin & lowz) >> 1);
+    const uint32_t okb = 2u * (static_cast<uint32_t>(K) - (kmin >> sb));  // O + K, O = K - 2 bad
+    key = (static_cast<uint64_t>(okb) << 32) | (0xFFFFFFFFu - mb);
   }
   key = wave_max_u64(key);
   __shared__ uint64_t wbest[4];
