@@ -400,11 +400,13 @@ static unsigned blocks_for(size_t n, unsigned b) { return static_cast<unsigned>(
 
 // Gray chunk exponent: 2^c candidates per lane, c <= N - 1.
 static int chunk_exponent(int N) { return (N - 1) < 12 ? (N - 1) : 12; }
-// MWD walks chunks of 2^6 candidates per lane (short serial walks, many lanes
-// even for small N), larger from N = 31 on so that the 2^(N-1-c) / 256 blocks
-// per replica stay within the grid's y limit (c >= N - 24).
+// MWD walks chunks of 2^6 candidates per lane up to N = 20 (short serial walks, many lanes for
+// small N) and of 2^10 from N = 21 on, so that a lane's setup (the full score of its first
+// candidate) and its block's reduction amortise over its walk: N = 30 with 16 replicas took
+// 3.48 ms with 2^6-chunks and 1.77 ms with 2^10.  The grid's y dimension, 2^(N-1-c) / 256
+// blocks per replica, stays within its limit up to N = 32.
 static int mwd_chunk_exponent(int N) {
-  const int c = (N - 24) > 6 ? (N - 24) : 6;
+  const int c = (N <= 20) ? 6 : ((N - 22) > 10 ? (N - 22) : 10);
   return (N - 1) < c ? (N - 1) : c;
 }
 
