@@ -38,7 +38,10 @@ def _check(sqa, h, J, spins, slice_, decoder, ref_fn, **kw):
         assert E[r] == O.logical_energy(J, q), (decoder, r)
 
 
-@pytest.mark.parametrize("N,R", [(3, 5), (5, 9), (8, 16), (12, 8), (16, 4)])
+# N = 20 walks 2^6-candidate chunks per lane, N = 21 and 22 2^10 (each lane ranks its chunk by a
+# 32-bit key of the pair count and the index's low bits, then forms the global key): random
+# readouts at p = 0.5 are rich in ties, which must go to the smallest candidate index both ways.
+@pytest.mark.parametrize("N,R", [(3, 5), (5, 9), (8, 16), (12, 8), (16, 4), (20, 3), (21, 3), (22, 2)])
 def test_mwd_matches_oracle_on_random_readouts(sqa, N, R):
     print(f"mwd N={N} R={R}", flush=True)
     rng = np.random.default_rng(N)
