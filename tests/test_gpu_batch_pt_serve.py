@@ -111,6 +111,28 @@ def test_team_mode_mixed_sizes(sqa):
     b.close()
 
 
+def test_team_mode_other_paths(sqa):
+    """Team mode on the sweep paths the mixed-size test leaves out: ME on Chimera (six-term
+    records), a runtime L (24, the last byte of each parity ragged), and field sums above 10
+    (6-bit and 8-bit field modes), beside a compile-time-L handle in the same launch: every
+    handle equals the oracle."""
+    spec = [(MEC, 8, 32, 4, -2), (ME, 10, 24, 6, -2), (LHZ, 9, 64, 5, -6), (ME, 8, 32, 3, -40),
+            (ME, 12, 64, 8, -2)]
+    specs = [dict(kind=kind, J=sk_instance(N, 420 + q), pen=pen, beta=6.0, L=L, M=16, R=R, g0=3.0, g1=0.05,
+                  seed=0x7ED00 + q) for q, (kind, N, L, R, pen) in enumerate(spec)]
+    print("team mode, Chimera records, runtime L and larger fields", flush=True)
+    hs = [sqa.SQA(s["kind"], s["J"], s["pen"], s["beta"], s["L"], s["M"], s["R"], s["g0"], s["g1"], s["seed"])
+          for s in specs]
+    assert max(h.fmax for h in hs) > 63          # an 8-bit field handle is in the set
+    b = sqa.Batch(hs)
+    b.run()
+    for s, h in zip(specs, hs):
+        _, _, ospins, oE = O.sqa_anneal(s["kind"], s["J"], s["pen"], s["beta"], s["L"], s["M"], s["R"], s["g0"],
+                                        s["g1"], s["seed"], nthreads=NTH)
+        assert (h.spins() == ospins).all() and (h.energies() == oE).all()
+    b.close()
+
+
 def test_batch_graph_replays_with_eager_work_between(sqa):
     specs = _mixed_jobs()[:4]
     hs = [sqa.SQA(s["kind"], s["J"], s["pen"], s["beta"], s["L"], s["M"], s["R"], s["g0"], s["g1"], s["seed"])
