@@ -101,7 +101,7 @@ def parse():
                     help="only measure the VALU issue rate of the sweep loops' instruction kinds")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 2 GiB device to device, source evicted from the last-level cache first")
-    ap.add_argument("--legs", default="single,per_instance,serving,pt,wolff,scan,ptscan,cpu",
+    ap.add_argument("--legs", default="single,per_instance,serving,pt,wolff,decoders,scan,ptscan,cpu",
                     help="comma list of the extra legs to run after the timed steps")
     ap.add_argument("--pt-sweeps", type=int, default=100_000, help="sweeps of the parallel-tempering leg")
     return ap.parse_args()
@@ -364,6 +364,50 @@ def serving_leg(sqa):
             "at_fraction_of_capacity": 0.75, "budget_bytes": budget, "slots": slots, "chunk_sweeps": chunk}
 
 
+def decoders_leg(sqa):
+    """The LHZ decoders on the device: minimum-weight (exhaustive over 2^(N-1) logical states),
+    maximum-likelihood at the Nishimori temperature of error rate 0.2 (the same walk with a
+    weight per state; N <= 24), belief propagation on the weight-3 parity checks (10 rounds, then one
+    random spanning tree) and majority over three random spanning trees.  Each at N = 24 with
+    64 replicas (the benchmark's largest LHZ handles) and N = 32 with 16 replicas (the serving
+    leg's largest), on the readout slice of a short anneal; a decode is queued on a stream and
+    timed with HIP events there (median of 5 after one warm-up)."""
+    import torch
+    from paper_1603_03755_amd.workloads import LHZ, sk_instance
+    stream = torch.cuda.Stream()
+    out = {}
+    for N, R in ((24, 64), (32, 16)):
+        h = sqa.SQA(LHZ, sk_instance(N, 1603 + N), -2, 10.0, 64, 50, R, 3.0, 0.01, 0x5EED + N)
+        h.anneal(stream)
+        stream.synchronize()
+        trees1 = sqa.sqa_random_trees(0x7EE + N, N, 1)
+        trees3 = sqa.sqa_random_trees(0x7EF + N, N, 3)
+        res = {}
+        for name, dec, kw in (("mwd", sqa.SQA_DEC_LHZ_MWD, {}),
+                              ("mld", sqa.SQA_DEC_LHZ_MLD, {"error_rate": 0.2}),
+                              ("bp", sqa.SQA_DEC_LHZ_BP, {"error_rate": 0.2, "iterations": 10, "trees": trees1}),
+                              ("trees", sqa.SQA_DEC_LHZ_TREES, {"trees": trees3})):
+            if name == "mld" and N > 24:     # the library's exhaustive MLD stops at N = 24
+                continue
+            ts = []
+            for rep in range(6):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                h.decode(dec, 0, stream=stream, host=False, **kw)
+                e1.record(stream)
+                stream.synchronize()
+                if rep:
+                    ts.append(e0.elapsed_time(e1))
+            ms = float(np.median(ts))
+            r = {"ms": ms}
+            if name in ("mwd", "mld"):
+                r["candidates_per_s"] = R * float(2 ** (N - 1)) / (ms / 1e3)
+            res[name] = r
+        h.close()
+        out[f"lhz_n{N}_r{R}"] = res
+    return out
+
+
 def single_leg(sqa):
     """The two single-instance configurations: the N = 8 instance as clique-chain ME (56
     sites) and as LHZ (28 sites), 16 replicas, L = 32, 10^3 sweeps, one handle each; a
@@ -622,6 +666,9 @@ def main():
     if "single" in legs:
         log("leg single")
         out["single_instance"] = single_leg(sqa)
+    if "decoders" in legs:
+        log("leg decoders")
+        out["decoders"] = decoders_leg(sqa)
     if "serving" in legs:
         log("leg serving")
         out["serving"] = serving_leg(sqa)
