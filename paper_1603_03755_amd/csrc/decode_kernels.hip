@@ -193,14 +193,41 @@ __global__ __launch_bounds__(64) void lhz_mld_kernel(const uint32_t *__restrict_
     z = m << 1;
     int o = full_score(rows, z, N, K, maskN);
     W = static_cast<int64_t>(wtab[omax - o]);
-    for (uint64_t t = 1; t < chunk; ++t) {
-      const int p = __builtin_ctzll(t) + 1;
-      const int d = row_disagreements(rows[p], z, p, maskN);
+    // step t of the chunk flips spin p = ctz(t) + 1; its interval sum opens (bit turned on) or
+    // closes (off) at the total W of the states before this one
+    auto step = [&](uint32_t row, int p, int64_t &sp) {
+      const int d = row_disagreements(row, z, p, maskN);
       o += 4 * d - 2 * (N - 1);
       z ^= 1u << p;
-      int64_t *sp = sacc + p * 64 + lane;
-      *sp += ((z >> p) & 1u) ? -W : W;           // bit p turned on: open; off: close
+      sp += ((z >> p) & 1u) ? -W : W;
       W += static_cast<int64_t>(wtab[omax - o]);
+    };
+    if (chunk >= 8) {
+      // eight steps at a time, as in the MWD walk: spins 1..3 (seven of every eight steps) keep
+      // their rows and interval sums in registers, the eighth step's in LDS
+      const uint32_t r1 = rows[1], r2 = rows[2], r3 = rows[3];
+      int64_t s1 = 0, s2 = 0, s3 = 0;
+      for (uint64_t u = 0; u < chunk; u += 8) {
+        if (u) {
+          const int p = __builtin_ctzll(u) + 1;
+          step(rows[p], p, sacc[p * 64 + lane]);
+        }
+        step(r1, 1, s1);
+        step(r2, 2, s2);
+        step(r1, 1, s1);
+        step(r3, 3, s3);
+        step(r1, 1, s1);
+        step(r2, 2, s2);
+        step(r1, 1, s1);
+      }
+      sacc[64 + lane] += s1;
+      sacc[128 + lane] += s2;
+      sacc[192 + lane] += s3;
+    } else {
+      for (uint64_t t = 1; t < chunk; ++t) {
+        const int p = __builtin_ctzll(t) + 1;
+        step(rows[p], p, sacc[p * 64 + lane]);
+      }
     }
   }
   // close the intervals of bits still on; S_i -> W - 2 S_i
