@@ -14,8 +14,9 @@ starts.
 Prints one JSON line.  Also reports the same instances launched one per
 instance (at a reduced sweep count, both ways), serving latency percentiles on
 a short Poisson job stream, parallel tempering, the same batch with the
-paper's time-like Wolff cluster moves, the roofline of the sweep kernels and
-the CPU oracle on a bounded sample of the workload.
+paper's time-like Wolff cluster moves, each LHZ decoder alone, the penalty
+scans, the roofline of the sweep kernels and the CPU oracle on a bounded
+sample of the workload.
 
 `--copy-calibration` instead runs only a cold 2 GiB device-to-device copy, the
 reference for scaling the FETCH_SIZE / WRITE_SIZE counters to bytes;
